@@ -1,0 +1,128 @@
+"""Seeded synthetic workloads (inputs only; none of the method's arithmetic).
+
+Each generator returns a dict with
+    x        scatterer positions (float64, M)
+    beta     spring stiffnesses  (float64, M)
+    packets  incident-field packets, (n, 5) rows (amp, centre, width, omega, phase):
+             f(s) = sum amp * exp(-(s - centre)^2 / (2 width^2)) * cos(omega (s - centre) + phase)
+    boundary 0 = periodic box [-pi, pi), 1 = free space
+    dt, n_steps
+    x_recv   receiver positions (float64, R; may be empty)
+    name     workload label
+
+The scatterer sets mirror the random-spring experiments of the paper
+(Section 6: uniform random positions, random strengths).  Springs are placed
+outside the 1e-12 support of the incident pulse at t = 0, as the paper
+requires of Gamma and supp f (Section 1), so the densities switch on smoothly.
+No public dataset is involved anywhere.
+"""
+import math
+
+import numpy as np
+
+PI = math.pi
+
+
+def _rng(*seed):
+    return np.random.default_rng(list(seed))
+
+
+def periodic_single_pulse(seed, M, dt, n_steps, beta_range=(1.0, 10.0),
+                          x_range=(0.3, 2.0), width=0.3, centre=-2.0, n_recv=0,
+                          name="periodic"):
+    """Periodic box, one Gaussian pulse, x ~ U(x_range), beta ~ U(beta_range)."""
+    r = _rng(seed)
+    x = r.uniform(x_range[0], x_range[1], M)
+    beta = r.uniform(beta_range[0], beta_range[1], M)
+    xr = np.linspace(x_range[0], x_range[1], n_recv) if n_recv else np.zeros(0)
+    return dict(x=x, beta=beta, packets=np.array([[1.0, centre, width, 0.0, 0.0]]),
+                boundary=0, dt=dt, n_steps=n_steps, x_recv=xr, name=name)
+
+
+def small_periodic():
+    """M = 16 springs in the periodic box, dt = 0.01, 600 steps, pulse of width
+    0.3 centred at -2 (the small parity case)."""
+    p = periodic_single_pulse(1, 16, 0.01, 600, name="periodic-M16-dt1e-2-Nt600")
+    return p
+
+
+def multiband_periodic(seed=2, M=10_000, dt=1e-3, n_steps=10_000):
+    """M = 1e4 springs, beta log-uniform in [0.1, 100], incident field a sum of
+    8 Gaussian wave packets (width 0.05) with angular carriers 50..500,
+    dt = 1e-3, 1e4 steps, periodic box (the throughput case)."""
+    r = _rng(seed)
+    x = r.uniform(-PI + 1.2, PI, M)
+    beta = np.exp(r.uniform(math.log(0.1), math.log(100.0), M))
+    om = 50.0 * 10.0 ** (np.arange(8) / 7.0)
+    c = -PI + 0.4 + 0.05 * np.arange(8)
+    packets = np.stack([np.full(8, 0.25), c, np.full(8, 0.05), om, np.zeros(8)], axis=1)
+    return dict(x=x, beta=beta, packets=packets, boundary=0, dt=dt, n_steps=n_steps,
+                x_recv=np.zeros(0), name=f"periodic-multiband-M{M}-dt{dt:g}-Nt{n_steps}")
+
+
+def clumped_free_space(seed=3, M=1_000_000, dt=5e-4, n_steps=4000, n_clumps=100,
+                       frac=0.1, clump_sigma=1e-3, margin=0.0528):
+    """Free space, M springs uniform in Omega with a fraction in tight Gaussian
+    clumps, beta ~ U[1, 10], Gaussian-modulated plane wave of angular
+    frequency 1000 entering from the left."""
+    r = _rng(seed)
+    lo, hi = -PI + margin, PI - margin
+    n_cl = int(round(frac * M))
+    n_un = M - n_cl
+    xu = r.uniform(lo, hi, n_un)
+    centres = r.uniform(lo + 0.01, hi - 0.01, n_clumps)
+    per = np.full(n_clumps, n_cl // n_clumps)
+    per[: n_cl - per.sum()] += 1
+    xc = np.concatenate([r.normal(c, clump_sigma, k) for c, k in zip(centres, per)])
+    xc = np.clip(xc, lo, hi)
+    x = np.concatenate([xu, xc])
+    beta = r.uniform(1.0, 10.0, M)
+    s0 = lo - 0.4
+    packets = np.array([[1.0, s0, 0.05, 1000.0, 0.0]])
+    return dict(x=x, beta=beta, packets=packets, boundary=1, dt=dt, n_steps=n_steps,
+                x_recv=np.zeros(0), name=f"free-clumped-M{M}-dt{dt:g}-Nt{n_steps}")
+
+
+def adjoint_periodic(seed=5, M=100_000, dt=1e-3, n_steps=5000, R=64):
+    """Periodic, M springs with beta ~ U[1, 10], a single Gaussian pulse
+    (width 0.05) and R receivers spread over the spring region."""
+    r = _rng(seed)
+    x = r.uniform(-PI + 1.2, PI, M)
+    beta = r.uniform(1.0, 10.0, M)
+    packets = np.array([[1.0, -PI + 0.6, 0.05, 0.0, 0.0]])
+    xr = -PI + 1.2 + (np.arange(R) + 0.5) * (2 * PI - 1.2) / R
+    return dict(x=x, beta=beta, packets=packets, boundary=0, dt=dt, n_steps=n_steps,
+                x_recv=xr, name=f"periodic-adjoint-M{M}-dt{dt:g}-Nt{n_steps}-R{R}")
+
+
+def batch_instances(seed=4, n=512, n_steps=2000, m_range=(100, 100_000)):
+    """n independent periodic problems with log-uniform M, dt in {1,2,5}e-3,
+    beta ~ U[1, 10] and one random Gaussian pulse each."""
+    out = []
+    for i in range(n):
+        r = _rng(seed, i)
+        M = int(round(math.exp(r.uniform(math.log(m_range[0]), math.log(m_range[1])))))
+        dt = float(r.choice([1e-3, 2e-3, 5e-3]))
+        w = r.uniform(0.03, 0.07)
+        c = r.uniform(-PI + 0.55, -PI + 0.65)
+        x = r.uniform(-PI + 1.2, PI, M)
+        beta = r.uniform(1.0, 10.0, M)
+        out.append(dict(x=x, beta=beta, packets=np.array([[1.0, c, w, 0.0, 0.0]]),
+                        boundary=0, dt=dt, n_steps=n_steps, x_recv=np.zeros(0),
+                        name=f"batch-{i}"))
+    return out
+
+
+def random_state(seed, M, K, W, m_hist, scale=1e-2):
+    """A synthetic mid-run state (density history, spectra ring, modes) used to
+    test one step from a state both sides receive as input."""
+    r = _rng(seed, 99)
+    hist = scale * r.standard_normal((m_hist, M))
+    ring = scale * (r.standard_normal((W, K + 1)) + 1j * r.standard_normal((W, K + 1)))
+    decay = np.exp(-np.arange(K + 1) / (0.3 * (K + 1)))
+    alpha = scale * decay * (r.standard_normal(K + 1) + 1j * r.standard_normal(K + 1))
+    dalpha = scale * decay * (r.standard_normal(K + 1) + 1j * r.standard_normal(K + 1))
+    ring[:, 0] = ring[:, 0].real
+    alpha[0] = alpha[0].real
+    dalpha[0] = dalpha[0].real
+    return dict(hist=hist, ring=ring, alpha=alpha, dalpha=dalpha)
