@@ -1,0 +1,150 @@
+/*
+ * wfp.h -- C ABI of the MI355X (gfx950) FP64 implementation of the
+ * windowed Fourier projection (WFP) march for point scatterers on a string
+ * (Al Hassanieh, Barnett, Greengard, "A fast algorithm for the wave equation
+ * using time-windowed Fourier projection").
+ *
+ * Problem (Section 1, eqs. (WE)-(kink), (gj); periodic box: Section 2,
+ * eq. (peri)): M springs at x_j in [-pi, pi) with stiffness beta_j > 0 are
+ * hit by the incident field u_inc(x, t) = f(x - t).  The scattered field is
+ * the single-layer potential of densities sigma_j(t) (eqs. (singleLayerSol),
+ * (SLPp)), which solve the Volterra system (IEfree)/(periodicIE)
+ *     -sigma_j(t) - beta_j u(x_j, t) = g_j(t) = beta_j f(x_j - t).
+ *
+ * Method (Sections 2-4): u = u_L + u_H with the Kaiser-Bessel blending
+ * window phi of timescale delta = W dt (eqs. (phi), (b)); u_H is the
+ * truncated Fourier series sum_{|k|<=K} alpha_k e^{-ikx} (eq. (historySol1))
+ * advanced by the exact propagator of the Lemma with the trapezoid driving
+ * terms of eq. (hkcompdisc); the densities' spectra S_k (eq. (densco)) come
+ * from a type-1 NUFFT and u_H at the scatterers from a type-2 NUFFT; u_L is
+ * the N_L-node Gauss-Legendre rule with p-point interpolation of Section 4.1;
+ * each step solves the sparse system (linearSystem).  Free space adds the
+ * radiation-boundary projection of Section 4.4.
+ *
+ * Conventions
+ *   - Time levels t_L = L dt, L = 0, 1, 2, ...  A "step" computes one new
+ *     level sigma^L from the levels before it (zero history before L = 0,
+ *     so the first step solves (I + S) sigma^0 = -g^0).
+ *   - All problem data passed to wfp_plan_create are HOST pointers and are
+ *     copied; the caller may free them after the call returns.
+ *   - All arrays passed to wfp_run / wfp_get_state / wfp_set_state are
+ *     DEVICE pointers (caller-owned, on the plan's device); these calls are
+ *     asynchronous and ordered on the plan's stream.
+ *   - Per-scatterer arrays are in the caller's original order.
+ *   - Complex arrays are interleaved (re, im) doubles.
+ *   - No C++ exception crosses this boundary; every call returns a status.
+ *     On error, wfp_last_error() returns a thread-local message.
+ */
+#ifndef WFP_H
+#define WFP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wfp_status;
+
+#define WFP_OK 0
+#define WFP_EINVAL (-1)     /* bad argument: M <= 0, dt <= 0, odd p, NaN input, NULL pointer */
+#define WFP_EDOMAIN (-2)    /* K dt > pi, delta = W dt >= pi, free-space point outside Omega,
+                               unsupported size (e.g. transform too long for one workgroup) */
+#define WFP_ENOMEM (-3)     /* device or host allocation failed */
+#define WFP_EHIP (-4)       /* a HIP runtime call failed */
+#define WFP_ESTATE (-5)     /* call not valid in the plan's current state */
+
+#define WFP_PERIODIC 0      /* periodic box [-pi, pi) (Section 2) */
+#define WFP_FREE_SPACE 1    /* free space via outgoing windowing (Section 4.4) */
+
+#define WFP_ABI_VERSION 1
+
+typedef struct wfp_plan wfp_plan;
+
+/* Problem statement (Section 1).  Host pointers, copied by wfp_plan_create. */
+typedef struct {
+  int64_t M;               /* number of springs, >= 1 */
+  const double* x;         /* [M] positions in [-pi, pi); free space: inside Omega */
+  const double* beta;      /* [M] stiffnesses > 0 */
+  int32_t boundary;        /* WFP_PERIODIC or WFP_FREE_SPACE */
+  int32_t n_packets;       /* 1..64 */
+  const double* packets;   /* [n_packets][5] = (amp, centre, width, omega, phase):
+                              f(s) = sum amp exp(-(s-centre)^2/(2 width^2)) cos(omega (s-centre) + phase);
+                              periodised over 2 pi in the periodic box */
+  int64_t R;               /* number of receivers (extra targets, Section 3.1), >= 0 */
+  const double* x_recv;    /* [R] receiver positions (may be NULL when R == 0) */
+} wfp_problem;
+
+/* Discretisation parameters.  A zero field selects the default shown. */
+typedef struct {
+  double dt;               /* time step, > 0 (required) */
+  double eps_window;       /* window tolerance eps; b = ln(1/eps)           [1e-12] */
+  double gamma;            /* Nyquist fraction lost to windowing (Remark r:gamma)  [0.5] */
+  int32_t W;               /* window length in steps, delta = W dt          [round(2b/(pi gamma))] */
+  int32_t p;               /* interpolation order (even)                     [8] */
+  int64_t K;               /* highest Fourier mode: periodic floor(pi/dt); free space the largest
+                              K <= pi/dt with 2K = 2^a 5^b                     [rule] */
+  int32_t n_gl_local;      /* Gauss-Legendre nodes of the local rule N_L     [W] */
+  int32_t n_gl_pq;         /* Gauss-Legendre nodes for p_k, q_k  N_g         [32] */
+  int32_t rbc_period;      /* free space: levels between RBC projections     [ceil(W h/dt), h = pi/K] */
+  int32_t nufft_width;     /* spreading-kernel width in fine-grid points     [16] */
+  int32_t solve_iters;     /* Jacobi sweeps of the per-step solve            [from a contraction bound] */
+  int32_t reserved;
+} wfp_params;
+
+/* Derived sizes of a plan (read-only report). */
+typedef struct {
+  int64_t M, R, K, n_fine, n_pairs, n_pairs_recv, level;
+  int32_t W, p, m_max, n_gl_local, rbc_period, nufft_width, solve_iters, boundary;
+  double dt, delta, b, solve_contraction;
+  int64_t device_bytes;
+} wfp_info;
+
+/* Create a plan: validates the problem, sorts the springs, precomputes the
+ * window, the one-step kernels p_k, q_k, the NUFFT deconvolution factors,
+ * neighbour ranges and the local weights Q_m(d) of every pair closer than
+ * delta (stored on the device), and zeroes the state (level 0).
+ * `stream` is a hipStream_t (NULL = default stream).  Synchronous.
+ * Errors: WFP_EINVAL, WFP_EDOMAIN, WFP_ENOMEM, WFP_EHIP; *out is NULL then. */
+wfp_status wfp_plan_create(const wfp_problem* prob, const wfp_params* par, void* stream,
+                           wfp_plan** out);
+
+/* Release every device and host resource of the plan (NULL is a no-op). */
+void wfp_plan_destroy(wfp_plan* plan);
+
+/* Fill *info with the plan's derived sizes. */
+wfp_status wfp_plan_info(const wfp_plan* plan, wfp_info* info);
+
+/* March n_steps levels (Section 4.2, eq. (periodicIE_disc)).
+ *   sigma_out  device [ceil(n_steps / save_every)][M] or NULL: row i holds the
+ *              densities of the (i*save_every)-th level computed by this call.
+ *   save_every >= 1 (ignored when sigma_out is NULL).
+ *   u_recv_out device [n_steps][R] or NULL: u(x_r, t_L) at every level computed
+ *              (u_L + u_H, eqs. (localSol2) and (historySol1)).
+ * Asynchronous on the plan's stream.  Errors: WFP_EINVAL, WFP_EHIP. */
+wfp_status wfp_run(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t save_every,
+                   double* u_recv_out);
+
+/* Checkpoint / resume.  With L the next level to be computed:
+ *   hist   device [m_max][M]:      hist[m][j] = sigma_j^{L-1-m}
+ *   ring   device [W][K+1][2]:     ring[m][k] = S_k^{L-2-m}  (spectra of past levels)
+ *   alpha  device [K+1][2], dalpha device [K+1][2]: alpha_k^{L-1}, alpha'_k^{L-1}
+ * Any pointer may be NULL on get (that part is skipped).  set_state requires all.
+ * Asynchronous on the plan's stream. */
+wfp_status wfp_get_state(wfp_plan* plan, int64_t* level, double* hist, double* ring,
+                         double* alpha, double* dalpha);
+wfp_status wfp_set_state(wfp_plan* plan, int64_t level, const double* hist, const double* ring,
+                         const double* alpha, const double* dalpha);
+
+/* Return the plan to level 0 with zero history (stream-ordered). */
+wfp_status wfp_reset(wfp_plan* plan);
+
+const char* wfp_status_string(wfp_status s);
+const char* wfp_last_error(void);
+int32_t wfp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WFP_H */

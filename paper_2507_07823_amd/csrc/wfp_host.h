@@ -1,0 +1,55 @@
+// Host-side numerics of the plan set-up (window series, Gauss-Legendre rules,
+// neighbour ranges).  Pure C++, no HIP; also compiled into the host unit test
+// of the library.
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+namespace wfp {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 2.0 * kPi;
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on the
+// three-term recurrence of P_n, carried in long double).
+void gauss_legendre(int n, std::vector<double>& z, std::vector<double>& w);
+
+// Modified Bessel I0 by its power series, in long double.
+long double bessel_i0(long double x);
+
+// Chebyshev series (a_0/2 + sum_{n>=1} a_n T_n) of the Kaiser-Bessel window in
+// the rescaled variable s = 2t/delta - 1 (Section 2, eq. (phi)):
+//   g(s)  = I0(b sqrt(1 - s^2)) * b / (2 sinh b),
+//   Phi(s) = int_{-1}^{s} g   (so phi(t) = Phi(s), phi'(t) = (2/delta) g(s),
+//                               phi''(t) = (4/delta^2) g'(s)).
+// The series do not depend on delta, so one set serves the time window and the
+// spatial window of the RBC.
+struct WindowSeries {
+  int n = 0;
+  std::vector<double> phi, g, dg;
+};
+WindowSeries window_series(double b, int n);
+double cheb_eval(const double* a, int n, double s);   // prime convention
+
+// Distance used for neighbour decisions (Definition lambdadef); the same
+// expression is evaluated on the device.
+inline double pair_distance(double a, double c, bool periodic) {
+  double d = std::fabs(a - c);
+  if (periodic && d > kPi) d = kTwoPi - d;
+  return d;
+}
+
+// Sources (sorted ascending in [-pi, pi)) closer than r to position x form a
+// circular index range [start, start + count) (mod M).  `inclusive` selects
+// d <= r instead of d < r.
+void source_range(const std::vector<double>& xs, double x, double r, bool periodic,
+                  bool inclusive, int& start, int& count);
+
+// 2^a 5^b test and the radix sequence (4s, at most one 2, then 5s) used by
+// the LDS FFT.
+bool is_pow2_pow5(int64_t n);
+std::vector<int> radix_sequence(int64_t n);
+
+}  // namespace wfp

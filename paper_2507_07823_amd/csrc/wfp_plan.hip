@@ -1,0 +1,761 @@
+// Plan creation, the level loop and the exported C ABI (include/wfp.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/wfp.h"
+#include "wfp_host.h"
+#include "wfp_kernels.h"
+
+using namespace wfp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Error {
+  wfp_status code;
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw Error{e_ == hipErrorOutOfMemory ? WFP_ENOMEM : WFP_EHIP,                    \
+                  std::string(#expr) + ": " + hipGetErrorString(e_)};                   \
+  } while (0)
+
+void fail(wfp_status c, const std::string& m) { throw Error{c, m}; }
+
+template <class T>
+T* dalloc(size_t n, int64_t& counter) {
+  T* p = nullptr;
+  if (n == 0) n = 1;
+  HIPCHK(hipMalloc(&p, n * sizeof(T)));
+  counter += (int64_t)(n * sizeof(T));
+  return p;
+}
+
+template <class T>
+void upload(T* d, const std::vector<T>& h, hipStream_t s) {
+  if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+FftPlan make_fft_plan(int64_t n) {
+  FftPlan fp{};
+  fp.n = (int)n;
+  std::vector<int> r = radix_sequence(n);
+  if ((int)r.size() > kMaxFftStages) fail(WFP_EDOMAIN, "FFT length has too many stages");
+  fp.nst = (int)r.size();
+  for (size_t i = 0; i < r.size(); ++i) fp.radix[i] = r[i];
+  for (int R : r)
+    if (n / R > (int64_t)kFftMaxB * kFftThreads) fail(WFP_EDOMAIN, "FFT length too large for one workgroup");
+  return fp;
+}
+
+}  // namespace
+
+struct wfp_plan {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t dev_bytes = 0;
+  // sizes and parameters
+  int64_t M = 0, R = 0, K = 0, level = 0, n_pairs = 0, n_pairs_recv = 0;
+  int boundary = 0, W = 0, p = 0, NQ = 0, NH = 0, ngl = 0, ngpq = 0, rbc_period = 0, width = 0, iters = 0;
+  int nf = 0, nfh = 0, ncheb = 0, T = 256, ntile = 0, ext_max = 0, npk = 0;
+  double dt = 0, delta = 0, b = 0, hf = 0, alpha_es = 0, beta_es = 0, h_rbc = 0, delta_s = 0, contraction = 0;
+  FftPlan fft_nf{}, fft_rbc{};
+  size_t lds_nf = 0, lds_rbc = 0, lds_jac = 0, lds_qw = 0;
+  std::vector<int> perm_h;
+  // device buffers
+  double *xs = nullptr, *beta = nullptr, *xr = nullptr, *packets = nullptr;
+  int* perm = nullptr;
+  double* hist = nullptr;
+  double2 *ring = nullptr, *alpha = nullptr, *dalpha = nullptr;
+  double *pk = nullptr, *qk = nullptr, *rot = nullptr, *dk1 = nullptr, *dk2 = nullptr;
+  double2* tw = nullptr;
+  double2* tw_rbc = nullptr;
+  double* grid = nullptr;
+  double2* zbuf = nullptr;
+  double2* ybuf = nullptr;
+  double* grid2 = nullptr;
+  double *rbc_u = nullptr, *rbc_v = nullptr;
+  int *cstart = nullptr, *ccount = nullptr;
+  int *nb_start = nullptr, *nb_count = nullptr, *near_start = nullptr, *near_count = nullptr;
+  int64_t* qoff = nullptr;
+  double* Q = nullptr;
+  double* rhs = nullptr;
+  int *ext_start = nullptr, *ext_len = nullptr;
+  int *rnb_start = nullptr, *rnb_count = nullptr;
+  int64_t* rqoff = nullptr;
+  double* Qr = nullptr;
+  double *cheb_phi = nullptr, *cheb_g = nullptr;
+  std::vector<void*> owned;
+
+  ~wfp_plan() {
+    for (void* ptr : owned) (void)hipFree(ptr);
+  }
+  template <class T>
+  T* alloc(size_t n) {
+    T* ptr = dalloc<T>(n, dev_bytes);
+    owned.push_back(ptr);
+    return ptr;
+  }
+};
+
+namespace {
+
+void zero_state(wfp_plan* P) {
+  auto fill = [&](double* ptr, int64_t n) {
+    hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, P->stream, ptr, n, 0.0);
+  };
+  fill(P->hist, (int64_t)P->NH * P->M);
+  fill((double*)P->ring, 2 * (int64_t)P->W * (P->K + 1));
+  fill((double*)P->alpha, 2 * (P->K + 1));
+  fill((double*)P->dalpha, 2 * (P->K + 1));
+  fill((double*)P->ybuf, 2 * (P->K + 1));
+  HIPCHK(hipGetLastError());
+  P->level = 0;
+}
+
+// Host-only checks of the problem and parameters (no HIP call), so invalid
+// input is reported before any device work.
+void validate(const wfp_problem* prob, const wfp_params* par) {
+  if (!prob || !par) fail(WFP_EINVAL, "NULL problem or params");
+  if (prob->M < 1) fail(WFP_EINVAL, "M must be >= 1");
+  if (prob->M > (int64_t)1 << 30) fail(WFP_EINVAL, "M too large");
+  if (!prob->x || !prob->beta) fail(WFP_EINVAL, "x and beta are required");
+  if (prob->boundary != WFP_PERIODIC && prob->boundary != WFP_FREE_SPACE) fail(WFP_EINVAL, "bad boundary");
+  if (prob->n_packets < 1 || prob->n_packets > 64 || !prob->packets) fail(WFP_EINVAL, "need 1..64 packets");
+  if (prob->R < 0 || (prob->R > 0 && !prob->x_recv)) fail(WFP_EINVAL, "bad receivers");
+  if (!(par->dt > 0) || !std::isfinite(par->dt)) fail(WFP_EINVAL, "dt must be positive");
+  if (par->eps_window < 0 || !(par->eps_window < 1) || par->gamma < 0 || !(par->gamma < 1))
+    fail(WFP_EINVAL, "eps_window and gamma must lie in [0, 1)");
+  if (par->W < 0 || par->K < 0 || par->n_gl_local < 0 || par->n_gl_pq < 0 || par->rbc_period < 0 ||
+      par->solve_iters < 0)
+    fail(WFP_EINVAL, "negative size parameter");
+  const int p = par->p > 0 ? par->p : 8;
+  if (par->p < 0 || p % 2 || p < 2 || p > kMaxP) fail(WFP_EINVAL, "p must be even, 2..12");
+  for (int64_t j = 0; j < prob->M; ++j) {
+    if (!std::isfinite(prob->x[j]) || !std::isfinite(prob->beta[j])) fail(WFP_EINVAL, "non-finite x or beta");
+    if (!(prob->beta[j] > 0)) fail(WFP_EINVAL, "beta must be positive");
+    if (prob->x[j] < -kPi || prob->x[j] >= kPi) fail(WFP_EINVAL, "x must lie in [-pi, pi)");
+  }
+  for (int64_t r = 0; r < prob->R; ++r)
+    if (!std::isfinite(prob->x_recv[r]) || prob->x_recv[r] < -kPi || prob->x_recv[r] >= kPi)
+      fail(WFP_EINVAL, "receiver outside [-pi, pi)");
+  for (int i = 0; i < prob->n_packets * 5; ++i)
+    if (!std::isfinite(prob->packets[i])) fail(WFP_EINVAL, "non-finite packet");
+  for (int i = 0; i < prob->n_packets; ++i)
+    if (!(prob->packets[5 * i + 2] > 0)) fail(WFP_EINVAL, "packet width must be positive");
+  const double eps = par->eps_window > 0 ? par->eps_window : 1e-12;
+  const double gamma = par->gamma > 0 ? par->gamma : 0.5;
+  const double b = std::log(1.0 / eps);
+  const int W = par->W > 0 ? par->W : (int)std::lround(2.0 * b / (kPi * gamma));
+  if (W * par->dt >= kPi) fail(WFP_EDOMAIN, "delta = W dt must be < pi");
+  if (par->K > 0 && (double)par->K * par->dt > kPi * (1 + 1e-14)) fail(WFP_EDOMAIN, "K dt must not exceed pi");
+  if (std::floor(kPi / par->dt) < 1 && par->K == 0) fail(WFP_EDOMAIN, "K < 1 (dt too large)");
+  if (prob->boundary == WFP_FREE_SPACE) {
+    int64_t K = par->K;
+    if (K == 0) {
+      K = (int64_t)std::floor(kPi / par->dt);
+      while (K > 1 && !is_pow2_pow5(2 * K)) --K;
+    }
+    const double h = kPi / (double)K;
+    const double margin = 3.0 * std::max(W * par->dt, W * h);
+    for (int64_t j = 0; j < prob->M; ++j)
+      if (prob->x[j] < -kPi + margin || prob->x[j] > kPi - margin)
+        fail(WFP_EDOMAIN, "free space: scatterer outside Omega");
+    for (int64_t r = 0; r < prob->R; ++r)
+      if (prob->x_recv[r] < -kPi + margin || prob->x_recv[r] > kPi - margin)
+        fail(WFP_EDOMAIN, "free space: receiver outside Omega");
+  }
+}
+
+void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
+  validate(prob, par);
+  const int64_t M = prob->M;
+  if (M < 1) fail(WFP_EINVAL, "M must be >= 1");
+  if (M > (int64_t)1 << 30) fail(WFP_EINVAL, "M too large");
+  if (!prob->x || !prob->beta) fail(WFP_EINVAL, "x and beta are required");
+  if (prob->boundary != WFP_PERIODIC && prob->boundary != WFP_FREE_SPACE) fail(WFP_EINVAL, "bad boundary");
+  if (prob->n_packets < 1 || prob->n_packets > 64 || !prob->packets) fail(WFP_EINVAL, "need 1..64 packets");
+  if (prob->R < 0 || (prob->R > 0 && !prob->x_recv)) fail(WFP_EINVAL, "bad receivers");
+  if (!(par->dt > 0) || !std::isfinite(par->dt)) fail(WFP_EINVAL, "dt must be positive");
+  const bool periodic = prob->boundary == WFP_PERIODIC;
+  P->M = M;
+  P->R = prob->R;
+  P->boundary = prob->boundary;
+  P->dt = par->dt;
+  const double eps = par->eps_window > 0 ? par->eps_window : 1e-12;
+  const double gamma = par->gamma > 0 ? par->gamma : 0.5;
+  P->b = std::log(1.0 / eps);
+  P->W = par->W > 0 ? par->W : (int)std::lround(2.0 * P->b / (kPi * gamma));
+  P->p = par->p > 0 ? par->p : 8;
+  if (P->p % 2 || P->p < 2 || P->p > kMaxP) fail(WFP_EINVAL, "p must be even, 2..12");
+  P->delta = P->W * P->dt;
+  if (P->delta >= kPi) fail(WFP_EDOMAIN, "delta = W dt must be < pi");
+  if (par->K > 0) {
+    P->K = par->K;
+  } else {
+    int64_t k = (int64_t)std::floor(kPi / P->dt);
+    if (!periodic)
+      while (k > 1 && !is_pow2_pow5(2 * k)) --k;
+    P->K = k;
+  }
+  if (P->K < 1) fail(WFP_EDOMAIN, "K < 1 (dt too large)");
+  if ((double)P->K * P->dt > kPi * (1 + 1e-14)) fail(WFP_EDOMAIN, "K dt must not exceed pi");
+  P->NQ = P->W + P->p / 2;   // lags m = 0..W-1+p/2 carry weights
+  P->NH = P->NQ;             // density levels kept: sigma^{L-1} .. sigma^{L-NQ}
+  P->ngl = par->n_gl_local > 0 ? par->n_gl_local : P->W;
+  P->ngpq = par->n_gl_pq > 0 ? par->n_gl_pq : 32;
+  P->width = par->nufft_width > 0 ? par->nufft_width : 16;
+  if (P->width > 64 || P->width < 4) fail(WFP_EINVAL, "nufft_width must be 4..64");
+  P->h_rbc = kPi / (double)P->K;
+  P->delta_s = P->W * P->h_rbc;
+  P->rbc_period = par->rbc_period > 0 ? par->rbc_period
+                                      : (int)std::ceil(P->W * P->h_rbc / P->dt - 1e-12);
+  // fine grid: smallest 2^a 5^b >= 2 (2K+1), even
+  int64_t nf = 2 * (2 * P->K + 1);
+  while (!(is_pow2_pow5(nf) && nf % 2 == 0)) ++nf;
+  P->nf = (int)nf;
+  P->nfh = (int)(nf / 2);
+  P->hf = kTwoPi / (double)nf;
+  P->alpha_es = 0.5 * P->width * P->hf;
+  P->beta_es = 2.30 * P->width;
+  P->fft_nf = make_fft_plan(P->nfh);
+  P->lds_nf = (size_t)P->nfh * sizeof(double2);
+  if (P->lds_nf > 160 * 1024) fail(WFP_EDOMAIN, "fine grid too long for the single-workgroup FFT");
+  if (!periodic) {
+    if (!is_pow2_pow5(2 * P->K)) fail(WFP_EDOMAIN, "free space needs 2K = 2^a 5^b");
+    P->fft_rbc = make_fft_plan(P->K);
+    P->lds_rbc = (size_t)P->K * sizeof(double2);
+    if (P->lds_rbc > 160 * 1024) fail(WFP_EDOMAIN, "RBC grid too long for the single-workgroup FFT");
+  }
+
+  hipStream_t s = P->stream;
+  // ---- scatterers: validate, sort ----
+  std::vector<double> xh(prob->x, prob->x + M), bh(prob->beta, prob->beta + M);
+  const double margin = 3.0 * std::max(P->delta, P->delta_s);
+  const double olo = -kPi + margin, ohi = kPi - margin;
+  for (int64_t j = 0; j < M; ++j) {
+    if (!std::isfinite(xh[j]) || !std::isfinite(bh[j])) fail(WFP_EINVAL, "non-finite x or beta");
+    if (!(bh[j] > 0)) fail(WFP_EINVAL, "beta must be positive");
+    if (xh[j] < -kPi || xh[j] >= kPi) fail(WFP_EINVAL, "x must lie in [-pi, pi)");
+    if (!periodic && (xh[j] < olo || xh[j] > ohi)) fail(WFP_EDOMAIN, "free space: scatterer outside Omega");
+  }
+  std::vector<double> xrh(prob->x_recv ? prob->x_recv : nullptr, prob->x_recv ? prob->x_recv + P->R : nullptr);
+  for (double v : xrh) {
+    if (!std::isfinite(v) || v < -kPi || v >= kPi) fail(WFP_EINVAL, "receiver outside [-pi, pi)");
+    if (!periodic && (v < olo || v > ohi)) fail(WFP_EDOMAIN, "free space: receiver outside Omega");
+  }
+  for (int i = 0; i < prob->n_packets * 5; ++i)
+    if (!std::isfinite(prob->packets[i])) fail(WFP_EINVAL, "non-finite packet");
+  for (int i = 0; i < prob->n_packets; ++i)
+    if (!(prob->packets[5 * i + 2] > 0)) fail(WFP_EINVAL, "packet width must be positive");
+  std::vector<int> perm(M);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return xh[a] < xh[c]; });
+  std::vector<double> xs(M), bs(M);
+  for (int64_t i = 0; i < M; ++i) {
+    xs[i] = xh[perm[i]];
+    bs[i] = bh[perm[i]];
+  }
+  P->perm_h = perm;
+
+  // ---- window series, Gauss-Legendre rules ----
+  WindowSeries ws = window_series(P->b, 128);
+  P->ncheb = ws.n;
+  {
+    const double one = cheb_eval(ws.phi.data(), ws.n, 1.0);
+    if (std::fabs(one - 1.0) > 1e-13) fail(WFP_EDOMAIN, "window series not normalised");
+  }
+  std::vector<double> glz, glw, gqz, gqw, gez, gew;
+  gauss_legendre(P->ngl, glz, glw);
+  gauss_legendre(P->ngpq, gqz, gqw);
+  gauss_legendre(256, gez, gew);
+
+  // ---- device allocations ----
+  P->xs = P->alloc<double>(M);
+  P->beta = P->alloc<double>(M);
+  P->perm = P->alloc<int>(M);
+  P->hist = P->alloc<double>((size_t)P->NH * M);
+  P->ring = P->alloc<double2>((size_t)P->W * (P->K + 1));
+  P->alpha = P->alloc<double2>(P->K + 1);
+  P->dalpha = P->alloc<double2>(P->K + 1);
+  P->pk = P->alloc<double>((size_t)P->W * (P->K + 1));
+  P->qk = P->alloc<double>((size_t)P->W * (P->K + 1));
+  P->rot = P->alloc<double>(3 * (P->K + 1));
+  P->dk1 = P->alloc<double>(P->K + 1);
+  P->dk2 = P->alloc<double>(P->K + 1);
+  P->tw = P->alloc<double2>(nf);
+  P->grid = P->alloc<double>(nf);
+  P->zbuf = P->alloc<double2>(P->nfh);
+  P->ybuf = P->alloc<double2>(P->K + 1);
+  P->grid2 = P->alloc<double>(nf);
+  P->cstart = P->alloc<int>(nf);
+  P->ccount = P->alloc<int>(nf);
+  P->rhs = P->alloc<double>(M);
+  P->cheb_phi = P->alloc<double>(ws.n);
+  P->cheb_g = P->alloc<double>(ws.n);
+  P->packets = P->alloc<double>(5 * prob->n_packets);
+  P->npk = prob->n_packets;
+  upload(P->xs, xs, s);
+  upload(P->beta, bs, s);
+  upload(P->perm, perm, s);
+  upload(P->cheb_phi, ws.phi, s);
+  upload(P->cheb_g, ws.g, s);
+  upload(P->packets, std::vector<double>(prob->packets, prob->packets + 5 * prob->n_packets), s);
+
+  // ---- twiddles e^{-2 pi i t / nf} ----
+  {
+    std::vector<double2> tw(nf);
+    for (int64_t t = 0; t < nf; ++t) {
+      const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)nf;
+      tw[t] = make_double2((double)std::cos(a), (double)std::sin(a));
+    }
+    upload(P->tw, tw, s);
+  }
+  // ---- NUFFT deconvolution: Psi_hat(k) = alpha int_{-1}^{1} psi(z) cos(k alpha z) dz ----
+  {
+    std::vector<double> d1(P->K + 1), d2(P->K + 1), psi(256);
+    for (int q = 0; q < 256; ++q) psi[q] = std::exp(P->beta_es * (std::sqrt(1.0 - gez[q] * gez[q]) - 1.0));
+    for (int64_t k = 0; k <= P->K; ++k) {
+      long double acc = 0;
+      for (int q = 0; q < 256; ++q) acc += (long double)gew[q] * psi[q] * std::cos((double)k * P->alpha_es * gez[q]);
+      const double ph = P->alpha_es * (double)acc;
+      const double sg = (k & 1) ? -1.0 : 1.0;
+      d1[k] = sg * P->hf / (kTwoPi * ph);
+      d2[k] = sg * P->hf / ph;
+    }
+    upload(P->dk1, d1, s);
+    upload(P->dk2, d2, s);
+  }
+  // ---- p_k, q_k tables and the propagator ----
+  {
+    std::vector<double> mu(P->ngpq), wmu(P->ngpq), dph((size_t)P->W * P->ngpq), ddph((size_t)P->W * P->ngpq);
+    for (int q = 0; q < P->ngpq; ++q) {
+      mu[q] = 0.5 * P->dt * (gqz[q] + 1.0);
+      wmu[q] = 0.5 * P->dt * gqw[q];
+    }
+    for (int m = 0; m < P->W; ++m)
+      for (int q = 0; q < P->ngpq; ++q) {
+        const double tau = m * P->dt + mu[q];
+        const double sv = 2.0 * tau / P->delta - 1.0;
+        dph[m * P->ngpq + q] = (2.0 / P->delta) * cheb_eval(ws.g.data(), ws.n, sv);
+        ddph[m * P->ngpq + q] = (4.0 / (P->delta * P->delta)) * cheb_eval(ws.dg.data(), ws.n, sv);
+      }
+    double* dmu = P->alloc<double>(P->ngpq);
+    double* dwmu = P->alloc<double>(P->ngpq);
+    double* ddph_d = P->alloc<double>(ddph.size());
+    double* dph_d = P->alloc<double>(dph.size());
+    upload(dmu, mu, s);
+    upload(dwmu, wmu, s);
+    upload(dph_d, dph, s);
+    upload(ddph_d, ddph, s);
+    hipLaunchKernelGGL(k_pq_tables, dim3(nblk(P->K + 1, 128)), dim3(128), 0, s, P->K, P->W, P->ngpq, P->dt,
+                       dph_d, ddph_d, dmu, dwmu, P->pk, P->qk, P->rot);
+    HIPCHK(hipGetLastError());
+  }
+  // ---- spreading ranges: sources within the kernel support of each cell ----
+  {
+    std::vector<int> cs(nf), cc(nf);
+    for (int64_t i = 0; i < nf; ++i) {
+      const double xc = -kPi + (double)i * P->hf;
+      source_range(xs, xc, P->alpha_es * (1.0 + 1e-12), true, true, cs[i], cc[i]);
+    }
+    upload(P->cstart, cs, s);
+    upload(P->ccount, cc, s);
+  }
+  // ---- neighbour rows of the scatterers and receivers ----
+  std::vector<int> nbs(M), nbc(M), ns(M), nc(M);
+  std::vector<int64_t> qo(M);
+  int64_t tot = 0;
+  for (int64_t j = 0; j < M; ++j) {
+    source_range(xs, xs[j], P->delta, periodic, false, nbs[j], nbc[j]);
+    source_range(xs, xs[j], P->dt, periodic, false, ns[j], nc[j]);
+    qo[j] = tot;
+    tot += (int64_t)nbc[j] * P->NQ;
+    P->n_pairs += nbc[j];
+  }
+  P->nb_start = P->alloc<int>(M);
+  P->nb_count = P->alloc<int>(M);
+  P->near_start = P->alloc<int>(M);
+  P->near_count = P->alloc<int>(M);
+  P->qoff = P->alloc<int64_t>(M);
+  P->Q = P->alloc<double>(tot);
+  upload(P->nb_start, nbs, s);
+  upload(P->nb_count, nbc, s);
+  upload(P->near_start, ns, s);
+  upload(P->near_count, nc, s);
+  upload(P->qoff, qo, s);
+  std::vector<double> lagw(P->p);
+  {
+    for (int r = 0; r < P->p; ++r) {
+      double f = 1.0;
+      for (int q = 0; q < P->p; ++q)
+        if (q != r) f *= (double)(r - q);
+      lagw[r] = 1.0 / f;
+    }
+  }
+  double* lagw_d = P->alloc<double>(P->p);
+  double* glz_d = P->alloc<double>(P->ngl);
+  double* glw_d = P->alloc<double>(P->ngl);
+  upload(lagw_d, lagw, s);
+  upload(glz_d, glz, s);
+  upload(glw_d, glw, s);
+  std::vector<double> half_beta(M);
+  for (int64_t j = 0; j < M; ++j) half_beta[j] = 0.5 * bs[j];
+  double* hb_d = P->alloc<double>(M);
+  upload(hb_d, half_beta, s);
+  const int qthreads = 128;
+  P->lds_qw = (size_t)P->NQ * qthreads * sizeof(double);
+  auto launch_qw = [&](int nrows, const double* xt, const int* st, const int* cnt, const int64_t* off,
+                       const double* scale, double* Qd) {
+    if (nrows == 0) return;
+#define WFP_QW(PP)                                                                                    \
+  hipLaunchKernelGGL(k_local_weights<PP>, dim3(nrows), dim3(qthreads), P->lds_qw, s, nrows, xt, P->xs,   \
+                     (int)M, st, cnt, off, scale, periodic ? 1 : 0, P->dt, P->delta, P->W, P->NQ, P->ngl, \
+                     glz_d, glw_d, P->cheb_phi, P->ncheb, lagw_d, Qd)
+    switch (P->p) {
+      case 2: WFP_QW(2); break;
+      case 4: WFP_QW(4); break;
+      case 6: WFP_QW(6); break;
+      case 8: WFP_QW(8); break;
+      case 10: WFP_QW(10); break;
+      default: WFP_QW(12); break;
+    }
+#undef WFP_QW
+    HIPCHK(hipGetLastError());
+  };
+  launch_qw((int)M, P->xs, P->nb_start, P->nb_count, P->qoff, hb_d, P->Q);
+  if (P->R > 0) {
+    std::vector<int> rs(P->R), rc(P->R);
+    std::vector<int64_t> ro(P->R);
+    int64_t rt = 0;
+    for (int64_t r = 0; r < P->R; ++r) {
+      source_range(xs, xrh[r], P->delta, periodic, false, rs[r], rc[r]);
+      ro[r] = rt;
+      rt += (int64_t)rc[r] * P->NQ;
+      P->n_pairs_recv += rc[r];
+    }
+    P->xr = P->alloc<double>(P->R);
+    P->rnb_start = P->alloc<int>(P->R);
+    P->rnb_count = P->alloc<int>(P->R);
+    P->rqoff = P->alloc<int64_t>(P->R);
+    P->Qr = P->alloc<double>(rt);
+    upload(P->xr, xrh, s);
+    upload(P->rnb_start, rs, s);
+    upload(P->rnb_count, rc, s);
+    upload(P->rqoff, ro, s);
+    std::vector<double> halfs(P->R, 0.5);
+    double* hr_d = P->alloc<double>(P->R);
+    upload(hr_d, halfs, s);
+    launch_qw((int)P->R, P->xr, P->rnb_start, P->rnb_count, P->rqoff, hr_d, P->Qr);
+  }
+  // ---- solve: contraction bound, sweep count, tiles with halos ----
+  {
+    double* cr = P->alloc<double>(M);
+    hipLaunchKernelGGL(k_row_contraction, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->nb_start, P->nb_count,
+                       P->qoff, P->Q, P->near_start, P->near_count, cr);
+    HIPCHK(hipGetLastError());
+    std::vector<double> crh(M);
+    HIPCHK(hipMemcpyAsync(crh.data(), cr, M * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double rho = 0;
+    for (double v : crh) rho = std::max(rho, v);
+    P->contraction = rho;
+    if (par->solve_iters > 0) {
+      P->iters = par->solve_iters;
+    } else if (rho <= 0) {
+      P->iters = 1;
+    } else {
+      if (rho >= 0.9) fail(WFP_EDOMAIN, "per-step system too weakly diagonally dominant for the Jacobi solve");
+      P->iters = 1 + (int)std::ceil(std::log(1e-18) / std::log(rho));
+    }
+    const double reach = P->iters * P->dt * (1.0 + 1e-9) + 1e-12;
+    P->T = 256;
+    P->ntile = (int)((M + P->T - 1) / P->T);
+    std::vector<int> es(P->ntile), el(P->ntile);
+    int ext_max = 0;
+    for (int t = 0; t < P->ntile; ++t) {
+      const int64_t a = (int64_t)t * P->T, c = std::min<int64_t>(M, a + P->T) - 1;
+      int s0, c0, s1, c1;
+      source_range(xs, xs[a], reach, periodic, true, s0, c0);
+      source_range(xs, xs[c], reach, periodic, true, s1, c1);
+      // extended range: from the first source near the tile's left end to the
+      // last source near its right end (circular), at least covering the tile
+      int64_t lo = s0, hi = (int64_t)s1 + c1;  // hi exclusive, may exceed M
+      if (!periodic) {
+        lo = std::min<int64_t>(lo, a);
+        hi = std::max<int64_t>(hi, c + 1);
+        es[t] = (int)lo;
+        el[t] = (int)(hi - lo);
+      } else {
+        // express both ends relative to the tile start a, going left / right
+        int64_t left = (a - lo + M) % M;          // points to the left of a
+        if (c0 >= M) left = 0;
+        int64_t right = (hi - 1 - c + 2 * M) % M;  // points to the right of c
+        if (c1 >= M) right = 0;
+        int64_t len = left + (c - a + 1) + right;
+        if (c0 >= M || c1 >= M || len >= M) {
+          es[t] = 0;
+          el[t] = (int)M;
+        } else {
+          es[t] = (int)((a - left + M) % M);
+          el[t] = (int)len;
+        }
+      }
+      ext_max = std::max(ext_max, el[t]);
+    }
+    P->ext_max = ext_max;
+    P->lds_jac = 2 * (size_t)ext_max * sizeof(double);
+    if (P->lds_jac > 160 * 1024) fail(WFP_EDOMAIN, "solve halo too large for one workgroup");
+    P->ext_start = P->alloc<int>(P->ntile);
+    P->ext_len = P->alloc<int>(P->ntile);
+    upload(P->ext_start, es, s);
+    upload(P->ext_len, el, s);
+  }
+  if (!periodic) {
+    P->tw_rbc = P->alloc<double2>(2 * P->K);
+    std::vector<double2> tw(2 * P->K);
+    for (int64_t t = 0; t < 2 * P->K; ++t) {
+      const long double a = -3.14159265358979323846264338327950288L * (long double)t / (long double)P->K;
+      tw[t] = make_double2((double)std::cos(a), (double)std::sin(a));
+    }
+    upload(P->tw_rbc, tw, s);
+    P->rbc_u = P->alloc<double>(2 * P->K);
+    P->rbc_v = P->alloc<double>(2 * P->K);
+  }
+  // kernels with more than 64 KB of LDS
+  HIPCHK(hipFuncSetAttribute((const void*)k_fft_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_fft_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_rbc_to_grid, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_rbc_to_modes, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  zero_state(P);
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, double* u_recv_out) {
+  hipStream_t s = P->stream;
+  const bool periodic = P->boundary == WFP_PERIODIC;
+  const Packets pk{P->npk, periodic ? 1 : 0, P->packets};
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t L = P->level + i;
+    const double t = (double)L * P->dt;
+    const double* sig_prev = P->hist + (int64_t)(((L - 1) % P->NH + P->NH) % P->NH) * P->M;
+    hipLaunchKernelGGL(k_spread, dim3(nblk(P->nf, 256)), dim3(256), 0, s, P->nf, P->hf, 1.0 / P->alpha_es,
+                       P->beta_es, P->xs, sig_prev, (int)P->M, P->cstart, P->ccount, P->grid);
+    hipLaunchKernelGGL(k_fft_r2c, dim3(1), dim3(kFftThreads), P->lds_nf, s, P->fft_nf, (const double2*)P->grid,
+                       P->tw, 2, P->zbuf);
+    hipLaunchKernelGGL(k_modes, dim3(nblk(P->K + 1, 256)), dim3(256), 0, s, P->K, P->W, P->nfh, L, P->zbuf,
+                       P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, P->ring, P->alpha, P->dalpha, P->ybuf);
+    if (!periodic && L > 0 && L % P->rbc_period == 0) {
+      hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->alpha,
+                         P->dalpha, P->tw_rbc, (double2*)P->rbc_u, (double2*)P->rbc_v);
+      hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->W,
+                         P->h_rbc, P->delta_s, P->cheb_phi, P->cheb_g, P->ncheb, P->rbc_u, P->rbc_v, P->tw_rbc,
+                         P->dk2, P->alpha, P->dalpha, P->ybuf);
+    }
+    hipLaunchKernelGGL(k_fft_c2r, dim3(1), dim3(kFftThreads), P->lds_nf, s, P->fft_nf, P->K, P->ybuf, P->tw, 2,
+                       (double2*)P->grid2);
+    hipLaunchKernelGGL(k_local_rhs, dim3(nblk(P->M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)P->M,
+                       P->NQ, P->NH, L, t, P->xs, P->beta, P->nb_start, P->nb_count, P->qoff, P->Q, P->hist,
+                       P->grid2, P->nf, P->hf, 1.0 / P->alpha_es, P->beta_es, P->width, pk, P->rhs);
+    double* slot = P->hist + (int64_t)(L % P->NH) * P->M;
+    double* save = (sigma_out && i % save_every == 0) ? sigma_out + (i / save_every) * P->M : nullptr;
+    hipLaunchKernelGGL(k_jacobi, dim3(P->ntile), dim3(256), P->lds_jac, s, (int)P->M, P->T, P->iters,
+                       P->ext_max, P->ext_start, P->ext_len, P->nb_start, P->qoff, P->Q, P->near_start,
+                       P->near_count, P->rhs, slot, save, P->perm);
+    if (P->R > 0 && u_recv_out) {
+      hipLaunchKernelGGL(k_receivers, dim3(nblk(P->R, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)P->R,
+                         (int)P->M, P->NQ, P->NH, L, P->xr, P->rnb_start, P->rnb_count, P->rqoff, P->Qr,
+                         P->hist, P->grid2, P->nf, P->hf, 1.0 / P->alpha_es, P->beta_es, P->width,
+                         u_recv_out + i * P->R);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  P->level += n;
+}
+
+wfp_status guard(const std::function<void()>& f) {
+  try {
+    f();
+    return WFP_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return WFP_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return WFP_EHIP;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+wfp_status wfp_plan_create(const wfp_problem* prob, const wfp_params* par, void* stream, wfp_plan** out) {
+  if (!out) {
+    g_last_error = "out is NULL";
+    return WFP_EINVAL;
+  }
+  *out = nullptr;
+  wfp_plan* P = nullptr;
+  wfp_status st = guard([&] {
+    validate(prob, par);
+    P = new wfp_plan();
+    HIPCHK(hipGetDevice(&P->device));
+    P->stream = (hipStream_t)stream;
+    build(P, prob, par);
+  });
+  if (st != WFP_OK) {
+    delete P;
+    return st;
+  }
+  *out = P;
+  return WFP_OK;
+}
+
+void wfp_plan_destroy(wfp_plan* plan) {
+  if (!plan) return;
+  (void)hipStreamSynchronize(plan->stream);
+  delete plan;
+}
+
+wfp_status wfp_plan_info(const wfp_plan* P, wfp_info* info) {
+  if (!P || !info) {
+    g_last_error = "NULL argument";
+    return WFP_EINVAL;
+  }
+  std::memset(info, 0, sizeof(*info));
+  info->M = P->M;
+  info->R = P->R;
+  info->K = P->K;
+  info->n_fine = P->nf;
+  info->n_pairs = P->n_pairs;
+  info->n_pairs_recv = P->n_pairs_recv;
+  info->level = P->level;
+  info->W = P->W;
+  info->p = P->p;
+  info->m_max = P->NH;
+  info->n_gl_local = P->ngl;
+  info->rbc_period = P->rbc_period;
+  info->nufft_width = P->width;
+  info->solve_iters = P->iters;
+  info->boundary = P->boundary;
+  info->dt = P->dt;
+  info->delta = P->delta;
+  info->b = P->b;
+  info->solve_contraction = P->contraction;
+  info->device_bytes = P->dev_bytes;
+  return WFP_OK;
+}
+
+wfp_status wfp_run(wfp_plan* P, int64_t n_steps, double* sigma_out, int64_t save_every, double* u_recv_out) {
+  if (!P || n_steps < 0) {
+    g_last_error = "bad plan or step count";
+    return WFP_EINVAL;
+  }
+  if (sigma_out && save_every < 1) {
+    g_last_error = "save_every must be >= 1";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(P->device));
+    run_levels(P, n_steps, sigma_out, sigma_out ? save_every : 1, u_recv_out);
+  });
+}
+
+wfp_status wfp_get_state(wfp_plan* P, int64_t* level, double* hist, double* ring, double* alpha,
+                         double* dalpha) {
+  if (!P) {
+    g_last_error = "NULL plan";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(P->device));
+    hipStream_t s = P->stream;
+    if (level) *level = P->level;
+    if (hist) {
+      const int64_t n = (int64_t)P->NH * P->M;
+      hipLaunchKernelGGL(k_hist_io, dim3(nblk(n, 256)), dim3(256), 0, s, (int)P->M, P->NH, P->level, 1,
+                         P->hist, hist, P->perm);
+    }
+    if (ring) {
+      const int64_t n = (int64_t)P->W * (P->K + 1);
+      hipLaunchKernelGGL(k_ring_io, dim3(nblk(n, 256)), dim3(256), 0, s, P->K, P->W, P->level, 1, P->ring,
+                         (double2*)ring);
+    }
+    if (alpha)
+      HIPCHK(hipMemcpyAsync(alpha, P->alpha, (P->K + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    if (dalpha)
+      HIPCHK(hipMemcpyAsync(dalpha, P->dalpha, (P->K + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+wfp_status wfp_set_state(wfp_plan* P, int64_t level, const double* hist, const double* ring,
+                         const double* alpha, const double* dalpha) {
+  if (!P || !hist || !ring || !alpha || !dalpha || level < 0) {
+    g_last_error = "set_state needs a plan, level >= 0 and all four arrays";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(P->device));
+    hipStream_t s = P->stream;
+    const int64_t nh = (int64_t)P->NH * P->M;
+    hipLaunchKernelGGL(k_hist_io, dim3(nblk(nh, 256)), dim3(256), 0, s, (int)P->M, P->NH, level, 0, P->hist,
+                       const_cast<double*>(hist), P->perm);
+    const int64_t nr = (int64_t)P->W * (P->K + 1);
+    hipLaunchKernelGGL(k_ring_io, dim3(nblk(nr, 256)), dim3(256), 0, s, P->K, P->W, level, 0, P->ring,
+                       (double2*)const_cast<double*>(ring));
+    HIPCHK(hipMemcpyAsync(P->alpha, alpha, (P->K + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(P->dalpha, dalpha, (P->K + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipGetLastError());
+    P->level = level;
+  });
+}
+
+wfp_status wfp_reset(wfp_plan* P) {
+  if (!P) {
+    g_last_error = "NULL plan";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(P->device));
+    zero_state(P);
+  });
+}
+
+const char* wfp_status_string(wfp_status s) {
+  switch (s) {
+    case WFP_OK: return "ok";
+    case WFP_EINVAL: return "invalid argument";
+    case WFP_EDOMAIN: return "outside the supported domain";
+    case WFP_ENOMEM: return "out of memory";
+    case WFP_EHIP: return "HIP runtime error";
+    case WFP_ESTATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* wfp_last_error(void) { return g_last_error.c_str(); }
+
+int32_t wfp_abi_version(void) { return WFP_ABI_VERSION; }
+
+}  // extern "C"

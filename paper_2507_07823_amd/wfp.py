@@ -1,0 +1,220 @@
+"""Python binding of libwfp (include/wfp.h): argument marshalling only.
+
+Every step of the march runs in the HIP library; this module never computes
+any part of the method.  Device arrays are torch tensors on the current CUDA
+(HIP) device; problem data is passed as host numpy arrays and copied by the
+library.  Importing this module does not touch the GPU; ``load_library``
+raises if libwfp.so has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwfp.so")
+
+WFP_OK = 0
+WFP_EINVAL = -1
+WFP_EDOMAIN = -2
+WFP_ENOMEM = -3
+WFP_EHIP = -4
+WFP_ESTATE = -5
+PERIODIC = 0
+FREE_SPACE = 1
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("x", _c_dp), ("beta", _c_dp), ("boundary", ctypes.c_int32),
+                ("n_packets", ctypes.c_int32), ("packets", _c_dp), ("R", ctypes.c_int64),
+                ("x_recv", _c_dp)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("eps_window", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("W", ctypes.c_int32), ("p", ctypes.c_int32), ("K", ctypes.c_int64),
+                ("n_gl_local", ctypes.c_int32), ("n_gl_pq", ctypes.c_int32), ("rbc_period", ctypes.c_int32),
+                ("nufft_width", ctypes.c_int32), ("solve_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("R", ctypes.c_int64), ("K", ctypes.c_int64), ("n_fine", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64), ("n_pairs_recv", ctypes.c_int64), ("level", ctypes.c_int64),
+                ("W", ctypes.c_int32), ("p", ctypes.c_int32), ("m_max", ctypes.c_int32),
+                ("n_gl_local", ctypes.c_int32), ("rbc_period", ctypes.c_int32), ("nufft_width", ctypes.c_int32),
+                ("solve_iters", ctypes.c_int32), ("boundary", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("delta", ctypes.c_double), ("b", ctypes.c_double), ("solve_contraction", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library():
+    """Load libwfp.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libwfp.so not built ({LIB_PATH}); run python -m paper_2507_07823_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.wfp_plan_create.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    lib.wfp_plan_create.restype = ctypes.c_int32
+    lib.wfp_plan_destroy.argtypes = [vp]
+    lib.wfp_plan_destroy.restype = None
+    lib.wfp_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
+    lib.wfp_plan_info.restype = ctypes.c_int32
+    lib.wfp_run.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
+    lib.wfp_run.restype = ctypes.c_int32
+    lib.wfp_get_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp]
+    lib.wfp_get_state.restype = ctypes.c_int32
+    lib.wfp_set_state.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
+    lib.wfp_set_state.restype = ctypes.c_int32
+    lib.wfp_reset.argtypes = [vp]
+    lib.wfp_reset.restype = ctypes.c_int32
+    lib.wfp_status_string.argtypes = [ctypes.c_int32]
+    lib.wfp_status_string.restype = ctypes.c_char_p
+    lib.wfp_last_error.argtypes = []
+    lib.wfp_last_error.restype = ctypes.c_char_p
+    lib.wfp_abi_version.argtypes = []
+    lib.wfp_abi_version.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+class WFPError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"wfp status {status}: {message}")
+        self.status = status
+
+
+def _check(status):
+    if status != WFP_OK:
+        lib = load_library()
+        raise WFPError(status, lib.wfp_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dbl(a):
+    return a.ctypes.data_as(_c_dp) if a is not None and a.size else None
+
+
+def make_params(dt, **kw):
+    prm = Params()
+    prm.dt = float(dt)
+    for k, v in kw.items():
+        if not hasattr(prm, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(prm, k, v)
+    return prm
+
+
+def _current_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A WFP plan on the current device (all precompute done at construction).
+
+    problem: dict with x, beta, packets (n, 5), boundary, x_recv (optional)
+    dt and keyword parameters as in ``wfp_params``.
+    """
+
+    def __init__(self, problem, dt, stream=None, **params):
+        lib = load_library()
+        self._lib = lib
+        self._keep = []
+        x = np.ascontiguousarray(problem["x"], dtype=np.float64)
+        beta = np.ascontiguousarray(problem["beta"], dtype=np.float64)
+        packets = np.ascontiguousarray(np.atleast_2d(problem["packets"]), dtype=np.float64)
+        xr = problem.get("x_recv")
+        xr = np.zeros(0) if xr is None else np.ascontiguousarray(xr, dtype=np.float64)
+        self._keep += [x, beta, packets, xr]
+        pr = Problem()
+        pr.M = x.size
+        pr.x = _dbl(x)
+        pr.beta = _dbl(beta)
+        pr.boundary = int(problem.get("boundary", PERIODIC))
+        pr.n_packets = packets.shape[0]
+        pr.packets = _dbl(packets)
+        pr.R = xr.size
+        pr.x_recv = _dbl(xr)
+        prm = make_params(dt, **params)
+        self._stream = stream if stream is not None else _current_stream()
+        h = ctypes.c_void_p()
+        _check(lib.wfp_plan_create(ctypes.byref(pr), ctypes.byref(prm), self._stream, ctypes.byref(h)))
+        self._h = h
+        self.info = self.query_info()
+
+    def query_info(self):
+        info = Info()
+        _check(self._lib.wfp_plan_info(self._h, ctypes.byref(info)))
+        return info.as_dict()
+
+    @property
+    def level(self):
+        return self.query_info()["level"]
+
+    def run(self, n_steps, sigma_out=None, save_every=1, u_recv_out=None):
+        """March n_steps levels into caller-provided device tensors (float64)."""
+        for t in (sigma_out, u_recv_out):
+            if t is not None:
+                assert t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous() and t.is_cuda
+        if sigma_out is not None:
+            rows = (n_steps + save_every - 1) // save_every
+            assert sigma_out.numel() >= rows * self.info["M"]
+        if u_recv_out is not None:
+            assert u_recv_out.numel() >= n_steps * self.info["R"]
+        _check(self._lib.wfp_run(self._h, int(n_steps), _ptr(sigma_out), int(save_every), _ptr(u_recv_out)))
+
+    def march(self, n_steps, save_every=1, receivers=True):
+        """Allocate outputs and march; returns (sigma rows, receiver values or None)."""
+        import torch
+        M, R = self.info["M"], self.info["R"]
+        rows = (n_steps + save_every - 1) // save_every
+        sig = torch.empty((rows, M), dtype=torch.float64, device="cuda")
+        u = torch.empty((n_steps, R), dtype=torch.float64, device="cuda") if (receivers and R) else None
+        self.run(n_steps, sig, save_every, u)
+        return sig, u
+
+    def get_state(self):
+        import torch
+        i = self.query_info()
+        M, K, W, mm = i["M"], i["K"], i["W"], i["m_max"]
+        hist = torch.empty((mm, M), dtype=torch.float64, device="cuda")
+        ring = torch.empty((W, K + 1, 2), dtype=torch.float64, device="cuda")
+        a = torch.empty((K + 1, 2), dtype=torch.float64, device="cuda")
+        da = torch.empty((K + 1, 2), dtype=torch.float64, device="cuda")
+        lvl = ctypes.c_int64()
+        _check(self._lib.wfp_get_state(self._h, ctypes.byref(lvl), _ptr(hist), _ptr(ring), _ptr(a), _ptr(da)))
+        return dict(L=lvl.value, hist=hist, ring=ring, alpha=a, dalpha=da)
+
+    def set_state(self, level, hist, ring, alpha, dalpha):
+        for t in (hist, ring, alpha, dalpha):
+            assert t.dtype.itemsize == 8 if hasattr(t.dtype, "itemsize") else True
+            assert t.is_contiguous() and t.is_cuda
+        _check(self._lib.wfp_set_state(self._h, int(level), _ptr(hist), _ptr(ring), _ptr(alpha), _ptr(dalpha)))
+
+    def reset(self):
+        _check(self._lib.wfp_reset(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.wfp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

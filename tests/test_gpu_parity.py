@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Metric: rho(a, b) = max |a - b| / max |b| over every compared entry; the bar
+is 1e-10 (both sides run the same discrete scheme in FP64; the HIP path
+replaces exponential sums by NUFFTs of ~1e-15 relative accuracy and the LU
+solve by converged Jacobi sweeps).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.march import Oracle, incident_driving
+from oracle.params import FREE_SPACE, PERIODIC, Params
+from paper_2507_07823_amd import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def rho(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def wfp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2507_07823_amd import wfp as w
+    w.load_library()
+    return w
+
+
+def oracle_for(prob, **kw):
+    prm = Params(dt=prob["dt"], boundary=prob["boundary"], **kw)
+    periodic = prob["boundary"] == PERIODIC
+    drv = incident_driving(prob["x"], prob["beta"], prob["packets"], periodic)
+    return Oracle(prob["x"], prob["beta"], prm, drv, x_recv=prob.get("x_recv"))
+
+
+def gpu_march(w, prob, n, save_every=1, **kw):
+    plan = w.Plan(prob, prob["dt"], **kw)
+    sig, u = plan.march(n, save_every)
+    import torch
+    torch.cuda.synchronize()
+    out = sig.cpu().numpy(), (None if u is None else u.cpu().numpy()), plan.info
+    plan.close()
+    return out
+
+
+def test_small_periodic_full_march(wfp):
+    p = workloads.small_periodic()
+    n = p["n_steps"] + 1
+    say(f"case small_periodic M={p['x'].size} levels={n}")
+    g, _, info = gpu_march(wfp, p, n)
+    o, _ = oracle_for(p).run(n)
+    assert info["K"] == 314 and info["W"] == 35 and info["m_max"] == 39
+    r = rho(g, o)
+    say(f"rho={r:.3e} iters={info['solve_iters']}")
+    assert r < TOL
+
+
+def _state_to_gpu(st):
+    import torch
+    c = lambda z: torch.from_numpy(np.ascontiguousarray(np.stack([z.real, z.imag], -1))).cuda()
+    return dict(hist=torch.from_numpy(np.ascontiguousarray(st["hist"])).cuda(), ring=c(st["ring"]),
+                alpha=c(st["alpha"]), dalpha=c(st["dalpha"]))
+
+
+def _state_from_gpu(st):
+    c = lambda t: t.cpu().numpy()[..., 0] + 1j * t.cpu().numpy()[..., 1]
+    return dict(L=st["L"], hist=st["hist"].cpu().numpy(), ring=c(st["ring"]), alpha=c(st["alpha"]),
+                dalpha=c(st["dalpha"]))
+
+
+@pytest.mark.parametrize("boundary", [PERIODIC, FREE_SPACE])
+def test_steps_from_synthetic_state(wfp, boundary):
+    """Both sides start from the same seeded mid-run state and advance a few
+    levels; every state component is compared (spectrum ring -> type-1 NUFFT
+    + FFT; alpha -> FIR + propagator (+ RBC); sigma -> type-2, local sum,
+    driving data and solve).  Several solve tiles and a ragged last tile."""
+    import torch
+    rng = np.random.default_rng(11)
+    M = 1100
+    if boundary == PERIODIC:
+        dt = 2e-3
+        x = rng.uniform(-math.pi, math.pi, M)
+    else:
+        dt = 5e-3
+        x = rng.uniform(-2.0, 2.0, M)
+    beta = rng.uniform(1, 10, M)
+    pk = np.array([[1.0, -1.0, 0.1, 20.0, 0.3], [0.5, 0.5, 0.2, 0.0, 0.0]])
+    p = dict(x=x, beta=beta, packets=pk, boundary=boundary, dt=dt, x_recv=np.zeros(0))
+    o = oracle_for(p)
+    prm = o.prm
+    st = workloads.random_state(5, M, prm.K, prm.W, prm.m_max)
+    # start at a level where the RBC fires after the first step (free space)
+    L0 = 3 * prm.rbc_period - 1 if boundary == FREE_SPACE else 1234
+    plan = wfp.Plan(p, dt)
+    say(f"case synthetic_state boundary={boundary} M={M} K={prm.K} L0={L0}")
+    gst = _state_to_gpu(st)
+    plan.set_state(L0, gst["hist"], gst["ring"], gst["alpha"], gst["dalpha"])
+    o.set_state(dict(L=L0, **st))
+    for step in range(3):
+        plan.run(1)
+        o.step()
+        torch.cuda.synchronize()
+        g = _state_from_gpu(plan.get_state())
+        e = o.get_state()
+        assert g["L"] == e["L"]
+        rs = rho(g["ring"][0], e["ring"][0])
+        ra = rho(g["alpha"], e["alpha"])
+        rd = rho(g["dalpha"], e["dalpha"])
+        rh = rho(g["hist"][0], e["hist"][0])
+        say(f"step {step}: ring {rs:.2e} alpha {ra:.2e} dalpha {rd:.2e} sigma {rh:.2e}")
+        assert rs < 1e-12 and ra < 1e-12 and rd < 1e-12 and rh < 1e-12
+        assert rho(g["hist"][:step + 1], e["hist"][:step + 1]) < 1e-12
+        assert np.array_equal(g["hist"][step + 1:], e["hist"][step + 1:])   # inputs, moved untouched
+    plan.close()
+
+
+def test_receivers_small(wfp):
+    p = workloads.periodic_single_pulse(21, 24, 0.01, 500, n_recv=9)
+    p["x_recv"] = np.concatenate([p["x_recv"], [p["x"][3], p["x"][5] + 0.004, -3.1]])
+    n = 501
+    say(f"case receivers M=24 R={p['x_recv'].size}")
+    g, gu, _ = gpu_march(wfp, p, n)
+    o, ou = oracle_for(p).run(n)
+    say(f"rho sigma {rho(g, o):.2e} u {rho(gu, ou):.2e}")
+    assert rho(g, o) < TOL and rho(gu, ou) < TOL
+
+
+def test_free_space_with_rbc(wfp):
+    rng = np.random.default_rng(5)
+    M = 40
+    x = rng.uniform(-0.5, 1.5, M)
+    beta = rng.uniform(1, 10, M)
+    xr = np.array([-1.8, -0.2, 1.7])
+    p = dict(x=x, beta=beta, packets=np.array([[1.0, -2.5, 0.2, 0.0, 0.0]]), boundary=FREE_SPACE, dt=0.01,
+             x_recv=xr)
+    n = 1100
+    say(f"case free_space M={M} levels={n}")
+    g, gu, info = gpu_march(wfp, p, n)
+    o, ou = oracle_for(p).run(n)
+    assert info["K"] == 256 and info["rbc_period"] == 43
+    say(f"rho sigma {rho(g, o):.2e} u {rho(gu, ou):.2e}")
+    assert rho(g, o) < TOL and rho(gu, ou) < TOL
+
+
+def test_checkpoint_resume_is_bitwise(wfp):
+    import torch
+    p = workloads.small_periodic()
+    plan = wfp.Plan(p, p["dt"])
+    a1, _ = plan.march(150)
+    st = plan.get_state()
+    st = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in st.items()}
+    a2, _ = plan.march(200)
+    plan.reset()
+    b0, _ = plan.march(10)
+    plan.set_state(st["L"], st["hist"], st["ring"], st["alpha"], st["dalpha"])
+    b2, _ = plan.march(200)
+    torch.cuda.synchronize()
+    assert torch.equal(a2, b2)
+    plan.close()
+
+
+def test_save_every_ragged_and_order(wfp):
+    p = workloads.small_periodic()
+    g1, _, _ = gpu_march(wfp, p, 101, save_every=1)
+    g7, _, _ = gpu_march(wfp, p, 101, save_every=7)
+    assert g7.shape == (15, 16)
+    assert np.array_equal(g7, g1[::7])
+
+
+def test_edge_single_spring_and_close_pair(wfp):
+    """M = 1 (closed-form case) and two springs closer than dt (coupled solve)."""
+    for x, beta in [(np.array([1.0]), np.array([5.0])), (np.array([0.5, 0.5037, 1.2]), np.array([9.0, 7.0, 2.0]))]:
+        p = dict(x=x, beta=beta, packets=np.array([[1.0, -2.0, 0.3, 0.0, 0.0]]), boundary=PERIODIC, dt=0.01,
+                 x_recv=np.zeros(0))
+        g, _, info = gpu_march(wfp, p, 401)
+        o, _ = oracle_for(p).run(401)
+        say(f"edge M={x.size} rho={rho(g, o):.2e} iters={info['solve_iters']}")
+        assert rho(g, o) < TOL
+
+
+def test_interpolation_order_4(wfp):
+    p = workloads.periodic_single_pulse(8, 30, 0.01, 300)
+    g, _, _ = gpu_march(wfp, p, 301, p=4)
+    o, _ = oracle_for(p, p=4).run(301)
+    assert rho(g, o) < TOL

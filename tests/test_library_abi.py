@@ -1,0 +1,73 @@
+"""The C ABI library loads on a machine without a GPU, exports every function
+declared in include/wfp.h, and rejects invalid problems before any device
+call (host-side validation)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_07823_amd import wfp
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return wfp.load_library()
+
+
+def declared_functions(root):
+    text = open(os.path.join(root, "include", "wfp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wfp_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib, root):
+    names = declared_functions(root)
+    assert "wfp_plan_create" in names and "wfp_run" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_abi_version_and_strings(lib):
+    assert lib.wfp_abi_version() == 1
+    assert lib.wfp_status_string(wfp.WFP_EDOMAIN) == b"outside the supported domain"
+
+
+def _create(problem, dt, **kw):
+    return wfp.Plan(problem, dt, stream=ctypes.c_void_p(0), **kw)
+
+
+def _base():
+    return dict(x=np.array([0.1, 0.5]), beta=np.array([1.0, 2.0]), packets=np.array([[1.0, -2.0, 0.3, 0.0, 0.0]]),
+                boundary=wfp.PERIODIC)
+
+
+@pytest.mark.parametrize("mutate,dt,kw,code", [
+    (lambda p: p.update(x=np.array([0.1, math.nan])), 0.01, {}, wfp.WFP_EINVAL),
+    (lambda p: p.update(beta=np.array([1.0, -1.0])), 0.01, {}, wfp.WFP_EINVAL),
+    (lambda p: p.update(x=np.array([0.1, 3.5])), 0.01, {}, wfp.WFP_EINVAL),
+    (lambda p: None, -0.01, {}, wfp.WFP_EINVAL),
+    (lambda p: None, 0.01, {"p": 5}, wfp.WFP_EINVAL),
+    (lambda p: None, 0.01, {"K": 400}, wfp.WFP_EDOMAIN),          # K dt > pi
+    (lambda p: None, 0.1, {}, wfp.WFP_EDOMAIN),                   # delta = 35 dt >= pi
+    (lambda p: p.update(boundary=wfp.FREE_SPACE, x=np.array([0.1, 3.0])), 0.01, {}, wfp.WFP_EDOMAIN),
+    (lambda p: p.update(packets=np.array([[1.0, -2.0, 0.0, 0.0, 0.0]])), 0.01, {}, wfp.WFP_EINVAL),
+    (lambda p: p.update(x_recv=np.array([4.0])), 0.01, {}, wfp.WFP_EINVAL),
+])
+def test_invalid_problems_rejected_on_host(mutate, dt, kw, code):
+    p = _base()
+    mutate(p)
+    with pytest.raises(wfp.WFPError) as e:
+        _create(p, dt, **kw)
+    assert e.value.status == code
+
+
+def test_empty_problem_rejected(lib):
+    p = _base()
+    p["x"] = np.zeros(0)
+    p["beta"] = np.zeros(0)
+    with pytest.raises(wfp.WFPError) as e:
+        _create(p, 0.01)
+    assert e.value.status == wfp.WFP_EINVAL
