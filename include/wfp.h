@@ -99,7 +99,20 @@ typedef struct {
   int32_t W, p, m_max, n_gl_local, rbc_period, nufft_width, solve_iters, boundary;
   double dt, delta, b, solve_contraction;
   int64_t device_bytes;
+  int64_t n_weights_nonzero;   /* nonzero stored local weights of lag >= 1 (scatterer rows) */
+  int64_t n_weights_stored;    /* stored local weights of lag >= 1 (scatterer rows) */
 } wfp_info;
+
+/* Stages of one level, for wfp_get_profile. */
+#define WFP_STAGE_SPREAD 0     /* type-1 spreading onto the fine grid */
+#define WFP_STAGE_FFT_FWD 1    /* real-to-complex FFT of the fine grid */
+#define WFP_STAGE_MODES 2      /* deconvolution, spectra ring, FIR, propagator */
+#define WFP_STAGE_RBC 3        /* free-space RBC projection (two kernels) */
+#define WFP_STAGE_FFT_INV 4    /* complex-to-real FFT for the type-2 transform */
+#define WFP_STAGE_LOCAL 5      /* local sum + type-2 interpolation + driving data */
+#define WFP_STAGE_SOLVE 6      /* per-step solve */
+#define WFP_STAGE_RECV 7       /* receivers */
+#define WFP_N_STAGES 8
 
 /* Create a plan: validates the problem, sorts the springs, precomputes the
  * window, the one-step kernels p_k, q_k, the NUFFT deconvolution factors,
@@ -136,6 +149,14 @@ wfp_status wfp_get_state(wfp_plan* plan, int64_t* level, double* hist, double* r
                          double* alpha, double* dalpha);
 wfp_status wfp_set_state(wfp_plan* plan, int64_t level, const double* hist, const double* ring,
                          const double* alpha, const double* dalpha);
+
+/* Per-stage timing with HIP events recorded around every kernel of later
+ * wfp_run calls on the plan's stream (enable != 0 clears the accumulators;
+ * timing adds event overhead to the march).  wfp_get_profile synchronises the
+ * stream and returns, per stage, the summed kernel milliseconds and launch
+ * counts (arrays of WFP_N_STAGES; either may be NULL). */
+wfp_status wfp_set_profiling(wfp_plan* plan, int32_t enable);
+wfp_status wfp_get_profile(wfp_plan* plan, double* ms, int64_t* launches);
 
 /* Return the plan to level 0 with zero history (stream-ordered). */
 wfp_status wfp_reset(wfp_plan* plan);

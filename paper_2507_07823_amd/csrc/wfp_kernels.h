@@ -38,53 +38,71 @@ __global__ void k_local_weights(int nrows, const double* __restrict__ xt,
                                 int periodic, double dt, double delta, int W, int NQ, int ngl,
                                 const double* __restrict__ glz, const double* __restrict__ glw,
                                 const double* __restrict__ cheb_phi, int ncheb,
-                                const double* __restrict__ lagw, double* __restrict__ Q);
+                                const double* __restrict__ lagw, const int64_t* __restrict__ pbase,
+                                signed char* __restrict__ mlo, double* __restrict__ Q);
+
+__global__ void k_row_ranges(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ pbase,
+                             const signed char* __restrict__ mlo, unsigned* __restrict__ ac);
+__global__ void k_pack_weights(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
+                               const double* __restrict__ Q, const unsigned* __restrict__ ac,
+                               const int64_t* __restrict__ rowbase, double* __restrict__ Qc);
+__global__ void k_gather_solve(int64_t ne, const int64_t* __restrict__ eq, const double* __restrict__ Q,
+                               double* __restrict__ ev, int64_t nr, const int64_t* __restrict__ rq,
+                               double* __restrict__ rdinv);
 
 __global__ void k_row_contraction(int M, const int* __restrict__ nb_start,
                                   const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
                                   const double* __restrict__ Q, const int* __restrict__ near_start,
                                   const int* __restrict__ near_count, double* __restrict__ out);
 
+__global__ void k_count_nonzero(int M, int NQ, const int* __restrict__ nb_count,
+                                const int64_t* __restrict__ qoff, const double* __restrict__ Q,
+                                unsigned long long* __restrict__ out);
+
 // ---- per-level kernels ----
-__global__ void k_spread(int nf, double hf, double inv_alpha, double beta_es,
-                         const double* __restrict__ xs, const double* __restrict__ sig, int M,
+__global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
+                            const int64_t* __restrict__ rowbase, const unsigned* __restrict__ ac,
+                            const double* __restrict__ Qc, const double* __restrict__ hist,
+                            double* __restrict__ loc);
+__global__ void k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta,
+                           Packets pk, int pp, double* __restrict__ ginc);
+__global__ void k_spread_weights(int nf, double hf, double inv_alpha, double beta_es, const double* __restrict__ xs,
+                                 int M, const int* __restrict__ cstart, const int* __restrict__ ccount,
+                                 const int64_t* __restrict__ woff, double* __restrict__ w);
+__global__ void k_interp_weights(int n, int nf, double hf, double inv_alpha, double beta_es, int width,
+                                 const double* __restrict__ x, int* __restrict__ i0s, double* __restrict__ w);
+
+__global__ void k_solve(int M, int iters, int ext_max, const int* __restrict__ tile_r0,
+                        const int* __restrict__ tile_el, const int* __restrict__ tile_g0,
+                        const int* __restrict__ tile_left, const int* __restrict__ tile_n,
+                        const int* __restrict__ rg, const double* __restrict__ rdinv,
+                        const int* __restrict__ rptr, const int* __restrict__ ecol,
+                        const double* __restrict__ ev, const double* __restrict__ ginc,
+                        const double* __restrict__ loc, const int* __restrict__ i0s,
+                        const double* __restrict__ iw, const double* __restrict__ beta,
+                        const double* __restrict__ grid2, int nf, int width, double* __restrict__ sig_out,
+                        double* __restrict__ save_row, const int* __restrict__ perm);
+
+__global__ void k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
+                            const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
+                            const double* __restrict__ Q, const double* __restrict__ hist,
+                            const int* __restrict__ i0s, const double* __restrict__ iw,
+                            const double* __restrict__ grid2, int nf, int width, double* __restrict__ out);
+
+// ---- history part as three kernels (four-step transform, n = n1 n2) ----
+__global__ void k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M,
                          const int* __restrict__ cstart, const int* __restrict__ ccount,
-                         double* __restrict__ grid);
-
-__global__ void k_fft_r2c(FftPlan fp, const double2* __restrict__ grid, const double2* __restrict__ tw,
-                          int tws, double2* __restrict__ zout);
-
-__global__ void k_modes(int64_t K, int W, int nfh, int64_t L, const double2* __restrict__ z,
-                        const double2* __restrict__ tw, const double* __restrict__ dk1,
-                        const double* __restrict__ dk2, const double* __restrict__ pk,
-                        const double* __restrict__ qk, const double* __restrict__ rot,
-                        double2* __restrict__ ring, double2* __restrict__ alpha,
-                        double2* __restrict__ dalpha, double2* __restrict__ y);
-
-__global__ void k_fft_c2r(FftPlan fp, int64_t K, const double2* __restrict__ y,
-                          const double2* __restrict__ tw, int tws, double2* __restrict__ grid_out);
-
-__global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, double t,
-                            const double* __restrict__ xs, const double* __restrict__ beta,
-                            const int* __restrict__ nb_start, const int* __restrict__ nb_count,
-                            const int64_t* __restrict__ qoff, const double* __restrict__ Q,
-                            const double* __restrict__ hist, const double* __restrict__ grid2, int nf,
-                            double hf, double inv_alpha, double beta_es, int width, Packets pk,
-                            double* __restrict__ rhs);
-
-__global__ void k_jacobi(int M, int T, int iters, int ext_max, const int* __restrict__ ext_start,
-                         const int* __restrict__ ext_len, const int* __restrict__ nb_start,
-                         const int64_t* __restrict__ qoff, const double* __restrict__ Q,
-                         const int* __restrict__ near_start, const int* __restrict__ near_count,
-                         const double* __restrict__ rhs, double* __restrict__ sig_out,
-                         double* __restrict__ save_row, const int* __restrict__ perm);
-
-__global__ void k_receivers(int R, int M, int NQ, int NH, int64_t L, const double* __restrict__ xr,
-                            const int* __restrict__ nb_start, const int* __restrict__ nb_count,
-                            const int64_t* __restrict__ qoff, const double* __restrict__ Q,
-                            const double* __restrict__ hist, const double* __restrict__ grid2, int nf,
-                            double hf, double inv_alpha, double beta_es, int width,
-                            double* __restrict__ out);
+                         const int64_t* __restrict__ woff, const double* __restrict__ sw,
+                         const double2* __restrict__ tw, double2* __restrict__ T1);
+__global__ void k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L,
+                         const double2* __restrict__ T1, const double2* __restrict__ tw,
+                         const double* __restrict__ dk1, const double* __restrict__ dk2,
+                         const double* __restrict__ pk, const double* __restrict__ qk,
+                         const double* __restrict__ rot, double2* __restrict__ ring,
+                         double2* __restrict__ alpha, double2* __restrict__ dalpha, double2* __restrict__ y,
+                         double2* __restrict__ V);
+__global__ void k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
+                         double2* __restrict__ grid2);
 
 // ---- free-space radiation boundary projection ----
 __global__ void k_rbc_to_grid(FftPlan fp, int64_t K, const double2* __restrict__ alpha,

@@ -139,6 +139,57 @@ __device__ void fft_lds(double2* buf, const FftPlan& fp, const double2* __restri
   }
 }
 
+// Batched variant: nb independent FFTs of length fp.n at buf + b * fp.n, all
+// threads of the block taking part (at most kFftMaxB butterflies per thread per
+// stage; checked on the host).
+template <int R>
+__device__ __forceinline__ void fft_stage_batch(double2* buf, int n, int nb, int Ns, const double2* __restrict__ tw,
+                                                int tws) {
+  const int per = n / R;
+  const int tot = per * nb;
+  const int step = n / (Ns * R);
+  double2 v[kFftMaxB][R];
+#pragma unroll
+  for (int c = 0; c < kFftMaxB; ++c) {
+    const int idx = threadIdx.x + c * blockDim.x;
+    if (idx < tot) {
+      const int b = idx / per, j = idx - b * per;
+      const double2* base = buf + b * n;
+      const int k = j % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[c][r] = base[j + r * per];
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[c][r] = cmul(v[c][r], tw[(int64_t)(r * k * step) * tws]);
+      butterfly<R>(v[c]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kFftMaxB; ++c) {
+    const int idx = threadIdx.x + c * blockDim.x;
+    if (idx < tot) {
+      const int b = idx / per, j = idx - b * per;
+      double2* base = buf + b * n;
+      const int k = j % Ns;
+      const int o = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) base[o + r * Ns] = v[c][r];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ void fft_batch(double2* buf, int nb, const FftPlan& fp, const double2* __restrict__ tw, int tws) {
+  int Ns = 1;
+  for (int s = 0; s < fp.nst; ++s) {
+    const int R = fp.radix[s];
+    if (R == 4) fft_stage_batch<4>(buf, fp.n, nb, Ns, tw, tws);
+    else if (R == 5) fft_stage_batch<5>(buf, fp.n, nb, Ns, tw, tws);
+    else fft_stage_batch<2>(buf, fp.n, nb, Ns, tw, tws);
+    Ns *= R;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -189,7 +240,8 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
                 const int64_t* __restrict__ qoff, const double* __restrict__ rowscale, int periodic,
                 double dt, double delta, int W, int NQ, int ngl, const double* __restrict__ glz,
                 const double* __restrict__ glw, const double* __restrict__ cheb_phi, int ncheb,
-                const double* __restrict__ lagw, double* __restrict__ Q) {
+                const double* __restrict__ lagw, const int64_t* __restrict__ pbase,
+                signed char* __restrict__ mlo, double* __restrict__ Q) {
   extern __shared__ double acc[];
   const int row = blockIdx.x;
   if (row >= nrows) return;
@@ -202,6 +254,7 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
   for (int i0 = 0; i0 < n; i0 += nt) {
     const int i = i0 + tid;
     for (int m = 0; m < NQ; ++m) acc[m * nt + tid] = 0.0;
+    int lowest = NQ;
     if (i < n) {
       int l = st + i;
       if (l >= M) l -= M;
@@ -217,6 +270,7 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
           const double om = half * glw[q] * (1.0 - phi);
           int m0 = (int)floor(s) - P / 2 + 1;
           if (m0 < mmin) m0 = mmin;
+          if (m0 < lowest) lowest = m0;
           const double u = s - m0;
           double pre[P];
           pre[0] = 1.0;
@@ -234,6 +288,7 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
     }
     if (i < n) {
       for (int m = 0; m < NQ; ++m) Q[base + (int64_t)m * n + i] = scale * acc[m * nt + tid];
+      if (mlo) mlo[pbase[row] + i] = (signed char)lowest;
     }
   }
 }
@@ -241,27 +296,27 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
 template __global__ void k_local_weights<2>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
                                             int, const double*, const double*, const double*, int,
-                                            const double*, double*);
+                                            const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<4>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
                                             int, const double*, const double*, const double*, int,
-                                            const double*, double*);
+                                            const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<6>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
                                             int, const double*, const double*, const double*, int,
-                                            const double*, double*);
+                                            const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<8>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
                                             int, const double*, const double*, const double*, int,
-                                            const double*, double*);
+                                            const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<10>(int, const double*, const double*, int, const int*, const int*,
                                              const int64_t*, const double*, int, double, double, int, int,
                                              int, const double*, const double*, const double*, int,
-                                             const double*, double*);
+                                             const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<12>(int, const double*, const double*, int, const int*, const int*,
                                              const int64_t*, const double*, int, double, double, int, int,
                                              int, const double*, const double*, const double*, int,
-                                             const double*, double*);
+                                             const double*, const int64_t*, signed char*, double*);
 
 // Jacobi contraction bound of the per-step system (I + S): for each row,
 // sum_{l != j} |S_jl| / (1 + S_jj) over its nearby sources.
@@ -288,238 +343,304 @@ __global__ void k_row_contraction(int M, const int* __restrict__ nb_start, const
   out[j] = off / diag;
 }
 
-// ---------------------------------------------------------------------------
-// Type-1 spreading (gather form, atomics-free): grid_i = sum_j sigma_j psi((x_j - x_i)/alpha)
-// over the sorted sources inside the kernel support of cell i.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-k_spread(int nf, double hf, double inv_alpha, double beta_es, const double* __restrict__ xs,
-         const double* __restrict__ sig, int M, const int* __restrict__ cstart,
-         const int* __restrict__ ccount, double* __restrict__ grid) {
+// For each row and lag m, the index range [a, a + c) of sources whose lowest
+// nonzero lag is <= m (one wavefront per row).  A source at distance d has
+// nonzero weights exactly for lags mlo(d)..NQ-1 and mlo grows with d, so the
+// range is the contiguous block of neighbours closest to the target.
+// Packed as a | (c << 16).
+__global__ void k_row_ranges(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ pbase,
+                             const signed char* __restrict__ mlo, unsigned* __restrict__ ac) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= M) return;
+  const int n = nb_count[j];
+  const signed char* __restrict__ ml = mlo + pbase[j];
+  for (int m = 0; m < NQ; ++m) {
+    int lo = 0x7fffffff, hi = -1;
+    for (int i = lane; i < n; i += 64)
+      if (ml[i] <= m) {
+        lo = min(lo, i);
+        hi = max(hi, i);
+      }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = min(lo, __shfl_xor(lo, o, 64));
+      hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    if (lane == 0) ac[(int64_t)j * NQ + m] = (hi < 0) ? 0u : ((unsigned)lo | ((unsigned)(hi - lo + 1) << 16));
+  }
+}
+
+// Copy the weights of lags m >= 1 inside each row's ranges to the packed layout
+// Qc[rowbase[j] + sum_{m' < m} c_{jm'} + (i - a_jm)].
+__global__ void k_pack_weights(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
+                               const double* __restrict__ Q, const unsigned* __restrict__ ac,
+                               const int64_t* __restrict__ rowbase, double* __restrict__ Qc) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= M) return;
+  const int n = nb_count[j];
+  int64_t off = rowbase[j];
+  for (int m = 1; m < NQ; ++m) {
+    const unsigned v = ac[(int64_t)j * NQ + m];
+    const int a = v & 0xffff, c = v >> 16;
+    for (int i = lane; i < c; i += 64) Qc[off + i] = Q[qoff[j] + (int64_t)m * n + a + i];
+    off += c;
+  }
+}
+
+// Values of the solve's tile matrices: off-diagonal couplings and the inverse
+// diagonal, gathered from the lag-0 weights.
+__global__ void k_gather_solve(int64_t ne, const int64_t* __restrict__ eq, const double* __restrict__ Q,
+                               double* __restrict__ ev, int64_t nr, const int64_t* __restrict__ rq,
+                               double* __restrict__ rdinv) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ne) ev[t] = Q[eq[t]];
+  if (t < nr) rdinv[t] = 1.0 / (1.0 + Q[rq[t]]);
+}
+
+// Spreading weights psi((x_j - x_i)/alpha) of every (cell, source) pair in the
+// cell's source range, at w[woff_i + c] (the points never move).
+__global__ void k_spread_weights(int nf, double hf, double inv_alpha, double beta_es, const double* __restrict__ xs,
+                                 int M, const int* __restrict__ cstart, const int* __restrict__ ccount,
+                                 const int64_t* __restrict__ woff, double* __restrict__ w) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nf) return;
   const double xc = -kPi + i * hf;
   const int st = cstart[i], cnt = ccount[i];
-  double acc = 0.0;
   for (int c = 0; c < cnt; ++c) {
     int j = st + c;
     if (j >= M) j -= M;
     double dx = xs[j] - xc;
     dx -= kTwoPi * rint(dx * kInvTwoPi);
-    acc += sig[j] * es_kernel(dx * inv_alpha, beta_es);
+    w[woff[i] + c] = es_kernel(dx * inv_alpha, beta_es);
   }
-  grid[i] = acc;
 }
 
-// Real-to-complex transform of the fine grid: z = FFT_{n}(grid[2j] + i grid[2j+1]).
-__global__ void __launch_bounds__(1024)
-k_fft_r2c(FftPlan fp, const double2* __restrict__ grid, const double2* __restrict__ tw, int tws,
-          double2* __restrict__ zout) {
-  extern __shared__ double2 buf[];
-  for (int j = threadIdx.x; j < fp.n; j += blockDim.x) buf[j] = grid[j];
-  __syncthreads();
-  fft_lds(buf, fp, tw, tws);
-  for (int j = threadIdx.x; j < fp.n; j += blockDim.x) zout[j] = buf[j];
-}
-
-// ---------------------------------------------------------------------------
-// Mode update for level L (time t_n -> t_{n+1}, n = L-1), one thread per k:
-//   X_k (real-FFT unpacking) -> S_k^n = dk1_k conj(X_k)   (eq. (densco) via the type-1 NUFFT)
-//   ring[n mod W] = S^n
-//   h_k = sum_m pk[m][k] S_k^{n-m},  g_k likewise            (eq. (hkcompdisc))
-//   (alpha, alpha') <- propagator + (h, g)                    (Lemma)
-//   y_k = dk2_k conj(alpha_k)                                 (type-2 pre-correction)
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-k_modes(int64_t K, int W, int nfh, int64_t L, const double2* __restrict__ z, const double2* __restrict__ tw,
-        const double* __restrict__ dk1, const double* __restrict__ dk2, const double* __restrict__ pk,
-        const double* __restrict__ qk, const double* __restrict__ rot, double2* __restrict__ ring,
-        double2* __restrict__ alpha, double2* __restrict__ dalpha, double2* __restrict__ y) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > K) return;
-  const double2 zk = z[k];
-  const double2 zc = cconj(z[k == 0 ? 0 : nfh - k]);
-  const double2 E = cscale(cadd(zk, zc), 0.5);
-  const double2 O = cscale(cmul_mi(csub(zk, zc)), 0.5);
-  const double2 X = cadd(E, cmul(tw[k], O));
-  const double2 S = cscale(cconj(X), dk1[k]);
-  const int64_t n = L - 1;
-  const int64_t stride = K + 1;
-  ring[(int64_t)mod_slot(n, W) * stride + k] = S;
-  double2 h = make_double2(0.0, 0.0), g = make_double2(0.0, 0.0);
-  for (int m = 0; m < W; ++m) {
-    const double2 Sm = (m == 0) ? S : ring[(int64_t)mod_slot(n - m, W) * stride + k];
-    const double p = pk[(int64_t)m * stride + k], q = qk[(int64_t)m * stride + k];
-    h.x = fma(p, Sm.x, h.x);
-    h.y = fma(p, Sm.y, h.y);
-    g.x = fma(q, Sm.x, g.x);
-    g.y = fma(q, Sm.y, g.y);
-  }
-  const double c = rot[3 * k], s = rot[3 * k + 1], r = rot[3 * k + 2];
-  const double2 a = alpha[k], da = dalpha[k];
-  const double2 an = make_double2(c * a.x + s * da.x + h.x, c * a.y + s * da.y + h.y);
-  const double2 dan = make_double2(r * a.x + c * da.x + g.x, r * a.y + c * da.y + g.y);
-  alpha[k] = an;
-  dalpha[k] = dan;
-  y[k] = cscale(cconj(an), dk2[k]);
-}
-
-// Complex-to-real transform: grid_i = sum_{|k|<=K} y_k e^{+2 pi i i k / N} for
-// Hermitian y (given for k = 0..K, zero above), via an n = N/2 complex inverse
-// transform of the packed spectrum and conjugation around the forward FFT.
-__global__ void __launch_bounds__(1024)
-k_fft_c2r(FftPlan fp, int64_t K, const double2* __restrict__ y, const double2* __restrict__ tw, int tws,
-          double2* __restrict__ grid_out) {
-  extern __shared__ double2 buf[];
-  const int n = fp.n;
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const double2 yk = (k <= K) ? y[k] : make_double2(0.0, 0.0);
-    const int km = n - k;
-    const double2 ym = (k > 0 && km <= K) ? cconj(y[km]) : make_double2(0.0, 0.0);
-    // Z_k = (yk + ym) + i e^{+2 pi i k/N} (yk - ym);  e^{+} = conj(tw[k])
-    const double2 zk = cadd(cadd(yk, ym), cmul_pi(cmul(cconj(tw[k]), csub(yk, ym))));
-    buf[k] = cconj(zk);
-  }
-  __syncthreads();
-  fft_lds(buf, fp, tw, tws);
-  for (int j = threadIdx.x; j < n; j += blockDim.x) grid_out[j] = cconj(buf[j]);
-}
-
-// ---------------------------------------------------------------------------
-// Right-hand side of the level-L system, one wavefront per scatterer row j:
-//   rhs_j = -g_j(t_L) - sum_{m>=1} sum_l (beta_j/2) Q_m(d_jl) sigma_l^{L-m} - beta_j u_H(x_j)
-// with u_H(x_j) interpolated from the type-2 grid (lanes over the kernel cells)
-// and g_j = beta_j f(x_j - t_L) (eq. (gj); f periodised in the periodic box).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double incident_profile(double s, const Packets& pk) {
-  if (pk.periodic) s -= kTwoPi * rint(s * kInvTwoPi);
-  double out = 0.0;
-  for (int i = 0; i < pk.n; ++i) {
-    const double a = pk.p[5 * i], c = pk.p[5 * i + 1], w = pk.p[5 * i + 2];
-    const double om = pk.p[5 * i + 3], ph = pk.p[5 * i + 4];
-    const double lim = 40.0 * w;   // exp(-y^2/(2w^2)) underflows to 0 beyond
-    if (pk.periodic) {
-      for (int m = -4; m <= 4; ++m) {
-        const double y = (s + kTwoPi * m) - c;
-        if (fabs(y) < lim) out += a * exp(-y * y / (2.0 * w * w)) * cos(om * y + ph);
-      }
-    } else {
-      const double y = s - c;
-      if (fabs(y) < lim) out += a * exp(-y * y / (2.0 * w * w)) * cos(om * y + ph);
-    }
-  }
-  return out;
-}
-
-__device__ __forceinline__ double interp_lane(double x, const double* __restrict__ grid2, int nf, double hf,
-                                              double inv_alpha, double beta_es, int width, int lane) {
-  // cells i0 .. i0+width-1 with i0 = ceil((x + pi)/hf - width/2)
-  double v = 0.0;
-  if (lane < width) {
-    const int i0 = (int)ceil((x + kPi) / hf - 0.5 * width);
-    int i = i0 + lane;
+// Interpolation stencil of a target x: first cell i0 = ceil((x + pi)/h_f - width/2)
+// and the weights psi((x - x_i)/alpha) of cells i0 .. i0 + width - 1 (mod n_f).
+__global__ void k_interp_weights(int n, int nf, double hf, double inv_alpha, double beta_es, int width,
+                                 const double* __restrict__ x, int* __restrict__ i0s, double* __restrict__ w) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double xj = x[j];
+  const int i0 = (int)ceil((xj + kPi) / hf - 0.5 * width);
+  i0s[j] = i0;
+  for (int q = 0; q < width; ++q) {
+    int i = i0 + q;
     i %= nf;
     if (i < 0) i += nf;
-    double dx = x - (-kPi + i * hf);
+    double dx = xj - (-kPi + i * hf);
     dx -= kTwoPi * rint(dx * kInvTwoPi);
-    v = grid2[i] * es_kernel(dx * inv_alpha, beta_es);
+    w[(int64_t)j * width + q] = es_kernel(dx * inv_alpha, beta_es);
   }
-  return v;
 }
 
-__global__ void __launch_bounds__(256)
-k_local_rhs(int M, int NQ, int NH, int64_t L, double t, const double* __restrict__ xs,
-            const double* __restrict__ beta, const int* __restrict__ nb_start, const int* __restrict__ nb_count,
-            const int64_t* __restrict__ qoff, const double* __restrict__ Q, const double* __restrict__ hist,
-            const double* __restrict__ grid2, int nf, double hf, double inv_alpha, double beta_es, int width,
-            Packets pk, double* __restrict__ rhs) {
+__device__ __forceinline__ double interp_pre(int j, const int* __restrict__ i0s, const double* __restrict__ w,
+                                             const double* __restrict__ grid2, int nf, int width) {
+  int i = i0s[j] % nf;
+  if (i < 0) i += nf;
+  double uh = 0.0;
+  for (int q = 0; q < width; ++q) {
+    uh = fma(w[(int64_t)j * width + q], grid2[i], uh);
+    if (++i == nf) i = 0;
+  }
+  return uh;
+}
+
+// Number of nonzero stored weights of lag m >= 1 (one wavefront per row).
+__global__ void k_count_nonzero(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
+                                const double* __restrict__ Q, unsigned long long* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= M) return;
   const int n = nb_count[j];
+  unsigned long long c = 0;
+  for (int64_t e = (int64_t)n + lane; e < (int64_t)NQ * n; e += 64) c += (Q[qoff[j] + e] != 0.0);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (lane == 0) atomicAdd(out, c);
+}
+
+// XCD-aware block order: consecutive hardware block ids go round-robin over
+// the 8 XCDs; give each XCD a contiguous range of logical blocks so rows that
+// share density history share an L2.  A bijection when nblocks % 8 == 0.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  const int per = (nblocks + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Local sum of lags m >= 1, one row per wavefront.  The row's packed weights
+// are one block per lag m (sources a_m .. a_m + c_m - 1 of its neighbour list,
+// offset off_m).  The wavefront works as four groups of 16 lanes, group g on
+// lag mb + g of the current quad of lags: each group streams one contiguous
+// segment of weights and densities (one 128-byte line per 16 lanes), with the
+// per-lag data broadcast from the lane that scanned it.
+constexpr int kMaxNQ = 64;
+
+__global__ void __launch_bounds__(256)
+k_local_rhs(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start, const int64_t* __restrict__ rowbase,
+            const unsigned* __restrict__ ac, const double* __restrict__ Qc, const double* __restrict__ hist,
+            double* __restrict__ loc) {
+  const int lane = threadIdx.x & 63;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int j = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= M) return;   // no block-level barrier in this kernel
   const int st = nb_start[j];
-  const int64_t base = qoff[j];
-  double acc = 0.0;
-  for (int m = 1; m < NQ; ++m) {
-    const double* __restrict__ sl = hist + (int64_t)mod_slot(L - m, NH) * M;
-    const double* __restrict__ qm = Q + base + (int64_t)m * n;
-    for (int i = lane; i < n; i += 64) {
-      int l = st + i;
-      if (l >= M) l -= M;
-      acc = fma(qm[i], sl[l], acc);
+  // lane m (1 <= m < NQ) holds lag m's range; exclusive scan of the counts
+  int cnt = 0, av = 0;
+  if (lane >= 1 && lane < NQ) {
+    const unsigned v = ac[(int64_t)j * NQ + lane];
+    av = v & 0xffff;
+    cnt = v >> 16;
+  }
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int excl = incl - cnt;
+  const double* __restrict__ q = Qc + rowbase[j];
+  const int grp = lane >> 4, gl = lane & 15;
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int mb = 1; mb < NQ; mb += 4) {
+    const int m = mb + grp;
+    const int src = m < 64 ? m : 0;
+    int c = __shfl(cnt, src, 64);
+    const int a = __shfl(av, src, 64);
+    const int off = __shfl(excl, src, 64);
+    if (m >= NQ) c = 0;
+    const double* __restrict__ qp = q + off;
+    const double* __restrict__ hp = hist + (int64_t)mod_slot(L - m, NH) * M;
+    int l0 = st + a;
+    if (l0 >= M) l0 -= M;
+    // up to 8 segment elements per lane with every load issued before use
+    for (int i0 = 0; i0 < c; i0 += 128) {
+      double qv[8], hv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + gl + 16 * u;
+        qv[u] = 0.0;
+        hv[u] = 0.0;
+        if (i < c) {
+          int la = l0 + i;
+          if (la >= M) la -= M;
+          qv[u] = qp[i];
+          hv[u] = hp[la];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        acc0 = fma(qv[u], hv[u], acc0);
+        acc1 = fma(qv[u + 1], hv[u + 1], acc1);
+      }
     }
   }
-  acc = wave_sum(acc);
-  const double x = xs[j];
-  const double uh = wave_sum(interp_lane(x, grid2, nf, hf, inv_alpha, beta_es, width, lane));
-  if (lane == 0) {
-    const double bj = beta[j];
-    const double g = bj * incident_profile(x - t, pk);
-    rhs[j] = -g - acc - bj * uh;
+  const double accs = wave_sum(acc0 + acc1);
+  if (lane == 0) loc[j] = accs;
+}
+
+// Driving data g_j(t) = beta_j f(x_j - t) (eq. (gj); f periodised in the
+// periodic box), stored negated: ginc_j = -g_j.  Thread (row, packet) sums the
+// packet's images; the packets are then added in order.  `pp` = packets per
+// row rounded up to a power of two; 256/pp rows per block.
+__global__ void __launch_bounds__(256)
+k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta, Packets pk, int pp,
+           double* __restrict__ ginc) {
+  __shared__ double term[256];
+  const int rpb = 256 / pp;
+  const int lr = threadIdx.x / pp, ip = threadIdx.x - lr * pp;
+  const int j = blockIdx.x * rpb + lr;
+  double f = 0.0;
+  if (j < M && ip < pk.n) {
+    double s = xs[j] - t;
+    if (pk.periodic) s -= kTwoPi * rint(s * kInvTwoPi);
+    const double a = pk.p[5 * ip], c = pk.p[5 * ip + 1], wd = pk.p[5 * ip + 2];
+    const double om = pk.p[5 * ip + 3], ph = pk.p[5 * ip + 4];
+    const double lim = 40.0 * wd;   // exp(-y^2/(2 w^2)) underflows to 0 beyond
+    if (pk.periodic) {
+      for (int im = -4; im <= 4; ++im) {
+        const double y = (s + kTwoPi * im) - c;
+        if (fabs(y) < lim) f += a * exp(-y * y / (2.0 * wd * wd)) * cos(om * y + ph);
+      }
+    } else {
+      const double y = s - c;
+      if (fabs(y) < lim) f += a * exp(-y * y / (2.0 * wd * wd)) * cos(om * y + ph);
+    }
+  }
+  term[threadIdx.x] = f;
+  __syncthreads();
+  if (ip == 0 && j < M) {
+    double tot = 0.0;
+    for (int q = 0; q < pk.n; ++q) tot += term[lr * pp + q];
+    ginc[j] = -beta[j] * tot;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Per-step solve (I + S) sigma^L = rhs, S_jl = (beta_j/2) Q_0(d_jl) for d < dt
-// (eq. (linearSystem)), by `iters` Jacobi sweeps from zero.  One block per
-// tile of T consecutive rows; the block iterates on the tile plus a halo
-// holding every point within `iters` couplings of it, so the tile's result is
-// identical to `iters` global sweeps.  The result goes to the history slot of
-// level L and, when requested, to a row of the caller's output (original order).
+// (eq. (linearSystem)), by `iters` Jacobi sweeps from zero, one block per tile
+// of consecutive rows.  The block holds the tile plus a halo of every point
+// within `iters` couplings of it (rows r0..r0+el-1 of the tile matrices, with
+// column indices local to that range), so the tile's result equals `iters`
+// global sweeps.  The right-hand side is completed here:
+//   rhs_j = part_j - beta_j u_H(x_j)
+// with part_j = -g_j - (local sum) and u_H(x_j) interpolated from the type-2
+// grid.  The result goes to the
+// history slot of level L and, when requested, to the caller's output row.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
-k_jacobi(int M, int T, int iters, int ext_max, const int* __restrict__ ext_start, const int* __restrict__ ext_len,
-         const int* __restrict__ nb_start, const int64_t* __restrict__ qoff, const double* __restrict__ Q,
-         const int* __restrict__ near_start, const int* __restrict__ near_count, const double* __restrict__ rhs,
-         double* __restrict__ sig_out, double* __restrict__ save_row, const int* __restrict__ perm) {
+k_solve(int M, int iters, int ext_max, const int* __restrict__ tile_r0, const int* __restrict__ tile_el,
+        const int* __restrict__ tile_g0, const int* __restrict__ tile_left, const int* __restrict__ tile_n,
+        const int* __restrict__ rg, const double* __restrict__ rdinv, const int* __restrict__ rptr,
+        const int* __restrict__ ecol, const double* __restrict__ ev, const double* __restrict__ ginc,
+        const double* __restrict__ loc, const int* __restrict__ i0s, const double* __restrict__ iw,
+        const double* __restrict__ beta, const double* __restrict__ grid2, int nf, int width,
+        double* __restrict__ sig_out,
+        double* __restrict__ save_row, const int* __restrict__ perm) {
   extern __shared__ double sm[];
-  double* s0 = sm;
-  double* s1 = sm + ext_max;
-  const int tile = blockIdx.x;
-  const int es = ext_start[tile], el = ext_len[tile];
+  const int t = blockIdx.x;
+  const int r0 = tile_r0[t], el = tile_el[t];
+  const int k0 = rptr[r0], ne = rptr[r0 + el] - k0;
+  double* c = sm;
+  double* s0 = sm + ext_max;
+  double* s1 = sm + 2 * ext_max;
+  double* dinv = sm + 3 * ext_max;
+  double* val = sm + 4 * ext_max;                    // ne entries
+  int* col = (int*)(val + ne);                       // ne entries
+  int* ptr = col + ne;                               // el + 1 entries
+  for (int k = threadIdx.x; k < ne; k += blockDim.x) {
+    val[k] = ev[k0 + k];
+    col[k] = ecol[k0 + k];
+  }
+  for (int e = threadIdx.x; e <= el; e += blockDim.x) ptr[e] = rptr[r0 + e] - k0;
   for (int e = threadIdx.x; e < el; e += blockDim.x) {
-    int g = es + e;
-    if (g >= M) g -= M;
-    int self = g - nb_start[g];
-    if (self < 0) self += M;
-    s0[e] = rhs[g] / (1.0 + Q[qoff[g] + self]);
+    const int g = rg[r0 + e];
+    const double uh = interp_pre(g, i0s, iw, grid2, nf, width);
+    const double cv = (ginc[g] - loc[g]) - beta[g] * uh;
+    const double di = rdinv[r0 + e];
+    c[e] = cv;
+    dinv[e] = di;
+    s0[e] = cv * di;
   }
   __syncthreads();
   for (int it = 1; it < iters; ++it) {
     for (int e = threadIdx.x; e < el; e += blockDim.x) {
-      int g = es + e;
-      if (g >= M) g -= M;
-      const int st = nb_start[g];
-      const int64_t qb = qoff[g];
-      int self = g - st;
-      if (self < 0) self += M;
-      double acc = rhs[g];
-      const int ns = near_start[g], nc = near_count[g];
-      for (int c = 0; c < nc; ++c) {
-        int l = ns + c;
-        if (l >= M) l -= M;
-        if (l == g) continue;
-        int le = l - es;
-        if (le < 0) le += M;
-        if (le >= el) continue;  // outside the halo: only reaches points that are not kept
-        int i = l - st;
-        if (i < 0) i += M;
-        acc = fma(-Q[qb + i], s0[le], acc);
-      }
-      s1[e] = acc / (1.0 + Q[qb + self]);
+      double acc = c[e];
+      const int k1 = ptr[e + 1];
+      for (int k = ptr[e]; k < k1; ++k) acc = fma(-val[k], s0[col[k]], acc);
+      s1[e] = acc * dinv[e];
     }
     __syncthreads();
     double* tmp = s0;
     s0 = s1;
     s1 = tmp;
   }
-  const int t0 = tile * T;
-  for (int c = threadIdx.x; c < T; c += blockDim.x) {
-    const int g = t0 + c;
-    if (g >= M) break;
-    int le = g - es;
-    if (le < 0) le += M;
-    const double v = s0[le];
+  const int g0 = tile_g0[t], left = tile_left[t], nt = tile_n[t];
+  for (int k = threadIdx.x; k < nt; k += blockDim.x) {
+    const int g = g0 + k;
+    const double v = s0[left + k];
     sig_out[g] = v;
     if (save_row) save_row[perm[g]] = v;
   }
@@ -528,10 +649,10 @@ k_jacobi(int M, int T, int iters, int ext_max, const int* __restrict__ ext_start
 // Field at the receivers, one wavefront per receiver:
 //   u(x_r, t_L) = sum_{m>=0} sum_l (1/2) Q_m(d_rl) sigma_l^{L-m} + u_H(x_r)
 __global__ void __launch_bounds__(256)
-k_receivers(int R, int M, int NQ, int NH, int64_t L, const double* __restrict__ xr,
-            const int* __restrict__ nb_start, const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
-            const double* __restrict__ Q, const double* __restrict__ hist, const double* __restrict__ grid2,
-            int nf, double hf, double inv_alpha, double beta_es, int width, double* __restrict__ out) {
+k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
+            const int* __restrict__ nb_count, const int64_t* __restrict__ qoff, const double* __restrict__ Q,
+            const double* __restrict__ hist, const int* __restrict__ i0s, const double* __restrict__ iw,
+            const double* __restrict__ grid2, int nf, int width, double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= R) return;
@@ -549,8 +670,7 @@ k_receivers(int R, int M, int NQ, int NH, int64_t L, const double* __restrict__ 
     }
   }
   acc = wave_sum(acc);
-  const double uh = wave_sum(interp_lane(xr[r], grid2, nf, hf, inv_alpha, beta_es, width, lane));
-  if (lane == 0) out[r] = acc + uh;
+  if (lane == 0) out[r] = acc + interp_pre(r, i0s, iw, grid2, nf, width);
 }
 
 // ---------------------------------------------------------------------------
@@ -637,6 +757,192 @@ k_rbc_to_modes(FftPlan fp, int64_t K, int W, double h, double delta_s, const dou
     out[k] = a;
     if (!is_v) y[k] = cscale(cconj(a), dk2[k]);
   }
+}
+
+
+// ===========================================================================
+// History part of one level as three kernels.  The half-length complex
+// transform of the fine grid (n = N/2 points, N = n_f) is done in four steps
+// with n = n1 n2:  j = j1 + n1 j2,  k = k2 + n2 k1,
+//   X_{k2 + n2 k1} = sum_j1 w_n1^{j1 k1} [ w_n^{j1 k2} sum_j2 z_{j1 + n1 j2} w_n2^{j2 k2} ].
+// A: for one j1, spread the 2 n2 grid cells of z_{j1 + n1 j2}, FFT over j2,
+//    twiddle, store T1[k2][j1].
+// B: for the column pair {k2, n2 - k2} (which holds both k and n - k, as the
+//    real-transform unpacking needs): FFT over j1 -> X_k; spectra, FIR and
+//    propagator for the k <= K in these columns; pack the type-2 spectrum and
+//    run the first inverse step (FFT over k1, twiddle) -> V[j1][k2].
+// C: for one j1, inverse FFT over k2 -> z_{j1 + n1 j2} -> grid cells.
+// ===========================================================================
+__device__ __forceinline__ double spread_cell(int cell, const double* __restrict__ sig, int M,
+                                              const int* __restrict__ cstart, const int* __restrict__ ccount,
+                                              const int64_t* __restrict__ woff, const double* __restrict__ sw) {
+  const int st = cstart[cell], cnt = ccount[cell];
+  const double* __restrict__ w = sw + woff[cell];
+  double acc = 0.0;
+  for (int c = 0; c < cnt; ++c) {
+    int j = st + c;
+    if (j >= M) j -= M;
+    acc = fma(sig[j], w[c], acc);
+  }
+  return acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
+         const int* __restrict__ ccount, const int64_t* __restrict__ woff, const double* __restrict__ sw,
+         const double2* __restrict__ tw, double2* __restrict__ T1) {
+  extern __shared__ double2 buf[];
+  const int n2 = f2.n, j1 = blockIdx.x;
+  const int n = n1 * n2;
+  double* bd = (double*)buf;
+  for (int c = threadIdx.x; c < 2 * n2; c += blockDim.x) {
+    const int cell = 2 * (j1 + n1 * (c >> 1)) + (c & 1);
+    bd[c] = spread_cell(cell, sig, M, cstart, ccount, woff, sw);
+  }
+  __syncthreads();
+  fft_batch(buf, 1, f2, tw, 2 * n1);
+  for (int k2 = threadIdx.x; k2 < n2; k2 += blockDim.x) {
+    const int q = j1 * k2;                 // < n
+    T1[(int64_t)k2 * n1 + j1] = cmul(buf[k2], tw[2 * (q % n)]);
+  }
+}
+
+constexpr int kFirGroups = 4;
+
+// Partner of position (c, k1) in the column pair: where Z_{n - q} sits, q = col[c] + n2 k1.
+__device__ __forceinline__ int partner(int c, int k1, int k2c, int ncol, int n1) {
+  if (k2c == 0) return c * n1 + (n1 - k1) % n1;
+  const int cp = (ncol == 2) ? 1 - c : c;
+  return cp * n1 + (n1 - 1 - k1);
+}
+
+// mode 0: forward step 2 + modes + inverse step 1; mode 1: forward step 2 +
+// modes, writing y (the type-2 input) for a later projection; mode 2: inverse
+// step 1 from y.
+__global__ void __launch_bounds__(512)
+k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, const double2* __restrict__ T1,
+         const double2* __restrict__ tw, const double* __restrict__ dk1, const double* __restrict__ dk2,
+         const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,
+         double2* __restrict__ ring, double2* __restrict__ alpha, double2* __restrict__ dalpha,
+         double2* __restrict__ y, double2* __restrict__ V) {
+  extern __shared__ double2 smb[];
+  const int n1 = f1.n;
+  const int n = n1 * n2;
+  double2* buf = smb;                         // [2][n1]
+  double2* yl = smb + 2 * n1;                 // [2][n1]
+  double2* sS = smb + 4 * n1;                 // [2][n1]
+  double4* red = (double4*)(smb + 6 * n1);    // [kFirGroups][2 n1]
+  const int k2a = blockIdx.x, k2b = (n2 - k2a) % n2;
+  const int ncol = (k2a == k2b) ? 1 : 2;
+  const int np = ncol * n1;
+  const int64_t stride = K + 1;
+  auto colk2 = [&](int c) { return c == 0 ? k2a : k2b; };
+  if (mode != 2) {
+    for (int e = threadIdx.x; e < np; e += blockDim.x) {
+      const int c = e / n1, k1 = e - c * n1;
+      buf[e] = T1[(int64_t)colk2(c) * n1 + k1];
+    }
+    __syncthreads();
+    fft_batch(buf, ncol, f1, tw, 2 * n2);
+    const int64_t nn = L - 1;
+    // spectra S_q of the modes q <= K held by this block
+    for (int e = threadIdx.x; e < np; e += blockDim.x) {
+      const int c = e / n1, k1 = e - c * n1;
+      const int64_t q = colk2(c) + (int64_t)n2 * k1;
+      double2 S = make_double2(0.0, 0.0);
+      if (q <= K) {
+        const double2 zk = buf[e];
+        const double2 zc = cconj(buf[partner(c, k1, k2a, ncol, n1)]);
+        const double2 E = cscale(cadd(zk, zc), 0.5);
+        const double2 O = cscale(cmul_mi(csub(zk, zc)), 0.5);
+        const double2 X = cadd(E, cmul(tw[q], O));
+        S = cscale(cconj(X), dk1[q]);
+      }
+      sS[e] = S;
+    }
+    __syncthreads();
+    // FIR partial sums: work item (e, g) takes taps m = g, g + G, ...
+    for (int wi = threadIdx.x; wi < np * kFirGroups; wi += blockDim.x) {
+      const int g = wi / np, e = wi - g * np;
+      const int c = e / n1, k1 = e - c * n1;
+      const int64_t q = colk2(c) + (int64_t)n2 * k1;
+      double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (q <= K) {
+        for (int m = g; m < W; m += kFirGroups) {
+          const double2 Sm = (m == 0) ? sS[e] : ring[(int64_t)mod_slot(nn - m, W) * stride + q];
+          const double p = pk[(int64_t)m * stride + q], qq = qk[(int64_t)m * stride + q];
+          acc.x = fma(p, Sm.x, acc.x);
+          acc.y = fma(p, Sm.y, acc.y);
+          acc.z = fma(qq, Sm.x, acc.z);
+          acc.w = fma(qq, Sm.y, acc.w);
+        }
+      }
+      red[g * np + e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < np; e += blockDim.x) {
+      const int c = e / n1, k1 = e - c * n1;
+      const int64_t q = colk2(c) + (int64_t)n2 * k1;
+      double2 yq = make_double2(0.0, 0.0);
+      if (q <= K) {
+        double2 h = make_double2(0.0, 0.0), g = make_double2(0.0, 0.0);
+        for (int gg = 0; gg < kFirGroups; ++gg) {
+          const double4 v = red[gg * np + e];
+          h.x += v.x;
+          h.y += v.y;
+          g.x += v.z;
+          g.y += v.w;
+        }
+        ring[(int64_t)mod_slot(nn, W) * stride + q] = sS[e];
+        const double cr = rot[3 * q], sr = rot[3 * q + 1], rr = rot[3 * q + 2];
+        const double2 a = alpha[q], da = dalpha[q];
+        const double2 an = make_double2(cr * a.x + sr * da.x + h.x, cr * a.y + sr * da.y + h.y);
+        const double2 dan = make_double2(rr * a.x + cr * da.x + g.x, rr * a.y + cr * da.y + g.y);
+        alpha[q] = an;
+        dalpha[q] = dan;
+        yq = cscale(cconj(an), dk2[q]);
+        if (mode == 1) y[q] = yq;
+      }
+      yl[e] = yq;
+    }
+    if (mode == 1) return;   // block-uniform
+  } else {
+    for (int e = threadIdx.x; e < np; e += blockDim.x) {
+      const int c = e / n1, k1 = e - c * n1;
+      const int64_t q = colk2(c) + (int64_t)n2 * k1;
+      yl[e] = (q <= K) ? y[q] : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  // pack: Z'_q = (y_q + conj(y_{n-q})) + i e^{+2 pi i q/N} (y_q - conj(y_{n-q})); buf = conj(Z')
+  for (int e = threadIdx.x; e < np; e += blockDim.x) {
+    const int c = e / n1, k1 = e - c * n1;
+    const int q = colk2(c) + n2 * k1;
+    const double2 yk = yl[e];
+    const double2 ym = (q == 0) ? make_double2(0.0, 0.0) : cconj(yl[partner(c, k1, k2a, ncol, n1)]);
+    const double2 zq = cadd(cadd(yk, ym), cmul_pi(cmul(cconj(tw[q]), csub(yk, ym))));
+    buf[e] = cconj(zq);
+  }
+  __syncthreads();
+  fft_batch(buf, ncol, f1, tw, 2 * n2);
+  // V[j1][k2] = conj(buf) * e^{+2 pi i j1 k2 / n}
+  for (int e = threadIdx.x; e < np; e += blockDim.x) {
+    const int c = e / n1, j1 = e - c * n1;
+    const int k2 = colk2(c);
+    const int qq = (j1 * k2) % n;
+    V[(int64_t)j1 * n2 + k2] = cmul(cconj(buf[e]), cconj(tw[2 * qq]));
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
+         double2* __restrict__ grid2) {
+  extern __shared__ double2 buf[];
+  const int n2 = f2.n, j1 = blockIdx.x;
+  for (int k2 = threadIdx.x; k2 < n2; k2 += blockDim.x) buf[k2] = cconj(V[(int64_t)j1 * n2 + k2]);
+  __syncthreads();
+  fft_batch(buf, 1, f2, tw, 2 * n1);
+  for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) grid2[j1 + n1 * j2] = cconj(buf[j2]);
 }
 
 // ---------------------------------------------------------------------------

@@ -74,8 +74,10 @@ struct wfp_plan {
   int boundary = 0, W = 0, p = 0, NQ = 0, NH = 0, ngl = 0, ngpq = 0, rbc_period = 0, width = 0, iters = 0;
   int nf = 0, nfh = 0, ncheb = 0, T = 256, ntile = 0, ext_max = 0, npk = 0;
   double dt = 0, delta = 0, b = 0, hf = 0, alpha_es = 0, beta_es = 0, h_rbc = 0, delta_s = 0, contraction = 0;
-  FftPlan fft_nf{}, fft_rbc{};
-  size_t lds_nf = 0, lds_rbc = 0, lds_jac = 0, lds_qw = 0;
+  FftPlan fft_nf{}, fft_rbc{}, fft_n1{}, fft_n2{};
+  int n1 = 0, n2 = 0;           // four-step split of the half-length transform
+  double2 *T1 = nullptr, *V = nullptr;
+  size_t lds_rbc = 0, lds_jac = 0, lds_qw = 0;
   std::vector<int> perm_h;
   // device buffers
   double *xs = nullptr, *beta = nullptr, *xr = nullptr, *packets = nullptr;
@@ -85,25 +87,59 @@ struct wfp_plan {
   double *pk = nullptr, *qk = nullptr, *rot = nullptr, *dk1 = nullptr, *dk2 = nullptr;
   double2* tw = nullptr;
   double2* tw_rbc = nullptr;
-  double* grid = nullptr;
-  double2* zbuf = nullptr;
   double2* ybuf = nullptr;
   double* grid2 = nullptr;
   double *rbc_u = nullptr, *rbc_v = nullptr;
   int *cstart = nullptr, *ccount = nullptr;
-  int *nb_start = nullptr, *nb_count = nullptr, *near_start = nullptr, *near_count = nullptr;
+  int *nb_start = nullptr, *nb_count = nullptr;
   int64_t* qoff = nullptr;
-  double* Q = nullptr;
-  double* rhs = nullptr;
-  int *ext_start = nullptr, *ext_len = nullptr;
+  double* Q = nullptr;          // dense weights of the scatterer rows (plan set-up only)
+  double* Qc = nullptr;         // packed weights of lags >= 1
+  unsigned* ac = nullptr;       // per (row, lag) source range a | c << 16
+  int64_t* rowbase = nullptr;   // packed offset of each row
+  double* ginc = nullptr;       // -g_j(t_L), per row
+  double* loc = nullptr;        // local sum of lags >= 1, per row
+  // solve tiles
+  int *tile_r0 = nullptr, *tile_el = nullptr, *tile_g0 = nullptr, *tile_left = nullptr, *tile_n = nullptr;
+  int *srow_g = nullptr, *srow_ptr = nullptr, *scol = nullptr;
+  double *srow_dinv = nullptr, *sval = nullptr;
+  int solve_threads = 64;
+  // precomputed spreading / interpolation weights
+  int64_t* swoff = nullptr;
+  double* sw = nullptr;
+  int *i0s = nullptr, *ri0s = nullptr;
+  double *iw = nullptr, *riw = nullptr;
   int *rnb_start = nullptr, *rnb_count = nullptr;
   int64_t* rqoff = nullptr;
   double* Qr = nullptr;
   double *cheb_phi = nullptr, *cheb_g = nullptr;
+  int64_t n_weights_nonzero = 0, n_weights_stored = 0;
   std::vector<void*> owned;
+  // per-stage event timing
+  bool profiling = false;
+  double prof_ms[WFP_N_STAGES] = {};
+  int64_t prof_n[WFP_N_STAGES] = {};
+  struct Pending {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
 
   ~wfp_plan() {
+    for (auto& q : pending) {
+      (void)hipEventDestroy(q.a);
+      (void)hipEventDestroy(q.b);
+    }
+    for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
     for (void* ptr : owned) (void)hipFree(ptr);
+  }
+  void release(void* ptr) {
+    for (auto& o : owned)
+      if (o == ptr) {
+        (void)hipFree(o);
+        o = nullptr;
+      }
   }
   template <class T>
   T* alloc(size_t n) {
@@ -182,6 +218,53 @@ void validate(const wfp_problem* prob, const wfp_params* par) {
   }
 }
 
+hipEvent_t take_event(wfp_plan* P) {
+  if (!P->free_events.empty()) {
+    hipEvent_t e = P->free_events.back();
+    P->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+void flush_profile(wfp_plan* P) {
+  if (P->pending.empty()) return;
+  for (auto& q : P->pending) HIPCHK(hipEventSynchronize(q.b));   // events live on two streams
+  for (auto& q : P->pending) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, q.a, q.b));
+    P->prof_ms[q.stage] += ms;
+    P->prof_n[q.stage] += 1;
+    P->free_events.push_back(q.a);
+    P->free_events.push_back(q.b);
+  }
+  P->pending.clear();
+}
+
+// Brackets one stage's kernels with events when profiling is on.
+struct StageTimer {
+  wfp_plan* P;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(wfp_plan* p, int stg, hipStream_t stream) : P(p), stage(stg), st(stream) {
+    if (P->profiling) {
+      a = take_event(P);
+      HIPCHK(hipEventRecord(a, st));
+    }
+  }
+  ~StageTimer() noexcept(false) {
+    if (P->profiling) {
+      hipEvent_t b = take_event(P);
+      HIPCHK(hipEventRecord(b, st));
+      P->pending.push_back({stage, a, b});
+      if (P->pending.size() >= 1024) flush_profile(P);
+    }
+  }
+};
+
 void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   validate(prob, par);
   const int64_t M = prob->M;
@@ -203,6 +286,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   P->W = par->W > 0 ? par->W : (int)std::lround(2.0 * P->b / (kPi * gamma));
   P->p = par->p > 0 ? par->p : 8;
   if (P->p % 2 || P->p < 2 || P->p > kMaxP) fail(WFP_EINVAL, "p must be even, 2..12");
+  if (P->W + P->p / 2 > 64) fail(WFP_EDOMAIN, "W + p/2 must not exceed 64");
   P->delta = P->W * P->dt;
   if (P->delta >= kPi) fail(WFP_EDOMAIN, "delta = W dt must be < pi");
   if (par->K > 0) {
@@ -233,9 +317,23 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   P->hf = kTwoPi / (double)nf;
   P->alpha_es = 0.5 * P->width * P->hf;
   P->beta_es = 2.30 * P->width;
-  P->fft_nf = make_fft_plan(P->nfh);
-  P->lds_nf = (size_t)P->nfh * sizeof(double2);
-  if (P->lds_nf > 160 * 1024) fail(WFP_EDOMAIN, "fine grid too long for the single-workgroup FFT");
+  {
+    // n = nf/2 = n1 n2 with n1 the largest 2^a 5^b divisor not above sqrt(n)
+    const int64_t n = P->nfh;
+    int64_t best = 1;
+    for (int64_t d = 1; d * d <= n; ++d)
+      if (n % d == 0 && is_pow2_pow5(d)) best = d;
+    P->n1 = (int)best;
+    P->n2 = (int)(n / best);
+    if (P->n2 > 1024) fail(WFP_EDOMAIN, "fine grid too long for the four-step transform");
+    P->fft_n1 = make_fft_plan(P->n1);
+    P->fft_n2 = make_fft_plan(P->n2);
+    // batched LDS stages run on 256 threads with at most kFftMaxB butterflies each
+    for (int i = 0; i < P->fft_n1.nst; ++i)
+      if (2 * P->n1 / P->fft_n1.radix[i] > kFftMaxB * 256) fail(WFP_EDOMAIN, "four-step factor n1 too long");
+    for (int i = 0; i < P->fft_n2.nst; ++i)
+      if (P->n2 / P->fft_n2.radix[i] > kFftMaxB * 256) fail(WFP_EDOMAIN, "four-step factor n2 too long");
+  }
   if (!periodic) {
     if (!is_pow2_pow5(2 * P->K)) fail(WFP_EDOMAIN, "free space needs 2K = 2^a 5^b");
     P->fft_rbc = make_fft_plan(P->K);
@@ -299,13 +397,12 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   P->dk1 = P->alloc<double>(P->K + 1);
   P->dk2 = P->alloc<double>(P->K + 1);
   P->tw = P->alloc<double2>(nf);
-  P->grid = P->alloc<double>(nf);
-  P->zbuf = P->alloc<double2>(P->nfh);
+  P->T1 = P->alloc<double2>(P->nfh);
+  P->V = P->alloc<double2>(P->nfh);
   P->ybuf = P->alloc<double2>(P->K + 1);
   P->grid2 = P->alloc<double>(nf);
   P->cstart = P->alloc<int>(nf);
   P->ccount = P->alloc<int>(nf);
-  P->rhs = P->alloc<double>(M);
   P->cheb_phi = P->alloc<double>(ws.n);
   P->cheb_g = P->alloc<double>(ws.n);
   P->packets = P->alloc<double>(5 * prob->n_packets);
@@ -370,35 +467,50 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   // ---- spreading ranges: sources within the kernel support of each cell ----
   {
     std::vector<int> cs(nf), cc(nf);
+    std::vector<int64_t> wo(nf);
+    int64_t wt = 0;
     for (int64_t i = 0; i < nf; ++i) {
       const double xc = -kPi + (double)i * P->hf;
       source_range(xs, xc, P->alpha_es * (1.0 + 1e-12), true, true, cs[i], cc[i]);
+      wo[i] = wt;
+      wt += cc[i];
     }
     upload(P->cstart, cs, s);
     upload(P->ccount, cc, s);
+    P->swoff = P->alloc<int64_t>(nf);
+    P->sw = P->alloc<double>(wt);
+    upload(P->swoff, wo, s);
+    hipLaunchKernelGGL(k_spread_weights, dim3(nblk(nf, 256)), dim3(256), 0, s, (int)nf, P->hf, 1.0 / P->alpha_es,
+                       P->beta_es, P->xs, (int)M, P->cstart, P->ccount, P->swoff, P->sw);
+    HIPCHK(hipGetLastError());
+    P->i0s = P->alloc<int>(M);
+    P->iw = P->alloc<double>((size_t)M * P->width);
+    hipLaunchKernelGGL(k_interp_weights, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, (int)nf, P->hf,
+                       1.0 / P->alpha_es, P->beta_es, P->width, P->xs, P->i0s, P->iw);
+    HIPCHK(hipGetLastError());
   }
   // ---- neighbour rows of the scatterers and receivers ----
   std::vector<int> nbs(M), nbc(M), ns(M), nc(M);
-  std::vector<int64_t> qo(M);
+  std::vector<int64_t> qo(M), pb(M);
   int64_t tot = 0;
   for (int64_t j = 0; j < M; ++j) {
     source_range(xs, xs[j], P->delta, periodic, false, nbs[j], nbc[j]);
     source_range(xs, xs[j], P->dt, periodic, false, ns[j], nc[j]);
     qo[j] = tot;
+    pb[j] = P->n_pairs;
     tot += (int64_t)nbc[j] * P->NQ;
     P->n_pairs += nbc[j];
   }
   P->nb_start = P->alloc<int>(M);
   P->nb_count = P->alloc<int>(M);
-  P->near_start = P->alloc<int>(M);
-  P->near_count = P->alloc<int>(M);
   P->qoff = P->alloc<int64_t>(M);
+  int64_t* pbase = P->alloc<int64_t>(M);
+  signed char* mlo = P->alloc<signed char>(P->n_pairs);
   P->Q = P->alloc<double>(tot);
   upload(P->nb_start, nbs, s);
   upload(P->nb_count, nbc, s);
-  upload(P->near_start, ns, s);
-  upload(P->near_count, nc, s);
   upload(P->qoff, qo, s);
+  upload(pbase, pb, s);
   std::vector<double> lagw(P->p);
   {
     for (int r = 0; r < P->p; ++r) {
@@ -421,12 +533,12 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   const int qthreads = 128;
   P->lds_qw = (size_t)P->NQ * qthreads * sizeof(double);
   auto launch_qw = [&](int nrows, const double* xt, const int* st, const int* cnt, const int64_t* off,
-                       const double* scale, double* Qd) {
+                       const double* scale, const int64_t* pbs, signed char* ml, double* Qd) {
     if (nrows == 0) return;
 #define WFP_QW(PP)                                                                                    \
   hipLaunchKernelGGL(k_local_weights<PP>, dim3(nrows), dim3(qthreads), P->lds_qw, s, nrows, xt, P->xs,   \
                      (int)M, st, cnt, off, scale, periodic ? 1 : 0, P->dt, P->delta, P->W, P->NQ, P->ngl, \
-                     glz_d, glw_d, P->cheb_phi, P->ncheb, lagw_d, Qd)
+                     glz_d, glw_d, P->cheb_phi, P->ncheb, lagw_d, pbs, ml, Qd)
     switch (P->p) {
       case 2: WFP_QW(2); break;
       case 4: WFP_QW(4); break;
@@ -438,7 +550,44 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
 #undef WFP_QW
     HIPCHK(hipGetLastError());
   };
-  launch_qw((int)M, P->xs, P->nb_start, P->nb_count, P->qoff, hb_d, P->Q);
+  launch_qw((int)M, P->xs, P->nb_start, P->nb_count, P->qoff, hb_d, pbase, mlo, P->Q);
+  {
+    unsigned long long* cnt = P->alloc<unsigned long long>(1);
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_count_nonzero, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ,
+                       P->nb_count, P->qoff, P->Q, cnt);
+    HIPCHK(hipGetLastError());
+    unsigned long long h = 0;
+    HIPCHK(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    P->n_weights_nonzero = (int64_t)h;
+    P->release(cnt);
+  }
+  // ---- pack the weights of lags >= 1 to each row's nonzero source ranges ----
+  {
+    for (int64_t j = 0; j < M; ++j)
+      if (nbc[j] >= 65536) fail(WFP_EDOMAIN, "more than 65535 neighbours of one scatterer");
+    P->ac = P->alloc<unsigned>((size_t)M * P->NQ);
+    hipLaunchKernelGGL(k_row_ranges, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ,
+                       P->nb_count, pbase, mlo, P->ac);
+    HIPCHK(hipGetLastError());
+    std::vector<unsigned> ach((size_t)M * P->NQ);
+    HIPCHK(hipMemcpyAsync(ach.data(), P->ac, ach.size() * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int64_t> rb(M);
+    int64_t packed = 0;
+    for (int64_t j = 0; j < M; ++j) {
+      rb[j] = packed;
+      for (int m = 1; m < P->NQ; ++m) packed += ach[(size_t)j * P->NQ + m] >> 16;
+    }
+    P->n_weights_stored = packed;
+    P->rowbase = P->alloc<int64_t>(M);
+    P->Qc = P->alloc<double>(packed);
+    upload(P->rowbase, rb, s);
+    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ,
+                       P->nb_count, P->qoff, P->Q, P->ac, P->rowbase, P->Qc);
+    HIPCHK(hipGetLastError());
+  }
   if (P->R > 0) {
     std::vector<int> rs(P->R), rc(P->R);
     std::vector<int64_t> ro(P->R);
@@ -461,17 +610,29 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     std::vector<double> halfs(P->R, 0.5);
     double* hr_d = P->alloc<double>(P->R);
     upload(hr_d, halfs, s);
-    launch_qw((int)P->R, P->xr, P->rnb_start, P->rnb_count, P->rqoff, hr_d, P->Qr);
+    launch_qw((int)P->R, P->xr, P->rnb_start, P->rnb_count, P->rqoff, hr_d, nullptr, nullptr, P->Qr);
+    P->ri0s = P->alloc<int>(P->R);
+    P->riw = P->alloc<double>((size_t)P->R * P->width);
+    hipLaunchKernelGGL(k_interp_weights, dim3(nblk(P->R, 256)), dim3(256), 0, s, (int)P->R, P->nf, P->hf,
+                       1.0 / P->alpha_es, P->beta_es, P->width, P->xr, P->ri0s, P->riw);
+    HIPCHK(hipGetLastError());
   }
   // ---- solve: contraction bound, sweep count, tiles with halos ----
   {
+    int* near_start = P->alloc<int>(M);
+    int* near_count = P->alloc<int>(M);
+    upload(near_start, ns, s);
+    upload(near_count, nc, s);
     double* cr = P->alloc<double>(M);
     hipLaunchKernelGGL(k_row_contraction, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->nb_start, P->nb_count,
-                       P->qoff, P->Q, P->near_start, P->near_count, cr);
+                       P->qoff, P->Q, near_start, near_count, cr);
     HIPCHK(hipGetLastError());
     std::vector<double> crh(M);
     HIPCHK(hipMemcpyAsync(crh.data(), cr, M * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    P->release(cr);
+    P->release(near_start);
+    P->release(near_count);
     double rho = 0;
     for (double v : crh) rho = std::max(rho, v);
     P->contraction = rho;
@@ -484,48 +645,119 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
       P->iters = 1 + (int)std::ceil(std::log(1e-18) / std::log(rho));
     }
     const double reach = P->iters * P->dt * (1.0 + 1e-9) + 1e-12;
-    P->T = 256;
-    P->ntile = (int)((M + P->T - 1) / P->T);
-    std::vector<int> es(P->ntile), el(P->ntile);
-    int ext_max = 0;
-    for (int t = 0; t < P->ntile; ++t) {
-      const int64_t a = (int64_t)t * P->T, c = std::min<int64_t>(M, a + P->T) - 1;
-      int s0, c0, s1, c1;
-      source_range(xs, xs[a], reach, periodic, true, s0, c0);
-      source_range(xs, xs[c], reach, periodic, true, s1, c1);
-      // extended range: from the first source near the tile's left end to the
-      // last source near its right end (circular), at least covering the tile
-      int64_t lo = s0, hi = (int64_t)s1 + c1;  // hi exclusive, may exceed M
-      if (!periodic) {
-        lo = std::min<int64_t>(lo, a);
-        hi = std::max<int64_t>(hi, c + 1);
-        es[t] = (int)lo;
-        el[t] = (int)(hi - lo);
-      } else {
-        // express both ends relative to the tile start a, going left / right
-        int64_t left = (a - lo + M) % M;          // points to the left of a
-        if (c0 >= M) left = 0;
-        int64_t right = (hi - 1 - c + 2 * M) % M;  // points to the right of c
-        if (c1 >= M) right = 0;
-        int64_t len = left + (c - a + 1) + right;
-        if (c0 >= M || c1 >= M || len >= M) {
-          es[t] = 0;
-          el[t] = (int)M;
+    // extended (tile + halo) ranges for a tile size T
+    auto tiles = [&](int T, std::vector<int>& es, std::vector<int>& el) {
+      const int nt = (int)((M + T - 1) / T);
+      es.assign(nt, 0);
+      el.assign(nt, 0);
+      int emax = 0;
+      for (int t = 0; t < nt; ++t) {
+        const int64_t a0 = (int64_t)t * T, c0i = std::min<int64_t>(M, a0 + T) - 1;
+        int s0, n0, s1, n1;
+        source_range(xs, xs[a0], reach, periodic, true, s0, n0);
+        source_range(xs, xs[c0i], reach, periodic, true, s1, n1);
+        int64_t lo = s0, hi = (int64_t)s1 + n1;
+        if (!periodic) {
+          lo = std::min<int64_t>(lo, a0);
+          hi = std::max<int64_t>(hi, c0i + 1);
+          es[t] = (int)lo;
+          el[t] = (int)(hi - lo);
         } else {
-          es[t] = (int)((a - left + M) % M);
-          el[t] = (int)len;
+          int64_t left = (a0 - lo + M) % M;
+          int64_t right = (hi - 1 - c0i + 2 * M) % M;
+          int64_t len = left + (c0i - a0 + 1) + right;
+          if (n0 >= M || n1 >= M || len >= M) {
+            es[t] = (int)a0;   // whole circle, starting at the tile
+            el[t] = (int)M;
+          } else {
+            es[t] = (int)((a0 - left + M) % M);
+            el[t] = (int)len;
+          }
         }
+        emax = std::max(emax, el[t]);
       }
-      ext_max = std::max(ext_max, el[t]);
+      return emax;
+    };
+    std::vector<int> es, el;
+    int T = 64, emax = tiles(T, es, el);
+    while (emax > 4 * T && T < 2048) {
+      T *= 2;
+      emax = tiles(T, es, el);
     }
-    P->ext_max = ext_max;
-    P->lds_jac = 2 * (size_t)ext_max * sizeof(double);
-    if (P->lds_jac > 160 * 1024) fail(WFP_EDOMAIN, "solve halo too large for one workgroup");
-    P->ext_start = P->alloc<int>(P->ntile);
-    P->ext_len = P->alloc<int>(P->ntile);
-    upload(P->ext_start, es, s);
-    upload(P->ext_len, el, s);
+    P->T = T;
+    P->ntile = (int)es.size();
+    P->ext_max = emax;
+    P->solve_threads = (int)std::min<int64_t>(256, 64 * nblk(emax, 64));
+    // tile matrices: rows of the extended range, couplings to other rows of it
+    std::vector<int> tr0(P->ntile), tg0(P->ntile), tleft(P->ntile), tn(P->ntile), rg, rptr, col;
+    std::vector<int64_t> rq, eq;
+    rptr.push_back(0);
+    for (int t = 0; t < P->ntile; ++t) {
+      const int64_t a0 = (int64_t)t * T;
+      tr0[t] = (int)rg.size();
+      tg0[t] = (int)a0;
+      tn[t] = (int)(std::min<int64_t>(M, a0 + T) - a0);
+      tleft[t] = (int)((a0 - es[t] + M) % M);
+      for (int e = 0; e < el[t]; ++e) {
+        const int64_t g = (es[t] + e) % M;
+        rg.push_back((int)g);
+        int64_t self = (g - nbs[g] + M) % M;
+        rq.push_back(qo[g] + self);
+        for (int k = 0; k < nc[g]; ++k) {
+          const int64_t l = (ns[g] + k) % M;
+          if (l == g) continue;
+          const int64_t le = (l - es[t] + M) % M;
+          if (le >= el[t]) continue;   // outside the halo: only reaches rows that are not kept
+          col.push_back((int)le);
+          eq.push_back(qo[g] + (l - nbs[g] + M) % M);
+        }
+        rptr.push_back((int)col.size());
+      }
+    }
+    P->tile_r0 = P->alloc<int>(P->ntile);
+    P->tile_el = P->alloc<int>(P->ntile);
+    P->tile_g0 = P->alloc<int>(P->ntile);
+    P->tile_left = P->alloc<int>(P->ntile);
+    P->tile_n = P->alloc<int>(P->ntile);
+    P->srow_g = P->alloc<int>(rg.size());
+    P->srow_ptr = P->alloc<int>(rptr.size());
+    P->scol = P->alloc<int>(col.size());
+    P->srow_dinv = P->alloc<double>(rg.size());
+    P->sval = P->alloc<double>(col.size());
+    upload(P->tile_r0, tr0, s);
+    upload(P->tile_el, el, s);
+    upload(P->tile_g0, tg0, s);
+    upload(P->tile_left, tleft, s);
+    upload(P->tile_n, tn, s);
+    upload(P->srow_g, rg, s);
+    upload(P->srow_ptr, rptr, s);
+    upload(P->scol, col, s);
+    int64_t* eq_d = P->alloc<int64_t>(eq.size());
+    int64_t* rq_d = P->alloc<int64_t>(rq.size());
+    upload(eq_d, eq, s);
+    upload(rq_d, rq, s);
+    const int64_t ne = (int64_t)col.size(), nr = (int64_t)rg.size();
+    // LDS of the solve: c, s0, s1, dinv per row, (value, column) per coupling, row pointers
+    int max_ne = 0;
+    for (int t = 0; t < P->ntile; ++t) max_ne = std::max(max_ne, rptr[tr0[t] + el[t]] - rptr[tr0[t]]);
+    P->lds_jac = (size_t)emax * 4 * sizeof(double) + (size_t)max_ne * (sizeof(double) + sizeof(int)) +
+                 (size_t)(emax + 1) * sizeof(int);
+    if (P->lds_jac > 160 * 1024) fail(WFP_EDOMAIN, "solve tile too large for one workgroup");
+    hipLaunchKernelGGL(k_gather_solve, dim3(nblk(std::max(ne, nr), 256)), dim3(256), 0, s, ne, eq_d, P->Q,
+                       P->sval, nr, rq_d, P->srow_dinv);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    P->release(eq_d);
+    P->release(rq_d);
   }
+  // the dense weights of the scatterer rows are no longer needed
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(P->Q);
+  P->Q = nullptr;
+  P->release(mlo);
+  P->release(pbase);
+  P->ginc = P->alloc<double>(M);
+  P->loc = P->alloc<double>(M);
   if (!periodic) {
     P->tw_rbc = P->alloc<double2>(2 * P->K);
     std::vector<double2> tw(2 * P->K);
@@ -538,51 +770,80 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->rbc_v = P->alloc<double>(2 * P->K);
   }
   // kernels with more than 64 KB of LDS
-  HIPCHK(hipFuncSetAttribute((const void*)k_fft_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-  HIPCHK(hipFuncSetAttribute((const void*)k_fft_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_rbc_to_grid, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_rbc_to_modes, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-  HIPCHK(hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   zero_state(P);
   HIPCHK(hipStreamSynchronize(s));
 }
 
+// One level L, in stream order: driving data, local sum (levels < L), the
+// history part (three kernels; the free-space projection when due), solve,
+// receivers.
 void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, double* u_recv_out) {
   hipStream_t s = P->stream;
   const bool periodic = P->boundary == WFP_PERIODIC;
   const Packets pk{P->npk, periodic ? 1 : 0, P->packets};
+  int pp = 1;
+  while (pp < P->npk) pp *= 2;
+  const int rows_inc = 256 / pp;
+  // a multiple of 8 blocks, so the XCD-aware block remap is a bijection
+  const int nrowblk = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
+  const unsigned nb_b = (unsigned)(P->n2 / 2 + 1);
+  const size_t lds_b = 6 * (size_t)P->n1 * sizeof(double2) + 8 * (size_t)P->n1 * sizeof(double4);
   for (int64_t i = 0; i < n; ++i) {
     const int64_t L = P->level + i;
     const double t = (double)L * P->dt;
     const double* sig_prev = P->hist + (int64_t)(((L - 1) % P->NH + P->NH) % P->NH) * P->M;
-    hipLaunchKernelGGL(k_spread, dim3(nblk(P->nf, 256)), dim3(256), 0, s, P->nf, P->hf, 1.0 / P->alpha_es,
-                       P->beta_es, P->xs, sig_prev, (int)P->M, P->cstart, P->ccount, P->grid);
-    hipLaunchKernelGGL(k_fft_r2c, dim3(1), dim3(kFftThreads), P->lds_nf, s, P->fft_nf, (const double2*)P->grid,
-                       P->tw, 2, P->zbuf);
-    hipLaunchKernelGGL(k_modes, dim3(nblk(P->K + 1, 256)), dim3(256), 0, s, P->K, P->W, P->nfh, L, P->zbuf,
-                       P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, P->ring, P->alpha, P->dalpha, P->ybuf);
-    if (!periodic && L > 0 && L % P->rbc_period == 0) {
+    hipLaunchKernelGGL(k_incident, dim3(nblk(P->M, rows_inc)), dim3(256), 0, s, (int)P->M, t, P->xs, P->beta, pk,
+                       pp, P->ginc);
+    {
+      StageTimer st(P, WFP_STAGE_LOCAL, s);
+      hipLaunchKernelGGL(k_local_rhs, dim3(nrowblk), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L,
+                         P->nb_start, P->rowbase, P->ac, P->Qc, P->hist, P->loc);
+    }
+    {
+      StageTimer st(P, WFP_STAGE_SPREAD, s);
+      hipLaunchKernelGGL(k_hist_a, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, sig_prev,
+                         (int)P->M, P->cstart, P->ccount, P->swoff, P->sw, P->tw, P->T1);
+    }
+    const bool rbc = !periodic && L > 0 && L % P->rbc_period == 0;
+    {
+      StageTimer st(P, WFP_STAGE_MODES, s);
+      hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, rbc ? 1 : 0, P->fft_n1, P->n2, P->K, P->W, L,
+                         P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, P->ring, P->alpha, P->dalpha,
+                         P->ybuf, P->V);
+    }
+    if (rbc) {
+      StageTimer st(P, WFP_STAGE_RBC, s);
       hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->alpha,
                          P->dalpha, P->tw_rbc, (double2*)P->rbc_u, (double2*)P->rbc_v);
       hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->W,
                          P->h_rbc, P->delta_s, P->cheb_phi, P->cheb_g, P->ncheb, P->rbc_u, P->rbc_v, P->tw_rbc,
                          P->dk2, P->alpha, P->dalpha, P->ybuf);
+      hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, L, P->T1,
+                         P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, P->ring, P->alpha, P->dalpha, P->ybuf,
+                         P->V);
     }
-    hipLaunchKernelGGL(k_fft_c2r, dim3(1), dim3(kFftThreads), P->lds_nf, s, P->fft_nf, P->K, P->ybuf, P->tw, 2,
-                       (double2*)P->grid2);
-    hipLaunchKernelGGL(k_local_rhs, dim3(nblk(P->M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)P->M,
-                       P->NQ, P->NH, L, t, P->xs, P->beta, P->nb_start, P->nb_count, P->qoff, P->Q, P->hist,
-                       P->grid2, P->nf, P->hf, 1.0 / P->alpha_es, P->beta_es, P->width, pk, P->rhs);
+    {
+      StageTimer st(P, WFP_STAGE_FFT_INV, s);
+      hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, P->V,
+                         P->tw, (double2*)P->grid2);
+    }
     double* slot = P->hist + (int64_t)(L % P->NH) * P->M;
     double* save = (sigma_out && i % save_every == 0) ? sigma_out + (i / save_every) * P->M : nullptr;
-    hipLaunchKernelGGL(k_jacobi, dim3(P->ntile), dim3(256), P->lds_jac, s, (int)P->M, P->T, P->iters,
-                       P->ext_max, P->ext_start, P->ext_len, P->nb_start, P->qoff, P->Q, P->near_start,
-                       P->near_count, P->rhs, slot, save, P->perm);
+    {
+      StageTimer st(P, WFP_STAGE_SOLVE, s);
+      hipLaunchKernelGGL(k_solve, dim3(P->ntile), dim3(P->solve_threads), P->lds_jac, s, (int)P->M, P->iters,
+                         P->ext_max, P->tile_r0, P->tile_el, P->tile_g0, P->tile_left, P->tile_n, P->srow_g,
+                         P->srow_dinv, P->srow_ptr, P->scol, P->sval, P->ginc, P->loc, P->i0s, P->iw, P->beta,
+                         P->grid2, P->nf, P->width, slot, save, P->perm);
+    }
     if (P->R > 0 && u_recv_out) {
+      StageTimer st(P, WFP_STAGE_RECV, s);
       hipLaunchKernelGGL(k_receivers, dim3(nblk(P->R, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)P->R,
-                         (int)P->M, P->NQ, P->NH, L, P->xr, P->rnb_start, P->rnb_count, P->rqoff, P->Qr,
-                         P->hist, P->grid2, P->nf, P->hf, 1.0 / P->alpha_es, P->beta_es, P->width,
-                         u_recv_out + i * P->R);
+                         (int)P->M, P->NQ, P->NH, L, P->rnb_start, P->rnb_count, P->rqoff, P->Qr, P->hist,
+                         P->ri0s, P->riw, P->grid2, P->nf, P->width, u_recv_out + i * P->R);
     }
   }
   HIPCHK(hipGetLastError());
@@ -663,7 +924,40 @@ wfp_status wfp_plan_info(const wfp_plan* P, wfp_info* info) {
   info->b = P->b;
   info->solve_contraction = P->contraction;
   info->device_bytes = P->dev_bytes;
+  info->n_weights_nonzero = P->n_weights_nonzero;
+  info->n_weights_stored = P->n_weights_stored;
   return WFP_OK;
+}
+
+wfp_status wfp_set_profiling(wfp_plan* P, int32_t enable) {
+  if (!P) {
+    g_last_error = "NULL plan";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    flush_profile(P);
+    P->profiling = enable != 0;
+    if (P->profiling)
+      for (int i = 0; i < WFP_N_STAGES; ++i) {
+        P->prof_ms[i] = 0;
+        P->prof_n[i] = 0;
+      }
+  });
+}
+
+wfp_status wfp_get_profile(wfp_plan* P, double* ms, int64_t* launches) {
+  if (!P) {
+    g_last_error = "NULL plan";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipStreamSynchronize(P->stream));
+    flush_profile(P);
+    for (int i = 0; i < WFP_N_STAGES; ++i) {
+      if (ms) ms[i] = P->prof_ms[i];
+      if (launches) launches[i] = P->prof_n[i];
+    }
+  });
 }
 
 wfp_status wfp_run(wfp_plan* P, int64_t n_steps, double* sigma_out, int64_t save_every, double* u_recv_out) {

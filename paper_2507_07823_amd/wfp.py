@@ -22,6 +22,7 @@ WFP_EHIP = -4
 WFP_ESTATE = -5
 PERIODIC = 0
 FREE_SPACE = 1
+STAGES = ("spread", "fft_fwd", "modes", "rbc", "fft_inv", "local", "solve", "receivers")
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -46,7 +47,8 @@ class Info(ctypes.Structure):
                 ("n_gl_local", ctypes.c_int32), ("rbc_period", ctypes.c_int32), ("nufft_width", ctypes.c_int32),
                 ("solve_iters", ctypes.c_int32), ("boundary", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("delta", ctypes.c_double), ("b", ctypes.c_double), ("solve_contraction", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("n_weights_nonzero", ctypes.c_int64),
+                ("n_weights_stored", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -76,6 +78,10 @@ def load_library():
     lib.wfp_get_state.restype = ctypes.c_int32
     lib.wfp_set_state.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
     lib.wfp_set_state.restype = ctypes.c_int32
+    lib.wfp_set_profiling.argtypes = [vp, ctypes.c_int32]
+    lib.wfp_set_profiling.restype = ctypes.c_int32
+    lib.wfp_get_profile.argtypes = [vp, _c_dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.wfp_get_profile.restype = ctypes.c_int32
     lib.wfp_reset.argtypes = [vp]
     lib.wfp_reset.restype = ctypes.c_int32
     lib.wfp_status_string.argtypes = [ctypes.c_int32]
@@ -204,6 +210,16 @@ class Plan:
             assert t.dtype.itemsize == 8 if hasattr(t.dtype, "itemsize") else True
             assert t.is_contiguous() and t.is_cuda
         _check(self._lib.wfp_set_state(self._h, int(level), _ptr(hist), _ptr(ring), _ptr(alpha), _ptr(dalpha)))
+
+    def set_profiling(self, on=True):
+        _check(self._lib.wfp_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self):
+        """{stage: (total ms, launches)} from the library's HIP-event timing."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = (ctypes.c_int64 * len(STAGES))()
+        _check(self._lib.wfp_get_profile(self._h, ms, n))
+        return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
 
     def reset(self):
         _check(self._lib.wfp_reset(self._h))
