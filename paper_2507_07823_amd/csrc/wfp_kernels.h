@@ -27,8 +27,8 @@ struct Packets {
 // ---- set-up kernels ----
 __global__ void k_pq_tables(int64_t K, int W, int ng, double dt, const double* __restrict__ dphi_tab,
                             const double* __restrict__ ddphi_tab, const double* __restrict__ mu,
-                            const double* __restrict__ wmu, double* __restrict__ pk,
-                            double* __restrict__ qk, double* __restrict__ rot);
+                            const double* __restrict__ wmu, int n1, int n2, int64_t npos,
+                            double* __restrict__ pk, double* __restrict__ qk, double* __restrict__ rot);
 
 template <int P>
 __global__ void k_local_weights(int nrows, const double* __restrict__ xt,
@@ -61,7 +61,7 @@ __global__ void k_count_nonzero(int M, int NQ, const int* __restrict__ nb_count,
 
 // ---- per-level kernels ----
 __global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
-                            const int64_t* __restrict__ rowbase, const unsigned* __restrict__ ac,
+                            const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                             const double* __restrict__ Qc, const double* __restrict__ hist,
                             double* __restrict__ loc);
 __global__ void k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta,
@@ -83,6 +83,15 @@ __global__ void k_solve(int M, int iters, int ext_max, const int* __restrict__ t
                         const double* __restrict__ grid2, int nf, int width, double* __restrict__ sig_out,
                         double* __restrict__ save_row, const int* __restrict__ perm);
 
+__global__ void k_solve_direct(int M, const int* __restrict__ dt_g0, const int* __restrict__ dt_n,
+                               const int* __restrict__ dt_p0, const int* __restrict__ pt_cs,
+                               const int* __restrict__ pt_cn, const int64_t* __restrict__ pt_inv,
+                               const double* __restrict__ inv, const double* __restrict__ ginc,
+                               const double* __restrict__ loc, const int* __restrict__ i0s,
+                               const double* __restrict__ iw, const double* __restrict__ beta,
+                               const double* __restrict__ grid2, int nf, int width,
+                               double* __restrict__ sig_out, double* __restrict__ save_row,
+                               const int* __restrict__ perm);
 __global__ void k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
                             const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
                             const double* __restrict__ Q, const double* __restrict__ hist,
@@ -94,7 +103,7 @@ __global__ void k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int
                          const int* __restrict__ cstart, const int* __restrict__ ccount,
                          const int64_t* __restrict__ woff, const double* __restrict__ sw,
                          const double2* __restrict__ tw, double2* __restrict__ T1);
-__global__ void k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L,
+__global__ void k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos,
                          const double2* __restrict__ T1, const double2* __restrict__ tw,
                          const double* __restrict__ dk1, const double* __restrict__ dk2,
                          const double* __restrict__ pk, const double* __restrict__ qk,
@@ -105,10 +114,10 @@ __global__ void k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, cons
                          double2* __restrict__ grid2);
 
 // ---- free-space radiation boundary projection ----
-__global__ void k_rbc_to_grid(FftPlan fp, int64_t K, const double2* __restrict__ alpha,
+__global__ void k_rbc_to_grid(FftPlan fp, int64_t K, int n1, int n2, const double2* __restrict__ alpha,
                               const double2* __restrict__ dalpha, const double2* __restrict__ tw,
                               double2* __restrict__ gu, double2* __restrict__ gv);
-__global__ void k_rbc_to_modes(FftPlan fp, int64_t K, int W, double h, double delta_s,
+__global__ void k_rbc_to_modes(FftPlan fp, int64_t K, int n1, int n2, int W, double h, double delta_s,
                                const double* __restrict__ cheb_phi, const double* __restrict__ cheb_g,
                                int ncheb, const double* __restrict__ gu, const double* __restrict__ gv,
                                const double2* __restrict__ tw, const double* __restrict__ dk2,
@@ -118,8 +127,10 @@ __global__ void k_rbc_to_modes(FftPlan fp, int64_t K, int W, double h, double de
 // ---- state movement ----
 __global__ void k_hist_io(int M, int NH, int64_t L, int to_user, double* __restrict__ hist,
                           double* __restrict__ user, const int* __restrict__ perm);
-__global__ void k_ring_io(int64_t K, int W, int64_t L, int to_user, double2* __restrict__ ring,
-                          double2* __restrict__ user);
+__global__ void k_ring_io(int64_t K, int W, int64_t L, int n1, int n2, int64_t npos, int to_user,
+                          double2* __restrict__ ring, double2* __restrict__ user);
+__global__ void k_modes_io(int64_t K, int n1, int n2, int to_user, double2* __restrict__ a,
+                           double2* __restrict__ user);
 __global__ void k_fill(double* __restrict__ p, int64_t n, double v);
 
 }  // namespace wfp

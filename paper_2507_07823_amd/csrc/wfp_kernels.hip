@@ -52,6 +52,17 @@ __device__ __forceinline__ double cheb(const double* __restrict__ a, int n, doub
   return fma(s, b1, 0.5 * a[0] - b2);
 }
 
+// Storage position of Fourier mode q in every per-mode array (tables, spectra
+// ring, alpha, alpha'): the order in which the history kernel's blocks visit
+// the modes.  q = k2 + n2 k1 lives in block b = min(k2, n2 - k2) (column pair
+// {k2, n2 - k2}), column c = (k2 > n2/2), at b * 2 n1 + c * n1 + k1.
+__device__ __forceinline__ int64_t mode_pos(int64_t q, int n1, int n2) {
+  const int k2 = (int)(q % n2), k1 = (int)(q / n2);
+  const int b = (k2 == 0) ? 0 : min(k2, n2 - k2);
+  const int c = (k2 == b) ? 0 : 1;
+  return (int64_t)b * 2 * n1 + c * n1 + k1;
+}
+
 __device__ __forceinline__ int mod_slot(int64_t n, int N) {
   int s = (int)(n % N);
   return s < 0 ? s + N : s;
@@ -200,10 +211,11 @@ __device__ void fft_batch(double2* buf, int nb, const FftPlan& fp, const double2
 // ---------------------------------------------------------------------------
 __global__ void k_pq_tables(int64_t K, int W, int ng, double dt, const double* __restrict__ dphi_tab,
                             const double* __restrict__ ddphi_tab, const double* __restrict__ mu,
-                            const double* __restrict__ wmu, double* __restrict__ pk,
-                            double* __restrict__ qk, double* __restrict__ rot) {
+                            const double* __restrict__ wmu, int n1, int n2, int64_t npos,
+                            double* __restrict__ pk, double* __restrict__ qk, double* __restrict__ rot) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k > K) return;
+  const int64_t pos = mode_pos(k, n1, n2);
   const double kd = (double)k;
   for (int m = 0; m < W; ++m) {
     double ps = 0.0, qs = 0.0;
@@ -216,12 +228,12 @@ __global__ void k_pq_tables(int64_t K, int W, int ng, double dt, const double* _
       ps += wmu[q] * sk_u * psi;
       qs += wmu[q] * cos(kd * u) * psi;
     }
-    pk[(int64_t)m * (K + 1) + k] = dt * ps;
-    qk[(int64_t)m * (K + 1) + k] = dt * qs;
+    pk[(int64_t)m * npos + pos] = dt * ps;
+    qk[(int64_t)m * npos + pos] = dt * qs;
   }
-  rot[3 * k + 0] = cos(kd * dt);
-  rot[3 * k + 1] = (k == 0) ? dt : sin(kd * dt) / kd;
-  rot[3 * k + 2] = -kd * sin(kd * dt);
+  rot[3 * pos + 0] = cos(kd * dt);
+  rot[3 * pos + 1] = (k == 0) ? dt : sin(kd * dt) / kd;
+  rot[3 * pos + 2] = -kd * sin(kd * dt);
 }
 
 // ---------------------------------------------------------------------------
@@ -472,50 +484,36 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
 
 // Local sum of lags m >= 1, one row per wavefront.  The row's packed weights
 // are one block per lag m (sources a_m .. a_m + c_m - 1 of its neighbour list,
-// offset off_m).  The wavefront works as four groups of 16 lanes, group g on
-// lag mb + g of the current quad of lags: each group streams one contiguous
-// segment of weights and densities (one 128-byte line per 16 lanes), with the
-// per-lag data broadcast from the lane that scanned it.
+// at offset off_m within the row).  Lane m loads lag m's (a, c, off); the
+// wavefront then works as four groups of 16 lanes, group g on lag mb + g of
+// the current quad of lags: each group streams one contiguous block of
+// weights and densities (one 128-byte line per 16 lanes), eight elements per
+// lane with every load issued before use.
 constexpr int kMaxNQ = 64;
 
 __global__ void __launch_bounds__(256)
-k_local_rhs(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start, const int64_t* __restrict__ rowbase,
-            const unsigned* __restrict__ ac, const double* __restrict__ Qc, const double* __restrict__ hist,
-            double* __restrict__ loc) {
+k_local_rhs(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
+            const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
+            const double* __restrict__ hist, double* __restrict__ loc) {
   const int lane = threadIdx.x & 63;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int j = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= M) return;   // no block-level barrier in this kernel
   const int st = nb_start[j];
-  // lane m (1 <= m < NQ) holds lag m's range; exclusive scan of the counts
-  int cnt = 0, av = 0;
-  if (lane >= 1 && lane < NQ) {
-    const unsigned v = ac[(int64_t)j * NQ + lane];
-    av = v & 0xffff;
-    cnt = v >> 16;
-  }
-  int incl = cnt;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
-  const int excl = incl - cnt;
+  uint2 mine = make_uint2(0u, 0u);
+  if (lane >= 1 && lane < NQ) mine = acx[(int64_t)j * NQ + lane];
   const double* __restrict__ q = Qc + rowbase[j];
   const int grp = lane >> 4, gl = lane & 15;
   double acc0 = 0.0, acc1 = 0.0;
   for (int mb = 1; mb < NQ; mb += 4) {
     const int m = mb + grp;
     const int src = m < 64 ? m : 0;
-    int c = __shfl(cnt, src, 64);
-    const int a = __shfl(av, src, 64);
-    const int off = __shfl(excl, src, 64);
-    if (m >= NQ) c = 0;
-    const double* __restrict__ qp = q + off;
+    const unsigned vx = __shfl(mine.x, src, 64), vy = __shfl(mine.y, src, 64);
+    const int c = m < NQ ? (int)(vx >> 16) : 0;
+    const double* __restrict__ qp = q + vy;
     const double* __restrict__ hp = hist + (int64_t)mod_slot(L - m, NH) * M;
-    int l0 = st + a;
+    int l0 = st + (int)(vx & 0xffff);
     if (l0 >= M) l0 -= M;
-    // up to 8 segment elements per lane with every load issued before use
     for (int i0 = 0; i0 < c; i0 += 128) {
       double qv[8], hv[8];
 #pragma unroll
@@ -639,10 +637,41 @@ k_solve(int M, int iters, int ext_max, const int* __restrict__ tile_r0, const in
   }
   const int g0 = tile_g0[t], left = tile_left[t], nt = tile_n[t];
   for (int k = threadIdx.x; k < nt; k += blockDim.x) {
-    const int g = g0 + k;
+    int g = g0 + k;
+    if (g >= M) g -= M;   // a run may wrap around the periodic box
     const double v = s0[left + k];
     sig_out[g] = v;
     if (save_row) save_row[perm[g]] = v;
+  }
+}
+
+// Per-step solve on small nearby-runs: I + S is block diagonal over maximal
+// runs of consecutive springs closer than dt; a run of s springs is solved with
+// its precomputed inverse,  sigma_i = sum_k inv[i][k] rhs_k.  One block per
+// tile of whole runs (points g0 .. g0 + n - 1, circular).  Per point: the
+// run's first local index, its size and the offset of its inverse row.
+__global__ void __launch_bounds__(256)
+k_solve_direct(int M, const int* __restrict__ dt_g0, const int* __restrict__ dt_n, const int* __restrict__ dt_p0,
+               const int* __restrict__ pt_cs, const int* __restrict__ pt_cn, const int64_t* __restrict__ pt_inv,
+               const double* __restrict__ inv, const double* __restrict__ ginc, const double* __restrict__ loc,
+               const int* __restrict__ i0s, const double* __restrict__ iw, const double* __restrict__ beta,
+               const double* __restrict__ grid2, int nf, int width, double* __restrict__ sig_out,
+               double* __restrict__ save_row, const int* __restrict__ perm) {
+  __shared__ double c[256];
+  const int t = blockIdx.x;
+  const int g0 = dt_g0[t], n = dt_n[t], p0 = dt_p0[t];
+  const int e = threadIdx.x;
+  int g = g0 + e;
+  if (g >= M) g -= M;
+  if (e < n) c[e] = (ginc[g] - loc[g]) - beta[g] * interp_pre(g, i0s, iw, grid2, nf, width);
+  __syncthreads();
+  if (e < n) {
+    const int cs = pt_cs[p0 + e], cn = pt_cn[p0 + e];
+    const double* __restrict__ row = inv + pt_inv[p0 + e];
+    double acc = 0.0;
+    for (int k = 0; k < cn; ++k) acc = fma(row[k], c[cs + k], acc);
+    sig_out[g] = acc;
+    if (save_row) save_row[perm[g]] = acc;
   }
 }
 
@@ -679,20 +708,21 @@ k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_
 // the modes |k| < K (k = K dropped): grid = c2r of y_k = (-1)^k conj(a_k).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024)
-k_rbc_to_grid(FftPlan fp, int64_t K, const double2* __restrict__ alpha, const double2* __restrict__ dalpha,
-              const double2* __restrict__ tw, double2* __restrict__ gu, double2* __restrict__ gv) {
+k_rbc_to_grid(FftPlan fp, int64_t K, int n1, int n2, const double2* __restrict__ alpha,
+              const double2* __restrict__ dalpha, const double2* __restrict__ tw, double2* __restrict__ gu,
+              double2* __restrict__ gv) {
   extern __shared__ double2 buf[];
   const double2* __restrict__ a = (blockIdx.x == 0) ? alpha : dalpha;
   double2* __restrict__ out = (blockIdx.x == 0) ? gu : gv;
   const int n = fp.n;  // == K
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     const double sk = (k & 1) ? -1.0 : 1.0;
-    const double2 yk = cscale(cconj(a[k]), sk);
+    const double2 yk = cscale(cconj(a[mode_pos(k, n1, n2)]), sk);
     const int km = n - k;   // 1..K-1 for k >= 1
     double2 ym = make_double2(0.0, 0.0);
     if (k > 0) {
       const double sm = (km & 1) ? -1.0 : 1.0;
-      ym = cconj(cscale(cconj(a[km]), sm));
+      ym = cconj(cscale(cconj(a[mode_pos(km, n1, n2)]), sm));
     }
     const double2 zk = cadd(cadd(yk, ym), cmul_pi(cmul(cconj(tw[k]), csub(yk, ym))));
     buf[k] = cconj(zk);
@@ -707,7 +737,8 @@ k_rbc_to_grid(FftPlan fp, int64_t K, const double2* __restrict__ alpha, const do
 // then back to modes alpha_k = (1/2K) (-1)^k conj(X_k), k < K, alpha_K = 0.
 // Block 0 writes alpha and the type-2 input y, block 1 writes alpha'.
 __global__ void __launch_bounds__(1024)
-k_rbc_to_modes(FftPlan fp, int64_t K, int W, double h, double delta_s, const double* __restrict__ cheb_phi,
+k_rbc_to_modes(FftPlan fp, int64_t K, int n1, int n2, int W, double h, double delta_s,
+               const double* __restrict__ cheb_phi,
                const double* __restrict__ cheb_g, int ncheb, const double* __restrict__ gu,
                const double* __restrict__ gv, const double2* __restrict__ tw, const double* __restrict__ dk2,
                double2* __restrict__ alpha, double2* __restrict__ dalpha, double2* __restrict__ y) {
@@ -754,8 +785,9 @@ k_rbc_to_modes(FftPlan fp, int64_t K, int W, double h, double delta_s, const dou
       const double sk = (k & 1) ? -1.0 : 1.0;
       a = cscale(cconj(X), sk * inv);
     }
-    out[k] = a;
-    if (!is_v) y[k] = cscale(cconj(a), dk2[k]);
+    const int64_t pos = mode_pos(k, n1, n2);
+    out[pos] = a;
+    if (!is_v) y[k] = cscale(cconj(a), dk2[pos]);
   }
 }
 
@@ -807,7 +839,7 @@ k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* _
   }
 }
 
-constexpr int kFirGroups = 4;
+constexpr int kFirGroups = 8;
 
 // Partner of position (c, k1) in the column pair: where Z_{n - q} sits, q = col[c] + n2 k1.
 __device__ __forceinline__ int partner(int c, int k1, int k2c, int ncol, int n1) {
@@ -820,7 +852,7 @@ __device__ __forceinline__ int partner(int c, int k1, int k2c, int ncol, int n1)
 // modes, writing y (the type-2 input) for a later projection; mode 2: inverse
 // step 1 from y.
 __global__ void __launch_bounds__(512)
-k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, const double2* __restrict__ T1,
+k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos, const double2* __restrict__ T1,
          const double2* __restrict__ tw, const double* __restrict__ dk1, const double* __restrict__ dk2,
          const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,
          double2* __restrict__ ring, double2* __restrict__ alpha, double2* __restrict__ dalpha,
@@ -835,7 +867,8 @@ k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, const double
   const int k2a = blockIdx.x, k2b = (n2 - k2a) % n2;
   const int ncol = (k2a == k2b) ? 1 : 2;
   const int np = ncol * n1;
-  const int64_t stride = K + 1;
+  const int64_t stride = npos;
+  const int64_t pb = (int64_t)k2a * 2 * n1;   // position of this block's first mode
   auto colk2 = [&](int c) { return c == 0 ? k2a : k2b; };
   if (mode != 2) {
     for (int e = threadIdx.x; e < np; e += blockDim.x) {
@@ -856,7 +889,7 @@ k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, const double
         const double2 E = cscale(cadd(zk, zc), 0.5);
         const double2 O = cscale(cmul_mi(csub(zk, zc)), 0.5);
         const double2 X = cadd(E, cmul(tw[q], O));
-        S = cscale(cconj(X), dk1[q]);
+        S = cscale(cconj(X), dk1[pb + e]);
       }
       sS[e] = S;
     }
@@ -868,9 +901,10 @@ k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, const double
       const int64_t q = colk2(c) + (int64_t)n2 * k1;
       double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
       if (q <= K) {
+#pragma unroll 2
         for (int m = g; m < W; m += kFirGroups) {
-          const double2 Sm = (m == 0) ? sS[e] : ring[(int64_t)mod_slot(nn - m, W) * stride + q];
-          const double p = pk[(int64_t)m * stride + q], qq = qk[(int64_t)m * stride + q];
+          const double2 Sm = (m == 0) ? sS[e] : ring[(int64_t)mod_slot(nn - m, W) * stride + pb + e];
+          const double p = pk[(int64_t)m * stride + pb + e], qq = qk[(int64_t)m * stride + pb + e];
           acc.x = fma(p, Sm.x, acc.x);
           acc.y = fma(p, Sm.y, acc.y);
           acc.z = fma(qq, Sm.x, acc.z);
@@ -893,14 +927,15 @@ k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, const double
           g.x += v.z;
           g.y += v.w;
         }
-        ring[(int64_t)mod_slot(nn, W) * stride + q] = sS[e];
-        const double cr = rot[3 * q], sr = rot[3 * q + 1], rr = rot[3 * q + 2];
-        const double2 a = alpha[q], da = dalpha[q];
+        const int64_t ps = pb + e;
+        ring[(int64_t)mod_slot(nn, W) * stride + ps] = sS[e];
+        const double cr = rot[3 * ps], sr = rot[3 * ps + 1], rr = rot[3 * ps + 2];
+        const double2 a = alpha[ps], da = dalpha[ps];
         const double2 an = make_double2(cr * a.x + sr * da.x + h.x, cr * a.y + sr * da.y + h.y);
         const double2 dan = make_double2(rr * a.x + cr * da.x + g.x, rr * a.y + cr * da.y + g.y);
-        alpha[q] = an;
-        dalpha[q] = dan;
-        yq = cscale(cconj(an), dk2[q]);
+        alpha[ps] = an;
+        dalpha[ps] = dan;
+        yq = cscale(cconj(an), dk2[ps]);
         if (mode == 1) y[q] = yq;
       }
       yl[e] = yq;
@@ -960,17 +995,27 @@ __global__ void k_hist_io(int M, int NH, int64_t L, int to_user, double* __restr
   else *h = *u;
 }
 
-__global__ void k_ring_io(int64_t K, int W, int64_t L, int to_user, double2* __restrict__ ring,
-                          double2* __restrict__ user) {
+__global__ void k_ring_io(int64_t K, int W, int64_t L, int n1, int n2, int64_t npos, int to_user,
+                          double2* __restrict__ ring, double2* __restrict__ user) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)W * (K + 1)) return;
   const int m = (int)(t / (K + 1));
   const int64_t k = t % (K + 1);
   const int slot = mod_slot(L - 2 - m, W);
-  double2* r = ring + (int64_t)slot * (K + 1) + k;
+  double2* r = ring + (int64_t)slot * npos + mode_pos(k, n1, n2);
   double2* u = user + (int64_t)m * (K + 1) + k;
   if (to_user) *u = *r;
   else *r = *u;
+}
+
+// alpha or alpha' between the position order and the caller's k order.
+__global__ void k_modes_io(int64_t K, int n1, int n2, int to_user, double2* __restrict__ a,
+                           double2* __restrict__ user) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > K) return;
+  double2* r = a + mode_pos(k, n1, n2);
+  if (to_user) user[k] = *r;
+  else *r = user[k];
 }
 
 __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {

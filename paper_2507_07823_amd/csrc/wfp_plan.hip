@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,6 +52,42 @@ void upload(T* d, const std::vector<T>& h, hipStream_t s) {
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Same mode position as the device (see mode_pos in the kernels).
+int64_t mode_pos_host(int64_t q, int n1, int n2) {
+  const int k2 = (int)(q % n2), k1 = (int)(q / n2);
+  const int b = (k2 == 0) ? 0 : std::min(k2, n2 - k2);
+  const int c = (k2 == b) ? 0 : 1;
+  return (int64_t)b * 2 * n1 + c * n1 + k1;
+}
+
+// Inverse of a small dense matrix (row-major n x n) by Gauss-Jordan elimination
+// with partial pivoting in long double.
+void invert_dense(int n, const double* a, double* out) {
+  std::vector<long double> m((size_t)n * 2 * n, 0.0L);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) m[(size_t)i * 2 * n + j] = a[(size_t)i * n + j];
+    m[(size_t)i * 2 * n + n + i] = 1.0L;
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs((double)m[(size_t)r * 2 * n + c]) > std::fabs((double)m[(size_t)piv * 2 * n + c])) piv = r;
+    if (m[(size_t)piv * 2 * n + c] == 0.0L) fail(WFP_EDOMAIN, "singular per-step system");
+    if (piv != c)
+      for (int j = 0; j < 2 * n; ++j) std::swap(m[(size_t)piv * 2 * n + j], m[(size_t)c * 2 * n + j]);
+    const long double d = m[(size_t)c * 2 * n + c];
+    for (int j = 0; j < 2 * n; ++j) m[(size_t)c * 2 * n + j] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const long double f = m[(size_t)r * 2 * n + c];
+      if (f == 0.0L) continue;
+      for (int j = 0; j < 2 * n; ++j) m[(size_t)r * 2 * n + j] -= f * m[(size_t)c * 2 * n + j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) out[(size_t)i * n + j] = (double)m[(size_t)i * 2 * n + n + j];
+}
+
 FftPlan make_fft_plan(int64_t n) {
   FftPlan fp{};
   fp.n = (int)n;
@@ -76,6 +113,7 @@ struct wfp_plan {
   double dt = 0, delta = 0, b = 0, hf = 0, alpha_es = 0, beta_es = 0, h_rbc = 0, delta_s = 0, contraction = 0;
   FftPlan fft_nf{}, fft_rbc{}, fft_n1{}, fft_n2{};
   int n1 = 0, n2 = 0;           // four-step split of the half-length transform
+  int64_t npos = 0;             // length of the per-mode arrays (mode-position order)
   double2 *T1 = nullptr, *V = nullptr;
   size_t lds_rbc = 0, lds_jac = 0, lds_qw = 0;
   std::vector<int> perm_h;
@@ -96,6 +134,8 @@ struct wfp_plan {
   double* Q = nullptr;          // dense weights of the scatterer rows (plan set-up only)
   double* Qc = nullptr;         // packed weights of lags >= 1
   unsigned* ac = nullptr;       // per (row, lag) source range a | c << 16
+  uint2* acx = nullptr;         // per (row, lag): (a | c << 16, packed offset within the row)
+  int nqd = 0;                  // quads of lags per row (local-sum tasks per row)
   int64_t* rowbase = nullptr;   // packed offset of each row
   double* ginc = nullptr;       // -g_j(t_L), per row
   double* loc = nullptr;        // local sum of lags >= 1, per row
@@ -104,6 +144,11 @@ struct wfp_plan {
   int *srow_g = nullptr, *srow_ptr = nullptr, *scol = nullptr;
   double *srow_dinv = nullptr, *sval = nullptr;
   int solve_threads = 64;
+  // direct solve of small runs
+  int n_direct_tiles = 0;
+  int *dt_g0 = nullptr, *dt_n = nullptr, *dt_p0 = nullptr, *pt_cs = nullptr, *pt_cn = nullptr;
+  int64_t* pt_inv = nullptr;
+  double* inv = nullptr;
   // precomputed spreading / interpolation weights
   int64_t* swoff = nullptr;
   double* sw = nullptr;
@@ -156,9 +201,9 @@ void zero_state(wfp_plan* P) {
     hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, P->stream, ptr, n, 0.0);
   };
   fill(P->hist, (int64_t)P->NH * P->M);
-  fill((double*)P->ring, 2 * (int64_t)P->W * (P->K + 1));
-  fill((double*)P->alpha, 2 * (P->K + 1));
-  fill((double*)P->dalpha, 2 * (P->K + 1));
+  fill((double*)P->ring, 2 * (int64_t)P->W * P->npos);
+  fill((double*)P->alpha, 2 * P->npos);
+  fill((double*)P->dalpha, 2 * P->npos);
   fill((double*)P->ybuf, 2 * (P->K + 1));
   HIPCHK(hipGetLastError());
   P->level = 0;
@@ -328,6 +373,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     if (P->n2 > 1024) fail(WFP_EDOMAIN, "fine grid too long for the four-step transform");
     P->fft_n1 = make_fft_plan(P->n1);
     P->fft_n2 = make_fft_plan(P->n2);
+    P->npos = (int64_t)(P->n2 / 2 + 1) * 2 * P->n1;
     // batched LDS stages run on 256 threads with at most kFftMaxB butterflies each
     for (int i = 0; i < P->fft_n1.nst; ++i)
       if (2 * P->n1 / P->fft_n1.radix[i] > kFftMaxB * 256) fail(WFP_EDOMAIN, "four-step factor n1 too long");
@@ -388,14 +434,14 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   P->beta = P->alloc<double>(M);
   P->perm = P->alloc<int>(M);
   P->hist = P->alloc<double>((size_t)P->NH * M);
-  P->ring = P->alloc<double2>((size_t)P->W * (P->K + 1));
-  P->alpha = P->alloc<double2>(P->K + 1);
-  P->dalpha = P->alloc<double2>(P->K + 1);
-  P->pk = P->alloc<double>((size_t)P->W * (P->K + 1));
-  P->qk = P->alloc<double>((size_t)P->W * (P->K + 1));
-  P->rot = P->alloc<double>(3 * (P->K + 1));
-  P->dk1 = P->alloc<double>(P->K + 1);
-  P->dk2 = P->alloc<double>(P->K + 1);
+  P->ring = P->alloc<double2>((size_t)P->W * P->npos);
+  P->alpha = P->alloc<double2>(P->npos);
+  P->dalpha = P->alloc<double2>(P->npos);
+  P->pk = P->alloc<double>((size_t)P->W * P->npos);
+  P->qk = P->alloc<double>((size_t)P->W * P->npos);
+  P->rot = P->alloc<double>(3 * P->npos);
+  P->dk1 = P->alloc<double>(P->npos);
+  P->dk2 = P->alloc<double>(P->npos);
   P->tw = P->alloc<double2>(nf);
   P->T1 = P->alloc<double2>(P->nfh);
   P->V = P->alloc<double2>(P->nfh);
@@ -425,15 +471,16 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   }
   // ---- NUFFT deconvolution: Psi_hat(k) = alpha int_{-1}^{1} psi(z) cos(k alpha z) dz ----
   {
-    std::vector<double> d1(P->K + 1), d2(P->K + 1), psi(256);
+    std::vector<double> d1(P->npos, 0.0), d2(P->npos, 0.0), psi(256);
     for (int q = 0; q < 256; ++q) psi[q] = std::exp(P->beta_es * (std::sqrt(1.0 - gez[q] * gez[q]) - 1.0));
     for (int64_t k = 0; k <= P->K; ++k) {
       long double acc = 0;
       for (int q = 0; q < 256; ++q) acc += (long double)gew[q] * psi[q] * std::cos((double)k * P->alpha_es * gez[q]);
       const double ph = P->alpha_es * (double)acc;
       const double sg = (k & 1) ? -1.0 : 1.0;
-      d1[k] = sg * P->hf / (kTwoPi * ph);
-      d2[k] = sg * P->hf / ph;
+      const int64_t pos = mode_pos_host(k, P->n1, P->n2);
+      d1[pos] = sg * P->hf / (kTwoPi * ph);
+      d2[pos] = sg * P->hf / ph;
     }
     upload(P->dk1, d1, s);
     upload(P->dk2, d2, s);
@@ -461,7 +508,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     upload(dph_d, dph, s);
     upload(ddph_d, ddph, s);
     hipLaunchKernelGGL(k_pq_tables, dim3(nblk(P->K + 1, 128)), dim3(128), 0, s, P->K, P->W, P->ngpq, P->dt,
-                       dph_d, ddph_d, dmu, dwmu, P->pk, P->qk, P->rot);
+                       dph_d, ddph_d, dmu, dwmu, P->n1, P->n2, P->npos, P->pk, P->qk, P->rot);
     HIPCHK(hipGetLastError());
   }
   // ---- spreading ranges: sources within the kernel support of each cell ----
@@ -575,11 +622,22 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     HIPCHK(hipMemcpyAsync(ach.data(), P->ac, ach.size() * sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     std::vector<int64_t> rb(M);
+    std::vector<uint2> acxh((size_t)M * P->NQ);
     int64_t packed = 0;
     for (int64_t j = 0; j < M; ++j) {
       rb[j] = packed;
-      for (int m = 1; m < P->NQ; ++m) packed += ach[(size_t)j * P->NQ + m] >> 16;
+      unsigned within = 0;
+      for (int m = 0; m < P->NQ; ++m) {
+        const unsigned v = ach[(size_t)j * P->NQ + m];
+        acxh[(size_t)j * P->NQ + m] = make_uint2(v, within);
+        if (m >= 1) within += v >> 16;
+      }
+      packed += within;
     }
+    P->nqd = (P->NQ - 1 + 3) / 4;
+    P->acx = P->alloc<uint2>(acxh.size());
+    upload(P->acx, acxh, s);
+    HIPCHK(hipStreamSynchronize(s));
     P->n_weights_stored = packed;
     P->rowbase = P->alloc<int64_t>(M);
     P->Qc = P->alloc<double>(packed);
@@ -645,110 +703,225 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
       P->iters = 1 + (int)std::ceil(std::log(1e-18) / std::log(rho));
     }
     const double reach = P->iters * P->dt * (1.0 + 1e-9) + 1e-12;
-    // extended (tile + halo) ranges for a tile size T
-    auto tiles = [&](int T, std::vector<int>& es, std::vector<int>& el) {
-      const int nt = (int)((M + T - 1) / T);
-      es.assign(nt, 0);
-      el.assign(nt, 0);
-      int emax = 0;
-      for (int t = 0; t < nt; ++t) {
-        const int64_t a0 = (int64_t)t * T, c0i = std::min<int64_t>(M, a0 + T) - 1;
-        int s0, n0, s1, n1;
-        source_range(xs, xs[a0], reach, periodic, true, s0, n0);
-        source_range(xs, xs[c0i], reach, periodic, true, s1, n1);
-        int64_t lo = s0, hi = (int64_t)s1 + n1;
-        if (!periodic) {
-          lo = std::min<int64_t>(lo, a0);
-          hi = std::max<int64_t>(hi, c0i + 1);
-          es[t] = (int)lo;
-          el[t] = (int)(hi - lo);
-        } else {
-          int64_t left = (a0 - lo + M) % M;
-          int64_t right = (hi - 1 - c0i + 2 * M) % M;
-          int64_t len = left + (c0i - a0 + 1) + right;
-          if (n0 >= M || n1 >= M || len >= M) {
-            es[t] = (int)a0;   // whole circle, starting at the tile
-            el[t] = (int)M;
-          } else {
-            es[t] = (int)((a0 - left + M) % M);
-            el[t] = (int)len;
+    // ---- runs of consecutive springs closer than dt: I + S is block diagonal over them ----
+    std::vector<char> link(M, 0);
+    for (int64_t i = 0; i < M; ++i)
+      if (periodic || i + 1 < M) link[i] = pair_distance(xs[i], xs[(i + 1) % M], periodic) < P->dt;
+    struct Run { int64_t start, len; };
+    std::vector<Run> runs;
+    bool whole_circle = false;
+    {
+      int64_t b0 = -1;
+      if (periodic) {
+        for (int64_t i = 0; i < M; ++i)
+          if (!link[i]) { b0 = i; break; }
+        if (b0 < 0) whole_circle = true;
+      }
+      if (whole_circle) {
+        runs.push_back({0, M});
+      } else {
+        const int64_t s0 = periodic ? (b0 + 1) % M : 0;
+        int64_t cur = s0, len = 1;
+        for (int64_t k = 1; k < M; ++k) {
+          const int64_t i = (s0 + k - 1) % M;
+          if (link[i]) ++len;
+          else {
+            runs.push_back({cur, len});
+            cur = (s0 + k) % M;
+            len = 1;
           }
         }
-        emax = std::max(emax, el[t]);
+        runs.push_back({cur, len});
+      }
+    }
+    const int64_t kDirectMax = 96;
+    // ---- direct tiles: whole small runs, contiguous, up to 256 points ----
+    {
+      std::vector<int> dg0, dn, dp0, pcs, pcn;
+      std::vector<int64_t> pinv, gq;          // gq: weight index of each inverse-matrix coupling
+      std::vector<int64_t> run_inv_off;       // per small run: offset of its inverse
+      std::vector<std::array<int64_t, 2>> small;   // (start, len)
+      int64_t inv_total = 0;
+      int64_t next_contig = -1;
+      for (const Run& r : runs) {
+        if (whole_circle || r.len > kDirectMax) { next_contig = -1; continue; }
+        const bool cont = (next_contig == r.start) && !dn.empty() && dn.back() + r.len <= 256;
+        if (!cont) {
+          dg0.push_back((int)r.start);
+          dn.push_back(0);
+          dp0.push_back((int)pcs.size());
+        }
+        const int cs = dn.back();
+        for (int64_t k = 0; k < r.len; ++k) {
+          pcs.push_back(cs);
+          pcn.push_back((int)r.len);
+          pinv.push_back(inv_total + k * r.len);
+        }
+        dn.back() += (int)r.len;
+        run_inv_off.push_back(inv_total);
+        small.push_back({r.start, r.len});
+        inv_total += r.len * r.len;
+        next_contig = (r.start + r.len) % M;
+      }
+      P->n_direct_tiles = (int)dg0.size();
+      if (P->n_direct_tiles > 0) {
+        // couplings inside each small run: (run, i, j) -> weight index of S_ij (lag 0)
+        std::vector<int64_t> coup_q;
+        std::vector<int64_t> coup_pos;   // position in the inverse-matrix buffer
+        for (size_t rr = 0; rr < small.size(); ++rr) {
+          const int64_t st = small[rr][0], len = small[rr][1];
+          for (int64_t i = 0; i < len; ++i) {
+            const int64_t gi = (st + i) % M;
+            for (int64_t j = 0; j < len; ++j) {
+              const int64_t gj = (st + j) % M;
+              if (pair_distance(xs[gi], xs[gj], periodic) < P->dt) {
+                coup_q.push_back(qo[gi] + (gj - nbs[gi] + M) % M);
+                coup_pos.push_back(run_inv_off[rr] + i * len + j);
+              }
+            }
+          }
+        }
+        int64_t* cq_d = P->alloc<int64_t>(coup_q.size());
+        double* cv_d = P->alloc<double>(coup_q.size());
+        upload(cq_d, coup_q, s);
+        hipLaunchKernelGGL(k_gather_solve, dim3(nblk(coup_q.size(), 256)), dim3(256), 0, s,
+                           (int64_t)coup_q.size(), cq_d, P->Q, cv_d, (int64_t)0, (const int64_t*)nullptr,
+                           (double*)nullptr);
+        HIPCHK(hipGetLastError());
+        std::vector<double> cv(coup_q.size());
+        HIPCHK(hipMemcpyAsync(cv.data(), cv_d, cv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        P->release(cq_d);
+        P->release(cv_d);
+        std::vector<double> A(inv_total, 0.0);
+        for (size_t k = 0; k < coup_q.size(); ++k) A[coup_pos[k]] = cv[k];
+        std::vector<double> inv(inv_total, 0.0);
+        for (size_t rr = 0; rr < small.size(); ++rr) {
+          const int64_t len = small[rr][1], off = run_inv_off[rr];
+          for (int64_t i = 0; i < len; ++i) A[off + i * len + i] += 1.0;
+          invert_dense((int)len, &A[off], &inv[off]);
+        }
+        P->dt_g0 = P->alloc<int>(dg0.size());
+        P->dt_n = P->alloc<int>(dn.size());
+        P->dt_p0 = P->alloc<int>(dp0.size());
+        P->pt_cs = P->alloc<int>(pcs.size());
+        P->pt_cn = P->alloc<int>(pcn.size());
+        P->pt_inv = P->alloc<int64_t>(pinv.size());
+        P->inv = P->alloc<double>(inv.size());
+        upload(P->dt_g0, dg0, s);
+        upload(P->dt_n, dn, s);
+        upload(P->dt_p0, dp0, s);
+        upload(P->pt_cs, pcs, s);
+        upload(P->pt_cn, pcn, s);
+        upload(P->pt_inv, pinv, s);
+        upload(P->inv, inv, s);
+      }
+    }
+    // ---- Jacobi tiles over the large runs: chunks of T points plus every point
+    // of the same run within `reach` (a coupling never leaves its run) ----
+    std::vector<int> es, el, tg0, tleft, tn;
+    auto build_tiles = [&](int T) {
+      es.clear(); el.clear(); tg0.clear(); tleft.clear(); tn.clear();
+      int emax = 0;
+      for (const Run& r : runs) {
+        if (!whole_circle && r.len <= kDirectMax) continue;
+        for (int64_t a0 = 0; a0 < r.len; a0 += T) {
+          const int64_t b0 = std::min<int64_t>(r.len, a0 + T);
+          int64_t lo = a0, hi = b0;   // run-relative, extended below
+          const double xa = xs[(r.start + a0) % M], xb = xs[(r.start + b0 - 1) % M];
+          if (whole_circle) {
+            // circular run: extend across the wrap, at most the whole circle
+            int64_t ext_l = 0, ext_r = 0;
+            while (ext_l < M && pair_distance(xs[((r.start + a0 - ext_l - 1) % M + M) % M], xa, periodic) <= reach)
+              ++ext_l;
+            while (ext_r < M && pair_distance(xs[(r.start + b0 + ext_r) % M], xb, periodic) <= reach) ++ext_r;
+            if (ext_l + ext_r + (b0 - a0) >= M) {
+              lo = a0;
+              hi = a0 + M;
+            } else {
+              lo = a0 - ext_l;
+              hi = b0 + ext_r;
+            }
+          } else {
+            while (lo > 0 && pair_distance(xs[(r.start + lo - 1) % M], xa, periodic) <= reach) --lo;
+            while (hi < r.len && pair_distance(xs[(r.start + hi) % M], xb, periodic) <= reach) ++hi;
+          }
+          es.push_back((int)(((r.start + lo) % M + M) % M));
+          el.push_back((int)(hi - lo));
+          tg0.push_back((int)((r.start + a0) % M));
+          tleft.push_back((int)(a0 - lo));
+          tn.push_back((int)(b0 - a0));
+          emax = std::max(emax, (int)(hi - lo));
+        }
       }
       return emax;
     };
-    std::vector<int> es, el;
-    int T = 64, emax = tiles(T, es, el);
+    int T = 64, emax = build_tiles(T);
     while (emax > 4 * T && T < 2048) {
       T *= 2;
-      emax = tiles(T, es, el);
+      emax = build_tiles(T);
     }
     P->T = T;
     P->ntile = (int)es.size();
     P->ext_max = emax;
-    P->solve_threads = (int)std::min<int64_t>(256, 64 * nblk(emax, 64));
-    // tile matrices: rows of the extended range, couplings to other rows of it
-    std::vector<int> tr0(P->ntile), tg0(P->ntile), tleft(P->ntile), tn(P->ntile), rg, rptr, col;
-    std::vector<int64_t> rq, eq;
-    rptr.push_back(0);
-    for (int t = 0; t < P->ntile; ++t) {
-      const int64_t a0 = (int64_t)t * T;
-      tr0[t] = (int)rg.size();
-      tg0[t] = (int)a0;
-      tn[t] = (int)(std::min<int64_t>(M, a0 + T) - a0);
-      tleft[t] = (int)((a0 - es[t] + M) % M);
-      for (int e = 0; e < el[t]; ++e) {
-        const int64_t g = (es[t] + e) % M;
-        rg.push_back((int)g);
-        int64_t self = (g - nbs[g] + M) % M;
-        rq.push_back(qo[g] + self);
-        for (int k = 0; k < nc[g]; ++k) {
-          const int64_t l = (ns[g] + k) % M;
-          if (l == g) continue;
-          const int64_t le = (l - es[t] + M) % M;
-          if (le >= el[t]) continue;   // outside the halo: only reaches rows that are not kept
-          col.push_back((int)le);
-          eq.push_back(qo[g] + (l - nbs[g] + M) % M);
+    P->solve_threads = (int)std::min<int64_t>(256, 64 * nblk(std::max(emax, 1), 64));
+    if (P->ntile > 0) {
+      std::vector<int> tr0(P->ntile), rg, rptr, col;
+      std::vector<int64_t> rq, eq;
+      rptr.push_back(0);
+      for (int t = 0; t < P->ntile; ++t) {
+        tr0[t] = (int)rg.size();
+        for (int e = 0; e < el[t]; ++e) {
+          const int64_t g = ((int64_t)es[t] + e) % M;
+          rg.push_back((int)g);
+          const int64_t self = (g - nbs[g] + M) % M;
+          rq.push_back(qo[g] + self);
+          for (int k = 0; k < nc[g]; ++k) {
+            const int64_t l = (ns[g] + k) % M;
+            if (l == g) continue;
+            const int64_t le = (l - es[t] + M) % M;
+            if (le >= el[t]) continue;   // outside the halo: only reaches rows that are not kept
+            col.push_back((int)le);
+            eq.push_back(qo[g] + (l - nbs[g] + M) % M);
+          }
+          rptr.push_back((int)col.size());
         }
-        rptr.push_back((int)col.size());
       }
+      P->tile_r0 = P->alloc<int>(P->ntile);
+      P->tile_el = P->alloc<int>(P->ntile);
+      P->tile_g0 = P->alloc<int>(P->ntile);
+      P->tile_left = P->alloc<int>(P->ntile);
+      P->tile_n = P->alloc<int>(P->ntile);
+      P->srow_g = P->alloc<int>(rg.size());
+      P->srow_ptr = P->alloc<int>(rptr.size());
+      P->scol = P->alloc<int>(col.size());
+      P->srow_dinv = P->alloc<double>(rg.size());
+      P->sval = P->alloc<double>(col.size());
+      upload(P->tile_r0, tr0, s);
+      upload(P->tile_el, el, s);
+      upload(P->tile_g0, tg0, s);
+      upload(P->tile_left, tleft, s);
+      upload(P->tile_n, tn, s);
+      upload(P->srow_g, rg, s);
+      upload(P->srow_ptr, rptr, s);
+      upload(P->scol, col, s);
+      int64_t* eq_d = P->alloc<int64_t>(eq.size());
+      int64_t* rq_d = P->alloc<int64_t>(rq.size());
+      upload(eq_d, eq, s);
+      upload(rq_d, rq, s);
+      const int64_t ne = (int64_t)col.size(), nr = (int64_t)rg.size();
+      int max_ne = 0;
+      for (int t = 0; t < P->ntile; ++t) max_ne = std::max(max_ne, rptr[tr0[t] + el[t]] - rptr[tr0[t]]);
+      P->lds_jac = (size_t)emax * 4 * sizeof(double) + (size_t)max_ne * (sizeof(double) + sizeof(int)) +
+                   (size_t)(emax + 1) * sizeof(int);
+      if (P->lds_jac > 160 * 1024) fail(WFP_EDOMAIN, "solve tile too large for one workgroup");
+      hipLaunchKernelGGL(k_gather_solve, dim3(nblk(std::max(ne, nr), 256)), dim3(256), 0, s, ne, eq_d, P->Q,
+                         P->sval, nr, rq_d, P->srow_dinv);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+      P->release(eq_d);
+      P->release(rq_d);
     }
-    P->tile_r0 = P->alloc<int>(P->ntile);
-    P->tile_el = P->alloc<int>(P->ntile);
-    P->tile_g0 = P->alloc<int>(P->ntile);
-    P->tile_left = P->alloc<int>(P->ntile);
-    P->tile_n = P->alloc<int>(P->ntile);
-    P->srow_g = P->alloc<int>(rg.size());
-    P->srow_ptr = P->alloc<int>(rptr.size());
-    P->scol = P->alloc<int>(col.size());
-    P->srow_dinv = P->alloc<double>(rg.size());
-    P->sval = P->alloc<double>(col.size());
-    upload(P->tile_r0, tr0, s);
-    upload(P->tile_el, el, s);
-    upload(P->tile_g0, tg0, s);
-    upload(P->tile_left, tleft, s);
-    upload(P->tile_n, tn, s);
-    upload(P->srow_g, rg, s);
-    upload(P->srow_ptr, rptr, s);
-    upload(P->scol, col, s);
-    int64_t* eq_d = P->alloc<int64_t>(eq.size());
-    int64_t* rq_d = P->alloc<int64_t>(rq.size());
-    upload(eq_d, eq, s);
-    upload(rq_d, rq, s);
-    const int64_t ne = (int64_t)col.size(), nr = (int64_t)rg.size();
-    // LDS of the solve: c, s0, s1, dinv per row, (value, column) per coupling, row pointers
-    int max_ne = 0;
-    for (int t = 0; t < P->ntile; ++t) max_ne = std::max(max_ne, rptr[tr0[t] + el[t]] - rptr[tr0[t]]);
-    P->lds_jac = (size_t)emax * 4 * sizeof(double) + (size_t)max_ne * (sizeof(double) + sizeof(int)) +
-                 (size_t)(emax + 1) * sizeof(int);
-    if (P->lds_jac > 160 * 1024) fail(WFP_EDOMAIN, "solve tile too large for one workgroup");
-    hipLaunchKernelGGL(k_gather_solve, dim3(nblk(std::max(ne, nr), 256)), dim3(256), 0, s, ne, eq_d, P->Q,
-                       P->sval, nr, rq_d, P->srow_dinv);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
-    P->release(eq_d);
-    P->release(rq_d);
   }
   // the dense weights of the scatterer rows are no longer needed
   HIPCHK(hipStreamSynchronize(s));
@@ -773,6 +946,9 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   HIPCHK(hipFuncSetAttribute((const void*)k_rbc_to_grid, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_rbc_to_modes, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_hist_b, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  if (6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4) > 160 * 1024)
+    fail(WFP_EDOMAIN, "four-step factor n1 too long for the history kernel's LDS");
   zero_state(P);
   HIPCHK(hipStreamSynchronize(s));
 }
@@ -784,13 +960,13 @@ void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, d
   hipStream_t s = P->stream;
   const bool periodic = P->boundary == WFP_PERIODIC;
   const Packets pk{P->npk, periodic ? 1 : 0, P->packets};
+  // a multiple of 8 blocks, so the XCD-aware block remap is a bijection
+  const int nlocblk = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
   int pp = 1;
   while (pp < P->npk) pp *= 2;
   const int rows_inc = 256 / pp;
-  // a multiple of 8 blocks, so the XCD-aware block remap is a bijection
-  const int nrowblk = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
   const unsigned nb_b = (unsigned)(P->n2 / 2 + 1);
-  const size_t lds_b = 6 * (size_t)P->n1 * sizeof(double2) + 8 * (size_t)P->n1 * sizeof(double4);
+  const size_t lds_b = 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4);
   for (int64_t i = 0; i < n; ++i) {
     const int64_t L = P->level + i;
     const double t = (double)L * P->dt;
@@ -799,8 +975,8 @@ void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, d
                        pp, P->ginc);
     {
       StageTimer st(P, WFP_STAGE_LOCAL, s);
-      hipLaunchKernelGGL(k_local_rhs, dim3(nrowblk), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L,
-                         P->nb_start, P->rowbase, P->ac, P->Qc, P->hist, P->loc);
+      hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L,
+                         P->nb_start, P->rowbase, P->acx, P->Qc, P->hist, P->loc);
     }
     {
       StageTimer st(P, WFP_STAGE_SPREAD, s);
@@ -811,17 +987,19 @@ void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, d
     {
       StageTimer st(P, WFP_STAGE_MODES, s);
       hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, rbc ? 1 : 0, P->fft_n1, P->n2, P->K, P->W, L,
-                         P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, P->ring, P->alpha, P->dalpha,
+                         P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, P->ring, P->alpha, P->dalpha,
                          P->ybuf, P->V);
     }
     if (rbc) {
       StageTimer st(P, WFP_STAGE_RBC, s);
-      hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->alpha,
-                         P->dalpha, P->tw_rbc, (double2*)P->rbc_u, (double2*)P->rbc_v);
-      hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->W,
+      hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->n1, P->n2,
+                         P->alpha, P->dalpha, P->tw_rbc, (double2*)P->rbc_u, (double2*)P->rbc_v);
+      hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->n1,
+                         P->n2, P->W,
                          P->h_rbc, P->delta_s, P->cheb_phi, P->cheb_g, P->ncheb, P->rbc_u, P->rbc_v, P->tw_rbc,
                          P->dk2, P->alpha, P->dalpha, P->ybuf);
-      hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, L, P->T1,
+      hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, L, P->npos,
+                         P->T1,
                          P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, P->ring, P->alpha, P->dalpha, P->ybuf,
                          P->V);
     }
@@ -834,10 +1012,15 @@ void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, d
     double* save = (sigma_out && i % save_every == 0) ? sigma_out + (i / save_every) * P->M : nullptr;
     {
       StageTimer st(P, WFP_STAGE_SOLVE, s);
-      hipLaunchKernelGGL(k_solve, dim3(P->ntile), dim3(P->solve_threads), P->lds_jac, s, (int)P->M, P->iters,
-                         P->ext_max, P->tile_r0, P->tile_el, P->tile_g0, P->tile_left, P->tile_n, P->srow_g,
-                         P->srow_dinv, P->srow_ptr, P->scol, P->sval, P->ginc, P->loc, P->i0s, P->iw, P->beta,
-                         P->grid2, P->nf, P->width, slot, save, P->perm);
+      if (P->n_direct_tiles > 0)
+        hipLaunchKernelGGL(k_solve_direct, dim3(P->n_direct_tiles), dim3(256), 0, s, (int)P->M, P->dt_g0, P->dt_n,
+                           P->dt_p0, P->pt_cs, P->pt_cn, P->pt_inv, P->inv, P->ginc, P->loc, P->i0s, P->iw,
+                           P->beta, P->grid2, P->nf, P->width, slot, save, P->perm);
+      if (P->ntile > 0)
+        hipLaunchKernelGGL(k_solve, dim3(P->ntile), dim3(P->solve_threads), P->lds_jac, s, (int)P->M, P->iters,
+                           P->ext_max, P->tile_r0, P->tile_el, P->tile_g0, P->tile_left, P->tile_n, P->srow_g,
+                           P->srow_dinv, P->srow_ptr, P->scol, P->sval, P->ginc, P->loc, P->i0s, P->iw, P->beta,
+                           P->grid2, P->nf, P->width, slot, save, P->perm);
     }
     if (P->R > 0 && u_recv_out) {
       StageTimer st(P, WFP_STAGE_RECV, s);
@@ -992,13 +1175,15 @@ wfp_status wfp_get_state(wfp_plan* P, int64_t* level, double* hist, double* ring
     }
     if (ring) {
       const int64_t n = (int64_t)P->W * (P->K + 1);
-      hipLaunchKernelGGL(k_ring_io, dim3(nblk(n, 256)), dim3(256), 0, s, P->K, P->W, P->level, 1, P->ring,
-                         (double2*)ring);
+      hipLaunchKernelGGL(k_ring_io, dim3(nblk(n, 256)), dim3(256), 0, s, P->K, P->W, P->level, P->n1, P->n2,
+                         P->npos, 1, P->ring, (double2*)ring);
     }
     if (alpha)
-      HIPCHK(hipMemcpyAsync(alpha, P->alpha, (P->K + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_modes_io, dim3(nblk(P->K + 1, 256)), dim3(256), 0, s, P->K, P->n1, P->n2, 1, P->alpha,
+                         (double2*)alpha);
     if (dalpha)
-      HIPCHK(hipMemcpyAsync(dalpha, P->dalpha, (P->K + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_modes_io, dim3(nblk(P->K + 1, 256)), dim3(256), 0, s, P->K, P->n1, P->n2, 1,
+                         P->dalpha, (double2*)dalpha);
     HIPCHK(hipGetLastError());
   });
 }
@@ -1016,10 +1201,12 @@ wfp_status wfp_set_state(wfp_plan* P, int64_t level, const double* hist, const d
     hipLaunchKernelGGL(k_hist_io, dim3(nblk(nh, 256)), dim3(256), 0, s, (int)P->M, P->NH, level, 0, P->hist,
                        const_cast<double*>(hist), P->perm);
     const int64_t nr = (int64_t)P->W * (P->K + 1);
-    hipLaunchKernelGGL(k_ring_io, dim3(nblk(nr, 256)), dim3(256), 0, s, P->K, P->W, level, 0, P->ring,
-                       (double2*)const_cast<double*>(ring));
-    HIPCHK(hipMemcpyAsync(P->alpha, alpha, (P->K + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(P->dalpha, dalpha, (P->K + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_ring_io, dim3(nblk(nr, 256)), dim3(256), 0, s, P->K, P->W, level, P->n1, P->n2, P->npos,
+                       0, P->ring, (double2*)const_cast<double*>(ring));
+    hipLaunchKernelGGL(k_modes_io, dim3(nblk(P->K + 1, 256)), dim3(256), 0, s, P->K, P->n1, P->n2, 0, P->alpha,
+                       (double2*)const_cast<double*>(alpha));
+    hipLaunchKernelGGL(k_modes_io, dim3(nblk(P->K + 1, 256)), dim3(256), 0, s, P->K, P->n1, P->n2, 0, P->dalpha,
+                       (double2*)const_cast<double*>(dalpha));
     HIPCHK(hipGetLastError());
     P->level = level;
   });
