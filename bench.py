@@ -2,7 +2,7 @@
 """Throughput of the WFP march on one MI355X: scatterer-steps per second.
 
 Workload: the periodic multiband problem (M = 1e4 springs, beta log-uniform in
-[0.1, 100], 8 Gaussian wave packets with angular carriers 50..500, dt = 1e-3,
+[0.1, 10], 8 Gaussian wave packets with angular carriers 50..500, dt = 1e-3,
 K = 3141, W = 35, p = 8), FP64.  A step is one time level of the march (spread,
 FFT, mode update, inverse FFT, local sum + interpolation, solve).  Plan
 creation (sorting, tables, local weights) happens before timing, as in the
@@ -18,11 +18,13 @@ Printed: one JSON line on stdout (diagnostics on stderr).
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
 """
 import argparse
+import csv
+import hashlib
 import json
-import math
 import os
 import sys
 import time
+from collections import defaultdict
 
 import numpy as np
 
@@ -32,6 +34,94 @@ sys.path.insert(0, ROOT)
 METRIC = "scatterer-steps/s (M*N_t/s) at 1e-10 rel err; batched & adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "multiband_sigma.npz")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_07823_amd", "csrc", "wfp_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_local_rhs.periodic-multiband-M1e4.traffic.txt")
+COPY_BYTES = 1 << 28          # the calibration copy moves 256 MiB
+
+
+def kernel_source_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def read_traffic():
+    """HBM bytes per launch of the local-sum kernel from the committed counter
+    summary, or None when it is missing or the kernel source has changed since
+    the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_dispatch"])
+
+
+def _counter_means(d, counter):
+    """Mean per dispatch of one counter, per kernel, from a rocprofv3 --pmc run."""
+    acc = defaultdict(list)
+    for fn in os.listdir(d):
+        if fn.endswith("counter_collection.csv"):
+            with open(os.path.join(d, fn)) as f:
+                for r in csv.DictReader(f):
+                    if r["Counter_Name"] == counter:
+                        acc[r["Kernel_Name"].split("(")[0]].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, kernel="wfp::k_local_rhs"):
+    """Text summary: FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of ``kernel``,
+    each scaled by what the counter reads for a 256 MiB device copy."""
+    cf = _counter_means(cal_fetch_dir, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][0]
+    cw = _counter_means(cal_write_dir, "WRITE_SIZE")["__amd_rocclr_copyBuffer"][0]
+    ff = COPY_BYTES / 1024.0 / cf
+    fw = COPY_BYTES / 1024.0 / cw
+    fe, n = _counter_means(fetch_dir, "FETCH_SIZE")[kernel]
+    wr, _ = _counter_means(write_dir, "WRITE_SIZE")[kernel]
+    traffic = 1024.0 * (fe * ff + wr * fw)
+    return "\n".join([
+        f"kernel: {kernel}",
+        f"kernel_source_sha256: {kernel_source_hash()}",
+        f"dispatches: {n}",
+        f"FETCH_SIZE_KiB_per_dispatch: {fe:.3f}",
+        f"WRITE_SIZE_KiB_per_dispatch: {wr:.3f}",
+        f"copy_256MiB_FETCH_SIZE_KiB: {cf:.3f}",
+        f"copy_256MiB_WRITE_SIZE_KiB: {cw:.3f}",
+        f"fetch_scale: {ff:.4f}",
+        f"write_scale: {fw:.4f}",
+        f"traffic_bytes_per_dispatch: {traffic:.0f}",
+    ])
+
+
+def stats_summary(d, top=20):
+    """Text table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    rows = []
+    for fn in os.listdir(d):
+        if fn.endswith("kernel_stats.csv"):
+            with open(os.path.join(d, fn)) as f:
+                rows += list(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"{'kernel':<32} {'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
+    for r in rows[:top]:
+        out.append(f"{r['Name'].split('(')[0][:32]:<32} {int(r['Calls']):>7} {float(r['AverageNs']) / 1e3:>10.3f} "
+                   f"{float(r['MinNs']) / 1e3:>10.3f} {float(r['MaxNs']) / 1e3:>10.3f} "
+                   f"{float(r['Percentage']):>6.2f}")
+    return "\n".join(out)
+
+
+def copy_calibration():
+    """A plain 256 MiB device-to-device copy, three times (counter calibration)."""
+    import torch
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log("copied 3 x 256 MiB")
 
 
 def log(*a):
@@ -101,6 +191,42 @@ def cpu_baseline(p, n_steps):
                       f"timed after its {pre:.0f} s set-up"}
 
 
+def adjoint_leg(levels, every):
+    """Forward + gradient pass on the adjoint workload (M = 1e5 springs, 64
+    receivers, dt = 1e-3) over `levels` levels with checkpoints every `every`
+    levels, against the plain forward march of the same plan.  The first
+    gradient call (derivative-weight set-up) is not timed."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    p = workloads.adjoint_periodic()
+    M, R = p["x"].size, p["x_recv"].size
+    t0 = time.perf_counter()
+    plan = wfp.Plan(p, p["dt"], checkpoint_every=every)
+    setup = time.perf_counter() - t0
+    u = torch.empty((levels, R), dtype=torch.float64, device="cuda")
+    plan.run(levels, None, 1, u)
+    plan.gradient(p["dt"] * u)                       # warm-up and one-time set-up
+    plan.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(levels, None, 1, u)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    e = p["dt"] * u                                  # dJ/du of J = dt/2 sum u^2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gb, gx = plan.gradient(e)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    ok = bool(torch.isfinite(gb).all() and torch.isfinite(gx).all())
+    plan.close()
+    return {"workload": "periodic adjoint", "M": M, "R": R, "levels": levels, "checkpoint_every": every,
+            "plan_setup_s": setup, "forward_s": t_fwd, "gradient_s": t_bwd,
+            "plain_scatterer_steps_per_s": M * levels / t_fwd,
+            "forward_plus_gradient_scatterer_steps_per_s": M * levels / (t_fwd + t_bwd),
+            "gradient_over_plain_time": t_bwd / t_fwd, "finite": ok}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +235,20 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--adjoint-levels", type=int, default=500,
+                    help="levels of the adjoint leg (0 skips it)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 256 MiB copy used to calibrate the HBM counters")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="print the traffic summary of rocprofv3 --pmc runs and exit")
+    ap.add_argument("--stats-summary", metavar="DIR", help="print a rocprofv3 --stats table and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(pmc_summary(*args.pmc_summary))
+        return
+    if args.stats_summary:
+        print(stats_summary(args.stats_summary))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the march has no multi-GPU "
               "path in this build", file=sys.stderr)
@@ -118,6 +257,9 @@ def main():
     from paper_2507_07823_amd import wfp, workloads
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     p = workloads.multiband_periodic()
     M = p["x"].size
     t0 = time.perf_counter()
@@ -158,9 +300,15 @@ def main():
         dom = max(stages, key=lambda s: stages[s]["avg_us"] * stages[s]["launches"])
         st = stages[dom]
         achieved = st["GBps"]
+        traffic = read_traffic() if dom == "local" else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                    "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                     "avg_launch_us": st["avg_us"], "bytes_per_launch": st["bytes"]}
+
+    adjoint = None
+    if args.adjoint_levels > 0:
+        adjoint = adjoint_leg(args.adjoint_levels, 250)
+        log(f"adjoint leg: {adjoint}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -174,7 +322,7 @@ def main():
         "config": {"workload": "periodic multiband springs", "M": M, "dt": p["dt"], "K": info["K"],
                    "W": info["W"], "p": info["p"], "n_fine": info["n_fine"], "pairs": info["n_pairs"],
                    "levels_timed": args.steps, "parallelism": "single GPU"},
-        "parity": parity, "roofline": roofline, "stages": stages, "cpu_baseline": cpu,
+        "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()

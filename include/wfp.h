@@ -58,7 +58,7 @@ typedef int32_t wfp_status;
 #define WFP_PERIODIC 0      /* periodic box [-pi, pi) (Section 2) */
 #define WFP_FREE_SPACE 1    /* free space via outgoing windowing (Section 4.4) */
 
-#define WFP_ABI_VERSION 1
+#define WFP_ABI_VERSION 2
 
 typedef struct wfp_plan wfp_plan;
 
@@ -90,7 +90,8 @@ typedef struct {
   int32_t rbc_period;      /* free space: levels between RBC projections     [ceil(W h/dt), h = pi/K] */
   int32_t nufft_width;     /* spreading-kernel width in fine-grid points     [16] */
   int32_t solve_iters;     /* Jacobi sweeps of the per-step solve            [from a contraction bound] */
-  int32_t reserved;
+  int32_t checkpoint_every;/* > 0: wfp_run stores the march state every this many levels (for
+                              wfp_adjoint); 0: no checkpoints                [0] */
 } wfp_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -101,6 +102,9 @@ typedef struct {
   int64_t device_bytes;
   int64_t n_weights_nonzero;   /* nonzero stored local weights of lag >= 1 (scatterer rows) */
   int64_t n_weights_stored;    /* stored local weights of lag >= 1 (scatterer rows) */
+  int32_t solve_mode;          /* 0: dense inverses of small nearby-runs and LDS tiles,
+                                  1: global Jacobi sweeps (dense nearby coupling) */
+  int32_t reserved;
 } wfp_info;
 
 /* Stages of one level, for wfp_get_profile. */
@@ -138,6 +142,24 @@ wfp_status wfp_plan_info(const wfp_plan* plan, wfp_info* info);
  * Asynchronous on the plan's stream.  Errors: WFP_EINVAL, WFP_EHIP. */
 wfp_status wfp_run(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t save_every,
                    double* u_recv_out);
+
+/* Gradient of a receiver loss J(u) through the march (not in the paper: the
+ * transpose of every step of Section 4.2, run backwards in time).
+ * Requires a periodic plan with R >= 1 and checkpoint_every > 0 whose levels
+ * 0 .. n_levels-1 were computed by wfp_run since plan creation or wfp_reset
+ * (no wfp_set_state in between); the plan's own state is not changed.
+ *   dJdu       device [n_levels][R]: dJ/du(x_r, t_L) for the levels 0..n_levels-1
+ *   grad_beta  device [M] (caller order): dJ/dbeta_j
+ *   grad_x     device [M] (caller order) or NULL: dJ/dx_j (the local weights are
+ *              differentiated in the distance; where a pair sits exactly at the
+ *              nearby/intermediate switch d = dt the one-sided derivative of
+ *              its class is used)
+ * Device memory: the first call allocates a second and third march state, a
+ * segment of checkpoint_every density levels and, with grad_x, derivative
+ * weights as large as the local weights.  Asynchronous on the plan's stream.
+ * Errors: WFP_EINVAL, WFP_EDOMAIN (free space), WFP_ESTATE, WFP_ENOMEM, WFP_EHIP. */
+wfp_status wfp_adjoint(wfp_plan* plan, int64_t n_levels, const double* dJdu, double* grad_beta,
+                       double* grad_x);
 
 /* Checkpoint / resume.  With L the next level to be computed:
  *   hist   device [m_max][M]:      hist[m][j] = sigma_j^{L-1-m}

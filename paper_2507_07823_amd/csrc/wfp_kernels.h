@@ -18,6 +18,18 @@ struct FftPlan {
   int radix[kMaxFftStages];
 };
 
+// Extra spreading sources (the receivers in the gradient pass): values val[i]
+// at sorted positions i = 0..n-1 with per-cell ranges and weights like the
+// scatterers'.  val == nullptr means none.
+struct ExtraSources {
+  const double* val;
+  int n;
+  const int* cstart;
+  const int* ccount;
+  const int64_t* woff;
+  const double* w;
+};
+
 struct Packets {
   int n;
   int periodic;
@@ -37,15 +49,17 @@ __global__ void k_local_weights(int nrows, const double* __restrict__ xt,
                                 const int64_t* __restrict__ qoff, const double* __restrict__ rowscale,
                                 int periodic, double dt, double delta, int W, int NQ, int ngl,
                                 const double* __restrict__ glz, const double* __restrict__ glw,
-                                const double* __restrict__ cheb_phi, int ncheb,
+                                const double* __restrict__ cheb_phi, const double* __restrict__ cheb_g,
+                                int ncheb, int deriv,
                                 const double* __restrict__ lagw, const int64_t* __restrict__ pbase,
                                 signed char* __restrict__ mlo, double* __restrict__ Q);
 
 __global__ void k_row_ranges(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ pbase,
                              const signed char* __restrict__ mlo, unsigned* __restrict__ ac);
-__global__ void k_pack_weights(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
-                               const double* __restrict__ Q, const unsigned* __restrict__ ac,
-                               const int64_t* __restrict__ rowbase, double* __restrict__ Qc);
+__global__ void k_pack_weights(int M, int NQ, int m0, const int* __restrict__ nb_count,
+                               const int64_t* __restrict__ qoff, const double* __restrict__ Q,
+                               const unsigned* __restrict__ ac, const int64_t* __restrict__ rowbase,
+                               double* __restrict__ Qc);
 __global__ void k_gather_solve(int64_t ne, const int64_t* __restrict__ eq, const double* __restrict__ Q,
                                double* __restrict__ ev, int64_t nr, const int64_t* __restrict__ rq,
                                double* __restrict__ rdinv);
@@ -60,12 +74,12 @@ __global__ void k_count_nonzero(int M, int NQ, const int* __restrict__ nb_count,
                                 unsigned long long* __restrict__ out);
 
 // ---- per-level kernels ----
-__global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
+__global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb_start,
                             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                             const double* __restrict__ Qc, const double* __restrict__ hist,
                             double* __restrict__ loc);
 __global__ void k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta,
-                           Packets pk, int pp, double* __restrict__ ginc);
+                           Packets pk, int pp, int deriv, double* __restrict__ ginc);
 __global__ void k_spread_weights(int nf, double hf, double inv_alpha, double beta_es, const double* __restrict__ xs,
                                  int M, const int* __restrict__ cstart, const int* __restrict__ ccount,
                                  const int64_t* __restrict__ woff, double* __restrict__ w);
@@ -83,6 +97,15 @@ __global__ void k_solve(int M, int iters, int ext_max, const int* __restrict__ t
                         const double* __restrict__ grid2, int nf, int width, double* __restrict__ sig_out,
                         double* __restrict__ save_row, const int* __restrict__ perm);
 
+__global__ void k_solve_rhs(int M, const double* __restrict__ ginc, const double* __restrict__ loc,
+                            const double* __restrict__ beta, const int* __restrict__ i0s,
+                            const double* __restrict__ iw, const double* __restrict__ grid2, int nf, int width,
+                            const double* __restrict__ dinv, double* __restrict__ rhs, double* __restrict__ x);
+__global__ void k_jacobi_sweep(int M, const int* __restrict__ ptr, const int* __restrict__ col,
+                               const double* __restrict__ val, const double* __restrict__ dinv,
+                               const double* __restrict__ rhs, const double* __restrict__ xin,
+                               double* __restrict__ xout, double* __restrict__ save_row,
+                               const int* __restrict__ perm);
 __global__ void k_solve_direct(int M, const int* __restrict__ dt_g0, const int* __restrict__ dt_n,
                                const int* __restrict__ dt_p0, const int* __restrict__ pt_cs,
                                const int* __restrict__ pt_cn, const int64_t* __restrict__ pt_inv,
@@ -102,7 +125,7 @@ __global__ void k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* 
 __global__ void k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M,
                          const int* __restrict__ cstart, const int* __restrict__ ccount,
                          const int64_t* __restrict__ woff, const double* __restrict__ sw,
-                         const double2* __restrict__ tw, double2* __restrict__ T1);
+                         const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex);
 __global__ void k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos,
                          const double2* __restrict__ T1, const double2* __restrict__ tw,
                          const double* __restrict__ dk1, const double* __restrict__ dk2,
@@ -123,6 +146,27 @@ __global__ void k_rbc_to_modes(FftPlan fp, int64_t K, int n1, int n2, int W, dou
                                const double2* __restrict__ tw, const double* __restrict__ dk2,
                                double2* __restrict__ alpha, double2* __restrict__ dalpha,
                                double2* __restrict__ y);
+
+// ---- gradient pass ----
+__global__ void k_deriv_y(int64_t K, int n1, int n2, const double2* __restrict__ alpha,
+                          const double* __restrict__ dk2, double2* __restrict__ y);
+__global__ void k_adj_drive(int M, int R, int NQ, int64_t L, int64_t N, const int* __restrict__ ptr,
+                            const int* __restrict__ rr, const int* __restrict__ ri,
+                            const int64_t* __restrict__ rqoff, const int* __restrict__ rcount,
+                            const double* __restrict__ Qr, const double* __restrict__ dQr,
+                            const double* __restrict__ e, const double* __restrict__ beta,
+                            double* __restrict__ ginc, double* __restrict__ xw);
+__global__ void k_fwd_dterm(int M, const double* __restrict__ fprime, const double* __restrict__ xloc,
+                            const int* __restrict__ i0s, const double* __restrict__ iw,
+                            const double* __restrict__ gridd, int nf, int width, double* __restrict__ D);
+__global__ void k_adj_grad(int M, const double* __restrict__ q, const double* __restrict__ sig,
+                           const double* __restrict__ beta, const double* __restrict__ D,
+                           const double* __restrict__ xloc, const double* __restrict__ xw,
+                           const int* __restrict__ i0s, const double* __restrict__ iw,
+                           const double* __restrict__ gridd, int nf, int width, double* __restrict__ gb,
+                           double* __restrict__ gx);
+__global__ void k_gather(int n, const int* __restrict__ idx, const double* __restrict__ in, double* __restrict__ out);
+__global__ void k_unsort(int M, const int* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out);
 
 // ---- state movement ----
 __global__ void k_hist_io(int M, int NH, int64_t L, int to_user, double* __restrict__ hist,

@@ -244,6 +244,11 @@ __global__ void k_pq_tables(int64_t K, int W, int ng, double dt, const double* _
 // the P lags from max(m_min, floor(s) - P/2 + 1); Lagrange weights by
 // prefix/suffix products  v_r = lagw_r prod_{q != r} (u - q),  u = s - m0.
 // Per-thread accumulators live in LDS: acc[m * blockDim + tid].
+// With deriv != 0 the kernel writes dQ_m/dd times sign(wrap(x_target - x_source))
+// instead (for gradients with respect to positions): with ds/dd = (1 + z_i)/(2 dt),
+//   d/dd [node weight] = -(1/2) w_i (1 - phi(s dt)) - ((delta - d)/2) w_i phi'(s dt) dt ds/dd,
+// and the Lagrange weights differentiated by the product rule (the stencil is
+// piecewise constant in d).
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ void __launch_bounds__(128)
@@ -251,7 +256,8 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
                 const int* __restrict__ nb_start, const int* __restrict__ nb_count,
                 const int64_t* __restrict__ qoff, const double* __restrict__ rowscale, int periodic,
                 double dt, double delta, int W, int NQ, int ngl, const double* __restrict__ glz,
-                const double* __restrict__ glw, const double* __restrict__ cheb_phi, int ncheb,
+                const double* __restrict__ glw, const double* __restrict__ cheb_phi,
+                const double* __restrict__ cheb_g, int ncheb, int deriv,
                 const double* __restrict__ lagw, const int64_t* __restrict__ pbase,
                 signed char* __restrict__ mlo, double* __restrict__ Q) {
   extern __shared__ double acc[];
@@ -267,11 +273,17 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
     const int i = i0 + tid;
     for (int m = 0; m < NQ; ++m) acc[m * nt + tid] = 0.0;
     int lowest = NQ;
+    double sgn = 1.0;
     if (i < n) {
       int l = st + i;
       if (l >= M) l -= M;
       double d = fabs(xa - xs[l]);
       if (periodic && d > kPi) d = kTwoPi - d;
+      if (deriv) {
+        double y = xa - xs[l];
+        if (periodic) y -= kTwoPi * rint(y * kInvTwoPi);
+        sgn = (y > 0.0) ? 1.0 : ((y < 0.0) ? -1.0 : 0.0);
+      }
       if (d < delta) {
         const double D = d / dt;
         const int mmin = (d < dt) ? 0 : 1;
@@ -284,22 +296,42 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
           if (m0 < mmin) m0 = mmin;
           if (m0 < lowest) lowest = m0;
           const double u = s - m0;
-          double pre[P];
+          double pre[P], dpre[P];
           pre[0] = 1.0;
+          dpre[0] = 0.0;
 #pragma unroll
-          for (int r = 1; r < P; ++r) pre[r] = pre[r - 1] * (u - (r - 1));
-          double suf = 1.0;
+          for (int r = 1; r < P; ++r) {
+            dpre[r] = dpre[r - 1] * (u - (r - 1)) + pre[r - 1];
+            pre[r] = pre[r - 1] * (u - (r - 1));
+          }
+          if (!deriv) {
+            double suf = 1.0;
 #pragma unroll
-          for (int r = P - 1; r >= 0; --r) {
-            const double v = lagw[r] * pre[r] * suf;
-            suf *= (u - r);
-            acc[(m0 + r) * nt + tid] += om * v;
+            for (int r = P - 1; r >= 0; --r) {
+              const double v = lagw[r] * pre[r] * suf;
+              suf *= (u - r);
+              acc[(m0 + r) * nt + tid] += om * v;
+            }
+          } else {
+            const double ds = (1.0 + glz[q]) / (2.0 * dt);
+            const double dphi = (2.0 / delta) * cheb(cheb_g, ncheb, 2.0 * s / W - 1.0);
+            const double dom = -0.5 * glw[q] * (1.0 - phi) - half * glw[q] * dphi * dt * ds;
+            double suf = 1.0, dsuf = 0.0;
+#pragma unroll
+            for (int r = P - 1; r >= 0; --r) {
+              const double v = lagw[r] * pre[r] * suf;
+              const double dv = lagw[r] * (dpre[r] * suf + pre[r] * dsuf);
+              dsuf = dsuf * (u - r) + suf;
+              suf *= (u - r);
+              acc[(m0 + r) * nt + tid] += dom * v + om * dv * ds;
+            }
           }
         }
       }
     }
     if (i < n) {
-      for (int m = 0; m < NQ; ++m) Q[base + (int64_t)m * n + i] = scale * acc[m * nt + tid];
+      const double sc = deriv ? scale * sgn : scale;
+      for (int m = 0; m < NQ; ++m) Q[base + (int64_t)m * n + i] = sc * acc[m * nt + tid];
       if (mlo) mlo[pbase[row] + i] = (signed char)lowest;
     }
   }
@@ -307,27 +339,27 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
 
 template __global__ void k_local_weights<2>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
-                                            int, const double*, const double*, const double*, int,
+                                            int, const double*, const double*, const double*, const double*, int, int,
                                             const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<4>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
-                                            int, const double*, const double*, const double*, int,
+                                            int, const double*, const double*, const double*, const double*, int, int,
                                             const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<6>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
-                                            int, const double*, const double*, const double*, int,
+                                            int, const double*, const double*, const double*, const double*, int, int,
                                             const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<8>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
-                                            int, const double*, const double*, const double*, int,
+                                            int, const double*, const double*, const double*, const double*, int, int,
                                             const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<10>(int, const double*, const double*, int, const int*, const int*,
                                              const int64_t*, const double*, int, double, double, int, int,
-                                             int, const double*, const double*, const double*, int,
+                                             int, const double*, const double*, const double*, const double*, int, int,
                                              const double*, const int64_t*, signed char*, double*);
 template __global__ void k_local_weights<12>(int, const double*, const double*, int, const int*, const int*,
                                              const int64_t*, const double*, int, double, double, int, int,
-                                             int, const double*, const double*, const double*, int,
+                                             int, const double*, const double*, const double*, const double*, int, int,
                                              const double*, const int64_t*, signed char*, double*);
 
 // Jacobi contraction bound of the per-step system (I + S): for each row,
@@ -383,17 +415,18 @@ __global__ void k_row_ranges(int M, int NQ, const int* __restrict__ nb_count, co
   }
 }
 
-// Copy the weights of lags m >= 1 inside each row's ranges to the packed layout
-// Qc[rowbase[j] + sum_{m' < m} c_{jm'} + (i - a_jm)].
-__global__ void k_pack_weights(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
-                               const double* __restrict__ Q, const unsigned* __restrict__ ac,
-                               const int64_t* __restrict__ rowbase, double* __restrict__ Qc) {
+// Copy the weights of lags m >= m0 inside each row's ranges to the packed layout
+// Qc[rowbase[j] + sum_{m0 <= m' < m} c_{jm'} + (i - a_jm)].
+__global__ void k_pack_weights(int M, int NQ, int m0, const int* __restrict__ nb_count,
+                               const int64_t* __restrict__ qoff, const double* __restrict__ Q,
+                               const unsigned* __restrict__ ac, const int64_t* __restrict__ rowbase,
+                               double* __restrict__ Qc) {
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= M) return;
   const int n = nb_count[j];
   int64_t off = rowbase[j];
-  for (int m = 1; m < NQ; ++m) {
+  for (int m = m0; m < NQ; ++m) {
     const unsigned v = ac[(int64_t)j * NQ + m];
     const int a = v & 0xffff, c = v >> 16;
     for (int i = lane; i < c; i += 64) Qc[off + i] = Q[qoff[j] + (int64_t)m * n + a + i];
@@ -482,7 +515,8 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Local sum of lags m >= 1, one row per wavefront.  The row's packed weights
+// Local sum of lags m >= m0 (m0 = 1 for the right-hand side, 0 for the
+// derivative sums of the gradient), one row per wavefront.  The row's packed weights
 // are one block per lag m (sources a_m .. a_m + c_m - 1 of its neighbour list,
 // at offset off_m within the row).  Lane m loads lag m's (a, c, off); the
 // wavefront then works as four groups of 16 lanes, group g on lag mb + g of
@@ -492,7 +526,7 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
 constexpr int kMaxNQ = 64;
 
 __global__ void __launch_bounds__(256)
-k_local_rhs(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
+k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb_start,
             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
             const double* __restrict__ hist, double* __restrict__ loc) {
   const int lane = threadIdx.x & 63;
@@ -501,11 +535,11 @@ k_local_rhs(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
   if (j >= M) return;   // no block-level barrier in this kernel
   const int st = nb_start[j];
   uint2 mine = make_uint2(0u, 0u);
-  if (lane >= 1 && lane < NQ) mine = acx[(int64_t)j * NQ + lane];
+  if (lane >= m0 && lane < NQ) mine = acx[(int64_t)j * NQ + lane];
   const double* __restrict__ q = Qc + rowbase[j];
   const int grp = lane >> 4, gl = lane & 15;
   double acc0 = 0.0, acc1 = 0.0;
-  for (int mb = 1; mb < NQ; mb += 4) {
+  for (int mb = m0; mb < NQ; mb += 4) {
     const int m = mb + grp;
     const int src = m < 64 ? m : 0;
     const unsigned vx = __shfl(mine.x, src, 64), vy = __shfl(mine.y, src, 64);
@@ -542,10 +576,11 @@ k_local_rhs(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
 // Driving data g_j(t) = beta_j f(x_j - t) (eq. (gj); f periodised in the
 // periodic box), stored negated: ginc_j = -g_j.  Thread (row, packet) sums the
 // packet's images; the packets are then added in order.  `pp` = packets per
-// row rounded up to a power of two; 256/pp rows per block.
+// row rounded up to a power of two; 256/pp rows per block.  With deriv != 0 it
+// writes f'(x_j - t) instead (gradient with respect to positions).
 __global__ void __launch_bounds__(256)
 k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta, Packets pk, int pp,
-           double* __restrict__ ginc) {
+           int deriv, double* __restrict__ ginc) {
   __shared__ double term[256];
   const int rpb = 256 / pp;
   const int lr = threadIdx.x / pp, ip = threadIdx.x - lr * pp;
@@ -557,14 +592,14 @@ k_incident(int M, double t, const double* __restrict__ xs, const double* __restr
     const double a = pk.p[5 * ip], c = pk.p[5 * ip + 1], wd = pk.p[5 * ip + 2];
     const double om = pk.p[5 * ip + 3], ph = pk.p[5 * ip + 4];
     const double lim = 40.0 * wd;   // exp(-y^2/(2 w^2)) underflows to 0 beyond
-    if (pk.periodic) {
-      for (int im = -4; im <= 4; ++im) {
-        const double y = (s + kTwoPi * im) - c;
-        if (fabs(y) < lim) f += a * exp(-y * y / (2.0 * wd * wd)) * cos(om * y + ph);
+    const int i0 = pk.periodic ? -4 : 0, i1 = pk.periodic ? 4 : 0;
+    for (int im = i0; im <= i1; ++im) {
+      const double y = (s + kTwoPi * im) - c;
+      if (fabs(y) < lim) {
+        const double env = a * exp(-y * y / (2.0 * wd * wd));
+        if (deriv) f += env * (-(y / (wd * wd)) * cos(om * y + ph) - om * sin(om * y + ph));
+        else f += env * cos(om * y + ph);
       }
-    } else {
-      const double y = s - c;
-      if (fabs(y) < lim) f += a * exp(-y * y / (2.0 * wd * wd)) * cos(om * y + ph);
     }
   }
   term[threadIdx.x] = f;
@@ -572,7 +607,7 @@ k_incident(int M, double t, const double* __restrict__ xs, const double* __restr
   if (ip == 0 && j < M) {
     double tot = 0.0;
     for (int q = 0; q < pk.n; ++q) tot += term[lr * pp + q];
-    ginc[j] = -beta[j] * tot;
+    ginc[j] = deriv ? tot : -beta[j] * tot;
   }
 }
 
@@ -643,6 +678,37 @@ k_solve(int M, int iters, int ext_max, const int* __restrict__ tile_r0, const in
     sig_out[g] = v;
     if (save_row) save_row[perm[g]] = v;
   }
+}
+
+// Per-step solve when the tiles do not fit in LDS (dense nearby coupling along
+// long runs): global Jacobi sweeps, one launch each, CSR over all rows.
+// k_solve_rhs completes the right-hand side b_j = part_j - beta_j u_H(x_j) and
+// the first sweep from zero, x_j = b_j / (1 + S_jj); k_jacobi_sweep does
+// x'_j = (b_j - sum_{l != j} S_jl x_l) / (1 + S_jj) and, on the last sweep,
+// also writes the caller's row.
+__global__ void k_solve_rhs(int M, const double* __restrict__ ginc, const double* __restrict__ loc,
+                            const double* __restrict__ beta, const int* __restrict__ i0s,
+                            const double* __restrict__ iw, const double* __restrict__ grid2, int nf, int width,
+                            const double* __restrict__ dinv, double* __restrict__ rhs, double* __restrict__ x) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const double b = (ginc[j] - loc[j]) - beta[j] * interp_pre(j, i0s, iw, grid2, nf, width);
+  rhs[j] = b;
+  x[j] = b * dinv[j];
+}
+
+__global__ void k_jacobi_sweep(int M, const int* __restrict__ ptr, const int* __restrict__ col,
+                               const double* __restrict__ val, const double* __restrict__ dinv,
+                               const double* __restrict__ rhs, const double* __restrict__ xin,
+                               double* __restrict__ xout, double* __restrict__ save_row,
+                               const int* __restrict__ perm) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  double acc = rhs[j];
+  for (int k = ptr[j]; k < ptr[j + 1]; ++k) acc = fma(-val[k], xin[col[k]], acc);
+  const double v = acc * dinv[j];
+  xout[j] = v;
+  if (save_row) save_row[perm[j]] = v;
 }
 
 // Per-step solve on small nearby-runs: I + S is block diagonal over maximal
@@ -822,14 +888,16 @@ __device__ __forceinline__ double spread_cell(int cell, const double* __restrict
 __global__ void __launch_bounds__(256)
 k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
          const int* __restrict__ ccount, const int64_t* __restrict__ woff, const double* __restrict__ sw,
-         const double2* __restrict__ tw, double2* __restrict__ T1) {
+         const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex) {
   extern __shared__ double2 buf[];
   const int n2 = f2.n, j1 = blockIdx.x;
   const int n = n1 * n2;
   double* bd = (double*)buf;
   for (int c = threadIdx.x; c < 2 * n2; c += blockDim.x) {
     const int cell = 2 * (j1 + n1 * (c >> 1)) + (c & 1);
-    bd[c] = spread_cell(cell, sig, M, cstart, ccount, woff, sw);
+    double v = spread_cell(cell, sig, M, cstart, ccount, woff, sw);
+    if (ex.val) v += spread_cell(cell, ex.val, ex.n, ex.cstart, ex.ccount, ex.woff, ex.w);
+    bd[c] = v;
   }
   __syncthreads();
   fft_batch(buf, 1, f2, tw, 2 * n1);
@@ -978,6 +1046,91 @@ k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __res
   __syncthreads();
   fft_batch(buf, 1, f2, tw, 2 * n1);
   for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) grid2[j1 + n1 * j2] = cconj(buf[j2]);
+}
+
+// ---------------------------------------------------------------------------
+// Gradient pass.  The transpose of one level is the same level run backwards
+// in time with the adjoint densities q (solved with the same I + S) and the
+// receivers acting as sources of strength dJ/du_r; see the plan for the
+// bookkeeping.  These kernels are the pieces the forward level lacks.
+// ---------------------------------------------------------------------------
+
+// Type-2 input of d/dx u_H: the modes -i k alpha_k, deconvolved like y.
+__global__ void k_deriv_y(int64_t K, int n1, int n2, const double2* __restrict__ alpha,
+                          const double* __restrict__ dk2, double2* __restrict__ y) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q > K) return;
+  const int64_t pos = mode_pos(q, n1, n2);
+  // conj(-i q alpha) = i q conj(alpha)
+  y[q] = cscale(cmul_pi(cconj(alpha[pos])), (double)q * dk2[pos]);
+}
+
+// Adjoint driving data of scatterer j at forward level L from the receivers
+// within delta:  ginc_j = -beta_j sum_r sum_{m>=0, L+m<N} (1/2) Q_m(d_rj) e_r^{L+m}
+// and (when xw is given) the position-derivative sum with the signed weights
+// dQr.  e is the caller's [N][R] array dJ/du (receiver index order).
+__global__ void k_adj_drive(int M, int R, int NQ, int64_t L, int64_t N, const int* __restrict__ ptr,
+                            const int* __restrict__ rr, const int* __restrict__ ri,
+                            const int64_t* __restrict__ rqoff, const int* __restrict__ rcount,
+                            const double* __restrict__ Qr, const double* __restrict__ dQr,
+                            const double* __restrict__ e, const double* __restrict__ beta,
+                            double* __restrict__ ginc, double* __restrict__ xw) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  double acc = 0.0, accd = 0.0;
+  for (int t = ptr[j]; t < ptr[j + 1]; ++t) {
+    const int r = rr[t];
+    const int n = rcount[r];
+    const int64_t base = rqoff[r] + ri[t];
+    for (int m = 0; m < NQ && L + m < N; ++m) {
+      const double ev = e[(L + m) * R + r];
+      acc = fma(Qr[base + (int64_t)m * n], ev, acc);
+      if (xw) accd = fma(dQr[base + (int64_t)m * n], ev, accd);
+    }
+  }
+  ginc[j] = -beta[j] * acc;
+  if (xw) xw[j] = accd;
+}
+
+// Forward derivative data of one level: D_j = f'(x_j - t) + (signed
+// derivative local sum of lags m >= 0) + d/dx u_H(x_j).
+__global__ void k_fwd_dterm(int M, const double* __restrict__ fprime, const double* __restrict__ xloc,
+                            const int* __restrict__ i0s, const double* __restrict__ iw,
+                            const double* __restrict__ gridd, int nf, int width, double* __restrict__ D) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  D[j] = fprime[j] + xloc[j] + interp_pre(j, i0s, iw, gridd, nf, width);
+}
+
+// Accumulate one level of the gradient (sorted order):
+//   gbeta_j += -q_j sigma_j / beta_j^2
+//   gx_j    += q_j D_j + sigma_j (xloc_j + xw_j + d/dx u_H^adj(x_j))
+__global__ void k_adj_grad(int M, const double* __restrict__ q, const double* __restrict__ sig,
+                           const double* __restrict__ beta, const double* __restrict__ D,
+                           const double* __restrict__ xloc, const double* __restrict__ xw,
+                           const int* __restrict__ i0s, const double* __restrict__ iw,
+                           const double* __restrict__ gridd, int nf, int width, double* __restrict__ gb,
+                           double* __restrict__ gx) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const double b = beta[j], qj = q[j], sj = sig[j];
+  gb[j] -= qj * sj / (b * b);
+  if (gx) {
+    const double w = xloc[j] + xw[j] + interp_pre(j, i0s, iw, gridd, nf, width);
+    gx[j] += qj * D[j] + sj * w;
+  }
+}
+
+// out[i] = in[idx[i]]
+__global__ void k_gather(int n, const int* __restrict__ idx, const double* __restrict__ in, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[idx[i]];
+}
+
+// out[perm[j]] = in[j]  (sorted -> caller order)
+__global__ void k_unsort(int M, const int* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < M) out[perm[j]] = in[j];
 }
 
 // ---------------------------------------------------------------------------

@@ -144,6 +144,10 @@ struct wfp_plan {
   int *srow_g = nullptr, *srow_ptr = nullptr, *scol = nullptr;
   double *srow_dinv = nullptr, *sval = nullptr;
   int solve_threads = 64;
+  // global-sweep solve (when tiles do not fit in LDS)
+  bool solve_global = false;
+  int *g_ptr = nullptr, *g_col = nullptr;
+  double *g_val = nullptr, *g_dinv = nullptr, *g_rhs = nullptr, *g_xa = nullptr, *g_xb = nullptr;
   // direct solve of small runs
   int n_direct_tiles = 0;
   int *dt_g0 = nullptr, *dt_n = nullptr, *dt_p0 = nullptr, *pt_cs = nullptr, *pt_cn = nullptr;
@@ -159,6 +163,33 @@ struct wfp_plan {
   double* Qr = nullptr;
   double *cheb_phi = nullptr, *cheb_g = nullptr;
   int64_t n_weights_nonzero = 0, n_weights_stored = 0;
+  // host copies kept for the gradient pass set-up
+  std::vector<double> xs_h, xr_h;
+  std::vector<int> nbc_h, rnbs_h, rnbc_h;
+  std::vector<int64_t> rqoff_h;
+  int64_t dense_total = 0;
+  double *glz_d = nullptr, *glw_d = nullptr, *lagw_d = nullptr;
+  // checkpoints of the current run (state at levels c * ckpt_every, c >= 1)
+  int ckpt_every = 0;
+  bool ck_from0 = true;          // the levels run so far started from level 0
+  std::vector<char*> ckpts;
+  size_t ckpt_bytes = 0;
+  // gradient pass: replay and adjoint states, per-segment buffers
+  bool grad_ready = false, gradx_ready = false;
+  double *rhist = nullptr, *ahist = nullptr;
+  double2 *rring = nullptr, *ralpha = nullptr, *rdalpha = nullptr;
+  double2 *aring = nullptr, *aalpha = nullptr, *adalpha = nullptr;
+  double *segsig = nullptr, *segD = nullptr, *gb_acc = nullptr, *gx_acc = nullptr;
+  double *xloc = nullptr, *xw = nullptr, *fprime = nullptr, *gridd = nullptr, *esort = nullptr;
+  double2* yd = nullptr;
+  int *adj_ptr = nullptr, *adj_rr = nullptr, *adj_ri = nullptr;
+  int *rsort = nullptr, *rcs = nullptr, *rcc = nullptr;
+  int64_t* rwo = nullptr;
+  double* rsw = nullptr;
+  double* DQa = nullptr;         // signed derivative weights, lags >= 0, packed by row
+  int64_t* drowbase = nullptr;
+  uint2* acxd = nullptr;
+  double* dQr = nullptr;         // receivers' signed derivative weights, layout of Qr
   std::vector<void*> owned;
   // per-stage event timing
   bool profiling = false;
@@ -207,6 +238,7 @@ void zero_state(wfp_plan* P) {
   fill((double*)P->ybuf, 2 * (P->K + 1));
   HIPCHK(hipGetLastError());
   P->level = 0;
+  P->ck_from0 = true;
 }
 
 // Host-only checks of the problem and parameters (no HIP call), so invalid
@@ -223,7 +255,7 @@ void validate(const wfp_problem* prob, const wfp_params* par) {
   if (par->eps_window < 0 || !(par->eps_window < 1) || par->gamma < 0 || !(par->gamma < 1))
     fail(WFP_EINVAL, "eps_window and gamma must lie in [0, 1)");
   if (par->W < 0 || par->K < 0 || par->n_gl_local < 0 || par->n_gl_pq < 0 || par->rbc_period < 0 ||
-      par->solve_iters < 0)
+      par->solve_iters < 0 || par->checkpoint_every < 0)
     fail(WFP_EINVAL, "negative size parameter");
   const int p = par->p > 0 ? par->p : 8;
   if (par->p < 0 || p % 2 || p < 2 || p > kMaxP) fail(WFP_EINVAL, "p must be even, 2..12");
@@ -310,6 +342,31 @@ struct StageTimer {
   }
 };
 
+constexpr int kQwThreads = 128;
+
+// Local weights (deriv = 0) or their signed distance derivatives (deriv = 1)
+// of `nrows` target rows against the sorted scatterers.
+void launch_local_weights(wfp_plan* P, int nrows, const double* xt, const int* st, const int* cnt,
+                          const int64_t* off, const double* scale, int deriv, const int64_t* pbs,
+                          signed char* ml, double* Qd) {
+  if (nrows == 0) return;
+  const int periodic = P->boundary == WFP_PERIODIC ? 1 : 0;
+#define WFP_QW(PP)                                                                                      \
+  hipLaunchKernelGGL(k_local_weights<PP>, dim3(nrows), dim3(kQwThreads), P->lds_qw, P->stream, nrows, xt,  \
+                     P->xs, (int)P->M, st, cnt, off, scale, periodic, P->dt, P->delta, P->W, P->NQ, P->ngl,  \
+                     P->glz_d, P->glw_d, P->cheb_phi, P->cheb_g, P->ncheb, deriv, P->lagw_d, pbs, ml, Qd)
+  switch (P->p) {
+    case 2: WFP_QW(2); break;
+    case 4: WFP_QW(4); break;
+    case 6: WFP_QW(6); break;
+    case 8: WFP_QW(8); break;
+    case 10: WFP_QW(10); break;
+    default: WFP_QW(12); break;
+  }
+#undef WFP_QW
+  HIPCHK(hipGetLastError());
+}
+
 void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   validate(prob, par);
   const int64_t M = prob->M;
@@ -323,6 +380,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   const bool periodic = prob->boundary == WFP_PERIODIC;
   P->M = M;
   P->R = prob->R;
+  P->ckpt_every = par->checkpoint_every;
   P->boundary = prob->boundary;
   P->dt = par->dt;
   const double eps = par->eps_window > 0 ? par->eps_window : 1e-12;
@@ -416,6 +474,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     bs[i] = bh[perm[i]];
   }
   P->perm_h = perm;
+  P->xs_h = xs;
 
   // ---- window series, Gauss-Legendre rules ----
   WindowSeries ws = window_series(P->b, 128);
@@ -573,29 +632,19 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   upload(lagw_d, lagw, s);
   upload(glz_d, glz, s);
   upload(glw_d, glw, s);
+  P->lagw_d = lagw_d;
+  P->glz_d = glz_d;
+  P->glw_d = glw_d;
+  P->nbc_h = nbc;
+  P->dense_total = tot;
   std::vector<double> half_beta(M);
   for (int64_t j = 0; j < M; ++j) half_beta[j] = 0.5 * bs[j];
   double* hb_d = P->alloc<double>(M);
   upload(hb_d, half_beta, s);
-  const int qthreads = 128;
-  P->lds_qw = (size_t)P->NQ * qthreads * sizeof(double);
+  P->lds_qw = (size_t)P->NQ * kQwThreads * sizeof(double);
   auto launch_qw = [&](int nrows, const double* xt, const int* st, const int* cnt, const int64_t* off,
                        const double* scale, const int64_t* pbs, signed char* ml, double* Qd) {
-    if (nrows == 0) return;
-#define WFP_QW(PP)                                                                                    \
-  hipLaunchKernelGGL(k_local_weights<PP>, dim3(nrows), dim3(qthreads), P->lds_qw, s, nrows, xt, P->xs,   \
-                     (int)M, st, cnt, off, scale, periodic ? 1 : 0, P->dt, P->delta, P->W, P->NQ, P->ngl, \
-                     glz_d, glw_d, P->cheb_phi, P->ncheb, lagw_d, pbs, ml, Qd)
-    switch (P->p) {
-      case 2: WFP_QW(2); break;
-      case 4: WFP_QW(4); break;
-      case 6: WFP_QW(6); break;
-      case 8: WFP_QW(8); break;
-      case 10: WFP_QW(10); break;
-      default: WFP_QW(12); break;
-    }
-#undef WFP_QW
-    HIPCHK(hipGetLastError());
+    launch_local_weights(P, nrows, xt, st, cnt, off, scale, 0, pbs, ml, Qd);
   };
   launch_qw((int)M, P->xs, P->nb_start, P->nb_count, P->qoff, hb_d, pbase, mlo, P->Q);
   {
@@ -642,7 +691,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->rowbase = P->alloc<int64_t>(M);
     P->Qc = P->alloc<double>(packed);
     upload(P->rowbase, rb, s);
-    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ,
+    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, 1,
                        P->nb_count, P->qoff, P->Q, P->ac, P->rowbase, P->Qc);
     HIPCHK(hipGetLastError());
   }
@@ -656,6 +705,10 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
       rt += (int64_t)rc[r] * P->NQ;
       P->n_pairs_recv += rc[r];
     }
+    P->xr_h = xrh;
+    P->rnbs_h = rs;
+    P->rnbc_h = rc;
+    P->rqoff_h = ro;
     P->xr = P->alloc<double>(P->R);
     P->rnb_start = P->alloc<int>(P->R);
     P->rnb_count = P->alloc<int>(P->R);
@@ -865,6 +918,53 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->ntile = (int)es.size();
     P->ext_max = emax;
     P->solve_threads = (int)std::min<int64_t>(256, 64 * nblk(std::max(emax, 1), 64));
+    {
+      // LDS the tiles would need: four vectors plus the tile's CSR
+      size_t need = 0;
+      for (int t = 0; t < P->ntile; ++t) {
+        int64_t ne = 0;
+        for (int e = 0; e < el[t]; ++e) ne += nc[((int64_t)es[t] + e) % M];
+        need = std::max(need, (size_t)emax * 4 * sizeof(double) + (size_t)ne * (sizeof(double) + sizeof(int)) +
+                                  (size_t)(emax + 1) * sizeof(int));
+      }
+      P->solve_global = need > 160 * 1024;
+    }
+    if (P->solve_global) {
+      // every row by global sweeps; the direct and tiled paths are not used
+      P->n_direct_tiles = 0;
+      P->ntile = 0;
+      std::vector<int> gp(M + 1, 0), gc;
+      std::vector<int64_t> geq, grq(M);
+      for (int64_t g = 0; g < M; ++g) {
+        grq[g] = qo[g] + (g - nbs[g] + M) % M;
+        for (int k = 0; k < nc[g]; ++k) {
+          const int64_t l = (ns[g] + k) % M;
+          if (l == g) continue;
+          gc.push_back((int)l);
+          geq.push_back(qo[g] + (l - nbs[g] + M) % M);
+        }
+        gp[g + 1] = (int)gc.size();
+      }
+      P->g_ptr = P->alloc<int>(M + 1);
+      P->g_col = P->alloc<int>(gc.size());
+      P->g_val = P->alloc<double>(gc.size());
+      P->g_dinv = P->alloc<double>(M);
+      P->g_rhs = P->alloc<double>(M);
+      P->g_xa = P->alloc<double>(M);
+      P->g_xb = P->alloc<double>(M);
+      upload(P->g_ptr, gp, s);
+      upload(P->g_col, gc, s);
+      int64_t* eq_d = P->alloc<int64_t>(geq.size());
+      int64_t* rq_d = P->alloc<int64_t>(M);
+      upload(eq_d, geq, s);
+      upload(rq_d, grq, s);
+      hipLaunchKernelGGL(k_gather_solve, dim3(nblk(std::max<int64_t>((int64_t)geq.size(), M), 256)), dim3(256), 0,
+                         s, (int64_t)geq.size(), eq_d, P->Q, P->g_val, (int64_t)M, rq_d, P->g_dinv);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+      P->release(eq_d);
+      P->release(rq_d);
+    }
     if (P->ntile > 0) {
       std::vector<int> tr0(P->ntile), rg, rptr, col;
       std::vector<int64_t> rq, eq;
@@ -953,84 +1053,377 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
-// One level L, in stream order: driving data, local sum (levels < L), the
-// history part (three kernels; the free-space projection when due), solve,
-// receivers.
-void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, double* u_recv_out) {
+// The march state a level reads and updates: density history ring, spectra
+// ring, alpha, alpha'.  The plan's own state, the replay copy and the adjoint
+// state of the gradient pass all use the same level code.
+struct StateRef {
+  double* hist;
+  double2* ring;
+  double2* alpha;
+  double2* dalpha;
+};
+
+StateRef main_state(wfp_plan* P) { return {P->hist, P->ring, P->alpha, P->dalpha}; }
+
+// One level L, in stream order: driving data (unless `driven`: P->ginc already
+// holds it), local sum (levels < L), the history part (three kernels; the
+// free-space projection when due), solve, receivers.
+void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const ExtraSources& ex, double* save,
+                 double* u_recv_row) {
   hipStream_t s = P->stream;
   const bool periodic = P->boundary == WFP_PERIODIC;
-  const Packets pk{P->npk, periodic ? 1 : 0, P->packets};
   // a multiple of 8 blocks, so the XCD-aware block remap is a bijection
   const int nlocblk = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
-  int pp = 1;
-  while (pp < P->npk) pp *= 2;
-  const int rows_inc = 256 / pp;
   const unsigned nb_b = (unsigned)(P->n2 / 2 + 1);
   const size_t lds_b = 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4);
+  const double t = (double)L * P->dt;
+  const double* sig_prev = S.hist + (int64_t)(((L - 1) % P->NH + P->NH) % P->NH) * P->M;
+  if (!driven) {
+    const Packets pk{P->npk, periodic ? 1 : 0, P->packets};
+    int pp = 1;
+    while (pp < P->npk) pp *= 2;
+    hipLaunchKernelGGL(k_incident, dim3(nblk(P->M, 256 / pp)), dim3(256), 0, s, (int)P->M, t, P->xs, P->beta, pk,
+                       pp, 0, P->ginc);
+  }
+  {
+    StageTimer st(P, WFP_STAGE_LOCAL, s);
+    hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L, 1,
+                       P->nb_start, P->rowbase, P->acx, P->Qc, S.hist, P->loc);
+  }
+  {
+    StageTimer st(P, WFP_STAGE_SPREAD, s);
+    hipLaunchKernelGGL(k_hist_a, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, sig_prev,
+                       (int)P->M, P->cstart, P->ccount, P->swoff, P->sw, P->tw, P->T1, ex);
+  }
+  const bool rbc = !periodic && L > 0 && L % P->rbc_period == 0;
+  {
+    StageTimer st(P, WFP_STAGE_MODES, s);
+    hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, rbc ? 1 : 0, P->fft_n1, P->n2, P->K, P->W, L,
+                       P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha,
+                       P->ybuf, P->V);
+  }
+  if (rbc) {
+    StageTimer st(P, WFP_STAGE_RBC, s);
+    hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->n1, P->n2,
+                       S.alpha, S.dalpha, P->tw_rbc, (double2*)P->rbc_u, (double2*)P->rbc_v);
+    hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->n1, P->n2,
+                       P->W, P->h_rbc, P->delta_s, P->cheb_phi, P->cheb_g, P->ncheb, P->rbc_u, P->rbc_v,
+                       P->tw_rbc, P->dk2, S.alpha, S.dalpha, P->ybuf);
+    hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, L, P->npos,
+                       P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha, P->ybuf,
+                       P->V);
+  }
+  {
+    StageTimer st(P, WFP_STAGE_FFT_INV, s);
+    hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, P->V,
+                       P->tw, (double2*)P->grid2);
+  }
+  double* slot = S.hist + (int64_t)(L % P->NH) * P->M;
+  {
+    StageTimer st(P, WFP_STAGE_SOLVE, s);
+    if (P->n_direct_tiles > 0)
+      hipLaunchKernelGGL(k_solve_direct, dim3(P->n_direct_tiles), dim3(256), 0, s, (int)P->M, P->dt_g0, P->dt_n,
+                         P->dt_p0, P->pt_cs, P->pt_cn, P->pt_inv, P->inv, P->ginc, P->loc, P->i0s, P->iw,
+                         P->beta, P->grid2, P->nf, P->width, slot, save, P->perm);
+    if (P->ntile > 0)
+      hipLaunchKernelGGL(k_solve, dim3(P->ntile), dim3(P->solve_threads), P->lds_jac, s, (int)P->M, P->iters,
+                         P->ext_max, P->tile_r0, P->tile_el, P->tile_g0, P->tile_left, P->tile_n, P->srow_g,
+                         P->srow_dinv, P->srow_ptr, P->scol, P->sval, P->ginc, P->loc, P->i0s, P->iw, P->beta,
+                         P->grid2, P->nf, P->width, slot, save, P->perm);
+    if (P->solve_global) {
+      const unsigned nb = nblk(P->M, 256);
+      double* xa = P->g_xa;
+      double* xb = P->g_xb;
+      hipLaunchKernelGGL(k_solve_rhs, dim3(nb), dim3(256), 0, s, (int)P->M, P->ginc, P->loc, P->beta, P->i0s, P->iw,
+                         P->grid2, P->nf, P->width, P->g_dinv, P->g_rhs, P->iters > 1 ? xa : slot);
+      if (P->iters == 1 && save)
+        hipLaunchKernelGGL(k_unsort, dim3(nb), dim3(256), 0, s, (int)P->M, P->perm, slot, save);
+      for (int it = 1; it < P->iters; ++it) {
+        const bool last = it == P->iters - 1;
+        double* out = last ? slot : xb;
+        hipLaunchKernelGGL(k_jacobi_sweep, dim3(nb), dim3(256), 0, s, (int)P->M, P->g_ptr, P->g_col, P->g_val,
+                           P->g_dinv, P->g_rhs, xa, out, last ? save : nullptr, P->perm);
+        std::swap(xa, xb);
+      }
+    }
+  }
+  if (P->R > 0 && u_recv_row) {
+    StageTimer st(P, WFP_STAGE_RECV, s);
+    hipLaunchKernelGGL(k_receivers, dim3(nblk(P->R, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)P->R,
+                       (int)P->M, P->NQ, P->NH, L, P->rnb_start, P->rnb_count, P->rqoff, P->Qr, S.hist,
+                       P->ri0s, P->riw, P->grid2, P->nf, P->width, u_recv_row);
+  }
+}
+
+size_t state_bytes(const wfp_plan* P) {
+  return (size_t)P->NH * P->M * sizeof(double) + ((size_t)P->W + 2) * P->npos * sizeof(double2);
+}
+
+// Copy a whole state (hist, ring, alpha, alpha') to or from a flat buffer.
+void copy_state(wfp_plan* P, const StateRef& S, char* buf, bool to_buf) {
+  hipStream_t s = P->stream;
+  const size_t nh = (size_t)P->NH * P->M * sizeof(double), nr = (size_t)P->W * P->npos * sizeof(double2),
+               na = (size_t)P->npos * sizeof(double2);
+  char* parts[4] = {(char*)S.hist, (char*)S.ring, (char*)S.alpha, (char*)S.dalpha};
+  const size_t sizes[4] = {nh, nr, na, na};
+  size_t off = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (to_buf) HIPCHK(hipMemcpyAsync(buf + off, parts[i], sizes[i], hipMemcpyDeviceToDevice, s));
+    else HIPCHK(hipMemcpyAsync(parts[i], buf + off, sizes[i], hipMemcpyDeviceToDevice, s));
+    off += sizes[i];
+  }
+}
+
+void zero_state_ref(wfp_plan* P, const StateRef& S) {
+  auto fill = [&](double* ptr, int64_t n) {
+    hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, P->stream, ptr, n, 0.0);
+  };
+  fill(S.hist, (int64_t)P->NH * P->M);
+  fill((double*)S.ring, 2 * (int64_t)P->W * P->npos);
+  fill((double*)S.alpha, 2 * P->npos);
+  fill((double*)S.dalpha, 2 * P->npos);
+  HIPCHK(hipGetLastError());
+}
+
+void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, double* u_recv_out) {
+  const StateRef S = main_state(P);
+  const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
   for (int64_t i = 0; i < n; ++i) {
     const int64_t L = P->level + i;
-    const double t = (double)L * P->dt;
-    const double* sig_prev = P->hist + (int64_t)(((L - 1) % P->NH + P->NH) % P->NH) * P->M;
-    hipLaunchKernelGGL(k_incident, dim3(nblk(P->M, rows_inc)), dim3(256), 0, s, (int)P->M, t, P->xs, P->beta, pk,
-                       pp, P->ginc);
-    {
-      StageTimer st(P, WFP_STAGE_LOCAL, s);
-      hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L,
-                         P->nb_start, P->rowbase, P->acx, P->Qc, P->hist, P->loc);
+    if (P->ckpt_every > 0 && P->ck_from0 && L > 0 && L % P->ckpt_every == 0) {
+      const size_t c = (size_t)(L / P->ckpt_every) - 1;
+      while (P->ckpts.size() <= c) P->ckpts.push_back(P->alloc<char>(state_bytes(P)));
+      copy_state(P, S, P->ckpts[c], true);
     }
-    {
-      StageTimer st(P, WFP_STAGE_SPREAD, s);
-      hipLaunchKernelGGL(k_hist_a, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, sig_prev,
-                         (int)P->M, P->cstart, P->ccount, P->swoff, P->sw, P->tw, P->T1);
-    }
-    const bool rbc = !periodic && L > 0 && L % P->rbc_period == 0;
-    {
-      StageTimer st(P, WFP_STAGE_MODES, s);
-      hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, rbc ? 1 : 0, P->fft_n1, P->n2, P->K, P->W, L,
-                         P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, P->ring, P->alpha, P->dalpha,
-                         P->ybuf, P->V);
-    }
-    if (rbc) {
-      StageTimer st(P, WFP_STAGE_RBC, s);
-      hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->n1, P->n2,
-                         P->alpha, P->dalpha, P->tw_rbc, (double2*)P->rbc_u, (double2*)P->rbc_v);
-      hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->n1,
-                         P->n2, P->W,
-                         P->h_rbc, P->delta_s, P->cheb_phi, P->cheb_g, P->ncheb, P->rbc_u, P->rbc_v, P->tw_rbc,
-                         P->dk2, P->alpha, P->dalpha, P->ybuf);
-      hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, L, P->npos,
-                         P->T1,
-                         P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, P->ring, P->alpha, P->dalpha, P->ybuf,
-                         P->V);
-    }
-    {
-      StageTimer st(P, WFP_STAGE_FFT_INV, s);
-      hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, P->V,
-                         P->tw, (double2*)P->grid2);
-    }
-    double* slot = P->hist + (int64_t)(L % P->NH) * P->M;
     double* save = (sigma_out && i % save_every == 0) ? sigma_out + (i / save_every) * P->M : nullptr;
-    {
-      StageTimer st(P, WFP_STAGE_SOLVE, s);
-      if (P->n_direct_tiles > 0)
-        hipLaunchKernelGGL(k_solve_direct, dim3(P->n_direct_tiles), dim3(256), 0, s, (int)P->M, P->dt_g0, P->dt_n,
-                           P->dt_p0, P->pt_cs, P->pt_cn, P->pt_inv, P->inv, P->ginc, P->loc, P->i0s, P->iw,
-                           P->beta, P->grid2, P->nf, P->width, slot, save, P->perm);
-      if (P->ntile > 0)
-        hipLaunchKernelGGL(k_solve, dim3(P->ntile), dim3(P->solve_threads), P->lds_jac, s, (int)P->M, P->iters,
-                           P->ext_max, P->tile_r0, P->tile_el, P->tile_g0, P->tile_left, P->tile_n, P->srow_g,
-                           P->srow_dinv, P->srow_ptr, P->scol, P->sval, P->ginc, P->loc, P->i0s, P->iw, P->beta,
-                           P->grid2, P->nf, P->width, slot, save, P->perm);
-    }
-    if (P->R > 0 && u_recv_out) {
-      StageTimer st(P, WFP_STAGE_RECV, s);
-      hipLaunchKernelGGL(k_receivers, dim3(nblk(P->R, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)P->R,
-                         (int)P->M, P->NQ, P->NH, L, P->rnb_start, P->rnb_count, P->rqoff, P->Qr, P->hist,
-                         P->ri0s, P->riw, P->grid2, P->nf, P->width, u_recv_out + i * P->R);
-    }
+    march_level(P, S, L, false, none, save, u_recv_out ? u_recv_out + i * P->R : nullptr);
   }
   HIPCHK(hipGetLastError());
   P->level += n;
+}
+
+// ---- gradient pass -------------------------------------------------------
+// The loss J depends on the receiver values u_r^L, L = 0..N-1, and the caller
+// passes e = dJ/du.  Transposing the level (eqs. (periodicIE_disc),
+// (hkcompdisc), (densco), (historySol1)) gives the same level run backwards in
+// time: with q^L = -beta lambda^L (lambda the adjoint of sigma^L),
+//   (I + S) q^L = -beta (sum_r sum_{m>=0} (1/2) Q_m(d_r.) e_r^{L+m}
+//                        + sum_{m>=1} (1/2) Q_m q^{L+m} + u_H^adj),
+// where u_H^adj is the history field of the sources q (scatterers) and e
+// (receivers) at the later levels, computed by the forward history kernels on
+// a second state whose level counter runs N-1-L.  Then
+//   dJ/dbeta_j = -sum_L q_j^L sigma_j^L / beta_j^2,
+//   dJ/dx_j    =  sum_L [ q_j^L D_j^L + sigma_j^L Dadj_j^L ],
+// D = f'(x_j - t_L) + d/dx (local sum of lags m >= 0 + u_H) of the forward
+// densities at x_j and Dadj the same derivative of the adjoint field (sources
+// q and e, local sum signed by sign(x_j - x_source)).  The forward densities
+// of each segment of `checkpoint_every` levels are recomputed from the
+// checkpoint that starts it.
+
+void grad_setup(wfp_plan* P) {
+  if (P->grad_ready) return;
+  const int64_t M = P->M, R = P->R, C = P->ckpt_every;
+  hipStream_t s = P->stream;
+  P->rhist = P->alloc<double>((size_t)P->NH * M);
+  P->ahist = P->alloc<double>((size_t)P->NH * M);
+  P->rring = P->alloc<double2>((size_t)P->W * P->npos);
+  P->aring = P->alloc<double2>((size_t)P->W * P->npos);
+  P->ralpha = P->alloc<double2>(P->npos);
+  P->rdalpha = P->alloc<double2>(P->npos);
+  P->aalpha = P->alloc<double2>(P->npos);
+  P->adalpha = P->alloc<double2>(P->npos);
+  P->segsig = P->alloc<double>((size_t)C * M);
+  P->gb_acc = P->alloc<double>(M);
+  P->gx_acc = P->alloc<double>(M);
+  P->xloc = P->alloc<double>(M);
+  P->xw = P->alloc<double>(M);
+  P->fprime = P->alloc<double>(M);
+  P->gridd = P->alloc<double>(P->nf);
+  P->yd = P->alloc<double2>(P->K + 1);
+  P->esort = P->alloc<double>(R);
+  // receivers as spreading sources, in ascending x
+  std::vector<int> ord(R);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return P->xr_h[a] < P->xr_h[c]; });
+  std::vector<double> xrs(R);
+  for (int64_t i = 0; i < R; ++i) xrs[i] = P->xr_h[ord[i]];
+  std::vector<int> cs(P->nf), cc(P->nf);
+  std::vector<int64_t> wo(P->nf);
+  int64_t wt = 0;
+  for (int i = 0; i < P->nf; ++i) {
+    const double xc = -kPi + (double)i * P->hf;
+    source_range(xrs, xc, P->alpha_es * (1.0 + 1e-12), true, true, cs[i], cc[i]);
+    wo[i] = wt;
+    wt += cc[i];
+  }
+  P->rsort = P->alloc<int>(R);
+  P->rcs = P->alloc<int>(P->nf);
+  P->rcc = P->alloc<int>(P->nf);
+  P->rwo = P->alloc<int64_t>(P->nf);
+  P->rsw = P->alloc<double>(wt);
+  double* xrs_d = P->alloc<double>(R);
+  upload(P->rsort, ord, s);
+  upload(P->rcs, cs, s);
+  upload(P->rcc, cc, s);
+  upload(P->rwo, wo, s);
+  upload(xrs_d, xrs, s);
+  hipLaunchKernelGGL(k_spread_weights, dim3(nblk(P->nf, 256)), dim3(256), 0, s, P->nf, P->hf, 1.0 / P->alpha_es,
+                     P->beta_es, xrs_d, (int)R, P->rcs, P->rcc, P->rwo, P->rsw);
+  HIPCHK(hipGetLastError());
+  // for every scatterer, the receivers within delta: (r, index in r's list)
+  std::vector<std::vector<std::pair<int, int>>> lists(M);
+  for (int64_t r = 0; r < R; ++r)
+    for (int i = 0; i < P->rnbc_h[r]; ++i) lists[(P->rnbs_h[r] + i) % M].push_back({(int)r, i});
+  std::vector<int> ptr(M + 1, 0), rr, ri;
+  for (int64_t j = 0; j < M; ++j) {
+    for (auto& e : lists[j]) {
+      rr.push_back(e.first);
+      ri.push_back(e.second);
+    }
+    ptr[j + 1] = (int)rr.size();
+  }
+  P->adj_ptr = P->alloc<int>(M + 1);
+  P->adj_rr = P->alloc<int>(rr.size());
+  P->adj_ri = P->alloc<int>(ri.size());
+  upload(P->adj_ptr, ptr, s);
+  upload(P->adj_rr, rr, s);
+  upload(P->adj_ri, ri, s);
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(xrs_d);
+  P->grad_ready = true;
+}
+
+// Signed derivative weights for the position gradient: scatterer rows packed
+// with lags m >= 0 (same source ranges as the weights), receivers in the
+// layout of their weights with the sign of x_source - x_receiver.
+void gradx_setup(wfp_plan* P) {
+  if (P->gradx_ready) return;
+  const int64_t M = P->M, R = P->R;
+  hipStream_t s = P->stream;
+  double* tmp = P->alloc<double>(P->dense_total);
+  double* hs = P->alloc<double>(std::max(M, R));
+  std::vector<double> halfs(std::max(M, R), 0.5);
+  upload(hs, halfs, s);
+  launch_local_weights(P, (int)M, P->xs, P->nb_start, P->nb_count, P->qoff, hs, 1, nullptr, nullptr, tmp);
+  std::vector<unsigned> ach((size_t)M * P->NQ);
+  HIPCHK(hipMemcpyAsync(ach.data(), P->ac, ach.size() * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int64_t> rb(M);
+  std::vector<uint2> acxh((size_t)M * P->NQ);
+  int64_t packed = 0;
+  for (int64_t j = 0; j < M; ++j) {
+    rb[j] = packed;
+    unsigned within = 0;
+    for (int m = 0; m < P->NQ; ++m) {
+      const unsigned v = ach[(size_t)j * P->NQ + m];
+      acxh[(size_t)j * P->NQ + m] = make_uint2(v, within);
+      within += v >> 16;
+    }
+    packed += within;
+  }
+  P->drowbase = P->alloc<int64_t>(M);
+  P->acxd = P->alloc<uint2>(acxh.size());
+  P->DQa = P->alloc<double>(packed);
+  upload(P->drowbase, rb, s);
+  upload(P->acxd, acxh, s);
+  hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, 0,
+                     P->nb_count, P->qoff, tmp, P->ac, P->drowbase, P->DQa);
+  HIPCHK(hipGetLastError());
+  std::vector<double> mhalf(R, -0.5);
+  double* mh = P->alloc<double>(R);
+  upload(mh, mhalf, s);
+  int64_t rt = 0;
+  for (int64_t r = 0; r < R; ++r) rt += (int64_t)P->rnbc_h[r] * P->NQ;
+  P->dQr = P->alloc<double>(rt);
+  launch_local_weights(P, (int)R, P->xr, P->rnb_start, P->rnb_count, P->rqoff, mh, 1, nullptr, nullptr, P->dQr);
+  P->segD = P->alloc<double>((size_t)P->ckpt_every * M);
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(tmp);
+  P->release(hs);
+  P->release(mh);
+  P->gradx_ready = true;
+}
+
+// d/dx u_H at the scatterers' grid: modes -i k alpha_k through the type-2
+// transform into P->gridd.
+void deriv_field(wfp_plan* P, const StateRef& S) {
+  hipStream_t s = P->stream;
+  const unsigned nb_b = (unsigned)(P->n2 / 2 + 1);
+  const size_t lds_b = 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4);
+  hipLaunchKernelGGL(k_deriv_y, dim3(nblk(P->K + 1, 256)), dim3(256), 0, s, P->K, P->n1, P->n2, S.alpha, P->dk2,
+                     P->yd);
+  hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, (int64_t)0,
+                     P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha, P->yd,
+                     P->V);
+  hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, P->V, P->tw,
+                     (double2*)P->gridd);
+}
+
+// Signed derivative local sum of lags m >= 0 of the densities in S at level L.
+void deriv_local(wfp_plan* P, const StateRef& S, int64_t L) {
+  const int nlocblk = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
+  hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, P->stream, (int)P->M, P->NQ, P->NH, L, 0,
+                     P->nb_start, P->drowbase, P->acxd, P->DQa, S.hist, P->xloc);
+}
+
+void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, double* grad_x) {
+  hipStream_t s = P->stream;
+  const int64_t M = P->M, R = P->R, C = P->ckpt_every;
+  const bool wx = grad_x != nullptr;
+  grad_setup(P);
+  if (wx) gradx_setup(P);
+  const StateRef rep{P->rhist, P->rring, P->ralpha, P->rdalpha};
+  const StateRef adj{P->ahist, P->aring, P->aalpha, P->adalpha};
+  const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+  const Packets pk{P->npk, 1, P->packets};
+  int pp = 1;
+  while (pp < P->npk) pp *= 2;
+  zero_state_ref(P, adj);
+  hipLaunchKernelGGL(k_fill, dim3(nblk(M, 256)), dim3(256), 0, s, P->gb_acc, M, 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(nblk(M, 256)), dim3(256), 0, s, P->gx_acc, M, 0.0);
+  const int64_t nseg = (N + C - 1) / C;
+  for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+    const int64_t a = sg * C, b = std::min(N, a + C);
+    if (sg == 0) zero_state_ref(P, rep);
+    else copy_state(P, rep, P->ckpts[(size_t)sg - 1], false);
+    for (int64_t L = a; L < b; ++L) {
+      march_level(P, rep, L, false, none, nullptr, nullptr);
+      HIPCHK(hipMemcpyAsync(P->segsig + (L - a) * M, P->rhist + (L % P->NH) * M, M * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+      if (wx) {
+        hipLaunchKernelGGL(k_incident, dim3(nblk(M, 256 / pp)), dim3(256), 0, s, (int)M, (double)L * P->dt, P->xs,
+                           P->beta, pk, pp, 1, P->fprime);
+        deriv_field(P, rep);
+        deriv_local(P, rep, L);
+        hipLaunchKernelGGL(k_fwd_dterm, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->fprime, P->xloc, P->i0s,
+                           P->iw, P->gridd, P->nf, P->width, P->segD + (L - a) * M);
+      }
+    }
+    for (int64_t L = b - 1; L >= a; --L) {
+      const int64_t Rv = N - 1 - L;
+      hipLaunchKernelGGL(k_adj_drive, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, (int)R, P->NQ, L, N, P->adj_ptr,
+                         P->adj_rr, P->adj_ri, P->rqoff, P->rnb_count, P->Qr, wx ? P->dQr : nullptr, e, P->beta,
+                         P->ginc, wx ? P->xw : nullptr);
+      ExtraSources ex = none;
+      if (L + 1 < N) {
+        hipLaunchKernelGGL(k_gather, dim3(nblk(R, 256)), dim3(256), 0, s, (int)R, P->rsort, e + (L + 1) * R,
+                           P->esort);
+        ex = ExtraSources{P->esort, (int)R, P->rcs, P->rcc, P->rwo, P->rsw};
+      }
+      march_level(P, adj, Rv, true, ex, nullptr, nullptr);
+      if (wx) {
+        deriv_field(P, adj);
+        deriv_local(P, adj, Rv);
+      }
+      hipLaunchKernelGGL(k_adj_grad, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->ahist + (Rv % P->NH) * M,
+                         P->segsig + (L - a) * M, P->beta, wx ? P->segD + (L - a) * M : nullptr, P->xloc, P->xw,
+                         P->i0s, P->iw, P->gridd, P->nf, P->width, P->gb_acc, wx ? P->gx_acc : nullptr);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_unsort, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->perm, P->gb_acc, grad_beta);
+  if (wx) hipLaunchKernelGGL(k_unsort, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->perm, P->gx_acc, grad_x);
+  HIPCHK(hipGetLastError());
 }
 
 wfp_status guard(const std::function<void()>& f) {
@@ -1109,6 +1502,7 @@ wfp_status wfp_plan_info(const wfp_plan* P, wfp_info* info) {
   info->device_bytes = P->dev_bytes;
   info->n_weights_nonzero = P->n_weights_nonzero;
   info->n_weights_stored = P->n_weights_stored;
+  info->solve_mode = P->solve_global ? 1 : 0;
   return WFP_OK;
 }
 
@@ -1155,6 +1549,29 @@ wfp_status wfp_run(wfp_plan* P, int64_t n_steps, double* sigma_out, int64_t save
   return guard([&] {
     HIPCHK(hipSetDevice(P->device));
     run_levels(P, n_steps, sigma_out, sigma_out ? save_every : 1, u_recv_out);
+  });
+}
+
+wfp_status wfp_adjoint(wfp_plan* P, int64_t n_levels, const double* dJdu, double* grad_beta, double* grad_x) {
+  if (!P || !dJdu || !grad_beta || n_levels < 1) {
+    g_last_error = "adjoint needs a plan, n_levels >= 1, dJ/du and grad_beta";
+    return WFP_EINVAL;
+  }
+  if (P->boundary != WFP_PERIODIC) {
+    g_last_error = "the gradient pass covers the periodic box only";
+    return WFP_EDOMAIN;
+  }
+  if (P->R < 1) {
+    g_last_error = "the gradient pass needs receivers (R >= 1)";
+    return WFP_EINVAL;
+  }
+  if (P->ckpt_every < 1 || !P->ck_from0 || P->level < n_levels) {
+    g_last_error = "run the n_levels levels from level 0 with checkpoint_every > 0 first";
+    return WFP_ESTATE;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(P->device));
+    run_adjoint(P, n_levels, dJdu, grad_beta, grad_x);
   });
 }
 
@@ -1209,6 +1626,7 @@ wfp_status wfp_set_state(wfp_plan* P, int64_t level, const double* hist, const d
                        (double2*)const_cast<double*>(dalpha));
     HIPCHK(hipGetLastError());
     P->level = level;
+    P->ck_from0 = false;   // the checkpoints no longer describe this history
   });
 }
 

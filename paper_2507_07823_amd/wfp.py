@@ -37,7 +37,8 @@ class Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("eps_window", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("W", ctypes.c_int32), ("p", ctypes.c_int32), ("K", ctypes.c_int64),
                 ("n_gl_local", ctypes.c_int32), ("n_gl_pq", ctypes.c_int32), ("rbc_period", ctypes.c_int32),
-                ("nufft_width", ctypes.c_int32), ("solve_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("nufft_width", ctypes.c_int32), ("solve_iters", ctypes.c_int32),
+                ("checkpoint_every", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -48,7 +49,7 @@ class Info(ctypes.Structure):
                 ("solve_iters", ctypes.c_int32), ("boundary", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("delta", ctypes.c_double), ("b", ctypes.c_double), ("solve_contraction", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("n_weights_nonzero", ctypes.c_int64),
-                ("n_weights_stored", ctypes.c_int64)]
+                ("n_weights_stored", ctypes.c_int64), ("solve_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -74,6 +75,8 @@ def load_library():
     lib.wfp_plan_info.restype = ctypes.c_int32
     lib.wfp_run.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
     lib.wfp_run.restype = ctypes.c_int32
+    lib.wfp_adjoint.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
+    lib.wfp_adjoint.restype = ctypes.c_int32
     lib.wfp_get_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp]
     lib.wfp_get_state.restype = ctypes.c_int32
     lib.wfp_set_state.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
@@ -192,6 +195,17 @@ class Plan:
         u = torch.empty((n_steps, R), dtype=torch.float64, device="cuda") if (receivers and R) else None
         self.run(n_steps, sig, save_every, u)
         return sig, u
+
+    def gradient(self, dJdu, positions=True):
+        """dJ/dbeta and dJ/dx (or None) for the levels 0..N-1 run since the
+        last reset, given dJ/du at the receivers (device tensor [N][R])."""
+        import torch
+        assert dJdu.dtype == torch.float64 and dJdu.is_cuda and dJdu.is_contiguous() and dJdu.dim() == 2
+        M = self.info["M"]
+        gb = torch.empty(M, dtype=torch.float64, device="cuda")
+        gx = torch.empty(M, dtype=torch.float64, device="cuda") if positions else None
+        _check(self._lib.wfp_adjoint(self._h, int(dJdu.shape[0]), _ptr(dJdu), _ptr(gb), _ptr(gx)))
+        return gb, gx
 
     def get_state(self):
         import torch

@@ -196,3 +196,55 @@ def test_interpolation_order_4(wfp):
     g, _, _ = gpu_march(wfp, p, 301, p=4)
     o, _ = oracle_for(p, p=4).run(301)
     assert rho(g, o) < TOL
+
+
+def test_multiband_full_size_against_stored_oracle(wfp):
+    """The throughput workload at full size (M = 1e4, dt = 1e-3, levels
+    0..10000, in the launch configuration bench.py times) against the stored
+    oracle values of tests/golden/multiband_sigma.npz (written by
+    tests/golden/make_golden.py from the oracle alone): every density at
+    levels 250, 1000, 4000 and 10000 and 200 sampled springs every 100 levels."""
+    import os
+    import torch
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "multiband_sigma.npz"))
+    p = workloads.multiband_periodic()
+    n = int(g["n_levels"])
+    say(f"multiband full size: M={p['x'].size} levels={n}")
+    plan = wfp.Plan(p, p["dt"])
+    every = 50
+    sig = torch.empty(((n + every - 1) // every, p["x"].size), dtype=torch.float64, device="cuda")
+    plan.run(n, sig, every)
+    torch.cuda.synchronize()
+    s = sig.cpu().numpy()
+    plan.close()
+    smax = float(g["sigma_max"])
+    worst = 0.0
+    for L, row in zip(g["full_levels"], g["full"]):
+        worst = max(worst, float(np.max(np.abs(s[L // every] - row))))
+    for i, row in enumerate(g["strided"]):
+        L = i * int(g["strided_every"])
+        worst = max(worst, float(np.max(np.abs(s[L // every][g["sample"]] - row))))
+    say(f"  rho = {worst / smax:.2e}")
+    assert worst / smax < TOL
+
+
+def test_dense_cluster_global_solve(wfp):
+    """400 springs inside an interval of length 0.01 at dt = 1e-3: about 80
+    nearby sources per row along one run, more than an LDS tile holds, so the
+    solve takes the global-sweep path (solve_mode 1)."""
+    rng = np.random.default_rng(21)
+    M = 400
+    x = rng.uniform(0.5, 0.51, M)
+    beta = rng.uniform(0.1, 1.0, M)
+    prob = dict(x=x, beta=beta, packets=np.array([[1.0, 0.2, 0.03, 0.0, 0.0]]), boundary=PERIODIC,
+                x_recv=np.array([0.49, 0.505, 0.53]), dt=1e-3)
+    n = 300
+    say(f"dense cluster: M={M} dt=1e-3 levels={n}")
+    sig, u, info = gpu_march(wfp, prob, n)
+    assert info["solve_mode"] == 1
+    o = oracle_for(prob)
+    ref, uref = o.run(n)
+    assert np.max(np.abs(ref)) > 1e-3
+    e1, e2 = rho(sig, ref), rho(u, uref)
+    say(f"  rho(sigma) = {e1:.2e}  rho(u) = {e2:.2e}")
+    assert e1 < TOL and e2 < TOL
