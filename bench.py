@@ -227,6 +227,42 @@ def adjoint_leg(levels, every):
             "gradient_over_plain_time": t_bwd / t_fwd, "finite": ok}
 
 
+def batch_leg(n_inst, levels, m_max):
+    """The batched form on uneven periodic instances (M log-uniform in
+    [100, m_max], dt in {1e-3, 2e-3, 5e-3}, beta ~ U[1, 10], one random pulse
+    each), autotuned, against the same instances marched one plain plan at a
+    time."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    insts = workloads.batch_instances(n=n_inst, n_steps=levels, m_range=(100, m_max))
+    total_m = int(sum(p["x"].size for p in insts))
+    t0 = time.perf_counter()
+    b = wfp.Batch(insts, [p["dt"] for p in insts])
+    setup = time.perf_counter() - t0
+    shape = b.autotune(3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(levels)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.reset()
+    plans = [b.plan(i) for i in range(b.n)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl in plans:
+        pl.run(levels)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    b.reset()
+    b.close()
+    return {"workload": "batched periodic instances", "instances": n_inst, "M_range": [100, m_max],
+            "total_M": total_m, "levels": levels, "plan_setup_s": setup,
+            "autotuned": {"rows_per_block": shape[0], "xcd_remap": shape[1]},
+            "batched_scatterer_steps_per_s": total_m * levels / t_batch,
+            "plain_one_by_one_scatterer_steps_per_s": total_m * levels / t_plain,
+            "batched_over_plain": t_plain / t_batch}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +273,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--adjoint-levels", type=int, default=500,
                     help="levels of the adjoint leg (0 skips it)")
+    ap.add_argument("--batch-levels", type=int, default=200, help="levels of the batched leg (0 skips it)")
+    ap.add_argument("--batch-instances", type=int, default=512)
+    ap.add_argument("--batch-max-m", type=int, default=10_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 256 MiB copy used to calibrate the HBM counters")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
@@ -310,6 +349,11 @@ def main():
         adjoint = adjoint_leg(args.adjoint_levels, 250)
         log(f"adjoint leg: {adjoint}")
 
+    batch = None
+    if args.batch_levels > 0:
+        batch = batch_leg(args.batch_instances, args.batch_levels, args.batch_max_m)
+        log(f"batch leg: {batch}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_steps)
@@ -322,7 +366,7 @@ def main():
         "config": {"workload": "periodic multiband springs", "M": M, "dt": p["dt"], "K": info["K"],
                    "W": info["W"], "p": info["p"], "n_fine": info["n_fine"], "pairs": info["n_pairs"],
                    "levels_timed": args.steps, "parallelism": "single GPU"},
-        "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "cpu_baseline": cpu,
+        "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()

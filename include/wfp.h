@@ -183,6 +183,40 @@ wfp_status wfp_get_profile(wfp_plan* plan, double* ms, int64_t* launches);
 /* Return the plan to level 0 with zero history (stream-ordered). */
 wfp_status wfp_reset(wfp_plan* plan);
 
+/* Batched form (not in the paper): n independent periodic problems without
+ * receivers, each with its own x, beta, incident field and dt, marched in
+ * lockstep.  Each stage of a level is one launch over an (instance, block) work
+ * list and the whole level is one HIP graph replayed per level; every instance
+ * computes exactly what its own plan would (same kernel bodies, same order).
+ *   wfp_batch_create  host problem data as for wfp_plan_create (probs[n],
+ *                     pars[n]); builds one plan per instance.  Synchronous.
+ *                     Errors: WFP_EINVAL (R != 0), WFP_EDOMAIN (free space, or
+ *                     an instance whose stages exceed the LDS), as for plans.
+ *   wfp_batch_run     march n_steps levels of every instance; sigma_final is a
+ *                     HOST array of n DEVICE pointers (entries may be NULL, the
+ *                     array may be NULL): instance i's densities of its last
+ *                     level, [M_i] in caller order.  Ordered after prior work on
+ *                     `stream`; later work on `stream` waits for it.
+ *   wfp_batch_reset   all instances back to level 0.
+ *   wfp_batch_autotune  from level 0: times trial_levels levels for each launch
+ *                     shape of the local sum (4 or 8 rows per block, with or
+ *                     without the XCD-aware block order), keeps the fastest,
+ *                     reports it and leaves the batch at level 0.
+ *   wfp_batch_size    number of instances and the current level.
+ *   wfp_batch_plan    instance i's plan (owned by the batch: never destroy it;
+ *                     wfp_get_state / wfp_plan_info on it are valid between runs).
+ *   wfp_batch_destroy releases everything (NULL is a no-op). */
+typedef struct wfp_batch wfp_batch;
+wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_params* pars, void* stream,
+                            wfp_batch** out);
+wfp_status wfp_batch_run(wfp_batch* batch, int64_t n_steps, double* const* sigma_final);
+wfp_status wfp_batch_reset(wfp_batch* batch);
+wfp_status wfp_batch_autotune(wfp_batch* batch, int32_t trial_levels, int32_t* rows_per_block,
+                              int32_t* xcd_remap);
+wfp_status wfp_batch_size(const wfp_batch* batch, int32_t* n, int64_t* level);
+wfp_plan* wfp_batch_plan(wfp_batch* batch, int32_t i);
+void wfp_batch_destroy(wfp_batch* batch);
+
 const char* wfp_status_string(wfp_status s);
 const char* wfp_last_error(void);
 int32_t wfp_abi_version(void);

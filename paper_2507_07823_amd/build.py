@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwfp.so")
-SOURCES = ["wfp_kernels.hip", "wfp_plan.hip", "wfp_host.cpp"]
+SOURCES = ["wfp_kernels.hip", "wfp_plan.hip", "wfp_batch.hip", "wfp_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,404 @@
+// Batched form: many independent periodic problems marched in lockstep, each
+// stage of a level one launch over an (instance, block) work list, the whole
+// level captured once in a HIP graph (the level index lives on the device).
+// Each instance is an ordinary plan (wfp_plan_create); the batch only adds the
+// descriptor table, the work lists, the graph and the launch-shape autotuner.
+#include "wfp_internal.h"
+
+struct wfp_batch {
+  int device = 0;
+  hipStream_t user_stream = nullptr;   // the caller's stream (ordering only)
+  hipStream_t bs = nullptr;            // the batch's own stream (graph capture)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<wfp_plan*> plans;
+  int64_t level = 0;
+  int64_t* level_d = nullptr;
+  InstDesc* desc_d = nullptr;
+  // work lists (device) and their lengths
+  int2 *wl_inc = nullptr, *wl_loc4 = nullptr, *wl_loc8 = nullptr, *wl_a = nullptr, *wl_b = nullptr,
+       *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr;
+  int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0;
+  size_t lds_a = 0, lds_b = 0, lds_c = 0, lds_til = 0;
+  int max_sweeps = 0;                  // largest sweep count of the global-solve instances
+  // launch shape of the local sum: rows per block (4 or 8) and the XCD remap
+  int loc_rows = 4, loc_xcd = 1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void*> owned;
+  ~wfp_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (wfp_plan* p : plans) wfp_plan_destroy(p);
+    for (void* q : owned) (void)hipFree(q);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (bs) (void)hipStreamDestroy(bs);
+  }
+  template <class T>
+  T* alloc(size_t n) {
+    int64_t dummy = 0;
+    T* q = dalloc<T>(n, dummy);
+    owned.push_back(q);
+    return q;
+  }
+};
+
+namespace {
+
+InstDesc describe(const wfp_plan* P) {
+  InstDesc d{};
+  d.M = (int)P->M;
+  d.NQ = P->NQ;
+  d.NH = P->NH;
+  d.W = P->W;
+  d.nf = P->nf;
+  d.width = P->width;
+  d.n1 = P->n1;
+  d.n2 = P->n2;
+  d.iters = P->iters;
+  d.npk = P->npk;
+  int pp = 1;
+  while (pp < P->npk) pp *= 2;
+  d.pp = pp;
+  d.ext_max = P->ext_max;
+  d.global_solve = P->solve_global ? 1 : 0;
+  d.K = P->K;
+  d.npos = P->npos;
+  d.dt = P->dt;
+  d.f1 = P->fft_n1;
+  d.f2 = P->fft_n2;
+  d.xs = P->xs;
+  d.beta = P->beta;
+  d.packets = P->packets;
+  d.nb_start = P->nb_start;
+  d.rowbase = P->rowbase;
+  d.acx = P->acx;
+  d.Qc = P->Qc;
+  d.hist = P->hist;
+  d.loc = P->loc;
+  d.ginc = P->ginc;
+  d.cstart = P->cstart;
+  d.ccount = P->ccount;
+  d.swoff = P->swoff;
+  d.sw = P->sw;
+  d.tw = P->tw;
+  d.T1 = P->T1;
+  d.V = P->V;
+  d.grid2 = P->grid2;
+  d.dk1 = P->dk1;
+  d.dk2 = P->dk2;
+  d.pk = P->pk;
+  d.qk = P->qk;
+  d.rot = P->rot;
+  d.ring = P->ring;
+  d.alpha = P->alpha;
+  d.dalpha = P->dalpha;
+  d.ybuf = P->ybuf;
+  d.dt_g0 = P->dt_g0;
+  d.dt_n = P->dt_n;
+  d.dt_p0 = P->dt_p0;
+  d.pt_cs = P->pt_cs;
+  d.pt_cn = P->pt_cn;
+  d.pt_inv = P->pt_inv;
+  d.inv = P->inv;
+  d.tile_r0 = P->tile_r0;
+  d.tile_el = P->tile_el;
+  d.tile_g0 = P->tile_g0;
+  d.tile_left = P->tile_left;
+  d.tile_n = P->tile_n;
+  d.srow_g = P->srow_g;
+  d.srow_ptr = P->srow_ptr;
+  d.scol = P->scol;
+  d.srow_dinv = P->srow_dinv;
+  d.sval = P->sval;
+  d.i0s = P->i0s;
+  d.iw = P->iw;
+  d.g_ptr = P->g_ptr;
+  d.g_col = P->g_col;
+  d.g_val = P->g_val;
+  d.g_dinv = P->g_dinv;
+  d.g_rhs = P->g_rhs;
+  d.g_xa = P->g_xa;
+  d.g_xb = P->g_xb;
+  return d;
+}
+
+// Work list of (instance, block) items, padded to a multiple of `pad` with
+// instance -1.
+int2* upload_work(wfp_batch* B, const std::vector<int2>& w, int pad, int& n) {
+  std::vector<int2> v = w;
+  while (pad > 1 && v.size() % pad) v.push_back(make_int2(-1, 0));
+  n = (int)v.size();
+  if (v.empty()) return nullptr;
+  int2* d = B->alloc<int2>(v.size());
+  HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice, B->bs));
+  return d;
+}
+
+void build_batch(wfp_batch* B) {
+  const int n = (int)B->plans.size();
+  std::vector<InstDesc> desc(n);
+  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows;
+  for (int i = 0; i < n; ++i) {
+    const wfp_plan* P = B->plans[i];
+    desc[i] = describe(P);
+    const int M = (int)P->M;
+    const int rpb = 256 / desc[i].pp;
+    for (int b = 0; b < (int)nblk(M, rpb); ++b) inc.push_back(make_int2(i, b));
+    for (int b = 0; b < (int)nblk(M, 4); ++b) loc4.push_back(make_int2(i, b));
+    for (int b = 0; b < (int)nblk(M, 8); ++b) loc8.push_back(make_int2(i, b));
+    for (int b = 0; b < P->n1; ++b) wa.push_back(make_int2(i, b));
+    for (int b = 0; b < P->n2 / 2 + 1; ++b) wb.push_back(make_int2(i, b));
+    for (int b = 0; b < P->n1; ++b) wc.push_back(make_int2(i, b));
+    for (int b = 0; b < P->n_direct_tiles; ++b) dir.push_back(make_int2(i, b));
+    for (int b = 0; b < P->ntile; ++b) til.push_back(make_int2(i, b));
+    if (P->solve_global) {
+      for (int b = 0; b < (int)nblk(M, 256); ++b) rows.push_back(make_int2(i, b));
+      B->max_sweeps = std::max(B->max_sweeps, P->iters);
+    }
+    B->lds_a = std::max(B->lds_a, (size_t)P->n2 * sizeof(double2));
+    B->lds_b = std::max(B->lds_b, 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4));
+    B->lds_til = std::max(B->lds_til, P->lds_jac);
+  }
+  B->lds_c = B->lds_a;
+  B->desc_d = B->alloc<InstDesc>(n);
+  HIPCHK(hipMemcpyAsync(B->desc_d, desc.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice, B->bs));
+  B->wl_inc = upload_work(B, inc, 1, B->n_inc);
+  B->wl_loc4 = upload_work(B, loc4, 8, B->n_loc4);
+  B->wl_loc8 = upload_work(B, loc8, 8, B->n_loc8);
+  B->wl_a = upload_work(B, wa, 1, B->n_a);
+  B->wl_b = upload_work(B, wb, 1, B->n_b);
+  B->wl_c = upload_work(B, wc, 1, B->n_c);
+  B->wl_dir = upload_work(B, dir, 1, B->n_dir);
+  B->wl_til = upload_work(B, til, 1, B->n_til);
+  B->wl_rows = upload_work(B, rows, 1, B->n_rows);
+  B->level_d = B->alloc<int64_t>(1);
+  if (B->lds_b > 160 * 1024 || B->lds_til > 160 * 1024) fail(WFP_EDOMAIN, "batched stage needs more than 160 KB of LDS");
+  HIPCHK(hipFuncSetAttribute((const void*)kb_hist_b, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)kb_solve, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipStreamSynchronize(B->bs));
+}
+
+// The launches of one level on the batch stream, in stream order.
+void enqueue_level(wfp_batch* B) {
+  hipStream_t s = B->bs;
+  BatchLaunch bl{B->desc_d, nullptr, B->level_d};
+  bl.work = B->wl_inc;
+  hipLaunchKernelGGL(kb_incident, dim3(B->n_inc), dim3(256), 0, s, bl);
+  if (B->loc_rows == 8) {
+    bl.work = B->wl_loc8;
+    hipLaunchKernelGGL(kb_local, dim3(B->n_loc8), dim3(512), 0, s, bl, B->loc_xcd);
+  } else {
+    bl.work = B->wl_loc4;
+    hipLaunchKernelGGL(kb_local, dim3(B->n_loc4), dim3(256), 0, s, bl, B->loc_xcd);
+  }
+  bl.work = B->wl_a;
+  hipLaunchKernelGGL(kb_hist_a, dim3(B->n_a), dim3(256), B->lds_a, s, bl);
+  bl.work = B->wl_b;
+  hipLaunchKernelGGL(kb_hist_b, dim3(B->n_b), dim3(512), B->lds_b, s, bl);
+  bl.work = B->wl_c;
+  hipLaunchKernelGGL(kb_hist_c, dim3(B->n_c), dim3(256), B->lds_c, s, bl);
+  if (B->n_dir) {
+    bl.work = B->wl_dir;
+    hipLaunchKernelGGL(kb_solve_direct, dim3(B->n_dir), dim3(256), 0, s, bl);
+  }
+  if (B->n_til) {
+    bl.work = B->wl_til;
+    hipLaunchKernelGGL(kb_solve, dim3(B->n_til), dim3(256), B->lds_til, s, bl);
+  }
+  if (B->n_rows) {
+    bl.work = B->wl_rows;
+    hipLaunchKernelGGL(kb_solve_rhs, dim3(B->n_rows), dim3(256), 0, s, bl);
+    for (int it = 1; it < B->max_sweeps; ++it) hipLaunchKernelGGL(kb_jacobi_sweep, dim3(B->n_rows), dim3(256), 0, s, bl, it);
+  }
+  hipLaunchKernelGGL(kb_advance, dim3(1), dim3(64), 0, s, B->level_d);
+}
+
+void drop_graph(wfp_batch* B) {
+  if (B->exec) HIPCHK(hipGraphExecDestroy(B->exec));
+  if (B->graph) HIPCHK(hipGraphDestroy(B->graph));
+  B->exec = nullptr;
+  B->graph = nullptr;
+}
+
+void capture(wfp_batch* B) {
+  if (B->exec) return;
+  HIPCHK(hipStreamBeginCapture(B->bs, hipStreamCaptureModeThreadLocal));
+  enqueue_level(B);
+  HIPCHK(hipStreamEndCapture(B->bs, &B->graph));
+  HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+}
+
+void set_level(wfp_batch* B, int64_t L) {
+  B->level = L;
+  HIPCHK(hipMemcpyAsync(B->level_d, &B->level, sizeof(int64_t), hipMemcpyHostToDevice, B->bs));
+  HIPCHK(hipStreamSynchronize(B->bs));
+  for (wfp_plan* P : B->plans) P->level = L;
+}
+
+void run_batch(wfp_batch* B, int64_t n) {
+  capture(B);
+  for (int64_t i = 0; i < n; ++i) HIPCHK(hipGraphLaunch(B->exec, B->bs));
+  B->level += n;
+  for (wfp_plan* P : B->plans) P->level = B->level;
+}
+
+void reset_batch(wfp_batch* B) {
+  for (wfp_plan* P : B->plans)
+    if (wfp_reset(P) != WFP_OK) fail(WFP_EHIP, g_last_error);
+  HIPCHK(hipStreamSynchronize(B->bs));
+  set_level(B, 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_params* pars, void* stream,
+                            wfp_batch** out) {
+  if (!out || n < 1 || !probs || !pars) {
+    g_last_error = "batch needs n >= 1, problems, parameters and an output handle";
+    return WFP_EINVAL;
+  }
+  *out = nullptr;
+  for (int32_t i = 0; i < n; ++i) {
+    if (probs[i].boundary != WFP_PERIODIC) {
+      g_last_error = "the batched form covers periodic problems";
+      return WFP_EDOMAIN;
+    }
+    if (probs[i].R != 0) {
+      g_last_error = "the batched form has no receivers (R must be 0)";
+      return WFP_EINVAL;
+    }
+  }
+  wfp_batch* B = new wfp_batch();
+  wfp_status st = guard([&] {
+    HIPCHK(hipGetDevice(&B->device));
+    B->user_stream = (hipStream_t)stream;
+    HIPCHK(hipStreamCreateWithFlags(&B->bs, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+    for (int32_t i = 0; i < n; ++i) {
+      wfp_plan* P = nullptr;
+      const wfp_status s = wfp_plan_create(&probs[i], &pars[i], B->bs, &P);
+      if (s != WFP_OK) throw Error{s, "instance " + std::to_string(i) + ": " + g_last_error};
+      B->plans.push_back(P);
+    }
+    build_batch(B);
+    set_level(B, 0);
+  });
+  if (st != WFP_OK) {
+    delete B;
+    return st;
+  }
+  *out = B;
+  return WFP_OK;
+}
+
+void wfp_batch_destroy(wfp_batch* B) {
+  if (!B) return;
+  (void)hipStreamSynchronize(B->bs);
+  delete B;
+}
+
+wfp_status wfp_batch_run(wfp_batch* B, int64_t n_steps, double* const* sigma_final) {
+  if (!B || n_steps < 0) {
+    g_last_error = "bad batch or step count";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(B->device));
+    HIPCHK(hipEventRecord(B->ev_in, B->user_stream));
+    HIPCHK(hipStreamWaitEvent(B->bs, B->ev_in, 0));
+    run_batch(B, n_steps);
+    if (sigma_final && B->level > 0) {
+      for (size_t i = 0; i < B->plans.size(); ++i) {
+        const wfp_plan* P = B->plans[i];
+        if (!sigma_final[i]) continue;
+        const double* last = P->hist + (int64_t)(((B->level - 1) % P->NH + P->NH) % P->NH) * P->M;
+        hipLaunchKernelGGL(k_unsort, dim3(nblk(P->M, 256)), dim3(256), 0, B->bs, (int)P->M, P->perm, last,
+                           sigma_final[i]);
+      }
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipEventRecord(B->ev_out, B->bs));
+    HIPCHK(hipStreamWaitEvent(B->user_stream, B->ev_out, 0));
+  });
+}
+
+wfp_status wfp_batch_reset(wfp_batch* B) {
+  if (!B) {
+    g_last_error = "NULL batch";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(B->device));
+    HIPCHK(hipEventRecord(B->ev_in, B->user_stream));
+    HIPCHK(hipStreamWaitEvent(B->bs, B->ev_in, 0));
+    reset_batch(B);
+  });
+}
+
+wfp_status wfp_batch_autotune(wfp_batch* B, int32_t trial_levels, int32_t* rows_per_block, int32_t* xcd_remap) {
+  if (!B || trial_levels < 1) {
+    g_last_error = "autotune needs a batch and trial_levels >= 1";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(B->device));
+    if (B->level != 0) fail(WFP_ESTATE, "autotune runs from level 0 (call wfp_batch_reset first)");
+    HIPCHK(hipStreamSynchronize(B->user_stream));
+    hipEvent_t a, c;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&c));
+    float best = 1e30f;
+    int br = 4, bx = 1;
+    const int cand[4][2] = {{4, 1}, {8, 1}, {4, 0}, {8, 0}};
+    for (const auto& cd : cand) {
+      B->loc_rows = cd[0];
+      B->loc_xcd = cd[1];
+      drop_graph(B);
+      capture(B);
+      HIPCHK(hipGraphLaunch(B->exec, B->bs));       // warm-up level
+      HIPCHK(hipEventRecord(a, B->bs));
+      for (int32_t i = 0; i < trial_levels; ++i) HIPCHK(hipGraphLaunch(B->exec, B->bs));
+      HIPCHK(hipEventRecord(c, B->bs));
+      HIPCHK(hipEventSynchronize(c));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, a, c));
+      if (ms < best) {
+        best = ms;
+        br = cd[0];
+        bx = cd[1];
+      }
+      reset_batch(B);
+    }
+    HIPCHK(hipEventDestroy(a));
+    HIPCHK(hipEventDestroy(c));
+    B->loc_rows = br;
+    B->loc_xcd = bx;
+    drop_graph(B);
+    if (rows_per_block) *rows_per_block = br;
+    if (xcd_remap) *xcd_remap = bx;
+  });
+}
+
+wfp_status wfp_batch_size(const wfp_batch* B, int32_t* n, int64_t* level) {
+  if (!B) {
+    g_last_error = "NULL batch";
+    return WFP_EINVAL;
+  }
+  if (n) *n = (int32_t)B->plans.size();
+  if (level) *level = B->level;
+  return WFP_OK;
+}
+
+wfp_plan* wfp_batch_plan(wfp_batch* B, int32_t i) {
+  if (!B || i < 0 || i >= (int32_t)B->plans.size()) {
+    g_last_error = "bad batch or instance index";
+    return nullptr;
+  }
+  return B->plans[i];
+}
+
+}  // extern "C"

@@ -168,6 +168,57 @@ __global__ void k_adj_grad(int M, const double* __restrict__ q, const double* __
 __global__ void k_gather(int n, const int* __restrict__ idx, const double* __restrict__ in, double* __restrict__ out);
 __global__ void k_unsort(int M, const int* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out);
 
+// ---- batched form: one launch per stage over an (instance, block) work list ----
+// Everything the level kernels of one instance read.
+struct InstDesc {
+  int M, NQ, NH, W, nf, width, n1, n2, iters, npk, pp, ext_max, global_solve;
+  int64_t K, npos;
+  double dt;
+  FftPlan f1, f2;
+  const double *xs, *beta, *packets;
+  const int* nb_start;
+  const int64_t* rowbase;
+  const uint2* acx;
+  const double* Qc;
+  double *hist, *loc, *ginc;
+  const int *cstart, *ccount;
+  const int64_t* swoff;
+  const double* sw;
+  const double2* tw;
+  double2 *T1, *V;
+  double* grid2;
+  const double *dk1, *dk2, *pk, *qk, *rot;
+  double2 *ring, *alpha, *dalpha, *ybuf;
+  const int *dt_g0, *dt_n, *dt_p0, *pt_cs, *pt_cn;
+  const int64_t* pt_inv;
+  const double* inv;
+  const int *tile_r0, *tile_el, *tile_g0, *tile_left, *tile_n, *srow_g, *srow_ptr, *scol;
+  const double *srow_dinv, *sval;
+  const int* i0s;
+  const double* iw;
+  const int *g_ptr, *g_col;
+  const double *g_val, *g_dinv;
+  double *g_rhs, *g_xa, *g_xb;
+};
+
+// Work item (instance, block within the instance); instance < 0 pads the list.
+struct BatchLaunch {
+  const InstDesc* desc;
+  const int2* work;
+  const int64_t* level;   // the level all instances compute (device)
+};
+
+__global__ void kb_incident(BatchLaunch b);
+__global__ void kb_local(BatchLaunch b, int xcd);
+__global__ void kb_hist_a(BatchLaunch b);
+__global__ void kb_hist_b(BatchLaunch b);
+__global__ void kb_hist_c(BatchLaunch b);
+__global__ void kb_solve_direct(BatchLaunch b);
+__global__ void kb_solve(BatchLaunch b);
+__global__ void kb_solve_rhs(BatchLaunch b);
+__global__ void kb_jacobi_sweep(BatchLaunch b, int it);
+__global__ void kb_advance(int64_t* level);
+
 // ---- state movement ----
 __global__ void k_hist_io(int M, int NH, int64_t L, int to_user, double* __restrict__ hist,
                           double* __restrict__ user, const int* __restrict__ perm);

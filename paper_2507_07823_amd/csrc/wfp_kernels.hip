@@ -525,12 +525,11 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
 // lane with every load issued before use.
 constexpr int kMaxNQ = 64;
 
-__global__ void __launch_bounds__(256)
-k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb_start,
+__device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb_start,
             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
-            const double* __restrict__ hist, double* __restrict__ loc) {
+            const double* __restrict__ hist, double* __restrict__ loc, int bid) {
   const int lane = threadIdx.x & 63;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int lb = bid;
   const int j = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= M) return;   // no block-level barrier in this kernel
   const int st = nb_start[j];
@@ -573,18 +572,24 @@ k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb
   if (lane == 0) loc[j] = accs;
 }
 
+__global__ void __launch_bounds__(256)
+k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb_start,
+            const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
+            const double* __restrict__ hist, double* __restrict__ loc) {
+  k_local_rhs_body(M, NQ, NH, L, m0, nb_start, rowbase, acx, Qc, hist, loc, xcd_block(blockIdx.x, gridDim.x));
+}
+
 // Driving data g_j(t) = beta_j f(x_j - t) (eq. (gj); f periodised in the
 // periodic box), stored negated: ginc_j = -g_j.  Thread (row, packet) sums the
 // packet's images; the packets are then added in order.  `pp` = packets per
 // row rounded up to a power of two; 256/pp rows per block.  With deriv != 0 it
 // writes f'(x_j - t) instead (gradient with respect to positions).
-__global__ void __launch_bounds__(256)
-k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta, Packets pk, int pp,
-           int deriv, double* __restrict__ ginc) {
+__device__ __forceinline__ void k_incident_body(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta, Packets pk, int pp,
+           int deriv, double* __restrict__ ginc, int bid) {
   __shared__ double term[256];
   const int rpb = 256 / pp;
   const int lr = threadIdx.x / pp, ip = threadIdx.x - lr * pp;
-  const int j = blockIdx.x * rpb + lr;
+  const int j = bid * rpb + lr;
   double f = 0.0;
   if (j < M && ip < pk.n) {
     double s = xs[j] - t;
@@ -611,6 +616,12 @@ k_incident(int M, double t, const double* __restrict__ xs, const double* __restr
   }
 }
 
+__global__ void __launch_bounds__(256)
+k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta, Packets pk, int pp,
+           int deriv, double* __restrict__ ginc) {
+  k_incident_body(M, t, xs, beta, pk, pp, deriv, ginc, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Per-step solve (I + S) sigma^L = rhs, S_jl = (beta_j/2) Q_0(d_jl) for d < dt
 // (eq. (linearSystem)), by `iters` Jacobi sweeps from zero, one block per tile
@@ -623,17 +634,16 @@ k_incident(int M, double t, const double* __restrict__ xs, const double* __restr
 // grid.  The result goes to the
 // history slot of level L and, when requested, to the caller's output row.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-k_solve(int M, int iters, int ext_max, const int* __restrict__ tile_r0, const int* __restrict__ tile_el,
+__device__ __forceinline__ void k_solve_body(int M, int iters, int ext_max, const int* __restrict__ tile_r0, const int* __restrict__ tile_el,
         const int* __restrict__ tile_g0, const int* __restrict__ tile_left, const int* __restrict__ tile_n,
         const int* __restrict__ rg, const double* __restrict__ rdinv, const int* __restrict__ rptr,
         const int* __restrict__ ecol, const double* __restrict__ ev, const double* __restrict__ ginc,
         const double* __restrict__ loc, const int* __restrict__ i0s, const double* __restrict__ iw,
         const double* __restrict__ beta, const double* __restrict__ grid2, int nf, int width,
         double* __restrict__ sig_out,
-        double* __restrict__ save_row, const int* __restrict__ perm) {
+        double* __restrict__ save_row, const int* __restrict__ perm, int bid) {
   extern __shared__ double sm[];
-  const int t = blockIdx.x;
+  const int t = bid;
   const int r0 = tile_r0[t], el = tile_el[t];
   const int k0 = rptr[r0], ne = rptr[r0 + el] - k0;
   double* c = sm;
@@ -680,29 +690,48 @@ k_solve(int M, int iters, int ext_max, const int* __restrict__ tile_r0, const in
   }
 }
 
+__global__ void __launch_bounds__(256)
+k_solve(int M, int iters, int ext_max, const int* __restrict__ tile_r0, const int* __restrict__ tile_el,
+        const int* __restrict__ tile_g0, const int* __restrict__ tile_left, const int* __restrict__ tile_n,
+        const int* __restrict__ rg, const double* __restrict__ rdinv, const int* __restrict__ rptr,
+        const int* __restrict__ ecol, const double* __restrict__ ev, const double* __restrict__ ginc,
+        const double* __restrict__ loc, const int* __restrict__ i0s, const double* __restrict__ iw,
+        const double* __restrict__ beta, const double* __restrict__ grid2, int nf, int width,
+        double* __restrict__ sig_out,
+        double* __restrict__ save_row, const int* __restrict__ perm) {
+  k_solve_body(M, iters, ext_max, tile_r0, tile_el, tile_g0, tile_left, tile_n, rg, rdinv, rptr, ecol, ev, ginc, loc, i0s, iw, beta, grid2, nf, width, sig_out, save_row, perm, blockIdx.x);
+}
+
 // Per-step solve when the tiles do not fit in LDS (dense nearby coupling along
 // long runs): global Jacobi sweeps, one launch each, CSR over all rows.
 // k_solve_rhs completes the right-hand side b_j = part_j - beta_j u_H(x_j) and
 // the first sweep from zero, x_j = b_j / (1 + S_jj); k_jacobi_sweep does
 // x'_j = (b_j - sum_{l != j} S_jl x_l) / (1 + S_jj) and, on the last sweep,
 // also writes the caller's row.
-__global__ void k_solve_rhs(int M, const double* __restrict__ ginc, const double* __restrict__ loc,
+__device__ __forceinline__ void k_solve_rhs_body(int M, const double* __restrict__ ginc, const double* __restrict__ loc,
                             const double* __restrict__ beta, const int* __restrict__ i0s,
                             const double* __restrict__ iw, const double* __restrict__ grid2, int nf, int width,
-                            const double* __restrict__ dinv, double* __restrict__ rhs, double* __restrict__ x) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+                            const double* __restrict__ dinv, double* __restrict__ rhs, double* __restrict__ x, int bid) {
+  const int j = bid * blockDim.x + threadIdx.x;
   if (j >= M) return;
   const double b = (ginc[j] - loc[j]) - beta[j] * interp_pre(j, i0s, iw, grid2, nf, width);
   rhs[j] = b;
   x[j] = b * dinv[j];
 }
 
-__global__ void k_jacobi_sweep(int M, const int* __restrict__ ptr, const int* __restrict__ col,
+__global__ void k_solve_rhs(int M, const double* __restrict__ ginc, const double* __restrict__ loc,
+                            const double* __restrict__ beta, const int* __restrict__ i0s,
+                            const double* __restrict__ iw, const double* __restrict__ grid2, int nf, int width,
+                            const double* __restrict__ dinv, double* __restrict__ rhs, double* __restrict__ x) {
+  k_solve_rhs_body(M, ginc, loc, beta, i0s, iw, grid2, nf, width, dinv, rhs, x, blockIdx.x);
+}
+
+__device__ __forceinline__ void k_jacobi_sweep_body(int M, const int* __restrict__ ptr, const int* __restrict__ col,
                                const double* __restrict__ val, const double* __restrict__ dinv,
                                const double* __restrict__ rhs, const double* __restrict__ xin,
                                double* __restrict__ xout, double* __restrict__ save_row,
-                               const int* __restrict__ perm) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+                               const int* __restrict__ perm, int bid) {
+  const int j = bid * blockDim.x + threadIdx.x;
   if (j >= M) return;
   double acc = rhs[j];
   for (int k = ptr[j]; k < ptr[j + 1]; ++k) acc = fma(-val[k], xin[col[k]], acc);
@@ -711,20 +740,27 @@ __global__ void k_jacobi_sweep(int M, const int* __restrict__ ptr, const int* __
   if (save_row) save_row[perm[j]] = v;
 }
 
+__global__ void k_jacobi_sweep(int M, const int* __restrict__ ptr, const int* __restrict__ col,
+                               const double* __restrict__ val, const double* __restrict__ dinv,
+                               const double* __restrict__ rhs, const double* __restrict__ xin,
+                               double* __restrict__ xout, double* __restrict__ save_row,
+                               const int* __restrict__ perm) {
+  k_jacobi_sweep_body(M, ptr, col, val, dinv, rhs, xin, xout, save_row, perm, blockIdx.x);
+}
+
 // Per-step solve on small nearby-runs: I + S is block diagonal over maximal
 // runs of consecutive springs closer than dt; a run of s springs is solved with
 // its precomputed inverse,  sigma_i = sum_k inv[i][k] rhs_k.  One block per
 // tile of whole runs (points g0 .. g0 + n - 1, circular).  Per point: the
 // run's first local index, its size and the offset of its inverse row.
-__global__ void __launch_bounds__(256)
-k_solve_direct(int M, const int* __restrict__ dt_g0, const int* __restrict__ dt_n, const int* __restrict__ dt_p0,
+__device__ __forceinline__ void k_solve_direct_body(int M, const int* __restrict__ dt_g0, const int* __restrict__ dt_n, const int* __restrict__ dt_p0,
                const int* __restrict__ pt_cs, const int* __restrict__ pt_cn, const int64_t* __restrict__ pt_inv,
                const double* __restrict__ inv, const double* __restrict__ ginc, const double* __restrict__ loc,
                const int* __restrict__ i0s, const double* __restrict__ iw, const double* __restrict__ beta,
                const double* __restrict__ grid2, int nf, int width, double* __restrict__ sig_out,
-               double* __restrict__ save_row, const int* __restrict__ perm) {
+               double* __restrict__ save_row, const int* __restrict__ perm, int bid) {
   __shared__ double c[256];
-  const int t = blockIdx.x;
+  const int t = bid;
   const int g0 = dt_g0[t], n = dt_n[t], p0 = dt_p0[t];
   const int e = threadIdx.x;
   int g = g0 + e;
@@ -739,6 +775,16 @@ k_solve_direct(int M, const int* __restrict__ dt_g0, const int* __restrict__ dt_
     sig_out[g] = acc;
     if (save_row) save_row[perm[g]] = acc;
   }
+}
+
+__global__ void __launch_bounds__(256)
+k_solve_direct(int M, const int* __restrict__ dt_g0, const int* __restrict__ dt_n, const int* __restrict__ dt_p0,
+               const int* __restrict__ pt_cs, const int* __restrict__ pt_cn, const int64_t* __restrict__ pt_inv,
+               const double* __restrict__ inv, const double* __restrict__ ginc, const double* __restrict__ loc,
+               const int* __restrict__ i0s, const double* __restrict__ iw, const double* __restrict__ beta,
+               const double* __restrict__ grid2, int nf, int width, double* __restrict__ sig_out,
+               double* __restrict__ save_row, const int* __restrict__ perm) {
+  k_solve_direct_body(M, dt_g0, dt_n, dt_p0, pt_cs, pt_cn, pt_inv, inv, ginc, loc, i0s, iw, beta, grid2, nf, width, sig_out, save_row, perm, blockIdx.x);
 }
 
 // Field at the receivers, one wavefront per receiver:
@@ -885,12 +931,11 @@ __device__ __forceinline__ double spread_cell(int cell, const double* __restrict
   return acc;
 }
 
-__global__ void __launch_bounds__(256)
-k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
+__device__ __forceinline__ void k_hist_a_body(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
          const int* __restrict__ ccount, const int64_t* __restrict__ woff, const double* __restrict__ sw,
-         const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex) {
+         const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex, int bid) {
   extern __shared__ double2 buf[];
-  const int n2 = f2.n, j1 = blockIdx.x;
+  const int n2 = f2.n, j1 = bid;
   const int n = n1 * n2;
   double* bd = (double*)buf;
   for (int c = threadIdx.x; c < 2 * n2; c += blockDim.x) {
@@ -907,6 +952,13 @@ k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* _
   }
 }
 
+__global__ void __launch_bounds__(256)
+k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
+         const int* __restrict__ ccount, const int64_t* __restrict__ woff, const double* __restrict__ sw,
+         const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex) {
+  k_hist_a_body(f2, n1, sig, M, cstart, ccount, woff, sw, tw, T1, ex, blockIdx.x);
+}
+
 constexpr int kFirGroups = 8;
 
 // Partner of position (c, k1) in the column pair: where Z_{n - q} sits, q = col[c] + n2 k1.
@@ -919,12 +971,11 @@ __device__ __forceinline__ int partner(int c, int k1, int k2c, int ncol, int n1)
 // mode 0: forward step 2 + modes + inverse step 1; mode 1: forward step 2 +
 // modes, writing y (the type-2 input) for a later projection; mode 2: inverse
 // step 1 from y.
-__global__ void __launch_bounds__(512)
-k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos, const double2* __restrict__ T1,
+__device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos, const double2* __restrict__ T1,
          const double2* __restrict__ tw, const double* __restrict__ dk1, const double* __restrict__ dk2,
          const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,
          double2* __restrict__ ring, double2* __restrict__ alpha, double2* __restrict__ dalpha,
-         double2* __restrict__ y, double2* __restrict__ V) {
+         double2* __restrict__ y, double2* __restrict__ V, int bid) {
   extern __shared__ double2 smb[];
   const int n1 = f1.n;
   const int n = n1 * n2;
@@ -932,7 +983,7 @@ k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos
   double2* yl = smb + 2 * n1;                 // [2][n1]
   double2* sS = smb + 4 * n1;                 // [2][n1]
   double4* red = (double4*)(smb + 6 * n1);    // [kFirGroups][2 n1]
-  const int k2a = blockIdx.x, k2b = (n2 - k2a) % n2;
+  const int k2a = bid, k2b = (n2 - k2a) % n2;
   const int ncol = (k2a == k2b) ? 1 : 2;
   const int np = ncol * n1;
   const int64_t stride = npos;
@@ -1037,15 +1088,29 @@ k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos
   }
 }
 
-__global__ void __launch_bounds__(256)
-k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
-         double2* __restrict__ grid2) {
+__global__ void __launch_bounds__(512)
+k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos, const double2* __restrict__ T1,
+         const double2* __restrict__ tw, const double* __restrict__ dk1, const double* __restrict__ dk2,
+         const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,
+         double2* __restrict__ ring, double2* __restrict__ alpha, double2* __restrict__ dalpha,
+         double2* __restrict__ y, double2* __restrict__ V) {
+  k_hist_b_body(mode, f1, n2, K, W, L, npos, T1, tw, dk1, dk2, pk, qk, rot, ring, alpha, dalpha, y, V, blockIdx.x);
+}
+
+__device__ __forceinline__ void k_hist_c_body(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
+         double2* __restrict__ grid2, int bid) {
   extern __shared__ double2 buf[];
-  const int n2 = f2.n, j1 = blockIdx.x;
+  const int n2 = f2.n, j1 = bid;
   for (int k2 = threadIdx.x; k2 < n2; k2 += blockDim.x) buf[k2] = cconj(V[(int64_t)j1 * n2 + k2]);
   __syncthreads();
   fft_batch(buf, 1, f2, tw, 2 * n1);
   for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) grid2[j1 + n1 * j2] = cconj(buf[j2]);
+}
+
+__global__ void __launch_bounds__(256)
+k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
+         double2* __restrict__ grid2) {
+  k_hist_c_body(f2, n1, V, tw, grid2, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1131,6 +1196,97 @@ __global__ void k_gather(int n, const int* __restrict__ idx, const double* __res
 __global__ void k_unsort(int M, const int* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < M) out[perm[j]] = in[j];
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: each stage of a level is one launch over a work list of
+// (instance, block) items; every item runs the single-instance kernel body
+// with its instance's descriptor.  The level index is read from device memory
+// so that a whole level can be captured once in a HIP graph and replayed.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) kb_incident(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  const Packets pk{d.npk, 1, d.packets};
+  k_incident_body(d.M, (double)(*b.level) * d.dt, d.xs, d.beta, pk, d.pp, 0, d.ginc, w.y);
+}
+
+__global__ void __launch_bounds__(512) kb_local(BatchLaunch b, int xcd) {
+  const int2 w = b.work[xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  k_local_rhs_body(d.M, d.NQ, d.NH, *b.level, 1, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, d.loc, w.y);
+}
+
+__global__ void __launch_bounds__(256) kb_hist_a(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  const double* sig = d.hist + (int64_t)mod_slot(*b.level - 1, d.NH) * d.M;
+  const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+  k_hist_a_body(d.f2, d.n1, sig, d.M, d.cstart, d.ccount, d.swoff, d.sw, d.tw, d.T1, none, w.y);
+}
+
+__global__ void __launch_bounds__(512) kb_hist_b(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  k_hist_b_body(0, d.f1, d.n2, d.K, d.W, *b.level, d.npos, d.T1, d.tw, d.dk1, d.dk2, d.pk, d.qk, d.rot, d.ring,
+                d.alpha, d.dalpha, d.ybuf, d.V, w.y);
+}
+
+__global__ void __launch_bounds__(256) kb_hist_c(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  k_hist_c_body(d.f2, d.n1, d.V, d.tw, (double2*)d.grid2, w.y);
+}
+
+__global__ void __launch_bounds__(256) kb_solve_direct(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
+  k_solve_direct_body(d.M, d.dt_g0, d.dt_n, d.dt_p0, d.pt_cs, d.pt_cn, d.pt_inv, d.inv, d.ginc, d.loc, d.i0s, d.iw,
+                      d.beta, d.grid2, d.nf, d.width, slot, nullptr, nullptr, w.y);
+}
+
+__global__ void __launch_bounds__(256) kb_solve(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
+  k_solve_body(d.M, d.iters, d.ext_max, d.tile_r0, d.tile_el, d.tile_g0, d.tile_left, d.tile_n, d.srow_g,
+               d.srow_dinv, d.srow_ptr, d.scol, d.sval, d.ginc, d.loc, d.i0s, d.iw, d.beta, d.grid2, d.nf, d.width,
+               slot, nullptr, nullptr, w.y);
+}
+
+__global__ void __launch_bounds__(256) kb_solve_rhs(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
+  k_solve_rhs_body(d.M, d.ginc, d.loc, d.beta, d.i0s, d.iw, d.grid2, d.nf, d.width, d.g_dinv, d.g_rhs,
+                   d.iters > 1 ? d.g_xa : slot, w.y);
+}
+
+// Sweep `it` (1-based) of the instances whose sweep count exceeds it; the
+// buffers alternate as in the single-instance solve and the last sweep writes
+// the history slot.
+__global__ void __launch_bounds__(256) kb_jacobi_sweep(BatchLaunch b, int it) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  if (it >= d.iters) return;
+  double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
+  const double* xin = (it & 1) ? d.g_xa : d.g_xb;
+  double* xout = (it == d.iters - 1) ? slot : ((it & 1) ? d.g_xb : d.g_xa);
+  k_jacobi_sweep_body(d.M, d.g_ptr, d.g_col, d.g_val, d.g_dinv, d.g_rhs, xin, xout, nullptr, nullptr, w.y);
+}
+
+__global__ void kb_advance(int64_t* level) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *level += 1;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,229 +1,9 @@
 // Plan creation, the level loop and the exported C ABI (include/wfp.h).
-#include <hip/hip_runtime.h>
+#include "wfp_internal.h"
 
-#include <algorithm>
-#include <array>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <functional>
-#include <numeric>
-#include <string>
-#include <vector>
-
-#include "../../include/wfp.h"
-#include "wfp_host.h"
-#include "wfp_kernels.h"
-
-using namespace wfp;
-
-namespace {
-
+namespace wfpi {
 thread_local std::string g_last_error;
-
-struct Error {
-  wfp_status code;
-  std::string msg;
-};
-
-#define HIPCHK(expr)                                                                    \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      throw Error{e_ == hipErrorOutOfMemory ? WFP_ENOMEM : WFP_EHIP,                    \
-                  std::string(#expr) + ": " + hipGetErrorString(e_)};                   \
-  } while (0)
-
-void fail(wfp_status c, const std::string& m) { throw Error{c, m}; }
-
-template <class T>
-T* dalloc(size_t n, int64_t& counter) {
-  T* p = nullptr;
-  if (n == 0) n = 1;
-  HIPCHK(hipMalloc(&p, n * sizeof(T)));
-  counter += (int64_t)(n * sizeof(T));
-  return p;
-}
-
-template <class T>
-void upload(T* d, const std::vector<T>& h, hipStream_t s) {
-  if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-}
-
-inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-
-// Same mode position as the device (see mode_pos in the kernels).
-int64_t mode_pos_host(int64_t q, int n1, int n2) {
-  const int k2 = (int)(q % n2), k1 = (int)(q / n2);
-  const int b = (k2 == 0) ? 0 : std::min(k2, n2 - k2);
-  const int c = (k2 == b) ? 0 : 1;
-  return (int64_t)b * 2 * n1 + c * n1 + k1;
-}
-
-// Inverse of a small dense matrix (row-major n x n) by Gauss-Jordan elimination
-// with partial pivoting in long double.
-void invert_dense(int n, const double* a, double* out) {
-  std::vector<long double> m((size_t)n * 2 * n, 0.0L);
-  for (int i = 0; i < n; ++i) {
-    for (int j = 0; j < n; ++j) m[(size_t)i * 2 * n + j] = a[(size_t)i * n + j];
-    m[(size_t)i * 2 * n + n + i] = 1.0L;
-  }
-  for (int c = 0; c < n; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < n; ++r)
-      if (std::fabs((double)m[(size_t)r * 2 * n + c]) > std::fabs((double)m[(size_t)piv * 2 * n + c])) piv = r;
-    if (m[(size_t)piv * 2 * n + c] == 0.0L) fail(WFP_EDOMAIN, "singular per-step system");
-    if (piv != c)
-      for (int j = 0; j < 2 * n; ++j) std::swap(m[(size_t)piv * 2 * n + j], m[(size_t)c * 2 * n + j]);
-    const long double d = m[(size_t)c * 2 * n + c];
-    for (int j = 0; j < 2 * n; ++j) m[(size_t)c * 2 * n + j] /= d;
-    for (int r = 0; r < n; ++r) {
-      if (r == c) continue;
-      const long double f = m[(size_t)r * 2 * n + c];
-      if (f == 0.0L) continue;
-      for (int j = 0; j < 2 * n; ++j) m[(size_t)r * 2 * n + j] -= f * m[(size_t)c * 2 * n + j];
-    }
-  }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) out[(size_t)i * n + j] = (double)m[(size_t)i * 2 * n + n + j];
-}
-
-FftPlan make_fft_plan(int64_t n) {
-  FftPlan fp{};
-  fp.n = (int)n;
-  std::vector<int> r = radix_sequence(n);
-  if ((int)r.size() > kMaxFftStages) fail(WFP_EDOMAIN, "FFT length has too many stages");
-  fp.nst = (int)r.size();
-  for (size_t i = 0; i < r.size(); ++i) fp.radix[i] = r[i];
-  for (int R : r)
-    if (n / R > (int64_t)kFftMaxB * kFftThreads) fail(WFP_EDOMAIN, "FFT length too large for one workgroup");
-  return fp;
-}
-
-}  // namespace
-
-struct wfp_plan {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int64_t dev_bytes = 0;
-  // sizes and parameters
-  int64_t M = 0, R = 0, K = 0, level = 0, n_pairs = 0, n_pairs_recv = 0;
-  int boundary = 0, W = 0, p = 0, NQ = 0, NH = 0, ngl = 0, ngpq = 0, rbc_period = 0, width = 0, iters = 0;
-  int nf = 0, nfh = 0, ncheb = 0, T = 256, ntile = 0, ext_max = 0, npk = 0;
-  double dt = 0, delta = 0, b = 0, hf = 0, alpha_es = 0, beta_es = 0, h_rbc = 0, delta_s = 0, contraction = 0;
-  FftPlan fft_nf{}, fft_rbc{}, fft_n1{}, fft_n2{};
-  int n1 = 0, n2 = 0;           // four-step split of the half-length transform
-  int64_t npos = 0;             // length of the per-mode arrays (mode-position order)
-  double2 *T1 = nullptr, *V = nullptr;
-  size_t lds_rbc = 0, lds_jac = 0, lds_qw = 0;
-  std::vector<int> perm_h;
-  // device buffers
-  double *xs = nullptr, *beta = nullptr, *xr = nullptr, *packets = nullptr;
-  int* perm = nullptr;
-  double* hist = nullptr;
-  double2 *ring = nullptr, *alpha = nullptr, *dalpha = nullptr;
-  double *pk = nullptr, *qk = nullptr, *rot = nullptr, *dk1 = nullptr, *dk2 = nullptr;
-  double2* tw = nullptr;
-  double2* tw_rbc = nullptr;
-  double2* ybuf = nullptr;
-  double* grid2 = nullptr;
-  double *rbc_u = nullptr, *rbc_v = nullptr;
-  int *cstart = nullptr, *ccount = nullptr;
-  int *nb_start = nullptr, *nb_count = nullptr;
-  int64_t* qoff = nullptr;
-  double* Q = nullptr;          // dense weights of the scatterer rows (plan set-up only)
-  double* Qc = nullptr;         // packed weights of lags >= 1
-  unsigned* ac = nullptr;       // per (row, lag) source range a | c << 16
-  uint2* acx = nullptr;         // per (row, lag): (a | c << 16, packed offset within the row)
-  int nqd = 0;                  // quads of lags per row (local-sum tasks per row)
-  int64_t* rowbase = nullptr;   // packed offset of each row
-  double* ginc = nullptr;       // -g_j(t_L), per row
-  double* loc = nullptr;        // local sum of lags >= 1, per row
-  // solve tiles
-  int *tile_r0 = nullptr, *tile_el = nullptr, *tile_g0 = nullptr, *tile_left = nullptr, *tile_n = nullptr;
-  int *srow_g = nullptr, *srow_ptr = nullptr, *scol = nullptr;
-  double *srow_dinv = nullptr, *sval = nullptr;
-  int solve_threads = 64;
-  // global-sweep solve (when tiles do not fit in LDS)
-  bool solve_global = false;
-  int *g_ptr = nullptr, *g_col = nullptr;
-  double *g_val = nullptr, *g_dinv = nullptr, *g_rhs = nullptr, *g_xa = nullptr, *g_xb = nullptr;
-  // direct solve of small runs
-  int n_direct_tiles = 0;
-  int *dt_g0 = nullptr, *dt_n = nullptr, *dt_p0 = nullptr, *pt_cs = nullptr, *pt_cn = nullptr;
-  int64_t* pt_inv = nullptr;
-  double* inv = nullptr;
-  // precomputed spreading / interpolation weights
-  int64_t* swoff = nullptr;
-  double* sw = nullptr;
-  int *i0s = nullptr, *ri0s = nullptr;
-  double *iw = nullptr, *riw = nullptr;
-  int *rnb_start = nullptr, *rnb_count = nullptr;
-  int64_t* rqoff = nullptr;
-  double* Qr = nullptr;
-  double *cheb_phi = nullptr, *cheb_g = nullptr;
-  int64_t n_weights_nonzero = 0, n_weights_stored = 0;
-  // host copies kept for the gradient pass set-up
-  std::vector<double> xs_h, xr_h;
-  std::vector<int> nbc_h, rnbs_h, rnbc_h;
-  std::vector<int64_t> rqoff_h;
-  int64_t dense_total = 0;
-  double *glz_d = nullptr, *glw_d = nullptr, *lagw_d = nullptr;
-  // checkpoints of the current run (state at levels c * ckpt_every, c >= 1)
-  int ckpt_every = 0;
-  bool ck_from0 = true;          // the levels run so far started from level 0
-  std::vector<char*> ckpts;
-  size_t ckpt_bytes = 0;
-  // gradient pass: replay and adjoint states, per-segment buffers
-  bool grad_ready = false, gradx_ready = false;
-  double *rhist = nullptr, *ahist = nullptr;
-  double2 *rring = nullptr, *ralpha = nullptr, *rdalpha = nullptr;
-  double2 *aring = nullptr, *aalpha = nullptr, *adalpha = nullptr;
-  double *segsig = nullptr, *segD = nullptr, *gb_acc = nullptr, *gx_acc = nullptr;
-  double *xloc = nullptr, *xw = nullptr, *fprime = nullptr, *gridd = nullptr, *esort = nullptr;
-  double2* yd = nullptr;
-  int *adj_ptr = nullptr, *adj_rr = nullptr, *adj_ri = nullptr;
-  int *rsort = nullptr, *rcs = nullptr, *rcc = nullptr;
-  int64_t* rwo = nullptr;
-  double* rsw = nullptr;
-  double* DQa = nullptr;         // signed derivative weights, lags >= 0, packed by row
-  int64_t* drowbase = nullptr;
-  uint2* acxd = nullptr;
-  double* dQr = nullptr;         // receivers' signed derivative weights, layout of Qr
-  std::vector<void*> owned;
-  // per-stage event timing
-  bool profiling = false;
-  double prof_ms[WFP_N_STAGES] = {};
-  int64_t prof_n[WFP_N_STAGES] = {};
-  struct Pending {
-    int stage;
-    hipEvent_t a, b;
-  };
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> free_events;
-
-  ~wfp_plan() {
-    for (auto& q : pending) {
-      (void)hipEventDestroy(q.a);
-      (void)hipEventDestroy(q.b);
-    }
-    for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
-    for (void* ptr : owned) (void)hipFree(ptr);
-  }
-  void release(void* ptr) {
-    for (auto& o : owned)
-      if (o == ptr) {
-        (void)hipFree(o);
-        o = nullptr;
-      }
-  }
-  template <class T>
-  T* alloc(size_t n) {
-    T* ptr = dalloc<T>(n, dev_bytes);
-    owned.push_back(ptr);
-    return ptr;
-  }
-};
+}  // namespace wfpi
 
 namespace {
 
@@ -1426,6 +1206,10 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
   HIPCHK(hipGetLastError());
 }
 
+
+}  // namespace
+
+namespace wfpi {
 wfp_status guard(const std::function<void()>& f) {
   try {
     f();
@@ -1441,8 +1225,7 @@ wfp_status guard(const std::function<void()>& f) {
     return WFP_EHIP;
   }
 }
-
-}  // namespace
+}  // namespace wfpi
 
 extern "C" {
 

@@ -87,6 +87,22 @@ def load_library():
     lib.wfp_get_profile.restype = ctypes.c_int32
     lib.wfp_reset.argtypes = [vp]
     lib.wfp_reset.restype = ctypes.c_int32
+    lib.wfp_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.POINTER(Params), vp,
+                                     ctypes.POINTER(vp)]
+    lib.wfp_batch_create.restype = ctypes.c_int32
+    lib.wfp_batch_run.argtypes = [vp, ctypes.c_int64, vp]
+    lib.wfp_batch_run.restype = ctypes.c_int32
+    lib.wfp_batch_reset.argtypes = [vp]
+    lib.wfp_batch_reset.restype = ctypes.c_int32
+    lib.wfp_batch_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]
+    lib.wfp_batch_autotune.restype = ctypes.c_int32
+    lib.wfp_batch_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    lib.wfp_batch_size.restype = ctypes.c_int32
+    lib.wfp_batch_plan.argtypes = [vp, ctypes.c_int32]
+    lib.wfp_batch_plan.restype = vp
+    lib.wfp_batch_destroy.argtypes = [vp]
+    lib.wfp_batch_destroy.restype = None
     lib.wfp_status_string.argtypes = [ctypes.c_int32]
     lib.wfp_status_string.restype = ctypes.c_char_p
     lib.wfp_last_error.argtypes = []
@@ -132,6 +148,23 @@ def _current_stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _fill_problem(pr, problem, keep):
+    x = np.ascontiguousarray(problem["x"], dtype=np.float64)
+    beta = np.ascontiguousarray(problem["beta"], dtype=np.float64)
+    packets = np.ascontiguousarray(np.atleast_2d(problem["packets"]), dtype=np.float64)
+    xr = problem.get("x_recv")
+    xr = np.zeros(0) if xr is None else np.ascontiguousarray(xr, dtype=np.float64)
+    keep += [x, beta, packets, xr]
+    pr.M = x.size
+    pr.x = _dbl(x)
+    pr.beta = _dbl(beta)
+    pr.boundary = int(problem.get("boundary", PERIODIC))
+    pr.n_packets = packets.shape[0]
+    pr.packets = _dbl(packets)
+    pr.R = xr.size
+    pr.x_recv = _dbl(xr)
+
+
 class Plan:
     """A WFP plan on the current device (all precompute done at construction).
 
@@ -143,21 +176,9 @@ class Plan:
         lib = load_library()
         self._lib = lib
         self._keep = []
-        x = np.ascontiguousarray(problem["x"], dtype=np.float64)
-        beta = np.ascontiguousarray(problem["beta"], dtype=np.float64)
-        packets = np.ascontiguousarray(np.atleast_2d(problem["packets"]), dtype=np.float64)
-        xr = problem.get("x_recv")
-        xr = np.zeros(0) if xr is None else np.ascontiguousarray(xr, dtype=np.float64)
-        self._keep += [x, beta, packets, xr]
+        self._owned = True
         pr = Problem()
-        pr.M = x.size
-        pr.x = _dbl(x)
-        pr.beta = _dbl(beta)
-        pr.boundary = int(problem.get("boundary", PERIODIC))
-        pr.n_packets = packets.shape[0]
-        pr.packets = _dbl(packets)
-        pr.R = xr.size
-        pr.x_recv = _dbl(xr)
+        _fill_problem(pr, problem, self._keep)
         prm = make_params(dt, **params)
         self._stream = stream if stream is not None else _current_stream()
         h = ctypes.c_void_p()
@@ -238,9 +259,90 @@ class Plan:
     def reset(self):
         _check(self._lib.wfp_reset(self._h))
 
+    @classmethod
+    def _borrow(cls, lib, handle):
+        """A non-owning view of a plan that belongs to a batch."""
+        p = cls.__new__(cls)
+        p._lib = lib
+        p._keep = []
+        p._owned = False
+        p._h = ctypes.c_void_p(handle)
+        p.info = p.query_info()
+        return p
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value and getattr(self, "_owned", True):
+            self._lib.wfp_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent periodic problems marched in lockstep (wfp_batch_*).
+
+    problems: list of dicts as for Plan (no receivers), dts: list of time
+    steps, keyword parameters shared by every instance.
+    """
+
+    def __init__(self, problems, dts, stream=None, **params):
+        lib = load_library()
+        self._lib = lib
+        self._keep = []
+        n = len(problems)
+        probs = (Problem * n)()
+        pars = (Params * n)()
+        for i, (pb, dt) in enumerate(zip(problems, dts)):
+            _fill_problem(probs[i], pb, self._keep)
+            pars[i] = make_params(dt, **params)
+        self._keep += [probs, pars]
+        self.n = n
+        self._stream = stream if stream is not None else _current_stream()
+        h = ctypes.c_void_p()
+        _check(lib.wfp_batch_create(n, probs, pars, self._stream, ctypes.byref(h)))
+        self._h = h
+        self.sizes = [int(np.asarray(p["x"]).size) for p in problems]
+
+    @property
+    def level(self):
+        lvl = ctypes.c_int64()
+        _check(self._lib.wfp_batch_size(self._h, None, ctypes.byref(lvl)))
+        return lvl.value
+
+    def run(self, n_steps, sigma_final=None):
+        """March n_steps levels; sigma_final: list of float64 CUDA tensors [M_i] (or None)."""
+        arr = None
+        if sigma_final is not None:
+            arr = (ctypes.c_void_p * self.n)()
+            for i, t in enumerate(sigma_final):
+                if t is not None:
+                    assert t.is_cuda and t.is_contiguous() and t.element_size() == 8 and t.numel() >= self.sizes[i]
+                    arr[i] = t.data_ptr()
+        _check(self._lib.wfp_batch_run(self._h, int(n_steps), arr))
+
+    def reset(self):
+        _check(self._lib.wfp_batch_reset(self._h))
+
+    def autotune(self, trial_levels=5):
+        r = ctypes.c_int32()
+        x = ctypes.c_int32()
+        _check(self._lib.wfp_batch_autotune(self._h, int(trial_levels), ctypes.byref(r), ctypes.byref(x)))
+        return r.value, x.value
+
+    def plan(self, i):
+        """Instance i's plan (borrowed: valid while the batch lives)."""
+        h = self._lib.wfp_batch_plan(self._h, int(i))
+        if not h:
+            raise WFPError(WFP_EINVAL, self._lib.wfp_last_error().decode())
+        return Plan._borrow(self._lib, h)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
-            self._lib.wfp_plan_destroy(self._h)
+            self._lib.wfp_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

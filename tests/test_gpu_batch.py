@@ -1,0 +1,135 @@
+"""The batched form (wfp_batch_*): every instance of a batch computes what its
+own plan computes (same kernel bodies and reduction order; inlined into the
+batched kernels the compiler contracts some multiply-adds differently, so the
+two agree to rounding -- ~5e-14 after 137 levels -- not bitwise; the bar here is
+rho <= 1e-12), one small instance is also checked against the oracle, and
+the autotuned launch shape does not change any result (bitwise: the same
+batched kernels run, only their block shape changes)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.march import Oracle, incident_driving
+from oracle.params import Params
+from paper_2507_07823_amd import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def rho(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    m = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / m) if m > 0 else float(np.max(np.abs(a)))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def wfp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2507_07823_amd import wfp as w
+    w.load_library()
+    return w
+
+
+def _instances():
+    """Uneven instances: the small parity case, random springs at three time
+    steps (different K and fine grids), and a dense cluster that takes the
+    global-sweep solve."""
+    out = [workloads.small_periodic()]
+    rng = np.random.default_rng(31)
+    for i, (M, dt) in enumerate([(300, 5e-3), (1200, 2e-3), (57, 1e-2), (2500, 1e-3)]):
+        x = rng.uniform(-np.pi + 1.2, np.pi, M)
+        beta = rng.uniform(1.0, 10.0, M)
+        out.append(dict(x=x, beta=beta, packets=np.array([[1.0, -np.pi + 0.6, 0.05 + 0.01 * i, 0.0, 0.0]]),
+                        boundary=0, dt=dt))
+    x = rng.uniform(0.5, 0.51, 400)
+    out.append(dict(x=x, beta=rng.uniform(0.1, 1.0, 400), packets=np.array([[1.0, 0.2, 0.03, 0.0, 0.0]]),
+                    boundary=0, dt=1e-3))
+    for p in out:
+        p["x_recv"] = np.zeros(0)
+    return out
+
+
+def _plain(w, p, n):
+    import torch
+    plan = w.Plan(p, p["dt"])
+    sig = torch.empty((n, p["x"].size), dtype=torch.float64, device="cuda")
+    plan.run(n, sig, 1)
+    st = plan.get_state()
+    torch.cuda.synchronize()
+    out = sig[-1].cpu().numpy(), {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in st.items()}, plan.info
+    plan.close()
+    return out
+
+
+def _batch_run(b, insts, n):
+    import torch
+    fin = [torch.empty(p["x"].size, dtype=torch.float64, device="cuda") for p in insts]
+    b.run(n, fin)
+    torch.cuda.synchronize()
+    return [f.cpu().numpy() for f in fin]
+
+
+def test_batch_matches_plain_plans(wfp):
+    import torch
+    insts = _instances()
+    n = 137
+    say(f"batch: {len(insts)} instances, M = {[p['x'].size for p in insts]}, levels {n}")
+    b = wfp.Batch(insts, [p["dt"] for p in insts])
+    fin = _batch_run(b, insts, n)
+    assert b.level == n
+    modes = []
+    worst = 0.0
+    for i, p in enumerate(insts):
+        last, st, info = _plain(wfp, p, n)
+        modes.append(info["solve_mode"])
+        bst = b.plan(i).get_state()
+        torch.cuda.synchronize()
+        errs = {"sigma": rho(fin[i], last)}
+        for k in ("hist", "ring", "alpha", "dalpha"):
+            errs[k] = rho(bst[k].cpu().numpy(), st[k])
+        say(f"  instance {i} (M={p['x'].size}, dt={p['dt']:g}, solve_mode={info['solve_mode']}): "
+            + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+        worst = max(worst, max(errs.values()))
+        assert bst["L"] == st["L"] == n
+    assert worst <= TOL
+    assert 1 in modes and 0 in modes          # both solve paths are exercised
+    b.close()
+
+
+def test_batch_instance_against_oracle(wfp):
+    insts = _instances()
+    n = 200
+    b = wfp.Batch(insts, [p["dt"] for p in insts])
+    fin = _batch_run(b, insts, n)
+    b.close()
+    p = insts[0]
+    o = Oracle(p["x"], p["beta"], Params(dt=p["dt"]), incident_driving(p["x"], p["beta"], p["packets"], True))
+    ref, _ = o.run(n)
+    err = float(np.max(np.abs(fin[0] - ref[-1])) / np.max(np.abs(ref)))
+    say(f"batch instance 0 vs oracle at level {n - 1}: rho = {err:.2e}")
+    assert err < 1e-10
+
+
+def test_autotune_and_reset_keep_results(wfp):
+    insts = _instances()
+    n = 60
+    b = wfp.Batch(insts, [p["dt"] for p in insts])
+    first = _batch_run(b, insts, n)
+    b.reset()
+    assert b.level == 0
+    shape = b.autotune(3)
+    say(f"autotuned local-sum shape: rows per block {shape[0]}, xcd remap {shape[1]}")
+    assert shape[0] in (4, 8) and shape[1] in (0, 1)
+    assert b.level == 0
+    again = _batch_run(b, insts, n)
+    for a, c in zip(first, again):
+        assert np.array_equal(a, c)
+    b.close()
