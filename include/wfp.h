@@ -92,6 +92,12 @@ typedef struct {
   int32_t solve_iters;     /* Jacobi sweeps of the per-step solve            [from a contraction bound] */
   int32_t checkpoint_every;/* > 0: wfp_run stores the march state every this many levels (for
                               wfp_adjoint); 0: no checkpoints                [0] */
+  int32_t overlap_cus;     /* > 0: wfp_run puts the history chain (spread, FFTs, modes) on its
+                              own stream restricted to the first overlap_cus compute units,
+                              concurrent with the local sum on the others (results are the same
+                              bit for bit); < 0: one stream; 0: the library's choice, which is
+                              one XCD's compute units when the local sum reads at least 64 MB
+                              per level, else one stream                          [0] */
 } wfp_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -104,7 +110,7 @@ typedef struct {
   int64_t n_weights_stored;    /* stored local weights of lag >= 1 (scatterer rows) */
   int32_t solve_mode;          /* 0: dense inverses of small nearby-runs and LDS tiles,
                                   1: global Jacobi sweeps (dense nearby coupling) */
-  int32_t reserved;
+  int32_t overlap_cus;         /* compute units of the concurrent history chain, -1: one stream */
 } wfp_info;
 
 /* Stages of one level, for wfp_get_profile. */

@@ -280,7 +280,10 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
     HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
     for (int32_t i = 0; i < n; ++i) {
       wfp_plan* P = nullptr;
-      const wfp_status s = wfp_plan_create(&probs[i], &pars[i], B->bs, &P);
+      // the batch overlaps instances instead of streams: one stream per plan
+      wfp_params pi = pars[i];
+      pi.overlap_cus = -1;
+      const wfp_status s = wfp_plan_create(&probs[i], &pi, B->bs, &P);
       if (s != WFP_OK) throw Error{s, "instance " + std::to_string(i) + ": " + g_last_error};
       B->plans.push_back(P);
     }

@@ -152,6 +152,10 @@ struct wfp_plan {
   int *srow_g = nullptr, *srow_ptr = nullptr, *scol = nullptr;
   double *srow_dinv = nullptr, *sval = nullptr;
   int solve_threads = 64;
+  // concurrent history chain: masked streams for the chain (sb) and the rest (sa)
+  int overlap_cus = 0;
+  hipStream_t sa = nullptr, sb = nullptr;
+  hipEvent_t ev_solved = nullptr, ev_chain = nullptr, ev_join = nullptr;
   // global-sweep solve (when tiles do not fit in LDS)
   bool solve_global = false;
   int *g_ptr = nullptr, *g_col = nullptr;
@@ -211,6 +215,11 @@ struct wfp_plan {
   std::vector<hipEvent_t> free_events;
 
   ~wfp_plan() {
+    // sa and sb are shared by every plan on the device (never destroyed)
+    if (sa) (void)hipStreamSynchronize(sa);
+    if (sb) (void)hipStreamSynchronize(sb);
+    for (hipEvent_t e : {ev_solved, ev_chain, ev_join})
+      if (e) (void)hipEventDestroy(e);
     for (auto& q : pending) {
       (void)hipEventDestroy(q.a);
       (void)hipEventDestroy(q.b);

@@ -1,6 +1,9 @@
 // Plan creation, the level loop and the exported C ABI (include/wfp.h).
 #include "wfp_internal.h"
 
+#include <map>
+#include <mutex>
+
 namespace wfpi {
 thread_local std::string g_last_error;
 }  // namespace wfpi
@@ -161,6 +164,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   P->M = M;
   P->R = prob->R;
   P->ckpt_every = par->checkpoint_every;
+  P->overlap_cus = par->overlap_cus;
   P->boundary = prob->boundary;
   P->dt = par->dt;
   const double eps = par->eps_window > 0 ? par->eps_window : 1e-12;
@@ -829,6 +833,49 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   HIPCHK(hipFuncSetAttribute((const void*)k_hist_b, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   if (6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4) > 160 * 1024)
     fail(WFP_EDOMAIN, "four-step factor n1 too long for the history kernel's LDS");
+  {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, P->device));
+    const int ncu = prop.multiProcessorCount;
+    if (P->overlap_cus == 0) {
+      // the chain on one XCD (its own L2) while the local sum streams its
+      // weights on the others, when the local sum is long enough to hide it
+      int nx = 1;
+      if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, P->device) != hipSuccess || nx < 2) nx = 1;
+      const bool worth = 8.0 * (double)P->n_weights_stored >= 64.0 * 1024 * 1024;
+      P->overlap_cus = (nx > 1 && worth) ? ncu / nx : -1;
+    }
+  }
+  if (P->overlap_cus > 0) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, P->device));
+    const int ncu = prop.multiProcessorCount;
+    if (P->overlap_cus >= ncu) fail(WFP_EINVAL, "overlap_cus must be below the number of compute units");
+    const int words = (ncu + 31) / 32;
+    std::vector<uint32_t> ma(words, 0u), mb(words, 0u);
+    for (int c = 0; c < ncu; ++c) {
+      if (c < P->overlap_cus) mb[c / 32] |= 1u << (c % 32);
+      else ma[c / 32] |= 1u << (c % 32);
+    }
+    // one pair of masked streams per (device, split), shared by all plans and
+    // kept until the process ends: each masked stream holds a hardware queue
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, std::pair<hipStream_t, hipStream_t>> pool;
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(P->device, P->overlap_cus);
+    auto it = pool.find(key);
+    if (it == pool.end()) {
+      hipStream_t a = nullptr, b = nullptr;
+      HIPCHK(hipExtStreamCreateWithCUMask(&a, (uint32_t)words, ma.data()));
+      HIPCHK(hipExtStreamCreateWithCUMask(&b, (uint32_t)words, mb.data()));
+      it = pool.emplace(key, std::make_pair(a, b)).first;
+    }
+    P->sa = it->second.first;
+    P->sb = it->second.second;
+    HIPCHK(hipEventCreateWithFlags(&P->ev_solved, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_chain, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+  }
   zero_state(P);
   HIPCHK(hipStreamSynchronize(s));
 }
@@ -849,8 +896,13 @@ StateRef main_state(wfp_plan* P) { return {P->hist, P->ring, P->alpha, P->dalpha
 // holds it), local sum (levels < L), the history part (three kernels; the
 // free-space projection when due), solve, receivers.
 void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const ExtraSources& ex, double* save,
-                 double* u_recv_row) {
-  hipStream_t s = P->stream;
+                 double* u_recv_row, bool overlap = false) {
+  // overlap: the history chain on P->sb (its own compute units) after the
+  // previous level's solve and receivers, everything else on P->sa; the solve
+  // waits for both.
+  hipStream_t s = overlap ? P->sa : P->stream;
+  hipStream_t sc = overlap ? P->sb : s;
+  if (overlap) HIPCHK(hipStreamWaitEvent(sc, P->ev_solved, 0));
   const bool periodic = P->boundary == WFP_PERIODIC;
   // a multiple of 8 blocks, so the XCD-aware block remap is a bijection
   const int nlocblk = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
@@ -871,32 +923,36 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
                        P->nb_start, P->rowbase, P->acx, P->Qc, S.hist, P->loc);
   }
   {
-    StageTimer st(P, WFP_STAGE_SPREAD, s);
-    hipLaunchKernelGGL(k_hist_a, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, sig_prev,
+    StageTimer st(P, WFP_STAGE_SPREAD, sc);
+    hipLaunchKernelGGL(k_hist_a, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), sc, P->fft_n2, P->n1, sig_prev,
                        (int)P->M, P->cstart, P->ccount, P->swoff, P->sw, P->tw, P->T1, ex);
   }
   const bool rbc = !periodic && L > 0 && L % P->rbc_period == 0;
   {
-    StageTimer st(P, WFP_STAGE_MODES, s);
-    hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, rbc ? 1 : 0, P->fft_n1, P->n2, P->K, P->W, L,
+    StageTimer st(P, WFP_STAGE_MODES, sc);
+    hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, sc, rbc ? 1 : 0, P->fft_n1, P->n2, P->K, P->W, L,
                        P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha,
                        P->ybuf, P->V);
   }
   if (rbc) {
-    StageTimer st(P, WFP_STAGE_RBC, s);
-    hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->n1, P->n2,
+    StageTimer st(P, WFP_STAGE_RBC, sc);
+    hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, sc, P->fft_rbc, P->K, P->n1, P->n2,
                        S.alpha, S.dalpha, P->tw_rbc, (double2*)P->rbc_u, (double2*)P->rbc_v);
-    hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, s, P->fft_rbc, P->K, P->n1, P->n2,
+    hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, sc, P->fft_rbc, P->K, P->n1, P->n2,
                        P->W, P->h_rbc, P->delta_s, P->cheb_phi, P->cheb_g, P->ncheb, P->rbc_u, P->rbc_v,
                        P->tw_rbc, P->dk2, S.alpha, S.dalpha, P->ybuf);
-    hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, L, P->npos,
+    hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, sc, 2, P->fft_n1, P->n2, P->K, P->W, L, P->npos,
                        P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha, P->ybuf,
                        P->V);
   }
   {
-    StageTimer st(P, WFP_STAGE_FFT_INV, s);
-    hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, P->V,
+    StageTimer st(P, WFP_STAGE_FFT_INV, sc);
+    hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), sc, P->fft_n2, P->n1, P->V,
                        P->tw, (double2*)P->grid2);
+  }
+  if (overlap) {
+    HIPCHK(hipEventRecord(P->ev_chain, sc));
+    HIPCHK(hipStreamWaitEvent(s, P->ev_chain, 0));
   }
   double* slot = S.hist + (int64_t)(L % P->NH) * P->M;
   {
@@ -933,6 +989,8 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
                        (int)P->M, P->NQ, P->NH, L, P->rnb_start, P->rnb_count, P->rqoff, P->Qr, S.hist,
                        P->ri0s, P->riw, P->grid2, P->nf, P->width, u_recv_row);
   }
+  // the next level's chain overwrites grid2, read by the solve and receivers above
+  if (overlap) HIPCHK(hipEventRecord(P->ev_solved, s));
 }
 
 size_t state_bytes(const wfp_plan* P) {
@@ -968,6 +1026,14 @@ void zero_state_ref(wfp_plan* P, const StateRef& S) {
 void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, double* u_recv_out) {
   const StateRef S = main_state(P);
   const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+  // the concurrent chain is used when configured and no checkpoints are taken
+  const bool ov = P->overlap_cus > 0 && P->ckpt_every == 0 && n > 0;
+  if (ov) {
+    // order after earlier work on the caller's stream
+    HIPCHK(hipEventRecord(P->ev_join, P->stream));
+    HIPCHK(hipStreamWaitEvent(P->sa, P->ev_join, 0));
+    HIPCHK(hipEventRecord(P->ev_solved, P->sa));
+  }
   for (int64_t i = 0; i < n; ++i) {
     const int64_t L = P->level + i;
     if (P->ckpt_every > 0 && P->ck_from0 && L > 0 && L % P->ckpt_every == 0) {
@@ -976,7 +1042,12 @@ void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, d
       copy_state(P, S, P->ckpts[c], true);
     }
     double* save = (sigma_out && i % save_every == 0) ? sigma_out + (i / save_every) * P->M : nullptr;
-    march_level(P, S, L, false, none, save, u_recv_out ? u_recv_out + i * P->R : nullptr);
+    march_level(P, S, L, false, none, save, u_recv_out ? u_recv_out + i * P->R : nullptr, ov);
+  }
+  if (ov) {
+    // later work on the caller's stream waits for the whole run
+    HIPCHK(hipEventRecord(P->ev_join, P->sa));
+    HIPCHK(hipStreamWaitEvent(P->stream, P->ev_join, 0));
   }
   HIPCHK(hipGetLastError());
   P->level += n;
@@ -1286,6 +1357,7 @@ wfp_status wfp_plan_info(const wfp_plan* P, wfp_info* info) {
   info->n_weights_nonzero = P->n_weights_nonzero;
   info->n_weights_stored = P->n_weights_stored;
   info->solve_mode = P->solve_global ? 1 : 0;
+  info->overlap_cus = P->overlap_cus;
   return WFP_OK;
 }
 

@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
                 ("W", ctypes.c_int32), ("p", ctypes.c_int32), ("K", ctypes.c_int64),
                 ("n_gl_local", ctypes.c_int32), ("n_gl_pq", ctypes.c_int32), ("rbc_period", ctypes.c_int32),
                 ("nufft_width", ctypes.c_int32), ("solve_iters", ctypes.c_int32),
-                ("checkpoint_every", ctypes.c_int32)]
+                ("checkpoint_every", ctypes.c_int32), ("overlap_cus", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -49,7 +49,7 @@ class Info(ctypes.Structure):
                 ("solve_iters", ctypes.c_int32), ("boundary", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("delta", ctypes.c_double), ("b", ctypes.c_double), ("solve_contraction", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("n_weights_nonzero", ctypes.c_int64),
-                ("n_weights_stored", ctypes.c_int64), ("solve_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_weights_stored", ctypes.c_int64), ("solve_mode", ctypes.c_int32), ("overlap_cus", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -248,3 +248,25 @@ def test_dense_cluster_global_solve(wfp):
     e1, e2 = rho(sig, ref), rho(u, uref)
     say(f"  rho(sigma) = {e1:.2e}  rho(u) = {e2:.2e}")
     assert e1 < TOL and e2 < TOL
+
+
+def test_concurrent_chain_is_bitwise_identical(wfp):
+    """The history chain on its own compute units (overlap_cus > 0) computes
+    exactly what the single-stream level computes, receivers included."""
+    import torch
+    p = workloads.multiband_periodic()
+    p = dict(p, x_recv=np.linspace(-1.0, 2.0, 8))
+    n = 300
+    out = []
+    for cus in (-1, 32):
+        plan = wfp.Plan(p, p["dt"], overlap_cus=cus)
+        assert plan.info["overlap_cus"] == cus
+        sig, u = plan.march(n, 7)
+        torch.cuda.synchronize()
+        out.append((sig.cpu().numpy(), u.cpu().numpy()))
+        plan.close()
+    say(f"concurrent chain: M={p['x'].size} levels={n}")
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    plan = wfp.Plan(p, p["dt"])
+    say(f"  library choice: overlap_cus = {plan.info['overlap_cus']}")
+    plan.close()
