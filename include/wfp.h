@@ -98,6 +98,10 @@ typedef struct {
                               bit for bit); < 0: one stream; 0: the library's choice, which is
                               one XCD's compute units when the local sum reads at least 64 MB
                               per level, else one stream                          [0] */
+  int32_t local_mode;      /* 1: local weights stored per pair (read every level); 2: evaluated on the
+                              fly every level (memory O(M), arithmetic O(pairs N_L p)); 0: stored when
+                              they fit in 60% of the free device memory, else on the fly   [0] */
+  int32_t reserved;
 } wfp_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -111,6 +115,8 @@ typedef struct {
   int32_t solve_mode;          /* 0: dense inverses of small nearby-runs and LDS tiles,
                                   1: global Jacobi sweeps (dense nearby coupling) */
   int32_t overlap_cus;         /* compute units of the concurrent history chain, -1: one stream */
+  int32_t local_mode;          /* 1: stored local weights, 2: evaluated on the fly */
+  int32_t reserved;
 } wfp_info;
 
 /* Stages of one level, for wfp_get_profile. */
@@ -148,6 +154,14 @@ wfp_status wfp_plan_info(const wfp_plan* plan, wfp_info* info);
  * Asynchronous on the plan's stream.  Errors: WFP_EINVAL, WFP_EHIP. */
 wfp_status wfp_run(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t save_every,
                    double* u_recv_out);
+
+/* The explicit local part at the springs for the next level L (the plan's
+ * level), eqs. (localSol1)/(localSol2) without the implicit lag 0:
+ *   out[j] = sum_{m>=1} sum_{l: d_jl < delta} (1/2) Q_m(d_jl) sigma_l^{L-m}
+ * from the current density history.  out: device [M], caller order.  Useful
+ * to check the local sum on its own (e.g. after wfp_set_state).
+ * Asynchronous on the plan's stream.  Errors: WFP_EINVAL, WFP_EHIP. */
+wfp_status wfp_local_part(wfp_plan* plan, double* out);
 
 /* Gradient of a receiver loss J(u) through the march (not in the paper: the
  * transpose of every step of Section 4.2, run backwards in time).

@@ -283,6 +283,7 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
       // the batch overlaps instances instead of streams: one stream per plan
       wfp_params pi = pars[i];
       pi.overlap_cus = -1;
+      pi.local_mode = 1;   // the batched local sum reads stored weights
       const wfp_status s = wfp_plan_create(&probs[i], &pi, B->bs, &P);
       if (s != WFP_OK) throw Error{s, "instance " + std::to_string(i) + ": " + g_last_error};
       B->plans.push_back(P);

@@ -164,4 +164,40 @@ std::vector<int> radix_sequence(int64_t n) {
   return r;
 }
 
+
+std::vector<double> window_pieces(const WindowSeries& ws, int pieces, int deg) {
+  const int n = deg + 1;
+  std::vector<double> out((size_t)pieces * n);
+  std::vector<long double> t(n);
+  for (int i = 0; i < n; ++i) t[i] = std::cos(3.14159265358979323846264338327950288L * (i + 0.5L) / n);
+  for (int k = 0; k < pieces; ++k) {
+    const long double half = 1.0L / pieces;
+    const long double centre = -1.0L + (2.0L * k + 1.0L) / pieces;
+    // Vandermonde system V c = f, V_ij = t_i^j
+    std::vector<long double> a((size_t)n * (n + 1));
+    for (int i = 0; i < n; ++i) {
+      long double p = 1.0L;
+      for (int j = 0; j < n; ++j) {
+        a[(size_t)i * (n + 1) + j] = p;
+        p *= t[i];
+      }
+      a[(size_t)i * (n + 1) + n] = cheb_eval(ws.phi.data(), ws.n, (double)(centre + half * t[i]));
+    }
+    for (int c = 0; c < n; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < n; ++r)
+        if (std::fabs((double)a[(size_t)r * (n + 1) + c]) > std::fabs((double)a[(size_t)piv * (n + 1) + c])) piv = r;
+      for (int j = 0; j <= n; ++j) std::swap(a[(size_t)piv * (n + 1) + j], a[(size_t)c * (n + 1) + j]);
+      for (int r = 0; r < n; ++r) {
+        if (r == c) continue;
+        const long double f = a[(size_t)r * (n + 1) + c] / a[(size_t)c * (n + 1) + c];
+        for (int j = c; j <= n; ++j) a[(size_t)r * (n + 1) + j] -= f * a[(size_t)c * (n + 1) + j];
+      }
+    }
+    for (int j = 0; j < n; ++j)
+      out[(size_t)k * n + j] = (double)(a[(size_t)j * (n + 1) + n] / a[(size_t)j * (n + 1) + j]);
+  }
+  return out;
+}
+
 }  // namespace wfp

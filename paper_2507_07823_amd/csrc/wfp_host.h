@@ -31,6 +31,12 @@ struct WindowSeries {
   std::vector<double> phi, g, dg;
 };
 WindowSeries window_series(double b, int n);
+
+// The window phi(u) of a series on [-1, 1] as `pieces` polynomials of degree
+// `deg`: piece k covers u in [-1 + 2k/pieces, -1 + 2(k+1)/pieces] and holds
+// monomial coefficients c_0..c_deg in t = (u - centre) / half_width,
+// interpolating phi at deg + 1 Chebyshev points (solved in long double).
+std::vector<double> window_pieces(const WindowSeries& ws, int pieces, int deg);
 double cheb_eval(const double* a, int n, double s);   // prime convention
 
 // Distance used for neighbour decisions (Definition lambdadef); the same

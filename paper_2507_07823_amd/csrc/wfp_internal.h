@@ -152,6 +152,10 @@ struct wfp_plan {
   int *srow_g = nullptr, *srow_ptr = nullptr, *scol = nullptr;
   double *srow_dinv = nullptr, *sval = nullptr;
   int solve_threads = 64;
+  // local weights evaluated on the fly (when the stored ones would not fit)
+  bool otf = false;
+  double *otf_z = nullptr, *otf_w = nullptr, *phitab = nullptr, *half_beta = nullptr;
+  double* halfs = nullptr;       // 1/2 per row (the local part without beta)
   // concurrent history chain: masked streams for the chain (sb) and the rest (sa)
   int overlap_cus = 0;
   hipStream_t sa = nullptr, sb = nullptr;

@@ -52,7 +52,16 @@ __global__ void k_local_weights(int nrows, const double* __restrict__ xt,
                                 const double* __restrict__ cheb_phi, const double* __restrict__ cheb_g,
                                 int ncheb, int deriv,
                                 const double* __restrict__ lagw, const int64_t* __restrict__ pbase,
-                                signed char* __restrict__ mlo, double* __restrict__ Q);
+                                signed char* __restrict__ mlo, int nq_out, double* __restrict__ Q);
+
+constexpr int kPhiPieces = 128, kPhiDeg = 7;
+template <int P>
+__global__ void k_local_otf(int M, int NH, int64_t L, const int* __restrict__ nb_start,
+                            const int* __restrict__ nb_count, const double* __restrict__ xs,
+                            const double* __restrict__ hist, const double* __restrict__ scale, int periodic,
+                            double dt, double delta, int W, int ngl, const double* __restrict__ zs,
+                            const double* __restrict__ ws, const double* __restrict__ phitab,
+                            const double* __restrict__ lagw, double* __restrict__ out);
 
 __global__ void k_row_ranges(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ pbase,
                              const signed char* __restrict__ mlo, unsigned* __restrict__ ac);
@@ -165,6 +174,7 @@ __global__ void k_adj_grad(int M, const double* __restrict__ q, const double* __
                            const int* __restrict__ i0s, const double* __restrict__ iw,
                            const double* __restrict__ gridd, int nf, int width, double* __restrict__ gb,
                            double* __restrict__ gx);
+__global__ void k_unscale(int M, const double* __restrict__ beta, double* __restrict__ v);
 __global__ void k_gather(int n, const int* __restrict__ idx, const double* __restrict__ in, double* __restrict__ out);
 __global__ void k_unsort(int M, const int* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out);
 

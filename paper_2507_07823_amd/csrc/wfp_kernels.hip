@@ -243,8 +243,8 @@ __global__ void k_pq_tables(int64_t K, int W, int ng, double dt, const double* _
 // (steps before t_{n+1}); weight ((delta - d)/2) w_i (1 - phi(s dt)); stencil
 // the P lags from max(m_min, floor(s) - P/2 + 1); Lagrange weights by
 // prefix/suffix products  v_r = lagw_r prod_{q != r} (u - q),  u = s - m0.
-// Per-thread accumulators live in LDS: acc[m * blockDim + tid].
-// With deriv != 0 the kernel writes dQ_m/dd times sign(wrap(x_target - x_source))
+// Per-thread accumulators live in LDS: acc[m * blockDim + tid]; lags
+// 0..nq_out-1 are written.  With deriv != 0 the kernel writes dQ_m/dd times sign(wrap(x_target - x_source))
 // instead (for gradients with respect to positions): with ds/dd = (1 + z_i)/(2 dt),
 //   d/dd [node weight] = -(1/2) w_i (1 - phi(s dt)) - ((delta - d)/2) w_i phi'(s dt) dt ds/dd,
 // and the Lagrange weights differentiated by the product rule (the stencil is
@@ -259,7 +259,7 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
                 const double* __restrict__ glw, const double* __restrict__ cheb_phi,
                 const double* __restrict__ cheb_g, int ncheb, int deriv,
                 const double* __restrict__ lagw, const int64_t* __restrict__ pbase,
-                signed char* __restrict__ mlo, double* __restrict__ Q) {
+                signed char* __restrict__ mlo, int nq_out, double* __restrict__ Q) {
   extern __shared__ double acc[];
   const int row = blockIdx.x;
   if (row >= nrows) return;
@@ -331,7 +331,7 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
     }
     if (i < n) {
       const double sc = deriv ? scale * sgn : scale;
-      for (int m = 0; m < NQ; ++m) Q[base + (int64_t)m * n + i] = sc * acc[m * nt + tid];
+      for (int m = 0; m < nq_out; ++m) Q[base + (int64_t)m * n + i] = sc * acc[m * nt + tid];
       if (mlo) mlo[pbase[row] + i] = (signed char)lowest;
     }
   }
@@ -340,27 +340,27 @@ k_local_weights(int nrows, const double* __restrict__ xt, const double* __restri
 template __global__ void k_local_weights<2>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
                                             int, const double*, const double*, const double*, const double*, int, int,
-                                            const double*, const int64_t*, signed char*, double*);
+                                            const double*, const int64_t*, signed char*, int, double*);
 template __global__ void k_local_weights<4>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
                                             int, const double*, const double*, const double*, const double*, int, int,
-                                            const double*, const int64_t*, signed char*, double*);
+                                            const double*, const int64_t*, signed char*, int, double*);
 template __global__ void k_local_weights<6>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
                                             int, const double*, const double*, const double*, const double*, int, int,
-                                            const double*, const int64_t*, signed char*, double*);
+                                            const double*, const int64_t*, signed char*, int, double*);
 template __global__ void k_local_weights<8>(int, const double*, const double*, int, const int*, const int*,
                                             const int64_t*, const double*, int, double, double, int, int,
                                             int, const double*, const double*, const double*, const double*, int, int,
-                                            const double*, const int64_t*, signed char*, double*);
+                                            const double*, const int64_t*, signed char*, int, double*);
 template __global__ void k_local_weights<10>(int, const double*, const double*, int, const int*, const int*,
                                              const int64_t*, const double*, int, double, double, int, int,
                                              int, const double*, const double*, const double*, const double*, int, int,
-                                             const double*, const int64_t*, signed char*, double*);
+                                             const double*, const int64_t*, signed char*, int, double*);
 template __global__ void k_local_weights<12>(int, const double*, const double*, int, const int*, const int*,
                                              const int64_t*, const double*, int, double, double, int, int,
                                              int, const double*, const double*, const double*, const double*, int, int,
-                                             const double*, const int64_t*, signed char*, double*);
+                                             const double*, const int64_t*, signed char*, int, double*);
 
 // Jacobi contraction bound of the per-step system (I + S): for each row,
 // sum_{l != j} |S_jl| / (1 + S_jj) over its nearby sources.
@@ -578,6 +578,113 @@ k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb
             const double* __restrict__ hist, double* __restrict__ loc) {
   k_local_rhs_body(M, NQ, NH, L, m0, nb_start, rowbase, acx, Qc, hist, loc, xcd_block(blockIdx.x, gridDim.x));
 }
+
+// Local sum of lags m >= 1 with the weights evaluated on the fly (when the
+// stored weights would not fit): for every source l within delta,
+//   sum_i om_i(d) sum_r v_{i,r} sigma_l^{L - m0_i - r},   m0_i + r >= 1,
+// which equals sum_{m>=1} Q_m(d) sigma_l^{L-m} of the stored path regrouped
+// by quadrature node (Section 4.1: node lag s_i = W - (W - d/dt)(1 + z_i)/2,
+// weight ((delta - d)/2) w_i (1 - phi(s_i dt)), the P lags from
+// max(m_min, floor(s_i) - P/2 + 1)).  One wavefront per target row, lanes over
+// sources.  The nodes come in order of decreasing s_i, so the stencil start
+// never grows: each lane keeps the P densities of its current stencil in
+// registers and shifts in one older level per step down.  phi comes from a
+// piecewise polynomial table (kPhiPieces pieces of degree kPhiDeg in
+// u = 2 s / W - 1, staged in LDS).
+template <int P>
+__global__ void __launch_bounds__(256)
+k_local_otf(int M, int NH, int64_t L, const int* __restrict__ nb_start, const int* __restrict__ nb_count,
+            const double* __restrict__ xs, const double* __restrict__ hist, const double* __restrict__ scale,
+            int periodic, double dt, double delta, int W, int ngl, const double* __restrict__ zs,
+            const double* __restrict__ ws, const double* __restrict__ phitab, const double* __restrict__ lagw,
+            double* __restrict__ out) {
+  __shared__ double tab[kPhiPieces * (kPhiDeg + 1)];
+  __shared__ double nz[64], nw[64];
+  for (int i = threadIdx.x; i < kPhiPieces * (kPhiDeg + 1); i += blockDim.x) tab[i] = phitab[i];
+  for (int i = threadIdx.x; i < ngl; i += blockDim.x) {
+    nz[i] = zs[i];
+    nw[i] = ws[i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int j = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= M) return;   // no barrier below
+  const double xa = xs[j];
+  const int st = nb_start[j], n = nb_count[j];
+  double lw[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) lw[r] = lagw[r];
+  double acc = 0.0;
+  for (int i = lane; i < n; i += 64) {
+    int l = st + i;
+    if (l >= M) l -= M;
+    double d = fabs(xa - xs[l]);
+    if (periodic && d > kPi) d = kTwoPi - d;
+    if (!(d < delta)) continue;
+    const double D = d / dt;
+    const int mmin = (d < dt) ? 0 : 1;
+    const double half = 0.5 * (delta - d);
+    double w[P];
+    int mc = 0x7fffffff;
+    double pair = 0.0;
+    for (int q = 0; q < ngl; ++q) {
+      const double s = W - (W - D) * (1.0 + nz[q]) / 2.0;
+      // 1 - phi(s dt) from the table
+      const double u = 2.0 * s / W - 1.0;
+      int pc = (int)((u + 1.0) * (0.5 * kPhiPieces));
+      pc = pc < 0 ? 0 : (pc >= kPhiPieces ? kPhiPieces - 1 : pc);
+      const double t = (u + 1.0) * kPhiPieces - (2 * pc + 1);   // in [-1, 1] on the piece
+      const double* c = tab + pc * (kPhiDeg + 1);
+      double ph = c[kPhiDeg];
+#pragma unroll
+      for (int k = kPhiDeg - 1; k >= 0; --k) ph = fma(ph, t, c[k]);
+      const double om = half * nw[q] * (1.0 - ph);
+      int m0 = (int)floor(s) - P / 2 + 1;
+      if (m0 < mmin) m0 = mmin;
+      if (mc == 0x7fffffff) {
+        mc = m0;
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          const int m = m0 + r;
+          w[r] = (m >= 1) ? hist[(int64_t)mod_slot(L - m, NH) * M + l] : 0.0;
+        }
+      }
+      while (mc > m0) {   // one level older at the front of the window
+#pragma unroll
+        for (int r = P - 1; r >= 1; --r) w[r] = w[r - 1];
+        --mc;
+        w[0] = (mc >= 1) ? hist[(int64_t)mod_slot(L - mc, NH) * M + l] : 0.0;
+      }
+      const double uu = s - m0;
+      double pre[P];
+      pre[0] = 1.0;
+#pragma unroll
+      for (int r = 1; r < P; ++r) pre[r] = pre[r - 1] * (uu - (r - 1));
+      double suf = 1.0, dot = 0.0;
+#pragma unroll
+      for (int r = P - 1; r >= 0; --r) {
+        dot = fma(lw[r] * pre[r] * suf, w[r], dot);
+        suf *= (uu - r);
+      }
+      pair = fma(om, dot, pair);
+    }
+    acc += pair;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) out[j] = scale[j] * acc;
+}
+
+#define WFP_OTF_INST(PP)                                                                                        \
+  template __global__ void k_local_otf<PP>(int, int, int64_t, const int*, const int*, const double*,           \
+                                           const double*, const double*, int, double, double, int, int,        \
+                                           const double*, const double*, const double*, const double*, double*);
+WFP_OTF_INST(2)
+WFP_OTF_INST(4)
+WFP_OTF_INST(6)
+WFP_OTF_INST(8)
+WFP_OTF_INST(10)
+WFP_OTF_INST(12)
+#undef WFP_OTF_INST
 
 // Driving data g_j(t) = beta_j f(x_j - t) (eq. (gj); f periodised in the
 // periodic box), stored negated: ginc_j = -g_j.  Thread (row, packet) sums the
@@ -1184,6 +1291,13 @@ __global__ void k_adj_grad(int M, const double* __restrict__ q, const double* __
     const double w = xloc[j] + xw[j] + interp_pre(j, i0s, iw, gridd, nf, width);
     gx[j] += qj * D[j] + sj * w;
   }
+}
+
+// v_j <- v_j / (beta_j / 2): a local sum with the stored beta_j/2-scaled weights
+// back to the field value.
+__global__ void k_unscale(int M, const double* __restrict__ beta, double* __restrict__ v) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < M) v[j] = v[j] / (0.5 * beta[j]);
 }
 
 // out[i] = in[idx[i]]

@@ -38,7 +38,7 @@ void validate(const wfp_problem* prob, const wfp_params* par) {
   if (par->eps_window < 0 || !(par->eps_window < 1) || par->gamma < 0 || !(par->gamma < 1))
     fail(WFP_EINVAL, "eps_window and gamma must lie in [0, 1)");
   if (par->W < 0 || par->K < 0 || par->n_gl_local < 0 || par->n_gl_pq < 0 || par->rbc_period < 0 ||
-      par->solve_iters < 0 || par->checkpoint_every < 0)
+      par->solve_iters < 0 || par->checkpoint_every < 0 || par->local_mode < 0 || par->local_mode > 2)
     fail(WFP_EINVAL, "negative size parameter");
   const int p = par->p > 0 ? par->p : 8;
   if (par->p < 0 || p % 2 || p < 2 || p > kMaxP) fail(WFP_EINVAL, "p must be even, 2..12");
@@ -131,13 +131,14 @@ constexpr int kQwThreads = 128;
 // of `nrows` target rows against the sorted scatterers.
 void launch_local_weights(wfp_plan* P, int nrows, const double* xt, const int* st, const int* cnt,
                           const int64_t* off, const double* scale, int deriv, const int64_t* pbs,
-                          signed char* ml, double* Qd) {
+                          signed char* ml, double* Qd, int nq_out = -1) {
+  if (nq_out < 0) nq_out = P->NQ;
   if (nrows == 0) return;
   const int periodic = P->boundary == WFP_PERIODIC ? 1 : 0;
 #define WFP_QW(PP)                                                                                      \
   hipLaunchKernelGGL(k_local_weights<PP>, dim3(nrows), dim3(kQwThreads), P->lds_qw, P->stream, nrows, xt,  \
                      P->xs, (int)P->M, st, cnt, off, scale, periodic, P->dt, P->delta, P->W, P->NQ, P->ngl,  \
-                     P->glz_d, P->glw_d, P->cheb_phi, P->cheb_g, P->ncheb, deriv, P->lagw_d, pbs, ml, Qd)
+                     P->glz_d, P->glw_d, P->cheb_phi, P->cheb_g, P->ncheb, deriv, P->lagw_d, pbs, ml, nq_out, Qd)
   switch (P->p) {
     case 2: WFP_QW(2); break;
     case 4: WFP_QW(4); break;
@@ -391,12 +392,33 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     tot += (int64_t)nbc[j] * P->NQ;
     P->n_pairs += nbc[j];
   }
+  // stored weights (dense per pair during set-up, then packed) or on the fly
+  {
+    int mode = par->local_mode;
+    if (mode == 0) {
+      size_t fr = 0, to = 0;
+      HIPCHK(hipMemGetInfo(&fr, &to));
+      const double need = 8.0 * (double)tot * 1.7;    // dense set-up array + packed weights
+      mode = need < 0.6 * (double)fr ? 1 : 2;
+    }
+    P->otf = mode == 2;
+  }
+  // on the fly: only the lag-0 weights of nearby pairs are stored (for the solve)
+  std::vector<int64_t> qoN(M);
+  int64_t totN = 0;
+  for (int64_t j = 0; j < M; ++j) {
+    qoN[j] = totN;
+    totN += nc[j];
+  }
+  auto lag0 = [&](int64_t g, int64_t l) -> int64_t {
+    return P->otf ? qoN[g] + (l - ns[g] + M) % M : qo[g] + (l - nbs[g] + M) % M;
+  };
   P->nb_start = P->alloc<int>(M);
   P->nb_count = P->alloc<int>(M);
   P->qoff = P->alloc<int64_t>(M);
   int64_t* pbase = P->alloc<int64_t>(M);
-  signed char* mlo = P->alloc<signed char>(P->n_pairs);
-  P->Q = P->alloc<double>(tot);
+  signed char* mlo = P->otf ? nullptr : P->alloc<signed char>(P->n_pairs);
+  P->Q = P->alloc<double>(P->otf ? totN : tot);
   upload(P->nb_start, nbs, s);
   upload(P->nb_count, nbc, s);
   upload(P->qoff, qo, s);
@@ -430,8 +452,51 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
                        const double* scale, const int64_t* pbs, signed char* ml, double* Qd) {
     launch_local_weights(P, nrows, xt, st, cnt, off, scale, 0, pbs, ml, Qd);
   };
-  launch_qw((int)M, P->xs, P->nb_start, P->nb_count, P->qoff, hb_d, pbase, mlo, P->Q);
-  {
+  int* near_start = P->alloc<int>(M);
+  int* near_count = P->alloc<int>(M);
+  int64_t* near_off = P->alloc<int64_t>(M);
+  upload(near_start, ns, s);
+  upload(near_count, nc, s);
+  upload(near_off, qoN, s);
+  if (P->otf) {
+    launch_local_weights(P, (int)M, P->xs, near_start, near_count, near_off, hb_d, 0, nullptr, nullptr, P->Q, 1);
+    // on-the-fly tables: GL nodes in ascending z (decreasing lag), the window
+    // phi as kPhiPieces polynomials of degree kPhiDeg in the local variable
+    std::vector<int> ord(P->ngl);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int a, int c) { return glz[a] < glz[c]; });
+    std::vector<double> za(P->ngl), wa(P->ngl);
+    for (int q = 0; q < P->ngl; ++q) {
+      za[q] = glz[ord[q]];
+      wa[q] = glw[ord[q]];
+    }
+    if (P->ngl > 64) fail(WFP_EDOMAIN, "on-the-fly local weights take at most 64 quadrature nodes");
+    std::vector<double> tab = window_pieces(ws, kPhiPieces, kPhiDeg);
+    {
+      // the table reproduces the series to rounding
+      double worst = 0.0;
+      for (int i = 0; i <= 20000; ++i) {
+        const double u = -1.0 + 2.0 * i / 20000.0;
+        int pc = (int)((u + 1.0) * (0.5 * kPhiPieces));
+        pc = pc < 0 ? 0 : (pc >= kPhiPieces ? kPhiPieces - 1 : pc);
+        const double tt = (u + 1.0) * kPhiPieces - (2 * pc + 1);
+        double v = tab[(size_t)pc * (kPhiDeg + 1) + kPhiDeg];
+        for (int k = kPhiDeg - 1; k >= 0; --k) v = std::fma(v, tt, tab[(size_t)pc * (kPhiDeg + 1) + k]);
+        worst = std::max(worst, std::fabs(v - cheb_eval(ws.phi.data(), ws.n, u)));
+      }
+      if (worst > 1e-15) fail(WFP_EDOMAIN, "window table for the on-the-fly weights is not accurate");
+    }
+    P->otf_z = P->alloc<double>(P->ngl);
+    P->otf_w = P->alloc<double>(P->ngl);
+    P->phitab = P->alloc<double>(tab.size());
+    upload(P->otf_z, za, s);
+    upload(P->otf_w, wa, s);
+    upload(P->phitab, tab, s);
+    P->half_beta = hb_d;
+  } else {
+    launch_qw((int)M, P->xs, P->nb_start, P->nb_count, P->qoff, hb_d, pbase, mlo, P->Q);
+  }
+  if (!P->otf) {
     unsigned long long* cnt = P->alloc<unsigned long long>(1);
     HIPCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_count_nonzero, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ,
@@ -444,7 +509,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->release(cnt);
   }
   // ---- pack the weights of lags >= 1 to each row's nonzero source ranges ----
-  {
+  if (!P->otf) {
     for (int64_t j = 0; j < M; ++j)
       if (nbc[j] >= 65536) fail(WFP_EDOMAIN, "more than 65535 neighbours of one scatterer");
     P->ac = P->alloc<unsigned>((size_t)M * P->NQ);
@@ -514,20 +579,18 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   }
   // ---- solve: contraction bound, sweep count, tiles with halos ----
   {
-    int* near_start = P->alloc<int>(M);
-    int* near_count = P->alloc<int>(M);
-    upload(near_start, ns, s);
-    upload(near_count, nc, s);
     double* cr = P->alloc<double>(M);
-    hipLaunchKernelGGL(k_row_contraction, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->nb_start, P->nb_count,
-                       P->qoff, P->Q, near_start, near_count, cr);
+    if (P->otf)
+      hipLaunchKernelGGL(k_row_contraction, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, near_start, near_count,
+                         near_off, P->Q, near_start, near_count, cr);
+    else
+      hipLaunchKernelGGL(k_row_contraction, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->nb_start,
+                         P->nb_count, P->qoff, P->Q, near_start, near_count, cr);
     HIPCHK(hipGetLastError());
     std::vector<double> crh(M);
     HIPCHK(hipMemcpyAsync(crh.data(), cr, M * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     P->release(cr);
-    P->release(near_start);
-    P->release(near_count);
     double rho = 0;
     for (double v : crh) rho = std::max(rho, v);
     P->contraction = rho;
@@ -612,7 +675,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
             for (int64_t j = 0; j < len; ++j) {
               const int64_t gj = (st + j) % M;
               if (pair_distance(xs[gi], xs[gj], periodic) < P->dt) {
-                coup_q.push_back(qo[gi] + (gj - nbs[gi] + M) % M);
+                coup_q.push_back(lag0(gi, gj));
                 coup_pos.push_back(run_inv_off[rr] + i * len + j);
               }
             }
@@ -720,12 +783,12 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
       std::vector<int> gp(M + 1, 0), gc;
       std::vector<int64_t> geq, grq(M);
       for (int64_t g = 0; g < M; ++g) {
-        grq[g] = qo[g] + (g - nbs[g] + M) % M;
+        grq[g] = lag0(g, g);
         for (int k = 0; k < nc[g]; ++k) {
           const int64_t l = (ns[g] + k) % M;
           if (l == g) continue;
           gc.push_back((int)l);
-          geq.push_back(qo[g] + (l - nbs[g] + M) % M);
+          geq.push_back(lag0(g, l));
         }
         gp[g + 1] = (int)gc.size();
       }
@@ -758,15 +821,14 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
         for (int e = 0; e < el[t]; ++e) {
           const int64_t g = ((int64_t)es[t] + e) % M;
           rg.push_back((int)g);
-          const int64_t self = (g - nbs[g] + M) % M;
-          rq.push_back(qo[g] + self);
+          rq.push_back(lag0(g, g));
           for (int k = 0; k < nc[g]; ++k) {
             const int64_t l = (ns[g] + k) % M;
             if (l == g) continue;
             const int64_t le = (l - es[t] + M) % M;
             if (le >= el[t]) continue;   // outside the halo: only reaches rows that are not kept
             col.push_back((int)le);
-            eq.push_back(qo[g] + (l - nbs[g] + M) % M);
+            eq.push_back(lag0(g, l));
           }
           rptr.push_back((int)col.size());
         }
@@ -811,8 +873,11 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   HIPCHK(hipStreamSynchronize(s));
   P->release(P->Q);
   P->Q = nullptr;
-  P->release(mlo);
+  if (mlo) P->release(mlo);
   P->release(pbase);
+  P->release(near_start);
+  P->release(near_count);
+  P->release(near_off);
   P->ginc = P->alloc<double>(M);
   P->loc = P->alloc<double>(M);
   if (!periodic) {
@@ -880,6 +945,25 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
+// Local sum of lags >= 1 with the weights evaluated on the fly, scaled per row.
+void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, const double* scale, double* out) {
+  const int nblocks = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
+  const int periodic = P->boundary == WFP_PERIODIC ? 1 : 0;
+#define WFP_OTF(PP)                                                                                             \
+  hipLaunchKernelGGL(k_local_otf<PP>, dim3(nblocks), dim3(kRowThreads), 0, s, (int)P->M, P->NH, L, P->nb_start, \
+                     P->nb_count, P->xs, hist, scale, periodic, P->dt, P->delta, P->W, P->ngl, P->otf_z, P->otf_w,  \
+                     P->phitab, P->lagw_d, out)
+  switch (P->p) {
+    case 2: WFP_OTF(2); break;
+    case 4: WFP_OTF(4); break;
+    case 6: WFP_OTF(6); break;
+    case 8: WFP_OTF(8); break;
+    case 10: WFP_OTF(10); break;
+    default: WFP_OTF(12); break;
+  }
+#undef WFP_OTF
+}
+
 // The march state a level reads and updates: density history ring, spectra
 // ring, alpha, alpha'.  The plan's own state, the replay copy and the adjoint
 // state of the gradient pass all use the same level code.
@@ -919,8 +1003,11 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
   }
   {
     StageTimer st(P, WFP_STAGE_LOCAL, s);
-    hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L, 1,
-                       P->nb_start, P->rowbase, P->acx, P->Qc, S.hist, P->loc);
+    if (P->otf)
+      launch_local_otf(P, s, S.hist, L, P->half_beta, P->loc);
+    else
+      hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L, 1,
+                         P->nb_start, P->rowbase, P->acx, P->Qc, S.hist, P->loc);
   }
   {
     StageTimer st(P, WFP_STAGE_SPREAD, sc);
@@ -1358,6 +1445,7 @@ wfp_status wfp_plan_info(const wfp_plan* P, wfp_info* info) {
   info->n_weights_stored = P->n_weights_stored;
   info->solve_mode = P->solve_global ? 1 : 0;
   info->overlap_cus = P->overlap_cus;
+  info->local_mode = P->otf ? 2 : 1;
   return WFP_OK;
 }
 
@@ -1407,6 +1495,32 @@ wfp_status wfp_run(wfp_plan* P, int64_t n_steps, double* sigma_out, int64_t save
   });
 }
 
+wfp_status wfp_local_part(wfp_plan* P, double* out) {
+  if (!P || !out) {
+    g_last_error = "local_part needs a plan and an output array";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(P->device));
+    hipStream_t s = P->stream;
+    const int64_t M = P->M;
+    if (!P->halfs) {
+      P->halfs = P->alloc<double>(M);
+      hipLaunchKernelGGL(k_fill, dim3(nblk(M, 256)), dim3(256), 0, s, P->halfs, M, 0.5);
+    }
+    if (P->otf) {
+      launch_local_otf(P, s, P->hist, P->level, P->halfs, P->loc);
+    } else {
+      const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
+      hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)M, P->NQ, P->NH, P->level, 1,
+                         P->nb_start, P->rowbase, P->acx, P->Qc, P->hist, P->loc);
+      hipLaunchKernelGGL(k_unscale, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->beta, P->loc);
+    }
+    hipLaunchKernelGGL(k_unsort, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->perm, P->loc, out);
+    HIPCHK(hipGetLastError());
+  });
+}
+
 wfp_status wfp_adjoint(wfp_plan* P, int64_t n_levels, const double* dJdu, double* grad_beta, double* grad_x) {
   if (!P || !dJdu || !grad_beta || n_levels < 1) {
     g_last_error = "adjoint needs a plan, n_levels >= 1, dJ/du and grad_beta";
@@ -1419,6 +1533,10 @@ wfp_status wfp_adjoint(wfp_plan* P, int64_t n_levels, const double* dJdu, double
   if (P->R < 1) {
     g_last_error = "the gradient pass needs receivers (R >= 1)";
     return WFP_EINVAL;
+  }
+  if (P->otf) {
+    g_last_error = "the gradient pass needs stored local weights (local_mode 1)";
+    return WFP_EDOMAIN;
   }
   if (P->ckpt_every < 1 || !P->ck_from0 || P->level < n_levels) {
     g_last_error = "run the n_levels levels from level 0 with checkpoint_every > 0 first";

@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
                 ("W", ctypes.c_int32), ("p", ctypes.c_int32), ("K", ctypes.c_int64),
                 ("n_gl_local", ctypes.c_int32), ("n_gl_pq", ctypes.c_int32), ("rbc_period", ctypes.c_int32),
                 ("nufft_width", ctypes.c_int32), ("solve_iters", ctypes.c_int32),
-                ("checkpoint_every", ctypes.c_int32), ("overlap_cus", ctypes.c_int32)]
+                ("checkpoint_every", ctypes.c_int32), ("overlap_cus", ctypes.c_int32),
+                ("local_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -49,7 +50,8 @@ class Info(ctypes.Structure):
                 ("solve_iters", ctypes.c_int32), ("boundary", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("delta", ctypes.c_double), ("b", ctypes.c_double), ("solve_contraction", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("n_weights_nonzero", ctypes.c_int64),
-                ("n_weights_stored", ctypes.c_int64), ("solve_mode", ctypes.c_int32), ("overlap_cus", ctypes.c_int32)]
+                ("n_weights_stored", ctypes.c_int64), ("solve_mode", ctypes.c_int32), ("overlap_cus", ctypes.c_int32),
+                ("local_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -75,6 +77,8 @@ def load_library():
     lib.wfp_plan_info.restype = ctypes.c_int32
     lib.wfp_run.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
     lib.wfp_run.restype = ctypes.c_int32
+    lib.wfp_local_part.argtypes = [vp, vp]
+    lib.wfp_local_part.restype = ctypes.c_int32
     lib.wfp_adjoint.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
     lib.wfp_adjoint.restype = ctypes.c_int32
     lib.wfp_get_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp]
@@ -216,6 +220,13 @@ class Plan:
         u = torch.empty((n_steps, R), dtype=torch.float64, device="cuda") if (receivers and R) else None
         self.run(n_steps, sig, save_every, u)
         return sig, u
+
+    def local_part(self):
+        """The explicit local part (lags >= 1) at every spring for the next level."""
+        import torch
+        out = torch.empty(self.info["M"], dtype=torch.float64, device="cuda")
+        _check(self._lib.wfp_local_part(self._h, _ptr(out)))
+        return out
 
     def gradient(self, dJdu, positions=True):
         """dJ/dbeta and dJ/dx (or None) for the levels 0..N-1 run since the
