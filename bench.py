@@ -263,6 +263,49 @@ def batch_leg(n_inst, levels, m_max):
             "batched_over_plain": t_plain / t_batch}
 
 
+# FP64 operations of one quadrature node in the on-the-fly local sum, counted
+# as the method needs them: node lag (1 FMA), window polynomial of degree 5
+# (5 FMA), node weight (2 mul), the degree-7 interpolant of the density
+# history in Newton form (7 sub + 7 FMA), accumulation (1 FMA).
+OTF_FLOPS_PER_NODE = 2 + 10 + 2 + 7 + 14 + 2
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def clumped_leg(levels):
+    """The clumped free-space workload at full size (M = 1e6, dt = 5e-4, K = 6250,
+    local weights on the fly): set-up time and the rate over `levels` levels
+    from rest (the per-level work does not depend on the densities)."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    p = workloads.clumped_free_space()
+    M = p["x"].size
+    t0 = time.perf_counter()
+    plan = wfp.Plan(p, p["dt"])
+    setup = time.perf_counter() - t0
+    info = plan.info
+    plan.run(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(levels)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.set_profiling(True)
+    plan.run(levels)
+    prof = plan.profile()
+    plan.set_profiling(False)
+    plan.close()
+    ms, n = prof["local"]
+    avg = ms / n
+    flops = info["n_pairs"] * info["n_gl_local"] * OTF_FLOPS_PER_NODE
+    achieved = flops / (avg * 1e-3) / 1e12
+    return {"workload": "clumped free space", "M": M, "dt": p["dt"], "K": info["K"], "pairs": info["n_pairs"],
+            "local_mode": info["local_mode"], "solve_mode": info["solve_mode"], "plan_setup_s": setup,
+            "levels": levels, "ms_per_level": 1e3 * el / levels, "scatterer_steps_per_s": M * levels / el,
+            "local_sum": {"bound": "alu", "avg_ms": avg, "flops_per_launch": flops, "achieved_tflops": achieved,
+                          "peak_tflops": FP64_VECTOR_PEAK_TFLOPS, "frac": achieved / FP64_VECTOR_PEAK_TFLOPS},
+            "stages_ms": {k: v[0] / v[1] for k, v in prof.items() if v[1]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,6 +319,7 @@ def main():
     ap.add_argument("--batch-levels", type=int, default=200, help="levels of the batched leg (0 skips it)")
     ap.add_argument("--batch-instances", type=int, default=512)
     ap.add_argument("--batch-max-m", type=int, default=10_000)
+    ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 256 MiB copy used to calibrate the HBM counters")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
@@ -354,6 +398,11 @@ def main():
         batch = batch_leg(args.batch_instances, args.batch_levels, args.batch_max_m)
         log(f"batch leg: {batch}")
 
+    clumped = None
+    if args.clumped_levels > 0:
+        clumped = clumped_leg(args.clumped_levels)
+        log(f"clumped leg: {clumped}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_steps)
@@ -366,7 +415,7 @@ def main():
         "config": {"workload": "periodic multiband springs", "M": M, "dt": p["dt"], "K": info["K"],
                    "W": info["W"], "p": info["p"], "n_fine": info["n_fine"], "pairs": info["n_pairs"],
                    "levels_timed": args.steps, "parallelism": "single GPU"},
-        "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch, "cpu_baseline": cpu,
+        "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch, "clumped": clumped, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()

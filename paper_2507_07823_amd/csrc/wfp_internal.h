@@ -161,7 +161,7 @@ struct wfp_plan {
   hipStream_t sa = nullptr, sb = nullptr;
   hipEvent_t ev_solved = nullptr, ev_chain = nullptr, ev_join = nullptr;
   // global-sweep solve (when tiles do not fit in LDS)
-  bool solve_global = false;
+  bool solve_global = false, g_wave = false;
   int *g_ptr = nullptr, *g_col = nullptr;
   double *g_val = nullptr, *g_dinv = nullptr, *g_rhs = nullptr, *g_xa = nullptr, *g_xb = nullptr;
   // direct solve of small runs

@@ -54,14 +54,15 @@ __global__ void k_local_weights(int nrows, const double* __restrict__ xt,
                                 const double* __restrict__ lagw, const int64_t* __restrict__ pbase,
                                 signed char* __restrict__ mlo, int nq_out, double* __restrict__ Q);
 
-constexpr int kPhiPieces = 128, kPhiDeg = 7;
+constexpr int kPhiPieces = 512, kPhiDeg = 5;
+constexpr int kOtfRows = 16, kOtfChunk = 256;
 template <int P>
-__global__ void k_local_otf(int M, int NH, int64_t L, const int* __restrict__ nb_start,
+__global__ void k_local_otf(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start,
                             const int* __restrict__ nb_count, const double* __restrict__ xs,
                             const double* __restrict__ hist, const double* __restrict__ scale, int periodic,
                             double dt, double delta, int W, int ngl, const double* __restrict__ zs,
                             const double* __restrict__ ws, const double* __restrict__ phitab,
-                            const double* __restrict__ lagw, double* __restrict__ out);
+                            double* __restrict__ out);
 
 __global__ void k_row_ranges(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ pbase,
                              const signed char* __restrict__ mlo, unsigned* __restrict__ ac);
@@ -115,6 +116,11 @@ __global__ void k_jacobi_sweep(int M, const int* __restrict__ ptr, const int* __
                                const double* __restrict__ rhs, const double* __restrict__ xin,
                                double* __restrict__ xout, double* __restrict__ save_row,
                                const int* __restrict__ perm);
+__global__ void k_jacobi_sweep_wave(int M, const int* __restrict__ ptr, const int* __restrict__ col,
+                                    const double* __restrict__ val, const double* __restrict__ dinv,
+                                    const double* __restrict__ rhs, const double* __restrict__ xin,
+                                    double* __restrict__ xout, double* __restrict__ save_row,
+                                    const int* __restrict__ perm);
 __global__ void k_solve_direct(int M, const int* __restrict__ dt_g0, const int* __restrict__ dt_n,
                                const int* __restrict__ dt_p0, const int* __restrict__ pt_cs,
                                const int* __restrict__ pt_cn, const int64_t* __restrict__ pt_inv,

@@ -792,6 +792,8 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
         }
         gp[g + 1] = (int)gc.size();
       }
+      // a wavefront per row when rows are long
+      P->g_wave = gc.size() > (size_t)16 * M;
       P->g_ptr = P->alloc<int>(M + 1);
       P->g_col = P->alloc<int>(gc.size());
       P->g_val = P->alloc<double>(gc.size());
@@ -896,6 +898,15 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   HIPCHK(hipFuncSetAttribute((const void*)k_rbc_to_modes, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_hist_b, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  if (P->otf) {
+    const size_t need = (size_t)(P->NQ - 1) * kOtfChunk * sizeof(double) +
+                        (size_t)kPhiPieces * (kPhiDeg + 1) * sizeof(double) + 2048;
+    if (need > 160 * 1024) fail(WFP_EDOMAIN, "on-the-fly local sum: density stage too large for LDS");
+    const void* fns[6] = {(const void*)k_local_otf<2>, (const void*)k_local_otf<4>, (const void*)k_local_otf<6>,
+                          (const void*)k_local_otf<8>, (const void*)k_local_otf<10>, (const void*)k_local_otf<12>};
+    const int dyn = (int)((size_t)(P->NQ - 1) * kOtfChunk * sizeof(double));
+    for (const void* f : fns) HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
+  }
   if (6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4) > 160 * 1024)
     fail(WFP_EDOMAIN, "four-step factor n1 too long for the history kernel's LDS");
   {
@@ -947,12 +958,13 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
 
 // Local sum of lags >= 1 with the weights evaluated on the fly, scaled per row.
 void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, const double* scale, double* out) {
-  const int nblocks = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
+  const int nblocks = 8 * (int)nblk(nblk(P->M, kOtfRows), 8);
   const int periodic = P->boundary == WFP_PERIODIC ? 1 : 0;
-#define WFP_OTF(PP)                                                                                             \
-  hipLaunchKernelGGL(k_local_otf<PP>, dim3(nblocks), dim3(kRowThreads), 0, s, (int)P->M, P->NH, L, P->nb_start, \
-                     P->nb_count, P->xs, hist, scale, periodic, P->dt, P->delta, P->W, P->ngl, P->otf_z, P->otf_w,  \
-                     P->phitab, P->lagw_d, out)
+  const size_t lds = (size_t)(P->NQ - 1) * kOtfChunk * sizeof(double);
+#define WFP_OTF(PP)                                                                                              \
+  hipLaunchKernelGGL(k_local_otf<PP>, dim3(nblocks), dim3(64 * kOtfRows), lds, s, (int)P->M, P->NH, P->NQ, L,     \
+                     P->nb_start, P->nb_count, P->xs, hist, scale, periodic, P->dt, P->delta, P->W, P->ngl,        \
+                     P->otf_z, P->otf_w, P->phitab, out)
   switch (P->p) {
     case 2: WFP_OTF(2); break;
     case 4: WFP_OTF(4); break;
@@ -1064,8 +1076,12 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
       for (int it = 1; it < P->iters; ++it) {
         const bool last = it == P->iters - 1;
         double* out = last ? slot : xb;
-        hipLaunchKernelGGL(k_jacobi_sweep, dim3(nb), dim3(256), 0, s, (int)P->M, P->g_ptr, P->g_col, P->g_val,
-                           P->g_dinv, P->g_rhs, xa, out, last ? save : nullptr, P->perm);
+        if (P->g_wave)
+          hipLaunchKernelGGL(k_jacobi_sweep_wave, dim3(nblk(P->M, 4)), dim3(256), 0, s, (int)P->M, P->g_ptr,
+                             P->g_col, P->g_val, P->g_dinv, P->g_rhs, xa, out, last ? save : nullptr, P->perm);
+        else
+          hipLaunchKernelGGL(k_jacobi_sweep, dim3(nb), dim3(256), 0, s, (int)P->M, P->g_ptr, P->g_col, P->g_val,
+                             P->g_dinv, P->g_rhs, xa, out, last ? save : nullptr, P->perm);
         std::swap(xa, xb);
       }
     }
