@@ -13,8 +13,9 @@ Printed: one JSON line on stdout (diagnostics on stderr).
   parity      max |sigma_gpu - sigma_oracle| / max |sigma_oracle| against the
               stored oracle values (tests/golden/multiband_sigma.npz)
   roofline    the dominant kernel, timed with HIP events on the plan's stream in
-              a second pass over the same steps; algorithmic bytes per launch
-              as stated in the design notes
+              a second pass over the same steps (while timing, the library runs
+              every stage on that stream, so the kernel is timed alone);
+              algorithmic bytes per launch as stated in the design notes
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
 """
 import argparse
@@ -95,6 +96,21 @@ def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, kernel="wfp:
         f"write_scale: {fw:.4f}",
         f"traffic_bytes_per_dispatch: {traffic:.0f}",
     ])
+
+
+def trace_tail_mean(d, kernel, n):
+    """Mean duration (us) of the last n dispatches of `kernel` in a rocprofv3
+    kernel trace (kernel_trace.csv), e.g. bench.py's timed-alone pass."""
+    durs = []
+    for fn in os.listdir(d):
+        if fn.endswith("kernel_trace.csv"):
+            with open(os.path.join(d, fn)) as f:
+                for r in csv.DictReader(f):
+                    if r["Kernel_Name"].split("(")[0] == kernel:
+                        durs.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    durs.sort()
+    tail = [x for _, x in durs[-n:]]
+    return sum(tail) / len(tail) / 1e3 if tail else None
 
 
 def stats_summary(d, top=20):
@@ -320,17 +336,25 @@ def main():
     ap.add_argument("--batch-instances", type=int, default=512)
     ap.add_argument("--batch-max-m", type=int, default=10_000)
     ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
+    ap.add_argument("--overlap-cus", type=int, default=0,
+                    help="plan parameter overlap_cus (0: library choice, -1: one stream)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 256 MiB copy used to calibrate the HBM counters")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
                     help="print the traffic summary of rocprofv3 --pmc runs and exit")
     ap.add_argument("--stats-summary", metavar="DIR", help="print a rocprofv3 --stats table and exit")
+    ap.add_argument("--trace-tail", nargs=3, metavar=("DIR", "KERNEL", "N"),
+                    help="print the mean duration of the last N dispatches of KERNEL in a kernel trace and exit")
     args = ap.parse_args()
     if args.pmc_summary:
         print(pmc_summary(*args.pmc_summary))
         return
     if args.stats_summary:
         print(stats_summary(args.stats_summary))
+        return
+    if args.trace_tail:
+        d, k, n = args.trace_tail
+        print(f"{k}: mean of the last {n} dispatches {trace_tail_mean(d, k, int(n)):.3f} us")
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the march has no multi-GPU "
@@ -346,7 +370,7 @@ def main():
     p = workloads.multiband_periodic()
     M = p["x"].size
     t0 = time.perf_counter()
-    plan = wfp.Plan(p, p["dt"])
+    plan = wfp.Plan(p, p["dt"], overlap_cus=args.overlap_cus)
     info = plan.info
     log(f"plan: {time.perf_counter() - t0:.2f} s, info {info}")
     if args.warmup:

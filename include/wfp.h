@@ -194,7 +194,9 @@ wfp_status wfp_set_state(wfp_plan* plan, int64_t level, const double* hist, cons
 
 /* Per-stage timing with HIP events recorded around every kernel of later
  * wfp_run calls on the plan's stream (enable != 0 clears the accumulators;
- * timing adds event overhead to the march).  wfp_get_profile synchronises the
+ * timing adds event overhead to the march, and while it is on every stage runs
+ * on the plan's stream, without the concurrent history chain, so that each
+ * stage is timed alone).  wfp_get_profile synchronises the
  * stream and returns, per stage, the summed kernel milliseconds and launch
  * counts (arrays of WFP_N_STAGES; either may be NULL). */
 wfp_status wfp_set_profiling(wfp_plan* plan, int32_t enable);

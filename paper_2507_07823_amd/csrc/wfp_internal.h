@@ -1,6 +1,7 @@
 // Internal plan state shared by the single-problem march, the gradient pass
 // and the batched form.  Not part of the C ABI.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -957,14 +957,15 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
 }
 
 // Local sum of lags >= 1 with the weights evaluated on the fly, scaled per row.
-void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, const double* scale, double* out) {
+void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, const double* scale, double* out,
+                      hipEvent_t ea = nullptr, hipEvent_t eb = nullptr) {
   const int nblocks = 8 * (int)nblk(nblk(P->M, kOtfRows), 8);
   const int periodic = P->boundary == WFP_PERIODIC ? 1 : 0;
   const size_t lds = (size_t)(P->NQ - 1) * kOtfChunk * sizeof(double);
-#define WFP_OTF(PP)                                                                                              \
-  hipLaunchKernelGGL(k_local_otf<PP>, dim3(nblocks), dim3(64 * kOtfRows), lds, s, (int)P->M, P->NH, P->NQ, L,     \
-                     P->nb_start, P->nb_count, P->xs, hist, scale, periodic, P->dt, P->delta, P->W, P->ngl,        \
-                     P->otf_z, P->otf_w, P->phitab, out)
+#define WFP_OTF(PP)                                                                                               \
+  hipExtLaunchKernelGGL(k_local_otf<PP>, dim3(nblocks), dim3(64 * kOtfRows), lds, s, ea, eb, 0, (int)P->M, P->NH,  \
+                        P->NQ, L, P->nb_start, P->nb_count, P->xs, hist, scale, periodic, P->dt, P->delta, P->W,    \
+                        P->ngl, P->otf_z, P->otf_w, P->phitab, out)
   switch (P->p) {
     case 2: WFP_OTF(2); break;
     case 4: WFP_OTF(4); break;
@@ -1014,12 +1015,21 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
                        pp, 0, P->ginc);
   }
   {
-    StageTimer st(P, WFP_STAGE_LOCAL, s);
+    // timed with events bound to the kernel's own dispatch (no marker gaps)
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (P->profiling) {
+      ea = take_event(P);
+      eb = take_event(P);
+    }
     if (P->otf)
-      launch_local_otf(P, s, S.hist, L, P->half_beta, P->loc);
+      launch_local_otf(P, s, S.hist, L, P->half_beta, P->loc, ea, eb);
     else
-      hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L, 1,
-                         P->nb_start, P->rowbase, P->acx, P->Qc, S.hist, P->loc);
+      hipExtLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, ea, eb, 0, (int)P->M, P->NQ,
+                            P->NH, L, 1, P->nb_start, P->rowbase, P->acx, P->Qc, S.hist, P->loc);
+    if (P->profiling) {
+      P->pending.push_back({WFP_STAGE_LOCAL, ea, eb});
+      if (P->pending.size() >= 1024) flush_profile(P);
+    }
   }
   {
     StageTimer st(P, WFP_STAGE_SPREAD, sc);
@@ -1130,7 +1140,8 @@ void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, d
   const StateRef S = main_state(P);
   const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
   // the concurrent chain is used when configured and no checkpoints are taken
-  const bool ov = P->overlap_cus > 0 && P->ckpt_every == 0 && n > 0;
+  // (per-stage timing measures each stage alone: one stream while profiling)
+  const bool ov = P->overlap_cus > 0 && P->ckpt_every == 0 && n > 0 && !P->profiling;
   if (ov) {
     // order after earlier work on the caller's stream
     HIPCHK(hipEventRecord(P->ev_join, P->stream));
