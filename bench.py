@@ -255,6 +255,7 @@ def batch_leg(n_inst, levels, m_max):
     t0 = time.perf_counter()
     b = wfp.Batch(insts, [p["dt"] for p in insts])
     setup = time.perf_counter() - t0
+    n_otf = sum(1 for i in range(b.n) if b.plan(i).info["local_mode"] == 2)
     shape = b.autotune(3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -272,7 +273,7 @@ def batch_leg(n_inst, levels, m_max):
     b.reset()
     b.close()
     return {"workload": "batched periodic instances", "instances": n_inst, "M_range": [100, m_max],
-            "total_M": total_m, "levels": levels, "plan_setup_s": setup,
+            "total_M": total_m, "levels": levels, "plan_setup_s": setup, "instances_on_the_fly": n_otf,
             "autotuned": {"rows_per_block": shape[0], "xcd_remap": shape[1]},
             "batched_scatterer_steps_per_s": total_m * levels / t_batch,
             "plain_one_by_one_scatterer_steps_per_s": total_m * levels / t_plain,
@@ -334,7 +335,9 @@ def main():
                     help="levels of the adjoint leg (0 skips it)")
     ap.add_argument("--batch-levels", type=int, default=200, help="levels of the batched leg (0 skips it)")
     ap.add_argument("--batch-instances", type=int, default=512)
-    ap.add_argument("--batch-max-m", type=int, default=10_000)
+    ap.add_argument("--batch-max-m", type=int, default=10_000,
+                    help="largest M of the batched leg (1e5 is the full recipe; its large instances then "
+                         "evaluate their local weights on the fly and a level takes about a second)")
     ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
     ap.add_argument("--overlap-cus", type=int, default=0,
                     help="plan parameter overlap_cus (0: library choice, -1: one stream)")

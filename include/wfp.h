@@ -211,7 +211,9 @@ wfp_status wfp_reset(wfp_plan* plan);
  * list and the whole level is one HIP graph replayed per level; every instance
  * computes exactly what its own plan would (same kernel bodies, same order).
  *   wfp_batch_create  host problem data as for wfp_plan_create (probs[n],
- *                     pars[n]); builds one plan per instance.  Synchronous.
+ *                     pars[n]); builds one plan per instance (one stream each;
+ *                     local weights stored or on the fly per pars[i].local_mode,
+ *                     on the fly with p = 8 only).  Synchronous.
  *                     Errors: WFP_EINVAL (R != 0), WFP_EDOMAIN (free space, or
  *                     an instance whose stages exceed the LDS), as for plans.
  *   wfp_batch_run     march n_steps levels of every instance; sigma_final is a

@@ -16,9 +16,9 @@ struct wfp_batch {
   InstDesc* desc_d = nullptr;
   // work lists (device) and their lengths
   int2 *wl_inc = nullptr, *wl_loc4 = nullptr, *wl_loc8 = nullptr, *wl_a = nullptr, *wl_b = nullptr,
-       *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr;
-  int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0;
-  size_t lds_a = 0, lds_b = 0, lds_c = 0, lds_til = 0;
+       *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr, *wl_otf = nullptr;
+  int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0, n_otf = 0;
+  size_t lds_a = 0, lds_b = 0, lds_c = 0, lds_til = 0, lds_otf = 0;
   int max_sweeps = 0;                  // largest sweep count of the global-solve instances
   // launch shape of the local sum: rows per block (4 or 8) and the XCD remap
   int loc_rows = 4, loc_xcd = 1;
@@ -120,6 +120,14 @@ InstDesc describe(const wfp_plan* P) {
   d.g_rhs = P->g_rhs;
   d.g_xa = P->g_xa;
   d.g_xb = P->g_xb;
+  d.otf = P->otf ? 1 : 0;
+  d.ngl = P->ngl;
+  d.delta = P->delta;
+  d.nb_count = P->nb_count;
+  d.otf_z = P->otf_z;
+  d.otf_w = P->otf_w;
+  d.phitab = P->phitab;
+  d.half_beta = P->half_beta;
   return d;
 }
 
@@ -138,15 +146,21 @@ int2* upload_work(wfp_batch* B, const std::vector<int2>& w, int pad, int& n) {
 void build_batch(wfp_batch* B) {
   const int n = (int)B->plans.size();
   std::vector<InstDesc> desc(n);
-  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows;
+  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf;
   for (int i = 0; i < n; ++i) {
     const wfp_plan* P = B->plans[i];
     desc[i] = describe(P);
     const int M = (int)P->M;
     const int rpb = 256 / desc[i].pp;
     for (int b = 0; b < (int)nblk(M, rpb); ++b) inc.push_back(make_int2(i, b));
-    for (int b = 0; b < (int)nblk(M, 4); ++b) loc4.push_back(make_int2(i, b));
-    for (int b = 0; b < (int)nblk(M, 8); ++b) loc8.push_back(make_int2(i, b));
+    if (P->otf) {
+      if (P->p != 8) fail(WFP_EDOMAIN, "batched on-the-fly local sums take p = 8");
+      for (int b = 0; b < (int)nblk(M, kOtfRows); ++b) otf.push_back(make_int2(i, b));
+      B->lds_otf = std::max(B->lds_otf, (size_t)(P->NQ - 1) * kOtfChunk * sizeof(double));
+    } else {
+      for (int b = 0; b < (int)nblk(M, 4); ++b) loc4.push_back(make_int2(i, b));
+      for (int b = 0; b < (int)nblk(M, 8); ++b) loc8.push_back(make_int2(i, b));
+    }
     for (int b = 0; b < P->n1; ++b) wa.push_back(make_int2(i, b));
     for (int b = 0; b < P->n2 / 2 + 1; ++b) wb.push_back(make_int2(i, b));
     for (int b = 0; b < P->n1; ++b) wc.push_back(make_int2(i, b));
@@ -172,6 +186,10 @@ void build_batch(wfp_batch* B) {
   B->wl_dir = upload_work(B, dir, 1, B->n_dir);
   B->wl_til = upload_work(B, til, 1, B->n_til);
   B->wl_rows = upload_work(B, rows, 1, B->n_rows);
+  B->wl_otf = upload_work(B, otf, 8, B->n_otf);
+  if (B->n_otf)
+    HIPCHK(hipFuncSetAttribute((const void*)kb_local_otf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)B->lds_otf));
   B->level_d = B->alloc<int64_t>(1);
   if (B->lds_b > 160 * 1024 || B->lds_til > 160 * 1024) fail(WFP_EDOMAIN, "batched stage needs more than 160 KB of LDS");
   HIPCHK(hipFuncSetAttribute((const void*)kb_hist_b, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -185,12 +203,16 @@ void enqueue_level(wfp_batch* B) {
   BatchLaunch bl{B->desc_d, nullptr, B->level_d};
   bl.work = B->wl_inc;
   hipLaunchKernelGGL(kb_incident, dim3(B->n_inc), dim3(256), 0, s, bl);
-  if (B->loc_rows == 8) {
+  if (B->loc_rows == 8 && B->n_loc8) {
     bl.work = B->wl_loc8;
     hipLaunchKernelGGL(kb_local, dim3(B->n_loc8), dim3(512), 0, s, bl, B->loc_xcd);
-  } else {
+  } else if (B->n_loc4) {
     bl.work = B->wl_loc4;
     hipLaunchKernelGGL(kb_local, dim3(B->n_loc4), dim3(256), 0, s, bl, B->loc_xcd);
+  }
+  if (B->n_otf) {
+    bl.work = B->wl_otf;
+    hipLaunchKernelGGL(kb_local_otf, dim3(B->n_otf), dim3(64 * kOtfRows), B->lds_otf, s, bl);
   }
   bl.work = B->wl_a;
   hipLaunchKernelGGL(kb_hist_a, dim3(B->n_a), dim3(256), B->lds_a, s, bl);
@@ -283,7 +305,6 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
       // the batch overlaps instances instead of streams: one stream per plan
       wfp_params pi = pars[i];
       pi.overlap_cus = -1;
-      pi.local_mode = 1;   // the batched local sum reads stored weights
       const wfp_status s = wfp_plan_create(&probs[i], &pi, B->bs, &P);
       if (s != WFP_OK) throw Error{s, "instance " + std::to_string(i) + ": " + g_last_error};
       B->plans.push_back(P);

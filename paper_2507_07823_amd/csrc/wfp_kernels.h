@@ -215,6 +215,11 @@ struct InstDesc {
   const int *g_ptr, *g_col;
   const double *g_val, *g_dinv;
   double *g_rhs, *g_xa, *g_xb;
+  // local weights on the fly (p = 8)
+  int otf, ngl;
+  double delta;
+  const int* nb_count;
+  const double *otf_z, *otf_w, *phitab, *half_beta;
 };
 
 // Work item (instance, block within the instance); instance < 0 pads the list.
@@ -226,6 +231,7 @@ struct BatchLaunch {
 
 __global__ void kb_incident(BatchLaunch b);
 __global__ void kb_local(BatchLaunch b, int xcd);
+__global__ void kb_local_otf(BatchLaunch b);
 __global__ void kb_hist_a(BatchLaunch b);
 __global__ void kb_hist_b(BatchLaunch b);
 __global__ void kb_hist_c(BatchLaunch b);

@@ -676,11 +676,13 @@ __device__ __forceinline__ void otf_node(OtfPair<P>& a, double na_q, double nw_q
 // once per block; each row takes the chunk's sources inside its own range,
 // two per lane walking their nodes together.
 template <int P>
-__global__ void __launch_bounds__(1024)
-k_local_otf(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start, const int* __restrict__ nb_count,
-            const double* __restrict__ xs, const double* __restrict__ hist, const double* __restrict__ scale,
-            int periodic, double dt, double delta, int W, int ngl, const double* __restrict__ zs,
-            const double* __restrict__ ws, const double* __restrict__ phitab, double* __restrict__ out) {
+__device__ __forceinline__ void k_local_otf_body(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start,
+                                                 const int* __restrict__ nb_count, const double* __restrict__ xs,
+                                                 const double* __restrict__ hist, const double* __restrict__ scale,
+                                                 int periodic, double dt, double delta, int W, int ngl,
+                                                 const double* __restrict__ zs, const double* __restrict__ ws,
+                                                 const double* __restrict__ phitab, double* __restrict__ out,
+                                                 int lb) {
   extern __shared__ double sg[];                              // [NQ - 1][kOtfChunk]
   __shared__ double tab[kPhiPieces * (kPhiDeg + 1)];
   __shared__ double na[64], nw[64];
@@ -692,7 +694,7 @@ k_local_otf(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start, 
     nw[i] = 0.5 * ws[i];
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int j0 = xcd_block(blockIdx.x, gridDim.x) * kOtfRows;
+  const int j0 = lb * kOtfRows;
   const int j = j0 + wv;
   const bool row = j < M;
   if (lane == 0) {
@@ -761,6 +763,16 @@ k_local_otf(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start, 
   }
   acc = wave_sum(acc);
   if (row && lane == 0) out[j] = scale[j] * acc;
+}
+
+template <int P>
+__global__ void __launch_bounds__(1024)
+k_local_otf(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start, const int* __restrict__ nb_count,
+            const double* __restrict__ xs, const double* __restrict__ hist, const double* __restrict__ scale,
+            int periodic, double dt, double delta, int W, int ngl, const double* __restrict__ zs,
+            const double* __restrict__ ws, const double* __restrict__ phitab, double* __restrict__ out) {
+  k_local_otf_body<P>(M, NH, NQ, L, nb_start, nb_count, xs, hist, scale, periodic, dt, delta, W, ngl, zs, ws, phitab,
+                      out, xcd_block(blockIdx.x, gridDim.x));
 }
 
 #define WFP_OTF_INST(PP)                                                                                        \
@@ -1440,6 +1452,14 @@ __global__ void __launch_bounds__(512) kb_local(BatchLaunch b, int xcd) {
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
   k_local_rhs_body(d.M, d.NQ, d.NH, *b.level, 1, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, d.loc, w.y);
+}
+
+__global__ void __launch_bounds__(1024) kb_local_otf(BatchLaunch b) {
+  const int2 w = b.work[xcd_block(blockIdx.x, gridDim.x)];
+  if (w.x < 0) return;   // block-uniform
+  const InstDesc& d = b.desc[w.x];
+  k_local_otf_body<8>(d.M, d.NH, d.NQ, *b.level, d.nb_start, d.nb_count, d.xs, d.hist, d.half_beta, 1, d.dt,
+                      d.delta, d.W, d.ngl, d.otf_z, d.otf_w, d.phitab, d.loc, w.y);
 }
 
 __global__ void __launch_bounds__(256) kb_hist_a(BatchLaunch b) {

@@ -297,10 +297,11 @@ class Batch:
     """Independent periodic problems marched in lockstep (wfp_batch_*).
 
     problems: list of dicts as for Plan (no receivers), dts: list of time
-    steps, keyword parameters shared by every instance.
+    steps, keyword parameters shared by every instance, per_instance: optional
+    list of per-instance parameter dicts.
     """
 
-    def __init__(self, problems, dts, stream=None, **params):
+    def __init__(self, problems, dts, stream=None, per_instance=None, **params):
         lib = load_library()
         self._lib = lib
         self._keep = []
@@ -309,7 +310,10 @@ class Batch:
         pars = (Params * n)()
         for i, (pb, dt) in enumerate(zip(problems, dts)):
             _fill_problem(probs[i], pb, self._keep)
-            pars[i] = make_params(dt, **params)
+            kw = dict(params)
+            if per_instance is not None:
+                kw.update(per_instance[i])
+            pars[i] = make_params(dt, **kw)
         self._keep += [probs, pars]
         self.n = n
         self._stream = stream if stream is not None else _current_stream()

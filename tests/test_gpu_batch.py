@@ -133,3 +133,34 @@ def test_autotune_and_reset_keep_results(wfp):
     for a, c in zip(first, again):
         assert np.array_equal(a, c)
     b.close()
+
+
+def test_batch_with_on_the_fly_instances(wfp):
+    """Instances whose local weights are evaluated on the fly (local_mode 2)
+    next to stored ones: each matches its own plan with the same mode."""
+    import torch
+    insts = _instances()
+    n = 90
+    modes = [2, 1, 2, 1, 2, 1]
+    b = wfp.Batch(insts, [p["dt"] for p in insts], per_instance=[{"local_mode": m} for m in modes])
+    fin = _batch_run(b, insts, n)
+    worst = 0.0
+    for i, p in enumerate(insts):
+        assert b.plan(i).info["local_mode"] == modes[i]
+        last, _, _ = _plain(wfp, dict(p), n) if modes[i] == 1 else _plain_mode(wfp, p, n, modes[i])
+        e = rho(fin[i], last)
+        say(f"  instance {i} local_mode {modes[i]}: rho {e:.1e}")
+        worst = max(worst, e)
+    b.close()
+    assert worst <= TOL
+
+
+def _plain_mode(w, p, n, mode):
+    import torch
+    plan = w.Plan(p, p["dt"], local_mode=mode)
+    sig = torch.empty((n, p["x"].size), dtype=torch.float64, device="cuda")
+    plan.run(n, sig, 1)
+    torch.cuda.synchronize()
+    out = sig[-1].cpu().numpy(), None, plan.info
+    plan.close()
+    return out
