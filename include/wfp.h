@@ -213,7 +213,9 @@ wfp_status wfp_reset(wfp_plan* plan);
  *   wfp_batch_create  host problem data as for wfp_plan_create (probs[n],
  *                     pars[n]); builds one plan per instance (one stream each;
  *                     local weights stored or on the fly per pars[i].local_mode,
- *                     on the fly with p = 8 only).  Synchronous.
+ *                     on the fly with p = 8 only; local_mode 0 here: stored for the
+ *                     instances with the fewest neighbour pairs while their weights
+ *                     fit in 45 % of the free device memory).  Synchronous.
  *                     Errors: WFP_EINVAL (R != 0), WFP_EDOMAIN (free space, or
  *                     an instance whose stages exceed the LDS), as for plans.
  *   wfp_batch_run     march n_steps levels of every instance; sigma_final is a

@@ -272,6 +272,63 @@ void reset_batch(wfp_batch* B) {
   set_level(B, 0);
 }
 
+// Number of ordered (target, source) pairs closer than delta (periodic box).
+int64_t count_pairs(const double* x, int64_t M, double delta) {
+  std::vector<double> xs(x, x + M);
+  std::sort(xs.begin(), xs.end());
+  // sources within delta of each target, by two pointers over three copies of
+  // the circle (targets in the middle one)
+  std::vector<double> ext(3 * M);
+  for (int64_t i = 0; i < M; ++i) {
+    ext[i] = xs[i] - kTwoPi;
+    ext[i + M] = xs[i];
+    ext[i + 2 * M] = xs[i] + kTwoPi;
+  }
+  int64_t tot = 0, hi = M, lo = 0;
+  for (int64_t j = M; j < 2 * M; ++j) {
+    while (hi < 3 * M && ext[hi] - ext[j] < delta) ++hi;
+    while (ext[j] - ext[lo] >= delta) ++lo;
+    tot += std::min<int64_t>(hi - lo, M);
+  }
+  return tot;
+}
+
+// Local-weight mode of every instance whose parameters leave it to the
+// library: stored weights for the instances with the fewest pairs while their
+// packed weights fit in 45 % of the free device memory (and the set-up array
+// of one instance in 25 %), on the fly for the rest.
+std::vector<int> choose_local_modes(int n, const wfp_problem* probs, const wfp_params* pars) {
+  size_t fr = 0, to = 0;
+  HIPCHK(hipMemGetInfo(&fr, &to));
+  std::vector<int> mode(n);
+  std::vector<std::pair<double, int>> cand;
+  std::vector<double> packed(n), dense(n);
+  for (int i = 0; i < n; ++i) {
+    mode[i] = pars[i].local_mode;
+    if (mode[i] != 0) continue;
+    const double eps = pars[i].eps_window > 0 ? pars[i].eps_window : 1e-12;
+    const double gamma = pars[i].gamma > 0 ? pars[i].gamma : 0.5;
+    const int W = pars[i].W > 0 ? pars[i].W : (int)std::lround(2.0 * std::log(1.0 / eps) / (kPi * gamma));
+    const int p = pars[i].p > 0 ? pars[i].p : 8;
+    const double pairs = (double)count_pairs(probs[i].x, probs[i].M, W * pars[i].dt);
+    packed[i] = 8.0 * pairs * (W / 2 + p);        // nonzero lags per pair
+    dense[i] = 8.0 * pairs * (W + p / 2);
+    cand.push_back({packed[i], i});
+  }
+  std::sort(cand.begin(), cand.end());
+  double used = 0.0;
+  for (auto& c : cand) {
+    const int i = c.second;
+    if (used + packed[i] <= 0.45 * (double)fr && dense[i] <= 0.25 * (double)fr) {
+      mode[i] = 1;
+      used += packed[i];
+    } else {
+      mode[i] = 2;
+    }
+  }
+  return mode;
+}
+
 }  // namespace
 
 extern "C" {
@@ -300,11 +357,13 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
     HIPCHK(hipStreamCreateWithFlags(&B->bs, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+    const std::vector<int> modes = choose_local_modes(n, probs, pars);
     for (int32_t i = 0; i < n; ++i) {
       wfp_plan* P = nullptr;
       // the batch overlaps instances instead of streams: one stream per plan
       wfp_params pi = pars[i];
       pi.overlap_cus = -1;
+      pi.local_mode = modes[i];
       const wfp_status s = wfp_plan_create(&probs[i], &pi, B->bs, &P);
       if (s != WFP_OK) throw Error{s, "instance " + std::to_string(i) + ": " + g_last_error};
       B->plans.push_back(P);
