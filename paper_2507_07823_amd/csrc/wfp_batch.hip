@@ -16,10 +16,17 @@ struct wfp_batch {
   InstDesc* desc_d = nullptr;
   // work lists (device) and their lengths
   int2 *wl_inc = nullptr, *wl_loc4 = nullptr, *wl_loc8 = nullptr, *wl_a = nullptr, *wl_b = nullptr,
-       *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr, *wl_otf = nullptr;
-  int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0, n_otf = 0;
+       *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr, *wl_otf = nullptr,
+       *wl_swt = nullptr, *wl_sww = nullptr;
+  int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0, n_otf = 0,
+      n_swt = 0, n_sww = 0;
   size_t lds_a = 0, lds_b = 0, lds_c = 0, lds_til = 0, lds_otf = 0;
-  int max_sweeps = 0;                  // largest sweep count of the global-solve instances
+  // Jacobi sweeps of the global-solve instances, thread per row (swt) or
+  // wavefront per row (sww); both lists are ordered by decreasing sweep count,
+  // so sweep `it` launches the prefix of cnt_swt[it] (cnt_sww[it]) items
+  // whose instances still iterate
+  int max_sweeps = 0;
+  std::vector<int> cnt_swt, cnt_sww;
   // launch shape of the local sum: rows per block (4 or 8) and the XCD remap
   int loc_rows = 4, loc_xcd = 1;
   hipGraph_t graph = nullptr;
@@ -143,10 +150,33 @@ int2* upload_work(wfp_batch* B, const std::vector<int2>& w, int pad, int& n) {
   return d;
 }
 
+// Work list for a kernel that remaps its blocks to XCDs (xcd_block: XCD k runs
+// positions [k * per, (k + 1) * per)).  Each instance's blocks are cut into 8
+// contiguous chunks and chunk k goes to XCD k's range, so every XCD gets an
+// equal share of every instance (instances differ in cost per block) while
+// neighbouring rows, which share sources, stay on one L2.  `ib` holds
+// (instance, blocks) pairs; the ranges are padded with instance -1.
+std::vector<int2> xcd_balanced(const std::vector<int2>& ib) {
+  std::vector<int2> part[8];
+  for (const int2& e : ib)
+    for (int k = 0; k < 8; ++k)
+      for (int b = (int)((int64_t)e.y * k / 8); b < (int)((int64_t)e.y * (k + 1) / 8); ++b)
+        part[k].push_back(make_int2(e.x, b));
+  size_t per = 0;
+  for (int k = 0; k < 8; ++k) per = std::max(per, part[k].size());
+  std::vector<int2> out;
+  out.reserve(8 * per);
+  for (int k = 0; k < 8; ++k) {
+    out.insert(out.end(), part[k].begin(), part[k].end());
+    out.resize((k + 1) * per, make_int2(-1, 0));
+  }
+  return out;
+}
+
 void build_batch(wfp_batch* B) {
   const int n = (int)B->plans.size();
   std::vector<InstDesc> desc(n);
-  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf;
+  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf;   // otf, loc4, loc8: (instance, blocks)
   for (int i = 0; i < n; ++i) {
     const wfp_plan* P = B->plans[i];
     desc[i] = describe(P);
@@ -155,11 +185,11 @@ void build_batch(wfp_batch* B) {
     for (int b = 0; b < (int)nblk(M, rpb); ++b) inc.push_back(make_int2(i, b));
     if (P->otf) {
       if (P->p != 8) fail(WFP_EDOMAIN, "batched on-the-fly local sums take p = 8");
-      for (int b = 0; b < (int)nblk(M, kOtfRows); ++b) otf.push_back(make_int2(i, b));
+      otf.push_back(make_int2(i, (int)nblk(M, kOtfRows)));
       B->lds_otf = std::max(B->lds_otf, (size_t)(P->NQ - 1) * kOtfChunk * sizeof(double));
     } else {
-      for (int b = 0; b < (int)nblk(M, 4); ++b) loc4.push_back(make_int2(i, b));
-      for (int b = 0; b < (int)nblk(M, 8); ++b) loc8.push_back(make_int2(i, b));
+      loc4.push_back(make_int2(i, (int)nblk(M, 4)));
+      loc8.push_back(make_int2(i, (int)nblk(M, 8)));
     }
     for (int b = 0; b < P->n1; ++b) wa.push_back(make_int2(i, b));
     for (int b = 0; b < P->n2 / 2 + 1; ++b) wb.push_back(make_int2(i, b));
@@ -174,19 +204,38 @@ void build_batch(wfp_batch* B) {
     B->lds_b = std::max(B->lds_b, 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4));
     B->lds_til = std::max(B->lds_til, P->lds_jac);
   }
+  // sweep lists: global-solve instances by decreasing sweep count
+  std::vector<int> order;
+  for (int i = 0; i < n; ++i)
+    if (B->plans[i]->solve_global && B->plans[i]->iters > 1) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return B->plans[a]->iters > B->plans[c]->iters; });
+  std::vector<int2> swt, sww;
+  B->cnt_swt.assign(std::max(B->max_sweeps, 1), 0);
+  B->cnt_sww.assign(std::max(B->max_sweeps, 1), 0);
+  for (int i : order) {
+    const wfp_plan* P = B->plans[i];
+    std::vector<int2>& lst = P->g_wave ? sww : swt;
+    const int rpb = P->g_wave ? 4 : 256;
+    for (int b = 0; b < (int)nblk(P->M, rpb); ++b) lst.push_back(make_int2(i, b));
+    std::vector<int>& cnt = P->g_wave ? B->cnt_sww : B->cnt_swt;
+    for (int it = 1; it < P->iters; ++it) cnt[it] = (int)lst.size();
+  }
   B->lds_c = B->lds_a;
   B->desc_d = B->alloc<InstDesc>(n);
   HIPCHK(hipMemcpyAsync(B->desc_d, desc.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice, B->bs));
   B->wl_inc = upload_work(B, inc, 1, B->n_inc);
-  B->wl_loc4 = upload_work(B, loc4, 8, B->n_loc4);
-  B->wl_loc8 = upload_work(B, loc8, 8, B->n_loc8);
+  B->wl_loc4 = upload_work(B, xcd_balanced(loc4), 8, B->n_loc4);
+  B->wl_loc8 = upload_work(B, xcd_balanced(loc8), 8, B->n_loc8);
   B->wl_a = upload_work(B, wa, 1, B->n_a);
   B->wl_b = upload_work(B, wb, 1, B->n_b);
   B->wl_c = upload_work(B, wc, 1, B->n_c);
   B->wl_dir = upload_work(B, dir, 1, B->n_dir);
   B->wl_til = upload_work(B, til, 1, B->n_til);
   B->wl_rows = upload_work(B, rows, 1, B->n_rows);
-  B->wl_otf = upload_work(B, otf, 8, B->n_otf);
+  B->wl_otf = upload_work(B, xcd_balanced(otf), 8, B->n_otf);
+  B->wl_swt = upload_work(B, swt, 1, B->n_swt);
+  B->wl_sww = upload_work(B, sww, 1, B->n_sww);
   if (B->n_otf)
     HIPCHK(hipFuncSetAttribute((const void*)kb_local_otf, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)B->lds_otf));
@@ -231,7 +280,16 @@ void enqueue_level(wfp_batch* B) {
   if (B->n_rows) {
     bl.work = B->wl_rows;
     hipLaunchKernelGGL(kb_solve_rhs, dim3(B->n_rows), dim3(256), 0, s, bl);
-    for (int it = 1; it < B->max_sweeps; ++it) hipLaunchKernelGGL(kb_jacobi_sweep, dim3(B->n_rows), dim3(256), 0, s, bl, it);
+    for (int it = 1; it < B->max_sweeps; ++it) {
+      if (B->cnt_swt[it]) {
+        bl.work = B->wl_swt;
+        hipLaunchKernelGGL(kb_jacobi_sweep, dim3(B->cnt_swt[it]), dim3(256), 0, s, bl, it);
+      }
+      if (B->cnt_sww[it]) {
+        bl.work = B->wl_sww;
+        hipLaunchKernelGGL(kb_jacobi_sweep_wave, dim3(B->cnt_sww[it]), dim3(256), 0, s, bl, it);
+      }
+    }
   }
   hipLaunchKernelGGL(kb_advance, dim3(1), dim3(64), 0, s, B->level_d);
 }

@@ -239,6 +239,7 @@ __global__ void kb_solve_direct(BatchLaunch b);
 __global__ void kb_solve(BatchLaunch b);
 __global__ void kb_solve_rhs(BatchLaunch b);
 __global__ void kb_jacobi_sweep(BatchLaunch b, int it);
+__global__ void kb_jacobi_sweep_wave(BatchLaunch b, int it);
 __global__ void kb_advance(int64_t* level);
 
 // ---- state movement ----

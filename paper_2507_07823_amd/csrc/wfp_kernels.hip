@@ -958,13 +958,13 @@ __global__ void k_jacobi_sweep(int M, const int* __restrict__ ptr, const int* __
 
 // The same sweep with one wavefront per row (lanes over the row's entries),
 // for rows with many nearby sources: the entry loads coalesce.
-__global__ void __launch_bounds__(256)
-k_jacobi_sweep_wave(int M, const int* __restrict__ ptr, const int* __restrict__ col,
-                    const double* __restrict__ val, const double* __restrict__ dinv,
-                    const double* __restrict__ rhs, const double* __restrict__ xin, double* __restrict__ xout,
-                    double* __restrict__ save_row, const int* __restrict__ perm) {
+__device__ __forceinline__ void k_jacobi_sweep_wave_body(int M, const int* __restrict__ ptr,
+                               const int* __restrict__ col, const double* __restrict__ val,
+                               const double* __restrict__ dinv, const double* __restrict__ rhs,
+                               const double* __restrict__ xin, double* __restrict__ xout,
+                               double* __restrict__ save_row, const int* __restrict__ perm, int bid) {
   const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int j = bid * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= M) return;
   double acc = 0.0;
   for (int k = ptr[j] + lane; k < ptr[j + 1]; k += 64) acc = fma(val[k], xin[col[k]], acc);
@@ -974,6 +974,14 @@ k_jacobi_sweep_wave(int M, const int* __restrict__ ptr, const int* __restrict__ 
     xout[j] = v;
     if (save_row) save_row[perm[j]] = v;
   }
+}
+
+__global__ void __launch_bounds__(256)
+k_jacobi_sweep_wave(int M, const int* __restrict__ ptr, const int* __restrict__ col,
+                    const double* __restrict__ val, const double* __restrict__ dinv,
+                    const double* __restrict__ rhs, const double* __restrict__ xin, double* __restrict__ xout,
+                    double* __restrict__ save_row, const int* __restrict__ perm) {
+  k_jacobi_sweep_wave_body(M, ptr, col, val, dinv, rhs, xin, xout, save_row, perm, blockIdx.x);
 }
 
 // Per-step solve on small nearby-runs: I + S is block diagonal over maximal
@@ -1526,6 +1534,19 @@ __global__ void __launch_bounds__(256) kb_jacobi_sweep(BatchLaunch b, int it) {
   const double* xin = (it & 1) ? d.g_xa : d.g_xb;
   double* xout = (it == d.iters - 1) ? slot : ((it & 1) ? d.g_xb : d.g_xa);
   k_jacobi_sweep_body(d.M, d.g_ptr, d.g_col, d.g_val, d.g_dinv, d.g_rhs, xin, xout, nullptr, nullptr, w.y);
+}
+
+// The same sweep with one wavefront per row (4 rows per block), for instances
+// whose rows hold many nearby sources.
+__global__ void __launch_bounds__(256) kb_jacobi_sweep_wave(BatchLaunch b, int it) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  if (it >= d.iters) return;
+  double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
+  const double* xin = (it & 1) ? d.g_xa : d.g_xb;
+  double* xout = (it == d.iters - 1) ? slot : ((it & 1) ? d.g_xb : d.g_xa);
+  k_jacobi_sweep_wave_body(d.M, d.g_ptr, d.g_col, d.g_val, d.g_dinv, d.g_rhs, xin, xout, nullptr, nullptr, w.y);
 }
 
 __global__ void kb_advance(int64_t* level) {
