@@ -54,11 +54,12 @@ typedef int32_t wfp_status;
 #define WFP_ENOMEM (-3)     /* device or host allocation failed */
 #define WFP_EHIP (-4)       /* a HIP runtime call failed */
 #define WFP_ESTATE (-5)     /* call not valid in the plan's current state */
+#define WFP_ENONFINITE (-6) /* check_finite: the newest densities or the mode state hold NaN or Inf */
 
 #define WFP_PERIODIC 0      /* periodic box [-pi, pi) (Section 2) */
 #define WFP_FREE_SPACE 1    /* free space via outgoing windowing (Section 4.4) */
 
-#define WFP_ABI_VERSION 2
+#define WFP_ABI_VERSION 3
 
 typedef struct wfp_plan wfp_plan;
 
@@ -101,7 +102,11 @@ typedef struct {
   int32_t local_mode;      /* 1: local weights stored per pair (read every level); 2: evaluated on the
                               fly every level (memory O(M), arithmetic O(pairs N_L p)); 0: stored when
                               they fit in 60% of the free device memory, else on the fly   [0] */
-  int32_t reserved;
+  int32_t check_finite;    /* nonzero: every wfp_run ends by checking the newest density level and the
+                              mode state alpha, alpha' for NaN or Inf (one small kernel), waits for the
+                              plan's stream and returns WFP_ENONFINITE if any is found (the levels stay
+                              marched: an unstable march, e.g. with very stiff springs, is caught
+                              here); 0: no check, wfp_run stays asynchronous      [0] */
 } wfp_params;
 
 /* Derived sizes of a plan (read-only report). */
@@ -151,7 +156,9 @@ wfp_status wfp_plan_info(const wfp_plan* plan, wfp_info* info);
  *   save_every >= 1 (ignored when sigma_out is NULL).
  *   u_recv_out device [n_steps][R] or NULL: u(x_r, t_L) at every level computed
  *              (u_L + u_H, eqs. (localSol2) and (historySol1)).
- * Asynchronous on the plan's stream.  Errors: WFP_EINVAL, WFP_EHIP. */
+ * Asynchronous on the plan's stream, unless the plan checks for non-finite
+ * values (check_finite), which waits for the stream at the end.
+ * Errors: WFP_EINVAL, WFP_EHIP, WFP_ENONFINITE. */
 wfp_status wfp_run(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t save_every,
                    double* u_recv_out);
 

@@ -210,6 +210,9 @@ struct wfp_plan {
   std::vector<void*> owned;
   // per-stage event timing
   bool profiling = false;
+  // finite-value check at the end of wfp_run
+  bool check_finite = false;
+  int* finite_flag = nullptr;
   double prof_ms[WFP_N_STAGES] = {};
   int64_t prof_n[WFP_N_STAGES] = {};
   struct Pending {

@@ -250,5 +250,8 @@ __global__ void k_ring_io(int64_t K, int W, int64_t L, int n1, int n2, int64_t n
 __global__ void k_modes_io(int64_t K, int n1, int n2, int to_user, double2* __restrict__ a,
                            double2* __restrict__ user);
 __global__ void k_fill(double* __restrict__ p, int64_t n, double v);
+__global__ void k_fill_int(int* __restrict__ p, int64_t n, int v);
+__global__ void k_check_finite(const double* __restrict__ a, int64_t na, const double* __restrict__ b, int64_t nb,
+                               int* __restrict__ flag);
 
 }  // namespace wfp

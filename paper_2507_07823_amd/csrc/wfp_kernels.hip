@@ -1596,4 +1596,20 @@ __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
   if (i < n) p[i] = v;
 }
 
+__global__ void k_fill_int(int* __restrict__ p, int64_t n, int v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Sets *flag to 1 when any of a[0 .. na) or b[0 .. nb) is NaN or infinite
+// (grid-stride loop; b may be NULL with nb = 0).
+__global__ void k_check_finite(const double* __restrict__ a, int64_t na, const double* __restrict__ b, int64_t nb,
+                               int* __restrict__ flag) {
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride)
+    bad |= !isfinite(i < na ? a[i] : b[i - na]);
+  if (bad) atomicOr(flag, 1);
+}
+
 }  // namespace wfp

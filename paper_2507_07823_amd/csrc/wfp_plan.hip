@@ -165,6 +165,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   P->M = M;
   P->R = prob->R;
   P->ckpt_every = par->checkpoint_every;
+  P->check_finite = par->check_finite != 0;
   P->overlap_cus = par->overlap_cus;
   P->boundary = prob->boundary;
   P->dt = par->dt;
@@ -1507,6 +1508,26 @@ wfp_status wfp_get_profile(wfp_plan* P, double* ms, int64_t* launches) {
   });
 }
 
+namespace {
+// The newest density level and alpha, alpha' checked for NaN or Inf; waits
+// for the plan's stream.
+void check_finite(wfp_plan* P) {
+  hipStream_t s = P->stream;
+  if (!P->finite_flag) P->finite_flag = P->alloc<int>(1);
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, P->finite_flag, 1, 0);
+  const double* newest = P->hist + (int64_t)((P->level - 1) % P->NH) * P->M;
+  const int64_t na = 2 * P->npos;
+  hipLaunchKernelGGL(k_check_finite, dim3(std::min<int64_t>(nblk(P->M, 256), 1024)), dim3(256), 0, s, newest,
+                     P->M, (const double*)P->alpha, na, P->finite_flag);
+  hipLaunchKernelGGL(k_check_finite, dim3(std::min<int64_t>(nblk(na, 256), 1024)), dim3(256), 0, s,
+                     (const double*)P->dalpha, na, nullptr, 0, P->finite_flag);
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, P->finite_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (bad) fail(WFP_ENONFINITE, "non-finite densities or mode state after level " + std::to_string(P->level));
+}
+}  // namespace
+
 wfp_status wfp_run(wfp_plan* P, int64_t n_steps, double* sigma_out, int64_t save_every, double* u_recv_out) {
   if (!P || n_steps < 0) {
     g_last_error = "bad plan or step count";
@@ -1519,6 +1540,7 @@ wfp_status wfp_run(wfp_plan* P, int64_t n_steps, double* sigma_out, int64_t save
   return guard([&] {
     HIPCHK(hipSetDevice(P->device));
     run_levels(P, n_steps, sigma_out, sigma_out ? save_every : 1, u_recv_out);
+    if (P->check_finite && n_steps > 0) check_finite(P);
   });
 }
 
@@ -1649,6 +1671,7 @@ const char* wfp_status_string(wfp_status s) {
     case WFP_ENOMEM: return "out of memory";
     case WFP_EHIP: return "HIP runtime error";
     case WFP_ESTATE: return "invalid state";
+    case WFP_ENONFINITE: return "non-finite values in the march";
     default: return "unknown status";
   }
 }

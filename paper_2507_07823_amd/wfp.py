@@ -20,6 +20,7 @@ WFP_EDOMAIN = -2
 WFP_ENOMEM = -3
 WFP_EHIP = -4
 WFP_ESTATE = -5
+WFP_ENONFINITE = -6
 PERIODIC = 0
 FREE_SPACE = 1
 STAGES = ("spread", "fft_fwd", "modes", "rbc", "fft_inv", "local", "solve", "receivers")
@@ -39,7 +40,7 @@ class Params(ctypes.Structure):
                 ("n_gl_local", ctypes.c_int32), ("n_gl_pq", ctypes.c_int32), ("rbc_period", ctypes.c_int32),
                 ("nufft_width", ctypes.c_int32), ("solve_iters", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32), ("overlap_cus", ctypes.c_int32),
-                ("local_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("local_mode", ctypes.c_int32), ("check_finite", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -270,3 +270,28 @@ def test_concurrent_chain_is_bitwise_identical(wfp):
     plan = wfp.Plan(p, p["dt"])
     say(f"  library choice: overlap_cus = {plan.info['overlap_cus']}")
     plan.close()
+
+
+def test_check_finite(wfp):
+    """check_finite: a healthy march returns OK with the same densities bit for
+    bit; a NaN planted in the density history (from the host, through
+    wfp_set_state) reaches the new level and wfp_run returns WFP_ENONFINITE."""
+    import torch
+    p = workloads.small_periodic()
+    plain = wfp.Plan(p, p["dt"])
+    a, _ = plain.march(120)
+    plain.close()
+    plan = wfp.Plan(p, p["dt"], check_finite=1)
+    b, _ = plan.march(120)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    st = plan.get_state()
+    hist = st["hist"].clone()
+    hist[3, 5] = float("nan")
+    plan.set_state(st["L"], hist, st["ring"], st["alpha"], st["dalpha"])
+    say("check_finite: NaN planted in the density history at lag 4")
+    with pytest.raises(wfp.WFPError) as ei:
+        plan.run(1)
+    assert ei.value.status == wfp.WFP_ENONFINITE
+    assert plan.level == st["L"] + 1
+    plan.close()
