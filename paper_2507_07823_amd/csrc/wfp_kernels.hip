@@ -522,9 +522,14 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
 // at offset off_m within the row).  Lane m loads lag m's (a, c, off); the
 // wavefront then works as four groups of 16 lanes, group g on lag mb + g of
 // the current quad of lags: each group streams one contiguous block of
-// weights and densities (one 128-byte line per 16 lanes), eight elements per
-// lane with every load issued before use.
+// weights and densities, two consecutive elements per lane and load (16-byte
+// loads, 256 bytes per group), eight elements per lane with every load issued
+// before use.  A pair's second element may lie one past the block (its value
+// is dropped; the packed arrays carry two spare elements) or, for the
+// densities, wrap to source 0.
 constexpr int kMaxNQ = 64;
+// two consecutive doubles, 8-byte aligned (one 16-byte load)
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
 __device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb_start,
             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
@@ -549,23 +554,32 @@ __device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t 
     int l0 = st + (int)(vx & 0xffff);
     if (l0 >= M) l0 -= M;
     for (int i0 = 0; i0 < c; i0 += 128) {
-      double qv[8], hv[8];
+      d2u qv[4], hv[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = i0 + gl + 16 * u;
-        qv[u] = 0.0;
-        hv[u] = 0.0;
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 2 * gl + 32 * u;
+        qv[u] = d2u{0.0, 0.0};
+        hv[u] = d2u{0.0, 0.0};
         if (i < c) {
           int la = l0 + i;
           if (la >= M) la -= M;
-          qv[u] = qp[i];
-          hv[u] = hp[la];
+          qv[u] = *(const d2u*)(qp + i);
+          if (la + 1 < M) {
+            hv[u] = *(const d2u*)(hp + la);
+          } else {
+            hv[u].x = hp[la];
+            hv[u].y = hp[0];
+          }
+          if (i + 1 >= c) {
+            qv[u].y = 0.0;
+            hv[u].y = 0.0;
+          }
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; u += 2) {
-        acc0 = fma(qv[u], hv[u], acc0);
-        acc1 = fma(qv[u + 1], hv[u + 1], acc1);
+      for (int u = 0; u < 4; ++u) {
+        acc0 = fma(qv[u].x, hv[u].x, acc0);
+        acc1 = fma(qv[u].y, hv[u].y, acc1);
       }
     }
   }
@@ -1324,7 +1338,9 @@ __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int6
   }
 }
 
-__global__ void __launch_bounds__(512)
+// at most 128 VGPRs, so that two blocks share a compute unit: the chain runs
+// its n2/2 + 1 blocks on one XCD's 32 compute units in one round
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos, const double2* __restrict__ T1,
          const double2* __restrict__ tw, const double* __restrict__ dk1, const double* __restrict__ dk2,
          const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,

@@ -539,7 +539,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     HIPCHK(hipStreamSynchronize(s));
     P->n_weights_stored = packed;
     P->rowbase = P->alloc<int64_t>(M);
-    P->Qc = P->alloc<double>(packed);
+    P->Qc = P->alloc<double>(packed + 2);   // spare elements for paired loads
     upload(P->rowbase, rb, s);
     hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, 1,
                        P->nb_count, P->qoff, P->Q, P->ac, P->rowbase, P->Qc);
@@ -1289,7 +1289,7 @@ void gradx_setup(wfp_plan* P) {
   }
   P->drowbase = P->alloc<int64_t>(M);
   P->acxd = P->alloc<uint2>(acxh.size());
-  P->DQa = P->alloc<double>(packed);
+  P->DQa = P->alloc<double>(packed + 2);   // spare elements for paired loads
   upload(P->drowbase, rb, s);
   upload(P->acxd, acxh, s);
   hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, 0,
