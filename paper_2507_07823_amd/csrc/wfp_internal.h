@@ -146,7 +146,11 @@ struct wfp_plan {
   uint2* acx = nullptr;         // per (row, lag): (a | c << 16, packed offset within the row)
   int nqd = 0;                  // quads of lags per row (local-sum tasks per row)
   int64_t* rowbase = nullptr;   // packed offset of each row
-  double* ginc = nullptr;       // -g_j(t_L), per row
+  double* ginc = nullptr;       // -g_j(t_L), per row (set by the gradient pass's drive)
+  // driving data of g_chunk consecutive levels from g_lvl0 (row L - g_lvl0)
+  double* gbuf = nullptr;
+  int g_chunk = 0;
+  int64_t g_lvl0 = -1;
   double* loc = nullptr;        // local sum of lags >= 1, per row
   // solve tiles
   int *tile_r0 = nullptr, *tile_el = nullptr, *tile_g0 = nullptr, *tile_left = nullptr, *tile_n = nullptr;
@@ -157,10 +161,16 @@ struct wfp_plan {
   bool otf = false;
   double *otf_z = nullptr, *otf_w = nullptr, *phitab = nullptr, *half_beta = nullptr;
   double* halfs = nullptr;       // 1/2 per row (the local part without beta)
-  // concurrent history chain: masked streams for the chain (sb) and the rest (sa)
+  // stored weights: the lags >= 2 part of the local sum of level L, in
+  // locb[L & 1] (its lag-1 part is added after sigma^{L-1} is solved)
+  double* locb = nullptr;
+  // concurrent history chain: masked streams for the chain (sb) and the rest
+  // (sa), and sd on the same compute units as sa for the lags >= 2 part of the
+  // next level's local sum
   int overlap_cus = 0;
-  hipStream_t sa = nullptr, sb = nullptr;
+  hipStream_t sa = nullptr, sb = nullptr, sd = nullptr;
   hipEvent_t ev_solved = nullptr, ev_chain = nullptr, ev_join = nullptr;
+  hipEvent_t ev_big[2] = {nullptr, nullptr};
   // global-sweep solve (when tiles do not fit in LDS)
   bool solve_global = false, g_wave = false;
   int *g_ptr = nullptr, *g_col = nullptr;
@@ -223,10 +233,11 @@ struct wfp_plan {
   std::vector<hipEvent_t> free_events;
 
   ~wfp_plan() {
-    // sa and sb are shared by every plan on the device (never destroyed)
+    // sa, sb and sd are shared by every plan on the device (never destroyed)
     if (sa) (void)hipStreamSynchronize(sa);
     if (sb) (void)hipStreamSynchronize(sb);
-    for (hipEvent_t e : {ev_solved, ev_chain, ev_join})
+    if (sd) (void)hipStreamSynchronize(sd);
+    for (hipEvent_t e : {ev_solved, ev_chain, ev_join, ev_big[0], ev_big[1]})
       if (e) (void)hipEventDestroy(e);
     for (auto& q : pending) {
       (void)hipEventDestroy(q.a);

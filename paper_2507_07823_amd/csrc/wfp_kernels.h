@@ -84,12 +84,18 @@ __global__ void k_count_nonzero(int M, int NQ, const int* __restrict__ nb_count,
                                 unsigned long long* __restrict__ out);
 
 // ---- per-level kernels ----
-__global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb_start,
+__global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
                             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                             const double* __restrict__ Qc, const double* __restrict__ hist,
-                            double* __restrict__ loc);
+                            const double* __restrict__ addin, double* __restrict__ loc);
+__global__ void k_local_lag1(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
+                             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
+                             const double* __restrict__ Qc, const double* __restrict__ hist,
+                             const double* __restrict__ addin, double* __restrict__ loc);
 __global__ void k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta,
                            Packets pk, int pp, int deriv, double* __restrict__ ginc);
+__global__ void k_incident_levels(int M, int64_t L0, double dt, const double* __restrict__ xs,
+                                  const double* __restrict__ beta, Packets pk, int pp, double* __restrict__ out);
 __global__ void k_spread_weights(int nf, double hf, double inv_alpha, double beta_es, const double* __restrict__ xs,
                                  int M, const int* __restrict__ cstart, const int* __restrict__ ccount,
                                  const int64_t* __restrict__ woff, double* __restrict__ w);

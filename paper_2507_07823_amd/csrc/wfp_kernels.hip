@@ -516,8 +516,9 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Local sum of lags m >= m0 (m0 = 1 for the right-hand side, 0 for the
-// derivative sums of the gradient), one row per wavefront.  The row's packed weights
+// Local sum of lags m0 <= m < m1 (m0 = 1 or 2 for the right-hand side, 0 for
+// the derivative sums of the gradient; m1 = NQ, or 2 for the lag-1 part), plus
+// addin[j] when addin is not NULL, one row per wavefront.  The row's packed weights
 // are one block per lag m (sources a_m .. a_m + c_m - 1 of its neighbour list,
 // at offset off_m within the row).  Lane m loads lag m's (a, c, off); the
 // wavefront then works as four groups of 16 lanes, group g on lag mb + g of
@@ -531,24 +532,25 @@ constexpr int kMaxNQ = 64;
 // two consecutive doubles, 8-byte aligned (one 16-byte load)
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
-__device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb_start,
-            const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
-            const double* __restrict__ hist, double* __restrict__ loc, int bid) {
+__device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t L, int m0, int m1,
+            const int* __restrict__ nb_start, const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
+            const double* __restrict__ Qc, const double* __restrict__ hist, const double* __restrict__ addin,
+            double* __restrict__ loc, int bid) {
   const int lane = threadIdx.x & 63;
   const int lb = bid;
   const int j = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= M) return;   // no block-level barrier in this kernel
   const int st = nb_start[j];
   uint2 mine = make_uint2(0u, 0u);
-  if (lane >= m0 && lane < NQ) mine = acx[(int64_t)j * NQ + lane];
+  if (lane >= m0 && lane < m1) mine = acx[(int64_t)j * NQ + lane];
   const double* __restrict__ q = Qc + rowbase[j];
   const int grp = lane >> 4, gl = lane & 15;
   double acc0 = 0.0, acc1 = 0.0;
-  for (int mb = m0; mb < NQ; mb += 4) {
+  for (int mb = m0; mb < m1; mb += 4) {
     const int m = mb + grp;
     const int src = m < 64 ? m : 0;
     const unsigned vx = __shfl(mine.x, src, 64), vy = __shfl(mine.y, src, 64);
-    const int c = m < NQ ? (int)(vx >> 16) : 0;
+    const int c = m < m1 ? (int)(vx >> 16) : 0;
     const double* __restrict__ qp = q + vy;
     const double* __restrict__ hp = hist + (int64_t)mod_slot(L - m, NH) * M;
     int l0 = st + (int)(vx & 0xffff);
@@ -584,14 +586,27 @@ __device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t 
     }
   }
   const double accs = wave_sum(acc0 + acc1);
-  if (lane == 0) loc[j] = accs;
+  if (lane == 0) loc[j] = addin ? addin[j] + accs : accs;
 }
 
 __global__ void __launch_bounds__(256)
-k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, const int* __restrict__ nb_start,
+k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
-            const double* __restrict__ hist, double* __restrict__ loc) {
-  k_local_rhs_body(M, NQ, NH, L, m0, nb_start, rowbase, acx, Qc, hist, loc, xcd_block(blockIdx.x, gridDim.x));
+            const double* __restrict__ hist, const double* __restrict__ addin, double* __restrict__ loc) {
+  k_local_rhs_body(M, NQ, NH, L, m0, m1, nb_start, rowbase, acx, Qc, hist, addin, loc,
+                   xcd_block(blockIdx.x, gridDim.x));
+}
+
+// The lag-1 part of the right-hand side local sum added to the lags >= 2 part
+// (which depends only on levels before L - 1, so it can be computed while
+// level L - 1 is still being solved): its own kernel name, so that kernel
+// traces keep the two apart.
+__global__ void __launch_bounds__(256)
+k_local_lag1(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start, const int64_t* __restrict__ rowbase,
+             const uint2* __restrict__ acx, const double* __restrict__ Qc, const double* __restrict__ hist,
+             const double* __restrict__ addin, double* __restrict__ loc) {
+  k_local_rhs_body(M, NQ, NH, L, 1, 2, nb_start, rowbase, acx, Qc, hist, addin, loc,
+                   xcd_block(blockIdx.x, gridDim.x));
 }
 
 // Local sum of lags m >= 1 with the weights evaluated on the fly (when the
@@ -842,6 +857,15 @@ __global__ void __launch_bounds__(256)
 k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta, Packets pk, int pp,
            int deriv, double* __restrict__ ginc) {
   k_incident_body(M, t, xs, beta, pk, pp, deriv, ginc, blockIdx.x);
+}
+
+// Driving data of gridDim.y consecutive levels L0, L0 + 1, ... (row y of out
+// for level L0 + y): the values k_incident writes level by level.
+__global__ void __launch_bounds__(256)
+k_incident_levels(int M, int64_t L0, double dt, const double* __restrict__ xs, const double* __restrict__ beta,
+                  Packets pk, int pp, double* __restrict__ out) {
+  const int64_t L = L0 + blockIdx.y;
+  k_incident_body(M, (double)L * dt, xs, beta, pk, pp, 0, out + (int64_t)blockIdx.y * M, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1475,7 +1499,8 @@ __global__ void __launch_bounds__(512) kb_local(BatchLaunch b, int xcd) {
   const int2 w = b.work[xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
-  k_local_rhs_body(d.M, d.NQ, d.NH, *b.level, 1, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, d.loc, w.y);
+  k_local_rhs_body(d.M, d.NQ, d.NH, *b.level, 1, d.NQ, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, nullptr, d.loc,
+                   w.y);
 }
 
 __global__ void __launch_bounds__(1024) kb_local_otf(BatchLaunch b) {

@@ -540,6 +540,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->n_weights_stored = packed;
     P->rowbase = P->alloc<int64_t>(M);
     P->Qc = P->alloc<double>(packed + 2);   // spare elements for paired loads
+    P->locb = P->alloc<double>(2 * (size_t)M);
     upload(P->rowbase, rb, s);
     hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, 1,
                        P->nb_count, P->qoff, P->Q, P->ac, P->rowbase, P->Qc);
@@ -928,30 +929,40 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     HIPCHK(hipGetDeviceProperties(&prop, P->device));
     const int ncu = prop.multiProcessorCount;
     if (P->overlap_cus >= ncu) fail(WFP_EINVAL, "overlap_cus must be below the number of compute units");
+    // the chain (sb) and the solve (sa) on the first overlap_cus compute
+    // units, the local sum and driving data (sd) on the rest
     const int words = (ncu + 31) / 32;
-    std::vector<uint32_t> ma(words, 0u), mb(words, 0u);
+    std::vector<uint32_t> ma(words, 0u), mb(words, 0u), md(words, 0u);
     for (int c = 0; c < ncu; ++c) {
-      if (c < P->overlap_cus) mb[c / 32] |= 1u << (c % 32);
-      else ma[c / 32] |= 1u << (c % 32);
+      if (c < P->overlap_cus) {
+        mb[c / 32] |= 1u << (c % 32);
+        ma[c / 32] |= 1u << (c % 32);
+      } else {
+        md[c / 32] |= 1u << (c % 32);
+      }
     }
     // one pair of masked streams per (device, split), shared by all plans and
     // kept until the process ends: each masked stream holds a hardware queue
     static std::mutex mu;
-    static std::map<std::pair<int, int>, std::pair<hipStream_t, hipStream_t>> pool;
+    static std::map<std::pair<int, int>, std::array<hipStream_t, 3>> pool;
     std::lock_guard<std::mutex> lock(mu);
     auto key = std::make_pair(P->device, P->overlap_cus);
     auto it = pool.find(key);
     if (it == pool.end()) {
-      hipStream_t a = nullptr, b = nullptr;
-      HIPCHK(hipExtStreamCreateWithCUMask(&a, (uint32_t)words, ma.data()));
-      HIPCHK(hipExtStreamCreateWithCUMask(&b, (uint32_t)words, mb.data()));
-      it = pool.emplace(key, std::make_pair(a, b)).first;
+      std::array<hipStream_t, 3> st{nullptr, nullptr, nullptr};
+      HIPCHK(hipExtStreamCreateWithCUMask(&st[0], (uint32_t)words, ma.data()));
+      HIPCHK(hipExtStreamCreateWithCUMask(&st[1], (uint32_t)words, mb.data()));
+      HIPCHK(hipExtStreamCreateWithCUMask(&st[2], (uint32_t)words, md.data()));
+      it = pool.emplace(key, st).first;
     }
-    P->sa = it->second.first;
-    P->sb = it->second.second;
+    P->sa = it->second[0];
+    P->sb = it->second[1];
+    P->sd = it->second[2];
     HIPCHK(hipEventCreateWithFlags(&P->ev_solved, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&P->ev_chain, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_big[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_big[1], hipEventDisableTiming));
   }
   zero_state(P);
   HIPCHK(hipStreamSynchronize(s));
@@ -990,31 +1001,62 @@ struct StateRef {
 
 StateRef main_state(wfp_plan* P) { return {P->hist, P->ring, P->alpha, P->dalpha}; }
 
-// One level L, in stream order: driving data (unless `driven`: P->ginc already
-// holds it), local sum (levels < L), the history part (three kernels; the
-// free-space projection when due), solve, receivers.
-void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const ExtraSources& ex, double* save,
-                 double* u_recv_row, bool overlap = false) {
-  // overlap: the history chain on P->sb (its own compute units) after the
-  // previous level's solve and receivers, everything else on P->sa; the solve
-  // waits for both.
-  hipStream_t s = overlap ? P->sa : P->stream;
-  hipStream_t sc = overlap ? P->sb : s;
-  if (overlap) HIPCHK(hipStreamWaitEvent(sc, P->ev_solved, 0));
-  const bool periodic = P->boundary == WFP_PERIODIC;
-  // a multiple of 8 blocks, so the XCD-aware block remap is a bijection
-  const int nlocblk = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
-  const unsigned nb_b = (unsigned)(P->n2 / 2 + 1);
-  const size_t lds_b = 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4);
-  const double t = (double)L * P->dt;
-  const double* sig_prev = S.hist + (int64_t)(((L - 1) % P->NH + P->NH) % P->NH) * P->M;
-  if (!driven) {
-    const Packets pk{P->npk, periodic ? 1 : 0, P->packets};
+// Stored weights: the lags >= 2 part of level L's local sum into locb[L & 1]
+// (reads sigma^{L-2} and older only), and its lag-1 part added to it.
+void launch_local_big(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, hipEvent_t ea = nullptr,
+                      hipEvent_t eb = nullptr) {
+  const int nb = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
+  hipExtLaunchKernelGGL(k_local_rhs, dim3(nb), dim3(kRowThreads), 0, s, ea, eb, 0, (int)P->M, P->NQ, P->NH, L, 2,
+                        P->NQ, P->nb_start, P->rowbase, P->acx, P->Qc, hist, (const double*)nullptr,
+                        P->locb + (L & 1) * P->M);
+}
+
+// Row of level L's driving data g_j(t_L) (eq. (gj)).  The values depend on L
+// only, so they are computed for g_chunk levels at a time, on `s` (every
+// reader of the previous chunk is ordered before it on that stream, or
+// before the solve the stream has waited for).
+const double* driving_row(wfp_plan* P, hipStream_t s, int64_t L) {
+  if (!P->gbuf) {
+    P->g_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(8 << 20) / P->M));
+    P->gbuf = P->alloc<double>((size_t)P->g_chunk * P->M);
+  }
+  if (P->g_lvl0 < 0 || L < P->g_lvl0 || L >= P->g_lvl0 + P->g_chunk) {
+    const Packets pk{P->npk, P->boundary == WFP_PERIODIC ? 1 : 0, P->packets};
     int pp = 1;
     while (pp < P->npk) pp *= 2;
-    hipLaunchKernelGGL(k_incident, dim3(nblk(P->M, 256 / pp)), dim3(256), 0, s, (int)P->M, t, P->xs, P->beta, pk,
-                       pp, 0, P->ginc);
+    hipLaunchKernelGGL(k_incident_levels, dim3(nblk(P->M, 256 / pp), P->g_chunk), dim3(256), 0, s, (int)P->M, L,
+                       P->dt, P->xs, P->beta, pk, pp, P->gbuf);
+    P->g_lvl0 = L;
   }
+  return P->gbuf + (L - P->g_lvl0) * P->M;
+}
+
+void launch_local_lag1(wfp_plan* P, hipStream_t s, const double* hist, int64_t L) {
+  const int nb = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
+  hipLaunchKernelGGL(k_local_lag1, dim3(nb), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L, P->nb_start,
+                     P->rowbase, P->acx, P->Qc, hist, P->locb + (L & 1) * P->M, P->loc);
+}
+
+// One level L, in stream order: driving data (unless `driven`: P->ginc already
+// holds it), local sum (levels < L), the history part (three kernels; the
+// free-space projection when due), solve, receivers.  Stored weights: the
+// local sum is its lags >= 2 part and its lag-1 part.  `ahead`: the driving
+// data and the whole local sum of level L were launched on P->sd by the
+// caller, which signals ev_big[L & 1] after them.
+void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const ExtraSources& ex, double* save,
+                 double* u_recv_row, bool overlap = false, bool ahead = false) {
+  // overlap: the history chain on P->sb (its own compute units) after the
+  // previous level's solve and receivers, everything else on P->sa; the solve
+  // waits for both.  ahead: the solve and receivers follow the chain on P->sb
+  // (no wait between queues on the chain -> solve -> chain path).
+  hipStream_t sc = overlap ? P->sb : P->stream;
+  hipStream_t s = overlap ? (ahead ? P->sb : P->sa) : P->stream;
+  if (overlap && sc != s) HIPCHK(hipStreamWaitEvent(sc, P->ev_solved, 0));
+  const bool periodic = P->boundary == WFP_PERIODIC;
+  const unsigned nb_b = (unsigned)(P->n2 / 2 + 1);
+  const size_t lds_b = 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4);
+  const double* sig_prev = S.hist + (int64_t)(((L - 1) % P->NH + P->NH) % P->NH) * P->M;
+  const double* gin = driven ? P->ginc : driving_row(P, s, L);
   {
     // timed with events bound to the kernel's own dispatch (no marker gaps)
     hipEvent_t ea = nullptr, eb = nullptr;
@@ -1022,11 +1064,17 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
       ea = take_event(P);
       eb = take_event(P);
     }
-    if (P->otf)
+    if (P->otf && overlap) {
+      // on the local sum's compute units, joined before the solve
+      HIPCHK(hipStreamWaitEvent(P->sd, P->ev_solved, 0));
+      launch_local_otf(P, P->sd, S.hist, L, P->half_beta, P->loc);
+      HIPCHK(hipEventRecord(P->ev_big[L & 1], P->sd));
+      HIPCHK(hipStreamWaitEvent(s, P->ev_big[L & 1], 0));
+    } else if (P->otf) {
       launch_local_otf(P, s, S.hist, L, P->half_beta, P->loc, ea, eb);
-    else
-      hipExtLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, ea, eb, 0, (int)P->M, P->NQ,
-                            P->NH, L, 1, P->nb_start, P->rowbase, P->acx, P->Qc, S.hist, P->loc);
+    } else if (!ahead) {
+      launch_local_big(P, s, S.hist, L, ea, eb);
+    }
     if (P->profiling) {
       P->pending.push_back({WFP_STAGE_LOCAL, ea, eb});
       if (P->pending.size() >= 1024) flush_profile(P);
@@ -1060,27 +1108,29 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
     hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), sc, P->fft_n2, P->n1, P->V,
                        P->tw, (double2*)P->grid2);
   }
-  if (overlap) {
+  if (overlap && sc != s) {
     HIPCHK(hipEventRecord(P->ev_chain, sc));
     HIPCHK(hipStreamWaitEvent(s, P->ev_chain, 0));
   }
   double* slot = S.hist + (int64_t)(L % P->NH) * P->M;
   {
     StageTimer st(P, WFP_STAGE_SOLVE, s);
+    if (ahead) HIPCHK(hipStreamWaitEvent(s, P->ev_big[L & 1], 0));   // driving data and local sum of level L
+    else if (!P->otf) launch_local_lag1(P, s, S.hist, L);
     if (P->n_direct_tiles > 0)
       hipLaunchKernelGGL(k_solve_direct, dim3(P->n_direct_tiles), dim3(256), 0, s, (int)P->M, P->dt_g0, P->dt_n,
-                         P->dt_p0, P->pt_cs, P->pt_cn, P->pt_inv, P->inv, P->ginc, P->loc, P->i0s, P->iw,
+                         P->dt_p0, P->pt_cs, P->pt_cn, P->pt_inv, P->inv, gin, P->loc, P->i0s, P->iw,
                          P->beta, P->grid2, P->nf, P->width, slot, save, P->perm);
     if (P->ntile > 0)
       hipLaunchKernelGGL(k_solve, dim3(P->ntile), dim3(P->solve_threads), P->lds_jac, s, (int)P->M, P->iters,
                          P->ext_max, P->tile_r0, P->tile_el, P->tile_g0, P->tile_left, P->tile_n, P->srow_g,
-                         P->srow_dinv, P->srow_ptr, P->scol, P->sval, P->ginc, P->loc, P->i0s, P->iw, P->beta,
+                         P->srow_dinv, P->srow_ptr, P->scol, P->sval, gin, P->loc, P->i0s, P->iw, P->beta,
                          P->grid2, P->nf, P->width, slot, save, P->perm);
     if (P->solve_global) {
       const unsigned nb = nblk(P->M, 256);
       double* xa = P->g_xa;
       double* xb = P->g_xb;
-      hipLaunchKernelGGL(k_solve_rhs, dim3(nb), dim3(256), 0, s, (int)P->M, P->ginc, P->loc, P->beta, P->i0s, P->iw,
+      hipLaunchKernelGGL(k_solve_rhs, dim3(nb), dim3(256), 0, s, (int)P->M, gin, P->loc, P->beta, P->i0s, P->iw,
                          P->grid2, P->nf, P->width, P->g_dinv, P->g_rhs, P->iters > 1 ? xa : slot);
       if (P->iters == 1 && save)
         hipLaunchKernelGGL(k_unsort, dim3(nb), dim3(256), 0, s, (int)P->M, P->perm, slot, save);
@@ -1143,25 +1193,44 @@ void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, d
   // the concurrent chain is used when configured and no checkpoints are taken
   // (per-stage timing measures each stage alone: one stream while profiling)
   const bool ov = P->overlap_cus > 0 && P->ckpt_every == 0 && n > 0 && !P->profiling;
+  // stored weights, concurrent chain: once level L - 1 is solved, sd computes
+  // level L's driving data and lag-1 part, then the lags >= 2 part of level
+  // L + 1 (it needs sigma^{L-1} and older only), while sb runs level L's chain
+  // and sa its solve
+  const bool ahead = ov && !P->otf;
+  // the queue that solves (and signals ev_solved)
+  hipStream_t sm = ahead ? P->sb : P->sa;
   if (ov) {
     // order after earlier work on the caller's stream
     HIPCHK(hipEventRecord(P->ev_join, P->stream));
-    HIPCHK(hipStreamWaitEvent(P->sa, P->ev_join, 0));
-    HIPCHK(hipEventRecord(P->ev_solved, P->sa));
+    HIPCHK(hipStreamWaitEvent(sm, P->ev_join, 0));
+    HIPCHK(hipEventRecord(P->ev_solved, sm));
+  }
+  if (ahead) {
+    HIPCHK(hipStreamWaitEvent(P->sd, P->ev_solved, 0));
+    launch_local_big(P, P->sd, S.hist, P->level);
   }
   for (int64_t i = 0; i < n; ++i) {
     const int64_t L = P->level + i;
+    if (ahead) {
+      // sigma^{L-1} and older are final once level L - 1 is solved
+      HIPCHK(hipStreamWaitEvent(P->sd, P->ev_solved, 0));
+      driving_row(P, P->sd, L);
+      launch_local_lag1(P, P->sd, S.hist, L);
+      HIPCHK(hipEventRecord(P->ev_big[L & 1], P->sd));
+      if (i + 1 < n) launch_local_big(P, P->sd, S.hist, L + 1);
+    }
     if (P->ckpt_every > 0 && P->ck_from0 && L > 0 && L % P->ckpt_every == 0) {
       const size_t c = (size_t)(L / P->ckpt_every) - 1;
       while (P->ckpts.size() <= c) P->ckpts.push_back(P->alloc<char>(state_bytes(P)));
       copy_state(P, S, P->ckpts[c], true);
     }
     double* save = (sigma_out && i % save_every == 0) ? sigma_out + (i / save_every) * P->M : nullptr;
-    march_level(P, S, L, false, none, save, u_recv_out ? u_recv_out + i * P->R : nullptr, ov);
+    march_level(P, S, L, false, none, save, u_recv_out ? u_recv_out + i * P->R : nullptr, ov, ahead);
   }
   if (ov) {
     // later work on the caller's stream waits for the whole run
-    HIPCHK(hipEventRecord(P->ev_join, P->sa));
+    HIPCHK(hipEventRecord(P->ev_join, sm));
     HIPCHK(hipStreamWaitEvent(P->stream, P->ev_join, 0));
   }
   HIPCHK(hipGetLastError());
@@ -1329,7 +1398,7 @@ void deriv_field(wfp_plan* P, const StateRef& S) {
 void deriv_local(wfp_plan* P, const StateRef& S, int64_t L) {
   const int nlocblk = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
   hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, P->stream, (int)P->M, P->NQ, P->NH, L, 0,
-                     P->nb_start, P->drowbase, P->acxd, P->DQa, S.hist, P->xloc);
+                     P->NQ, P->nb_start, P->drowbase, P->acxd, P->DQa, S.hist, (const double*)nullptr, P->xloc);
 }
 
 void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, double* grad_x) {
@@ -1562,7 +1631,7 @@ wfp_status wfp_local_part(wfp_plan* P, double* out) {
     } else {
       const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
       hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)M, P->NQ, P->NH, P->level, 1,
-                         P->nb_start, P->rowbase, P->acx, P->Qc, P->hist, P->loc);
+                         P->NQ, P->nb_start, P->rowbase, P->acx, P->Qc, P->hist, (const double*)nullptr, P->loc);
       hipLaunchKernelGGL(k_unscale, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->beta, P->loc);
     }
     hipLaunchKernelGGL(k_unsort, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->perm, P->loc, out);
