@@ -149,9 +149,11 @@ def stage_bytes(info, stage):
     M, K, nf, W, mm = info["M"], info["K"], info["n_fine"], info["W"], info["m_max"]
     nnz = info["n_weights_nonzero"]
     if stage == "local":
-        # nonzero local weights (lag >= 1), the density stack, per-row data
-        # (x, beta, rhs out, start/count, offset), the type-2 grid
-        return 8 * nnz + 8 * (mm - 1) * M + 40 * M + 8 * nf
+        # the lags >= 2 kernel: nonzero weights of lags 2 .. m_max - 1, those
+        # density levels, the per-row lag table (8 bytes per lag), neighbour
+        # start and packed offset per row, one double out per row
+        nl = mm - 2
+        return 8 * (nnz - info["n_weights_lag1"]) + 8 * nl * M + 8 * nl * M + 20 * M
     if stage == "modes":
         # FFT output rows k and N/2-k, dk1, dk2, p/q tables, spectra ring, alpha,
         # alpha', write ring slot, alpha, alpha', y

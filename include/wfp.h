@@ -59,7 +59,7 @@ typedef int32_t wfp_status;
 #define WFP_PERIODIC 0      /* periodic box [-pi, pi) (Section 2) */
 #define WFP_FREE_SPACE 1    /* free space via outgoing windowing (Section 4.4) */
 
-#define WFP_ABI_VERSION 3
+#define WFP_ABI_VERSION 4
 
 typedef struct wfp_plan wfp_plan;
 
@@ -93,12 +93,13 @@ typedef struct {
   int32_t solve_iters;     /* Jacobi sweeps of the per-step solve            [from a contraction bound] */
   int32_t checkpoint_every;/* > 0: wfp_run stores the march state every this many levels (for
                               wfp_adjoint); 0: no checkpoints                [0] */
-  int32_t overlap_cus;     /* > 0: wfp_run puts the history chain (spread, FFTs, modes) on its
-                              own stream restricted to the first overlap_cus compute units,
-                              concurrent with the local sum on the others (results are the same
-                              bit for bit); < 0: one stream; 0: the library's choice, which is
-                              one XCD's compute units when the local sum reads at least 64 MB
-                              per level, else one stream                          [0] */
+  int32_t overlap_cus;     /* > 0: wfp_run puts the history chain (spread, FFTs, modes) and the
+                              solve on a stream restricted to the first overlap_cus compute
+                              units and the local sum on the others, the next level's local
+                              sum (lags >= 2) overlapping the current level's chain and solve
+                              (results are the same bit for bit); < 0: one stream; 0: the
+                              library's choice, which is one XCD's compute units when the local
+                              sum reads at least 64 MB per level, else one stream   [0] */
   int32_t local_mode;      /* 1: local weights stored per pair (read every level); 2: evaluated on the
                               fly every level (memory O(M), arithmetic O(pairs N_L p)); 0: stored when
                               they fit in 60% of the free device memory, else on the fly   [0] */
@@ -122,6 +123,7 @@ typedef struct {
   int32_t overlap_cus;         /* compute units of the concurrent history chain, -1: one stream */
   int32_t local_mode;          /* 1: stored local weights, 2: evaluated on the fly */
   int32_t reserved;
+  int64_t n_weights_lag1;      /* nonzero stored local weights of lag 1 (part of n_weights_nonzero) */
 } wfp_info;
 
 /* Stages of one level, for wfp_get_profile. */

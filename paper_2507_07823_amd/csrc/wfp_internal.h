@@ -189,7 +189,7 @@ struct wfp_plan {
   int64_t* rqoff = nullptr;
   double* Qr = nullptr;
   double *cheb_phi = nullptr, *cheb_g = nullptr;
-  int64_t n_weights_nonzero = 0, n_weights_stored = 0;
+  int64_t n_weights_nonzero = 0, n_weights_stored = 0, n_weights_lag1 = 0;
   // host copies kept for the gradient pass set-up
   std::vector<double> xs_h, xr_h;
   std::vector<int> nbc_h, rnbs_h, rnbc_h;

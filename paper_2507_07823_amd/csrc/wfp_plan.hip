@@ -507,6 +507,14 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     HIPCHK(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     P->n_weights_nonzero = (int64_t)h;
+    // lag 1 alone (lags 0 .. 1 counted from lag 1)
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_count_nonzero, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, 2,
+                       P->nb_count, P->qoff, P->Q, cnt);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    P->n_weights_lag1 = (int64_t)h;
     P->release(cnt);
   }
   // ---- pack the weights of lags >= 1 to each row's nonzero source ranges ----
@@ -1543,6 +1551,7 @@ wfp_status wfp_plan_info(const wfp_plan* P, wfp_info* info) {
   info->solve_mode = P->solve_global ? 1 : 0;
   info->overlap_cus = P->overlap_cus;
   info->local_mode = P->otf ? 2 : 1;
+  info->n_weights_lag1 = P->n_weights_lag1;
   return WFP_OK;
 }
 

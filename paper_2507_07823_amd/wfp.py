@@ -52,7 +52,7 @@ class Info(ctypes.Structure):
                 ("delta", ctypes.c_double), ("b", ctypes.c_double), ("solve_contraction", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("n_weights_nonzero", ctypes.c_int64),
                 ("n_weights_stored", ctypes.c_int64), ("solve_mode", ctypes.c_int32), ("overlap_cus", ctypes.c_int32),
-                ("local_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("local_mode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_weights_lag1", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
