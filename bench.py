@@ -40,9 +40,19 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_local_rhs.periodic-multiband-M1
 COPY_BYTES = 1 << 28          # the calibration copy moves 256 MiB
 
 
+# the local-sum kernel's own source text (its comment, the paired-load type,
+# the body and the kernel), from the first marker up to the second
+KERNEL_REGION = ("// Local sum of lags m0 <= m < m1", "// The lag-1 part of the right-hand side local sum")
+
+
 def kernel_source_hash():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 of the local-sum kernel's source region: the counter summary
+    holds only while that text is unchanged."""
+    with open(KERNEL_SOURCE, encoding="utf-8") as f:
+        src = f.read()
+    a = src.index(KERNEL_REGION[0])
+    b = src.index(KERNEL_REGION[1], a)
+    return hashlib.sha256(src[a:b].encode("utf-8")).hexdigest()
 
 
 def read_traffic():

@@ -599,14 +599,56 @@ k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restr
 
 // The lag-1 part of the right-hand side local sum added to the lags >= 2 part
 // (which depends only on levels before L - 1, so it can be computed while
-// level L - 1 is still being solved): its own kernel name, so that kernel
-// traces keep the two apart.
+// level L - 1 is still being solved).  A row's lag-1 block is short (pairs
+// closer than about p/2 dt), so 16 lanes take a row, two consecutive elements
+// per lane and load as in k_local_rhs, and a wavefront takes four rows.
 __global__ void __launch_bounds__(256)
 k_local_lag1(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start, const int64_t* __restrict__ rowbase,
              const uint2* __restrict__ acx, const double* __restrict__ Qc, const double* __restrict__ hist,
              const double* __restrict__ addin, double* __restrict__ loc) {
-  k_local_rhs_body(M, NQ, NH, L, 1, 2, nb_start, rowbase, acx, Qc, hist, addin, loc,
-                   xcd_block(blockIdx.x, gridDim.x));
+  const int gl = threadIdx.x & 15;
+  const int j = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 4) + (threadIdx.x >> 4);
+  if (j >= M) return;   // no barrier; the reduction below stays inside the row's 16 lanes
+  const uint2 v = acx[(int64_t)j * NQ + 1];
+  const int c = (int)(v.x >> 16);
+  const double* __restrict__ qp = Qc + rowbase[j] + v.y;
+  const double* __restrict__ hp = hist + (int64_t)mod_slot(L - 1, NH) * M;
+  int l0 = nb_start[j] + (int)(v.x & 0xffff);
+  if (l0 >= M) l0 -= M;
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int i0 = 0; i0 < c; i0 += 128) {
+    d2u qv[4], hv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 2 * gl + 32 * u;
+      qv[u] = d2u{0.0, 0.0};
+      hv[u] = d2u{0.0, 0.0};
+      if (i < c) {
+        int la = l0 + i;
+        if (la >= M) la -= M;
+        qv[u] = *(const d2u*)(qp + i);
+        if (la + 1 < M) {
+          hv[u] = *(const d2u*)(hp + la);
+        } else {
+          hv[u].x = hp[la];
+          hv[u].y = hp[0];
+        }
+        if (i + 1 >= c) {
+          qv[u].y = 0.0;
+          hv[u].y = 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc0 = fma(qv[u].x, hv[u].x, acc0);
+      acc1 = fma(qv[u].y, hv[u].y, acc1);
+    }
+  }
+  double sum = acc0 + acc1;
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (gl == 0) loc[j] = addin[j] + sum;
 }
 
 // Local sum of lags m >= 1 with the weights evaluated on the fly (when the

@@ -1040,7 +1040,7 @@ const double* driving_row(wfp_plan* P, hipStream_t s, int64_t L) {
 }
 
 void launch_local_lag1(wfp_plan* P, hipStream_t s, const double* hist, int64_t L) {
-  const int nb = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
+  const int nb = 8 * (int)nblk(nblk(P->M, 16), 8);   // 16 rows per block of 256 threads
   hipLaunchKernelGGL(k_local_lag1, dim3(nb), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L, P->nb_start,
                      P->rowbase, P->acx, P->Qc, hist, P->locb + (L & 1) * P->M, P->loc);
 }

@@ -272,6 +272,37 @@ def test_concurrent_chain_is_bitwise_identical(wfp):
     plan.close()
 
 
+def test_pipelined_runs_of_any_length(wfp):
+    """The pipelined schedule (next level's local sum started while the
+    current level is finished) split into runs of 1, 2, 3 and 257 levels, with
+    a state restored in between and the driving data crossing a block of
+    levels: bit for bit the one-stream march."""
+    import torch
+    p = workloads.multiband_periodic()
+    runs = [1, 2, 3, 257, 1]
+    out = []
+    for cus in (-1, 32):
+        plan = wfp.Plan(p, p["dt"], overlap_cus=cus)
+        i = plan.info
+        gst = _state_to_gpu(workloads.random_state(6, i["M"], i["K"], i["W"], i["m_max"]))
+        plan.set_state(5000, gst["hist"], gst["ring"], gst["alpha"], gst["dalpha"])
+        rows = []
+        for k in runs:
+            sig, _ = plan.march(k)
+            rows.append(sig)
+        st = plan.get_state()
+        st = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in st.items()}
+        more, _ = plan.march(40)
+        plan.set_state(st["L"], st["hist"], st["ring"], st["alpha"], st["dalpha"])
+        again, _ = plan.march(40)
+        torch.cuda.synchronize()
+        assert torch.equal(more, again)
+        out.append(torch.cat(rows + [more]).cpu().numpy())
+        plan.close()
+    say(f"pipelined runs {runs} + 40 (restored): levels {out[0].shape[0]}")
+    assert np.array_equal(out[0], out[1])
+
+
 def test_check_finite(wfp):
     """check_finite: a healthy march returns OK with the same densities bit for
     bit; a NaN planted in the density history (from the host, through
