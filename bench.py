@@ -255,7 +255,7 @@ def adjoint_leg(levels, every):
             "gradient_over_plain_time": t_bwd / t_fwd, "finite": ok}
 
 
-def batch_leg(n_inst, levels, m_max):
+def batch_leg(n_inst, levels, m_max, trial_levels=3):
     """The batched form on uneven periodic instances (M log-uniform in
     [100, m_max], dt in {1e-3, 2e-3, 5e-3}, beta ~ U[1, 10], one random pulse
     each), autotuned, against the same instances marched one plain plan at a
@@ -268,7 +268,7 @@ def batch_leg(n_inst, levels, m_max):
     b = wfp.Batch(insts, [p["dt"] for p in insts])
     setup = time.perf_counter() - t0
     n_otf = sum(1 for i in range(b.n) if b.plan(i).info["local_mode"] == 2)
-    shape = b.autotune(3)
+    shape = b.autotune(trial_levels)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.run(levels)
@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--batch-max-m", type=int, default=10_000,
                     help="largest M of the batched leg (1e5 is the full recipe; its large instances then "
                          "evaluate their local weights on the fly and a level takes about a second)")
+    ap.add_argument("--batch-full-levels", type=int, default=3,
+                    help="levels of a second batched leg over the full M range [100, 1e5] (0 skips it)")
     ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
     ap.add_argument("--overlap-cus", type=int, default=0,
                     help="plan parameter overlap_cus (0: library choice, -1: one stream)")
@@ -436,6 +438,10 @@ def main():
     if args.batch_levels > 0:
         batch = batch_leg(args.batch_instances, args.batch_levels, args.batch_max_m)
         log(f"batch leg: {batch}")
+    batch_full = None
+    if args.batch_full_levels > 0:
+        batch_full = batch_leg(args.batch_instances, args.batch_full_levels, 100_000, trial_levels=1)
+        log(f"full-range batch leg: {batch_full}")
 
     clumped = None
     if args.clumped_levels > 0:
@@ -454,7 +460,8 @@ def main():
         "config": {"workload": "periodic multiband springs", "M": M, "dt": p["dt"], "K": info["K"],
                    "W": info["W"], "p": info["p"], "n_fine": info["n_fine"], "pairs": info["n_pairs"],
                    "levels_timed": args.steps, "parallelism": "single GPU"},
-        "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch, "clumped": clumped, "cpu_baseline": cpu,
+        "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch,
+        "batch_full_range": batch_full, "clumped": clumped, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()
