@@ -303,6 +303,40 @@ def test_pipelined_runs_of_any_length(wfp):
     assert np.array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("case", ["free_space_stored", "periodic_on_the_fly"])
+def test_overlap_forced_matches_one_stream(wfp, case):
+    """Concurrent schedules the library does not pick by itself, forced with
+    overlap_cus = 32: free space with stored weights (the RBC projection on the
+    chain's queue, receivers on) and on-the-fly weights (the local sum on its
+    own queue): bit for bit the one-stream march."""
+    import torch
+    rng = np.random.default_rng(21)
+    if case == "free_space_stored":
+        prm = Params(dt=5e-3, boundary=FREE_SPACE)
+        lo, hi = prm.omega
+        x = rng.uniform(lo + 0.1, hi - 0.1, 3000)
+        p = dict(x=x, beta=rng.uniform(1, 10, x.size), packets=np.array([[1.0, lo - 0.2, 0.1, 20.0, 0.0]]),
+                 boundary=FREE_SPACE, dt=prm.dt, x_recv=np.array([lo + 0.05, 0.0, hi - 0.05]))
+        kw = dict(local_mode=1)
+    else:
+        p = workloads.small_periodic()
+        kw = dict(local_mode=2)
+    n = 160
+    out = []
+    for cus in (-1, 32):
+        plan = wfp.Plan(p, p["dt"], overlap_cus=cus, **kw)
+        assert plan.info["overlap_cus"] == cus
+        sig, u = plan.march(n)
+        torch.cuda.synchronize()
+        out.append((sig.cpu().numpy(), None if u is None else u.cpu().numpy()))
+        plan.close()
+    say(f"forced overlap, {case}: levels={n} max |sigma| = {np.max(np.abs(out[0][0])):.3e}")
+    assert np.max(np.abs(out[0][0])) > 0
+    assert np.array_equal(out[0][0], out[1][0])
+    if out[0][1] is not None:
+        assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_check_finite(wfp):
     """check_finite: a healthy march returns OK with the same densities bit for
     bit; a NaN planted in the density history (from the host, through
