@@ -208,6 +208,7 @@ struct wfp_plan {
   double2 *aring = nullptr, *aalpha = nullptr, *adalpha = nullptr;
   double *segsig = nullptr, *segD = nullptr, *gb_acc = nullptr, *gx_acc = nullptr;
   double *xloc = nullptr, *xw = nullptr, *fprime = nullptr, *gridd = nullptr, *esort = nullptr;
+  double* xloc2 = nullptr;       // forward derivative local sum of the level being swept back
   double2* yd = nullptr;
   int *adj_ptr = nullptr, *adj_rr = nullptr, *adj_ri = nullptr;
   int *rsort = nullptr, *rcs = nullptr, *rcc = nullptr;

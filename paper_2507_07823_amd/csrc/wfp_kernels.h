@@ -177,15 +177,22 @@ __global__ void k_adj_drive(int M, int R, int NQ, int64_t L, int64_t N, const in
                             const double* __restrict__ Qr, const double* __restrict__ dQr,
                             const double* __restrict__ e, const double* __restrict__ beta,
                             double* __restrict__ ginc, double* __restrict__ xw);
-__global__ void k_fwd_dterm(int M, const double* __restrict__ fprime, const double* __restrict__ xloc,
-                            const int* __restrict__ i0s, const double* __restrict__ iw,
-                            const double* __restrict__ gridd, int nf, int width, double* __restrict__ D);
+__global__ void k_fwd_dterm(int M, const double* __restrict__ fprime, const int* __restrict__ i0s,
+                            const double* __restrict__ iw, const double* __restrict__ gridd, int nf, int width,
+                            double* __restrict__ D);
 __global__ void k_adj_grad(int M, const double* __restrict__ q, const double* __restrict__ sig,
                            const double* __restrict__ beta, const double* __restrict__ D,
-                           const double* __restrict__ xloc, const double* __restrict__ xw,
-                           const int* __restrict__ i0s, const double* __restrict__ iw,
+                           const double* __restrict__ Dloc, const double* __restrict__ xloc,
+                           const double* __restrict__ xw, const int* __restrict__ i0s, const double* __restrict__ iw,
                            const double* __restrict__ gridd, int nf, int width, double* __restrict__ gb,
                            double* __restrict__ gx);
+__global__ void k_local_deriv2(int M, int NQ, int NH, const int* __restrict__ nb_start,
+                               const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
+                               const double* __restrict__ Qc, const double* __restrict__ h1, int64_t r1,
+                               const double* __restrict__ h2, int64_t L2, double* __restrict__ out1,
+                               double* __restrict__ out2);
+__global__ void k_seg_head(int M, int NH, int64_t a, int nlev, const double* __restrict__ hist,
+                           double* __restrict__ out);
 __global__ void k_unscale(int M, const double* __restrict__ beta, double* __restrict__ v);
 __global__ void k_gather(int n, const int* __restrict__ idx, const double* __restrict__ in, double* __restrict__ out);
 __global__ void k_unsort(int M, const int* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out);

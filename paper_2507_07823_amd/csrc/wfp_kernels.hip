@@ -651,6 +651,78 @@ k_local_lag1(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
   if (gl == 0) loc[j] = addin[j] + sum;
 }
 
+// The gradient pass's two signed derivative local sums (lags 0 .. NQ - 1) in
+// one stream of the derivative weights: out1 from levels held in a linear
+// buffer (row r1 - m for lag m: the forward densities of the segment and the
+// NQ - 1 levels before it), out2 from a density ring (slot L2 - m mod NH: the
+// adjoint state).  Same row layout and loads as k_local_rhs_body.
+__global__ void __launch_bounds__(256)
+k_local_deriv2(int M, int NQ, int NH, const int* __restrict__ nb_start, const int64_t* __restrict__ rowbase,
+               const uint2* __restrict__ acx, const double* __restrict__ Qc, const double* __restrict__ h1, int64_t r1,
+               const double* __restrict__ h2, int64_t L2, double* __restrict__ out1, double* __restrict__ out2) {
+  const int lane = threadIdx.x & 63;
+  const int j = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= M) return;   // no block-level barrier in this kernel
+  const int st = nb_start[j];
+  uint2 mine = make_uint2(0u, 0u);
+  if (lane < NQ) mine = acx[(int64_t)j * NQ + lane];
+  const double* __restrict__ q = Qc + rowbase[j];
+  const int grp = lane >> 4, gl = lane & 15;
+  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+  for (int mb = 0; mb < NQ; mb += 4) {
+    const int m = mb + grp;
+    const int src = m < 64 ? m : 0;
+    const unsigned vx = __shfl(mine.x, src, 64), vy = __shfl(mine.y, src, 64);
+    const int c = m < NQ ? (int)(vx >> 16) : 0;
+    const double* __restrict__ qp = q + vy;
+    const double* __restrict__ hp1 = h1 + (r1 - (m < NQ ? m : 0)) * M;
+    const double* __restrict__ hp2 = h2 + (int64_t)mod_slot(L2 - m, NH) * M;
+    int l0 = st + (int)(vx & 0xffff);
+    if (l0 >= M) l0 -= M;
+    for (int i0 = 0; i0 < c; i0 += 128) {
+      d2u qv[4], hv[4], gv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 2 * gl + 32 * u;
+        qv[u] = d2u{0.0, 0.0};
+        hv[u] = d2u{0.0, 0.0};
+        gv[u] = d2u{0.0, 0.0};
+        if (i < c) {
+          int la = l0 + i;
+          if (la >= M) la -= M;
+          qv[u] = *(const d2u*)(qp + i);
+          if (la + 1 < M) {
+            hv[u] = *(const d2u*)(hp1 + la);
+            gv[u] = *(const d2u*)(hp2 + la);
+          } else {
+            hv[u].x = hp1[la];
+            hv[u].y = hp1[0];
+            gv[u].x = hp2[la];
+            gv[u].y = hp2[0];
+          }
+          if (i + 1 >= c) {
+            qv[u].y = 0.0;
+            hv[u].y = 0.0;
+            gv[u].y = 0.0;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a0 = fma(qv[u].x, hv[u].x, a0);
+        a1 = fma(qv[u].y, hv[u].y, a1);
+        b0 = fma(qv[u].x, gv[u].x, b0);
+        b1 = fma(qv[u].y, gv[u].y, b1);
+      }
+    }
+  }
+  const double s1 = wave_sum(a0 + a1), s2 = wave_sum(b0 + b1);
+  if (lane == 0) {
+    out1[j] = s1;
+    out2[j] = s2;
+  }
+}
+
 // Local sum of lags m >= 1 with the weights evaluated on the fly (when the
 // stored weights would not fit): for every source l within delta,
 //   sum_i om_i(d) p_i(s_i),   p_i = the degree-(P-1) interpolant of the
@@ -1477,21 +1549,23 @@ __global__ void k_adj_drive(int M, int R, int NQ, int64_t L, int64_t N, const in
 
 // Forward derivative data of one level: D_j = f'(x_j - t) + (signed
 // derivative local sum of lags m >= 0) + d/dx u_H(x_j).
-__global__ void k_fwd_dterm(int M, const double* __restrict__ fprime, const double* __restrict__ xloc,
-                            const int* __restrict__ i0s, const double* __restrict__ iw,
-                            const double* __restrict__ gridd, int nf, int width, double* __restrict__ D) {
+__global__ void k_fwd_dterm(int M, const double* __restrict__ fprime, const int* __restrict__ i0s,
+                            const double* __restrict__ iw, const double* __restrict__ gridd, int nf, int width,
+                            double* __restrict__ D) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= M) return;
-  D[j] = fprime[j] + xloc[j] + interp_pre(j, i0s, iw, gridd, nf, width);
+  D[j] = fprime[j] + interp_pre(j, i0s, iw, gridd, nf, width);
 }
 
 // Accumulate one level of the gradient (sorted order):
 //   gbeta_j += -q_j sigma_j / beta_j^2
-//   gx_j    += q_j D_j + sigma_j (xloc_j + xw_j + d/dx u_H^adj(x_j))
+//   gx_j    += q_j (D_j + Dloc_j) + sigma_j (xloc_j + xw_j + d/dx u_H^adj(x_j))
+// with D = f' + d/dx u_H of the forward state and Dloc the forward
+// derivative local sum.
 __global__ void k_adj_grad(int M, const double* __restrict__ q, const double* __restrict__ sig,
                            const double* __restrict__ beta, const double* __restrict__ D,
-                           const double* __restrict__ xloc, const double* __restrict__ xw,
-                           const int* __restrict__ i0s, const double* __restrict__ iw,
+                           const double* __restrict__ Dloc, const double* __restrict__ xloc,
+                           const double* __restrict__ xw, const int* __restrict__ i0s, const double* __restrict__ iw,
                            const double* __restrict__ gridd, int nf, int width, double* __restrict__ gb,
                            double* __restrict__ gx) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1500,8 +1574,18 @@ __global__ void k_adj_grad(int M, const double* __restrict__ q, const double* __
   gb[j] -= qj * sj / (b * b);
   if (gx) {
     const double w = xloc[j] + xw[j] + interp_pre(j, i0s, iw, gridd, nf, width);
-    gx[j] += qj * D[j] + sj * w;
+    gx[j] += qj * (D[j] + Dloc[j]) + sj * w;
   }
+}
+
+// Rows 0 .. nlev - 1 of out = levels a - nlev .. a - 1 of a density ring
+// (slot L mod NH), the head of the gradient pass's segment buffer.
+__global__ void k_seg_head(int M, int NH, int64_t a, int nlev, const double* __restrict__ hist,
+                           double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nlev * M) return;
+  const int r = (int)(t / M), j = (int)(t % M);
+  out[t] = hist[(int64_t)mod_slot(a - nlev + r, NH) * M + j];
 }
 
 // v_j <- v_j / (beta_j / 2): a local sum with the stored beta_j/2-scaled weights

@@ -1275,10 +1275,12 @@ void grad_setup(wfp_plan* P) {
   P->rdalpha = P->alloc<double2>(P->npos);
   P->aalpha = P->alloc<double2>(P->npos);
   P->adalpha = P->alloc<double2>(P->npos);
-  P->segsig = P->alloc<double>((size_t)C * M);
+  // the segment's densities after the NQ - 1 levels before it (row NQ - 1 + L - a)
+  P->segsig = P->alloc<double>((size_t)(C + P->NQ - 1) * M);
   P->gb_acc = P->alloc<double>(M);
   P->gx_acc = P->alloc<double>(M);
   P->xloc = P->alloc<double>(M);
+  P->xloc2 = P->alloc<double>(M);
   P->xw = P->alloc<double>(M);
   P->fprime = P->alloc<double>(M);
   P->gridd = P->alloc<double>(P->nf);
@@ -1402,13 +1404,6 @@ void deriv_field(wfp_plan* P, const StateRef& S) {
                      (double2*)P->gridd);
 }
 
-// Signed derivative local sum of lags m >= 0 of the densities in S at level L.
-void deriv_local(wfp_plan* P, const StateRef& S, int64_t L) {
-  const int nlocblk = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
-  hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, P->stream, (int)P->M, P->NQ, P->NH, L, 0,
-                     P->NQ, P->nb_start, P->drowbase, P->acxd, P->DQa, S.hist, (const double*)nullptr, P->xloc);
-}
-
 void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, double* grad_x) {
   hipStream_t s = P->stream;
   const int64_t M = P->M, R = P->R, C = P->ckpt_every;
@@ -1429,17 +1424,22 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
     const int64_t a = sg * C, b = std::min(N, a + C);
     if (sg == 0) zero_state_ref(P, rep);
     else copy_state(P, rep, P->ckpts[(size_t)sg - 1], false);
+    const int hd = P->NQ - 1;   // levels kept before the segment
+    hipLaunchKernelGGL(k_seg_head, dim3(nblk((int64_t)hd * M, 256)), dim3(256), 0, s, (int)M, P->NH, a, hd,
+                       P->rhist, P->segsig);
     for (int64_t L = a; L < b; ++L) {
       march_level(P, rep, L, false, none, nullptr, nullptr);
-      HIPCHK(hipMemcpyAsync(P->segsig + (L - a) * M, P->rhist + (L % P->NH) * M, M * sizeof(double),
+      HIPCHK(hipMemcpyAsync(P->segsig + (hd + L - a) * M, P->rhist + (L % P->NH) * M, M * sizeof(double),
                             hipMemcpyDeviceToDevice, s));
       if (wx) {
+        // f' and d/dx u_H need the forward state of level L; the forward
+        // derivative local sum is formed in the backward sweep below, in the
+        // same pass over the derivative weights as the adjoint one
         hipLaunchKernelGGL(k_incident, dim3(nblk(M, 256 / pp)), dim3(256), 0, s, (int)M, (double)L * P->dt, P->xs,
                            P->beta, pk, pp, 1, P->fprime);
         deriv_field(P, rep);
-        deriv_local(P, rep, L);
-        hipLaunchKernelGGL(k_fwd_dterm, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->fprime, P->xloc, P->i0s,
-                           P->iw, P->gridd, P->nf, P->width, P->segD + (L - a) * M);
+        hipLaunchKernelGGL(k_fwd_dterm, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->fprime, P->i0s, P->iw,
+                           P->gridd, P->nf, P->width, P->segD + (L - a) * M);
       }
     }
     for (int64_t L = b - 1; L >= a; --L) {
@@ -1456,11 +1456,15 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
       march_level(P, adj, Rv, true, ex, nullptr, nullptr);
       if (wx) {
         deriv_field(P, adj);
-        deriv_local(P, adj, Rv);
+        const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
+        hipLaunchKernelGGL(k_local_deriv2, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)M, P->NQ, P->NH,
+                           P->nb_start, P->drowbase, P->acxd, P->DQa, (const double*)P->segsig,
+                           (int64_t)(hd + L - a), (const double*)P->ahist, Rv, P->xloc2, P->xloc);
       }
       hipLaunchKernelGGL(k_adj_grad, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->ahist + (Rv % P->NH) * M,
-                         P->segsig + (L - a) * M, P->beta, wx ? P->segD + (L - a) * M : nullptr, P->xloc, P->xw,
-                         P->i0s, P->iw, P->gridd, P->nf, P->width, P->gb_acc, wx ? P->gx_acc : nullptr);
+                         P->segsig + (hd + L - a) * M, P->beta, wx ? P->segD + (L - a) * M : nullptr, P->xloc2,
+                         P->xloc, P->xw, P->i0s, P->iw, P->gridd, P->nf, P->width, P->gb_acc,
+                         wx ? P->gx_acc : nullptr);
     }
     HIPCHK(hipGetLastError());
   }
