@@ -132,8 +132,8 @@ typedef struct {
 #define WFP_STAGE_MODES 2      /* deconvolution, spectra ring, FIR, propagator */
 #define WFP_STAGE_RBC 3        /* free-space RBC projection (two kernels) */
 #define WFP_STAGE_FFT_INV 4    /* complex-to-real FFT for the type-2 transform */
-#define WFP_STAGE_LOCAL 5      /* local sum + type-2 interpolation + driving data */
-#define WFP_STAGE_SOLVE 6      /* per-step solve */
+#define WFP_STAGE_LOCAL 5      /* local sum (stored weights: its lags >= 2 part) */
+#define WFP_STAGE_SOLVE 6      /* per-step solve (stored weights: with the local sum's lag-1 part) */
 #define WFP_STAGE_RECV 7       /* receivers */
 #define WFP_N_STAGES 8
 
@@ -184,8 +184,8 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
  *              nearby/intermediate switch d = dt the one-sided derivative of
  *              its class is used)
  * Device memory: the first call allocates a second and third march state, a
- * segment of checkpoint_every density levels and, with grad_x, derivative
- * weights as large as the local weights.  Asynchronous on the plan's stream.
+ * segment of checkpoint_every + m_max - 1 density levels and, with grad_x,
+ * derivative weights as large as the local weights.  Asynchronous on the plan's stream.
  * Errors: WFP_EINVAL, WFP_EDOMAIN (free space), WFP_ESTATE, WFP_ENOMEM, WFP_EHIP. */
 wfp_status wfp_adjoint(wfp_plan* plan, int64_t n_levels, const double* dJdu, double* grad_beta,
                        double* grad_x);
@@ -218,7 +218,8 @@ wfp_status wfp_reset(wfp_plan* plan);
  * receivers, each with its own x, beta, incident field and dt, marched in
  * lockstep.  Each stage of a level is one launch over an (instance, block) work
  * list and the whole level is one HIP graph replayed per level; every instance
- * computes exactly what its own plan would (same kernel bodies, same order).
+ * computes what its own plan would, to rounding (the same kernel bodies; a plan
+ * marched on its own adds the lag-1 part of its local sum separately).
  *   wfp_batch_create  host problem data as for wfp_plan_create (probs[n],
  *                     pars[n]); builds one plan per instance (one stream each;
  *                     local weights stored or on the fly per pars[i].local_mode,
