@@ -9,7 +9,8 @@ struct wfp_batch {
   int device = 0;
   hipStream_t user_stream = nullptr;   // the caller's stream (ordering only)
   hipStream_t bs = nullptr;            // the batch's own stream (graph capture)
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t bs2 = nullptr;           // second branch of the captured level (history chain)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
   std::vector<wfp_plan*> plans;
   int64_t level = 0;
   int64_t* level_d = nullptr;
@@ -17,9 +18,9 @@ struct wfp_batch {
   // work lists (device) and their lengths
   int2 *wl_inc = nullptr, *wl_loc4 = nullptr, *wl_loc8 = nullptr, *wl_a = nullptr, *wl_b = nullptr,
        *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr, *wl_otf = nullptr,
-       *wl_swt = nullptr, *wl_sww = nullptr;
+       *wl_swt = nullptr, *wl_sww = nullptr, *wl_g8 = nullptr, *wl_g4 = nullptr;
   int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0, n_otf = 0,
-      n_swt = 0, n_sww = 0;
+      n_swt = 0, n_sww = 0, n_g8 = 0, n_g4 = 0;
   size_t lds_a = 0, lds_b = 0, lds_c = 0, lds_til = 0, lds_otf = 0;
   // Jacobi sweeps of the global-solve instances, thread per row (swt) or
   // wavefront per row (sww); both lists are ordered by decreasing sweep count,
@@ -39,6 +40,9 @@ struct wfp_batch {
     for (void* q : owned) (void)hipFree(q);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (bs2) (void)hipStreamDestroy(bs2);
     if (bs) (void)hipStreamDestroy(bs);
   }
   template <class T>
@@ -176,7 +180,9 @@ std::vector<int2> xcd_balanced(const std::vector<int2>& ib) {
 void build_batch(wfp_batch* B) {
   const int n = (int)B->plans.size();
   std::vector<InstDesc> desc(n);
-  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf;   // otf, loc4, loc8: (instance, blocks)
+  // otf, loc4, loc8, g8, g4: (instance, blocks); g8 / g4: instances whose
+  // lag blocks are short (the plan's lanes per lag), 4 rows per block
+  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf, g8, g4;
   for (int i = 0; i < n; ++i) {
     const wfp_plan* P = B->plans[i];
     desc[i] = describe(P);
@@ -187,6 +193,10 @@ void build_batch(wfp_batch* B) {
       if (P->p != 8) fail(WFP_EDOMAIN, "batched on-the-fly local sums take p = 8");
       otf.push_back(make_int2(i, (int)nblk(M, kOtfRows)));
       B->lds_otf = std::max(B->lds_otf, (size_t)(P->NQ - 1) * kOtfChunk * sizeof(double));
+    } else if (P->lgrp == 8) {
+      g8.push_back(make_int2(i, (int)nblk(M, 4)));
+    } else if (P->lgrp == 4) {
+      g4.push_back(make_int2(i, (int)nblk(M, 4)));
     } else {
       loc4.push_back(make_int2(i, (int)nblk(M, 4)));
       loc8.push_back(make_int2(i, (int)nblk(M, 8)));
@@ -234,6 +244,8 @@ void build_batch(wfp_batch* B) {
   B->wl_til = upload_work(B, til, 1, B->n_til);
   B->wl_rows = upload_work(B, rows, 1, B->n_rows);
   B->wl_otf = upload_work(B, xcd_balanced(otf), 8, B->n_otf);
+  B->wl_g8 = upload_work(B, xcd_balanced(g8), 8, B->n_g8);
+  B->wl_g4 = upload_work(B, xcd_balanced(g4), 8, B->n_g4);
   B->wl_swt = upload_work(B, swt, 1, B->n_swt);
   B->wl_sww = upload_work(B, sww, 1, B->n_sww);
   if (B->n_otf)
@@ -246,12 +258,28 @@ void build_batch(wfp_batch* B) {
   HIPCHK(hipStreamSynchronize(B->bs));
 }
 
-// The launches of one level on the batch stream, in stream order.
+// The launches of one level (captured into the level's graph): the history
+// chain (spread, modes, inverse FFT) and the local sum read only levels before
+// L and write disjoint buffers, so the chain is a second branch of the graph
+// (on bs2) that joins before the solve.
 void enqueue_level(wfp_batch* B) {
   hipStream_t s = B->bs;
   BatchLaunch bl{B->desc_d, nullptr, B->level_d};
   bl.work = B->wl_inc;
   hipLaunchKernelGGL(kb_incident, dim3(B->n_inc), dim3(256), 0, s, bl);
+  HIPCHK(hipEventRecord(B->ev_fork, s));
+  HIPCHK(hipStreamWaitEvent(B->bs2, B->ev_fork, 0));
+  {
+    hipStream_t c = B->bs2;
+    BatchLaunch bc{B->desc_d, nullptr, B->level_d};
+    bc.work = B->wl_a;
+    hipLaunchKernelGGL(kb_hist_a, dim3(B->n_a), dim3(256), B->lds_a, c, bc);
+    bc.work = B->wl_b;
+    hipLaunchKernelGGL(kb_hist_b, dim3(B->n_b), dim3(512), B->lds_b, c, bc);
+    bc.work = B->wl_c;
+    hipLaunchKernelGGL(kb_hist_c, dim3(B->n_c), dim3(256), B->lds_c, c, bc);
+    HIPCHK(hipEventRecord(B->ev_join, c));
+  }
   if (B->loc_rows == 8 && B->n_loc8) {
     bl.work = B->wl_loc8;
     hipLaunchKernelGGL(kb_local, dim3(B->n_loc8), dim3(512), 0, s, bl, B->loc_xcd);
@@ -259,16 +287,19 @@ void enqueue_level(wfp_batch* B) {
     bl.work = B->wl_loc4;
     hipLaunchKernelGGL(kb_local, dim3(B->n_loc4), dim3(256), 0, s, bl, B->loc_xcd);
   }
+  if (B->n_g8) {
+    bl.work = B->wl_g8;
+    hipLaunchKernelGGL(kb_local_g8, dim3(B->n_g8), dim3(256), 0, s, bl);
+  }
+  if (B->n_g4) {
+    bl.work = B->wl_g4;
+    hipLaunchKernelGGL(kb_local_g4, dim3(B->n_g4), dim3(256), 0, s, bl);
+  }
   if (B->n_otf) {
     bl.work = B->wl_otf;
     hipLaunchKernelGGL(kb_local_otf, dim3(B->n_otf), dim3(64 * kOtfRows), B->lds_otf, s, bl);
   }
-  bl.work = B->wl_a;
-  hipLaunchKernelGGL(kb_hist_a, dim3(B->n_a), dim3(256), B->lds_a, s, bl);
-  bl.work = B->wl_b;
-  hipLaunchKernelGGL(kb_hist_b, dim3(B->n_b), dim3(512), B->lds_b, s, bl);
-  bl.work = B->wl_c;
-  hipLaunchKernelGGL(kb_hist_c, dim3(B->n_c), dim3(256), B->lds_c, s, bl);
+  HIPCHK(hipStreamWaitEvent(s, B->ev_join, 0));
   if (B->n_dir) {
     bl.work = B->wl_dir;
     hipLaunchKernelGGL(kb_solve_direct, dim3(B->n_dir), dim3(256), 0, s, bl);
@@ -413,8 +444,11 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
     HIPCHK(hipGetDevice(&B->device));
     B->user_stream = (hipStream_t)stream;
     HIPCHK(hipStreamCreateWithFlags(&B->bs, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&B->bs2, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
     const std::vector<int> modes = choose_local_modes(n, probs, pars);
     for (int32_t i = 0; i < n; ++i) {
       wfp_plan* P = nullptr;

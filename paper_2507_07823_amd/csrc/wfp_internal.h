@@ -164,6 +164,8 @@ struct wfp_plan {
   // stored weights: the lags >= 2 part of the local sum of level L, in
   // locb[L & 1] (its lag-1 part is added after sigma^{L-1} is solved)
   double* locb = nullptr;
+  // lanes per lag in the local sum (16, or 8 / 4 when the lag blocks are short)
+  int lgrp = 16;
   // concurrent history chain: masked streams for the chain (sb) and the rest
   // (sa), and sd on the same compute units as sa for the lags >= 2 part of the
   // next level's local sum

@@ -88,6 +88,14 @@ __global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, int m1, co
                             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                             const double* __restrict__ Qc, const double* __restrict__ hist,
                             const double* __restrict__ addin, double* __restrict__ loc);
+__global__ void k_local_rhs_g8(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
+                               const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
+                               const double* __restrict__ Qc, const double* __restrict__ hist,
+                               const double* __restrict__ addin, double* __restrict__ loc);
+__global__ void k_local_rhs_g4(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
+                               const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
+                               const double* __restrict__ Qc, const double* __restrict__ hist,
+                               const double* __restrict__ addin, double* __restrict__ loc);
 __global__ void k_local_lag1(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
                              const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                              const double* __restrict__ Qc, const double* __restrict__ hist,
@@ -244,6 +252,8 @@ struct BatchLaunch {
 
 __global__ void kb_incident(BatchLaunch b);
 __global__ void kb_local(BatchLaunch b, int xcd);
+__global__ void kb_local_g8(BatchLaunch b);
+__global__ void kb_local_g4(BatchLaunch b);
 __global__ void kb_local_otf(BatchLaunch b);
 __global__ void kb_hist_a(BatchLaunch b);
 __global__ void kb_hist_b(BatchLaunch b);

@@ -532,6 +532,9 @@ constexpr int kMaxNQ = 64;
 // two consecutive doubles, 8-byte aligned (one 16-byte load)
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
+// G lanes per lag (16 by default; 8 or 4 for rows whose lag blocks are
+// short: 64 / G lags per trip, 8 G elements per lane group and trip).
+template <int G = 16>
 __device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t L, int m0, int m1,
             const int* __restrict__ nb_start, const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
             const double* __restrict__ Qc, const double* __restrict__ hist, const double* __restrict__ addin,
@@ -544,9 +547,9 @@ __device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t 
   uint2 mine = make_uint2(0u, 0u);
   if (lane >= m0 && lane < m1) mine = acx[(int64_t)j * NQ + lane];
   const double* __restrict__ q = Qc + rowbase[j];
-  const int grp = lane >> 4, gl = lane & 15;
+  const int grp = lane / G, gl = lane % G;
   double acc0 = 0.0, acc1 = 0.0;
-  for (int mb = m0; mb < m1; mb += 4) {
+  for (int mb = m0; mb < m1; mb += 64 / G) {
     const int m = mb + grp;
     const int src = m < 64 ? m : 0;
     const unsigned vx = __shfl(mine.x, src, 64), vy = __shfl(mine.y, src, 64);
@@ -555,11 +558,11 @@ __device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t 
     const double* __restrict__ hp = hist + (int64_t)mod_slot(L - m, NH) * M;
     int l0 = st + (int)(vx & 0xffff);
     if (l0 >= M) l0 -= M;
-    for (int i0 = 0; i0 < c; i0 += 128) {
+    for (int i0 = 0; i0 < c; i0 += 8 * G) {
       d2u qv[4], hv[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int i = i0 + 2 * gl + 32 * u;
+        const int i = i0 + 2 * gl + 2 * G * u;
         qv[u] = d2u{0.0, 0.0};
         hv[u] = d2u{0.0, 0.0};
         if (i < c) {
@@ -595,6 +598,23 @@ k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restr
             const double* __restrict__ hist, const double* __restrict__ addin, double* __restrict__ loc) {
   k_local_rhs_body(M, NQ, NH, L, m0, m1, nb_start, rowbase, acx, Qc, hist, addin, loc,
                    xcd_block(blockIdx.x, gridDim.x));
+}
+
+// The same for rows with short lag blocks (8 or 4 lanes per lag).
+__global__ void __launch_bounds__(256)
+k_local_rhs_g8(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
+               const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
+               const double* __restrict__ hist, const double* __restrict__ addin, double* __restrict__ loc) {
+  k_local_rhs_body<8>(M, NQ, NH, L, m0, m1, nb_start, rowbase, acx, Qc, hist, addin, loc,
+                      xcd_block(blockIdx.x, gridDim.x));
+}
+
+__global__ void __launch_bounds__(256)
+k_local_rhs_g4(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
+               const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
+               const double* __restrict__ hist, const double* __restrict__ addin, double* __restrict__ loc) {
+  k_local_rhs_body<4>(M, NQ, NH, L, m0, m1, nb_start, rowbase, acx, Qc, hist, addin, loc,
+                      xcd_block(blockIdx.x, gridDim.x));
 }
 
 // The lag-1 part of the right-hand side local sum added to the lags >= 2 part
@@ -1627,6 +1647,23 @@ __global__ void __launch_bounds__(512) kb_local(BatchLaunch b, int xcd) {
   const InstDesc& d = b.desc[w.x];
   k_local_rhs_body(d.M, d.NQ, d.NH, *b.level, 1, d.NQ, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, nullptr, d.loc,
                    w.y);
+}
+
+// Instances whose lag blocks are short: 8 or 4 lanes per lag.
+__global__ void __launch_bounds__(256) kb_local_g8(BatchLaunch b) {
+  const int2 w = b.work[xcd_block(blockIdx.x, gridDim.x)];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  k_local_rhs_body<8>(d.M, d.NQ, d.NH, *b.level, 1, d.NQ, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, nullptr,
+                      d.loc, w.y);
+}
+
+__global__ void __launch_bounds__(256) kb_local_g4(BatchLaunch b) {
+  const int2 w = b.work[xcd_block(blockIdx.x, gridDim.x)];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  k_local_rhs_body<4>(d.M, d.NQ, d.NH, *b.level, 1, d.NQ, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, nullptr,
+                      d.loc, w.y);
 }
 
 __global__ void __launch_bounds__(1024) kb_local_otf(BatchLaunch b) {

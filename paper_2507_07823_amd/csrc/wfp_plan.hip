@@ -549,6 +549,9 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->rowbase = P->alloc<int64_t>(M);
     P->Qc = P->alloc<double>(packed + 2);   // spare elements for paired loads
     P->locb = P->alloc<double>(2 * (size_t)M);
+    // short lag blocks (few neighbours) take more lags per trip
+    const double meanc = (double)packed / ((double)M * (P->NQ - 1));
+    P->lgrp = meanc >= 48.0 ? 16 : (meanc >= 20.0 ? 8 : 4);
     upload(P->rowbase, rb, s);
     hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, 1,
                        P->nb_count, P->qoff, P->Q, P->ac, P->rowbase, P->Qc);
@@ -1011,12 +1014,25 @@ StateRef main_state(wfp_plan* P) { return {P->hist, P->ring, P->alpha, P->dalpha
 
 // Stored weights: the lags >= 2 part of level L's local sum into locb[L & 1]
 // (reads sigma^{L-2} and older only), and its lag-1 part added to it.
+// The stored-weight local sum of lags m0 <= m < NQ into out, with the plan's
+// lanes per lag.
+void launch_local_sum(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, int m0, double* out,
+                      hipEvent_t ea = nullptr, hipEvent_t eb = nullptr) {
+  const int nb = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
+#define WFP_LOC(KER)                                                                                             \
+  hipExtLaunchKernelGGL(KER, dim3(nb), dim3(kRowThreads), 0, s, ea, eb, 0, (int)P->M, P->NQ, P->NH, L, m0, P->NQ, \
+                        P->nb_start, P->rowbase, P->acx, P->Qc, hist, (const double*)nullptr, out)
+  switch (P->lgrp) {
+    case 8: WFP_LOC(k_local_rhs_g8); break;
+    case 4: WFP_LOC(k_local_rhs_g4); break;
+    default: WFP_LOC(k_local_rhs); break;
+  }
+#undef WFP_LOC
+}
+
 void launch_local_big(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, hipEvent_t ea = nullptr,
                       hipEvent_t eb = nullptr) {
-  const int nb = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
-  hipExtLaunchKernelGGL(k_local_rhs, dim3(nb), dim3(kRowThreads), 0, s, ea, eb, 0, (int)P->M, P->NQ, P->NH, L, 2,
-                        P->NQ, P->nb_start, P->rowbase, P->acx, P->Qc, hist, (const double*)nullptr,
-                        P->locb + (L & 1) * P->M);
+  launch_local_sum(P, s, hist, L, 2, P->locb + (L & 1) * P->M, ea, eb);
 }
 
 // Row of level L's driving data g_j(t_L) (eq. (gj)).  The values depend on L
@@ -1642,9 +1658,7 @@ wfp_status wfp_local_part(wfp_plan* P, double* out) {
     if (P->otf) {
       launch_local_otf(P, s, P->hist, P->level, P->halfs, P->loc);
     } else {
-      const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
-      hipLaunchKernelGGL(k_local_rhs, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)M, P->NQ, P->NH, P->level, 1,
-                         P->NQ, P->nb_start, P->rowbase, P->acx, P->Qc, P->hist, (const double*)nullptr, P->loc);
+      launch_local_sum(P, s, P->hist, P->level, 1, P->loc);
       hipLaunchKernelGGL(k_unscale, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->beta, P->loc);
     }
     hipLaunchKernelGGL(k_unsort, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->perm, P->loc, out);
