@@ -300,6 +300,51 @@ OTF_FLOPS_PER_NODE = 2 + 10 + 2 + 7 + 14 + 2
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
+def balanced_leg(levels, sizes):
+    """The free-space scaling study of Section 6 (springs uniform in [-2, 2],
+    beta in [0.1, 3], p = 6, dt chosen for about 100 neighbours) at each M of
+    `sizes`: set-up time, the rate over `levels` levels from rest (the
+    per-level work does not depend on the densities) and the per-stage times
+    of a second, profiled pass.  The paper's CPU rate for this study is
+    quoted as context (other hardware, M up to 1e6)."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    rows = []
+    for M in sizes:
+        lv = levels if M < 500_000 else max(levels // 5, 50)
+        p = workloads.paper_balanced_free_space(M)
+        t0 = time.perf_counter()
+        plan = wfp.Plan(p, p["dt"], p=p["p"])
+        setup = time.perf_counter() - t0
+        info = plan.info
+        plan.run(min(lv, 100))
+        torch.cuda.synchronize()
+        plan.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run(lv)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        plan.reset()
+        plan.set_profiling(True)
+        plan.run(lv)
+        prof = plan.profile()
+        plan.set_profiling(False)
+        plan.close()
+        stages = {k: 1e3 * v[0] / v[1] for k, v in prof.items() if v[1]}
+        row = {"M": M, "dt": p["dt"], "K": info["K"], "p": info["p"], "n_fine": info["n_fine"],
+               "mean_neighbours": info["n_pairs"] / M, "local_mode": info["local_mode"],
+               "solve_mode": info["solve_mode"], "plan_setup_s": setup, "levels": lv,
+               "ms_per_level": 1e3 * el / lv, "scatterer_steps_per_s": M * lv / el, "stages_us": stages}
+        if info["local_mode"] == 1 and "local" in stages:     # stored weights: HBM-bound local sum
+            row["local_GBps"] = stage_bytes(info, "local") / (stages["local"] * 1e-6) / 1e9
+        rows.append(row)
+        log(f"balanced M={M}: {rows[-1]}")
+    return {"workload": "free-space scaling study (Section 6), p = 6, about 100 neighbours", "sizes": rows,
+            "paper_context": {"scatterer_steps_per_s": 1.5e5, "hardware": "2 x Xeon Platinum 8362 (64 cores)",
+                              "note": "the paper's asymptotic CPU rate for this study, M up to 1e6"}}
+
+
 def clumped_leg(levels):
     """The clumped free-space workload at full size (M = 1e6, dt = 5e-4, K = 6250,
     local weights on the fly): set-up time and the rate over `levels` levels
@@ -353,6 +398,10 @@ def main():
     ap.add_argument("--batch-full-levels", type=int, default=3,
                     help="levels of a second batched leg over the full M range [100, 1e5] (0 skips it)")
     ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
+    ap.add_argument("--balanced-levels", type=int, default=2000,
+                    help="levels per size of the free-space scaling-study leg (0 skips it)")
+    ap.add_argument("--balanced-sizes", type=str, default="1000,10000,100000,1000000",
+                    help="comma-separated M of the scaling-study leg")
     ap.add_argument("--overlap-cus", type=int, default=0,
                     help="plan parameter overlap_cus (0: library choice, -1: one stream)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -448,6 +497,10 @@ def main():
         clumped = clumped_leg(args.clumped_levels)
         log(f"clumped leg: {clumped}")
 
+    balanced = None
+    if args.balanced_levels > 0:
+        balanced = balanced_leg(args.balanced_levels, [int(v) for v in args.balanced_sizes.split(",")])
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_steps)
@@ -461,7 +514,7 @@ def main():
                    "W": info["W"], "p": info["p"], "n_fine": info["n_fine"], "pairs": info["n_pairs"],
                    "levels_timed": args.steps, "parallelism": "single GPU"},
         "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch,
-        "batch_full_range": batch_full, "clumped": clumped, "cpu_baseline": cpu,
+        "batch_full_range": batch_full, "clumped": clumped, "balanced": balanced, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()

@@ -31,7 +31,10 @@ import scipy.sparse.linalg as spla
 from .history import mode_step, pq_tables, rotation
 from .local import free_distance, local_weights, periodic_distance
 from .params import FREE_SPACE, PERIODIC, Params
-from .rbc import rbc_project
+from .rbc import rbc_project, rbc_project_fft
+
+# the boundary projection evaluates its sums directly up to this K (dense tables)
+RBC_DIRECT_MAX_K = 16384
 
 TWO_PI = 2.0 * math.pi
 
@@ -178,7 +181,8 @@ class Oracle:
         self.alpha, self.dalpha = mode_step(self.alpha, self.dalpha, self.ring,
                                             self.P, self.Q, self.rot, prm.dt)
         if not self.periodic and self.L > 0 and self.L % prm.rbc_period == 0:
-            self.alpha, self.dalpha = rbc_project(self.alpha, self.dalpha, prm)
+            project = rbc_project if prm.K <= RBC_DIRECT_MAX_K else rbc_project_fft
+            self.alpha, self.dalpha = project(self.alpha, self.dalpha, prm)
 
     def step(self):
         """Compute sigma^L (and receiver values at t_L); advance L."""

@@ -210,6 +210,7 @@ void build_batch(wfp_batch* B) {
       for (int b = 0; b < (int)nblk(M, 256); ++b) rows.push_back(make_int2(i, b));
       B->max_sweeps = std::max(B->max_sweeps, P->iters);
     }
+    if (P->hist_threads != 256) fail(WFP_EDOMAIN, "batched instances need fine grids of at most 1024 butterflies per row stage");
     B->lds_a = std::max(B->lds_a, (size_t)P->n2 * sizeof(double2));
     B->lds_b = std::max(B->lds_b, 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4));
     B->lds_til = std::max(B->lds_til, P->lds_jac);

@@ -121,6 +121,13 @@ struct wfp_plan {
   int nf = 0, nfh = 0, ncheb = 0, T = 256, ntile = 0, ext_max = 0, npk = 0;
   double dt = 0, delta = 0, b = 0, hf = 0, alpha_es = 0, beta_es = 0, h_rbc = 0, delta_s = 0, contraction = 0;
   FftPlan fft_nf{}, fft_rbc{}, fft_n1{}, fft_n2{};
+  // threads of the row passes (256, or 1024 for long rows)
+  int hist_threads = 256;
+  // boundary projection over workgroups for long grids: K = rbc_a rbc_b
+  bool rbc_split = false;
+  int rbc_a = 0, rbc_b = 0;
+  FftPlan fft_rbc_a{}, fft_rbc_b{};
+  double2 *rbc_z = nullptr, *rbc_t = nullptr;
   int n1 = 0, n2 = 0;           // four-step split of the half-length transform
   int64_t npos = 0;             // length of the per-mode arrays (mode-position order)
   double2 *T1 = nullptr, *V = nullptr;

@@ -164,6 +164,13 @@ __global__ void k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t
                          double2* __restrict__ V);
 __global__ void k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
                          double2* __restrict__ grid2);
+// the same row passes with 1024 threads, for rows of more than 1024 butterflies per stage at 256
+__global__ void k_hist_a_wide(FftPlan f2, int n1, const double* __restrict__ sig, int M,
+                              const int* __restrict__ cstart, const int* __restrict__ ccount,
+                              const int64_t* __restrict__ woff, const double* __restrict__ sw,
+                              const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex);
+__global__ void k_hist_c_wide(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
+                              double2* __restrict__ grid2);
 
 // ---- free-space radiation boundary projection ----
 __global__ void k_rbc_to_grid(FftPlan fp, int64_t K, int n1, int n2, const double2* __restrict__ alpha,
@@ -175,6 +182,22 @@ __global__ void k_rbc_to_modes(FftPlan fp, int64_t K, int n1, int n2, int W, dou
                                const double2* __restrict__ tw, const double* __restrict__ dk2,
                                double2* __restrict__ alpha, double2* __restrict__ dalpha,
                                double2* __restrict__ y);
+// long grids: pack, the length-K transform in two passes over workgroups (K = a b), unpack
+__global__ void k_rbc_grid_pack(int64_t K, int n1, int n2, const double2* __restrict__ alpha,
+                                const double2* __restrict__ dalpha, const double2* __restrict__ tw,
+                                double2* __restrict__ z);
+__global__ void k_rbc_fft_pass1(FftPlan fb, int a, int64_t K, const double2* __restrict__ tw,
+                                const double2* __restrict__ z, double2* __restrict__ T);
+__global__ void k_rbc_fft_pass2(FftPlan fa, int b, int64_t K, const double2* __restrict__ tw,
+                                const double2* __restrict__ T, double2* __restrict__ out0,
+                                double2* __restrict__ out1, int conj_out);
+__global__ void k_rbc_modes_pack(int64_t K, int W, double h, double delta_s, const double* __restrict__ cheb_phi,
+                                 const double* __restrict__ cheb_g, int ncheb, const double* __restrict__ gu,
+                                 const double* __restrict__ gv, double2* __restrict__ z);
+__global__ void k_rbc_modes_unpack(int64_t K, int n1, int n2, const double2* __restrict__ X,
+                                   const double2* __restrict__ tw, const double* __restrict__ dk2,
+                                   double2* __restrict__ alpha, double2* __restrict__ dalpha,
+                                   double2* __restrict__ y);
 
 // ---- gradient pass ----
 __global__ void k_deriv_y(int64_t K, int n1, int n2, const double2* __restrict__ alpha,

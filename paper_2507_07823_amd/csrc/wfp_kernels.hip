@@ -1312,6 +1312,123 @@ k_rbc_to_modes(FftPlan fp, int64_t K, int n1, int n2, int W, double h, double de
 }
 
 
+// ---------------------------------------------------------------------------
+// The same projection for grids too long for one workgroup (K complex points,
+// K = a b): the length-K transform runs in four steps over workgroups,
+//   pass 1, block (j1, s): FFT over j2 of z_s[j1 + a j2], j2 < b, times
+//           e^{-2 pi i j1 k2 / K} -> T_s[k2 a + j1];
+//   pass 2, block (k2, s): FFT over j1 of T_s[k2 a + j1], j1 < a
+//           -> X_s[k2 + b k1],
+// with s = 0 for u (from alpha) and s = 1 for v (from alpha'), each sequence
+// K long.  The packing before and the unpacking after the transform are the
+// elementwise steps of the one-workgroup kernels above.  tw[t] = e^{-2 pi i t / (2K)}.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_rbc_grid_pack(int64_t K, int n1, int n2, const double2* __restrict__ alpha, const double2* __restrict__ dalpha,
+                const double2* __restrict__ tw, double2* __restrict__ z) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * K) return;
+  const int sidx = idx >= K ? 1 : 0;
+  const int64_t k = idx - sidx * K;
+  const double2* __restrict__ a = sidx ? dalpha : alpha;
+  const double sk = (k & 1) ? -1.0 : 1.0;
+  const double2 yk = cscale(cconj(a[mode_pos(k, n1, n2)]), sk);
+  double2 ym = make_double2(0.0, 0.0);
+  if (k > 0) {
+    const int64_t km = K - k;
+    const double sm = (km & 1) ? -1.0 : 1.0;
+    ym = cconj(cscale(cconj(a[mode_pos(km, n1, n2)]), sm));
+  }
+  const double2 zk = cadd(cadd(yk, ym), cmul_pi(cmul(cconj(tw[k]), csub(yk, ym))));
+  z[idx] = cconj(zk);
+}
+
+__global__ void __launch_bounds__(256)
+k_rbc_fft_pass1(FftPlan fb, int a, int64_t K, const double2* __restrict__ tw, const double2* __restrict__ z,
+                double2* __restrict__ T) {
+  extern __shared__ double2 buf[];
+  const int b = fb.n, j1 = blockIdx.x;
+  const int64_t off = (int64_t)blockIdx.y * K;
+  for (int j2 = threadIdx.x; j2 < b; j2 += blockDim.x) buf[j2] = z[off + j1 + (int64_t)a * j2];
+  __syncthreads();
+  fft_batch(buf, 1, fb, tw, 2 * a);
+  for (int k2 = threadIdx.x; k2 < b; k2 += blockDim.x)
+    T[off + (int64_t)k2 * a + j1] = cmul(buf[k2], tw[2 * (int64_t)j1 * k2]);   // j1 k2 < K
+}
+
+__global__ void __launch_bounds__(256)
+k_rbc_fft_pass2(FftPlan fa, int b, int64_t K, const double2* __restrict__ tw, const double2* __restrict__ T,
+                double2* __restrict__ out0, double2* __restrict__ out1, int conj_out) {
+  extern __shared__ double2 buf[];
+  const int a = fa.n, k2 = blockIdx.x;
+  const int64_t off = (int64_t)blockIdx.y * K;
+  double2* __restrict__ out = blockIdx.y ? out1 : out0;
+  for (int j1 = threadIdx.x; j1 < a; j1 += blockDim.x) buf[j1] = T[off + (int64_t)k2 * a + j1];
+  __syncthreads();
+  fft_batch(buf, 1, fa, tw, 2 * b);
+  for (int k1 = threadIdx.x; k1 < a; k1 += blockDim.x) {
+    const double2 v = buf[k1];
+    out[k2 + (int64_t)b * k1] = conj_out ? cconj(v) : v;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_rbc_modes_pack(int64_t K, int W, double h, double delta_s, const double* __restrict__ cheb_phi,
+                 const double* __restrict__ cheb_g, int ncheb, const double* __restrict__ gu,
+                 const double* __restrict__ gv, double2* __restrict__ z) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * K) return;
+  const bool is_v = idx >= K;
+  const int64_t j = idx - (is_v ? K : 0);
+  double val[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int64_t ip = 2 * j + e;       // grid index 0..2K-1
+    const int64_t i = ip - K;           // -K..K-1
+    const int64_t ai = i < 0 ? -i : i;
+    double u = gu[ip];
+    double v = is_v ? gv[ip] : 0.0;
+    if (ai >= K - 2 * W) {
+      const double arg = (double)(K - ai - W) * h;
+      double rho, drho;
+      if (arg <= 0.0) rho = 0.0;
+      else if (arg >= delta_s) rho = 1.0;
+      else rho = cheb(cheb_phi, ncheb, 2.0 * arg / delta_s - 1.0);
+      if (arg >= 0.0 && arg <= delta_s) drho = (2.0 / delta_s) * cheb(cheb_g, ncheb, 2.0 * arg / delta_s - 1.0);
+      else drho = 0.0;
+      if (is_v) v = drho * u + rho * v;
+      else u = rho * u;
+    }
+    val[e] = is_v ? v : u;
+  }
+  z[idx] = make_double2(val[0], val[1]);
+}
+
+__global__ void __launch_bounds__(256)
+k_rbc_modes_unpack(int64_t K, int n1, int n2, const double2* __restrict__ X, const double2* __restrict__ tw,
+                   const double* __restrict__ dk2, double2* __restrict__ alpha, double2* __restrict__ dalpha,
+                   double2* __restrict__ y) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * (K + 1)) return;
+  const bool is_v = idx > K;
+  const int64_t k = idx - (is_v ? K + 1 : 0);
+  const double2* __restrict__ Z = X + (is_v ? K : 0);
+  const double inv = 1.0 / (2.0 * (double)K);
+  double2 a = make_double2(0.0, 0.0);
+  if (k < K) {
+    const double2 zk = Z[k];
+    const double2 zc = cconj(Z[k == 0 ? 0 : K - k]);
+    const double2 E = cscale(cadd(zk, zc), 0.5);
+    const double2 O = cscale(cmul_mi(csub(zk, zc)), 0.5);
+    const double2 Xk = cadd(E, cmul(tw[k], O));
+    const double sk = (k & 1) ? -1.0 : 1.0;
+    a = cscale(cconj(Xk), sk * inv);
+  }
+  const int64_t pos = mode_pos(k, n1, n2);
+  (is_v ? dalpha : alpha)[pos] = a;
+  if (!is_v) y[k] = cscale(cconj(a), dk2[pos]);
+}
+
 // ===========================================================================
 // History part of one level as three kernels.  The half-length complex
 // transform of the fine grid (n = N/2 points, N = n_f) is done in four steps
@@ -1364,6 +1481,14 @@ __global__ void __launch_bounds__(256)
 k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
          const int* __restrict__ ccount, const int64_t* __restrict__ woff, const double* __restrict__ sw,
          const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex) {
+  k_hist_a_body(f2, n1, sig, M, cstart, ccount, woff, sw, tw, T1, ex, blockIdx.x);
+}
+
+// Rows longer than 1024 butterflies per stage for 256 threads take 1024 threads.
+__global__ void __launch_bounds__(1024)
+k_hist_a_wide(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
+              const int* __restrict__ ccount, const int64_t* __restrict__ woff, const double* __restrict__ sw,
+              const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex) {
   k_hist_a_body(f2, n1, sig, M, cstart, ccount, woff, sw, tw, T1, ex, blockIdx.x);
 }
 
@@ -1520,6 +1645,12 @@ __device__ __forceinline__ void k_hist_c_body(FftPlan f2, int n1, const double2*
 __global__ void __launch_bounds__(256)
 k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
          double2* __restrict__ grid2) {
+  k_hist_c_body(f2, n1, V, tw, grid2, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024)
+k_hist_c_wide(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
+              double2* __restrict__ grid2) {
   k_hist_c_body(f2, n1, V, tw, grid2, blockIdx.x);
 }
 

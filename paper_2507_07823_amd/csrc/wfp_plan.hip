@@ -198,37 +198,72 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   P->delta_s = P->W * P->h_rbc;
   P->rbc_period = par->rbc_period > 0 ? par->rbc_period
                                       : (int)std::ceil(P->W * P->h_rbc / P->dt - 1e-12);
-  // fine grid: smallest 2^a 5^b >= 2 (2K+1), even
-  int64_t nf = 2 * (2 * P->K + 1);
-  while (!(is_pow2_pow5(nf) && nf % 2 == 0)) ++nf;
+  // fine grid: the smallest even 2^a 5^b >= 2 (2K+1) whose half length
+  // n = n1 n2 splits with n1 = the largest 2^a 5^b divisor not above sqrt(n)
+  // or 256 (the column pass holds 38 n1 complex values in LDS) and
+  // n2 <= 8192 (one row in LDS)
+  auto split = [](int64_t n, int64_t& n1) {
+    n1 = 0;
+    for (int64_t d = 1; d * d <= n && d <= 256; ++d)
+      if (n % d == 0 && is_pow2_pow5(d)) n1 = d;
+    return n1 > 0 && n / n1 <= 8192;
+  };
+  int64_t nf = 2 * (2 * P->K + 1), n1s = 0;
+  while (!(is_pow2_pow5(nf) && nf % 2 == 0 && split(nf / 2, n1s))) {
+    ++nf;
+    if (nf > ((int64_t)1 << 30)) fail(WFP_EDOMAIN, "fine grid too long for the four-step transform");
+  }
   P->nf = (int)nf;
   P->nfh = (int)(nf / 2);
   P->hf = kTwoPi / (double)nf;
   P->alpha_es = 0.5 * P->width * P->hf;
   P->beta_es = 2.30 * P->width;
   {
-    // n = nf/2 = n1 n2 with n1 the largest 2^a 5^b divisor not above sqrt(n)
     const int64_t n = P->nfh;
-    int64_t best = 1;
-    for (int64_t d = 1; d * d <= n; ++d)
-      if (n % d == 0 && is_pow2_pow5(d)) best = d;
-    P->n1 = (int)best;
-    P->n2 = (int)(n / best);
-    if (P->n2 > 1024) fail(WFP_EDOMAIN, "fine grid too long for the four-step transform");
+    P->n1 = (int)n1s;
+    P->n2 = (int)(n / n1s);
     P->fft_n1 = make_fft_plan(P->n1);
     P->fft_n2 = make_fft_plan(P->n2);
+    P->hist_threads = 256;
+    for (int i = 0; i < P->fft_n2.nst; ++i)
+      if (P->n2 / P->fft_n2.radix[i] > kFftMaxB * 256) P->hist_threads = 1024;
     P->npos = (int64_t)(P->n2 / 2 + 1) * 2 * P->n1;
     // batched LDS stages run on 256 threads with at most kFftMaxB butterflies each
     for (int i = 0; i < P->fft_n1.nst; ++i)
       if (2 * P->n1 / P->fft_n1.radix[i] > kFftMaxB * 256) fail(WFP_EDOMAIN, "four-step factor n1 too long");
     for (int i = 0; i < P->fft_n2.nst; ++i)
-      if (P->n2 / P->fft_n2.radix[i] > kFftMaxB * 256) fail(WFP_EDOMAIN, "four-step factor n2 too long");
+      if (P->n2 / P->fft_n2.radix[i] > kFftMaxB * P->hist_threads)
+        fail(WFP_EDOMAIN, "four-step factor n2 too long");
   }
   if (!periodic) {
     if (!is_pow2_pow5(2 * P->K)) fail(WFP_EDOMAIN, "free space needs 2K = 2^a 5^b");
-    P->fft_rbc = make_fft_plan(P->K);
-    P->lds_rbc = (size_t)P->K * sizeof(double2);
-    if (P->lds_rbc > 160 * 1024) fail(WFP_EDOMAIN, "RBC grid too long for the single-workgroup FFT");
+    // one workgroup holds the K complex points while they fit in LDS and no
+    // stage needs more than kFftMaxB butterflies per thread; longer grids
+    // split K = a b over workgroups (a the largest divisor not above sqrt(K))
+    bool one = (size_t)P->K * sizeof(double2) <= 160 * 1024;
+    for (int R : radix_sequence(P->K))
+      if (P->K / R > (int64_t)kFftMaxB * kFftThreads) one = false;
+    if (one) {
+      P->fft_rbc = make_fft_plan(P->K);
+      P->lds_rbc = (size_t)P->K * sizeof(double2);
+    } else {
+      int64_t a = 1;
+      for (int64_t d = 1; d * d <= P->K; ++d)
+        if (P->K % d == 0) a = d;
+      const int64_t b = P->K / a;
+      auto fits = [](int64_t n) {
+        if (n * (int64_t)sizeof(double2) > 160 * 1024) return false;
+        for (int R : radix_sequence(n))
+          if (n / R > (int64_t)kFftMaxB * 256) return false;
+        return true;
+      };
+      if (!fits(a) || !fits(b)) fail(WFP_EDOMAIN, "boundary projection grid too long");
+      P->rbc_split = true;
+      P->rbc_a = (int)a;
+      P->rbc_b = (int)b;
+      P->fft_rbc_a = make_fft_plan(a);
+      P->fft_rbc_b = make_fft_plan(b);
+    }
   }
 
   hipStream_t s = P->stream;
@@ -905,9 +940,19 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     upload(P->tw_rbc, tw, s);
     P->rbc_u = P->alloc<double>(2 * P->K);
     P->rbc_v = P->alloc<double>(2 * P->K);
+    if (P->rbc_split) {
+      P->rbc_z = P->alloc<double2>(2 * P->K);
+      P->rbc_t = P->alloc<double2>(2 * P->K);
+    }
   }
   // kernels with more than 64 KB of LDS
   HIPCHK(hipFuncSetAttribute((const void*)k_rbc_to_grid, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_rbc_fft_pass1, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_rbc_fft_pass2, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_hist_a, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_hist_c, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_hist_a_wide, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIPCHK(hipFuncSetAttribute((const void*)k_hist_c_wide, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_rbc_to_modes, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_hist_b, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -1012,6 +1057,25 @@ struct StateRef {
 
 StateRef main_state(wfp_plan* P) { return {P->hist, P->ring, P->alpha, P->dalpha}; }
 
+// Row passes of the fine-grid transform, at the plan's block size.
+void launch_hist_a(wfp_plan* P, hipStream_t s, const double* sig, ExtraSources ex) {
+  const size_t lds = P->n2 * sizeof(double2);
+  if (P->hist_threads == 256)
+    hipLaunchKernelGGL(k_hist_a, dim3(P->n1), dim3(256), lds, s, P->fft_n2, P->n1, sig, (int)P->M, P->cstart,
+                       P->ccount, P->swoff, P->sw, P->tw, P->T1, ex);
+  else
+    hipLaunchKernelGGL(k_hist_a_wide, dim3(P->n1), dim3(1024), lds, s, P->fft_n2, P->n1, sig, (int)P->M,
+                       P->cstart, P->ccount, P->swoff, P->sw, P->tw, P->T1, ex);
+}
+
+void launch_hist_c(wfp_plan* P, hipStream_t s, double2* grid) {
+  const size_t lds = P->n2 * sizeof(double2);
+  if (P->hist_threads == 256)
+    hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), lds, s, P->fft_n2, P->n1, P->V, P->tw, grid);
+  else
+    hipLaunchKernelGGL(k_hist_c_wide, dim3(P->n1), dim3(1024), lds, s, P->fft_n2, P->n1, P->V, P->tw, grid);
+}
+
 // Stored weights: the lags >= 2 part of level L's local sum into locb[L & 1]
 // (reads sigma^{L-2} and older only), and its lag-1 part added to it.
 // The stored-weight local sum of lags m0 <= m < NQ into out, with the plan's
@@ -1106,8 +1170,7 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
   }
   {
     StageTimer st(P, WFP_STAGE_SPREAD, sc);
-    hipLaunchKernelGGL(k_hist_a, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), sc, P->fft_n2, P->n1, sig_prev,
-                       (int)P->M, P->cstart, P->ccount, P->swoff, P->sw, P->tw, P->T1, ex);
+    launch_hist_a(P, sc, sig_prev, ex);
   }
   const bool rbc = !periodic && L > 0 && L % P->rbc_period == 0;
   {
@@ -1118,19 +1181,38 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
   }
   if (rbc) {
     StageTimer st(P, WFP_STAGE_RBC, sc);
-    hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, sc, P->fft_rbc, P->K, P->n1, P->n2,
-                       S.alpha, S.dalpha, P->tw_rbc, (double2*)P->rbc_u, (double2*)P->rbc_v);
-    hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, sc, P->fft_rbc, P->K, P->n1, P->n2,
-                       P->W, P->h_rbc, P->delta_s, P->cheb_phi, P->cheb_g, P->ncheb, P->rbc_u, P->rbc_v,
-                       P->tw_rbc, P->dk2, S.alpha, S.dalpha, P->ybuf);
+    if (!P->rbc_split) {
+      hipLaunchKernelGGL(k_rbc_to_grid, dim3(2), dim3(kFftThreads), P->lds_rbc, sc, P->fft_rbc, P->K, P->n1,
+                         P->n2, S.alpha, S.dalpha, P->tw_rbc, (double2*)P->rbc_u, (double2*)P->rbc_v);
+      hipLaunchKernelGGL(k_rbc_to_modes, dim3(2), dim3(kFftThreads), P->lds_rbc, sc, P->fft_rbc, P->K, P->n1,
+                         P->n2, P->W, P->h_rbc, P->delta_s, P->cheb_phi, P->cheb_g, P->ncheb, P->rbc_u, P->rbc_v,
+                         P->tw_rbc, P->dk2, S.alpha, S.dalpha, P->ybuf);
+    } else {
+      const unsigned ne = (unsigned)nblk(2 * P->K, 256);
+      const dim3 g1(P->rbc_a, 2), g2(P->rbc_b, 2);
+      const size_t l1 = P->rbc_b * sizeof(double2), l2 = P->rbc_a * sizeof(double2);
+      hipLaunchKernelGGL(k_rbc_grid_pack, dim3(ne), dim3(256), 0, sc, P->K, P->n1, P->n2, S.alpha, S.dalpha,
+                         P->tw_rbc, P->rbc_z);
+      hipLaunchKernelGGL(k_rbc_fft_pass1, g1, dim3(256), l1, sc, P->fft_rbc_b, P->rbc_a, P->K, P->tw_rbc,
+                         P->rbc_z, P->rbc_t);
+      hipLaunchKernelGGL(k_rbc_fft_pass2, g2, dim3(256), l2, sc, P->fft_rbc_a, P->rbc_b, P->K, P->tw_rbc,
+                         P->rbc_t, (double2*)P->rbc_u, (double2*)P->rbc_v, 1);
+      hipLaunchKernelGGL(k_rbc_modes_pack, dim3(ne), dim3(256), 0, sc, P->K, P->W, P->h_rbc, P->delta_s,
+                         P->cheb_phi, P->cheb_g, P->ncheb, P->rbc_u, P->rbc_v, P->rbc_z);
+      hipLaunchKernelGGL(k_rbc_fft_pass1, g1, dim3(256), l1, sc, P->fft_rbc_b, P->rbc_a, P->K, P->tw_rbc,
+                         P->rbc_z, P->rbc_t);
+      hipLaunchKernelGGL(k_rbc_fft_pass2, g2, dim3(256), l2, sc, P->fft_rbc_a, P->rbc_b, P->K, P->tw_rbc,
+                         P->rbc_t, P->rbc_z, P->rbc_z + P->K, 0);
+      hipLaunchKernelGGL(k_rbc_modes_unpack, dim3((unsigned)nblk(2 * (P->K + 1), 256)), dim3(256), 0, sc, P->K,
+                         P->n1, P->n2, P->rbc_z, P->tw_rbc, P->dk2, S.alpha, S.dalpha, P->ybuf);
+    }
     hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, sc, 2, P->fft_n1, P->n2, P->K, P->W, L, P->npos,
                        P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha, P->ybuf,
                        P->V);
   }
   {
     StageTimer st(P, WFP_STAGE_FFT_INV, sc);
-    hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), sc, P->fft_n2, P->n1, P->V,
-                       P->tw, (double2*)P->grid2);
+    launch_hist_c(P, sc, (double2*)P->grid2);
   }
   if (overlap && sc != s) {
     HIPCHK(hipEventRecord(P->ev_chain, sc));
@@ -1416,8 +1498,7 @@ void deriv_field(wfp_plan* P, const StateRef& S) {
   hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, (int64_t)0,
                      P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha, P->yd,
                      P->V);
-  hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), P->n2 * sizeof(double2), s, P->fft_n2, P->n1, P->V, P->tw,
-                     (double2*)P->gridd);
+  launch_hist_c(P, s, (double2*)P->gridd);
 }
 
 void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, double* grad_x) {

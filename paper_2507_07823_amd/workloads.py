@@ -93,6 +93,52 @@ def clumped_free_space(seed=3, M=1_000_000, dt=5e-4, n_steps=4000, n_clumps=100,
                 x_recv=np.zeros(0), name=f"free-clumped-M{M}-dt{dt:g}-Nt{n_steps}")
 
 
+def balanced_dt(M, m_typ=100.0, W=35, half_width=2.0):
+    """Time step giving a mean neighbour count m_typ within delta = W dt for M
+    springs spread uniformly over [-half_width, half_width]: 2 delta M / (2
+    half_width) = m_typ (edge effects ignored)."""
+    return m_typ * half_width / (M * W)
+
+
+def paper_balanced_free_space(M, seed=6, n_steps=2000, m_typ=100.0, min_sep=1e-6):
+    """The scaling study of Section 6 (timing): free space, M springs uniform
+    in [-2, 2] with pairwise separation at least min_sep (points closer than
+    that to their left neighbour are redrawn), beta ~ U[0.1, 3], Gaussian pulse
+    f(s) = exp(-30 (s + 3)^2) (width 1/sqrt(60)), dt from balanced_dt so the
+    mean neighbour count is about m_typ.  The study runs p = 6."""
+    r = _rng(seed, M)
+    x = np.sort(r.uniform(-2.0, 2.0, M))
+    for _ in range(100):
+        close = np.nonzero(np.diff(x) < min_sep)[0] + 1
+        if close.size == 0:
+            break
+        x[close] = r.uniform(-2.0, 2.0, close.size)
+        x.sort()
+    else:
+        raise RuntimeError("could not separate the springs")
+    x = x[r.permutation(M)]
+    beta = r.uniform(0.1, 3.0, M)
+    packets = np.array([[1.0, -3.0, 1.0 / math.sqrt(60.0), 0.0, 0.0]])
+    dt = balanced_dt(M, m_typ)
+    return dict(x=x, beta=beta, packets=packets, boundary=1, dt=dt, n_steps=n_steps,
+                x_recv=np.zeros(0), p=6, name=f"free-balanced-M{M}-dt{dt:.4g}-Nt{n_steps}")
+
+
+def long_grid_free_space(M=400, seed=8, n_steps=10, spread=0.02):
+    """Free space at the time step of the scaling study's largest size
+    (M = 1e6, so K = 524288) with only M springs, packed in [-spread, spread]
+    so each has a few neighbours: the fine grid and boundary grid of the
+    largest study size at a size the oracle can march.  Pulse and strengths
+    as in paper_balanced_free_space; p = 6."""
+    r = _rng(seed, M)
+    x = r.uniform(-spread, spread, M)
+    beta = r.uniform(0.1, 3.0, M)
+    packets = np.array([[1.0, -3.0, 1.0 / math.sqrt(60.0), 0.0, 0.0]])
+    dt = balanced_dt(1_000_000)
+    return dict(x=x, beta=beta, packets=packets, boundary=1, dt=dt, n_steps=n_steps,
+                x_recv=np.zeros(0), p=6, name=f"free-long-grid-M{M}-dt{dt:.4g}")
+
+
 def adjoint_periodic(seed=5, M=100_000, dt=1e-3, n_steps=5000, R=64):
     """Periodic, M springs with beta ~ U[1, 10], a single Gaussian pulse
     (width 0.05) and R receivers spread over the spring region."""

@@ -1,11 +1,25 @@
 """Writes stored expected values computed by the CPU oracle only.
 
     python tests/golden/make_golden.py multiband
+    python tests/golden/make_golden.py balanced
+    python tests/golden/make_golden.py longgrid
 
 multiband: the periodic multiband workload (M = 1e4, dt = 1e-3, 1e4 steps)
 marched by the oracle for levels 0..n_steps; stores sigma at a few levels for
 all scatterers, every 100th level for 200 sampled scatterers, and the max
 |sigma| over all levels.
+
+balanced: the free-space scaling-study workload (Section 6, p = 6) at
+M = 2e4 (K = 10240): the oracle starts from the seeded synthetic mid-run state
+at a level where the pulse has reached the springs and the boundary correction
+fires after the first step, advances BALANCED_STEPS levels, and stores sigma
+of every spring at each of them and every 8th mode of alpha, alpha' and the
+newest spectrum after the last one.
+
+longgrid: 400 springs at the time step of the scaling study's M = 1e6
+(K = 524288, fine grid 2.5e6 points): the same three levels from a seeded
+state, the boundary correction firing after the first; alpha, alpha' and
+the spectrum are stored every 256th mode.
 """
 import os
 import sys
@@ -21,6 +35,9 @@ from oracle.params import Params  # noqa: E402
 from paper_2507_07823_amd import workloads  # noqa: E402
 
 FULL_LEVELS = (250, 1000, 4000, 10000)
+BALANCED_M = 20_000
+BALANCED_STEPS = 3
+BALANCED_STATE_SEED = 7
 
 
 def multiband():
@@ -50,5 +67,45 @@ def multiband():
                         sigma_max=smax, n_levels=n)
 
 
+def start_level(prm, t):
+    """First level >= t / dt of the form k rbc_period - 1, so the boundary
+    correction fires after the first step."""
+    k = int(np.ceil((t / prm.dt + 1) / prm.rbc_period))
+    return k * prm.rbc_period - 1
+
+
+def state_steps(p, out, state_seed, t_start, mode_stride):
+    """The oracle from a seeded synthetic state at start_level(t_start):
+    BALANCED_STEPS levels, sigma of every spring at each, alpha, alpha' and
+    the newest spectrum every mode_stride-th mode after the last."""
+    M = p["x"].size
+    prm = Params(dt=p["dt"], boundary=1, p=p["p"])
+    t0 = time.time()
+    o = Oracle(p["x"], p["beta"], prm, incident_driving(p["x"], p["beta"], p["packets"], False))
+    print(f"precompute {time.time() - t0:.1f}s K={prm.K}", flush=True)
+    st = workloads.random_state(state_seed, M, prm.K, prm.W, prm.m_max)
+    L0 = start_level(prm, t_start)
+    o.set_state(dict(L=L0, **st))
+    sig = []
+    for _ in range(BALANCED_STEPS):
+        s, _ = o.step()
+        sig.append(s.copy())
+        print(f"step {len(sig)} {time.time() - t0:.1f}s", flush=True)
+    e = o.get_state()
+    k = mode_stride
+    np.savez_compressed(os.path.join(HERE, out), M=M, K=prm.K, L0=L0, state_seed=state_seed,
+                        sigma=np.array(sig), mode_stride=k, alpha=e["alpha"][::k], dalpha=e["dalpha"][::k],
+                        spectrum=e["ring"][0][::k])
+
+
+def longgrid():
+    state_steps(workloads.long_grid_free_space(), "longgrid_state_steps.npz", 9, 2.9, 256)
+
+
+def balanced():
+    state_steps(workloads.paper_balanced_free_space(BALANCED_M), "balanced_state_steps.npz",
+                BALANCED_STATE_SEED, 1.2, 8)
+
+
 if __name__ == "__main__":
-    {"multiband": multiband}[sys.argv[1]]()
+    {"multiband": multiband, "balanced": balanced, "longgrid": longgrid}[sys.argv[1]]()

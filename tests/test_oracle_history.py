@@ -81,3 +81,25 @@ def test_rotation_is_exact_free_propagation():
     wk = np.where(k == 0, 1.0, 2.0)
     u = np.real(np.exp(-1j * np.outer(x, k)) @ (wk * a))
     assert np.max(np.abs(u - free_wave_field(x, 150 * dt, -1.0, 0.2))) < 1e-13
+
+
+def test_rbc_fft_form_equals_direct_sums():
+    # the boundary projection's two sums taken by an FFT of length 2K agree
+    # with the same sums evaluated term by term (Section 4.4)
+    from oracle.params import FREE_SPACE
+    from oracle.rbc import rbc_project, rbc_project_fft
+    rng = np.random.default_rng(3)
+    for dt in (0.01, 3e-3):
+        prm = Params(dt=dt, boundary=FREE_SPACE)
+        K = prm.K
+        a = rng.standard_normal(K + 1) + 1j * rng.standard_normal(K + 1)
+        d = rng.standard_normal(K + 1) + 1j * rng.standard_normal(K + 1)
+        a[0] = a[0].real
+        d[0] = d[0].real
+        u1, v1 = rbc_project(a, d, prm)
+        u2, v2 = rbc_project_fft(a, d, prm)
+        assert u1[K] == 0 and u2[K] == 0 and v2[K] == 0
+        # the direct sums round their phases k x_i (up to K pi) to ~K pi eps
+        tol = 8 * K * math.pi * np.finfo(float).eps
+        assert np.max(np.abs(u1 - u2)) < tol * np.max(np.abs(u1))
+        assert np.max(np.abs(v1 - v2)) < tol * np.max(np.abs(v1))
