@@ -300,10 +300,10 @@ OTF_FLOPS_PER_NODE = 2 + 10 + 2 + 7 + 14 + 2
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
-def balanced_leg(levels, sizes):
+def balanced_leg(levels, sizes, autotune_levels):
     """The free-space scaling study of Section 6 (springs uniform in [-2, 2],
     beta in [0.1, 3], p = 6, dt chosen for about 100 neighbours) at each M of
-    `sizes`: set-up time, the rate over `levels` levels from rest (the
+    `sizes`: set-up time, the schedule wfp_plan_autotune picks, the rate over `levels` levels from rest (the
     per-level work does not depend on the densities) and the per-stage times
     of a second, profiled pass.  The paper's CPU rate for this study is
     quoted as context (other hardware, M up to 1e6)."""
@@ -316,6 +316,7 @@ def balanced_leg(levels, sizes):
         t0 = time.perf_counter()
         plan = wfp.Plan(p, p["dt"], p=p["p"])
         setup = time.perf_counter() - t0
+        plan.autotune(autotune_levels if M < 500_000 else max(autotune_levels // 5, 3))
         info = plan.info
         plan.run(min(lv, 100))
         torch.cuda.synchronize()
@@ -334,7 +335,8 @@ def balanced_leg(levels, sizes):
         stages = {k: 1e3 * v[0] / v[1] for k, v in prof.items() if v[1]}
         row = {"M": M, "dt": p["dt"], "K": info["K"], "p": info["p"], "n_fine": info["n_fine"],
                "mean_neighbours": info["n_pairs"] / M, "local_mode": info["local_mode"],
-               "solve_mode": info["solve_mode"], "plan_setup_s": setup, "levels": lv,
+               "solve_mode": info["solve_mode"], "overlap_cus": info["overlap_cus"], "plan_setup_s": setup,
+               "levels": lv,
                "ms_per_level": 1e3 * el / lv, "scatterer_steps_per_s": M * lv / el, "stages_us": stages}
         if info["local_mode"] == 1 and "local" in stages:     # stored weights: HBM-bound local sum
             row["local_GBps"] = stage_bytes(info, "local") / (stages["local"] * 1e-6) / 1e9
@@ -403,7 +405,9 @@ def main():
     ap.add_argument("--balanced-sizes", type=str, default="1000,10000,100000,1000000",
                     help="comma-separated M of the scaling-study leg")
     ap.add_argument("--overlap-cus", type=int, default=0,
-                    help="plan parameter overlap_cus (0: library choice, -1: one stream)")
+                    help="plan parameter overlap_cus (0: chosen by wfp_plan_autotune, -1: one stream)")
+    ap.add_argument("--autotune-levels", type=int, default=30,
+                    help="trial levels per candidate schedule of wfp_plan_autotune")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 256 MiB copy used to calibrate the HBM counters")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
@@ -437,8 +441,13 @@ def main():
     M = p["x"].size
     t0 = time.perf_counter()
     plan = wfp.Plan(p, p["dt"], overlap_cus=args.overlap_cus)
+    setup = time.perf_counter() - t0
+    if args.overlap_cus == 0:
+        t1 = time.perf_counter()
+        pick = plan.autotune(args.autotune_levels)
+        log(f"autotune: overlap_cus {pick} in {time.perf_counter() - t1:.2f} s")
     info = plan.info
-    log(f"plan: {time.perf_counter() - t0:.2f} s, info {info}")
+    log(f"plan: {setup:.2f} s, info {info}")
     if args.warmup:
         plan.march(args.warmup)
     plan.reset()
@@ -499,7 +508,8 @@ def main():
 
     balanced = None
     if args.balanced_levels > 0:
-        balanced = balanced_leg(args.balanced_levels, [int(v) for v in args.balanced_sizes.split(",")])
+        balanced = balanced_leg(args.balanced_levels, [int(v) for v in args.balanced_sizes.split(",")],
+                                args.autotune_levels)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -512,7 +522,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "periodic multiband springs", "M": M, "dt": p["dt"], "K": info["K"],
                    "W": info["W"], "p": info["p"], "n_fine": info["n_fine"], "pairs": info["n_pairs"],
-                   "levels_timed": args.steps, "parallelism": "single GPU"},
+                   "levels_timed": args.steps, "overlap_cus": info["overlap_cus"], "parallelism": "single GPU"},
         "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch,
         "batch_full_range": batch_full, "clumped": clumped, "balanced": balanced, "cpu_baseline": cpu,
     }

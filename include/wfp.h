@@ -214,6 +214,19 @@ wfp_status wfp_get_profile(wfp_plan* plan, double* ms, int64_t* launches);
 /* Return the plan to level 0 with zero history (stream-ordered). */
 wfp_status wfp_reset(wfp_plan* plan);
 
+/* Schedule choice by measurement (not in the paper): from level 0, marches
+ * 2 + trial_levels levels with the history chain and solve on one stream, and
+ * with them on 1, 2, 3 and 4 XCDs' worth of compute units beside the local
+ * sum (the overlap_cus parameter), keeps the fastest, reports it in
+ * *overlap_cus (may be NULL; -1 = one stream) and returns the plan to level 0
+ * with zero history.  Synchronous.  Which split wins depends on the sizes:
+ * the chain gains from running beside the local sum while its kernels are
+ * latency-bound (K of a few thousand) and loses once they are bandwidth-bound
+ * (K of 1e5 and more).  Plans with checkpoints (checkpoint_every > 0) march
+ * on one stream and keep it.  Errors: WFP_EINVAL (trial_levels < 1),
+ * WFP_ESTATE (plan not at level 0). */
+wfp_status wfp_plan_autotune(wfp_plan* plan, int32_t trial_levels, int32_t* overlap_cus);
+
 /* Batched form (not in the paper): n independent periodic problems without
  * receivers, each with its own x, beta, incident field and dt, marched in
  * lockstep.  Each stage of a level is one launch over an (instance, block) work

@@ -151,6 +151,55 @@ void launch_local_weights(wfp_plan* P, int nrows, const double* xt, const int* s
   HIPCHK(hipGetLastError());
 }
 
+// The concurrent schedule's streams for a split of `cus` compute units: the
+// chain (sb) and the solve (sa) on the first cus, the local sum and driving
+// data (sd) on the rest; cus <= 0 selects one stream.
+void set_overlap(wfp_plan* P, int cus) {
+  if (cus <= 0) {
+    P->overlap_cus = -1;
+    return;
+  }
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, P->device));
+  const int ncu = prop.multiProcessorCount;
+  if (cus >= ncu) fail(WFP_EINVAL, "overlap_cus must be below the number of compute units");
+  const int words = (ncu + 31) / 32;
+  std::vector<uint32_t> ma(words, 0u), mb(words, 0u), md(words, 0u);
+  for (int c = 0; c < ncu; ++c) {
+    if (c < cus) {
+      mb[c / 32] |= 1u << (c % 32);
+      ma[c / 32] |= 1u << (c % 32);
+    } else {
+      md[c / 32] |= 1u << (c % 32);
+    }
+  }
+  // one set of masked streams per (device, split), shared by all plans and
+  // kept until the process ends: each masked stream holds a hardware queue
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, std::array<hipStream_t, 3>> pool;
+  std::lock_guard<std::mutex> lock(mu);
+  auto key = std::make_pair(P->device, cus);
+  auto it = pool.find(key);
+  if (it == pool.end()) {
+    std::array<hipStream_t, 3> st{nullptr, nullptr, nullptr};
+    HIPCHK(hipExtStreamCreateWithCUMask(&st[0], (uint32_t)words, ma.data()));
+    HIPCHK(hipExtStreamCreateWithCUMask(&st[1], (uint32_t)words, mb.data()));
+    HIPCHK(hipExtStreamCreateWithCUMask(&st[2], (uint32_t)words, md.data()));
+    it = pool.emplace(key, st).first;
+  }
+  P->sa = it->second[0];
+  P->sb = it->second[1];
+  P->sd = it->second[2];
+  if (!P->ev_solved) {
+    HIPCHK(hipEventCreateWithFlags(&P->ev_solved, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_chain, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_big[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_big[1], hipEventDisableTiming));
+  }
+  P->overlap_cus = cus;
+}
+
 void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   validate(prob, par);
   const int64_t M = prob->M;
@@ -980,46 +1029,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
       P->overlap_cus = (nx > 1 && worth) ? ncu / nx : -1;
     }
   }
-  if (P->overlap_cus > 0) {
-    hipDeviceProp_t prop;
-    HIPCHK(hipGetDeviceProperties(&prop, P->device));
-    const int ncu = prop.multiProcessorCount;
-    if (P->overlap_cus >= ncu) fail(WFP_EINVAL, "overlap_cus must be below the number of compute units");
-    // the chain (sb) and the solve (sa) on the first overlap_cus compute
-    // units, the local sum and driving data (sd) on the rest
-    const int words = (ncu + 31) / 32;
-    std::vector<uint32_t> ma(words, 0u), mb(words, 0u), md(words, 0u);
-    for (int c = 0; c < ncu; ++c) {
-      if (c < P->overlap_cus) {
-        mb[c / 32] |= 1u << (c % 32);
-        ma[c / 32] |= 1u << (c % 32);
-      } else {
-        md[c / 32] |= 1u << (c % 32);
-      }
-    }
-    // one pair of masked streams per (device, split), shared by all plans and
-    // kept until the process ends: each masked stream holds a hardware queue
-    static std::mutex mu;
-    static std::map<std::pair<int, int>, std::array<hipStream_t, 3>> pool;
-    std::lock_guard<std::mutex> lock(mu);
-    auto key = std::make_pair(P->device, P->overlap_cus);
-    auto it = pool.find(key);
-    if (it == pool.end()) {
-      std::array<hipStream_t, 3> st{nullptr, nullptr, nullptr};
-      HIPCHK(hipExtStreamCreateWithCUMask(&st[0], (uint32_t)words, ma.data()));
-      HIPCHK(hipExtStreamCreateWithCUMask(&st[1], (uint32_t)words, mb.data()));
-      HIPCHK(hipExtStreamCreateWithCUMask(&st[2], (uint32_t)words, md.data()));
-      it = pool.emplace(key, st).first;
-    }
-    P->sa = it->second[0];
-    P->sb = it->second[1];
-    P->sd = it->second[2];
-    HIPCHK(hipEventCreateWithFlags(&P->ev_solved, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&P->ev_chain, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&P->ev_big[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&P->ev_big[1], hipEventDisableTiming));
-  }
+  if (P->overlap_cus > 0) set_overlap(P, P->overlap_cus);
   zero_state(P);
   HIPCHK(hipStreamSynchronize(s));
 }
@@ -1837,6 +1847,56 @@ wfp_status wfp_reset(wfp_plan* P) {
   return guard([&] {
     HIPCHK(hipSetDevice(P->device));
     zero_state(P);
+  });
+}
+
+wfp_status wfp_plan_autotune(wfp_plan* P, int32_t trial_levels, int32_t* overlap_cus) {
+  if (!P || trial_levels < 1) {
+    g_last_error = "autotune needs a plan and trial_levels >= 1";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(P->device));
+    if (P->level != 0) fail(WFP_ESTATE, "autotune runs from level 0 (call wfp_reset first)");
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, P->device));
+    const int ncu = prop.multiProcessorCount;
+    int nx = 1;
+    if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, P->device) != hipSuccess || nx < 1) nx = 1;
+    // one stream, or the chain and solve on 1..4 XCDs' worth of compute units
+    std::vector<int> cand{-1};
+    if (P->ckpt_every == 0)
+      for (int q = 1; q <= 4 && q < nx; ++q) cand.push_back(q * (ncu / nx));
+    hipStream_t s = P->stream;
+    hipEvent_t a, c;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&c));
+    const bool prof = P->profiling;
+    P->profiling = false;
+    float best = 1e30f;
+    int pick = -1;
+    for (int cus : cand) {
+      set_overlap(P, cus);
+      run_levels(P, 2, nullptr, 1, nullptr);          // warm-up levels
+      HIPCHK(hipEventRecord(a, s));
+      run_levels(P, trial_levels, nullptr, 1, nullptr);
+      HIPCHK(hipEventRecord(c, s));
+      HIPCHK(hipEventSynchronize(c));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, a, c));
+      if (ms < best) {
+        best = ms;
+        pick = cus;
+      }
+      zero_state(P);
+    }
+    HIPCHK(hipEventDestroy(a));
+    HIPCHK(hipEventDestroy(c));
+    P->profiling = prof;
+    set_overlap(P, pick);
+    zero_state(P);
+    HIPCHK(hipStreamSynchronize(s));
+    if (overlap_cus) *overlap_cus = P->overlap_cus;
   });
 }
 

@@ -92,6 +92,8 @@ def load_library():
     lib.wfp_get_profile.restype = ctypes.c_int32
     lib.wfp_reset.argtypes = [vp]
     lib.wfp_reset.restype = ctypes.c_int32
+    lib.wfp_plan_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.wfp_plan_autotune.restype = ctypes.c_int32
     lib.wfp_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.POINTER(Params), vp,
                                      ctypes.POINTER(vp)]
     lib.wfp_batch_create.restype = ctypes.c_int32
@@ -270,6 +272,14 @@ class Plan:
 
     def reset(self):
         _check(self._lib.wfp_reset(self._h))
+
+    def autotune(self, trial_levels=20):
+        """Time the concurrent-schedule splits from level 0, keep the fastest
+        (returns its overlap_cus, -1 for one stream); leaves the plan at level 0."""
+        out = ctypes.c_int32()
+        _check(self._lib.wfp_plan_autotune(self._h, int(trial_levels), ctypes.byref(out)))
+        self.info = self.query_info()
+        return out.value
 
     @classmethod
     def _borrow(cls, lib, handle):

@@ -272,6 +272,31 @@ def test_concurrent_chain_is_bitwise_identical(wfp):
     plan.close()
 
 
+def test_autotune_keeps_results_and_level(wfp):
+    """wfp_plan_autotune picks one of its candidate splits, leaves the plan at
+    level 0 with zero history, and the march that follows equals the
+    one-stream march bit for bit."""
+    import torch
+    p = workloads.paper_balanced_free_space(10_000)
+    n = 200
+    ref = wfp.Plan(p, p["dt"], p=6, overlap_cus=-1)
+    sref, _ = ref.march(n, 9)
+    torch.cuda.synchronize()
+    ref.close()
+    plan = wfp.Plan(p, p["dt"], p=6)
+    with pytest.raises(wfp.WFPError):
+        plan.autotune(0)
+    pick = plan.autotune(3)
+    say(f"autotune: overlap_cus = {pick}")
+    assert pick in (-1, 32, 64, 96, 128) and plan.info["overlap_cus"] == pick and plan.info["level"] == 0
+    sig, _ = plan.march(n, 9)
+    torch.cuda.synchronize()
+    assert np.array_equal(sig.cpu().numpy(), sref.cpu().numpy())
+    with pytest.raises(wfp.WFPError):
+        plan.autotune(3)                      # not at level 0
+    plan.close()
+
+
 def test_pipelined_runs_of_any_length(wfp):
     """The pipelined schedule (next level's local sum started while the
     current level is finished) split into runs of 1, 2, 3 and 257 levels, with
