@@ -22,6 +22,7 @@ import argparse
 import csv
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -347,6 +348,41 @@ def balanced_leg(levels, sizes, autotune_levels):
                               "note": "the paper's asymptotic CPU rate for this study, M up to 1e6"}}
 
 
+def convergence_leg(sizes=(10, 100), orders=(2, 4, 6, 8), dts=(0.0125, 0.00625, 0.003125)):
+    """The convergence test of Section 6.1 on the GPU: prescribed Gaussian
+    densities at M springs in [-1, 1] (free space), the march driven by the
+    data they imply (wfp_run_driven), the field at 10 receivers in [-1, 1]
+    compared with the exact field at 10 times covering 0 < t < 6 pi.  Reports
+    the maximum grid error per (M, p, dt) and the observed orders."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    T = 6.0 * math.pi
+    xg = np.linspace(-1.0, 1.0, 10)
+    out = []
+    for M in sizes:
+        prob = workloads.manufactured_springs(M)
+        for dt in dts:
+            n = int(math.floor(T / dt)) + 1
+            lv = np.minimum(np.round(np.arange(1, 11) * (T / 10) / dt).astype(int), n - 1)
+            ex = np.array([workloads.manufactured_potential(xg, L * dt, prob["x"], prob["mu"], prob["t0"])
+                           for L in lv])
+            g = torch.from_numpy(np.ascontiguousarray(workloads.manufactured_data(prob, dt, n))).cuda()
+            for p in orders:
+                plan = wfp.Plan(dict(prob, x_recv=xg), dt, p=p)
+                t0 = time.perf_counter()
+                _, u = plan.march_driven(g, save_every=n)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                plan.close()
+                err = float(np.max(np.abs(u.cpu().numpy()[lv] - ex)))
+                out.append({"M": M, "p": p, "dt": dt, "levels": n, "max_grid_error": err, "march_s": el})
+    for r in out:
+        prev = [q for q in out if q["M"] == r["M"] and q["p"] == r["p"] and q["dt"] == 2 * r["dt"]]
+        r["observed_order"] = math.log2(prev[0]["max_grid_error"] / r["max_grid_error"]) if prev else None
+    return {"workload": "manufactured solution (Section 6.1), free space, 10 x 10 space-time grid, T = 6 pi",
+            "runs": out}
+
+
 def clumped_leg(levels):
     """The clumped free-space workload at full size (M = 1e6, dt = 5e-4, K = 6250,
     local weights on the fly): set-up time and the rate over `levels` levels
@@ -400,6 +436,7 @@ def main():
     ap.add_argument("--batch-full-levels", type=int, default=3,
                     help="levels of a second batched leg over the full M range [100, 1e5] (0 skips it)")
     ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
+    ap.add_argument("--no-convergence", action="store_true", help="skip the manufactured-solution leg")
     ap.add_argument("--balanced-levels", type=int, default=2000,
                     help="levels per size of the free-space scaling-study leg (0 skips it)")
     ap.add_argument("--balanced-sizes", type=str, default="1000,10000,100000,1000000",
@@ -511,6 +548,11 @@ def main():
         balanced = balanced_leg(args.balanced_levels, [int(v) for v in args.balanced_sizes.split(",")],
                                 args.autotune_levels)
 
+    convergence = None
+    if not args.no_convergence:
+        convergence = convergence_leg()
+        log("convergence leg:", json.dumps(convergence))
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_steps)
@@ -524,7 +566,8 @@ def main():
                    "W": info["W"], "p": info["p"], "n_fine": info["n_fine"], "pairs": info["n_pairs"],
                    "levels_timed": args.steps, "overlap_cus": info["overlap_cus"], "parallelism": "single GPU"},
         "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch,
-        "batch_full_range": batch_full, "clumped": clumped, "balanced": balanced, "cpu_baseline": cpu,
+        "batch_full_range": batch_full, "clumped": clumped, "balanced": balanced, "convergence": convergence,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()

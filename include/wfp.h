@@ -164,6 +164,21 @@ wfp_status wfp_plan_info(const wfp_plan* plan, wfp_info* info);
 wfp_status wfp_run(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t save_every,
                    double* u_recv_out);
 
+/* March n_steps levels like wfp_run, with the driving data supplied by the
+ * caller instead of computed from the plan's incident packets: any incident
+ * wave, or data read off a manufactured solution (Section 6.1).
+ *   g  device [n_steps][M], caller's spring order: row i holds g_j at the
+ *      plan's level + i, the right side of the spring condition
+ *      -sigma_j - beta_j u(x_j, t) = g_j (eq. (gj): beta_j f(x_j - t) for an
+ *      incident wave f(x - t)).  Read during the call's stream work; the
+ *      caller keeps it alive until the stream has passed it.
+ *   sigma_out, save_every, u_recv_out as for wfp_run.
+ * One stream (no concurrent chain).  After it, wfp_adjoint refuses with
+ * WFP_ESTATE until wfp_reset: its forward replay computes the packets' data.
+ * Errors: WFP_EINVAL (g NULL with n_steps > 0), WFP_EHIP, WFP_ENONFINITE. */
+wfp_status wfp_run_driven(wfp_plan* plan, int64_t n_steps, const double* g, double* sigma_out,
+                          int64_t save_every, double* u_recv_out);
+
 /* The explicit local part at the springs for the next level L (the plan's
  * level), eqs. (localSol1)/(localSol2) without the implicit lag 0:
  *   out[j] = sum_{m>=1} sum_{l: d_jl < delta} (1/2) Q_m(d_jl) sigma_l^{L-m}

@@ -226,6 +226,8 @@ __global__ void k_seg_head(int M, int NH, int64_t a, int nlev, const double* __r
                            double* __restrict__ out);
 __global__ void k_unscale(int M, const double* __restrict__ beta, double* __restrict__ v);
 __global__ void k_gather(int n, const int* __restrict__ idx, const double* __restrict__ in, double* __restrict__ out);
+__global__ void k_drive_gather(int M, const int* __restrict__ perm, const double* __restrict__ g,
+                               double* __restrict__ out);
 __global__ void k_unsort(int M, const int* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out);
 
 // ---- batched form: one launch per stage over an (instance, block) work list ----

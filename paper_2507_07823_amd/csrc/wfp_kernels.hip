@@ -1752,6 +1752,15 @@ __global__ void k_gather(int n, const int* __restrict__ idx, const double* __res
   if (i < n) out[i] = in[idx[i]];
 }
 
+// Caller-supplied driving data g (caller order) into the solve's input in
+// sorted order, where it enters the right-hand side with a minus sign:
+// out[j] = -g[perm[j]].
+__global__ void k_drive_gather(int M, const int* __restrict__ perm, const double* __restrict__ g,
+                               double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < M) out[j] = -g[perm[j]];
+}
+
 // out[perm[j]] = in[j]  (sorted -> caller order)
 __global__ void k_unsort(int M, const int* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;

@@ -1733,6 +1733,37 @@ wfp_status wfp_run(wfp_plan* P, int64_t n_steps, double* sigma_out, int64_t save
   });
 }
 
+wfp_status wfp_run_driven(wfp_plan* P, int64_t n_steps, const double* g, double* sigma_out, int64_t save_every,
+                          double* u_recv_out) {
+  if (!P || n_steps < 0 || (n_steps > 0 && !g)) {
+    g_last_error = "bad plan, step count or driving data";
+    return WFP_EINVAL;
+  }
+  if (sigma_out && save_every < 1) {
+    g_last_error = "save_every must be >= 1";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(P->device));
+    if (n_steps == 0) return;
+    const StateRef S = main_state(P);
+    const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+    const int64_t M = P->M;
+    // the gradient pass replays levels with the incident packets' data
+    P->ck_from0 = false;
+    for (int64_t i = 0; i < n_steps; ++i) {
+      const int64_t L = P->level + i;
+      hipLaunchKernelGGL(k_drive_gather, dim3(nblk(M, 256)), dim3(256), 0, P->stream, (int)M, P->perm, g + i * M,
+                         P->ginc);
+      double* save = (sigma_out && i % save_every == 0) ? sigma_out + (i / save_every) * M : nullptr;
+      march_level(P, S, L, true, none, save, u_recv_out ? u_recv_out + i * P->R : nullptr);
+    }
+    HIPCHK(hipGetLastError());
+    P->level += n_steps;
+    if (P->check_finite) check_finite(P);
+  });
+}
+
 wfp_status wfp_local_part(wfp_plan* P, double* out) {
   if (!P || !out) {
     g_last_error = "local_part needs a plan and an output array";

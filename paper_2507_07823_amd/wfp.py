@@ -78,6 +78,8 @@ def load_library():
     lib.wfp_plan_info.restype = ctypes.c_int32
     lib.wfp_run.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
     lib.wfp_run.restype = ctypes.c_int32
+    lib.wfp_run_driven.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_int64, vp]
+    lib.wfp_run_driven.restype = ctypes.c_int32
     lib.wfp_local_part.argtypes = [vp, vp]
     lib.wfp_local_part.restype = ctypes.c_int32
     lib.wfp_adjoint.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
@@ -222,6 +224,21 @@ class Plan:
         sig = torch.empty((rows, M), dtype=torch.float64, device="cuda")
         u = torch.empty((n_steps, R), dtype=torch.float64, device="cuda") if (receivers and R) else None
         self.run(n_steps, sig, save_every, u)
+        return sig, u
+
+    def march_driven(self, g, save_every=1, receivers=True):
+        """March g.shape[0] levels with caller driving data g (float64 CUDA
+        tensor [n_steps][M], caller's spring order; g_j = beta_j f(x_j - t) for
+        an incident wave); returns (sigma rows, receiver values or None)."""
+        import torch
+        assert g.dtype == torch.float64 and g.is_cuda and g.is_contiguous() and g.dim() == 2
+        n_steps, M = g.shape
+        assert M == self.info["M"]
+        R = self.info["R"]
+        rows = (n_steps + save_every - 1) // save_every
+        sig = torch.empty((rows, M), dtype=torch.float64, device="cuda")
+        u = torch.empty((n_steps, R), dtype=torch.float64, device="cuda") if (receivers and R) else None
+        _check(self._lib.wfp_run_driven(self._h, int(n_steps), _ptr(g), _ptr(sig), int(save_every), _ptr(u)))
         return sig, u
 
     def local_part(self):

@@ -139,6 +139,75 @@ def long_grid_free_space(M=400, seed=8, n_steps=10, spread=0.02):
                 x_recv=np.zeros(0), p=6, name=f"free-long-grid-M{M}-dt{dt:.4g}")
 
 
+def incident_data(prob, dt, n_levels, images=4):
+    """Driving data beta_j f(x_j - t_L) of the problem's incident packets at
+    levels L = 0..n_levels-1, shape (n_levels, M); the periodic box sums the
+    images s + 2 pi m, |m| <= images, of the wrapped argument."""
+    x, beta, pk = prob["x"], prob["beta"], np.atleast_2d(prob["packets"])
+    periodic = prob["boundary"] == 0
+    out = np.zeros((n_levels, x.size))
+    for L in range(n_levels):
+        s = x - L * dt
+        if periodic:
+            s = s - 2 * PI * np.rint(s / (2 * PI))
+        ms = range(-images, images + 1) if periodic else [0]
+        f = np.zeros(x.size)
+        for a, c, w, om, ph in pk:
+            for m in ms:
+                y = s + 2 * PI * m - c
+                f += a * np.exp(-y * y / (2 * w * w)) * np.cos(om * y + ph)
+        out[L] = beta * f
+    return out
+
+
+def manufactured_springs(M, seed=10, min_sep=1e-4):
+    """The convergence test of Section 6.1: free space, M springs uniform in
+    [-1, 1] with pairwise separation at least min_sep (closer points redrawn),
+    prescribed densities sigma_j(t) = exp(-mu_j (t - t0_j)^2) with
+    mu ~ U[40, 50], t0 ~ U[1, 3], and beta ~ U[0.1, 3]."""
+    r = _rng(seed, M)
+    x = np.sort(r.uniform(-1.0, 1.0, M))
+    for _ in range(100):
+        close = np.nonzero(np.diff(x) < min_sep)[0] + 1
+        if close.size == 0:
+            break
+        x[close] = r.uniform(-1.0, 1.0, close.size)
+        x.sort()
+    else:
+        raise RuntimeError("could not separate the springs")
+    mu = r.uniform(40.0, 50.0, M)
+    t0 = r.uniform(1.0, 3.0, M)
+    beta = r.uniform(0.1, 3.0, M)
+    # the driving data come from manufactured_data; the plan's incident
+    # field is one packet of zero amplitude
+    return dict(x=x, beta=beta, mu=mu, t0=t0, boundary=1, packets=np.array([[0.0, 0.0, 1.0, 0.0, 0.0]]),
+                x_recv=np.zeros(0), name=f"manufactured-M{M}")
+
+
+def manufactured_potential(xq, t, x, mu, t0):
+    """Free-space field of the prescribed densities at points xq and time t:
+    u(x, t) = (1/2) sum_l int_0^{t - |x - x_l|} sigma_l(s) ds (the 1D wave
+    single layer), with int_0^T exp(-mu (s - t0)^2) ds =
+    (1/2) sqrt(pi/mu) [erf(sqrt(mu) (T - t0)) + erf(sqrt(mu) t0)] for T > 0."""
+    from scipy.special import erf
+    xq = np.atleast_1d(np.asarray(xq, dtype=np.float64))
+    T = t - np.abs(xq[:, None] - x[None, :])
+    rm = np.sqrt(mu)[None, :]
+    val = 0.5 * np.sqrt(PI) / rm * (erf(rm * (T - t0[None, :])) + erf(rm * t0[None, :]))
+    return 0.5 * np.where(T > 0.0, val, 0.0).sum(axis=1)
+
+
+def manufactured_data(prob, dt, n_levels):
+    """Driving data g_j(t_L) = -sigma_j(t_L) - beta_j u(x_j, t_L) of the
+    manufactured densities at levels L = 0..n_levels-1, shape (n_levels, M)."""
+    x, beta, mu, t0 = prob["x"], prob["beta"], prob["mu"], prob["t0"]
+    g = np.empty((n_levels, x.size))
+    for L in range(n_levels):
+        t = L * dt
+        g[L] = -np.exp(-mu * (t - t0) ** 2) - beta * manufactured_potential(x, t, x, mu, t0)
+    return g
+
+
 def adjoint_periodic(seed=5, M=100_000, dt=1e-3, n_steps=5000, R=64):
     """Periodic, M springs with beta ~ U[1, 10], a single Gaussian pulse
     (width 0.05) and R receivers spread over the spring region."""

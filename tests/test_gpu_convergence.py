@@ -1,0 +1,119 @@
+"""The convergence test of Section 6.1 through the HIP path: prescribed
+densities sigma_j(t) = exp(-mu_j (t - t0_j)^2) at M springs in [-1, 1] (free
+space) generate the exact field u_ex; the march is driven by the data
+g_j = -sigma_j - beta_j u_ex(x_j, t) (wfp_run_driven) and the field it
+computes at 10 receivers is compared with u_ex on a 10 x 10 space-time grid
+covering 0 < t < 6 pi.
+
+* Parity: the same driven march in the oracle (M = 10, p = 4), every density
+  and receiver value, 1e-10.
+* Order: the grid error falls like dt^(p+1) for p = 2, 4, 6 until it meets the
+  floor of the window tolerance, about M eps = 1e-11 (M = 10, eps = 1e-12).
+* Driven data equal to the packets' own data reproduce wfp_run.
+
+The GPU input comes from the inputs module (its closed form of u_ex); the
+expected field from the oracle's own closed form.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.exact import manufactured_driving, manufactured_field
+from oracle.march import Oracle
+from oracle.params import FREE_SPACE, Params
+from paper_2507_07823_amd import workloads
+
+pytestmark = pytest.mark.gpu
+T_END = 6.0 * math.pi
+XG = np.linspace(-1.0, 1.0, 10)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rho(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(np.asarray(b))))
+
+
+@pytest.fixture(scope="module")
+def wfp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2507_07823_amd import wfp as w
+    w.load_library()
+    return w
+
+
+def grid_levels(dt):
+    n = int(math.floor(T_END / dt)) + 1
+    lv = np.minimum(np.round(np.arange(1, 11) * (T_END / 10) / dt).astype(int), n - 1)
+    return n, lv
+
+
+def driven_march(w, prob, dt, p):
+    import torch
+    n, _ = grid_levels(dt)
+    g = torch.from_numpy(np.ascontiguousarray(workloads.manufactured_data(prob, dt, n))).cuda()
+    plan = w.Plan(dict(prob, x_recv=XG), dt, p=p)
+    sig, u = plan.march_driven(g)
+    torch.cuda.synchronize()
+    out = sig.cpu().numpy(), u.cpu().numpy()
+    plan.close()
+    return out
+
+
+def grid_error(prob, dt, u):
+    _, lv = grid_levels(dt)
+    ex = np.array([manufactured_field(XG, L * dt, prob["x"], prob["mu"], prob["t0"], False) for L in lv])
+    return float(np.max(np.abs(u[lv] - ex)))
+
+
+def test_manufactured_parity_with_oracle(wfp):
+    prob = workloads.manufactured_springs(10)
+    dt, p = 0.0125, 4
+    n, _ = grid_levels(dt)
+    say(f"case manufactured parity M=10 p={p} dt={dt} levels={n}")
+    sig, u = driven_march(wfp, prob, dt, p)
+    prm = Params(dt=dt, p=p, boundary=FREE_SPACE)
+    o = Oracle(prob["x"], prob["beta"], prm, manufactured_driving(prob["x"], prob["beta"], prob["mu"], prob["t0"], False),
+               x_recv=XG)
+    es, eu = o.run(n)
+    rs, ru = rho(sig, es), rho(u, eu)
+    say(f"rho sigma {rs:.2e} u {ru:.2e}")
+    assert rs < 1e-10 and ru < 1e-10
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_manufactured_order(wfp, p):
+    prob = workloads.manufactured_springs(10)
+    errs = []
+    for dt in (0.0125, 0.00625):
+        _, u = driven_march(wfp, prob, dt, p)
+        errs.append(grid_error(prob, dt, u))
+    order = math.log2(errs[0] / errs[1])
+    say(f"case manufactured order p={p}: errors {errs[0]:.3e} {errs[1]:.3e} observed order {order:.2f}")
+    floor = 5e-11                      # a few M eps
+    assert errs[1] < errs[0]
+    assert order > p or errs[1] < floor
+    assert errs[1] > 1e-13             # the window tolerance is not beaten
+
+
+def test_driven_equals_packets(wfp):
+    import torch
+    prob = workloads.small_periodic()
+    n = 400
+    plan = wfp.Plan(prob, prob["dt"])
+    s1, _ = plan.march(n)
+    torch.cuda.synchronize()
+    plan.reset()
+    g = torch.from_numpy(workloads.incident_data(prob, prob["dt"], n)).cuda()
+    s2, _ = plan.march_driven(g)
+    torch.cuda.synchronize()
+    r = rho(s2.cpu().numpy(), s1.cpu().numpy())
+    say(f"case driven vs packets rho {r:.2e}")
+    assert r < 1e-12
+    plan.close()
