@@ -383,6 +383,46 @@ def convergence_leg(sizes=(10, 100), orders=(2, 4, 6, 8), dts=(0.0125, 0.00625, 
             "runs": out}
 
 
+def filters_leg():
+    """The filter demonstrations of Section 6.3 (free space, dt = 0.01): the
+    two-spring cavity (9426 levels) and arrays of 10 and 200 springs (25134
+    levels), the march time of each and, for the cavity, the frequencies the
+    downstream total field passes (peaks of the Hann-windowed transform of the
+    total field over that of the incident wave).  The paper's run times (a laptop, other hardware) are
+    quoted as context."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    paper_s = {2: 16.0, 10: 91.0, 200: 114.0}
+    rows = []
+    for prob in [workloads.fabry_perot()] + workloads.spring_arrays():
+        M, n = prob["x"].size, prob["n_steps"]
+        t0 = time.perf_counter()
+        plan = wfp.Plan(prob, prob["dt"], p=prob["p"])
+        setup = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, u = plan.march(n, save_every=n)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        plan.close()
+        t = np.arange(n) * prob["dt"]
+        inc = np.exp(-prob["mu"] * (prob["x_recv"][0] - t - prob["t0"]) ** 2)
+        tot = u.cpu().numpy()[:, 0] + inc
+        row = {"M": M, "beta": float(prob["beta"][0]), "p": prob["p"], "levels": n, "plan_setup_s": setup,
+               "march_s": el, "paper_s": paper_s[M], "max_transmitted": float(np.max(np.abs(tot)))}
+        if M == 2:
+            # Hann-windowed transfer ratio over the run, w in [1, 11]
+            win = 0.5 - 0.5 * np.cos(2 * np.pi * t / t[-1])
+            w = np.linspace(1.0, 11.0, 4001)
+            ph = np.exp(1j * np.outer(w, t))
+            T = np.abs(ph @ (tot * win)) / np.abs(ph @ inc)
+            row["transmission_peaks"] = [float(w[i]) for i in range(1, w.size - 1)
+                                         if T[i] > T[i - 1] and T[i] > T[i + 1] and T[i] > 0.2 * T.max()]
+        rows.append(row)
+        log(f"filter M={M}: {row}")
+    return {"workload": "spring filters (Section 6.3), free space, dt = 0.01", "runs": rows}
+
+
 def clumped_leg(levels):
     """The clumped free-space workload at full size (M = 1e6, dt = 5e-4, K = 6250,
     local weights on the fly): set-up time and the rate over `levels` levels
@@ -437,6 +477,7 @@ def main():
                     help="levels of a second batched leg over the full M range [100, 1e5] (0 skips it)")
     ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
     ap.add_argument("--no-convergence", action="store_true", help="skip the manufactured-solution leg")
+    ap.add_argument("--no-filters", action="store_true", help="skip the spring-filter leg")
     ap.add_argument("--balanced-levels", type=int, default=2000,
                     help="levels per size of the free-space scaling-study leg (0 skips it)")
     ap.add_argument("--balanced-sizes", type=str, default="1000,10000,100000,1000000",
@@ -553,6 +594,10 @@ def main():
         convergence = convergence_leg()
         log("convergence leg:", json.dumps(convergence))
 
+    filters = None
+    if not args.no_filters:
+        filters = filters_leg()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_steps)
@@ -567,7 +612,7 @@ def main():
                    "levels_timed": args.steps, "overlap_cus": info["overlap_cus"], "parallelism": "single GPU"},
         "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch,
         "batch_full_range": batch_full, "clumped": clumped, "balanced": balanced, "convergence": convergence,
-        "cpu_baseline": cpu,
+        "filters": filters, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()

@@ -96,3 +96,54 @@ def free_wave_field(x, t, centre, width, n_images=4):
         y = x - t - centre - 2.0 * math.pi * m
         out += np.exp(-y * y / (2.0 * width * width))
     return out
+
+
+def spring_array_transmission(w, xs, beta):
+    """Transmission coefficient T(w) of free-space springs xs, beta at
+    frequencies w > 0: the total field right of every spring is
+    T(w) F(w) e^{iwx} for an incident wave F(w) e^{iwx}.  With the Green's
+    function (1/2) H(t - |x|) -> (i/(2w)) e^{iw|x|} and the spring condition
+    -sigma_j = beta_j u_tot(x_j),
+        (I + A) v = e^{iw x},   A_jl = (i beta_l/(2w)) e^{iw|x_j - x_l|},
+        T = 1 - sum_l (i beta_l/(2w)) e^{-iw x_l} v_l."""
+    xs = np.asarray(xs, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    M = xs.size
+    d = np.abs(xs[:, None] - xs[None, :])
+    out = np.empty(w.size, np.complex128)
+    chunk = 4096
+    for a in range(0, w.size, chunk):
+        ww = w[a:a + chunk]
+        A = (1j * beta[None, None, :] / (2.0 * ww[:, None, None])) * np.exp(1j * ww[:, None, None] * d[None, :, :])
+        A = A + np.eye(M)[None, :, :]
+        v = np.linalg.solve(A, np.exp(1j * ww[:, None] * xs[None, :])[..., None])[..., 0]
+        out[a:a + chunk] = 1.0 - ((1j * beta[None, :] / (2.0 * ww[:, None])) * np.exp(-1j * ww[:, None] * xs[None, :])
+                                  * v).sum(axis=1)
+    return out
+
+
+def spring_array_field(xr, t, xs, beta, mu, t0, w_max=None, dw=None):
+    """Total field u_inc + u at a point xr to the right of every spring, for
+    the free-space springs xs, beta and the incident wave f(x - t) with
+    f(s) = exp(-mu (s - t0)^2), at times t: the inverse transform of
+    T(w) F(w) e^{iw xr} (spring_array_transmission), with u(t) =
+    (1/2pi) int u^(w) e^{-iwt} dw and F(w) = sqrt(pi/mu) e^{-iw t0}
+    e^{-w^2/(4 mu)}, by the trapezoid rule on a midpoint grid of |w| <= w_max
+    (the spectrum falls like e^{-w^2/(4 mu)}); it converges geometrically while
+    dw is well below the width of the sharpest resonance (the resonances are
+    poles a distance ~ that width off the real axis)."""
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    if w_max is None:
+        w_max = math.sqrt(4.0 * mu * 40.0)              # e^{-40} of the peak
+    if dw is None:
+        dw = 1e-4
+    n = int(math.ceil(w_max / dw))
+    w = (np.arange(n) + 0.5) * dw                       # w > 0; w < 0 by conjugate symmetry
+    F = math.sqrt(math.pi / mu) * np.exp(-1j * w * t0 - w * w / (4.0 * mu))
+    U = spring_array_transmission(w, xs, beta) * F * np.exp(1j * w * xr)
+    # u(t) = (1/2pi) int U e^{-iwt} dw = (1/pi) Re int_0^inf U e^{-iwt} dw
+    out = np.empty(t.size)
+    for i, tt in enumerate(t):
+        out[i] = (dw / math.pi) * np.real(np.sum(U * np.exp(-1j * w * tt)))
+    return out

@@ -208,6 +208,32 @@ def manufactured_data(prob, dt, n_levels):
     return g
 
 
+def spring_filter(M, beta, t0, n_steps, span=(-1.0, 1.0), dt=0.01, x_recv=1.5, p=8):
+    """The filter demonstrations of Section 6.3: M equal springs evenly
+    spaced over `span` (both ends included), free space, incident wave
+    f(x - t) with f(s) = exp(-5 (s - t0)^2), dt = 0.01, interpolation order p,
+    one receiver downstream at x_recv."""
+    x = np.linspace(span[0], span[1], M)
+    return dict(x=x, beta=np.full(M, float(beta)),
+                packets=np.array([[1.0, t0, 1.0 / math.sqrt(10.0), 0.0, 0.0]]), boundary=1, dt=dt,
+                n_steps=n_steps, x_recv=np.array([x_recv]), p=p, mu=5.0, t0=t0,
+                name=f"filter-M{M}-beta{beta:g}")
+
+
+def fabry_perot():
+    """Two springs of stiffness 100 at -0.5 and 0.5 (cavity length 1), pulse
+    exp(-5 (s + 3)^2), 9426 levels of dt = 0.01, p = 6 (at beta dt / 2 = 0.5
+    the p = 8 local rule is unstable)."""
+    return spring_filter(2, 100.0, -3.0, 9426, span=(-0.5, 0.5), p=6)
+
+
+def spring_arrays():
+    """M = 10 springs of stiffness 100 (p = 6, as for the cavity) and M = 200
+    of stiffness 1 (p = 8), evenly on [-1, 1] (the spacing is a reading),
+    pulse exp(-5 (s + 4)^2), 25134 levels of dt = 0.01."""
+    return [spring_filter(10, 100.0, -4.0, 25134, p=6), spring_filter(200, 1.0, -4.0, 25134, p=8)]
+
+
 def adjoint_periodic(seed=5, M=100_000, dt=1e-3, n_steps=5000, R=64):
     """Periodic, M springs with beta ~ U[1, 10], a single Gaussian pulse
     (width 0.05) and R receivers spread over the spring region."""

@@ -124,3 +124,37 @@ def test_delay_differential_brute_force_free_space_with_rbc():
     sig, _ = o.run(1101)
     _, ref = solve_delay_system(x, beta, PULSE, False, 11.0, 110)
     assert np.max(np.abs(sig[::10] - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_frequency_domain_field_of_springs():
+    """The frequency-domain solution for point springs (spring_array_field):
+    M = 1 against the closed form in erfc (Section 5.1), M = 3 against the
+    oracle march's total field at a receiver right of the springs (free
+    space, waves leaving through the RBC)."""
+    from oracle.exact import spring_array_field, spring_array_transmission
+    # one spring: |T|^2 = 4 w^2 / (4 w^2 + beta^2), the textbook point scatterer
+    w = np.array([0.5, 2.0, 7.0])
+    T = spring_array_transmission(w, [0.3], [4.0])
+    assert np.max(np.abs(np.abs(T) ** 2 - 4 * w * w / (4 * w * w + 16.0))) < 1e-15
+    mu, t0 = 5.0, -3.0
+    # M = 1
+    x1, b1, xr = 0.3, 4.0, 1.0
+    t = np.linspace(0.0, 12.0, 25)
+    u = spring_array_field(xr, t, [x1], [b1], mu, t0, dw=2e-3)
+    tau = t - (xr - x1)
+    _, I = single_spring(np.maximum(tau, 0.0), x1, b1, 1.0, t0, 1.0 / math.sqrt(2.0 * mu))
+    ref = np.exp(-mu * (xr - t - t0) ** 2) + 0.5 * np.where(tau > 0.0, I, 0.0)
+    assert np.max(np.abs(u - ref)) < 1e-13
+    # M = 3, the march (p = 8, dt = 0.01) to 11 time units
+    x = np.array([0.5, 0.6, 1.0])
+    beta = np.array([3.0, 7.0, 5.0])
+    xr = 1.4
+    pulse = np.array([[1.0, t0, 1.0 / math.sqrt(2.0 * mu), 0.0, 0.0]])
+    prm = Params(dt=0.01, boundary=FREE_SPACE)
+    o = Oracle(x, beta, prm, incident_driving(x, beta, pulse, False), x_recv=np.array([xr]))
+    _, ur = o.run(1101)
+    lv = np.arange(0, 1101, 20)
+    tt = lv * prm.dt
+    tot = ur[lv, 0] + np.exp(-mu * (xr - tt - t0) ** 2)
+    ex = spring_array_field(xr, tt, x, beta, mu, t0, dw=1e-3)
+    assert np.max(np.abs(tot - ex)) < 1e-9 * np.max(np.abs(ex))
