@@ -423,6 +423,51 @@ def filters_leg():
     return {"workload": "spring filters (Section 6.3), free space, dt = 0.01", "runs": rows}
 
 
+def disordered_leg(large_levels):
+    """The long disordered runs of Section 6.2 (random springs on [-2, 2], a
+    pulse of width sqrt(8) times the mean spacing, p = 8): M = 1e3 marched
+    in full (72044 levels) and at dt / 2 (144088 levels), the estimated error
+    of the first from the second at 50 receivers; M = 1e4 timed over its
+    first `large_levels` levels (of 720440).  The paper's times (a laptop,
+    other hardware) are quoted as context."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    out = {"workload": "disordered springs (Section 6.2), free space, p = 8"}
+    us = []
+    for rf in (1, 2):
+        prob = workloads.disordered_long(1000, refine=rf)
+        n = prob["n_steps"]
+        plan = wfp.Plan(prob, prob["dt"], p=prob["p"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, u = plan.march(n, save_every=n)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"M1000_dt{'' if rf == 1 else '_half'}"] = {"dt": prob["dt"], "K": plan.info["K"], "levels": n,
+                                                         "march_s": el, "ms_per_level": 1e3 * el / n}
+        plan.close()
+        us.append(u.cpu().numpy())
+    ref = us[1][::2][: us[0].shape[0]]
+    out["M1000_estimated_rel_error"] = float(np.max(np.abs(us[0] - ref)) / np.max(np.abs(ref)))
+    out["M1000_paper"] = {"s_per_level": 0.02, "total_min": 24}
+    if large_levels > 0:
+        prob = workloads.disordered_long(10_000)
+        plan = wfp.Plan(prob, prob["dt"], p=prob["p"])
+        plan.run(50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run(large_levels)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ms = 1e3 * el / large_levels
+        out["M10000"] = {"dt": prob["dt"], "K": plan.info["K"], "levels_timed": large_levels, "ms_per_level": ms,
+                         "projected_full_run_min": ms * prob["n_steps"] / 6e4,
+                         "paper": {"s_per_level": 0.15, "total_h": 29.5}}
+        plan.close()
+    log(f"disordered leg: {out}")
+    return out
+
+
 def clumped_leg(levels):
     """The clumped free-space workload at full size (M = 1e6, dt = 5e-4, K = 6250,
     local weights on the fly): set-up time and the rate over `levels` levels
@@ -478,6 +523,8 @@ def main():
     ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
     ap.add_argument("--no-convergence", action="store_true", help="skip the manufactured-solution leg")
     ap.add_argument("--no-filters", action="store_true", help="skip the spring-filter leg")
+    ap.add_argument("--disordered-levels", type=int, default=20000,
+                    help="levels timed at M = 1e4 in the disordered leg (negative skips the leg)")
     ap.add_argument("--balanced-levels", type=int, default=2000,
                     help="levels per size of the free-space scaling-study leg (0 skips it)")
     ap.add_argument("--balanced-sizes", type=str, default="1000,10000,100000,1000000",
@@ -598,6 +645,10 @@ def main():
     if not args.no_filters:
         filters = filters_leg()
 
+    disordered = None
+    if args.disordered_levels >= 0:
+        disordered = disordered_leg(args.disordered_levels)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_steps)
@@ -612,7 +663,7 @@ def main():
                    "levels_timed": args.steps, "overlap_cus": info["overlap_cus"], "parallelism": "single GPU"},
         "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch,
         "batch_full_range": batch_full, "clumped": clumped, "balanced": balanced, "convergence": convergence,
-        "filters": filters, "cpu_baseline": cpu,
+        "filters": filters, "disordered": disordered, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()

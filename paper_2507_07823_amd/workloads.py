@@ -234,6 +234,25 @@ def spring_arrays():
     return [spring_filter(10, 100.0, -4.0, 25134, p=6), spring_filter(200, 1.0, -4.0, 25134, p=8)]
 
 
+def disordered_long(M, seed=11, refine=1, n_recv=50):
+    """The long disordered runs of Section 6.2: free space, M springs uniform
+    in [-2, 2], beta ~ U[0.1, 3], a narrow pulse f(s) = exp(-M^2 (s + 3)^2)
+    (width sqrt(8) times the mean spacing 4/M), p = 8, the paper's time steps
+    (1.308e-4 at M = 1e3, 1.308e-5 at M = 1e4; dt scales like 1/M) and level
+    counts (72044, 720440; about 3 pi), n_recv receivers evenly on
+    [-2.5, 2.5].  refine = 2 halves dt and doubles the levels (the paper's
+    self-convergence check)."""
+    r = _rng(seed, M)
+    x = r.uniform(-2.0, 2.0, M)
+    beta = r.uniform(0.1, 3.0, M)
+    width = 1.0 / (math.sqrt(2.0) * M)            # exp(-M^2 s^2) = exp(-s^2 / (2 width^2))
+    dt = 1.308e-4 * (1000.0 / M) / refine
+    n_steps = int(round(72.044 * M)) * refine
+    return dict(x=x, beta=beta, packets=np.array([[1.0, -3.0, width, 0.0, 0.0]]), boundary=1, dt=dt,
+                n_steps=n_steps, x_recv=np.linspace(-2.5, 2.5, n_recv), p=8,
+                name=f"disordered-M{M}-dt{dt:.4g}-Nt{n_steps}")
+
+
 def adjoint_periodic(seed=5, M=100_000, dt=1e-3, n_steps=5000, R=64):
     """Periodic, M springs with beta ~ U[1, 10], a single Gaussian pulse
     (width 0.05) and R receivers spread over the spring region."""
