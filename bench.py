@@ -468,6 +468,41 @@ def disordered_leg(large_levels):
     return out
 
 
+def disordered_full(M=10_000, chunk=50_000):
+    """The long disordered run at M in full, at dt and at dt / 2 (for M = 1e4:
+    720440 and 1440880 levels), marched in chunks with a progress line per
+    chunk; returns the times and the estimated error of the dt run at its 50
+    receivers."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    out = {"workload": f"disordered springs (Section 6.2), M = {M}, full run", "M": M}
+    us = []
+    for rf in (1, 2):
+        prob = workloads.disordered_long(M, refine=rf)
+        n, R = prob["n_steps"], prob["x_recv"].size
+        t0 = time.perf_counter()
+        plan = wfp.Plan(prob, prob["dt"], p=prob["p"])
+        setup = time.perf_counter() - t0
+        u = torch.empty((n, R), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a in range(0, n, chunk):
+            b = min(n, a + chunk)
+            plan.run(b - a, None, 1, u[a:b])
+            torch.cuda.synchronize()
+            log(f"disordered M={M} refine={rf}: level {b} of {n}, {time.perf_counter() - t0:.1f} s")
+        el = time.perf_counter() - t0
+        out[f"refine{rf}"] = {"dt": prob["dt"], "K": plan.info["K"], "n_fine": plan.info["n_fine"], "levels": n,
+                              "plan_setup_s": setup, "march_s": el, "ms_per_level": 1e3 * el / n}
+        plan.close()
+        us.append(u.cpu().numpy())
+        del u
+    ref = us[1][::2][: us[0].shape[0]]
+    out["estimated_rel_error"] = float(np.max(np.abs(us[0] - ref)) / np.max(np.abs(ref)))
+    out["field_max"] = float(np.max(np.abs(ref)))
+    return out
+
+
 def clumped_leg(levels):
     """The clumped free-space workload at full size (M = 1e6, dt = 5e-4, K = 6250,
     local weights on the fly): set-up time and the rate over `levels` levels
@@ -523,6 +558,9 @@ def main():
     ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
     ap.add_argument("--no-convergence", action="store_true", help="skip the manufactured-solution leg")
     ap.add_argument("--no-filters", action="store_true", help="skip the spring-filter leg")
+    ap.add_argument("--disordered-full", action="store_true",
+                    help="only run the M = 1e4 disordered run in full at dt and dt/2 (about 15 GPU-minutes) "
+                         "and print its result")
     ap.add_argument("--disordered-levels", type=int, default=20000,
                     help="levels timed at M = 1e4 in the disordered leg (negative skips the leg)")
     ap.add_argument("--balanced-levels", type=int, default=2000,
@@ -561,6 +599,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.disordered_full:
+        print(json.dumps(disordered_full()), flush=True)
         return
     p = workloads.multiband_periodic()
     M = p["x"].size
