@@ -123,6 +123,9 @@ struct wfp_plan {
   FftPlan fft_nf{}, fft_rbc{}, fft_n1{}, fft_n2{};
   // threads of the row passes (256, or 1024 for long rows)
   int hist_threads = 256;
+  // FIR tap groups of the column pass and its LDS bytes
+  int fir_groups = 8;
+  size_t lds_b = 0;
   // boundary projection over workgroups for long grids: K = rbc_a rbc_b
   bool rbc_split = false;
   int rbc_a = 0, rbc_b = 0;

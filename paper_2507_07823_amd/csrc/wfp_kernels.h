@@ -155,13 +155,14 @@ __global__ void k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int
                          const int* __restrict__ cstart, const int* __restrict__ ccount,
                          const int64_t* __restrict__ woff, const double* __restrict__ sw,
                          const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex);
+// FIR taps split over G groups whose partial sums meet in LDS ([G][2 n1] double4)
 __global__ void k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos,
                          const double2* __restrict__ T1, const double2* __restrict__ tw,
                          const double* __restrict__ dk1, const double* __restrict__ dk2,
                          const double* __restrict__ pk, const double* __restrict__ qk,
                          const double* __restrict__ rot, double2* __restrict__ ring,
                          double2* __restrict__ alpha, double2* __restrict__ dalpha, double2* __restrict__ y,
-                         double2* __restrict__ V);
+                         double2* __restrict__ V, int G);
 __global__ void k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
                          double2* __restrict__ grid2);
 // the same row passes with 1024 threads, for rows of more than 1024 butterflies per stage at 256

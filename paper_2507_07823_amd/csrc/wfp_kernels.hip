@@ -1508,14 +1508,14 @@ __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int6
          const double2* __restrict__ tw, const double* __restrict__ dk1, const double* __restrict__ dk2,
          const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,
          double2* __restrict__ ring, double2* __restrict__ alpha, double2* __restrict__ dalpha,
-         double2* __restrict__ y, double2* __restrict__ V, int bid) {
+         double2* __restrict__ y, double2* __restrict__ V, int G, int bid) {
   extern __shared__ double2 smb[];
   const int n1 = f1.n;
   const int n = n1 * n2;
   double2* buf = smb;                         // [2][n1]
   double2* yl = smb + 2 * n1;                 // [2][n1]
   double2* sS = smb + 4 * n1;                 // [2][n1]
-  double4* red = (double4*)(smb + 6 * n1);    // [kFirGroups][2 n1]
+  double4* red = (double4*)(smb + 6 * n1);    // [G][2 n1]
   const int k2a = bid, k2b = (n2 - k2a) % n2;
   const int ncol = (k2a == k2b) ? 1 : 2;
   const int np = ncol * n1;
@@ -1547,14 +1547,14 @@ __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int6
     }
     __syncthreads();
     // FIR partial sums: work item (e, g) takes taps m = g, g + G, ...
-    for (int wi = threadIdx.x; wi < np * kFirGroups; wi += blockDim.x) {
+    for (int wi = threadIdx.x; wi < np * G; wi += blockDim.x) {
       const int g = wi / np, e = wi - g * np;
       const int c = e / n1, k1 = e - c * n1;
       const int64_t q = colk2(c) + (int64_t)n2 * k1;
       double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
       if (q <= K) {
 #pragma unroll 2
-        for (int m = g; m < W; m += kFirGroups) {
+        for (int m = g; m < W; m += G) {
           const double2 Sm = (m == 0) ? sS[e] : ring[(int64_t)mod_slot(nn - m, W) * stride + pb + e];
           const double p = pk[(int64_t)m * stride + pb + e], qq = qk[(int64_t)m * stride + pb + e];
           acc.x = fma(p, Sm.x, acc.x);
@@ -1572,7 +1572,7 @@ __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int6
       double2 yq = make_double2(0.0, 0.0);
       if (q <= K) {
         double2 h = make_double2(0.0, 0.0), g = make_double2(0.0, 0.0);
-        for (int gg = 0; gg < kFirGroups; ++gg) {
+        for (int gg = 0; gg < G; ++gg) {
           const double4 v = red[gg * np + e];
           h.x += v.x;
           h.y += v.y;
@@ -1628,8 +1628,8 @@ k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos
          const double2* __restrict__ tw, const double* __restrict__ dk1, const double* __restrict__ dk2,
          const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,
          double2* __restrict__ ring, double2* __restrict__ alpha, double2* __restrict__ dalpha,
-         double2* __restrict__ y, double2* __restrict__ V) {
-  k_hist_b_body(mode, f1, n2, K, W, L, npos, T1, tw, dk1, dk2, pk, qk, rot, ring, alpha, dalpha, y, V, blockIdx.x);
+         double2* __restrict__ y, double2* __restrict__ V, int G) {
+  k_hist_b_body(mode, f1, n2, K, W, L, npos, T1, tw, dk1, dk2, pk, qk, rot, ring, alpha, dalpha, y, V, G, blockIdx.x);
 }
 
 __device__ __forceinline__ void k_hist_c_body(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
@@ -1828,7 +1828,7 @@ __global__ void __launch_bounds__(512) kb_hist_b(BatchLaunch b) {
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
   k_hist_b_body(0, d.f1, d.n2, d.K, d.W, *b.level, d.npos, d.T1, d.tw, d.dk1, d.dk2, d.pk, d.qk, d.rot, d.ring,
-                d.alpha, d.dalpha, d.ybuf, d.V, w.y);
+                d.alpha, d.dalpha, d.ybuf, d.V, kFirGroups, w.y);
 }
 
 __global__ void __launch_bounds__(256) kb_hist_c(BatchLaunch b) {

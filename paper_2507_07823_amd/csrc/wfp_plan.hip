@@ -1014,8 +1014,13 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     const int dyn = (int)((size_t)(P->NQ - 1) * kOtfChunk * sizeof(double));
     for (const void* f : fns) HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
   }
-  if (6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4) > 160 * 1024)
-    fail(WFP_EDOMAIN, "four-step factor n1 too long for the history kernel's LDS");
+  // the column pass holds 6 n1 complex values and the FIR partial sums of G
+  // tap groups ([G][2 n1] double4); column pairs of 400 modes or more keep one
+  // or two modes per thread with G = 2 (and fit two blocks per compute unit),
+  // shorter ones split the taps 8 ways to give every thread work
+  P->fir_groups = 2 * P->n1 >= 400 ? 2 : 8;
+  P->lds_b = 6 * (size_t)P->n1 * sizeof(double2) + (size_t)P->fir_groups * 2 * P->n1 * sizeof(double4);
+  if (P->lds_b > 160 * 1024) fail(WFP_EDOMAIN, "four-step factor n1 too long for the history kernel's LDS");
   {
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, P->device));
@@ -1152,7 +1157,7 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
   if (overlap && sc != s) HIPCHK(hipStreamWaitEvent(sc, P->ev_solved, 0));
   const bool periodic = P->boundary == WFP_PERIODIC;
   const unsigned nb_b = (unsigned)(P->n2 / 2 + 1);
-  const size_t lds_b = 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4);
+  const size_t lds_b = P->lds_b;
   const double* sig_prev = S.hist + (int64_t)(((L - 1) % P->NH + P->NH) % P->NH) * P->M;
   const double* gin = driven ? P->ginc : driving_row(P, s, L);
   {
@@ -1187,7 +1192,7 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
     StageTimer st(P, WFP_STAGE_MODES, sc);
     hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, sc, rbc ? 1 : 0, P->fft_n1, P->n2, P->K, P->W, L,
                        P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha,
-                       P->ybuf, P->V);
+                       P->ybuf, P->V, P->fir_groups);
   }
   if (rbc) {
     StageTimer st(P, WFP_STAGE_RBC, sc);
@@ -1218,7 +1223,7 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
     }
     hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, sc, 2, P->fft_n1, P->n2, P->K, P->W, L, P->npos,
                        P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha, P->ybuf,
-                       P->V);
+                       P->V, P->fir_groups);
   }
   {
     StageTimer st(P, WFP_STAGE_FFT_INV, sc);
@@ -1502,12 +1507,12 @@ void gradx_setup(wfp_plan* P) {
 void deriv_field(wfp_plan* P, const StateRef& S) {
   hipStream_t s = P->stream;
   const unsigned nb_b = (unsigned)(P->n2 / 2 + 1);
-  const size_t lds_b = 6 * (size_t)P->n1 * sizeof(double2) + 16 * (size_t)P->n1 * sizeof(double4);
+  const size_t lds_b = P->lds_b;
   hipLaunchKernelGGL(k_deriv_y, dim3(nblk(P->K + 1, 256)), dim3(256), 0, s, P->K, P->n1, P->n2, S.alpha, P->dk2,
                      P->yd);
   hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, (int64_t)0,
                      P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha, P->yd,
-                     P->V);
+                     P->V, P->fir_groups);
   launch_hist_c(P, s, (double2*)P->gridd);
 }
 
