@@ -124,17 +124,17 @@ def paper_balanced_free_space(M, seed=6, n_steps=2000, m_typ=100.0, min_sep=1e-6
                 x_recv=np.zeros(0), p=6, name=f"free-balanced-M{M}-dt{dt:.4g}-Nt{n_steps}")
 
 
-def long_grid_free_space(M=400, seed=8, n_steps=10, spread=0.02):
-    """Free space at the time step of the scaling study's largest size
-    (M = 1e6, so K = 524288) with only M springs, packed in [-spread, spread]
-    so each has a few neighbours: the fine grid and boundary grid of the
-    largest study size at a size the oracle can march.  Pulse and strengths
-    as in paper_balanced_free_space; p = 6."""
+def long_grid_free_space(M=400, seed=8, n_steps=10, spread=0.02, study_M=1_000_000):
+    """Free space at the time step of the scaling study's size study_M
+    (1e6: K = 524288; 1e5: K = 51200) with only M springs, packed in
+    [-spread, spread] so each has a few neighbours: the fine grid and boundary
+    grid of that study size at a size the oracle can march.  Pulse and
+    strengths as in paper_balanced_free_space; p = 6."""
     r = _rng(seed, M)
     x = r.uniform(-spread, spread, M)
     beta = r.uniform(0.1, 3.0, M)
     packets = np.array([[1.0, -3.0, 1.0 / math.sqrt(60.0), 0.0, 0.0]])
-    dt = balanced_dt(1_000_000)
+    dt = balanced_dt(study_M)
     return dict(x=x, beta=beta, packets=packets, boundary=1, dt=dt, n_steps=n_steps,
                 x_recv=np.zeros(0), p=6, name=f"free-long-grid-M{M}-dt{dt:.4g}")
 

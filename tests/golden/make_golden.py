@@ -3,6 +3,7 @@
     python tests/golden/make_golden.py multiband
     python tests/golden/make_golden.py balanced
     python tests/golden/make_golden.py longgrid
+    python tests/golden/make_golden.py midgrid
 
 multiband: the periodic multiband workload (M = 1e4, dt = 1e-3, 1e4 steps)
 marched by the oracle for levels 0..n_steps; stores sigma at a few levels for
@@ -20,6 +21,9 @@ longgrid: 400 springs at the time step of the scaling study's M = 1e6
 (K = 524288, fine grid 2.5e6 points): the same three levels from a seeded
 state, the boundary correction firing after the first; alpha, alpha' and
 the spectrum are stored every 256th mode.
+
+midgrid: the same at the time step of the study's M = 1e5 (K = 51200, a
+boundary grid split 200 x 256 over workgroups), every 32nd mode.
 """
 import os
 import sys
@@ -102,10 +106,14 @@ def longgrid():
     state_steps(workloads.long_grid_free_space(), "longgrid_state_steps.npz", 9, 2.9, 256)
 
 
+def midgrid():
+    state_steps(workloads.long_grid_free_space(spread=0.2, study_M=100_000), "midgrid_state_steps.npz", 12, 2.9, 32)
+
+
 def balanced():
     state_steps(workloads.paper_balanced_free_space(BALANCED_M), "balanced_state_steps.npz",
                 BALANCED_STATE_SEED, 1.2, 8)
 
 
 if __name__ == "__main__":
-    {"multiband": multiband, "balanced": balanced, "longgrid": longgrid}[sys.argv[1]]()
+    {"multiband": multiband, "balanced": balanced, "longgrid": longgrid, "midgrid": midgrid}[sys.argv[1]]()

@@ -5,9 +5,9 @@ about 100).
 
 * M = 1e3 (K = 512): a full march from rest through the pulse's passage,
   every density of every level against the oracle.
-* M = 2e4 (K = 10240) and 400 springs at the time step of the study's
-  M = 1e6 (K = 524288, a fine grid of 2.5e6 points whose rows take the
-  1024-thread passes): three levels from a seeded mid-run state across a
+* M = 2e4 (K = 10240), and 400 springs at the time steps of the study's
+  M = 1e5 (K = 51200 = 200 x 256) and M = 1e6 (K = 524288, a fine grid of
+  2.5e6 points whose rows take the 1024-thread passes): three levels from a seeded mid-run state across a
   boundary correction (computed over workgroups at these K), against the
   oracle's values stored by tests/golden/make_golden.py.
 """
@@ -68,12 +68,17 @@ def test_balanced_small_full_march(wfp):
     assert r < TOL
 
 
-@pytest.mark.parametrize("case", ["balanced", "longgrid"])
+@pytest.mark.parametrize("case", ["balanced", "midgrid", "longgrid"])
 def test_long_grids_from_state(wfp, case):
     import torch
     g = np.load(os.path.join(GOLDEN_DIR, f"{case}_state_steps.npz"))
     M = int(g["M"])
-    p = workloads.paper_balanced_free_space(M) if case == "balanced" else workloads.long_grid_free_space(M)
+    if case == "balanced":
+        p = workloads.paper_balanced_free_space(M)
+    elif case == "midgrid":
+        p = workloads.long_grid_free_space(M, spread=0.2, study_M=100_000)
+    else:
+        p = workloads.long_grid_free_space(M)
     prm = Params(dt=p["dt"], boundary=FREE_SPACE, p=p["p"])
     assert prm.K == int(g["K"])
     st = workloads.random_state(int(g["state_seed"]), M, prm.K, prm.W, prm.m_max)
