@@ -273,7 +273,10 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->n2 = (int)(n / n1s);
     P->fft_n1 = make_fft_plan(P->n1);
     P->fft_n2 = make_fft_plan(P->n2);
-    P->hist_threads = 256;
+    // rows of 1024 points or more run on 1024 threads: the n1 <= 256 row
+    // blocks are then about one per compute unit, and 256 threads (4
+    // wavefronts) cannot hide the latency of their gathers and FFT stages
+    P->hist_threads = P->n2 >= 1024 ? 1024 : 256;
     for (int i = 0; i < P->fft_n2.nst; ++i)
       if (P->n2 / P->fft_n2.radix[i] > kFftMaxB * 256) P->hist_threads = 1024;
     P->npos = (int64_t)(P->n2 / 2 + 1) * 2 * P->n1;
