@@ -93,6 +93,7 @@ InstDesc describe(const wfp_plan* P) {
   d.swoff = P->swoff;
   d.sw = P->sw;
   d.tw = P->tw;
+  d.tw1 = P->tw1;
   d.T1 = P->T1;
   d.V = P->V;
   d.grid2 = P->grid2;

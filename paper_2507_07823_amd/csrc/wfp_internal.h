@@ -143,6 +143,7 @@ struct wfp_plan {
   double2 *ring = nullptr, *alpha = nullptr, *dalpha = nullptr;
   double *pk = nullptr, *qk = nullptr, *rot = nullptr, *dk1 = nullptr, *dk2 = nullptr;
   double2* tw = nullptr;
+  double2* tw1 = nullptr;   // tw[n2 k1], k1 < n1 (the column pass's twiddle factor)
   double2* tw_rbc = nullptr;
   double2* ybuf = nullptr;
   double* grid2 = nullptr;

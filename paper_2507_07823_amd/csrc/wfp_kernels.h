@@ -158,7 +158,7 @@ __global__ void k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int
 // FIR taps split over G groups whose partial sums meet in LDS ([G][2 n1] double4)
 __global__ void k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos,
                          const double2* __restrict__ T1, const double2* __restrict__ tw,
-                         const double* __restrict__ dk1, const double* __restrict__ dk2,
+                         const double2* __restrict__ tw1, const double* __restrict__ dk1, const double* __restrict__ dk2,
                          const double* __restrict__ pk, const double* __restrict__ qk,
                          const double* __restrict__ rot, double2* __restrict__ ring,
                          double2* __restrict__ alpha, double2* __restrict__ dalpha, double2* __restrict__ y,
@@ -248,6 +248,7 @@ struct InstDesc {
   const int64_t* swoff;
   const double* sw;
   const double2* tw;
+  const double2* tw1;
   double2 *T1, *V;
   double* grid2;
   const double *dk1, *dk2, *pk, *qk, *rot;

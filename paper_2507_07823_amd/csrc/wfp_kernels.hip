@@ -1505,7 +1505,7 @@ __device__ __forceinline__ int partner(int c, int k1, int k2c, int ncol, int n1)
 // modes, writing y (the type-2 input) for a later projection; mode 2: inverse
 // step 1 from y.
 __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos, const double2* __restrict__ T1,
-         const double2* __restrict__ tw, const double* __restrict__ dk1, const double* __restrict__ dk2,
+         const double2* __restrict__ tw, const double2* __restrict__ tw1, const double* __restrict__ dk1, const double* __restrict__ dk2,
          const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,
          double2* __restrict__ ring, double2* __restrict__ alpha, double2* __restrict__ dalpha,
          double2* __restrict__ y, double2* __restrict__ V, int G, int bid) {
@@ -1540,7 +1540,9 @@ __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int6
         const double2 zc = cconj(buf[partner(c, k1, k2a, ncol, n1)]);
         const double2 E = cscale(cadd(zk, zc), 0.5);
         const double2 O = cscale(cmul_mi(csub(zk, zc)), 0.5);
-        const double2 X = cadd(E, cmul(tw[q], O));
+        // e^{-2 pi i q / N} = e^{-2 pi i k2 / N} e^{-2 pi i k1 / (2 n1)}: the column's
+        // factor and a short table instead of a stride-n2 gather
+        const double2 X = cadd(E, cmul(cmul(tw[colk2(c)], tw1[k1]), O));
         S = cscale(cconj(X), dk1[pb + e]);
       }
       sS[e] = S;
@@ -1607,7 +1609,7 @@ __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int6
     const int q = colk2(c) + n2 * k1;
     const double2 yk = yl[e];
     const double2 ym = (q == 0) ? make_double2(0.0, 0.0) : cconj(yl[partner(c, k1, k2a, ncol, n1)]);
-    const double2 zq = cadd(cadd(yk, ym), cmul_pi(cmul(cconj(tw[q]), csub(yk, ym))));
+    const double2 zq = cadd(cadd(yk, ym), cmul_pi(cmul(cconj(cmul(tw[colk2(c)], tw1[k1])), csub(yk, ym))));
     buf[e] = cconj(zq);
   }
   __syncthreads();
@@ -1625,11 +1627,12 @@ __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int6
 // its n2/2 + 1 blocks on one XCD's 32 compute units in one round
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos, const double2* __restrict__ T1,
-         const double2* __restrict__ tw, const double* __restrict__ dk1, const double* __restrict__ dk2,
-         const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,
-         double2* __restrict__ ring, double2* __restrict__ alpha, double2* __restrict__ dalpha,
-         double2* __restrict__ y, double2* __restrict__ V, int G) {
-  k_hist_b_body(mode, f1, n2, K, W, L, npos, T1, tw, dk1, dk2, pk, qk, rot, ring, alpha, dalpha, y, V, G, blockIdx.x);
+         const double2* __restrict__ tw, const double2* __restrict__ tw1, const double* __restrict__ dk1,
+         const double* __restrict__ dk2, const double* __restrict__ pk, const double* __restrict__ qk,
+         const double* __restrict__ rot, double2* __restrict__ ring, double2* __restrict__ alpha,
+         double2* __restrict__ dalpha, double2* __restrict__ y, double2* __restrict__ V, int G) {
+  k_hist_b_body(mode, f1, n2, K, W, L, npos, T1, tw, tw1, dk1, dk2, pk, qk, rot, ring, alpha, dalpha, y, V, G,
+                blockIdx.x);
 }
 
 __device__ __forceinline__ void k_hist_c_body(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
@@ -1827,7 +1830,7 @@ __global__ void __launch_bounds__(512) kb_hist_b(BatchLaunch b) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
-  k_hist_b_body(0, d.f1, d.n2, d.K, d.W, *b.level, d.npos, d.T1, d.tw, d.dk1, d.dk2, d.pk, d.qk, d.rot, d.ring,
+  k_hist_b_body(0, d.f1, d.n2, d.K, d.W, *b.level, d.npos, d.T1, d.tw, d.tw1, d.dk1, d.dk2, d.pk, d.qk, d.rot, d.ring,
                 d.alpha, d.dalpha, d.ybuf, d.V, kFirGroups, w.y);
 }
 

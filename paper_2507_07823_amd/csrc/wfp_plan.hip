@@ -400,6 +400,10 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
       tw[t] = make_double2((double)std::cos(a), (double)std::sin(a));
     }
     upload(P->tw, tw, s);
+    std::vector<double2> tw1(P->n1);
+    for (int k1 = 0; k1 < P->n1; ++k1) tw1[k1] = tw[(int64_t)P->n2 * k1];
+    P->tw1 = P->alloc<double2>(P->n1);
+    upload(P->tw1, tw1, s);
   }
   // ---- NUFFT deconvolution: Psi_hat(k) = alpha int_{-1}^{1} psi(z) cos(k alpha z) dz ----
   {
@@ -1194,8 +1198,8 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
   {
     StageTimer st(P, WFP_STAGE_MODES, sc);
     hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, sc, rbc ? 1 : 0, P->fft_n1, P->n2, P->K, P->W, L,
-                       P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha,
-                       P->ybuf, P->V, P->fir_groups);
+                       P->npos, P->T1, P->tw, P->tw1, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha,
+                       S.dalpha, P->ybuf, P->V, P->fir_groups);
   }
   if (rbc) {
     StageTimer st(P, WFP_STAGE_RBC, sc);
@@ -1225,8 +1229,8 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
                          P->n1, P->n2, P->rbc_z, P->tw_rbc, P->dk2, S.alpha, S.dalpha, P->ybuf);
     }
     hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, sc, 2, P->fft_n1, P->n2, P->K, P->W, L, P->npos,
-                       P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha, P->ybuf,
-                       P->V, P->fir_groups);
+                       P->T1, P->tw, P->tw1, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha,
+                       P->ybuf, P->V, P->fir_groups);
   }
   {
     StageTimer st(P, WFP_STAGE_FFT_INV, sc);
@@ -1514,8 +1518,8 @@ void deriv_field(wfp_plan* P, const StateRef& S) {
   hipLaunchKernelGGL(k_deriv_y, dim3(nblk(P->K + 1, 256)), dim3(256), 0, s, P->K, P->n1, P->n2, S.alpha, P->dk2,
                      P->yd);
   hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, (int64_t)0,
-                     P->npos, P->T1, P->tw, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha, P->yd,
-                     P->V, P->fir_groups);
+                     P->npos, P->T1, P->tw, P->tw1, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha,
+                     S.dalpha, P->yd, P->V, P->fir_groups);
   launch_hist_c(P, s, (double2*)P->gridd);
 }
 
