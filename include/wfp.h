@@ -59,7 +59,7 @@ typedef int32_t wfp_status;
 #define WFP_PERIODIC 0      /* periodic box [-pi, pi) (Section 2) */
 #define WFP_FREE_SPACE 1    /* free space via outgoing windowing (Section 4.4) */
 
-#define WFP_ABI_VERSION 4
+#define WFP_ABI_VERSION 5
 
 typedef struct wfp_plan wfp_plan;
 

@@ -1911,10 +1911,30 @@ wfp_status wfp_plan_autotune(wfp_plan* P, int32_t trial_levels, int32_t* overlap
     if (P->ckpt_every == 0)
       for (int q = 1; q <= 4 && q < nx; ++q) cand.push_back(q * (ncu / nx));
     hipStream_t s = P->stream;
-    hipEvent_t a, c;
+    hipEvent_t a = nullptr, c = nullptr;
+    const bool prof = P->profiling;
+    const int before = P->overlap_cus;
+    // on an error the plan keeps its schedule and profiling state
+    struct Restore {
+      wfp_plan* P;
+      bool prof;
+      int cus;
+      hipEvent_t* ev[2];
+      bool done = false;
+      ~Restore() {
+        for (hipEvent_t* e : ev)
+          if (*e) (void)hipEventDestroy(*e);
+        if (!done) {
+          P->profiling = prof;
+          try {
+            set_overlap(P, cus);
+          } catch (...) {
+          }
+        }
+      }
+    } restore{P, prof, before, {&a, &c}};
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&c));
-    const bool prof = P->profiling;
     P->profiling = false;
     float best = 1e30f;
     int pick = -1;
@@ -1933,10 +1953,9 @@ wfp_status wfp_plan_autotune(wfp_plan* P, int32_t trial_levels, int32_t* overlap
       }
       zero_state(P);
     }
-    HIPCHK(hipEventDestroy(a));
-    HIPCHK(hipEventDestroy(c));
     P->profiling = prof;
     set_overlap(P, pick);
+    restore.done = true;
     zero_state(P);
     HIPCHK(hipStreamSynchronize(s));
     if (overlap_cus) *overlap_cus = P->overlap_cus;
