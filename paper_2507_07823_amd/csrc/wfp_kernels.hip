@@ -1222,6 +1222,65 @@ k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_
   if (lane == 0) out[r] = acc + interp_pre(r, i0s, iw, grid2, nf, width);
 }
 
+// Element k of the packed input of the u (or v) grid transform from the modes
+// a: z_k = conj of (y_k + conj y_{K-k}) + i e^{+i pi k/K} (y_k - conj y_{K-k}),
+// y_k = (-1)^k conj(a_k); tw[k] = e^{-i pi k/K}.
+__device__ __forceinline__ double2 rbc_grid_in(int64_t k, int64_t K, int n1, int n2, const double2* __restrict__ a,
+                                               const double2* __restrict__ tw) {
+  const double sk = (k & 1) ? -1.0 : 1.0;
+  const double2 yk = cscale(cconj(a[mode_pos(k, n1, n2)]), sk);
+  double2 ym = make_double2(0.0, 0.0);
+  if (k > 0) {
+    const int64_t km = K - k;
+    const double sm = (km & 1) ? -1.0 : 1.0;
+    ym = cconj(cscale(cconj(a[mode_pos(km, n1, n2)]), sm));
+  }
+  return cconj(cadd(cadd(yk, ym), cmul_pi(cmul(cconj(tw[k]), csub(yk, ym)))));
+}
+
+// Grid values 2j and 2j+1 of u (is_v = false) or v after the roll-off on
+// |i - K| >= K - 2W, packed as one complex input of the transform back.
+__device__ __forceinline__ double2 rbc_modes_in(int64_t j, int64_t K, int W, double h, double delta_s, bool is_v,
+                                                const double* __restrict__ cheb_phi, const double* __restrict__ cheb_g,
+                                                int ncheb, const double* __restrict__ gu,
+                                                const double* __restrict__ gv) {
+  double val[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int64_t ip = 2 * j + e;       // grid index 0..2K-1
+    const int64_t i = ip - K;           // -K..K-1
+    const int64_t ai = i < 0 ? -i : i;
+    double u = gu[ip];
+    double v = is_v ? gv[ip] : 0.0;
+    if (ai >= K - 2 * W) {
+      const double arg = (double)(K - ai - W) * h;
+      double rho, drho;
+      if (arg <= 0.0) rho = 0.0;
+      else if (arg >= delta_s) rho = 1.0;
+      else rho = cheb(cheb_phi, ncheb, 2.0 * arg / delta_s - 1.0);
+      if (arg >= 0.0 && arg <= delta_s) drho = (2.0 / delta_s) * cheb(cheb_g, ncheb, 2.0 * arg / delta_s - 1.0);
+      else drho = 0.0;
+      if (is_v) v = drho * u + rho * v;
+      else u = rho * u;
+    }
+    val[e] = is_v ? v : u;
+  }
+  return make_double2(val[0], val[1]);
+}
+
+// Mode k (< K) from the transform Z of the rolled-off grid (real transform of
+// length 2K unpacked): alpha_k = (1/2K) (-1)^k conj(X_k).
+__device__ __forceinline__ double2 rbc_modes_out(int64_t k, int64_t K, const double2* __restrict__ Z,
+                                                 const double2* __restrict__ tw) {
+  const double2 zk = Z[k];
+  const double2 zc = cconj(Z[k == 0 ? 0 : K - k]);
+  const double2 E = cscale(cadd(zk, zc), 0.5);
+  const double2 O = cscale(cmul_mi(csub(zk, zc)), 0.5);
+  const double2 X = cadd(E, cmul(tw[k], O));
+  const double sk = (k & 1) ? -1.0 : 1.0;
+  return cscale(cconj(X), sk * (1.0 / (2.0 * (double)K)));
+}
+
 // ---------------------------------------------------------------------------
 // Free-space RBC projection (Section 4.4).  Block 0 handles alpha -> u,
 // block 1 alpha' -> v: values on x_i = -pi + i h, i = 0..2K-1 (h = pi/K), from
@@ -1235,18 +1294,7 @@ k_rbc_to_grid(FftPlan fp, int64_t K, int n1, int n2, const double2* __restrict__
   const double2* __restrict__ a = (blockIdx.x == 0) ? alpha : dalpha;
   double2* __restrict__ out = (blockIdx.x == 0) ? gu : gv;
   const int n = fp.n;  // == K
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const double sk = (k & 1) ? -1.0 : 1.0;
-    const double2 yk = cscale(cconj(a[mode_pos(k, n1, n2)]), sk);
-    const int km = n - k;   // 1..K-1 for k >= 1
-    double2 ym = make_double2(0.0, 0.0);
-    if (k > 0) {
-      const double sm = (km & 1) ? -1.0 : 1.0;
-      ym = cconj(cscale(cconj(a[mode_pos(km, n1, n2)]), sm));
-    }
-    const double2 zk = cadd(cadd(yk, ym), cmul_pi(cmul(cconj(tw[k]), csub(yk, ym))));
-    buf[k] = cconj(zk);
-  }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) buf[k] = rbc_grid_in(k, K, n1, n2, a, tw);
   __syncthreads();
   fft_lds(buf, fp, tw, 2);
   for (int j = threadIdx.x; j < n; j += blockDim.x) out[j] = cconj(buf[j]);
@@ -1265,46 +1313,14 @@ k_rbc_to_modes(FftPlan fp, int64_t K, int n1, int n2, int W, double h, double de
   extern __shared__ double2 buf[];
   const int n = fp.n;       // == K complex, 2K real points
   const bool is_v = blockIdx.x == 1;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    double val[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int ip = 2 * j + e;          // grid index 0..2K-1
-      int i = ip - (int)K;               // -K..K-1
-      const int ai = i < 0 ? -i : i;
-      double u = gu[ip];
-      double v = is_v ? gv[ip] : 0.0;
-      if (ai >= (int)K - 2 * W) {
-        const double arg = (double)((int)K - ai - W) * h;
-        double rho, drho;
-        if (arg <= 0.0) rho = 0.0;
-        else if (arg >= delta_s) rho = 1.0;
-        else rho = cheb(cheb_phi, ncheb, 2.0 * arg / delta_s - 1.0);
-        if (arg >= 0.0 && arg <= delta_s) drho = (2.0 / delta_s) * cheb(cheb_g, ncheb, 2.0 * arg / delta_s - 1.0);
-        else drho = 0.0;
-        if (is_v) v = drho * u + rho * v;
-        else u = rho * u;
-      }
-      val[e] = is_v ? v : u;
-    }
-    buf[j] = make_double2(val[0], val[1]);
-  }
+  for (int j = threadIdx.x; j < n; j += blockDim.x)
+    buf[j] = rbc_modes_in(j, K, W, h, delta_s, is_v, cheb_phi, cheb_g, ncheb, gu, gv);
   __syncthreads();
   fft_lds(buf, fp, tw, 2);
   // unpack the real transform of length 2K and return to modes
-  const double inv = 1.0 / (2.0 * (double)K);
   double2* __restrict__ out = is_v ? dalpha : alpha;
   for (int k = threadIdx.x; k <= n; k += blockDim.x) {
-    double2 a = make_double2(0.0, 0.0);
-    if (k < n) {
-      const double2 zk = buf[k];
-      const double2 zc = cconj(buf[k == 0 ? 0 : n - k]);
-      const double2 E = cscale(cadd(zk, zc), 0.5);
-      const double2 O = cscale(cmul_mi(csub(zk, zc)), 0.5);
-      const double2 X = cadd(E, cmul(tw[k], O));
-      const double sk = (k & 1) ? -1.0 : 1.0;
-      a = cscale(cconj(X), sk * inv);
-    }
+    const double2 a = k < n ? rbc_modes_out(k, K, buf, tw) : make_double2(0.0, 0.0);
     const int64_t pos = mode_pos(k, n1, n2);
     out[pos] = a;
     if (!is_v) y[k] = cscale(cconj(a), dk2[pos]);
@@ -1329,18 +1345,7 @@ k_rbc_grid_pack(int64_t K, int n1, int n2, const double2* __restrict__ alpha, co
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 2 * K) return;
   const int sidx = idx >= K ? 1 : 0;
-  const int64_t k = idx - sidx * K;
-  const double2* __restrict__ a = sidx ? dalpha : alpha;
-  const double sk = (k & 1) ? -1.0 : 1.0;
-  const double2 yk = cscale(cconj(a[mode_pos(k, n1, n2)]), sk);
-  double2 ym = make_double2(0.0, 0.0);
-  if (k > 0) {
-    const int64_t km = K - k;
-    const double sm = (km & 1) ? -1.0 : 1.0;
-    ym = cconj(cscale(cconj(a[mode_pos(km, n1, n2)]), sm));
-  }
-  const double2 zk = cadd(cadd(yk, ym), cmul_pi(cmul(cconj(tw[k]), csub(yk, ym))));
-  z[idx] = cconj(zk);
+  z[idx] = rbc_grid_in(idx - sidx * K, K, n1, n2, sidx ? dalpha : alpha, tw);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1379,29 +1384,7 @@ k_rbc_modes_pack(int64_t K, int W, double h, double delta_s, const double* __res
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 2 * K) return;
   const bool is_v = idx >= K;
-  const int64_t j = idx - (is_v ? K : 0);
-  double val[2];
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int64_t ip = 2 * j + e;       // grid index 0..2K-1
-    const int64_t i = ip - K;           // -K..K-1
-    const int64_t ai = i < 0 ? -i : i;
-    double u = gu[ip];
-    double v = is_v ? gv[ip] : 0.0;
-    if (ai >= K - 2 * W) {
-      const double arg = (double)(K - ai - W) * h;
-      double rho, drho;
-      if (arg <= 0.0) rho = 0.0;
-      else if (arg >= delta_s) rho = 1.0;
-      else rho = cheb(cheb_phi, ncheb, 2.0 * arg / delta_s - 1.0);
-      if (arg >= 0.0 && arg <= delta_s) drho = (2.0 / delta_s) * cheb(cheb_g, ncheb, 2.0 * arg / delta_s - 1.0);
-      else drho = 0.0;
-      if (is_v) v = drho * u + rho * v;
-      else u = rho * u;
-    }
-    val[e] = is_v ? v : u;
-  }
-  z[idx] = make_double2(val[0], val[1]);
+  z[idx] = rbc_modes_in(idx - (is_v ? K : 0), K, W, h, delta_s, is_v, cheb_phi, cheb_g, ncheb, gu, gv);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1412,18 +1395,7 @@ k_rbc_modes_unpack(int64_t K, int n1, int n2, const double2* __restrict__ X, con
   if (idx >= 2 * (K + 1)) return;
   const bool is_v = idx > K;
   const int64_t k = idx - (is_v ? K + 1 : 0);
-  const double2* __restrict__ Z = X + (is_v ? K : 0);
-  const double inv = 1.0 / (2.0 * (double)K);
-  double2 a = make_double2(0.0, 0.0);
-  if (k < K) {
-    const double2 zk = Z[k];
-    const double2 zc = cconj(Z[k == 0 ? 0 : K - k]);
-    const double2 E = cscale(cadd(zk, zc), 0.5);
-    const double2 O = cscale(cmul_mi(csub(zk, zc)), 0.5);
-    const double2 Xk = cadd(E, cmul(tw[k], O));
-    const double sk = (k & 1) ? -1.0 : 1.0;
-    a = cscale(cconj(Xk), sk * inv);
-  }
+  const double2 a = k < K ? rbc_modes_out(k, K, X + (is_v ? K : 0), tw) : make_double2(0.0, 0.0);
   const int64_t pos = mode_pos(k, n1, n2);
   (is_v ? dalpha : alpha)[pos] = a;
   if (!is_v) y[k] = cscale(cconj(a), dk2[pos]);
