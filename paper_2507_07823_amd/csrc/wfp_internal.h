@@ -247,6 +247,8 @@ struct wfp_plan {
   std::vector<hipEvent_t> free_events;
 
   ~wfp_plan() {
+    // work queued on the plan's stream may still read its buffers
+    (void)hipStreamSynchronize(stream);
     // sa, sb and sd are shared by every plan on the device (never destroyed)
     if (sa) (void)hipStreamSynchronize(sa);
     if (sb) (void)hipStreamSynchronize(sb);

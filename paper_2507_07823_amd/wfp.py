@@ -321,6 +321,35 @@ class Plan:
             pass
 
 
+def solve(x, beta, incident, dt, n_steps, boundary=0, x_recv=None, save_every=1, **params):
+    """One call: plan, march n_steps levels, release the plan.
+
+    x, beta   spring positions and stiffnesses (M; numpy arrays or tensors on
+              any device; the plan copies them)
+    incident  packets (n, 5): rows (amp, centre, width, omega, phase) of
+              f(s) = sum amp exp(-(s - centre)^2 / (2 width^2)) cos(omega (s - centre) + phase)
+    boundary  0 periodic box [-pi, pi), 1 free space
+    x_recv    receiver positions (R) or None
+    params    plan parameters (p, W, K, local_mode, ...; see make_params)
+    Returns (u_recv [n_steps][R] or None, sigma [ceil(n_steps/save_every)][M]),
+    float64 CUDA tensors in the caller's spring order."""
+    def host(a):
+        if a is None:
+            return np.zeros(0)
+        if hasattr(a, "detach"):
+            a = a.detach().cpu().numpy()
+        return np.ascontiguousarray(a, dtype=np.float64)
+
+    prob = dict(x=host(x), beta=host(beta), packets=np.atleast_2d(host(incident)), boundary=int(boundary),
+                x_recv=host(x_recv))
+    plan = Plan(prob, dt, **params)
+    try:
+        sig, u = plan.march(n_steps, save_every)
+    finally:
+        plan.close()
+    return u, sig
+
+
 class Batch:
     """Independent periodic problems marched in lockstep (wfp_batch_*).
 

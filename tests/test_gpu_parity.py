@@ -385,3 +385,18 @@ def test_check_finite(wfp):
     assert ei.value.status == wfp.WFP_ENONFINITE
     assert plan.level == st["L"] + 1
     plan.close()
+
+
+def test_solve_wrapper_matches_plan(wfp):
+    """wfp.solve (plan, march, release in one call; tensors in or out)
+    returns what a plan marched by hand returns."""
+    import torch
+    p = workloads.periodic_single_pulse(21, 24, 0.01, 300, n_recv=5)
+    plan = wfp.Plan(p, p["dt"])
+    s1, u1 = plan.march(300, 3)
+    torch.cuda.synchronize()
+    plan.close()
+    u2, s2 = wfp.solve(torch.from_numpy(p["x"]), p["beta"], p["packets"], p["dt"], 300, boundary=0,
+                       x_recv=p["x_recv"], save_every=3)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2) and torch.equal(u1, u2)
