@@ -123,6 +123,7 @@ struct wfp_plan {
   FftPlan fft_nf{}, fft_rbc{}, fft_n1{}, fft_n2{};
   // threads of the row passes (256, or 1024 for long rows)
   int hist_threads = 256;
+  double* gsp = nullptr;    // spread grid of the 1024-thread row passes (nf)
   // FIR tap groups of the column pass and its LDS bytes
   int fir_groups = 8;
   size_t lds_b = 0;

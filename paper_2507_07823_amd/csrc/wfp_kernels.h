@@ -166,10 +166,12 @@ __global__ void k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t
 __global__ void k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
                          double2* __restrict__ grid2);
 // the same row passes with 1024 threads, for rows of more than 1024 butterflies per stage at 256
-__global__ void k_hist_a_wide(FftPlan f2, int n1, const double* __restrict__ sig, int M,
-                              const int* __restrict__ cstart, const int* __restrict__ ccount,
-                              const int64_t* __restrict__ woff, const double* __restrict__ sw,
-                              const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex);
+__global__ void k_hist_a_wide(FftPlan f2, int n1, const double* __restrict__ grid, const double2* __restrict__ tw,
+                              double2* __restrict__ T1);
+// type-1 spreading, one thread per fine-grid cell (feeds k_hist_a_wide)
+__global__ void k_spread_grid(int nf, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
+                              const int* __restrict__ ccount, const int64_t* __restrict__ woff,
+                              const double* __restrict__ sw, ExtraSources ex, double* __restrict__ grid);
 __global__ void k_hist_c_wide(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
                               double2* __restrict__ grid2);
 

@@ -1430,13 +1430,18 @@ __device__ __forceinline__ double spread_cell(int cell, const double* __restrict
 
 __device__ __forceinline__ void k_hist_a_body(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
          const int* __restrict__ ccount, const int64_t* __restrict__ woff, const double* __restrict__ sw,
-         const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex, int bid) {
+         const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex, int bid,
+         const double* __restrict__ grid = nullptr) {
   extern __shared__ double2 buf[];
   const int n2 = f2.n, j1 = bid;
   const int n = n1 * n2;
   double* bd = (double*)buf;
   for (int c = threadIdx.x; c < 2 * n2; c += blockDim.x) {
     const int cell = 2 * (j1 + n1 * (c >> 1)) + (c & 1);
+    if (grid) {
+      bd[c] = grid[cell];   // spread beforehand by k_spread_grid
+      continue;
+    }
     double v = spread_cell(cell, sig, M, cstart, ccount, woff, sw);
     if (ex.val) v += spread_cell(cell, ex.val, ex.n, ex.cstart, ex.ccount, ex.woff, ex.w);
     bd[c] = v;
@@ -1457,11 +1462,30 @@ k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* _
 }
 
 // Rows longer than 1024 butterflies per stage for 256 threads take 1024 threads.
+// Long rows: the cells are spread beforehand into `grid` by k_spread_grid (one
+// thread per cell, coalesced), and the rows are read from it; blocks of
+// neighbouring rows share the grid's cache lines, so they run on one XCD.  The
+// grid is padded to a multiple of 8 blocks (the remap's bijection); blocks
+// past the last row return as a whole, before any barrier.
 __global__ void __launch_bounds__(1024)
-k_hist_a_wide(FftPlan f2, int n1, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
+k_hist_a_wide(FftPlan f2, int n1, const double* __restrict__ grid, const double2* __restrict__ tw,
+              double2* __restrict__ T1) {
+  const int j1 = xcd_block(blockIdx.x, gridDim.x);
+  if (j1 >= n1) return;
+  const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+  k_hist_a_body(f2, n1, nullptr, 0, nullptr, nullptr, nullptr, nullptr, tw, T1, none, j1, grid);
+}
+
+// Type-1 spreading onto the fine grid, one thread per cell.
+__global__ void __launch_bounds__(256)
+k_spread_grid(int nf, const double* __restrict__ sig, int M, const int* __restrict__ cstart,
               const int* __restrict__ ccount, const int64_t* __restrict__ woff, const double* __restrict__ sw,
-              const double2* __restrict__ tw, double2* __restrict__ T1, ExtraSources ex) {
-  k_hist_a_body(f2, n1, sig, M, cstart, ccount, woff, sw, tw, T1, ex, blockIdx.x);
+              ExtraSources ex, double* __restrict__ grid) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= nf) return;
+  double v = spread_cell(cell, sig, M, cstart, ccount, woff, sw);
+  if (ex.val) v += spread_cell(cell, ex.val, ex.n, ex.cstart, ex.ccount, ex.woff, ex.w);
+  grid[cell] = v;
 }
 
 constexpr int kFirGroups = 8;

@@ -379,6 +379,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   P->V = P->alloc<double2>(P->nfh);
   P->ybuf = P->alloc<double2>(P->K + 1);
   P->grid2 = P->alloc<double>(nf);
+  if (P->hist_threads == 1024) P->gsp = P->alloc<double>(nf);
   P->cstart = P->alloc<int>(nf);
   P->ccount = P->alloc<int>(nf);
   P->cheb_phi = P->alloc<double>(ws.n);
@@ -1085,9 +1086,12 @@ void launch_hist_a(wfp_plan* P, hipStream_t s, const double* sig, ExtraSources e
   if (P->hist_threads == 256)
     hipLaunchKernelGGL(k_hist_a, dim3(P->n1), dim3(256), lds, s, P->fft_n2, P->n1, sig, (int)P->M, P->cstart,
                        P->ccount, P->swoff, P->sw, P->tw, P->T1, ex);
-  else
-    hipLaunchKernelGGL(k_hist_a_wide, dim3(P->n1), dim3(1024), lds, s, P->fft_n2, P->n1, sig, (int)P->M,
-                       P->cstart, P->ccount, P->swoff, P->sw, P->tw, P->T1, ex);
+  else {
+    hipLaunchKernelGGL(k_spread_grid, dim3(nblk(P->nf, 256)), dim3(256), 0, s, P->nf, sig, (int)P->M, P->cstart,
+                       P->ccount, P->swoff, P->sw, ex, P->gsp);
+    hipLaunchKernelGGL(k_hist_a_wide, dim3(8 * nblk(P->n1, 8)), dim3(1024), lds, s, P->fft_n2, P->n1, P->gsp, P->tw,
+                       P->T1);
+  }
 }
 
 void launch_hist_c(wfp_plan* P, hipStream_t s, double2* grid) {
