@@ -162,7 +162,7 @@ __global__ void k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t
                          const double* __restrict__ pk, const double* __restrict__ qk,
                          const double* __restrict__ rot, double2* __restrict__ ring,
                          double2* __restrict__ alpha, double2* __restrict__ dalpha, double2* __restrict__ y,
-                         double2* __restrict__ V, int G);
+                         double2* __restrict__ V, int G, int vcol);
 __global__ void k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
                          double2* __restrict__ grid2);
 // the same row passes with 1024 threads, for rows of more than 1024 butterflies per stage at 256

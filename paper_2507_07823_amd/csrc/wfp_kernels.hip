@@ -1504,7 +1504,7 @@ __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int6
          const double2* __restrict__ tw, const double2* __restrict__ tw1, const double* __restrict__ dk1, const double* __restrict__ dk2,
          const double* __restrict__ pk, const double* __restrict__ qk, const double* __restrict__ rot,
          double2* __restrict__ ring, double2* __restrict__ alpha, double2* __restrict__ dalpha,
-         double2* __restrict__ y, double2* __restrict__ V, int G, int bid) {
+         double2* __restrict__ y, double2* __restrict__ V, int G, int bid, int vcol = 0) {
   extern __shared__ double2 smb[];
   const int n1 = f1.n;
   const int n = n1 * n2;
@@ -1615,7 +1615,9 @@ __device__ __forceinline__ void k_hist_b_body(int mode, FftPlan f1, int n2, int6
     const int c = e / n1, j1 = e - c * n1;
     const int k2 = colk2(c);
     const int qq = (j1 * k2) % n;
-    V[(int64_t)j1 * n2 + k2] = cmul(cconj(buf[e]), cconj(tw[2 * qq]));
+    const double2 v = cmul(cconj(buf[e]), cconj(tw[2 * qq]));
+    if (vcol) V[(int64_t)k2 * n1 + j1] = v;   // column-major: this column contiguous
+    else V[(int64_t)j1 * n2 + k2] = v;
   }
 }
 
@@ -1626,16 +1628,17 @@ k_hist_b(int mode, FftPlan f1, int n2, int64_t K, int W, int64_t L, int64_t npos
          const double2* __restrict__ tw, const double2* __restrict__ tw1, const double* __restrict__ dk1,
          const double* __restrict__ dk2, const double* __restrict__ pk, const double* __restrict__ qk,
          const double* __restrict__ rot, double2* __restrict__ ring, double2* __restrict__ alpha,
-         double2* __restrict__ dalpha, double2* __restrict__ y, double2* __restrict__ V, int G) {
+         double2* __restrict__ dalpha, double2* __restrict__ y, double2* __restrict__ V, int G, int vcol) {
   k_hist_b_body(mode, f1, n2, K, W, L, npos, T1, tw, tw1, dk1, dk2, pk, qk, rot, ring, alpha, dalpha, y, V, G,
-                blockIdx.x);
+                blockIdx.x, vcol);
 }
 
 __device__ __forceinline__ void k_hist_c_body(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
-         double2* __restrict__ grid2, int bid) {
+         double2* __restrict__ grid2, int bid, int vcol = 0) {
   extern __shared__ double2 buf[];
   const int n2 = f2.n, j1 = bid;
-  for (int k2 = threadIdx.x; k2 < n2; k2 += blockDim.x) buf[k2] = cconj(V[(int64_t)j1 * n2 + k2]);
+  for (int k2 = threadIdx.x; k2 < n2; k2 += blockDim.x)
+    buf[k2] = cconj(vcol ? V[(int64_t)k2 * n1 + j1] : V[(int64_t)j1 * n2 + k2]);
   __syncthreads();
   fft_batch(buf, 1, f2, tw, 2 * n1);
   for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) grid2[j1 + n1 * j2] = cconj(buf[j2]);
@@ -1650,7 +1653,12 @@ k_hist_c(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __res
 __global__ void __launch_bounds__(1024)
 k_hist_c_wide(FftPlan f2, int n1, const double2* __restrict__ V, const double2* __restrict__ tw,
               double2* __restrict__ grid2) {
-  k_hist_c_body(f2, n1, V, tw, grid2, blockIdx.x);
+  // V column-major (written a column at a time by the column pass); neighbouring
+  // rows on one XCD share its cache lines; the grid is padded to a multiple of
+  // 8 blocks and blocks past the last row return as a whole
+  const int j1 = xcd_block(blockIdx.x, gridDim.x);
+  if (j1 >= n1) return;
+  k_hist_c_body(f2, n1, V, tw, grid2, j1, 1);
 }
 
 // ---------------------------------------------------------------------------

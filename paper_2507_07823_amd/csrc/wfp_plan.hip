@@ -1099,7 +1099,8 @@ void launch_hist_c(wfp_plan* P, hipStream_t s, double2* grid) {
   if (P->hist_threads == 256)
     hipLaunchKernelGGL(k_hist_c, dim3(P->n1), dim3(256), lds, s, P->fft_n2, P->n1, P->V, P->tw, grid);
   else
-    hipLaunchKernelGGL(k_hist_c_wide, dim3(P->n1), dim3(1024), lds, s, P->fft_n2, P->n1, P->V, P->tw, grid);
+    hipLaunchKernelGGL(k_hist_c_wide, dim3(8 * nblk(P->n1, 8)), dim3(1024), lds, s, P->fft_n2, P->n1, P->V, P->tw,
+                       grid);
 }
 
 // Stored weights: the lags >= 2 part of level L's local sum into locb[L & 1]
@@ -1203,7 +1204,7 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
     StageTimer st(P, WFP_STAGE_MODES, sc);
     hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, sc, rbc ? 1 : 0, P->fft_n1, P->n2, P->K, P->W, L,
                        P->npos, P->T1, P->tw, P->tw1, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha,
-                       S.dalpha, P->ybuf, P->V, P->fir_groups);
+                       S.dalpha, P->ybuf, P->V, P->fir_groups, P->hist_threads == 1024 ? 1 : 0);
   }
   if (rbc) {
     StageTimer st(P, WFP_STAGE_RBC, sc);
@@ -1234,7 +1235,7 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
     }
     hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, sc, 2, P->fft_n1, P->n2, P->K, P->W, L, P->npos,
                        P->T1, P->tw, P->tw1, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha, S.dalpha,
-                       P->ybuf, P->V, P->fir_groups);
+                       P->ybuf, P->V, P->fir_groups, P->hist_threads == 1024 ? 1 : 0);
   }
   {
     StageTimer st(P, WFP_STAGE_FFT_INV, sc);
@@ -1523,7 +1524,7 @@ void deriv_field(wfp_plan* P, const StateRef& S) {
                      P->yd);
   hipLaunchKernelGGL(k_hist_b, dim3(nb_b), dim3(512), lds_b, s, 2, P->fft_n1, P->n2, P->K, P->W, (int64_t)0,
                      P->npos, P->T1, P->tw, P->tw1, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha,
-                     S.dalpha, P->yd, P->V, P->fir_groups);
+                     S.dalpha, P->yd, P->V, P->fir_groups, P->hist_threads == 1024 ? 1 : 0);
   launch_hist_c(P, s, (double2*)P->gridd);
 }
 
