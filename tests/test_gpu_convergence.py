@@ -116,4 +116,8 @@ def test_driven_equals_packets(wfp):
     r = rho(s2.cpu().numpy(), s1.cpu().numpy())
     say(f"case driven vs packets rho {r:.2e}")
     assert r < 1e-12
+    # no driving data for a non-empty run: rejected, nothing marched
+    lvl = plan.level
+    assert plan._lib.wfp_run_driven(plan._h, 5, None, None, 1, None) == wfp.WFP_EINVAL
+    assert plan.level == lvl
     plan.close()

@@ -90,3 +90,13 @@ def test_batch_rejects_receivers_and_free_space_before_any_device_work(lib):
     assert lib.wfp_batch_create(1, probs, pars, None, ctypes.byref(h)) == w.WFP_EDOMAIN
     assert lib.wfp_batch_create(0, probs, pars, None, ctypes.byref(h)) == w.WFP_EINVAL
     assert h.value is None
+
+
+def test_null_plan_arguments_rejected(lib):
+    """The driven march and the schedule autotune check their arguments
+    before any device call."""
+    NULL = ctypes.c_void_p(0)
+    g = (ctypes.c_double * 4)()
+    assert lib.wfp_run_driven(NULL, 1, ctypes.cast(g, ctypes.c_void_p), NULL, 1, NULL) == wfp.WFP_EINVAL
+    assert lib.wfp_plan_autotune(NULL, 3, None) == wfp.WFP_EINVAL
+    assert b"plan" in lib.wfp_last_error()
