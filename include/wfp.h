@@ -242,8 +242,8 @@ wfp_status wfp_reset(wfp_plan* plan);
  * WFP_ESTATE (plan not at level 0). */
 wfp_status wfp_plan_autotune(wfp_plan* plan, int32_t trial_levels, int32_t* overlap_cus);
 
-/* Batched form (not in the paper): n independent periodic problems without
- * receivers, each with its own x, beta, incident field and dt, marched in
+/* Batched form (not in the paper): n independent periodic problems, each
+ * with its own x, beta, incident field, receivers and dt, marched in
  * lockstep.  Each stage of a level is one launch over an (instance, block) work
  * list and the whole level is one HIP graph replayed per level; every instance
  * computes what its own plan would, to rounding (the same kernel bodies; a plan
@@ -254,13 +254,18 @@ wfp_status wfp_plan_autotune(wfp_plan* plan, int32_t trial_levels, int32_t* over
  *                     on the fly with p = 8 only; local_mode 0 here: stored for the
  *                     instances with the fewest neighbour pairs while their weights
  *                     fit in 45 % of the free device memory).  Synchronous.
- *                     Errors: WFP_EINVAL (R != 0), WFP_EDOMAIN (free space, or
- *                     an instance whose stages exceed the LDS), as for plans.
+ *                     Errors: WFP_EDOMAIN (free space, or an instance whose
+ *                     stages exceed the LDS), as for plans.
  *   wfp_batch_run     march n_steps levels of every instance; sigma_final is a
  *                     HOST array of n DEVICE pointers (entries may be NULL, the
  *                     array may be NULL): instance i's densities of its last
- *                     level, [M_i] in caller order.  Ordered after prior work on
- *                     `stream`; later work on `stream` waits for it.
+ *                     level, [M_i] in caller order.  u_recv_out likewise: the
+ *                     field at instance i's R_i receivers at every level of the
+ *                     call, [n_steps][R_i] (eqs. (localSol2), (historySol1)).
+ *                     Ordered after prior work on `stream`; later work on
+ *                     `stream` waits for it.  A call that passes receiver
+ *                     outputs (or follows one that did) first waits for the
+ *                     batch's earlier work.
  *   wfp_batch_reset   all instances back to level 0.
  *   wfp_batch_autotune  from level 0: times trial_levels levels for each launch
  *                     shape of the local sum (4 or 8 rows per block, with or
@@ -273,7 +278,8 @@ wfp_status wfp_plan_autotune(wfp_plan* plan, int32_t trial_levels, int32_t* over
 typedef struct wfp_batch wfp_batch;
 wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_params* pars, void* stream,
                             wfp_batch** out);
-wfp_status wfp_batch_run(wfp_batch* batch, int64_t n_steps, double* const* sigma_final);
+wfp_status wfp_batch_run(wfp_batch* batch, int64_t n_steps, double* const* u_recv_out,
+                         double* const* sigma_final);
 wfp_status wfp_batch_reset(wfp_batch* batch);
 wfp_status wfp_batch_autotune(wfp_batch* batch, int32_t trial_levels, int32_t* rows_per_block,
                               int32_t* xcd_remap);

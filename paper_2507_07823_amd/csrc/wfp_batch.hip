@@ -18,9 +18,14 @@ struct wfp_batch {
   // work lists (device) and their lengths
   int2 *wl_inc = nullptr, *wl_loc4 = nullptr, *wl_loc8 = nullptr, *wl_a = nullptr, *wl_b = nullptr,
        *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr, *wl_otf = nullptr,
-       *wl_swt = nullptr, *wl_sww = nullptr, *wl_g8 = nullptr, *wl_g4 = nullptr;
+       *wl_swt = nullptr, *wl_sww = nullptr, *wl_g8 = nullptr, *wl_g4 = nullptr, *wl_rcv = nullptr;
   int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0, n_otf = 0,
-      n_swt = 0, n_sww = 0, n_g8 = 0, n_g4 = 0;
+      n_swt = 0, n_sww = 0, n_g8 = 0, n_g4 = 0, n_rcv = 0;
+  // receiver outputs of the current run: per instance a device pointer (or
+  // NULL) and the level the run started at, read by the captured level
+  double** uout_d = nullptr;
+  int64_t* lvl0_d = nullptr;
+  bool uout_set = false;
   size_t lds_a = 0, lds_b = 0, lds_c = 0, lds_til = 0, lds_otf = 0;
   // Jacobi sweeps of the global-solve instances, thread per row (swt) or
   // wavefront per row (sww); both lists are ordered by decreasing sweep count,
@@ -140,6 +145,13 @@ InstDesc describe(const wfp_plan* P) {
   d.otf_w = P->otf_w;
   d.phitab = P->phitab;
   d.half_beta = P->half_beta;
+  d.R = (int)P->R;
+  d.rnb_start = P->rnb_start;
+  d.rnb_count = P->rnb_count;
+  d.rqoff = P->rqoff;
+  d.Qr = P->Qr;
+  d.ri0s = P->ri0s;
+  d.riw = P->riw;
   return d;
 }
 
@@ -183,7 +195,7 @@ void build_batch(wfp_batch* B) {
   std::vector<InstDesc> desc(n);
   // otf, loc4, loc8, g8, g4: (instance, blocks); g8 / g4: instances whose
   // lag blocks are short (the plan's lanes per lag), 4 rows per block
-  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf, g8, g4;
+  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf, g8, g4, rcv;
   for (int i = 0; i < n; ++i) {
     const wfp_plan* P = B->plans[i];
     desc[i] = describe(P);
@@ -207,6 +219,7 @@ void build_batch(wfp_batch* B) {
     for (int b = 0; b < P->n1; ++b) wc.push_back(make_int2(i, b));
     for (int b = 0; b < P->n_direct_tiles; ++b) dir.push_back(make_int2(i, b));
     for (int b = 0; b < P->ntile; ++b) til.push_back(make_int2(i, b));
+    for (int b = 0; b < (int)nblk(P->R, 4); ++b) rcv.push_back(make_int2(i, b));   // 4 receivers per block
     if (P->solve_global) {
       for (int b = 0; b < (int)nblk(M, 256); ++b) rows.push_back(make_int2(i, b));
       B->max_sweeps = std::max(B->max_sweeps, P->iters);
@@ -248,6 +261,11 @@ void build_batch(wfp_batch* B) {
   B->wl_otf = upload_work(B, xcd_balanced(otf), 8, B->n_otf);
   B->wl_g8 = upload_work(B, xcd_balanced(g8), 8, B->n_g8);
   B->wl_g4 = upload_work(B, xcd_balanced(g4), 8, B->n_g4);
+  B->wl_rcv = upload_work(B, rcv, 1, B->n_rcv);
+  B->uout_d = B->alloc<double*>(n);
+  B->lvl0_d = B->alloc<int64_t>(1);
+  HIPCHK(hipMemsetAsync(B->uout_d, 0, n * sizeof(double*), B->bs));
+  HIPCHK(hipMemsetAsync(B->lvl0_d, 0, sizeof(int64_t), B->bs));
   B->wl_swt = upload_work(B, swt, 1, B->n_swt);
   B->wl_sww = upload_work(B, sww, 1, B->n_sww);
   if (B->n_otf)
@@ -324,7 +342,26 @@ void enqueue_level(wfp_batch* B) {
       }
     }
   }
+  if (B->n_rcv) {
+    bl.work = B->wl_rcv;
+    hipLaunchKernelGGL(kb_receivers, dim3(B->n_rcv), dim3(256), 0, s, bl, B->uout_d, B->lvl0_d);
+  }
   hipLaunchKernelGGL(kb_advance, dim3(1), dim3(64), 0, s, B->level_d);
+}
+
+// Receiver outputs for the next run (NULL: none).  The captured level reads
+// the pointers and the start level from device memory, so they are written
+// here after the batch's earlier work has finished with them.
+void set_outputs(wfp_batch* B, double* const* u_recv_out) {
+  if (!B->n_rcv || (!u_recv_out && !B->uout_set)) return;
+  HIPCHK(hipStreamSynchronize(B->bs));
+  const size_t n = B->plans.size();
+  std::vector<double*> h(n, nullptr);
+  if (u_recv_out)
+    for (size_t i = 0; i < n; ++i) h[i] = u_recv_out[i];
+  HIPCHK(hipMemcpy(B->uout_d, h.data(), n * sizeof(double*), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(B->lvl0_d, &B->level, sizeof(int64_t), hipMemcpyHostToDevice));
+  B->uout_set = u_recv_out != nullptr;
 }
 
 void drop_graph(wfp_batch* B) {
@@ -436,10 +473,6 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
       g_last_error = "the batched form covers periodic problems";
       return WFP_EDOMAIN;
     }
-    if (probs[i].R != 0) {
-      g_last_error = "the batched form has no receivers (R must be 0)";
-      return WFP_EINVAL;
-    }
   }
   wfp_batch* B = new wfp_batch();
   wfp_status st = guard([&] {
@@ -479,13 +512,14 @@ void wfp_batch_destroy(wfp_batch* B) {
   delete B;
 }
 
-wfp_status wfp_batch_run(wfp_batch* B, int64_t n_steps, double* const* sigma_final) {
+wfp_status wfp_batch_run(wfp_batch* B, int64_t n_steps, double* const* u_recv_out, double* const* sigma_final) {
   if (!B || n_steps < 0) {
     g_last_error = "bad batch or step count";
     return WFP_EINVAL;
   }
   return guard([&] {
     HIPCHK(hipSetDevice(B->device));
+    set_outputs(B, u_recv_out);
     HIPCHK(hipEventRecord(B->ev_in, B->user_stream));
     HIPCHK(hipStreamWaitEvent(B->bs, B->ev_in, 0));
     run_batch(B, n_steps);
@@ -525,6 +559,7 @@ wfp_status wfp_batch_autotune(wfp_batch* B, int32_t trial_levels, int32_t* rows_
   return guard([&] {
     HIPCHK(hipSetDevice(B->device));
     if (B->level != 0) fail(WFP_ESTATE, "autotune runs from level 0 (call wfp_batch_reset first)");
+    set_outputs(B, nullptr);   // trial levels write no receiver rows
     HIPCHK(hipStreamSynchronize(B->user_stream));
     hipEvent_t a, c;
     HIPCHK(hipEventCreate(&a));

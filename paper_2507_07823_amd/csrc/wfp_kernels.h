@@ -270,6 +270,11 @@ struct InstDesc {
   double delta;
   const int* nb_count;
   const double *otf_z, *otf_w, *phitab, *half_beta;
+  // receivers
+  int R;
+  const int *rnb_start, *rnb_count, *ri0s;
+  const int64_t* rqoff;
+  const double *Qr, *riw;
 };
 
 // Work item (instance, block within the instance); instance < 0 pads the list.
@@ -280,6 +285,7 @@ struct BatchLaunch {
 };
 
 __global__ void kb_incident(BatchLaunch b);
+__global__ void kb_receivers(BatchLaunch b, double* const* __restrict__ uout, const int64_t* __restrict__ level0);
 __global__ void kb_local(BatchLaunch b, int xcd);
 __global__ void kb_local_g8(BatchLaunch b);
 __global__ void kb_local_g4(BatchLaunch b);

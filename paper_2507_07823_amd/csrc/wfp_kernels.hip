@@ -1197,14 +1197,14 @@ k_solve_direct(int M, const int* __restrict__ dt_g0, const int* __restrict__ dt_
 
 // Field at the receivers, one wavefront per receiver:
 //   u(x_r, t_L) = sum_{m>=0} sum_l (1/2) Q_m(d_rl) sigma_l^{L-m} + u_H(x_r)
-__global__ void __launch_bounds__(256)
-k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
-            const int* __restrict__ nb_count, const int64_t* __restrict__ qoff, const double* __restrict__ Q,
-            const double* __restrict__ hist, const int* __restrict__ i0s, const double* __restrict__ iw,
-            const double* __restrict__ grid2, int nf, int width, double* __restrict__ out) {
+__device__ __forceinline__ void k_receivers_body(int R, int M, int NQ, int NH, int64_t L,
+            const int* __restrict__ nb_start, const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
+            const double* __restrict__ Q, const double* __restrict__ hist, const int* __restrict__ i0s,
+            const double* __restrict__ iw, const double* __restrict__ grid2, int nf, int width,
+            double* __restrict__ out, int bid) {
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (r >= R) return;
+  const int r = bid * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= R) return;   // no block-level barrier in this body
   const int n = nb_count[r];
   const int st = nb_start[r];
   const int64_t base = qoff[r];
@@ -1220,6 +1220,14 @@ k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_
   }
   acc = wave_sum(acc);
   if (lane == 0) out[r] = acc + interp_pre(r, i0s, iw, grid2, nf, width);
+}
+
+__global__ void __launch_bounds__(256)
+k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
+            const int* __restrict__ nb_count, const int64_t* __restrict__ qoff, const double* __restrict__ Q,
+            const double* __restrict__ hist, const int* __restrict__ i0s, const double* __restrict__ iw,
+            const double* __restrict__ grid2, int nf, int width, double* __restrict__ out) {
+  k_receivers_body(R, M, NQ, NH, L, nb_start, nb_count, qoff, Q, hist, i0s, iw, grid2, nf, width, out, blockIdx.x);
 }
 
 // Element k of the packed input of the u (or v) grid transform from the modes
@@ -1898,6 +1906,20 @@ __global__ void __launch_bounds__(256) kb_jacobi_sweep_wave(BatchLaunch b, int i
   const double* xin = (it & 1) ? d.g_xa : d.g_xb;
   double* xout = (it == d.iters - 1) ? slot : ((it & 1) ? d.g_xb : d.g_xa);
   k_jacobi_sweep_wave_body(d.M, d.g_ptr, d.g_col, d.g_val, d.g_dinv, d.g_rhs, xin, xout, nullptr, nullptr, w.y);
+}
+
+// Receivers of every instance at the level being computed: instance i writes
+// row (*level - *level0) of uout[i] ([levels][R_i]; NULL: no output).
+__global__ void __launch_bounds__(256) kb_receivers(BatchLaunch b, double* const* __restrict__ uout,
+                                                    const int64_t* __restrict__ level0) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  double* out = uout[w.x];
+  if (!out) return;
+  const InstDesc& d = b.desc[w.x];
+  const int64_t L = *b.level;
+  k_receivers_body(d.R, d.M, d.NQ, d.NH, L, d.rnb_start, d.rnb_count, d.rqoff, d.Qr, d.hist, d.ri0s, d.riw,
+                   d.grid2, d.nf, d.width, out + (L - *level0) * d.R, w.y);
 }
 
 __global__ void kb_advance(int64_t* level) {

@@ -99,7 +99,7 @@ def load_library():
     lib.wfp_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Problem), ctypes.POINTER(Params), vp,
                                      ctypes.POINTER(vp)]
     lib.wfp_batch_create.restype = ctypes.c_int32
-    lib.wfp_batch_run.argtypes = [vp, ctypes.c_int64, vp]
+    lib.wfp_batch_run.argtypes = [vp, ctypes.c_int64, vp, vp]
     lib.wfp_batch_run.restype = ctypes.c_int32
     lib.wfp_batch_reset.argtypes = [vp]
     lib.wfp_batch_reset.restype = ctypes.c_int32
@@ -353,7 +353,7 @@ def solve(x, beta, incident, dt, n_steps, boundary=0, x_recv=None, save_every=1,
 class Batch:
     """Independent periodic problems marched in lockstep (wfp_batch_*).
 
-    problems: list of dicts as for Plan (no receivers), dts: list of time
+    problems: list of dicts as for Plan (receivers allowed), dts: list of time
     steps, keyword parameters shared by every instance, per_instance: optional
     list of per-instance parameter dicts.
     """
@@ -378,6 +378,7 @@ class Batch:
         _check(lib.wfp_batch_create(n, probs, pars, self._stream, ctypes.byref(h)))
         self._h = h
         self.sizes = [int(np.asarray(p["x"]).size) for p in problems]
+        self.receivers = [int(np.asarray(p.get("x_recv", np.zeros(0))).size) for p in problems]
 
     @property
     def level(self):
@@ -385,16 +386,22 @@ class Batch:
         _check(self._lib.wfp_batch_size(self._h, None, ctypes.byref(lvl)))
         return lvl.value
 
-    def run(self, n_steps, sigma_final=None):
-        """March n_steps levels; sigma_final: list of float64 CUDA tensors [M_i] (or None)."""
-        arr = None
-        if sigma_final is not None:
+    def run(self, n_steps, sigma_final=None, u_recv=None):
+        """March n_steps levels.  sigma_final: list of float64 CUDA tensors
+        [M_i] (or None); u_recv: list of float64 CUDA tensors [n_steps][R_i]
+        (or None) for the receivers' field at every level."""
+        def pointers(ts, need):
+            if ts is None:
+                return None
             arr = (ctypes.c_void_p * self.n)()
-            for i, t in enumerate(sigma_final):
+            for i, t in enumerate(ts):
                 if t is not None:
-                    assert t.is_cuda and t.is_contiguous() and t.element_size() == 8 and t.numel() >= self.sizes[i]
+                    assert t.is_cuda and t.is_contiguous() and t.element_size() == 8 and t.numel() >= need(i)
                     arr[i] = t.data_ptr()
-        _check(self._lib.wfp_batch_run(self._h, int(n_steps), arr))
+            return arr
+        sf = pointers(sigma_final, lambda i: self.sizes[i])
+        ur = pointers(u_recv, lambda i: n_steps * self.receivers[i])
+        _check(self._lib.wfp_batch_run(self._h, int(n_steps), ur, sf))
 
     def reset(self):
         _check(self._lib.wfp_batch_reset(self._h))
