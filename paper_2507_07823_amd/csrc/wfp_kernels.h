@@ -87,7 +87,8 @@ __global__ void k_count_nonzero(int M, int NQ, const int* __restrict__ nb_count,
 __global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
                             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                             const double* __restrict__ Qc, const double* __restrict__ hist,
-                            const double* __restrict__ addin, double* __restrict__ loc);
+                            const double* __restrict__ addin, double* __restrict__ loc,
+                            double* __restrict__ loc2);
 __global__ void k_local_rhs_g8(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
                                const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                                const double* __restrict__ Qc, const double* __restrict__ hist,
@@ -99,7 +100,8 @@ __global__ void k_local_rhs_g4(int M, int NQ, int NH, int64_t L, int m0, int m1,
 __global__ void k_local_lag1(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
                              const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                              const double* __restrict__ Qc, const double* __restrict__ hist,
-                             const double* __restrict__ addin, double* __restrict__ loc);
+                             const double* __restrict__ addin, const double* __restrict__ addin2,
+                             double* __restrict__ loc);
 __global__ void k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta,
                            Packets pk, int pp, int deriv, double* __restrict__ ginc);
 __global__ void k_incident_levels(int M, int64_t L0, double dt, const double* __restrict__ xs,

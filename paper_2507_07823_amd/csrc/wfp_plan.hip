@@ -641,6 +641,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->rowbase = P->alloc<int64_t>(M);
     P->Qc = P->alloc<double>(packed + 2);   // spare elements for paired loads
     P->locb = P->alloc<double>(2 * (size_t)M);
+    P->locb2 = P->alloc<double>(2 * (size_t)M);
     // short lag blocks (few neighbours) take more lags per trip
     const double meanc = (double)packed / ((double)M * (P->NQ - 1));
     P->lgrp = meanc >= 48.0 ? 16 : (meanc >= 20.0 ? 8 : 4);
@@ -1107,23 +1108,34 @@ void launch_hist_c(wfp_plan* P, hipStream_t s, double2* grid) {
 // (reads sigma^{L-2} and older only), and its lag-1 part added to it.
 // The stored-weight local sum of lags m0 <= m < NQ into out, with the plan's
 // lanes per lag.
+// out2 != NULL (16 lanes per lag only): two wavefronts per row, the second
+// half of the lags into out2.
 void launch_local_sum(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, int m0, double* out,
-                      hipEvent_t ea = nullptr, hipEvent_t eb = nullptr) {
-  const int nb = 8 * (int)nblk(nblk(P->M, kRowThreads / 64), 8);
+                      hipEvent_t ea = nullptr, hipEvent_t eb = nullptr, double* out2 = nullptr) {
+  const int64_t waves = out2 ? 2 * P->M : P->M;
+  const int nb = 8 * (int)nblk(nblk(waves, kRowThreads / 64), 8);
 #define WFP_LOC(KER)                                                                                             \
   hipExtLaunchKernelGGL(KER, dim3(nb), dim3(kRowThreads), 0, s, ea, eb, 0, (int)P->M, P->NQ, P->NH, L, m0, P->NQ, \
                         P->nb_start, P->rowbase, P->acx, P->Qc, hist, (const double*)nullptr, out)
   switch (P->lgrp) {
     case 8: WFP_LOC(k_local_rhs_g8); break;
     case 4: WFP_LOC(k_local_rhs_g4); break;
-    default: WFP_LOC(k_local_rhs); break;
+    default:
+      hipExtLaunchKernelGGL(k_local_rhs, dim3(nb), dim3(kRowThreads), 0, s, ea, eb, 0, (int)P->M, P->NQ, P->NH, L,
+                            m0, P->NQ, P->nb_start, P->rowbase, P->acx, P->Qc, hist, (const double*)nullptr, out,
+                            out2);
+      break;
   }
 #undef WFP_LOC
 }
 
+// The lags >= 2 part of level L's local sum: rows of 16 lanes per lag split
+// over two wavefronts (halves into locb and locb2, summed by the lag-1 part).
+double* locb_second(wfp_plan* P, int64_t L) { return P->lgrp == 16 ? P->locb2 + (L & 1) * P->M : nullptr; }
+
 void launch_local_big(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, hipEvent_t ea = nullptr,
                       hipEvent_t eb = nullptr) {
-  launch_local_sum(P, s, hist, L, 2, P->locb + (L & 1) * P->M, ea, eb);
+  launch_local_sum(P, s, hist, L, 2, P->locb + (L & 1) * P->M, ea, eb, locb_second(P, L));
 }
 
 // Row of level L's driving data g_j(t_L) (eq. (gj)).  The values depend on L
@@ -1149,7 +1161,7 @@ const double* driving_row(wfp_plan* P, hipStream_t s, int64_t L) {
 void launch_local_lag1(wfp_plan* P, hipStream_t s, const double* hist, int64_t L) {
   const int nb = 8 * (int)nblk(nblk(P->M, 16), 8);   // 16 rows per block of 256 threads
   hipLaunchKernelGGL(k_local_lag1, dim3(nb), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L, P->nb_start,
-                     P->rowbase, P->acx, P->Qc, hist, P->locb + (L & 1) * P->M, P->loc);
+                     P->rowbase, P->acx, P->Qc, hist, P->locb + (L & 1) * P->M, locb_second(P, L), P->loc);
 }
 
 // One level L, in stream order: driving data (unless `driven`: P->ginc already
