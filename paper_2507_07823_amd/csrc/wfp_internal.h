@@ -176,7 +176,10 @@ struct wfp_plan {
   // stored weights: the lags >= 2 part of the local sum of level L, in
   // locb[L & 1] (its lag-1 part is added after sigma^{L-1} is solved)
   double* locb = nullptr;
-  double* locb2 = nullptr;   // its second half of lags when rows take two wavefronts
+  // rows of 16 lanes per lag take lsplit wavefronts; parts 1 .. lsplit - 1 of
+  // level L's lags >= 2 sum go to locb2 + ((L & 1)(lsplit - 1) + q - 1) M
+  double* locb2 = nullptr;
+  int lsplit = 1;
   // lanes per lag in the local sum (16, or 8 / 4 when the lag blocks are short)
   int lgrp = 16;
   // concurrent history chain: masked streams for the chain (sb) and the rest

@@ -88,7 +88,7 @@ __global__ void k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, int m1, co
                             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                             const double* __restrict__ Qc, const double* __restrict__ hist,
                             const double* __restrict__ addin, double* __restrict__ loc,
-                            double* __restrict__ loc2);
+                            double* __restrict__ loc2, int nsplit);
 __global__ void k_local_rhs_g8(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
                                const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                                const double* __restrict__ Qc, const double* __restrict__ hist,
@@ -100,7 +100,7 @@ __global__ void k_local_rhs_g4(int M, int NQ, int NH, int64_t L, int m0, int m1,
 __global__ void k_local_lag1(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
                              const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
                              const double* __restrict__ Qc, const double* __restrict__ hist,
-                             const double* __restrict__ addin, const double* __restrict__ addin2,
+                             const double* __restrict__ addin, const double* __restrict__ addin2, int nadd2,
                              double* __restrict__ loc);
 __global__ void k_incident(int M, double t, const double* __restrict__ xs, const double* __restrict__ beta,
                            Packets pk, int pp, int deriv, double* __restrict__ ginc);

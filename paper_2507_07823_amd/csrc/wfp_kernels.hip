@@ -538,22 +538,24 @@ template <int G = 16>
 __device__ __forceinline__ void k_local_rhs_body(int M, int NQ, int NH, int64_t L, int m0, int m1,
             const int* __restrict__ nb_start, const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx,
             const double* __restrict__ Qc, const double* __restrict__ hist, const double* __restrict__ addin,
-            double* __restrict__ loc, int bid, double* __restrict__ loc2 = nullptr) {
+            double* __restrict__ loc, int bid, double* __restrict__ loc2 = nullptr, int nsplit = 1) {
   const int lane = threadIdx.x & 63;
   const int gw = bid * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  // loc2 != NULL: two wavefronts per row, the first on lags m0 .. mid - 1 into
-  // loc (plus addin), the second on mid .. m1 - 1 into loc2 (mid a whole
-  // number of lag groups after m0), so each walks half the row's lag blocks
+  // nsplit > 1: nsplit wavefronts per row, part q on the q-th of nsplit equal
+  // shares of the row's trips over lag groups (64 / G lags per trip); part 0
+  // into loc (plus addin), part q > 0 into loc2[(q - 1) M + j], so each walks
+  // a share of the row's lag blocks
   int j = gw;
-  if (loc2) {
-    j = gw >> 1;
-    const int mid = min(m1, m0 + (((m1 - m0) / 2 + 64 / G - 1) / (64 / G)) * (64 / G));
-    if (gw & 1) {
-      m0 = mid;
-      loc = loc2;
+  if (nsplit > 1) {
+    j = gw / nsplit;
+    const int part = gw - j * nsplit;
+    const int nt = (m1 - m0 + 64 / G - 1) / (64 / G);
+    const int a = m0 + (part * nt / nsplit) * (64 / G);
+    m1 = min(m1, m0 + ((part + 1) * nt / nsplit) * (64 / G));
+    m0 = a;
+    if (part > 0) {
+      loc = loc2 + (int64_t)(part - 1) * M;
       addin = nullptr;
-    } else {
-      m1 = mid;
     }
   }
   if (j >= M) return;   // no block-level barrier in this kernel
@@ -610,9 +612,9 @@ __global__ void __launch_bounds__(256)
 k_local_rhs(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __restrict__ nb_start,
             const int64_t* __restrict__ rowbase, const uint2* __restrict__ acx, const double* __restrict__ Qc,
             const double* __restrict__ hist, const double* __restrict__ addin, double* __restrict__ loc,
-            double* __restrict__ loc2) {
+            double* __restrict__ loc2, int nsplit) {
   k_local_rhs_body(M, NQ, NH, L, m0, m1, nb_start, rowbase, acx, Qc, hist, addin, loc,
-                   xcd_block(blockIdx.x, gridDim.x), loc2);
+                   xcd_block(blockIdx.x, gridDim.x), loc2, nsplit);
 }
 
 // The same for rows with short lag blocks (8 or 4 lanes per lag).
@@ -640,7 +642,8 @@ k_local_rhs_g4(int M, int NQ, int NH, int64_t L, int m0, int m1, const int* __re
 __global__ void __launch_bounds__(256)
 k_local_lag1(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start, const int64_t* __restrict__ rowbase,
              const uint2* __restrict__ acx, const double* __restrict__ Qc, const double* __restrict__ hist,
-             const double* __restrict__ addin, const double* __restrict__ addin2, double* __restrict__ loc) {
+             const double* __restrict__ addin, const double* __restrict__ addin2, int nadd2,
+             double* __restrict__ loc) {
   const int gl = threadIdx.x & 15;
   const int j = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 4) + (threadIdx.x >> 4);
   if (j >= M) return;   // no barrier; the reduction below stays inside the row's 16 lanes
@@ -683,7 +686,11 @@ k_local_lag1(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
   double sum = acc0 + acc1;
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-  if (gl == 0) loc[j] = (addin2 ? addin[j] + addin2[j] : addin[j]) + sum;
+  if (gl == 0) {
+    double a = addin[j];
+    for (int q = 0; q < nadd2; ++q) a += addin2[(int64_t)q * M + j];
+    loc[j] = a + sum;
+  }
 }
 
 // The gradient pass's two signed derivative local sums (lags 0 .. NQ - 1) in

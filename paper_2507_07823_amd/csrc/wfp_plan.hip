@@ -10,6 +10,10 @@ thread_local std::string g_last_error;
 
 namespace {
 
+// wavefronts per row of the stored-weight local sum (rows of 16 lanes per
+// lag); 2 measured fastest of 1 to 4 at M = 1e4, 1e5 and 1e6
+constexpr int kLocalSplit = 2;
+
 void zero_state(wfp_plan* P) {
   auto fill = [&](double* ptr, int64_t n) {
     hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, P->stream, ptr, n, 0.0);
@@ -641,10 +645,11 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->rowbase = P->alloc<int64_t>(M);
     P->Qc = P->alloc<double>(packed + 2);   // spare elements for paired loads
     P->locb = P->alloc<double>(2 * (size_t)M);
-    P->locb2 = P->alloc<double>(2 * (size_t)M);
     // short lag blocks (few neighbours) take more lags per trip
     const double meanc = (double)packed / ((double)M * (P->NQ - 1));
     P->lgrp = meanc >= 48.0 ? 16 : (meanc >= 20.0 ? 8 : 4);
+    P->lsplit = P->lgrp == 16 ? kLocalSplit : 1;
+    if (P->lsplit > 1) P->locb2 = P->alloc<double>(2 * (size_t)(P->lsplit - 1) * M);
     upload(P->rowbase, rb, s);
     hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, 1,
                        P->nb_count, P->qoff, P->Q, P->ac, P->rowbase, P->Qc);
@@ -1108,11 +1113,12 @@ void launch_hist_c(wfp_plan* P, hipStream_t s, double2* grid) {
 // (reads sigma^{L-2} and older only), and its lag-1 part added to it.
 // The stored-weight local sum of lags m0 <= m < NQ into out, with the plan's
 // lanes per lag.
-// out2 != NULL (16 lanes per lag only): two wavefronts per row, the second
-// half of the lags into out2.
+// out2 != NULL (16 lanes per lag only): P->lsplit wavefronts per row, parts
+// 1 .. lsplit - 1 of the lags into out2 (M values each).
 void launch_local_sum(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, int m0, double* out,
                       hipEvent_t ea = nullptr, hipEvent_t eb = nullptr, double* out2 = nullptr) {
-  const int64_t waves = out2 ? 2 * P->M : P->M;
+  const int nsplit = out2 ? P->lsplit : 1;
+  const int64_t waves = nsplit * P->M;
   const int nb = 8 * (int)nblk(nblk(waves, kRowThreads / 64), 8);
 #define WFP_LOC(KER)                                                                                             \
   hipExtLaunchKernelGGL(KER, dim3(nb), dim3(kRowThreads), 0, s, ea, eb, 0, (int)P->M, P->NQ, P->NH, L, m0, P->NQ, \
@@ -1123,15 +1129,18 @@ void launch_local_sum(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
     default:
       hipExtLaunchKernelGGL(k_local_rhs, dim3(nb), dim3(kRowThreads), 0, s, ea, eb, 0, (int)P->M, P->NQ, P->NH, L,
                             m0, P->NQ, P->nb_start, P->rowbase, P->acx, P->Qc, hist, (const double*)nullptr, out,
-                            out2);
+                            out2, nsplit);
       break;
   }
 #undef WFP_LOC
 }
 
 // The lags >= 2 part of level L's local sum: rows of 16 lanes per lag split
-// over two wavefronts (halves into locb and locb2, summed by the lag-1 part).
-double* locb_second(wfp_plan* P, int64_t L) { return P->lgrp == 16 ? P->locb2 + (L & 1) * P->M : nullptr; }
+// over P->lsplit wavefronts (part 0 into locb, the others into locb2, all
+// summed by the lag-1 part).
+double* locb_second(wfp_plan* P, int64_t L) {
+  return P->lsplit > 1 ? P->locb2 + (L & 1) * (P->lsplit - 1) * P->M : nullptr;
+}
 
 void launch_local_big(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, hipEvent_t ea = nullptr,
                       hipEvent_t eb = nullptr) {
@@ -1161,7 +1170,8 @@ const double* driving_row(wfp_plan* P, hipStream_t s, int64_t L) {
 void launch_local_lag1(wfp_plan* P, hipStream_t s, const double* hist, int64_t L) {
   const int nb = 8 * (int)nblk(nblk(P->M, 16), 8);   // 16 rows per block of 256 threads
   hipLaunchKernelGGL(k_local_lag1, dim3(nb), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L, P->nb_start,
-                     P->rowbase, P->acx, P->Qc, hist, P->locb + (L & 1) * P->M, locb_second(P, L), P->loc);
+                     P->rowbase, P->acx, P->Qc, hist, P->locb + (L & 1) * P->M, locb_second(P, L), P->lsplit - 1,
+                     P->loc);
 }
 
 // One level L, in stream order: driving data (unless `driven`: P->ginc already
