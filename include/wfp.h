@@ -159,8 +159,11 @@ wfp_status wfp_plan_info(const wfp_plan* plan, wfp_info* info);
  *   u_recv_out device [n_steps][R] or NULL: u(x_r, t_L) at every level computed
  *              (u_L + u_H, eqs. (localSol2) and (historySol1)).
  * Asynchronous on the plan's stream, unless the plan checks for non-finite
- * values (check_finite), which waits for the stream at the end.
- * Errors: WFP_EINVAL, WFP_EHIP, WFP_ENONFINITE. */
+ * values (check_finite), which waits for the stream at the end.  The first
+ * call allocates the plan's block of driving-data levels (device memory held
+ * until wfp_plan_destroy), and checkpointing runs allocate their checkpoints;
+ * later calls allocate nothing.
+ * Errors: WFP_EINVAL, WFP_EHIP, WFP_ENONFINITE, WFP_ENOMEM. */
 wfp_status wfp_run(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t save_every,
                    double* u_recv_out);
 
