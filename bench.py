@@ -595,8 +595,8 @@ def main():
         print(f"{k}: mean of the last {n} dispatches {trace_tail_mean(d, k, int(n)):.3f} us")
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the march has no multi-GPU "
-              "path in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library runs the march "
+              "on one GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2507_07823_amd import wfp, workloads
