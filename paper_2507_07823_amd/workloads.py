@@ -283,6 +283,26 @@ def batch_instances(seed=4, n=512, n_steps=2000, m_range=(100, 100_000)):
     return out
 
 
+def clumped_level_state(M, K, W, m_hist, seed=21, n_hot=2000):
+    """A synthetic mid-run state of the clumped free-space workload for a
+    one-level check at full size: a unit-normal density history, whose newest
+    level is nonzero only at n_hot springs (so that a direct spectrum of it
+    stays cheap), a unit-normal spectra ring and mode state (real k = 0
+    terms).  Returns the state and the indices of the nonzero springs."""
+    r = _rng(seed, M)
+    hist = r.standard_normal((m_hist, M))
+    hot = np.unique(r.choice(M, n_hot, replace=False))
+    hist[0] = 0.0
+    hist[0, hot] = r.standard_normal(hot.size)
+    ring = r.standard_normal((W, K + 1)) + 1j * r.standard_normal((W, K + 1))
+    alpha = r.standard_normal(K + 1) + 1j * r.standard_normal(K + 1)
+    dalpha = r.standard_normal(K + 1) + 1j * r.standard_normal(K + 1)
+    ring[:, 0] = ring[:, 0].real
+    alpha[0] = alpha[0].real
+    dalpha[0] = dalpha[0].real
+    return dict(hist=hist, ring=ring, alpha=alpha, dalpha=dalpha), hot
+
+
 def random_state(seed, M, K, W, m_hist, scale=1e-2):
     """A synthetic mid-run state (density history, spectra ring, modes) used to
     test one step from a state both sides receive as input."""

@@ -4,6 +4,8 @@
     python tests/golden/make_golden.py balanced
     python tests/golden/make_golden.py longgrid
     python tests/golden/make_golden.py midgrid
+    python tests/golden/make_golden.py clumped
+    python tests/golden/make_golden.py clumped_level
 
 multiband: the periodic multiband workload (M = 1e4, dt = 1e-3, 1e4 steps)
 marched by the oracle for levels 0..n_steps; stores sigma at a few levels for
@@ -24,6 +26,20 @@ the spectrum are stored every 256th mode.
 
 midgrid: the same at the time step of the study's M = 1e5 (K = 51200, a
 boundary grid split 200 x 256 over workgroups), every 32nd mode.
+
+clumped: the clumped free-space distribution at M = 1e4 (10 % of the springs
+in 100 Gaussian clumps of width 1e-3, beta ~ U[1, 10] for all springs, the
+omega = 1000 packet, dt = 5e-4, K = 6250, boundary projection every 36
+levels) marched by the oracle for levels 0..4000; stores sigma of every
+spring at a few levels, 100 uniform and 100 clumped springs every 10th
+level, the max |sigma| over all levels and alpha, alpha' after the last.
+
+clumped_level: the clumped free-space workload at full size (M = 1e6) from
+the seeded synthetic state workloads.clumped_level_state at a level where the
+boundary projection is due: the new spectrum of the newest density level and
+alpha, alpha' after the level (every mode), and at 96 sampled springs (48
+uniform, 48 clumped) the explicit local sum, the right-hand side b_j of the
+per-step system and the nearby entries of its matrix row.
 """
 import os
 import sys
@@ -71,6 +87,91 @@ def multiband():
                         sigma_max=smax, n_levels=n)
 
 
+CLUMPED_FULL_LEVELS = (500, 1000, 2000, 3000, 4000)
+CLUMPED_M = 10_000
+
+
+def clumped_sample(M):
+    """100 springs of the uniform part and 100 in clumps (the workload puts
+    the clumped 10 % last)."""
+    rng = np.random.default_rng(4321)
+    n_un = int(round(0.9 * M))
+    s = np.concatenate([rng.choice(n_un, 100, replace=False), n_un + rng.choice(M - n_un, 100, replace=False)])
+    s.sort()
+    return s
+
+
+def clumped():
+    p = workloads.clumped_free_space(M=CLUMPED_M, clump_beta=(1.0, 10.0))
+    prm = Params(dt=p["dt"], boundary=1)
+    t0 = time.time()
+    o = Oracle(p["x"], p["beta"], prm, incident_driving(p["x"], p["beta"], p["packets"], False))
+    print(f"precompute {time.time() - t0:.1f}s K={prm.K} pairs={o.n_pairs}", flush=True)
+    n = p["n_steps"] + 1
+    sample = clumped_sample(p["x"].size)
+    full, strided, smax = {}, [], 0.0
+    t0 = time.time()
+    for L in range(n):
+        s, _ = o.step()
+        smax = max(smax, float(np.max(np.abs(s))))
+        if L in CLUMPED_FULL_LEVELS:
+            full[L] = s.copy()
+        if L % 10 == 0:
+            strided.append(s[sample])
+        if L % 250 == 0:
+            print(f"level {L} {time.time() - t0:.0f}s max|sigma| {smax:.3e}", flush=True)
+    e = o.get_state()
+    np.savez_compressed(os.path.join(HERE, "clumped_sigma.npz"),
+                        M=p["x"].size, full_levels=np.array(CLUMPED_FULL_LEVELS),
+                        full=np.array([full[L] for L in CLUMPED_FULL_LEVELS]),
+                        sample=sample, strided=np.array(strided), strided_every=10,
+                        sigma_max=smax, n_levels=n, alpha=e["alpha"], dalpha=e["dalpha"])
+
+
+CLUMPED_LEVEL_L = 36 * 139          # a multiple of the projection period
+
+
+def clumped_level_rows(M):
+    rng = np.random.default_rng(7)
+    n_un = int(round(0.9 * M))
+    return np.concatenate([rng.choice(n_un, 48, replace=False), n_un + rng.choice(M - n_un, 48, replace=False)])
+
+
+def clumped_level():
+    from oracle.history import mode_step, pq_tables, rotation
+    from oracle.rbc import rbc_project
+    from oracle.rows import history_field, row_pieces, spectrum_direct
+    p = workloads.clumped_free_space()
+    x, beta = p["x"], p["beta"]
+    M = x.size
+    prm = Params(dt=p["dt"], boundary=1)
+    L = CLUMPED_LEVEL_L
+    assert L % prm.rbc_period == 0
+    st, hot = workloads.clumped_level_state(M, prm.K, prm.W, prm.m_max)
+    t0 = time.time()
+    s_new = spectrum_direct(x[hot], st["hist"][0, hot], prm.K)
+    ring = np.concatenate([s_new[None], st["ring"][:-1]])
+    P, Q = pq_tables(prm.K, prm.dt, prm.W, prm.delta, prm.b, prm.n_gl_pq)
+    a, da = mode_step(st["alpha"], st["dalpha"], ring, P, Q, rotation(prm.K, prm.dt), prm.dt)
+    a, da = rbc_project(a, da, prm)
+    print(f"modes {time.time() - t0:.1f}s", flush=True)
+    rows = clumped_level_rows(M)
+    g = incident_driving(x[rows], beta[rows], p["packets"], False)(L * prm.dt)
+    uH = history_field(x[rows], a)
+    local, rhs, nb_idx, nb_val, nb_ptr = [], [], [], [], [0]
+    for i, j in enumerate(rows):
+        loc, nb, srow = row_pieces(x, beta, st["hist"], j, prm, False)
+        local.append(loc)
+        rhs.append(-(g[i] + beta[j] * loc + beta[j] * uH[i]))
+        nb_idx.append(nb)
+        nb_val.append(srow)
+        nb_ptr.append(nb_ptr[-1] + nb.size)
+    print(f"rows {time.time() - t0:.1f}s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "clumped_level.npz"), M=M, K=prm.K, L=L, spectrum=s_new,
+                        alpha=a, dalpha=da, rows=rows, local=np.array(local), rhs=np.array(rhs),
+                        nb_idx=np.concatenate(nb_idx), nb_val=np.concatenate(nb_val), nb_ptr=np.array(nb_ptr))
+
+
 def start_level(prm, t):
     """First level >= t / dt of the form k rbc_period - 1, so the boundary
     correction fires after the first step."""
@@ -116,4 +217,5 @@ def balanced():
 
 
 if __name__ == "__main__":
-    {"multiband": multiband, "balanced": balanced, "longgrid": longgrid, "midgrid": midgrid}[sys.argv[1]]()
+    {"multiband": multiband, "balanced": balanced, "longgrid": longgrid, "midgrid": midgrid,
+     "clumped": clumped, "clumped_level": clumped_level}[sys.argv[1]]()

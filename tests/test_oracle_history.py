@@ -103,3 +103,44 @@ def test_rbc_fft_form_equals_direct_sums():
         tol = 8 * K * math.pi * np.finfo(float).eps
         assert np.max(np.abs(u1 - u2)) < tol * np.max(np.abs(u1))
         assert np.max(np.abs(v1 - v2)) < tol * np.max(np.abs(v1))
+
+
+def test_free_space_pulse_leaves_the_box():
+    """Section 4.4: a free pulse represented by its modes travels through the
+    box unchanged (exact propagator), and the outgoing-windowing projection
+    applied every P levels lets it leave: once it has crossed |x| = pi the
+    whole box holds a residual at the window tolerance eps = 1e-12, not the
+    periodic image that would re-enter from the other side.  Both directions
+    (the left end is the mirror of the right-end formula)."""
+    from oracle.params import FREE_SPACE
+    from oracle.rbc import rbc_project
+    prm = Params(dt=0.01, boundary=FREE_SPACE)
+    K = prm.K
+    k = np.arange(K + 1)
+    x = np.linspace(-math.pi, math.pi, 1501)
+    E = np.exp(-1j * np.outer(x, k))
+    wk = np.where(k == 0, 1.0, 2.0)
+    zero_ring = np.zeros((prm.W, K + 1), np.complex128)
+    zero_tab = np.zeros((prm.W, K + 1))
+    rot = rotation(K, prm.dt)
+    w = 0.08
+    inner = np.abs(x) < math.pi - 2 * prm.delta_s
+    for direction, c in ((1.0, 1.5), (-1.0, -1.5)):
+        # u(x, t) = G(x - direction t), G a Gaussian of width w centred at c:
+        # alpha_k = (1/2pi) int G e^{ikx}, alpha'_k = direction i k alpha_k
+        a = w / math.sqrt(2 * math.pi) * np.exp(-k * k * w * w / 2) * np.exp(1j * k * c)
+        da = direction * 1j * k * a
+        gone = None
+        for L in range(1, 400):
+            a, da = mode_step(a, da, zero_ring, zero_tab, zero_tab, rot, prm.dt)
+            if L % prm.rbc_period == 0:
+                a, da = rbc_project(a, da, prm)
+            t = L * prm.dt
+            u = (E @ (wk * a)).real
+            exact = np.exp(-(x - c - direction * t) ** 2 / (2 * w * w))
+            assert np.max(np.abs(u - exact)[inner]) < 1e-12, (direction, L)
+            if abs(c) + t > math.pi + 12 * w and gone is None:
+                gone = L
+            if gone is not None and L >= gone + prm.rbc_period:
+                assert np.max(np.abs(u)) < prm.eps, (direction, L, np.max(np.abs(u)))
+        assert gone is not None

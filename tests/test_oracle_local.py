@@ -64,3 +64,46 @@ def test_p8_rule_on_smooth_density_is_accurate():
 def test_periodic_distance():
     assert abs(periodic_distance(-3.1, 3.1) - (2 * math.pi - 6.2)) < 1e-15
     assert periodic_distance(0.5, -0.25) == 0.75
+
+
+def _brute_force_weights(d, prm):
+    """Q_m(d) of Section 4.1 written out node by node, independently of the
+    oracle's vectorised form: for every Gauss-Legendre node, the p grid lags
+    nearest to the node are picked by sorting all allowed lags m_min..m_max
+    by their distance to the node (the literal "p nearest available points"),
+    and the interpolation weights come from the Lagrange product formula
+    (not the barycentric one)."""
+    z, w = np.polynomial.legendre.leggauss(prm.n_gl_local)
+    m_min = 0 if d < prm.dt else 1
+    lags = np.arange(m_min, prm.m_max + 1)
+    Q = np.zeros(prm.m_max + 1)
+    for zi, wi in zip(z, w):
+        tau = (prm.delta - d) / 2 * zi + (prm.delta + d) / 2     # time before t_{n+1}
+        s = tau / prm.dt                                          # in steps
+        order = np.argsort(np.abs(lags - s), kind="stable")
+        stencil = np.sort(lags[order[:prm.p]])
+        node_w = (prm.delta - d) / 2 * wi * (1 - phi(np.array([tau]), prm.delta, prm.b)[0])
+        for a in stencil:
+            ell = 1.0
+            for c in stencil:
+                if c != a:
+                    ell *= (s - c) / (a - c)
+            Q[a] += node_w * ell
+    return Q
+
+
+def test_stencil_is_the_p_nearest_available_lags():
+    """Each node's stencil is the p lags nearest to it among those allowed
+    (eq. (interp)): the oracle's weights equal a brute-force selection by
+    sorted distance.  A stencil started one lag newer or older than the
+    nearest set fails this at every p."""
+    rng = np.random.default_rng(3)
+    for p in (2, 4, 6, 8):
+        prm = Params(dt=0.01, p=p)
+        ds = np.concatenate([[0.0, 0.37 * prm.dt, 0.999 * prm.dt, prm.dt, 1.5 * prm.dt, 12.3 * prm.dt,
+                              prm.delta - 0.6 * prm.dt], rng.uniform(0, prm.delta, 4)])
+        Q = local_weights(ds, prm.dt, prm.W, p, prm.delta, prm.b, prm.n_gl_local)
+        for i, d in enumerate(ds):
+            ref = _brute_force_weights(d, prm)
+            # the weights are O(dt); rounding of the two forms differs by ~1e-16 dt
+            assert np.max(np.abs(Q[i] - ref)) < 1e-14 * prm.dt, (p, d)
