@@ -173,6 +173,15 @@ struct wfp_plan {
   bool otf = false;
   double *otf_z = nullptr, *otf_w = nullptr, *phitab = nullptr, *half_beta = nullptr;
   double* halfs = nullptr;       // 1/2 per row (the local part without beta)
+  // symmetric on-the-fly local sum: per row the unwrapped end of its upper
+  // source range, per block of kOtfRows rows the end of their union and the
+  // offset of its column sums in otf_part; the rows' own sums in otf_rowacc
+  int* otf_up_end = nullptr;
+  int* otf_blk_end = nullptr;
+  int64_t* otf_part_off = nullptr;
+  double* otf_part = nullptr;
+  double* otf_rowacc = nullptr;
+  int otf_nblk = 0;
   // stored weights: the lags >= 2 part of the local sum of level L, in
   // locb[L & 1] (its lag-1 part is added after sigma^{L-1} is solved)
   double* locb = nullptr;

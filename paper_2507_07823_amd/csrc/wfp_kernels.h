@@ -56,6 +56,7 @@ __global__ void k_local_weights(int nrows, const double* __restrict__ xt,
 
 constexpr int kPhiPieces = 512, kPhiDeg = 5;
 constexpr int kOtfRows = 16, kOtfChunk = 256;
+constexpr int kMaxOtfLags = 48;      // lags 1 .. NQ - 1 of a row staged by the symmetric local sum
 template <int P>
 __global__ void k_local_otf(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start,
                             const int* __restrict__ nb_count, const double* __restrict__ xs,
@@ -63,6 +64,19 @@ __global__ void k_local_otf(int M, int NH, int NQ, int64_t L, const int* __restr
                             double dt, double delta, int W, int ngl, const double* __restrict__ zs,
                             const double* __restrict__ ws, const double* __restrict__ phitab,
                             double* __restrict__ out);
+
+template <int P>
+__global__ void k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end,
+                                const int* __restrict__ blk_end, const int64_t* __restrict__ part_off,
+                                int nblk_rows, const double* __restrict__ xs, const double* __restrict__ hist,
+                                int periodic, double dt, double delta, int W, int ngl,
+                                const double* __restrict__ zs, const double* __restrict__ ws,
+                                const double* __restrict__ phitab, double* __restrict__ rowacc,
+                                double* __restrict__ part);
+__global__ void k_local_otf_reduce(int M, int nblk_rows, int periodic, const int* __restrict__ blk_end,
+                                   const int64_t* __restrict__ part_off, const double* __restrict__ rowacc,
+                                   const double* __restrict__ part, const double* __restrict__ scale,
+                                   double* __restrict__ out);
 
 __global__ void k_row_ranges(int M, int NQ, const int* __restrict__ nb_count, const int64_t* __restrict__ pbase,
                              const signed char* __restrict__ mlo, unsigned* __restrict__ ac);

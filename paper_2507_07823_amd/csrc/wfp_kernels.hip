@@ -972,6 +972,195 @@ WFP_OTF_INST(10)
 WFP_OTF_INST(12)
 #undef WFP_OTF_INST
 
+// Local sum of lags m >= 1 with the weights evaluated on the fly, each
+// unordered pair of springs once.  Q_m(d) depends on the distance alone
+// (Section 4.1), so the pair (j, l) shares its quadrature nodes, node weights,
+// stencils and interpolation weights between the two rows it feeds:
+//   row j:  sum_i om_i(d) sum_r v_{i,r} sigma_l^{L-m0_i-r},
+//   row l:  sum_i om_i(d) sum_r v_{i,r} sigma_j^{L-m0_i-r},
+// with the P lags from m0_i = max(m_min, floor(s_i) - P/2 + 1) (lag 0 taken as
+// 0: it belongs to the implicit solve) and the Lagrange weights at u = s_i - m0_i
+//   v_r = [prod_{k<r} (u - k)/r!] [prod_{k>r} (k - u)/(P-1-r)!],
+// formed as products of a prefix and a suffix (the node weight om_i folded
+// into the suffix).  Sources are taken in sorted order: row j walks its upper
+// range, the springs from j (itself, once) up to the first one beyond delta
+// (unwrapped: periodic ranges continue past M - 1 at 0).  Every unordered pair
+// lies in exactly one upper range because delta < pi.
+// A block holds kOtfRows consecutive rows (one wavefront each); the union of
+// their upper ranges is walked in chunks of kOtfChunk sources whose histories
+// (lags 0..NQ-1, lag 0 zero) are staged in LDS, beside the rows' own.  Row j's
+// sum goes to rowacc[j]; the column sums (row l's terms) are added over the
+// block's wavefronts in LDS in a fixed order and written to
+// part[part_off[b] + (u - j0)] for the block's unwrapped source u;
+// k_local_otf_reduce adds them up per row.
+// Factors of the Lagrange weights at u: prefix (u - r)/(r + 1) = fma(u, ca, cb),
+// suffix (r + 1 - u)/(P - 1 - r) = fma(u, cc, cd), r = 0..P-2.  Held in
+// registers across the node loop (as operands they would take the scalar
+// constant bus twice per FMA and cost a register copy each).
+template <int P>
+struct LagFactors {
+  double ca[P - 1], cb[P - 1], cc[P - 1], cd[P - 1];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int r = 0; r < P - 1; ++r) {
+      ca[r] = 1.0 / (r + 1);
+      cb[r] = -(double)r / (r + 1);
+      cc[r] = -1.0 / (P - 1 - r);
+      cd[r] = (double)(r + 1) / (P - 1 - r);
+      asm volatile("" : "+v"(ca[r]), "+v"(cb[r]), "+v"(cc[r]), "+v"(cd[r]));
+    }
+  }
+};
+
+template <int P>
+__device__ __forceinline__ void sym_node(double Dm, double span, int mmin, double na_q, double nw_q,
+                                         const double* __restrict__ tab, double Wd, double pw,
+                                         const double* __restrict__ sgk, const double* __restrict__ rh,
+                                         const LagFactors<P>& lf, double& acc_a, double& acc_c) {
+  const double s = fma(Dm, na_q, Wd);         // W - (W - D)(1 + z_q)/2
+  // 1 - phi(s dt) from the table: piece pc covers s in [pc, pc + 1) / pw
+  const double v = s * pw;
+  int pc = (int)v;
+  pc = pc < 0 ? 0 : (pc >= kPhiPieces ? kPhiPieces - 1 : pc);
+  const double t = 2.0 * (v - pc) - 1.0;
+  const double* c = tab + pc * (kPhiDeg + 1);
+  double ph = c[kPhiDeg];
+#pragma unroll
+  for (int k = kPhiDeg - 1; k >= 0; --k) ph = fma(ph, t, c[k]);
+  const double om = span * nw_q * (1.0 - ph);
+  int m0 = (int)floor(s) - P / 2 + 1;
+  if (m0 < mmin) m0 = mmin;
+  // s rounds to W only for d within an ulp of delta (zero weight): keep the
+  // stencil inside lags 0 .. W + P/2 - 1
+  const int mtop = (int)Wd - P / 2;
+  if (m0 > mtop) m0 = mtop;
+  const double u = s - m0;
+  double A[P], B[P];
+  A[0] = 1.0;
+#pragma unroll
+  for (int r = 0; r < P - 1; ++r) A[r + 1] = A[r] * fma(u, lf.ca[r], lf.cb[r]);
+  B[P - 1] = om;
+#pragma unroll
+  for (int r = P - 2; r >= 0; --r) B[r] = B[r + 1] * fma(u, lf.cc[r], lf.cd[r]);
+  const double* sp = sgk + m0 * kOtfChunk;
+  const double* rp = rh + m0;
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    const double w = A[r] * B[r];
+    acc_a = fma(w, sp[r * kOtfChunk], acc_a);
+    acc_c = fma(w, rp[r], acc_c);
+  }
+}
+
+template <int P>
+__global__ void __launch_bounds__(1024)
+k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end, const int* __restrict__ blk_end,
+                const int64_t* __restrict__ part_off, int nblk_rows, const double* __restrict__ xs,
+                const double* __restrict__ hist, int periodic, double dt, double delta, int W, int ngl,
+                const double* __restrict__ zs, const double* __restrict__ ws, const double* __restrict__ phitab,
+                double* __restrict__ rowacc, double* __restrict__ part) {
+  extern __shared__ double sg[];                              // [NQ][kOtfChunk], then [kOtfRows][kOtfChunk]
+  __shared__ double tab[kPhiPieces * (kPhiDeg + 1)];
+  __shared__ double rh[kOtfRows][kMaxOtfLags + 1];
+  __shared__ double na[64], nw[64];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= nblk_rows) return;                                 // padding block: nothing to do
+  double* colp = sg + (size_t)NQ * kOtfChunk;                 // per-wavefront column sums of a chunk
+  for (int i = threadIdx.x; i < kPhiPieces * (kPhiDeg + 1); i += blockDim.x) tab[i] = phitab[i];
+  for (int i = threadIdx.x; i < ngl; i += blockDim.x) {
+    na[i] = 0.5 * (1.0 + zs[i]);
+    nw[i] = 0.5 * ws[i];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j0 = b * kOtfRows;
+  const int j = j0 + wv;
+  const bool row = j < M;
+  for (int e = threadIdx.x; e < kOtfRows * NQ; e += blockDim.x) {
+    const int w = e / NQ, m = e - w * NQ;
+    rh[w][m] = (m >= 1 && j0 + w < M) ? hist[(int64_t)mod_slot(L - m, NH) * M + (j0 + w)] : 0.0;
+  }
+  for (int k = threadIdx.x; k < kOtfChunk; k += blockDim.x) sg[k] = 0.0;   // lag 0
+  const long long uend = blk_end[b];                          // unwrapped end of the block's sources
+  const long long my1 = row ? up_end[j] : j;                  // row's upper range [j, my1)
+  const double xa = row ? xs[j] : 0.0;
+  const double Wd = (double)W;
+  const double pw = (double)kPhiPieces / Wd;
+  const int64_t pbase = part_off[b];
+  LagFactors<P> lf;
+  lf.init();
+  double acc = 0.0;
+  for (long long cb = j0; cb < uend; cb += kOtfChunk) {
+    __syncthreads();   // the previous chunk is no longer read
+    for (int e = threadIdx.x; e < (NQ - 1) * kOtfChunk; e += blockDim.x) {
+      const int m = e / kOtfChunk + 1, k = e - (m - 1) * kOtfChunk;
+      const long long u = cb + k;
+      double v = 0.0;
+      if (u < uend) v = hist[(int64_t)mod_slot(L - m, NH) * M + (int)(u % M)];
+      sg[m * kOtfChunk + k] = v;
+    }
+    for (int e = threadIdx.x; e < kOtfRows * kOtfChunk; e += blockDim.x) colp[e] = 0.0;
+    __syncthreads();
+    const long long a0 = (long long)j > cb ? (long long)j : cb;
+    const long long a1 = my1 < cb + kOtfChunk ? my1 : cb + kOtfChunk;
+    for (long long ua = a0 + lane; ua < a1; ua += 64) {
+      double d = fabs(xa - xs[(int)(ua % M)]);
+      if (periodic && d > kPi) d = kTwoPi - d;
+      const bool on = d < delta;
+      const int k = (int)(ua - cb);
+      const double Dm = on ? d / dt - Wd : -0.5 * Wd;    // off: D = W/2, nodes inside (0, W), zero weight
+      const int mmin = (on && d < dt) ? 0 : 1;
+      const double span = on ? delta - d : 0.0;
+      double pa = 0.0, pcol = 0.0;
+      for (int q = 0; q < ngl; ++q) sym_node<P>(Dm, span, mmin, na[q], nw[q], tab, Wd, pw, sg + k, rh[wv], lf, pa, pcol);
+      acc += pa;
+      if (ua != (long long)j) colp[wv * kOtfChunk + k] = pcol;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kOtfChunk; k += blockDim.x) {
+      const long long u = cb + k;
+      if (u < uend) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < kOtfRows; ++w) sum += colp[w * kOtfChunk + k];
+        part[pbase + (u - j0)] = sum;
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  if (row && lane == 0) rowacc[j] = acc;
+}
+
+// Row l's total of the symmetric local sum: its own upper-range sum plus the
+// column sums that the blocks covering l wrote for it (blocks at or below
+// l's own whose source range reaches l, and in the periodic box the blocks
+// whose range wraps past M - 1 to l + M), in a fixed order; scaled per row.
+__global__ void __launch_bounds__(256)
+k_local_otf_reduce(int M, int nblk_rows, int periodic, const int* __restrict__ blk_end,
+                   const int64_t* __restrict__ part_off, const double* __restrict__ rowacc,
+                   const double* __restrict__ part, const double* __restrict__ scale, double* __restrict__ out) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= M) return;
+  double acc = rowacc[l];
+  for (int b = l / kOtfRows; b >= 0 && blk_end[b] > l; --b) acc += part[part_off[b] + (l - b * kOtfRows)];
+  if (periodic) {
+    const long long lw = (long long)l + M;
+    for (int b = nblk_rows - 1; b >= 0 && blk_end[b] > lw; --b) acc += part[part_off[b] + (lw - (long long)b * kOtfRows)];
+  }
+  out[l] = scale[l] * acc;
+}
+
+#define WFP_OTFS_INST(PP)                                                                                      \
+  template __global__ void k_local_otf_sym<PP>(int, int, int, int64_t, const int*, const int*, const int64_t*, \
+                                               int, const double*, const double*, int, double, double, int, int, \
+                                               const double*, const double*, const double*, double*, double*);
+WFP_OTFS_INST(2)
+WFP_OTFS_INST(4)
+WFP_OTFS_INST(6)
+WFP_OTFS_INST(8)
+WFP_OTFS_INST(10)
+WFP_OTFS_INST(12)
+#undef WFP_OTFS_INST
+
 // Driving data g_j(t) = beta_j f(x_j - t) (eq. (gj); f periodised in the
 // periodic box), stored negated: ginc_j = -g_j.  Thread (row, packet) sums the
 // packet's images; the packets are then added in order.  `pp` = packets per

@@ -583,6 +583,34 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
       }
       if (worst > 1e-15) fail(WFP_EDOMAIN, "window table for the on-the-fly weights is not accurate");
     }
+    // upper source ranges of the symmetric local sum (each unordered pair once)
+    {
+      const int nb = (int)nblk(M, kOtfRows);
+      std::vector<int> up(M), be(nb, 0);
+      std::vector<int64_t> po(nb);
+      for (int64_t j = 0; j < M; ++j) {
+        const int64_t st = nbs[j] <= j ? nbs[j] : (int64_t)nbs[j] - M;
+        const int64_t e = st + nbc[j];
+        if (!(st <= j && j < e && e <= j + M)) fail(WFP_EINVAL, "neighbour range does not contain its row");
+        up[j] = (int)e;
+        be[j / kOtfRows] = std::max(be[j / kOtfRows], (int)e);
+      }
+      int64_t tot_part = 0;
+      for (int b = 0; b < nb; ++b) {
+        if (b > 0 && be[b] < be[b - 1]) fail(WFP_EINVAL, "upper source ranges not monotone");
+        po[b] = tot_part;
+        tot_part += (int64_t)be[b] - (int64_t)b * kOtfRows;
+      }
+      P->otf_nblk = nb;
+      P->otf_up_end = P->alloc<int>(M);
+      P->otf_blk_end = P->alloc<int>(nb);
+      P->otf_part_off = P->alloc<int64_t>(nb);
+      P->otf_part = P->alloc<double>(tot_part);
+      P->otf_rowacc = P->alloc<double>(M);
+      upload(P->otf_up_end, up, s);
+      upload(P->otf_blk_end, be, s);
+      upload(P->otf_part_off, po, s);
+    }
     P->otf_z = P->alloc<double>(P->ngl);
     P->otf_w = P->alloc<double>(P->ngl);
     P->phitab = P->alloc<double>(tab.size());
@@ -1027,6 +1055,16 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
                           (const void*)k_local_otf<8>, (const void*)k_local_otf<10>, (const void*)k_local_otf<12>};
     const int dyn = (int)((size_t)(P->NQ - 1) * kOtfChunk * sizeof(double));
     for (const void* f : fns) HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
+    const size_t sym_lds = (size_t)(P->NQ + kOtfRows) * kOtfChunk * sizeof(double) +
+                           (size_t)kPhiPieces * (kPhiDeg + 1) * sizeof(double) +
+                           (size_t)kOtfRows * (kMaxOtfLags + 1) * sizeof(double) + 128 * sizeof(double);
+    if (P->NQ - 1 > kMaxOtfLags || sym_lds > 160 * 1024)
+      fail(WFP_EDOMAIN, "on-the-fly local sum: too many lags for the LDS stage");
+    const void* sfns[6] = {(const void*)k_local_otf_sym<2>, (const void*)k_local_otf_sym<4>,
+                           (const void*)k_local_otf_sym<6>, (const void*)k_local_otf_sym<8>,
+                           (const void*)k_local_otf_sym<10>, (const void*)k_local_otf_sym<12>};
+    const int sdyn = (int)((size_t)(P->NQ + kOtfRows) * kOtfChunk * sizeof(double));
+    for (const void* f : sfns) HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, sdyn));
   }
   // the column pass holds 6 n1 complex values and the FIR partial sums of G
   // tap groups ([G][2 n1] double4); column pairs of 400 modes or more keep one
@@ -1053,16 +1091,19 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
-// Local sum of lags >= 1 with the weights evaluated on the fly, scaled per row.
+// Local sum of lags >= 1 with the weights evaluated on the fly, scaled per row:
+// each unordered pair once (k_local_otf_sym), then the per-row totals
+// (k_local_otf_reduce).  ea / eb bracket both launches.
 void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, const double* scale, double* out,
                       hipEvent_t ea = nullptr, hipEvent_t eb = nullptr) {
-  const int nblocks = 8 * (int)nblk(nblk(P->M, kOtfRows), 8);
+  const int nblocks = 8 * (int)nblk(P->otf_nblk, 8);
   const int periodic = P->boundary == WFP_PERIODIC ? 1 : 0;
-  const size_t lds = (size_t)(P->NQ - 1) * kOtfChunk * sizeof(double);
+  const size_t lds = (size_t)(P->NQ + kOtfRows) * kOtfChunk * sizeof(double);
 #define WFP_OTF(PP)                                                                                               \
-  hipExtLaunchKernelGGL(k_local_otf<PP>, dim3(nblocks), dim3(64 * kOtfRows), lds, s, ea, eb, 0, (int)P->M, P->NH,  \
-                        P->NQ, L, P->nb_start, P->nb_count, P->xs, hist, scale, periodic, P->dt, P->delta, P->W,    \
-                        P->ngl, P->otf_z, P->otf_w, P->phitab, out)
+  hipExtLaunchKernelGGL(k_local_otf_sym<PP>, dim3(nblocks), dim3(64 * kOtfRows), lds, s, ea, nullptr, 0,          \
+                        (int)P->M, P->NH, P->NQ, L, P->otf_up_end, P->otf_blk_end, P->otf_part_off, P->otf_nblk,  \
+                        P->xs, hist, periodic, P->dt, P->delta, P->W, P->ngl, P->otf_z, P->otf_w, P->phitab,    \
+                        P->otf_rowacc, P->otf_part)
   switch (P->p) {
     case 2: WFP_OTF(2); break;
     case 4: WFP_OTF(4); break;
@@ -1072,6 +1113,9 @@ void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
     default: WFP_OTF(12); break;
   }
 #undef WFP_OTF
+  hipExtLaunchKernelGGL(k_local_otf_reduce, dim3(nblk(P->M, 256)), dim3(256), 0, s, nullptr, eb, 0, (int)P->M,
+                        P->otf_nblk, periodic, P->otf_blk_end, P->otf_part_off, P->otf_rowacc, P->otf_part, scale,
+                        out);
 }
 
 // The march state a level reads and updates: density history ring, spectra
