@@ -1,22 +1,31 @@
 #!/usr/bin/env python3
 """Throughput of the WFP march on one MI355X: scatterer-steps per second.
 
-Workload: the periodic multiband problem (M = 1e4 springs, beta log-uniform in
-[0.1, 10], 8 Gaussian wave packets with angular carriers 50..500, dt = 1e-3,
-K = 3141, W = 35, p = 8), FP64.  A step is one time level of the march (spread,
-FFT, mode update, inverse FFT, local sum + interpolation, solve).  Plan
-creation (sorting, tables, local weights) happens before timing, as in the
-paper's timings; the timed region starts with every input resident in HBM.
+Headline workload: the clumped free-space problem at full size (M = 1e6 springs
+uniform in the box with 10 % in 100 Gaussian clumps of width 1e-3, a
+Gaussian-modulated plane wave of angular frequency 1000, dt = 5e-4, K = 6250,
+W = 35, p = 8, local weights evaluated on the fly), FP64.  A step is one time
+level of the march (spread, FFT, mode update, boundary projection when due,
+inverse FFT, local sum, solve).  Plan creation (sorting, tables, solve
+factors) happens before timing, as in the paper's timings; the timed region
+starts with every input resident in HBM.
 
 Printed: one JSON line on stdout (diagnostics on stderr).
   value       M * steps / seconds over the timed steps
-  parity      max |sigma_gpu - sigma_oracle| / max |sigma_oracle| against the
-              stored oracle values (tests/golden/multiband_sigma.npz)
-  roofline    the dominant kernel, timed with HIP events on the plan's stream in
-              a second pass over the same steps (while timing, the library runs
-              every stage on that stream, so the kernel is timed alone);
-              algorithmic bytes per launch as stated in the design notes
-  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
+  parity      one level of the same plan from a seeded synthetic state against
+              stored oracle values (tests/golden/clumped_level.npz): the new
+              spectrum and alpha, alpha' at every mode, the explicit local sum
+              at 96 sampled springs and the residual of the per-step system there
+  roofline    the on-the-fly local sum (the dominant kernel), timed with HIP
+              events on the plan's stream in a second pass (while timing, the
+              library runs every stage on that stream, so the kernel is timed
+              alone); algorithmic flops per launch = ordered neighbour pairs x
+              1.6 kflop
+  cpu_baseline  the FP64 CPU oracle on the same distribution at M = 1e4, run in
+              a child process beside the GPU legs
+Secondary legs (each in its own key): the periodic multiband workload (M = 1e4)
+with its stored-oracle parity, the gradient pass, the batched form, the
+scaling study, the convergence test, the filters and the disordered runs.
 """
 import argparse
 import csv
@@ -24,6 +33,8 @@ import hashlib
 import json
 import math
 import os
+import re
+import subprocess
 import sys
 import time
 from collections import defaultdict
@@ -36,41 +47,58 @@ sys.path.insert(0, ROOT)
 METRIC = "scatterer-steps/s (M*N_t/s) at 1e-10 rel err; batched & adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "multiband_sigma.npz")
+CLUMPED_GOLDEN = os.path.join(ROOT, "tests", "golden", "clumped_level.npz")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_07823_amd", "csrc", "wfp_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_local_rhs.periodic-multiband-M1e4.traffic.txt")
 COPY_BYTES = 1 << 28          # the calibration copy moves 256 MiB
 
+# Per kernel: its own source text (from the first marker up to the second)
+# and the committed counter summary of its HBM traffic.
+KERNELS = {
+    "wfp::k_local_rhs": dict(
+        region=("// Local sum of lags m0 <= m < m1", "// The lag-1 part of the right-hand side local sum"),
+        traffic=os.path.join(ROOT, "profiles", "k_local_rhs.periodic-multiband-M1e4.traffic.txt")),
+    "wfp::k_local_otf_sym": dict(
+        region=("// Local sum of lags m >= 1 with the weights evaluated on the fly, each",
+                "#define WFP_OTFS_INST"),
+        traffic=os.path.join(ROOT, "profiles", "k_local_otf_sym.clumped-free-space-M1e6.traffic.txt")),
+}
 
-# the local-sum kernel's own source text (its comment, the paired-load type,
-# the body and the kernel), from the first marker up to the second
-KERNEL_REGION = ("// Local sum of lags m0 <= m < m1", "// The lag-1 part of the right-hand side local sum")
 
-
-def kernel_source_hash():
-    """SHA-256 of the local-sum kernel's source region: the counter summary
-    holds only while that text is unchanged."""
+def kernel_source_hash(kernel):
+    """SHA-256 of a kernel's source region: its counter summary holds only
+    while that text is unchanged."""
+    a_mark, b_mark = KERNELS[kernel]["region"]
     with open(KERNEL_SOURCE, encoding="utf-8") as f:
         src = f.read()
-    a = src.index(KERNEL_REGION[0])
-    b = src.index(KERNEL_REGION[1], a)
+    a = src.index(a_mark)
+    b = src.index(b_mark, a)
     return hashlib.sha256(src[a:b].encode("utf-8")).hexdigest()
 
 
-def read_traffic():
-    """HBM bytes per launch of the local-sum kernel from the committed counter
-    summary, or None when it is missing or the kernel source has changed since
-    the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(kernel):
+    """HBM bytes per launch of a kernel from its committed counter summary, or
+    None when it is missing or the kernel source has changed since the
+    counters were taken."""
+    fn = KERNELS[kernel]["traffic"]
+    if not os.path.exists(fn):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(fn) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash():
+    if kv.get("kernel_source_sha256") != kernel_source_hash(kernel):
         return None
     return float(kv["traffic_bytes_per_dispatch"])
+
+
+def _kname(name):
+    """Kernel name without return type, template arguments and parameters."""
+    n = name.split("(")[0]
+    if n.startswith("void "):
+        n = n[5:]
+    return re.sub(r"<.*>", "", n)
 
 
 def _counter_means(d, counter):
@@ -81,11 +109,11 @@ def _counter_means(d, counter):
             with open(os.path.join(d, fn)) as f:
                 for r in csv.DictReader(f):
                     if r["Counter_Name"] == counter:
-                        acc[r["Kernel_Name"].split("(")[0]].append(float(r["Counter_Value"]))
+                        acc[_kname(r["Kernel_Name"])].append(float(r["Counter_Value"]))
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
-def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, kernel="wfp::k_local_rhs"):
+def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, kernel="wfp::k_local_otf_sym"):
     """Text summary: FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of ``kernel``,
     each scaled by what the counter reads for a 256 MiB device copy."""
     cf = _counter_means(cal_fetch_dir, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][0]
@@ -97,7 +125,7 @@ def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, kernel="wfp:
     traffic = 1024.0 * (fe * ff + wr * fw)
     return "\n".join([
         f"kernel: {kernel}",
-        f"kernel_source_sha256: {kernel_source_hash()}",
+        f"kernel_source_sha256: {kernel_source_hash(kernel)}",
         f"dispatches: {n}",
         f"FETCH_SIZE_KiB_per_dispatch: {fe:.3f}",
         f"WRITE_SIZE_KiB_per_dispatch: {wr:.3f}",
@@ -117,7 +145,7 @@ def trace_tail_mean(d, kernel, n):
         if fn.endswith("kernel_trace.csv"):
             with open(os.path.join(d, fn)) as f:
                 for r in csv.DictReader(f):
-                    if r["Kernel_Name"].split("(")[0] == kernel:
+                    if _kname(r["Kernel_Name"]) == kernel:
                         durs.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
     durs.sort()
     tail = [x for _, x in durs[-n:]]
@@ -134,7 +162,7 @@ def stats_summary(d, top=20):
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     out = [f"{'kernel':<32} {'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
     for r in rows[:top]:
-        out.append(f"{r['Name'].split('(')[0][:32]:<32} {int(r['Calls']):>7} {float(r['AverageNs']) / 1e3:>10.3f} "
+        out.append(f"{_kname(r['Name'])[:32]:<32} {int(r['Calls']):>7} {float(r['AverageNs']) / 1e3:>10.3f} "
                    f"{float(r['MinNs']) / 1e3:>10.3f} {float(r['MaxNs']) / 1e3:>10.3f} "
                    f"{float(r['Percentage']):>6.2f}")
     return "\n".join(out)
@@ -178,53 +206,126 @@ def stage_bytes(info, stage):
     return 0
 
 
-def check_golden(sig_rows, save_every, steps):
+def check_golden(plan, M):
+    """The multiband plan from level 0 through the stored oracle levels (an
+    untimed march): the full density rows and the sampled springs every 100th
+    level up to the last full level, compared with the oracle's.  Reports the
+    levels compared and whether any compared row carries the scattered field
+    (max |sigma| above 1e-3 of the run's maximum), so that a check made
+    before the pulse arrives cannot pass as parity."""
+    import torch
     if not os.path.exists(GOLDEN):
         return None
     g = np.load(GOLDEN)
     smax = float(g["sigma_max"])
-    worst = 0.0
-    n_cmp = 0
+    last = int(max(L for L in g["full_levels"] if L <= 1000))
+    plan.reset()
+    sig = torch.empty((last + 1, M), dtype=torch.float64, device="cuda")
+    plan.run(last + 1, sig, 1)
+    torch.cuda.synchronize()
+    s = sig.cpu().numpy()
+    worst, n_cmp, live, levels = 0.0, 0, 0.0, []
     for L, row in zip(g["full_levels"], g["full"]):
-        if L < steps and L % save_every == 0:
-            worst = max(worst, float(np.max(np.abs(sig_rows[L // save_every] - row))))
+        if L <= last:
+            worst = max(worst, float(np.max(np.abs(s[L] - row))))
             n_cmp += row.size
+            live = max(live, float(np.max(np.abs(row))))
+            levels.append(int(L))
     every = int(g["strided_every"])
     sample = g["sample"]
+    n_strided = 0
     for i, row in enumerate(g["strided"]):
         L = i * every
-        if L < steps and L % save_every == 0:
-            worst = max(worst, float(np.max(np.abs(sig_rows[L // save_every][sample] - row))))
+        if L <= last:
+            worst = max(worst, float(np.max(np.abs(s[L][sample] - row))))
             n_cmp += row.size
-    return dict(rel_err=worst / smax, compared=n_cmp, tol=1e-10)
+            n_strided += 1
+    return dict(rel_err=worst / smax, compared=n_cmp, full_levels=levels,
+                sampled_levels=f"0..{last} every {every} ({n_strided} levels, {sample.size} springs)",
+                field_present=bool(live > 1e-3 * smax), tol=1e-10)
 
 
-def cpu_baseline(p, n_steps):
+def clumped_parity(plan, p):
+    """One level of the headline plan from the seeded synthetic state of
+    workloads.clumped_level_state (a level where the boundary projection is
+    due), against the stored oracle values: the new spectrum and alpha, alpha'
+    at every mode, the explicit local sum at 96 sampled springs, and there the
+    residual sigma_j + sum_l S_jl sigma_l - b_j of the per-step system."""
+    import torch
+    from paper_2507_07823_amd import workloads
+    if not os.path.exists(CLUMPED_GOLDEN):
+        return None
+    g = np.load(CLUMPED_GOLDEN)
+    info = plan.info
+    M, K, W, mm = info["M"], info["K"], info["W"], info["m_max"]
+    st, _ = workloads.clumped_level_state(M, K, W, mm)
+
+    def dev(z):
+        return torch.from_numpy(np.ascontiguousarray(np.stack([z.real, z.imag], -1))).cuda()
+
+    plan.set_state(int(g["L"]), torch.from_numpy(st["hist"]).cuda(), dev(st["ring"]), dev(st["alpha"]),
+                   dev(st["dalpha"]))
+    loc = plan.local_part()
+    sig, _ = plan.march(1, receivers=False)
+    e = plan.get_state()
+    torch.cuda.synchronize()
+    loc = loc.cpu().numpy()
+    sig = sig.cpu().numpy()[0]
+    ring = e["ring"].cpu().numpy()
+    a = e["alpha"].cpu().numpy()
+    da = e["dalpha"].cpu().numpy()
+
+    def rho(x, y):
+        return float(np.max(np.abs(x - y)) / np.max(np.abs(y)))
+
+    rows = g["rows"]
+    ptr, idx, val = g["nb_ptr"], g["nb_idx"], g["nb_val"]
+    res = np.array([sig[j] + val[ptr[i]:ptr[i + 1]] @ sig[idx[ptr[i]:ptr[i + 1]]] - g["rhs"][i]
+                    for i, j in enumerate(rows)])
+    out = {"level": int(g["L"]),
+           "spectrum": rho(ring[0, :, 0] + 1j * ring[0, :, 1], g["spectrum"]),
+           "alpha": rho(a[:, 0] + 1j * a[:, 1], g["alpha"]),
+           "dalpha": rho(da[:, 0] + 1j * da[:, 1], g["dalpha"]),
+           "local_sum_sampled": rho(loc[rows], g["local"]),
+           "residual_sampled": float(np.max(np.abs(res)) / np.max(np.abs(g["rhs"]))),
+           "modes": int(K + 1), "sampled_springs": int(rows.size), "tol": 1e-10}
+    out["rel_err"] = max(out[k] for k in ("spectrum", "alpha", "dalpha", "local_sum_sampled", "residual_sampled"))
+    return out
+
+
+def cpu_baseline(levels):
+    """The FP64 CPU oracle (direct sums, per-pair weights, sparse LU) on the
+    clumped free-space distribution at M = 1e4 (beta ~ U[1, 10]), timed over
+    `levels` levels after its set-up."""
     from oracle.march import Oracle, incident_driving
     from oracle.params import Params
+    from paper_2507_07823_amd import workloads
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
+    p = workloads.clumped_free_space(M=10_000, clump_beta=(1.0, 10.0))
     t0 = time.perf_counter()
-    o = Oracle(p["x"], p["beta"], Params(dt=p["dt"]), incident_driving(p["x"], p["beta"], p["packets"], True))
+    o = Oracle(p["x"], p["beta"], Params(dt=p["dt"], boundary=1),
+               incident_driving(p["x"], p["beta"], p["packets"], False))
     pre = time.perf_counter() - t0
     t0 = time.perf_counter()
-    for _ in range(n_steps):
+    for _ in range(levels):
         o.step()
     el = time.perf_counter() - t0
     M = p["x"].size
-    return {"value": M * n_steps / el, "unit": "scatterer-steps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"same workload, levels 0..{n_steps - 1} of the CPU oracle (direct sums, sparse LU), "
-                      f"timed after its {pre:.0f} s set-up"}
+    return {"value": M * levels / el, "unit": "scatterer-steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"the clumped free-space distribution at M = {M} (K = 6250, dt = 5e-4), levels "
+                      f"0..{levels - 1} of the CPU oracle, timed after its {pre:.0f} s set-up"}
 
 
 def adjoint_leg(levels, every):
     """Forward + gradient pass on the adjoint workload (M = 1e5 springs, 64
     receivers, dt = 1e-3) over `levels` levels with checkpoints every `every`
-    levels, against the plain forward march of the same plan.  The first
-    gradient call (derivative-weight set-up) is not timed."""
+    levels, against the plain forward march of the same plan.  A first
+    gradient call over one checkpoint segment (derivative-weight set-up) is
+    not timed."""
     import torch
     from paper_2507_07823_amd import wfp, workloads
     p = workloads.adjoint_periodic()
@@ -233,8 +334,8 @@ def adjoint_leg(levels, every):
     plan = wfp.Plan(p, p["dt"], checkpoint_every=every)
     setup = time.perf_counter() - t0
     u = torch.empty((levels, R), dtype=torch.float64, device="cuda")
-    plan.run(levels, None, 1, u)
-    plan.gradient(p["dt"] * u)                       # warm-up and one-time set-up
+    plan.run(every, None, 1, u[:every])
+    plan.gradient(p["dt"] * u[:every])               # warm-up and one-time set-up on one segment
     plan.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -293,16 +394,16 @@ def batch_leg(n_inst, levels, m_max, trial_levels=3):
             "batched_over_plain": t_plain / t_batch}
 
 
-# FP64 operations of one quadrature node in the on-the-fly local sum, counted
-# as the method needs them: node lag (1 FMA), window polynomial of degree 5
-# (5 FMA), node weight (2 mul), the degree-7 interpolant of the density
-# history in Newton form (7 sub + 7 FMA), accumulation (1 FMA).
-OTF_FLOPS_PER_NODE = 2 + 10 + 2 + 7 + 14 + 2
+# Algorithmic FP64 operations of the on-the-fly local sum per ordered
+# neighbour pair: N_L = 35 quadrature nodes, each a node lag, a window weight
+# and a degree-7 interpolant of the source's history (about 46 flops), 1.6
+# kflop in all (the method's per-pair estimate).
+OTF_FLOPS_PER_PAIR = 1600.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def balanced_leg(levels, sizes, autotune_levels):
-    """The free-space scaling study of Section 6 (springs uniform in [-2, 2],
+    """The free-space scaling study of Section 6.2 (springs uniform in [-2, 2],
     beta in [0.1, 3], p = 6, dt chosen for about 100 neighbours) at each M of
     `sizes`: set-up time, the schedule wfp_plan_autotune picks, the rate over `levels` levels from rest (the
     per-level work does not depend on the densities) and the per-stage times
@@ -343,7 +444,7 @@ def balanced_leg(levels, sizes, autotune_levels):
             row["local_GBps"] = stage_bytes(info, "local") / (stages["local"] * 1e-6) / 1e9
         rows.append(row)
         log(f"balanced M={M}: {rows[-1]}")
-    return {"workload": "free-space scaling study (Section 6), p = 6, about 100 neighbours", "sizes": rows,
+    return {"workload": "free-space scaling study (Section 6.2), p = 6, about 100 neighbours", "sizes": rows,
             "paper_context": {"scatterer_steps_per_s": 1.5e5, "hardware": "2 x Xeon Platinum 8362 (64 cores)",
                               "note": "the paper's asymptotic CPU rate for this study, M up to 1e6"}}
 
@@ -384,7 +485,7 @@ def convergence_leg(sizes=(10, 100), orders=(2, 4, 6, 8), dts=(0.0125, 0.00625, 
 
 
 def filters_leg():
-    """The filter demonstrations of Section 6.3 (free space, dt = 0.01): the
+    """The filter demonstrations of Section 6.4 (free space, dt = 0.01): the
     two-spring cavity (9426 levels) and arrays of 10 and 200 springs (25134
     levels), the march time of each and, for the cavity, the frequencies the
     downstream total field passes (peaks of the Hann-windowed transform of the
@@ -420,11 +521,11 @@ def filters_leg():
                                          if T[i] > T[i - 1] and T[i] > T[i + 1] and T[i] > 0.2 * T.max()]
         rows.append(row)
         log(f"filter M={M}: {row}")
-    return {"workload": "spring filters (Section 6.3), free space, dt = 0.01", "runs": rows}
+    return {"workload": "spring filters (Section 6.4), free space, dt = 0.01", "runs": rows}
 
 
 def disordered_leg(large_levels):
-    """The long disordered runs of Section 6.2 (random springs on [-2, 2], a
+    """The long disordered runs of Section 6.3 (random springs on [-2, 2], a
     pulse of width sqrt(8) times the mean spacing, p = 8): M = 1e3 marched
     in full (72044 levels) and at dt / 2 (144088 levels), the estimated error
     of the first from the second at 50 receivers; M = 1e4 timed over its
@@ -432,7 +533,7 @@ def disordered_leg(large_levels):
     other hardware) are quoted as context."""
     import torch
     from paper_2507_07823_amd import wfp, workloads
-    out = {"workload": "disordered springs (Section 6.2), free space, p = 8"}
+    out = {"workload": "disordered springs (Section 6.3), free space, p = 8"}
     us = []
     for rf in (1, 2):
         prob = workloads.disordered_long(1000, refine=rf)
@@ -475,7 +576,7 @@ def disordered_full(M=10_000, chunk=50_000, refines=(1, 2)):
     receivers."""
     import torch
     from paper_2507_07823_amd import wfp, workloads
-    out = {"workload": f"disordered springs (Section 6.2), M = {M}, full run", "M": M}
+    out = {"workload": f"disordered springs (Section 6.3), M = {M}, full run", "M": M}
     us = []
     for rf in refines:
         prob = workloads.disordered_long(M, refine=rf)
@@ -504,10 +605,11 @@ def disordered_full(M=10_000, chunk=50_000, refines=(1, 2)):
     return out
 
 
-def clumped_leg(levels):
-    """The clumped free-space workload at full size (M = 1e6, dt = 5e-4, K = 6250,
-    local weights on the fly): set-up time and the rate over `levels` levels
-    from rest (the per-level work does not depend on the densities)."""
+def headline(steps, warmup, profile_levels):
+    """The clumped free-space workload at full size (M = 1e6): set-up, `warmup`
+    untimed levels, `steps` timed levels, then a profiled pass of
+    `profile_levels` levels for the per-stage times and the roofline of the
+    on-the-fly local sum, then the one-level parity check."""
     import torch
     from paper_2507_07823_amd import wfp, workloads
     p = workloads.clumped_free_space()
@@ -516,38 +618,107 @@ def clumped_leg(levels):
     plan = wfp.Plan(p, p["dt"])
     setup = time.perf_counter() - t0
     info = plan.info
-    plan.run(1)
+    log(f"clumped plan: {setup:.2f} s, info {info}")
+    if warmup:
+        plan.run(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan.run(levels)
+    plan.run(steps)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    elapsed = time.perf_counter() - t0
+    log(f"timed {steps} levels in {elapsed:.3f} s -> {M * steps / elapsed:.4e} scatterer-steps/s")
+    roofline, stages = None, None
+    if profile_levels:
+        plan.set_profiling(True)
+        plan.run(profile_levels)
+        prof = plan.profile()
+        plan.set_profiling(False)
+        stages = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in prof.items() if v[1]}
+        ms, n = prof["local"]
+        avg = ms / n
+        flops = info["n_pairs"] * OTF_FLOPS_PER_PAIR
+        achieved = flops / (avg * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": "wfp::k_local_otf_sym (+ k_local_otf_reduce)", "achieved": achieved,
+                    "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                    "traffic": read_traffic("wfp::k_local_otf_sym"), "avg_launch_ms": avg,
+                    "flops_per_launch": flops, "flop_count": "ordered neighbour pairs x 1.6 kflop",
+                    "timed_with": "HIP events on the plan's stream"}
+        log(f"stages: {json.dumps(stages)}")
+    parity = clumped_parity(plan, p)
+    log(f"parity vs oracle: {parity}")
+    plan.close()
+    cfg = {"workload": "clumped free space (10 % of springs in 100 Gaussian clumps of width 1e-3)",
+           "M": M, "dt": p["dt"], "K": info["K"], "W": info["W"], "p": info["p"], "n_fine": info["n_fine"],
+           "pairs": info["n_pairs"], "local_mode": "on the fly", "solve_mode": info["solve_mode"],
+           "beta_uniform": [1.0, 10.0], "beta_clumped": list(workloads.CLUMP_BETA),
+           "levels_timed": steps, "parallelism": "single GPU", "plan_setup_s": setup}
+    return dict(value=M * steps / elapsed, elapsed=elapsed, config=cfg, parity=parity, roofline=roofline,
+                stages=stages)
+
+
+def multiband_leg(steps, warmup, overlap_cus, autotune_levels):
+    """The periodic multiband workload (M = 1e4, stored weights): rate over
+    `steps` levels, the roofline of its local sum (HBM-bound) and parity with
+    the stored oracle march."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    p = workloads.multiband_periodic()
+    M = p["x"].size
+    t0 = time.perf_counter()
+    plan = wfp.Plan(p, p["dt"], overlap_cus=overlap_cus)
+    setup = time.perf_counter() - t0
+    if overlap_cus == 0:
+        pick = plan.autotune(autotune_levels)
+        log(f"multiband autotune: overlap_cus {pick}")
+    info = plan.info
+    if warmup:
+        plan.march(warmup)
+    plan.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan.reset()
     plan.set_profiling(True)
-    plan.run(levels)
+    plan.run(steps)
     prof = plan.profile()
     plan.set_profiling(False)
+    stages = {}
+    for s_, (ms, n) in prof.items():
+        if n:
+            avg = ms / n
+            b = stage_bytes(info, s_)
+            stages[s_] = {"avg_us": 1e3 * avg, "launches": n, "bytes": b,
+                          "GBps": (b / (avg * 1e-3) / 1e9) if b else None}
+    st = stages["local"]
+    roofline = {"bound": "hbm", "kernel": "wfp::k_local_rhs", "achieved": st["GBps"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": st["GBps"] / HBM_PEAK_GBS, "traffic": read_traffic("wfp::k_local_rhs"),
+                "avg_launch_us": st["avg_us"], "bytes_per_launch": st["bytes"]}
+    parity = check_golden(plan, M)
     plan.close()
-    ms, n = prof["local"]
-    avg = ms / n
-    flops = info["n_pairs"] * info["n_gl_local"] * OTF_FLOPS_PER_NODE
-    achieved = flops / (avg * 1e-3) / 1e12
-    return {"workload": "clumped free space", "M": M, "dt": p["dt"], "K": info["K"], "pairs": info["n_pairs"],
-            "local_mode": info["local_mode"], "solve_mode": info["solve_mode"], "plan_setup_s": setup,
-            "levels": levels, "ms_per_level": 1e3 * el / levels, "scatterer_steps_per_s": M * levels / el,
-            "local_sum": {"bound": "alu", "avg_ms": avg, "flops_per_launch": flops, "achieved_tflops": achieved,
-                          "peak_tflops": FP64_VECTOR_PEAK_TFLOPS, "frac": achieved / FP64_VECTOR_PEAK_TFLOPS},
-            "stages_ms": {k: v[0] / v[1] for k, v in prof.items() if v[1]}}
+    out = {"workload": "periodic multiband springs (beta log-uniform in [0.1, 10])", "M": M, "dt": p["dt"],
+           "K": info["K"], "p": info["p"], "pairs": info["n_pairs"], "overlap_cus": info["overlap_cus"],
+           "plan_setup_s": setup, "levels": steps, "ms_per_level": 1e3 * elapsed / steps,
+           "scatterer_steps_per_s": M * steps / elapsed, "roofline": roofline, "stages": stages, "parity": parity}
+    log(f"multiband leg: {out}")
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=20, help="timed levels of the headline workload")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed levels before them")
+    ap.add_argument("--profile-levels", type=int, default=5,
+                    help="levels of the headline's profiled pass (roofline, stage times; 0 skips it)")
+    ap.add_argument("--cpu-levels", type=int, default=40, help="levels of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--adjoint-levels", type=int, default=500,
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only run the CPU oracle baseline and print its JSON (the child process of a bench run)")
+    ap.add_argument("--multiband-levels", type=int, default=2000,
+                    help="levels of the periodic multiband leg (0 skips it)")
+    ap.add_argument("--adjoint-levels", type=int, default=5000,
                     help="levels of the adjoint leg (0 skips it)")
     ap.add_argument("--batch-levels", type=int, default=200, help="levels of the batched leg (0 skips it)")
     ap.add_argument("--batch-instances", type=int, default=512)
@@ -556,7 +727,6 @@ def main():
                          "evaluate their local weights on the fly and a level takes about a second)")
     ap.add_argument("--batch-full-levels", type=int, default=3,
                     help="levels of a second batched leg over the full M range [100, 1e5] (0 skips it)")
-    ap.add_argument("--clumped-levels", type=int, default=5, help="levels of the M = 1e6 leg (0 skips it)")
     ap.add_argument("--no-convergence", action="store_true", help="skip the manufactured-solution leg")
     ap.add_argument("--no-filters", action="store_true", help="skip the spring-filter leg")
     ap.add_argument("--disordered-full", action="store_true",
@@ -566,26 +736,29 @@ def main():
                     help="with --disordered-full: the runs to make (1 = dt, 2 = dt/2; both give the error estimate)")
     ap.add_argument("--disordered-levels", type=int, default=20000,
                     help="levels timed at M = 1e4 in the disordered leg (negative skips the leg)")
-    ap.add_argument("--balanced-levels", type=int, default=2000,
+    ap.add_argument("--balanced-levels", type=int, default=1000,
                     help="levels per size of the free-space scaling-study leg (0 skips it)")
     ap.add_argument("--balanced-only", action="store_true",
                     help="only run the scaling-study leg (for counter runs of its kernels) and print its result")
     ap.add_argument("--balanced-sizes", type=str, default="1000,10000,100000,1000000",
                     help="comma-separated M of the scaling-study leg")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only run the headline workload (for profiler runs) and print its JSON line")
     ap.add_argument("--overlap-cus", type=int, default=0,
-                    help="plan parameter overlap_cus (0: chosen by wfp_plan_autotune, -1: one stream)")
+                    help="multiband plan parameter overlap_cus (0: chosen by wfp_plan_autotune, -1: one stream)")
     ap.add_argument("--autotune-levels", type=int, default=30,
                     help="trial levels per candidate schedule of wfp_plan_autotune")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 256 MiB copy used to calibrate the HBM counters")
-    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+    ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR",
+                                                       "KERNEL"),
                     help="print the traffic summary of rocprofv3 --pmc runs and exit")
     ap.add_argument("--stats-summary", metavar="DIR", help="print a rocprofv3 --stats table and exit")
     ap.add_argument("--trace-tail", nargs=3, metavar=("DIR", "KERNEL", "N"),
                     help="print the mean duration of the last N dispatches of KERNEL in a kernel trace and exit")
     args = ap.parse_args()
     if args.pmc_summary:
-        print(pmc_summary(*args.pmc_summary))
+        print(pmc_summary(*args.pmc_summary[:4], kernel=args.pmc_summary[4]))
         return
     if args.stats_summary:
         print(stats_summary(args.stats_summary))
@@ -598,126 +771,77 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library runs the march "
               "on one GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
-    import torch
-    from paper_2507_07823_amd import wfp, workloads
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(args.cpu_levels)), flush=True)
+        return
+    # the CPU oracle baseline runs in a child process beside the GPU legs
+    child = None
+    if not (args.no_cpu_baseline or args.headline_only or args.balanced_only or args.disordered_full
+            or args.copy_calibration):
+        child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                                  "--cpu-levels", str(args.cpu_levels)], stdout=subprocess.PIPE, text=True)
+    try:
+        out = run_gpu_legs(args)
+    finally:
+        cpu = None
+        if child is not None:
+            so, _ = child.communicate()
+            try:
+                cpu = json.loads(so.strip().splitlines()[-1])
+            except (ValueError, IndexError):
+                cpu = None
+            log(f"cpu baseline: {cpu}")
+    if out is None:
+        return
+    out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
 
+
+def run_gpu_legs(args):
+    import torch
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
-        return
+        return None
     if args.balanced_only:
         print(json.dumps(balanced_leg(args.balanced_levels, [int(v) for v in args.balanced_sizes.split(",")],
                                       args.autotune_levels)), flush=True)
-        return
+        return None
     if args.disordered_full:
         print(json.dumps(disordered_full(refines=[int(v) for v in args.disordered_refines.split(",")])),
               flush=True)
-        return
-    p = workloads.multiband_periodic()
-    M = p["x"].size
-    t0 = time.perf_counter()
-    plan = wfp.Plan(p, p["dt"], overlap_cus=args.overlap_cus)
-    setup = time.perf_counter() - t0
-    if args.overlap_cus == 0:
-        t1 = time.perf_counter()
-        pick = plan.autotune(args.autotune_levels)
-        log(f"autotune: overlap_cus {pick} in {time.perf_counter() - t1:.2f} s")
-    info = plan.info
-    log(f"plan: {setup:.2f} s, info {info}")
-    if args.warmup:
-        plan.march(args.warmup)
-    plan.reset()
-    save_every = 50
-    rows = (args.steps + save_every - 1) // save_every
-    sig = torch.empty((rows, M), dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.run(args.steps, sig, save_every)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    value = M * args.steps / elapsed
-    log(f"timed {args.steps} steps in {elapsed:.4f} s -> {value:.4e} scatterer-steps/s")
-    parity = check_golden(sig.cpu().numpy(), save_every, args.steps)
-    log(f"parity vs oracle: {parity}")
-
-    roofline, stages = None, None
-    if not args.no_profile:
-        plan.reset()
-        plan.set_profiling(True)
-        plan.run(args.steps)
-        prof = plan.profile()
-        plan.set_profiling(False)
-        stages = {}
-        for s, (ms, n) in prof.items():
-            if n:
-                avg = ms / n
-                b = stage_bytes(info, s)
-                stages[s] = {"avg_us": 1e3 * avg, "launches": n, "bytes": b,
-                             "GBps": (b / (avg * 1e-3) / 1e9) if b else None}
-        log("stages:", json.dumps(stages))
-        dom = max(stages, key=lambda s: stages[s]["avg_us"] * stages[s]["launches"])
-        st = stages[dom]
-        achieved = st["GBps"]
-        traffic = read_traffic() if dom == "local" else None
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
-                    "avg_launch_us": st["avg_us"], "bytes_per_launch": st["bytes"]}
-
-    adjoint = None
-    if args.adjoint_levels > 0:
-        adjoint = adjoint_leg(args.adjoint_levels, 250)
-        log(f"adjoint leg: {adjoint}")
-
-    batch = None
-    if args.batch_levels > 0:
-        batch = batch_leg(args.batch_instances, args.batch_levels, args.batch_max_m)
-        log(f"batch leg: {batch}")
-    batch_full = None
-    if args.batch_full_levels > 0:
-        batch_full = batch_leg(args.batch_instances, args.batch_full_levels, 100_000, trial_levels=1)
-        log(f"full-range batch leg: {batch_full}")
-
-    clumped = None
-    if args.clumped_levels > 0:
-        clumped = clumped_leg(args.clumped_levels)
-        log(f"clumped leg: {clumped}")
-
-    balanced = None
-    if args.balanced_levels > 0:
-        balanced = balanced_leg(args.balanced_levels, [int(v) for v in args.balanced_sizes.split(",")],
-                                args.autotune_levels)
-
-    convergence = None
-    if not args.no_convergence:
-        convergence = convergence_leg()
-        log("convergence leg:", json.dumps(convergence))
-
-    filters = None
-    if not args.no_filters:
-        filters = filters_leg()
-
-    disordered = None
-    if args.disordered_levels >= 0:
-        disordered = disordered_leg(args.disordered_levels)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(p, args.cpu_steps)
-        log(f"cpu baseline: {cpu}")
-
+        return None
+    h = headline(args.steps, args.warmup, args.profile_levels)
     out = {
-        "metric": METRIC, "value": value, "unit": "scatterer-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "metric": METRIC, "value": h["value"], "unit": "scatterer-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * h["elapsed"] / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "periodic multiband springs", "M": M, "dt": p["dt"], "K": info["K"],
-                   "W": info["W"], "p": info["p"], "n_fine": info["n_fine"], "pairs": info["n_pairs"],
-                   "levels_timed": args.steps, "overlap_cus": info["overlap_cus"], "parallelism": "single GPU"},
-        "parity": parity, "roofline": roofline, "stages": stages, "adjoint": adjoint, "batch": batch,
-        "batch_full_range": batch_full, "clumped": clumped, "balanced": balanced, "convergence": convergence,
-        "filters": filters, "disordered": disordered, "cpu_baseline": cpu,
+        "config": h["config"], "parity": h["parity"], "roofline": h["roofline"], "stages": h["stages"],
     }
-    print(json.dumps(out), flush=True)
-    plan.close()
+    if args.headline_only:
+        return out
+    if args.multiband_levels > 0:
+        out["multiband"] = multiband_leg(args.multiband_levels, 200, args.overlap_cus, args.autotune_levels)
+    if args.adjoint_levels > 0:
+        out["adjoint"] = adjoint_leg(args.adjoint_levels, 250)
+        log(f"adjoint leg: {out['adjoint']}")
+    if args.batch_levels > 0:
+        out["batch"] = batch_leg(args.batch_instances, args.batch_levels, args.batch_max_m)
+        log(f"batch leg: {out['batch']}")
+    if args.batch_full_levels > 0:
+        out["batch_full_range"] = batch_leg(args.batch_instances, args.batch_full_levels, 100_000, trial_levels=1)
+        log(f"full-range batch leg: {out['batch_full_range']}")
+    if args.balanced_levels > 0:
+        out["balanced"] = balanced_leg(args.balanced_levels, [int(v) for v in args.balanced_sizes.split(",")],
+                                       args.autotune_levels)
+    if not args.no_convergence:
+        out["convergence"] = convergence_leg()
+        log("convergence leg:", json.dumps(out["convergence"]))
+    if not args.no_filters:
+        out["filters"] = filters_leg()
+    if args.disordered_levels >= 0:
+        out["disordered"] = disordered_leg(args.disordered_levels)
+    return out
 
 
 if __name__ == "__main__":

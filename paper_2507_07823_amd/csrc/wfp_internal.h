@@ -111,6 +111,11 @@ wfp_status guard(const std::function<void()>& f);
 
 using namespace wfpi;
 
+struct wfp_plan;
+// Drops the plan's hold on its split's masked streams (destroyed with the
+// last hold).  Never throws.
+void release_overlap_streams(wfp_plan* P) noexcept;
+
 struct wfp_plan {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -195,6 +200,7 @@ struct wfp_plan {
   // (sa), and sd on the same compute units as sa for the lags >= 2 part of the
   // next level's local sum
   int overlap_cus = 0;
+  int overlap_held = 0;          // split whose shared masked streams this plan holds (0: none)
   hipStream_t sa = nullptr, sb = nullptr, sd = nullptr;
   hipEvent_t ev_solved = nullptr, ev_chain = nullptr, ev_join = nullptr;
   hipEvent_t ev_big[2] = {nullptr, nullptr};
@@ -263,10 +269,12 @@ struct wfp_plan {
   ~wfp_plan() {
     // work queued on the plan's stream may still read its buffers
     (void)hipStreamSynchronize(stream);
-    // sa, sb and sd are shared by every plan on the device (never destroyed)
     if (sa) (void)hipStreamSynchronize(sa);
     if (sb) (void)hipStreamSynchronize(sb);
     if (sd) (void)hipStreamSynchronize(sd);
+    // sa, sb and sd are shared by the plans on the device with the same split;
+    // the last one to let go destroys them
+    release_overlap_streams(this);
     for (hipEvent_t e : {ev_solved, ev_chain, ev_join, ev_big[0], ev_big[1]})
       if (e) (void)hipEventDestroy(e);
     for (auto& q : pending) {

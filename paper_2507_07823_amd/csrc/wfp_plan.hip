@@ -8,6 +8,33 @@ namespace wfpi {
 thread_local std::string g_last_error;
 }  // namespace wfpi
 
+// Masked streams per (device, split), shared by the plans that use the split
+// and destroyed when the last of them lets go (each masked stream holds a
+// hardware queue until it is destroyed).
+struct MaskedStreams {
+  std::array<hipStream_t, 3> st{nullptr, nullptr, nullptr};
+  int holds = 0;
+};
+static std::mutex g_masked_mu;
+static std::map<std::pair<int, int>, MaskedStreams> g_masked;
+
+void release_overlap_streams(wfp_plan* P) noexcept {
+  if (P->overlap_held <= 0) return;
+  std::lock_guard<std::mutex> lock(g_masked_mu);
+  auto it = g_masked.find(std::make_pair(P->device, P->overlap_held));
+  if (it != g_masked.end() && --it->second.holds == 0) {
+    for (hipStream_t q : it->second.st)
+      if (q) {
+        (void)hipStreamSynchronize(q);
+        (void)hipStreamDestroy(q);
+      }
+    g_masked.erase(it);
+  }
+  P->overlap_held = 0;
+  P->sa = P->sb = P->sd = nullptr;
+}
+
+
 namespace {
 
 // wavefronts per row of the stored-weight local sum (rows of 16 lanes per
@@ -159,6 +186,15 @@ void launch_local_weights(wfp_plan* P, int nrows, const double* xt, const int* s
 // chain (sb) and the solve (sa) on the first cus, the local sum and driving
 // data (sd) on the rest; cus <= 0 selects one stream.
 void set_overlap(wfp_plan* P, int cus) {
+  if (cus == P->overlap_held && cus > 0) {
+    P->overlap_cus = cus;
+    return;
+  }
+  // work of the previous split is finished before its streams may go
+  if (P->sa) HIPCHK(hipStreamSynchronize(P->sa));
+  if (P->sb) HIPCHK(hipStreamSynchronize(P->sb));
+  if (P->sd) HIPCHK(hipStreamSynchronize(P->sd));
+  release_overlap_streams(P);
   if (cus <= 0) {
     P->overlap_cus = -1;
     return;
@@ -177,23 +213,23 @@ void set_overlap(wfp_plan* P, int cus) {
       md[c / 32] |= 1u << (c % 32);
     }
   }
-  // one set of masked streams per (device, split), shared by all plans and
-  // kept until the process ends: each masked stream holds a hardware queue
-  static std::mutex mu;
-  static std::map<std::pair<int, int>, std::array<hipStream_t, 3>> pool;
-  std::lock_guard<std::mutex> lock(mu);
-  auto key = std::make_pair(P->device, cus);
-  auto it = pool.find(key);
-  if (it == pool.end()) {
-    std::array<hipStream_t, 3> st{nullptr, nullptr, nullptr};
-    HIPCHK(hipExtStreamCreateWithCUMask(&st[0], (uint32_t)words, ma.data()));
-    HIPCHK(hipExtStreamCreateWithCUMask(&st[1], (uint32_t)words, mb.data()));
-    HIPCHK(hipExtStreamCreateWithCUMask(&st[2], (uint32_t)words, md.data()));
-    it = pool.emplace(key, st).first;
+  {
+    std::lock_guard<std::mutex> lock(g_masked_mu);
+    auto key = std::make_pair(P->device, cus);
+    auto it = g_masked.find(key);
+    if (it == g_masked.end()) {
+      MaskedStreams ms;
+      HIPCHK(hipExtStreamCreateWithCUMask(&ms.st[0], (uint32_t)words, ma.data()));
+      HIPCHK(hipExtStreamCreateWithCUMask(&ms.st[1], (uint32_t)words, mb.data()));
+      HIPCHK(hipExtStreamCreateWithCUMask(&ms.st[2], (uint32_t)words, md.data()));
+      it = g_masked.emplace(key, ms).first;
+    }
+    ++it->second.holds;
+    P->overlap_held = cus;
+    P->sa = it->second.st[0];
+    P->sb = it->second.st[1];
+    P->sd = it->second.st[2];
   }
-  P->sa = it->second[0];
-  P->sb = it->second[1];
-  P->sd = it->second[2];
   if (!P->ev_solved) {
     HIPCHK(hipEventCreateWithFlags(&P->ev_solved, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&P->ev_chain, hipEventDisableTiming));

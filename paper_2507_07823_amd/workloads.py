@@ -65,8 +65,12 @@ def multiband_periodic(seed=2, M=10_000, dt=1e-3, n_steps=10_000, beta_max=10.0)
                 x_recv=np.zeros(0), name=f"periodic-multiband-M{M}-dt{dt:g}-Nt{n_steps}")
 
 
+# stiffness range of the clumped springs at full size (see clumped_free_space)
+CLUMP_BETA = (0.1, 1.0)
+
+
 def clumped_free_space(seed=3, M=1_000_000, dt=5e-4, n_steps=4000, n_clumps=100,
-                       frac=0.1, clump_sigma=1e-3, margin=0.0528, clump_beta=(0.1, 1.0)):
+                       frac=0.1, clump_sigma=1e-3, margin=0.0528, clump_beta=CLUMP_BETA):
     """Free space, M springs uniform in Omega with a fraction in tight Gaussian
     clumps, Gaussian-modulated plane wave of angular frequency 1000 entering
     from the left.  Uniform springs: beta ~ U[1, 10].  Clumped springs: beta ~
@@ -101,7 +105,7 @@ def balanced_dt(M, m_typ=100.0, W=35, half_width=2.0):
 
 
 def paper_balanced_free_space(M, seed=6, n_steps=2000, m_typ=100.0, min_sep=1e-6):
-    """The scaling study of Section 6 (timing): free space, M springs uniform
+    """The scaling study of Section 6.2 (timing): free space, M springs uniform
     in [-2, 2] with pairwise separation at least min_sep (points closer than
     that to their left neighbour are redrawn), beta ~ U[0.1, 3], Gaussian pulse
     f(s) = exp(-30 (s + 3)^2) (width 1/sqrt(60)), dt from balanced_dt so the
@@ -209,7 +213,7 @@ def manufactured_data(prob, dt, n_levels):
 
 
 def spring_filter(M, beta, t0, n_steps, span=(-1.0, 1.0), dt=0.01, x_recv=1.5, p=8):
-    """The filter demonstrations of Section 6.3: M equal springs evenly
+    """The filter demonstrations of Section 6.4: M equal springs evenly
     spaced over `span` (both ends included), free space, incident wave
     f(x - t) with f(s) = exp(-5 (s - t0)^2), dt = 0.01, interpolation order p,
     one receiver downstream at x_recv."""
@@ -235,7 +239,7 @@ def spring_arrays():
 
 
 def disordered_long(M, seed=11, refine=1, n_recv=50):
-    """The long disordered runs of Section 6.2: free space, M springs uniform
+    """The long disordered runs of Section 6.3: free space, M springs uniform
     in [-2, 2], beta ~ U[0.1, 3], a narrow pulse f(s) = exp(-M^2 (s + 3)^2)
     (width sqrt(8) times the mean spacing 4/M), p = 8, the paper's time steps
     (1.308e-4 at M = 1e3, 1.308e-5 at M = 1e4; dt scales like 1/M) and level

@@ -1,5 +1,5 @@
 """Parity of the HIP path with the FP64 CPU oracle on the free-space scaling
-study of Section 6 (springs uniform in [-2, 2], beta in [0.1, 3], Gaussian
+study of Section 6.2 (springs uniform in [-2, 2], beta in [0.1, 3], Gaussian
 pulse exp(-30 (s + 3)^2), p = 6, dt such that the mean neighbour count is
 about 100).
 

@@ -1,4 +1,4 @@
-"""The long disordered run of Section 6.2 at M = 1e3 through the HIP path:
+"""The long disordered run of Section 6.3 at M = 1e3 through the HIP path:
 1000 random springs, a pulse of width sqrt(8) times the mean spacing, p = 8,
 72044 levels of dt = 1.308e-4 (about 3 pi), the field at 50 receivers; its
 accuracy estimated, as the paper does, against the same run at dt / 2

@@ -1,4 +1,4 @@
-"""The filter demonstrations of Section 6.3 through the HIP path, against
+"""The filter demonstrations of Section 6.4 through the HIP path, against
 the exact solution for point springs (oracle.exact.spring_array_field: the
 frequency-domain solve per frequency and its inverse transform, pinned in
 test_oracle_exact.py) and, for the two-spring cavity, against the oracle

@@ -5,7 +5,7 @@ Zero driving, a random density history: with p = 8 and dt = 1e-3 the march
 decays for beta dt / 2 = 0.2 and grows for beta dt / 2 = 0.4, while p = 4 still
 decays at 0.4.  Clusters of nearby stiff springs act like one spring of summed
 stiffness, which is why the throughput workload keeps beta <= 10 at M = 1e4,
-dt = 1e-3.  At beta dt / 2 = 0.5 (the filter demonstrations of Section 6.3:
+dt = 1e-3.  At beta dt / 2 = 0.5 (the filter demonstrations of Section 6.4:
 beta = 100, dt = 0.01, free space) p = 6 decays and p = 8 grows by ~0.18 per
 level, so those run at p = 6."""
 import math
