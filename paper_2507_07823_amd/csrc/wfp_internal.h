@@ -186,6 +186,7 @@ struct wfp_plan {
   int64_t* otf_part_off = nullptr;
   double* otf_part = nullptr;
   double* otf_rowacc = nullptr;
+  double *otf_na = nullptr, *otf_nw = nullptr;
   int otf_nblk = 0;
   // stored weights: the lags >= 2 part of the local sum of level L, in
   // locb[L & 1] (its lag-1 part is added after sigma^{L-1} is solved)

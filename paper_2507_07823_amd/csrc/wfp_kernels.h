@@ -70,7 +70,7 @@ __global__ void k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __r
                                 const int* __restrict__ blk_end, const int64_t* __restrict__ part_off,
                                 int nblk_rows, const double* __restrict__ xs, const double* __restrict__ hist,
                                 int periodic, double dt, double delta, int W, int ngl,
-                                const double* __restrict__ zs, const double* __restrict__ ws,
+                                const double* __restrict__ na, const double* __restrict__ nw,
                                 const double* __restrict__ phitab, double* __restrict__ rowacc,
                                 double* __restrict__ part);
 __global__ void k_local_otf_reduce(int M, int nblk_rows, int periodic, const int* __restrict__ blk_end,

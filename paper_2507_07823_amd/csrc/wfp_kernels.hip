@@ -1018,38 +1018,51 @@ __device__ __forceinline__ void sym_node(double Dm, double span, int mmin, doubl
                                          const double* __restrict__ sgk, const double* __restrict__ rh,
                                          const LagFactors<P>& lf, double& acc_a, double& acc_c) {
   const double s = fma(Dm, na_q, Wd);         // W - (W - D)(1 + z_q)/2
-  // 1 - phi(s dt) from the table: piece pc covers s in [pc, pc + 1) / pw
+  // window piece: pc covers s in [pc, pc + 1) / pw (its coefficients are
+  // loaded here and used last, so the loads overlap the interpolation)
   const double v = s * pw;
   int pc = (int)v;
   pc = pc < 0 ? 0 : (pc >= kPhiPieces ? kPhiPieces - 1 : pc);
-  const double t = 2.0 * (v - pc) - 1.0;
   const double* c = tab + pc * (kPhiDeg + 1);
-  double ph = c[kPhiDeg];
+  double cf[kPhiDeg + 1];
 #pragma unroll
-  for (int k = kPhiDeg - 1; k >= 0; --k) ph = fma(ph, t, c[k]);
-  const double om = span * nw_q * (1.0 - ph);
+  for (int k = 0; k <= kPhiDeg; ++k) cf[k] = c[k];
+  const double t = 2.0 * (v - pc) - 1.0;
   int m0 = (int)floor(s) - P / 2 + 1;
   if (m0 < mmin) m0 = mmin;
   // s rounds to W only for d within an ulp of delta (zero weight): keep the
   // stencil inside lags 0 .. W + P/2 - 1
   const int mtop = (int)Wd - P / 2;
   if (m0 > mtop) m0 = mtop;
+  const double* sp = sgk + m0 * kOtfChunk;
+  const double* rp = rh + m0;
+  double fa[P], fc[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    fa[r] = sp[r * kOtfChunk];
+    fc[r] = rp[r];
+  }
   const double u = s - m0;
   double A[P], B[P];
   A[0] = 1.0;
 #pragma unroll
   for (int r = 0; r < P - 1; ++r) A[r + 1] = A[r] * fma(u, lf.ca[r], lf.cb[r]);
-  B[P - 1] = om;
+  B[P - 1] = 1.0;
 #pragma unroll
   for (int r = P - 2; r >= 0; --r) B[r] = B[r + 1] * fma(u, lf.cc[r], lf.cd[r]);
-  const double* sp = sgk + m0 * kOtfChunk;
-  const double* rp = rh + m0;
+  double pa = 0.0, pcl = 0.0;
 #pragma unroll
   for (int r = 0; r < P; ++r) {
     const double w = A[r] * B[r];
-    acc_a = fma(w, sp[r * kOtfChunk], acc_a);
-    acc_c = fma(w, rp[r], acc_c);
+    pa = fma(w, fa[r], pa);
+    pcl = fma(w, fc[r], pcl);
   }
+  double ph = cf[kPhiDeg];
+#pragma unroll
+  for (int k = kPhiDeg - 1; k >= 0; --k) ph = fma(ph, t, cf[k]);
+  const double om = span * nw_q * (1.0 - ph);
+  acc_a = fma(om, pa, acc_a);
+  acc_c = fma(om, pcl, acc_c);
 }
 
 template <int P>
@@ -1057,27 +1070,25 @@ __global__ void __launch_bounds__(1024)
 k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end, const int* __restrict__ blk_end,
                 const int64_t* __restrict__ part_off, int nblk_rows, const double* __restrict__ xs,
                 const double* __restrict__ hist, int periodic, double dt, double delta, int W, int ngl,
-                const double* __restrict__ zs, const double* __restrict__ ws, const double* __restrict__ phitab,
+                const double* __restrict__ na, const double* __restrict__ nw, const double* __restrict__ phitab,
                 double* __restrict__ rowacc, double* __restrict__ part) {
   extern __shared__ double sg[];                              // [NQ][kOtfChunk], then [kOtfRows][kOtfChunk]
   __shared__ double tab[kPhiPieces * (kPhiDeg + 1)];
   __shared__ double rh[kOtfRows][kMaxOtfLags + 1];
-  __shared__ double na[64], nw[64];
+  __shared__ int64_t slot[kMaxOtfLags + 1];                   // row offset of lag m's density level
   const int b = xcd_block(blockIdx.x, gridDim.x);
   if (b >= nblk_rows) return;                                 // padding block: nothing to do
   double* colp = sg + (size_t)NQ * kOtfChunk;                 // per-wavefront column sums of a chunk
   for (int i = threadIdx.x; i < kPhiPieces * (kPhiDeg + 1); i += blockDim.x) tab[i] = phitab[i];
-  for (int i = threadIdx.x; i < ngl; i += blockDim.x) {
-    na[i] = 0.5 * (1.0 + zs[i]);
-    nw[i] = 0.5 * ws[i];
-  }
+  for (int m = threadIdx.x; m < NQ; m += blockDim.x) slot[m] = (int64_t)mod_slot(L - m, NH) * M;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int j0 = b * kOtfRows;
   const int j = j0 + wv;
   const bool row = j < M;
+  __syncthreads();
   for (int e = threadIdx.x; e < kOtfRows * NQ; e += blockDim.x) {
     const int w = e / NQ, m = e - w * NQ;
-    rh[w][m] = (m >= 1 && j0 + w < M) ? hist[(int64_t)mod_slot(L - m, NH) * M + (j0 + w)] : 0.0;
+    rh[w][m] = (m >= 1 && j0 + w < M) ? hist[slot[m] + (j0 + w)] : 0.0;
   }
   for (int k = threadIdx.x; k < kOtfChunk; k += blockDim.x) sg[k] = 0.0;   // lag 0
   const long long uend = blk_end[b];                          // unwrapped end of the block's sources
@@ -1093,9 +1104,9 @@ k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end
     __syncthreads();   // the previous chunk is no longer read
     for (int e = threadIdx.x; e < (NQ - 1) * kOtfChunk; e += blockDim.x) {
       const int m = e / kOtfChunk + 1, k = e - (m - 1) * kOtfChunk;
-      const long long u = cb + k;
+      const long long u = cb + k;                             // < 2M
       double v = 0.0;
-      if (u < uend) v = hist[(int64_t)mod_slot(L - m, NH) * M + (int)(u % M)];
+      if (u < uend) v = hist[slot[m] + (u < M ? u : u - M)];
       sg[m * kOtfChunk + k] = v;
     }
     for (int e = threadIdx.x; e < kOtfRows * kOtfChunk; e += blockDim.x) colp[e] = 0.0;
@@ -1103,7 +1114,7 @@ k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end
     const long long a0 = (long long)j > cb ? (long long)j : cb;
     const long long a1 = my1 < cb + kOtfChunk ? my1 : cb + kOtfChunk;
     for (long long ua = a0 + lane; ua < a1; ua += 64) {
-      double d = fabs(xa - xs[(int)(ua % M)]);
+      double d = fabs(xa - xs[ua < M ? (int)ua : (int)(ua - M)]);
       if (periodic && d > kPi) d = kTwoPi - d;
       const bool on = d < delta;
       const int k = (int)(ua - cb);

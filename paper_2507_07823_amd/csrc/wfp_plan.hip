@@ -652,6 +652,16 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     P->phitab = P->alloc<double>(tab.size());
     upload(P->otf_z, za, s);
     upload(P->otf_w, wa, s);
+    // node fractions (1 + z)/2 and half weights w/2 of the symmetric kernel
+    std::vector<double> nfr(P->ngl), nhw(P->ngl);
+    for (int q = 0; q < P->ngl; ++q) {
+      nfr[q] = 0.5 * (1.0 + za[q]);
+      nhw[q] = 0.5 * wa[q];
+    }
+    P->otf_na = P->alloc<double>(P->ngl);
+    P->otf_nw = P->alloc<double>(P->ngl);
+    upload(P->otf_na, nfr, s);
+    upload(P->otf_nw, nhw, s);
     upload(P->phitab, tab, s);
     P->half_beta = hb_d;
   } else {
@@ -1138,7 +1148,7 @@ void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
 #define WFP_OTF(PP)                                                                                               \
   hipExtLaunchKernelGGL(k_local_otf_sym<PP>, dim3(nblocks), dim3(64 * kOtfRows), lds, s, ea, nullptr, 0,          \
                         (int)P->M, P->NH, P->NQ, L, P->otf_up_end, P->otf_blk_end, P->otf_part_off, P->otf_nblk,  \
-                        P->xs, hist, periodic, P->dt, P->delta, P->W, P->ngl, P->otf_z, P->otf_w, P->phitab,    \
+                        P->xs, hist, periodic, P->dt, P->delta, P->W, P->ngl, P->otf_na, P->otf_nw, P->phitab,  \
                         P->otf_rowacc, P->otf_part)
   switch (P->p) {
     case 2: WFP_OTF(2); break;
