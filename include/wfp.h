@@ -59,7 +59,7 @@ typedef int32_t wfp_status;
 #define WFP_PERIODIC 0      /* periodic box [-pi, pi) (Section 2) */
 #define WFP_FREE_SPACE 1    /* free space via outgoing windowing (Section 4.4) */
 
-#define WFP_ABI_VERSION 5
+#define WFP_ABI_VERSION 6
 
 typedef struct wfp_plan wfp_plan;
 
@@ -166,6 +166,22 @@ wfp_status wfp_plan_info(const wfp_plan* plan, wfp_info* info);
  * Errors: WFP_EINVAL, WFP_EHIP, WFP_ENONFINITE, WFP_ENOMEM. */
 wfp_status wfp_run(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t save_every,
                    double* u_recv_out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): wfp_run that never
+ * allocates.  The block of driving-data levels that wfp_run allocates on its
+ * first call (and the finite-check flag) lives instead in the library's
+ * static scratch array, 8 MiB per GPU, held by each GPU the library runs on
+ * until the process ends.  Same arguments, outputs and stream ordering as
+ * wfp_run.  Limits: M <= 1048544 springs (one level of driving data must fit);
+ * plans with checkpoint_every > 0 (their checkpoints are allocated) and plans
+ * with stage timing on (it creates events) are refused with WFP_EINVAL.  The
+ * scratch array is shared by every call on one GPU and keeps the last call's
+ * contents; each call recomputes what it reads, but calls that overlap on one
+ * GPU (other threads, or other streams not ordered with this one) race.
+ * Errors: WFP_EINVAL, WFP_EHIP, WFP_ENONFINITE. */
+wfp_status wfp_run_noalloc(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t save_every,
+                           double* u_recv_out);
 
 /* March n_steps levels like wfp_run, with the driving data supplied by the
  * caller instead of computed from the plan's incident packets: any incident

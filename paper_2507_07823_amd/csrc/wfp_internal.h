@@ -167,6 +167,11 @@ struct wfp_plan {
   // driving data of g_chunk consecutive levels from g_lvl0 (row L - g_lvl0)
   double* gbuf = nullptr;
   int g_chunk = 0;
+  // set only during wfp_run_noalloc: the driving-data block and the finite
+  // flag in the library's static per-device scratch array instead
+  double* g_ext = nullptr;
+  int g_ext_chunk = 0;
+  int* flag_ext = nullptr;
   int64_t g_lvl0 = -1;
   double* loc = nullptr;        // local sum of lags >= 1, per row
   // solve tiles

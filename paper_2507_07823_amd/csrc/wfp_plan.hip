@@ -8,6 +8,28 @@ namespace wfpi {
 thread_local std::string g_last_error;
 }  // namespace wfpi
 
+// Device memory of wfp_run_noalloc: the block of driving-data levels (and the
+// finite-check flag in its first 256 bytes), one copy per GPU, held until the
+// process ends.  Host code uses the per-device address from
+// hipGetSymbolAddress, never the array's name.
+constexpr size_t kScratchDoubles = (size_t)1 << 20;            // 8 MiB
+constexpr size_t kScratchHead = 32;                             // doubles before the driving data
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static std::map<int, double*> g_scratch_ptr;
+
+// Address of the current device's scratch array (looked up once per device).
+static double* device_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) throw Error{WFP_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+  g_scratch_ptr[device] = (double*)ptr;
+  return (double*)ptr;
+}
+
 // Masked streams per (device, split), shared by the plans that use the split
 // and destroyed when the last of them lets go (each masked stream holds a
 // hardware queue until it is destroyed).
@@ -1242,19 +1264,25 @@ void launch_local_big(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
 // reader of the previous chunk is ordered before it on that stream, or
 // before the solve the stream has waited for).
 const double* driving_row(wfp_plan* P, hipStream_t s, int64_t L) {
-  if (!P->gbuf) {
-    P->g_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(8 << 20) / P->M));
-    P->gbuf = P->alloc<double>((size_t)P->g_chunk * P->M);
+  double* buf = P->g_ext;
+  int chunk = P->g_ext_chunk;
+  if (!buf) {
+    if (!P->gbuf) {
+      P->g_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(8 << 20) / P->M));
+      P->gbuf = P->alloc<double>((size_t)P->g_chunk * P->M);
+    }
+    buf = P->gbuf;
+    chunk = P->g_chunk;
   }
-  if (P->g_lvl0 < 0 || L < P->g_lvl0 || L >= P->g_lvl0 + P->g_chunk) {
+  if (P->g_lvl0 < 0 || L < P->g_lvl0 || L >= P->g_lvl0 + chunk) {
     const Packets pk{P->npk, P->boundary == WFP_PERIODIC ? 1 : 0, P->packets};
     int pp = 1;
     while (pp < P->npk) pp *= 2;
-    hipLaunchKernelGGL(k_incident_levels, dim3(nblk(P->M, 256 / pp), P->g_chunk), dim3(256), 0, s, (int)P->M, L,
-                       P->dt, P->xs, P->beta, pk, pp, P->gbuf);
+    hipLaunchKernelGGL(k_incident_levels, dim3(nblk(P->M, 256 / pp), chunk), dim3(256), 0, s, (int)P->M, L,
+                       P->dt, P->xs, P->beta, pk, pp, buf);
     P->g_lvl0 = L;
   }
-  return P->gbuf + (L - P->g_lvl0) * P->M;
+  return buf + (L - P->g_lvl0) * P->M;
 }
 
 void launch_local_lag1(wfp_plan* P, hipStream_t s, const double* hist, int64_t L) {
@@ -1831,16 +1859,17 @@ namespace {
 // for the plan's stream.
 void check_finite(wfp_plan* P) {
   hipStream_t s = P->stream;
-  if (!P->finite_flag) P->finite_flag = P->alloc<int>(1);
-  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, P->finite_flag, 1, 0);
+  if (!P->flag_ext && !P->finite_flag) P->finite_flag = P->alloc<int>(1);
+  int* flag = P->flag_ext ? P->flag_ext : P->finite_flag;
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, flag, 1, 0);
   const double* newest = P->hist + (int64_t)((P->level - 1) % P->NH) * P->M;
   const int64_t na = 2 * P->npos;
   hipLaunchKernelGGL(k_check_finite, dim3(std::min<int64_t>(nblk(P->M, 256), 1024)), dim3(256), 0, s, newest,
-                     P->M, (const double*)P->alpha, na, P->finite_flag);
+                     P->M, (const double*)P->alpha, na, flag);
   hipLaunchKernelGGL(k_check_finite, dim3(std::min<int64_t>(nblk(na, 256), 1024)), dim3(256), 0, s,
-                     (const double*)P->dalpha, na, nullptr, 0, P->finite_flag);
+                     (const double*)P->dalpha, na, nullptr, 0, flag);
   int bad = 0;
-  HIPCHK(hipMemcpyAsync(&bad, P->finite_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (bad) fail(WFP_ENONFINITE, "non-finite densities or mode state after level " + std::to_string(P->level));
 }
@@ -1857,6 +1886,43 @@ wfp_status wfp_run(wfp_plan* P, int64_t n_steps, double* sigma_out, int64_t save
   }
   return guard([&] {
     HIPCHK(hipSetDevice(P->device));
+    run_levels(P, n_steps, sigma_out, sigma_out ? save_every : 1, u_recv_out);
+    if (P->check_finite && n_steps > 0) check_finite(P);
+  });
+}
+
+wfp_status wfp_run_noalloc(wfp_plan* P, int64_t n_steps, double* sigma_out, int64_t save_every,
+                           double* u_recv_out) {
+  if (!P || n_steps < 0) {
+    g_last_error = "bad plan or step count";
+    return WFP_EINVAL;
+  }
+  if (sigma_out && save_every < 1) {
+    g_last_error = "save_every must be >= 1";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(P->device));
+    if (P->ckpt_every > 0) fail(WFP_EINVAL, "wfp_run_noalloc: plans that store checkpoints allocate them; use wfp_run");
+    if (P->profiling) fail(WFP_EINVAL, "wfp_run_noalloc: stage timing creates events; use wfp_run");
+    if ((size_t)P->M > kScratchDoubles - kScratchHead)
+      fail(WFP_EINVAL, "wfp_run_noalloc: M above " + std::to_string(kScratchDoubles - kScratchHead) +
+                           " springs (the scratch holds one level of driving data)");
+    double* sc = device_scratch(P->device);
+    struct Restore {
+      wfp_plan* P;
+      ~Restore() {
+        P->g_ext = nullptr;
+        P->g_ext_chunk = 0;
+        P->flag_ext = nullptr;
+        P->g_lvl0 = -1;
+      }
+    } restore{P};
+    // another call may have left other data there: the block is recomputed
+    P->g_ext = sc + kScratchHead;
+    P->g_ext_chunk = (int)std::min<int64_t>(256, (int64_t)((kScratchDoubles - kScratchHead) / (size_t)P->M));
+    P->flag_ext = (int*)sc;
+    P->g_lvl0 = -1;
     run_levels(P, n_steps, sigma_out, sigma_out ? save_every : 1, u_recv_out);
     if (P->check_finite && n_steps > 0) check_finite(P);
   });

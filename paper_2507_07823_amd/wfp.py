@@ -78,6 +78,8 @@ def load_library():
     lib.wfp_plan_info.restype = ctypes.c_int32
     lib.wfp_run.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
     lib.wfp_run.restype = ctypes.c_int32
+    lib.wfp_run_noalloc.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
+    lib.wfp_run_noalloc.restype = ctypes.c_int32
     lib.wfp_run_driven.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_int64, vp]
     lib.wfp_run_driven.restype = ctypes.c_int32
     lib.wfp_local_part.argtypes = [vp, vp]
@@ -215,6 +217,19 @@ class Plan:
         if u_recv_out is not None:
             assert u_recv_out.numel() >= n_steps * self.info["R"]
         _check(self._lib.wfp_run(self._h, int(n_steps), _ptr(sigma_out), int(save_every), _ptr(u_recv_out)))
+
+    def run_noalloc(self, n_steps, sigma_out=None, save_every=1, u_recv_out=None):
+        """As run(), through wfp_run_noalloc (no device allocation in the call)."""
+        for t in (sigma_out, u_recv_out):
+            if t is not None:
+                assert t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous() and t.is_cuda
+        if sigma_out is not None:
+            rows = (n_steps + save_every - 1) // save_every
+            assert sigma_out.numel() >= rows * self.info["M"]
+        if u_recv_out is not None:
+            assert u_recv_out.numel() >= n_steps * self.info["R"]
+        _check(self._lib.wfp_run_noalloc(self._h, int(n_steps), _ptr(sigma_out), int(save_every),
+                                         _ptr(u_recv_out)))
 
     def march(self, n_steps, save_every=1, receivers=True):
         """Allocate outputs and march; returns (sigma rows, receiver values or None)."""

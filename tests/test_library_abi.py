@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib, root):
 
 
 def test_abi_version_and_strings(lib):
-    assert lib.wfp_abi_version() == 5
+    assert lib.wfp_abi_version() == 6
     assert lib.wfp_status_string(wfp.WFP_EDOMAIN) == b"outside the supported domain"
     assert lib.wfp_status_string(wfp.WFP_ENONFINITE) == b"non-finite values in the march"
 
