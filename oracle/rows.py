@@ -21,14 +21,30 @@ from .local import free_distance, local_weights, periodic_distance
 TWO_PI = 2.0 * math.pi
 
 
-def spectrum_direct(x, sigma, K, chunk=512):
-    """S_k for k = 0..K of densities sigma at positions x (eq. (densco))."""
+def spectrum_direct(x, sigma, K, chunk=512, workers=1, modes=None):
+    """S_k for k = 0..K (or the given modes) of densities sigma at positions x
+    (eq. (densco)).
+    The springs are taken in chunks (in `workers` threads for large M) whose
+    partial sums are added in chunk order."""
     x = np.asarray(x, dtype=np.float64)
     sigma = np.asarray(sigma, dtype=np.float64)
-    k = np.arange(K + 1, dtype=np.float64)
-    out = np.zeros(K + 1, np.complex128)
-    for a in range(0, x.size, chunk):
-        out += np.exp(1j * np.outer(k, x[a:a + chunk])) @ sigma[a:a + chunk]
+    k = np.arange(K + 1, dtype=np.float64) if modes is None else np.asarray(modes, dtype=np.float64)
+    starts = list(range(0, x.size, chunk))
+
+    def part(a):
+        ph = np.outer(k, x[a:a + chunk])
+        sg = sigma[a:a + chunk]
+        return np.cos(ph) @ sg + 1j * (np.sin(ph) @ sg)
+
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            parts = list(ex.map(part, starts))
+    else:
+        parts = map(part, starts)
+    out = np.zeros(k.size, np.complex128)
+    for v in parts:
+        out += v
     return out / TWO_PI
 
 

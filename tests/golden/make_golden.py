@@ -6,6 +6,8 @@
     python tests/golden/make_golden.py midgrid
     python tests/golden/make_golden.py clumped
     python tests/golden/make_golden.py clumped_level
+    python tests/golden/make_golden.py growth_multiband
+    python tests/golden/make_golden.py growth_clump
 
 multiband: the periodic multiband workload (M = 1e4, dt = 1e-3, 1e4 steps)
 marched by the oracle for levels 0..n_steps; stores sigma at a few levels for
@@ -40,6 +42,12 @@ boundary projection is due: the new spectrum of the newest density level and
 alpha, alpha' after the level (every mode), and at 96 sampled springs (48
 uniform, 48 clumped) the explicit local sum, the right-hand side b_j of the
 per-step system and the nearby entries of its matrix row.
+
+growth_multiband, growth_clump: the homogeneous march (zero driving) from a
+seeded unit-normal density history (zero spectra ring and modes) of the
+multiband workload with beta log-uniform in [0.1, 100] (1600 levels), and of
+the first clump of the full-size clumped workload (1000 springs) with beta ~
+U[1, 10] (400 levels): max |sigma| at every level and sigma of the last.
 """
 import os
 import sys
@@ -172,6 +180,39 @@ def clumped_level():
                         nb_idx=np.concatenate(nb_idx), nb_val=np.concatenate(nb_val), nb_ptr=np.array(nb_ptr))
 
 
+GROWTH_STATE_SEED = 31
+
+
+def growth_problem(which):
+    """(x, beta, Params, levels) of a homogeneous-march growth check."""
+    if which == "multiband":
+        p = workloads.multiband_periodic(beta_max=100.0)
+        return p["x"], p["beta"], Params(dt=p["dt"]), 1600
+    p = workloads.clumped_free_space(clump_beta=(1.0, 10.0))
+    n_un = int(round(0.9 * p["x"].size))
+    sel = np.arange(n_un, n_un + 1000)
+    return p["x"][sel], p["beta"][sel], Params(dt=p["dt"], boundary=1), 400
+
+
+def growth(which):
+    x, beta, prm, n = growth_problem(which)
+    M = x.size
+    t0 = time.time()
+    o = Oracle(x, beta, prm, lambda t: np.zeros(M))
+    print(f"precompute {time.time() - t0:.1f}s", flush=True)
+    hist = np.random.default_rng(GROWTH_STATE_SEED).standard_normal((prm.m_max, M))
+    o.set_state(dict(L=0, hist=hist, ring=np.zeros((prm.W, prm.K + 1), np.complex128),
+                     alpha=np.zeros(prm.K + 1, np.complex128), dalpha=np.zeros(prm.K + 1, np.complex128)))
+    smax = []
+    for L in range(n):
+        s, _ = o.step()
+        smax.append(float(np.max(np.abs(s))))
+        if L % 100 == 0:
+            print(f"level {L} {time.time() - t0:.0f}s max|sigma| {smax[-1]:.3e}", flush=True)
+    np.savez_compressed(os.path.join(HERE, f"growth_{which}.npz"), seed=GROWTH_STATE_SEED, levels=n,
+                        sigma_max=np.array(smax), sigma_last=s)
+
+
 def start_level(prm, t):
     """First level >= t / dt of the form k rbc_period - 1, so the boundary
     correction fires after the first step."""
@@ -218,4 +259,5 @@ def balanced():
 
 if __name__ == "__main__":
     {"multiband": multiband, "balanced": balanced, "longgrid": longgrid, "midgrid": midgrid,
-     "clumped": clumped, "clumped_level": clumped_level}[sys.argv[1]]()
+     "clumped": clumped, "clumped_level": clumped_level,
+     "growth_multiband": lambda: growth("multiband"), "growth_clump": lambda: growth("clump")}[sys.argv[1]]()
