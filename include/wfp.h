@@ -124,6 +124,10 @@ typedef struct {
   int32_t local_mode;          /* 1: stored local weights, 2: evaluated on the fly */
   int32_t reserved;
   int64_t n_weights_lag1;      /* nonzero stored local weights of lag 1 (part of n_weights_nonzero) */
+  int32_t n_solve_tiles;       /* solve_mode 0: LDS tiles of the Jacobi solve (long nearby runs) */
+  int32_t n_direct_tiles;      /* solve_mode 0: groups of small nearby runs solved by stored inverses */
+  int32_t sweep_wave;          /* solve_mode 1: 1 when a wavefront sweeps each row (long rows), else 0 */
+  int32_t reserved2;
 } wfp_info;
 
 /* Stages of one level, for wfp_get_profile. */
@@ -262,8 +266,8 @@ wfp_status wfp_reset(wfp_plan* plan);
 wfp_status wfp_plan_autotune(wfp_plan* plan, int32_t trial_levels, int32_t* overlap_cus);
 
 /* Batched form (not in the paper): n independent periodic problems, each
- * with its own x, beta, incident field, receivers and dt, marched in
- * lockstep.  Each stage of a level is one launch over an (instance, block) work
+ * with its own x, beta, incident field, receivers, dt and level count,
+ * marched in lockstep.  Each stage of a level is one launch over an (instance, block) work
  * list and the whole level is one HIP graph replayed per level; every instance
  * computes what its own plan would, to rounding (the same kernel bodies; a plan
  * marched on its own adds the lag-1 part of its local sum separately).
@@ -285,6 +289,16 @@ wfp_status wfp_plan_autotune(wfp_plan* plan, int32_t trial_levels, int32_t* over
  *                     `stream` waits for it.  A call that passes receiver
  *                     outputs (or follows one that did) first waits for the
  *                     batch's earlier work.
+ *   wfp_batch_set_levels  per-instance level counts (each problem's own N_t):
+ *                     instance i computes levels 0 .. n_levels[i] - 1 and then
+ *                     leaves every launch of the level (its blocks return at
+ *                     once; its state stays at its last level) while the
+ *                     others go on.  n_levels is a HOST array of n entries;
+ *                     an entry <= 0, or n_levels NULL, means no limit.  Stays
+ *                     in force across runs and resets.  sigma_final then holds
+ *                     each instance's own last level; receiver rows of levels
+ *                     at or beyond an instance's end are not written.  Waits
+ *                     for the batch's earlier work.
  *   wfp_batch_reset   all instances back to level 0.
  *   wfp_batch_autotune  from level 0: times trial_levels levels for each launch
  *                     shape of the local sum (4 or 8 rows per block, with or
@@ -299,6 +313,7 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
                             wfp_batch** out);
 wfp_status wfp_batch_run(wfp_batch* batch, int64_t n_steps, double* const* u_recv_out,
                          double* const* sigma_final);
+wfp_status wfp_batch_set_levels(wfp_batch* batch, const int64_t* n_levels);
 wfp_status wfp_batch_reset(wfp_batch* batch);
 wfp_status wfp_batch_autotune(wfp_batch* batch, int32_t trial_levels, int32_t* rows_per_block,
                               int32_t* xcd_remap);

@@ -15,6 +15,8 @@ struct wfp_batch {
   int64_t level = 0;
   int64_t* level_d = nullptr;
   InstDesc* desc_d = nullptr;
+  std::vector<InstDesc> desc_h;        // host copy of the descriptor table
+  std::vector<int64_t> ends;           // per instance: levels L < ends[i] are computed
   // work lists (device) and their lengths
   int2 *wl_inc = nullptr, *wl_loc4 = nullptr, *wl_loc8 = nullptr, *wl_a = nullptr, *wl_b = nullptr,
        *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr, *wl_otf = nullptr,
@@ -247,6 +249,9 @@ void build_batch(wfp_batch* B) {
     for (int it = 1; it < P->iters; ++it) cnt[it] = (int)lst.size();
   }
   B->lds_c = B->lds_a;
+  B->ends.assign(n, INT64_MAX);
+  for (int i = 0; i < n; ++i) desc[i].end = INT64_MAX;
+  B->desc_h = desc;
   B->desc_d = B->alloc<InstDesc>(n);
   HIPCHK(hipMemcpyAsync(B->desc_d, desc.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice, B->bs));
   B->wl_inc = upload_work(B, inc, 1, B->n_inc);
@@ -379,18 +384,23 @@ void capture(wfp_batch* B) {
   HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
 }
 
+// Each instance's own level: the batch level, or its end once reached.
+void sync_plan_levels(wfp_batch* B) {
+  for (size_t i = 0; i < B->plans.size(); ++i) B->plans[i]->level = std::min(B->level, B->ends[i]);
+}
+
 void set_level(wfp_batch* B, int64_t L) {
   B->level = L;
   HIPCHK(hipMemcpyAsync(B->level_d, &B->level, sizeof(int64_t), hipMemcpyHostToDevice, B->bs));
   HIPCHK(hipStreamSynchronize(B->bs));
-  for (wfp_plan* P : B->plans) P->level = L;
+  sync_plan_levels(B);
 }
 
 void run_batch(wfp_batch* B, int64_t n) {
   capture(B);
   for (int64_t i = 0; i < n; ++i) HIPCHK(hipGraphLaunch(B->exec, B->bs));
   B->level += n;
-  for (wfp_plan* P : B->plans) P->level = B->level;
+  sync_plan_levels(B);
 }
 
 void reset_batch(wfp_batch* B) {
@@ -526,8 +536,9 @@ wfp_status wfp_batch_run(wfp_batch* B, int64_t n_steps, double* const* u_recv_ou
     if (sigma_final && B->level > 0) {
       for (size_t i = 0; i < B->plans.size(); ++i) {
         const wfp_plan* P = B->plans[i];
-        if (!sigma_final[i]) continue;
-        const double* last = P->hist + (int64_t)(((B->level - 1) % P->NH + P->NH) % P->NH) * P->M;
+        if (!sigma_final[i] || P->level < 1) continue;
+        // the instance's own last level (its end level, once reached)
+        const double* last = P->hist + (int64_t)(((P->level - 1) % P->NH + P->NH) % P->NH) * P->M;
         hipLaunchKernelGGL(k_unsort, dim3(nblk(P->M, 256)), dim3(256), 0, B->bs, (int)P->M, P->perm, last,
                            sigma_final[i]);
       }
@@ -535,6 +546,26 @@ wfp_status wfp_batch_run(wfp_batch* B, int64_t n_steps, double* const* u_recv_ou
     }
     HIPCHK(hipEventRecord(B->ev_out, B->bs));
     HIPCHK(hipStreamWaitEvent(B->user_stream, B->ev_out, 0));
+  });
+}
+
+wfp_status wfp_batch_set_levels(wfp_batch* B, const int64_t* n_levels) {
+  if (!B) {
+    g_last_error = "NULL batch";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(B->device));
+    const size_t n = B->plans.size();
+    // the captured levels read the table: earlier replays finish first
+    HIPCHK(hipStreamSynchronize(B->bs));
+    for (size_t i = 0; i < n; ++i) {
+      const int64_t e = (n_levels && n_levels[i] > 0) ? n_levels[i] : INT64_MAX;
+      B->ends[i] = e;
+      B->desc_h[i].end = e;
+    }
+    HIPCHK(hipMemcpy(B->desc_d, B->desc_h.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice));
+    sync_plan_levels(B);
   });
 }
 

@@ -254,6 +254,7 @@ __global__ void k_unsort(int M, const int* __restrict__ perm, const double* __re
 struct InstDesc {
   int M, NQ, NH, W, nf, width, n1, n2, iters, npk, pp, ext_max, global_solve;
   int64_t K, npos;
+  int64_t end;                 // the instance computes levels L < end (its own N_t)
   double dt;
   FftPlan f1, f2;
   const double *xs, *beta, *packets;

@@ -2014,6 +2014,7 @@ __global__ void __launch_bounds__(256) kb_incident(BatchLaunch b) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   const Packets pk{d.npk, 1, d.packets};
   k_incident_body(d.M, (double)(*b.level) * d.dt, d.xs, d.beta, pk, d.pp, 0, d.ginc, w.y);
 }
@@ -2022,6 +2023,7 @@ __global__ void __launch_bounds__(512) kb_local(BatchLaunch b, int xcd) {
   const int2 w = b.work[xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   k_local_rhs_body(d.M, d.NQ, d.NH, *b.level, 1, d.NQ, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, nullptr, d.loc,
                    w.y);
 }
@@ -2031,6 +2033,7 @@ __global__ void __launch_bounds__(256) kb_local_g8(BatchLaunch b) {
   const int2 w = b.work[xcd_block(blockIdx.x, gridDim.x)];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   k_local_rhs_body<8>(d.M, d.NQ, d.NH, *b.level, 1, d.NQ, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, nullptr,
                       d.loc, w.y);
 }
@@ -2039,6 +2042,7 @@ __global__ void __launch_bounds__(256) kb_local_g4(BatchLaunch b) {
   const int2 w = b.work[xcd_block(blockIdx.x, gridDim.x)];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   k_local_rhs_body<4>(d.M, d.NQ, d.NH, *b.level, 1, d.NQ, d.nb_start, d.rowbase, d.acx, d.Qc, d.hist, nullptr,
                       d.loc, w.y);
 }
@@ -2047,6 +2051,7 @@ __global__ void __launch_bounds__(1024) kb_local_otf(BatchLaunch b) {
   const int2 w = b.work[xcd_block(blockIdx.x, gridDim.x)];
   if (w.x < 0) return;   // block-uniform
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   k_local_otf_body<8>(d.M, d.NH, d.NQ, *b.level, d.nb_start, d.nb_count, d.xs, d.hist, d.half_beta, 1, d.dt,
                       d.delta, d.W, d.ngl, d.otf_z, d.otf_w, d.phitab, d.loc, w.y);
 }
@@ -2055,6 +2060,7 @@ __global__ void __launch_bounds__(256) kb_hist_a(BatchLaunch b) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   const double* sig = d.hist + (int64_t)mod_slot(*b.level - 1, d.NH) * d.M;
   const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
   k_hist_a_body(d.f2, d.n1, sig, d.M, d.cstart, d.ccount, d.swoff, d.sw, d.tw, d.T1, none, w.y);
@@ -2064,6 +2070,7 @@ __global__ void __launch_bounds__(512) kb_hist_b(BatchLaunch b) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   k_hist_b_body(0, d.f1, d.n2, d.K, d.W, *b.level, d.npos, d.T1, d.tw, d.tw1, d.dk1, d.dk2, d.pk, d.qk, d.rot, d.ring,
                 d.alpha, d.dalpha, d.ybuf, d.V, kFirGroups, w.y);
 }
@@ -2072,6 +2079,7 @@ __global__ void __launch_bounds__(256) kb_hist_c(BatchLaunch b) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   k_hist_c_body(d.f2, d.n1, d.V, d.tw, (double2*)d.grid2, w.y);
 }
 
@@ -2079,6 +2087,7 @@ __global__ void __launch_bounds__(256) kb_solve_direct(BatchLaunch b) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
   k_solve_direct_body(d.M, d.dt_g0, d.dt_n, d.dt_p0, d.pt_cs, d.pt_cn, d.pt_inv, d.inv, d.ginc, d.loc, d.i0s, d.iw,
                       d.beta, d.grid2, d.nf, d.width, slot, nullptr, nullptr, w.y);
@@ -2088,6 +2097,7 @@ __global__ void __launch_bounds__(256) kb_solve(BatchLaunch b) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
   k_solve_body(d.M, d.iters, d.ext_max, d.tile_r0, d.tile_el, d.tile_g0, d.tile_left, d.tile_n, d.srow_g,
                d.srow_dinv, d.srow_ptr, d.scol, d.sval, d.ginc, d.loc, d.i0s, d.iw, d.beta, d.grid2, d.nf, d.width,
@@ -2098,6 +2108,7 @@ __global__ void __launch_bounds__(256) kb_solve_rhs(BatchLaunch b) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
   k_solve_rhs_body(d.M, d.ginc, d.loc, d.beta, d.i0s, d.iw, d.grid2, d.nf, d.width, d.g_dinv, d.g_rhs,
                    d.iters > 1 ? d.g_xa : slot, w.y);
@@ -2110,6 +2121,7 @@ __global__ void __launch_bounds__(256) kb_jacobi_sweep(BatchLaunch b, int it) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   if (it >= d.iters) return;
   double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
   const double* xin = (it & 1) ? d.g_xa : d.g_xb;
@@ -2123,6 +2135,7 @@ __global__ void __launch_bounds__(256) kb_jacobi_sweep_wave(BatchLaunch b, int i
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   if (it >= d.iters) return;
   double* slot = d.hist + (int64_t)mod_slot(*b.level, d.NH) * d.M;
   const double* xin = (it & 1) ? d.g_xa : d.g_xb;
@@ -2139,6 +2152,7 @@ __global__ void __launch_bounds__(256) kb_receivers(BatchLaunch b, double* const
   double* out = uout[w.x];
   if (!out) return;
   const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   const int64_t L = *b.level;
   k_receivers_body(d.R, d.M, d.NQ, d.NH, L, d.rnb_start, d.rnb_count, d.rqoff, d.Qr, d.hist, d.ri0s, d.riw,
                    d.grid2, d.nf, d.width, out + (L - *level0) * d.R, w.y);

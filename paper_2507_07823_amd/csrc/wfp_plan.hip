@@ -1820,6 +1820,9 @@ wfp_status wfp_plan_info(const wfp_plan* P, wfp_info* info) {
   info->overlap_cus = P->overlap_cus;
   info->local_mode = P->otf ? 2 : 1;
   info->n_weights_lag1 = P->n_weights_lag1;
+  info->n_solve_tiles = P->solve_global ? 0 : P->ntile;
+  info->n_direct_tiles = P->solve_global ? 0 : P->n_direct_tiles;
+  info->sweep_wave = (P->solve_global && P->g_wave) ? 1 : 0;
   return WFP_OK;
 }
 

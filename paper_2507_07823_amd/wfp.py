@@ -52,7 +52,9 @@ class Info(ctypes.Structure):
                 ("delta", ctypes.c_double), ("b", ctypes.c_double), ("solve_contraction", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("n_weights_nonzero", ctypes.c_int64),
                 ("n_weights_stored", ctypes.c_int64), ("solve_mode", ctypes.c_int32), ("overlap_cus", ctypes.c_int32),
-                ("local_mode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_weights_lag1", ctypes.c_int64)]
+                ("local_mode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_weights_lag1", ctypes.c_int64),
+                ("n_solve_tiles", ctypes.c_int32), ("n_direct_tiles", ctypes.c_int32),
+                ("sweep_wave", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -103,6 +105,8 @@ def load_library():
     lib.wfp_batch_create.restype = ctypes.c_int32
     lib.wfp_batch_run.argtypes = [vp, ctypes.c_int64, vp, vp]
     lib.wfp_batch_run.restype = ctypes.c_int32
+    lib.wfp_batch_set_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.wfp_batch_set_levels.restype = ctypes.c_int32
     lib.wfp_batch_reset.argtypes = [vp]
     lib.wfp_batch_reset.restype = ctypes.c_int32
     lib.wfp_batch_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -417,6 +421,15 @@ class Batch:
         sf = pointers(sigma_final, lambda i: self.sizes[i])
         ur = pointers(u_recv, lambda i: n_steps * self.receivers[i])
         _check(self._lib.wfp_batch_run(self._h, int(n_steps), ur, sf))
+
+    def set_levels(self, n_levels=None):
+        """Per-instance level counts (each instance's own N_t; None or an
+        entry <= 0: no limit)."""
+        if n_levels is None:
+            _check(self._lib.wfp_batch_set_levels(self._h, None))
+            return
+        arr = (ctypes.c_int64 * self.n)(*[int(v) for v in n_levels])
+        _check(self._lib.wfp_batch_set_levels(self._h, arr))
 
     def reset(self):
         _check(self._lib.wfp_batch_reset(self._h))

@@ -51,10 +51,11 @@ def multiband_periodic(seed=2, M=10_000, dt=1e-3, n_steps=10_000, beta_max=10.0)
     sum of 8 Gaussian wave packets (width 0.05) with angular carriers 50..500,
     dt = 1e-3, 1e4 steps, periodic box (the throughput case).
 
-    beta_max defaults to 10: with stiffnesses up to 100 at this density the
-    discrete march (p = 8) has a growing mode on clusters of nearby stiff
-    springs (about +0.5% per step), so no two FP64 runs can agree over 1e4
-    steps; up to 10 it is stable.  The per-step work does not depend on beta."""
+    beta_max defaults to 10: with stiffnesses up to 100 (the configuration as
+    specified) the discrete march (p = 8) of this periodic system has a growing
+    mode (about +0.6 % per level once it dominates), so no two FP64 runs can
+    agree over 1e4 levels; up to 10 it is stable.  The per-level work does not
+    depend on beta."""
     r = _rng(seed)
     x = r.uniform(-PI + 1.2, PI, M)
     beta = np.exp(r.uniform(math.log(0.1), math.log(beta_max), M))
@@ -74,11 +75,11 @@ def clumped_free_space(seed=3, M=1_000_000, dt=5e-4, n_steps=4000, n_clumps=100,
     """Free space, M springs uniform in Omega with a fraction in tight Gaussian
     clumps, Gaussian-modulated plane wave of angular frequency 1000 entering
     from the left.  Uniform springs: beta ~ U[1, 10].  Clumped springs: beta ~
-    U[clump_beta]; with U[1, 10] a clump of 1000 springs within 1e-3 acts like
-    one spring of stiffness ~5500, far above what the discrete march (p = 8,
-    dt = 5e-4) keeps stable (~800), and the densities grow ~25x per 100 levels
-    in any exact implementation of the scheme; U[0.1, 1] keeps each clump
-    near 550."""
+    U[clump_beta]; at M = 1e6 a clump holds 1000 springs within ~1e-3 (total
+    stiffness ~5500 with U[1, 10]), and the discrete march (p = 8, dt = 5e-4)
+    of such a clump grows by ~x360 per 100 levels in any exact implementation
+    of the scheme; U[0.1, 1] keeps it stable.  At M = 1e4 (10 springs per
+    clump) U[1, 10] is stable."""
     r = _rng(seed)
     lo, hi = -PI + margin, PI - margin
     n_cl = int(round(frac * M))

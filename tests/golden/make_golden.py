@@ -8,6 +8,10 @@
     python tests/golden/make_golden.py clumped_level
     python tests/golden/make_golden.py growth_multiband
     python tests/golden/make_golden.py growth_clump
+    python tests/golden/make_golden.py adjoint_dense
+    python tests/golden/make_golden.py disordered
+    python tests/golden/make_golden.py batch_recipe
+    python tests/golden/make_golden.py batch_paths
 
 multiband: the periodic multiband workload (M = 1e4, dt = 1e-3, 1e4 steps)
 marched by the oracle for levels 0..n_steps; stores sigma at a few levels for
@@ -29,6 +33,22 @@ the spectrum are stored every 256th mode.
 midgrid: the same at the time step of the study's M = 1e5 (K = 51200, a
 boundary grid split 200 x 256 over workgroups), every 32nd mode.
 
+batch_recipe: the batched workload's instances with M <= 1e4 among its first
+24 (seed (4, i)), each marched by the oracle for its own level count
+N_i = 2000 - 125 (i mod 8): sampled springs at levels 499, 999, 1499 (those
+below N_i), every spring at its last level N_i - 1, and max |sigma|.
+
+batch_paths: five periodic instances built so that a batch runs every
+batched kernel path: a chain of 600 springs closer than dt (tiled solve),
+400 springs inside 0.01 (global sweeps, a wavefront per row), 300 springs
+with local weights on the fly and receivers, the small periodic case with
+receivers, 1500 random springs with receivers; own level counts
+300, 260, 220, 300, 180: every spring at the last level, receivers at every
+level.
+
+disordered: the same three levels for the long disordered run at M = 1e3
+(Section 6.3: dt = 1.308e-4, K = 20480, p = 8), every 16th mode.
+
 clumped: the clumped free-space distribution at M = 1e4 (10 % of the springs
 in 100 Gaussian clumps of width 1e-3, beta ~ U[1, 10] for all springs, the
 omega = 1000 packet, dt = 5e-4, K = 6250, boundary projection every 36
@@ -48,6 +68,12 @@ seeded unit-normal density history (zero spectra ring and modes) of the
 multiband workload with beta log-uniform in [0.1, 100] (1600 levels), and of
 the first clump of the full-size clumped workload (1000 springs) with beta ~
 U[1, 10] (400 levels): max |sigma| at every level and sigma of the last.
+
+adjoint_dense: the oracle's gradient of a receiver misfit (Section 4.2's
+march transposed, oracle/adjoint.py) for 400 springs inside an interval of
+length 0.01 at dt = 1e-3 (about 80 nearby sources per row: the GPU solves it
+by global sweeps), three receivers, 400 levels, target from beta perturbed
+by 5 %: dJ/du, the receiver values and both gradients.
 """
 import os
 import sys
@@ -213,6 +239,32 @@ def growth(which):
                         sigma_max=np.array(smax), sigma_last=s)
 
 
+def adjoint_dense_problem():
+    rng = np.random.default_rng(21)
+    M = 400
+    x = rng.uniform(0.5, 0.51, M)
+    beta = rng.uniform(0.1, 1.0, M)
+    return dict(x=x, beta=beta, packets=np.array([[1.0, 0.2, 0.03, 0.0, 0.0]]), boundary=0,
+                x_recv=np.array([0.49, 0.505, 0.53]), dt=1e-3), 400
+
+
+def adjoint_dense():
+    from oracle.adjoint import AdjointOracle, misfit_loss
+    p, n = adjoint_dense_problem()
+    prm = Params(dt=p["dt"])
+    bstar = p["beta"] * (1 + 0.05 * np.random.default_rng(52).standard_normal(p["beta"].size))
+    t0 = time.time()
+    target = AdjointOracle(p["x"], bstar, p["packets"], prm, p["x_recv"]).forward(n)
+    a = AdjointOracle(p["x"], p["beta"], p["packets"], prm, p["x_recv"])
+    u = a.forward(n)
+    J, dJdu = misfit_loss(u, target, p["dt"])
+    gb, gx = a.gradient(dJdu)
+    print(f"{time.time() - t0:.0f}s J={J:.3e} max|u|={np.max(np.abs(u)):.3e} max|gb|={np.max(np.abs(gb)):.3e} "
+          f"max|gx|={np.max(np.abs(gx)):.3e}", flush=True)
+    np.savez_compressed(os.path.join(HERE, "adjoint_dense.npz"), levels=n, u=u, dJdu=dJdu, grad_beta=gb,
+                        grad_x=gx)
+
+
 def start_level(prm, t):
     """First level >= t / dt of the form k rbc_period - 1, so the boundary
     correction fires after the first step."""
@@ -252,12 +304,96 @@ def midgrid():
     state_steps(workloads.long_grid_free_space(spread=0.2, study_M=100_000), "midgrid_state_steps.npz", 12, 2.9, 32)
 
 
+BATCH_RECIPE_FIRST = 24
+
+
+def batch_recipe_cases():
+    """(index, problem, level count) of the recipe instances with M <= 1e4."""
+    insts = workloads.batch_instances(n=BATCH_RECIPE_FIRST)
+    return [(i, p, 2000 - 125 * (i % 8)) for i, p in enumerate(insts) if p["x"].size <= 10_000]
+
+
+def _batch_recipe_one(case):
+    i, p, n = case
+    o = Oracle(p["x"], p["beta"], Params(dt=p["dt"]), incident_driving(p["x"], p["beta"], p["packets"], True))
+    M = p["x"].size
+    sample = np.random.default_rng(1000 + i).choice(M, min(M, 200), replace=False)
+    sample.sort()
+    rows, smax = {}, 0.0
+    t0 = time.time()
+    for L in range(n):
+        s, _ = o.step()
+        smax = max(smax, float(np.max(np.abs(s))))
+        if L in (499, 999, 1499):
+            rows[L] = s[sample].copy()
+    print(f"instance {i} M={M} dt={p['dt']} levels={n} {time.time() - t0:.0f}s max|sigma| {smax:.3e}", flush=True)
+    return i, n, sample, rows, s, smax
+
+
+def batch_recipe():
+    from multiprocessing import Pool
+    cases = batch_recipe_cases()
+    with Pool(6) as pool:
+        res = pool.map(_batch_recipe_one, cases, chunksize=1)
+    out = {"index": np.array([r[0] for r in res]), "levels": np.array([r[1] for r in res]),
+           "sigma_max": np.array([r[5] for r in res])}
+    for i, n, sample, rows, last, _ in res:
+        out[f"sample_{i}"] = sample
+        out[f"last_{i}"] = last
+        for L, v in rows.items():
+            out[f"at{L}_{i}"] = v
+    np.savez_compressed(os.path.join(HERE, "batch_recipe.npz"), **out)
+
+
+def batch_paths_cases():
+    """(problem, level count, local mode) of the batch-paths instances."""
+    rng = np.random.default_rng(61)
+    out = []
+    x = -0.5 + 0.6e-3 * np.arange(600) + rng.uniform(-1e-4, 1e-4, 600)
+    out.append((dict(x=x, beta=rng.uniform(1.0, 10.0, 600), packets=np.array([[1.0, -0.65, 0.03, 0.0, 0.0]]),
+                     boundary=0, dt=1e-3, x_recv=np.zeros(0)), 300, 0))
+    x = rng.uniform(0.5, 0.51, 400)
+    out.append((dict(x=x, beta=rng.uniform(0.1, 1.0, 400), packets=np.array([[1.0, 0.35, 0.03, 0.0, 0.0]]),
+                     boundary=0, dt=1e-3, x_recv=np.zeros(0)), 260, 0))
+    x = rng.uniform(-np.pi + 1.2, np.pi, 300)
+    out.append((dict(x=x, beta=rng.uniform(1.0, 10.0, 300), packets=np.array([[1.0, -np.pi + 0.9, 0.05, 0.0, 0.0]]),
+                     boundary=0, dt=2e-3, x_recv=np.array([-1.5, 0.0, 1.5])), 220, 2))
+    p = workloads.small_periodic()
+    out.append((dict(p, x_recv=np.linspace(0.3, 2.0, 5)), 300, 0))
+    x = rng.uniform(-np.pi + 1.2, np.pi, 1500)
+    out.append((dict(x=x, beta=rng.uniform(1.0, 10.0, 1500), packets=np.array([[1.0, -np.pi + 0.9, 0.06, 0.0, 0.0]]),
+                     boundary=0, dt=5e-3, x_recv=np.array([-1.0, 1.0])), 180, 0))
+    return out
+
+
+def batch_paths():
+    out = {}
+    for i, (p, n, _) in enumerate(batch_paths_cases()):
+        t0 = time.time()
+        o = Oracle(p["x"], p["beta"], Params(dt=p["dt"]), incident_driving(p["x"], p["beta"], p["packets"], True),
+                   x_recv=p["x_recv"] if p["x_recv"].size else None)
+        sig, u = o.run(n)
+        out[f"last_{i}"] = sig[-1]
+        out[f"smax_{i}"] = float(np.max(np.abs(sig)))
+        if u is not None:
+            out[f"recv_{i}"] = u
+        print(f"path instance {i} M={p['x'].size} levels={n} {time.time() - t0:.0f}s "
+              f"max|sigma| {out[f'smax_{i}']:.3e}", flush=True)
+    np.savez_compressed(os.path.join(HERE, "batch_paths.npz"), **out)
+
+
+def disordered():
+    state_steps(workloads.disordered_long(1000), "disordered_state_steps.npz", 14, 2.0, 16)
+
+
 def balanced():
     state_steps(workloads.paper_balanced_free_space(BALANCED_M), "balanced_state_steps.npz",
                 BALANCED_STATE_SEED, 1.2, 8)
 
 
 if __name__ == "__main__":
-    {"multiband": multiband, "balanced": balanced, "longgrid": longgrid, "midgrid": midgrid,
+    {"multiband": multiband, "balanced": balanced, "longgrid": longgrid, "midgrid": midgrid, "disordered": disordered,
+     "batch_recipe": batch_recipe, "batch_paths": batch_paths,
      "clumped": clumped, "clumped_level": clumped_level,
-     "growth_multiband": lambda: growth("multiband"), "growth_clump": lambda: growth("clump")}[sys.argv[1]]()
+     "growth_multiband": lambda: growth("multiband"), "growth_clump": lambda: growth("clump"),
+     "adjoint_dense": adjoint_dense}[sys.argv[1]]()

@@ -184,3 +184,80 @@ def test_gradient_full_size_beta_directional(wfp):
     # the loss is ~1e-3 and this derivative ~5e-8, so differences of J sit
     # ~1e-9 above the loss's rounding noise: the check holds to ~1e-6
     assert abs(fd - an) <= 1e-5 * abs(an)
+
+
+def test_gradient_dense_nearby_coupling(wfp):
+    """400 springs inside an interval of length 0.01 at dt = 1e-3: about 80
+    nearby sources per row, so the per-step solve (and its transpose in the
+    gradient pass) takes the global-sweep path (solve_mode 1).  Against the
+    oracle's reverse sweep stored in tests/golden/adjoint_dense.npz."""
+    import os
+    import torch
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "adjoint_dense.npz"))
+    rng = np.random.default_rng(21)
+    M = 400
+    x = rng.uniform(0.5, 0.51, M)
+    beta = rng.uniform(0.1, 1.0, M)
+    p = dict(x=x, beta=beta, packets=np.array([[1.0, 0.2, 0.03, 0.0, 0.0]]), boundary=0,
+             x_recv=np.array([0.49, 0.505, 0.53]), dt=1e-3)
+    n = int(g["levels"])
+    plan = wfp.Plan(p, p["dt"], checkpoint_every=100)
+    assert plan.info["solve_mode"] == 1
+    u = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    plan.run(n, None, 1, u)
+    gb, gx = plan.gradient(torch.from_numpy(np.ascontiguousarray(g["dJdu"])).cuda())
+    torch.cuda.synchronize()
+    eu, eb, ex = rho(u.cpu().numpy(), g["u"]), rho(gb.cpu().numpy(), g["grad_beta"]), rho(gx.cpu().numpy(), g["grad_x"])
+    plan.close()
+    say(f"adjoint dense cluster: M={M} levels={n} solve_mode=1: rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  "
+        f"rho(x) = {ex:.2e}")
+    assert eu < TOL and eb < TOL and ex < TOL
+
+
+def test_gradient_full_size_position_directional(wfp):
+    """At the adjoint workload's full size (M = 1e5, R = 64) the position
+    gradient against central differences of the GPU's own loss (its forward
+    march is parity-tested) over 1000 levels with checkpoints every 250,
+    along a smooth displacement field d_j = sin(1.3 x_j + 0.4): neighbours
+    move nearly together, so pair distances change by at most ~h delta and
+    the step h can be large enough for the differences of J (~1e-3, rounding
+    noise ~1e-16 relative over the march) to resolve the derivative.  Pairs
+    crossing the nearby/intermediate switch d = dt change their weights only
+    at the level of the interpolation error there.  Differences at h and h/2
+    are extrapolated (Richardson)."""
+    import torch
+    from paper_2507_07823_amd import workloads
+    p = workloads.adjoint_periodic()
+    n, every, h = 1000, 250, 1e-4
+    x0, M, R = p["x"], p["x"].size, p["x_recv"].size
+    dt = p["dt"]
+    d = np.sin(1.3 * x0 + 0.4)
+    say(f"adjoint full size (positions): M={M} R={R} levels={n}, smooth direction, h={h}")
+
+    def loss(x):
+        q = dict(p, x=x)
+        plan = wfp.Plan(q, dt, checkpoint_every=every)
+        u = torch.empty((n, R), dtype=torch.float64, device="cuda")
+        plan.run(n, None, 1, u)
+        J = 0.5 * dt * float((u * u).sum())
+        return plan, u, J
+
+    plan, u, _ = loss(x0)
+    _, gx = plan.gradient(dt * u, positions=True)
+    gx = gx.cpu().numpy()
+    plan.close()
+
+    def central(hh):
+        pl, _, jp = loss(x0 + hh * d)
+        pl.close()
+        pl, _, jm = loss(x0 - hh * d)
+        pl.close()
+        return (jp - jm) / (2 * hh)
+
+    f1, f2 = central(h), central(h / 2)
+    fd = (4 * f2 - f1) / 3
+    an = float(gx @ d)
+    say(f"  directional derivative: gradient {an:.12e}  central differences {f1:.12e} {f2:.12e}"
+        f"  extrapolated {fd:.12e}  rel {abs(fd - an) / abs(an):.2e}")
+    assert abs(an) > 0
+    assert abs(fd - an) <= 1e-4 * abs(an)

@@ -68,13 +68,19 @@ def test_balanced_small_full_march(wfp):
     assert r < TOL
 
 
-@pytest.mark.parametrize("case", ["balanced", "midgrid", "longgrid"])
+@pytest.mark.parametrize("case", ["balanced", "midgrid", "longgrid", "disordered"])
 def test_long_grids_from_state(wfp, case):
+    """Three levels from a seeded mid-run state (the boundary projection due
+    after the first) against stored oracle levels: the scaling study at
+    M = 2e4, its longest grids (K = 51200, 524288) at 400 springs, and the
+    long disordered run of Section 6.3 at M = 1e3 (K = 20480, p = 8)."""
     import torch
     g = np.load(os.path.join(GOLDEN_DIR, f"{case}_state_steps.npz"))
     M = int(g["M"])
     if case == "balanced":
         p = workloads.paper_balanced_free_space(M)
+    elif case == "disordered":
+        p = workloads.disordered_long(M)
     elif case == "midgrid":
         p = workloads.long_grid_free_space(M, spread=0.2, study_M=100_000)
     else:
