@@ -235,7 +235,7 @@ def test_gradient_full_size_position_directional(wfp):
     say(f"adjoint full size (positions): M={M} R={R} levels={n}, smooth direction, h={h}")
 
     def loss(x):
-        q = dict(p, x=x)
+        q = dict(p, x=np.mod(x + np.pi, 2 * np.pi) - np.pi)     # the box is periodic
         plan = wfp.Plan(q, dt, checkpoint_every=every)
         u = torch.empty((n, R), dtype=torch.float64, device="cuda")
         plan.run(n, None, 1, u)
