@@ -357,40 +357,47 @@ def adjoint_leg(levels, every):
             "gradient_over_plain_time": t_bwd / t_fwd, "finite": ok}
 
 
-def batch_leg(n_inst, levels, m_max, trial_levels=3):
+def batch_leg(n_inst, levels, m_max, trial_levels=3, uneven=True):
     """The batched form on uneven periodic instances (M log-uniform in
     [100, m_max], dt in {1e-3, 2e-3, 5e-3}, beta ~ U[1, 10], one random pulse
     each), autotuned, against the same instances marched one plain plan at a
-    time."""
+    time.  With `uneven`, instance i marches its own level count
+    levels - (i mod 4) levels / 8 (wfp_batch_set_levels), the plain plans the
+    same counts; the rate counts each instance's own levels."""
     import torch
     from paper_2507_07823_amd import wfp, workloads
     insts = workloads.batch_instances(n=n_inst, n_steps=levels, m_range=(100, m_max))
+    ends = [levels - (i % 4) * levels // 8 if uneven else levels for i in range(len(insts))]
+    work = int(sum(p["x"].size * e for p, e in zip(insts, ends)))
     total_m = int(sum(p["x"].size for p in insts))
     t0 = time.perf_counter()
     b = wfp.Batch(insts, [p["dt"] for p in insts])
     setup = time.perf_counter() - t0
     n_otf = sum(1 for i in range(b.n) if b.plan(i).info["local_mode"] == 2)
     shape = b.autotune(trial_levels)
+    b.set_levels(ends)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.run(levels)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    b.set_levels(None)
     b.reset()
     plans = [b.plan(i) for i in range(b.n)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for pl in plans:
-        pl.run(levels)
+    for pl, e in zip(plans, ends):
+        pl.run(e)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     b.reset()
     b.close()
     return {"workload": "batched periodic instances", "instances": n_inst, "M_range": [100, m_max],
-            "total_M": total_m, "levels": levels, "plan_setup_s": setup, "instances_on_the_fly": n_otf,
+            "total_M": total_m, "levels": levels, "level_counts": "own" if uneven else "equal",
+            "scatterer_steps": work, "plan_setup_s": setup, "instances_on_the_fly": n_otf,
             "autotuned": {"rows_per_block": shape[0], "xcd_remap": shape[1]},
-            "batched_scatterer_steps_per_s": total_m * levels / t_batch,
-            "plain_one_by_one_scatterer_steps_per_s": total_m * levels / t_plain,
+            "batched_scatterer_steps_per_s": work / t_batch,
+            "plain_one_by_one_scatterer_steps_per_s": work / t_plain,
             "batched_over_plain": t_plain / t_batch}
 
 
@@ -725,7 +732,7 @@ def main():
     ap.add_argument("--batch-max-m", type=int, default=10_000,
                     help="largest M of the batched leg (1e5 is the full recipe; its large instances then "
                          "evaluate their local weights on the fly and a level takes about a second)")
-    ap.add_argument("--batch-full-levels", type=int, default=3,
+    ap.add_argument("--batch-full-levels", type=int, default=50,
                     help="levels of a second batched leg over the full M range [100, 1e5] (0 skips it)")
     ap.add_argument("--no-convergence", action="store_true", help="skip the manufactured-solution leg")
     ap.add_argument("--no-filters", action="store_true", help="skip the spring-filter leg")
@@ -736,7 +743,7 @@ def main():
                     help="with --disordered-full: the runs to make (1 = dt, 2 = dt/2; both give the error estimate)")
     ap.add_argument("--disordered-levels", type=int, default=20000,
                     help="levels timed at M = 1e4 in the disordered leg (negative skips the leg)")
-    ap.add_argument("--balanced-levels", type=int, default=1000,
+    ap.add_argument("--balanced-levels", type=int, default=500,
                     help="levels per size of the free-space scaling-study leg (0 skips it)")
     ap.add_argument("--balanced-only", action="store_true",
                     help="only run the scaling-study leg (for counter runs of its kernels) and print its result")

@@ -20,7 +20,9 @@ struct wfp_batch {
   // work lists (device) and their lengths
   int2 *wl_inc = nullptr, *wl_loc4 = nullptr, *wl_loc8 = nullptr, *wl_a = nullptr, *wl_b = nullptr,
        *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr, *wl_otf = nullptr,
-       *wl_swt = nullptr, *wl_sww = nullptr, *wl_g8 = nullptr, *wl_g4 = nullptr, *wl_rcv = nullptr;
+       *wl_swt = nullptr, *wl_sww = nullptr, *wl_g8 = nullptr, *wl_g4 = nullptr, *wl_rcv = nullptr,
+       *wl_otfr = nullptr;
+  int n_otfr = 0;
   int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0, n_otf = 0,
       n_swt = 0, n_sww = 0, n_g8 = 0, n_g4 = 0, n_rcv = 0;
   // receiver outputs of the current run: per instance a device pointer (or
@@ -147,6 +149,14 @@ InstDesc describe(const wfp_plan* P) {
   d.otf_w = P->otf_w;
   d.phitab = P->phitab;
   d.half_beta = P->half_beta;
+  d.otf_up_end = P->otf_up_end;
+  d.otf_blk_end = P->otf_blk_end;
+  d.otf_part_off = P->otf_part_off;
+  d.otf_nblk = P->otf_nblk;
+  d.otf_na = P->otf_na;
+  d.otf_nw = P->otf_nw;
+  d.otf_part = P->otf_part;
+  d.otf_rowacc = P->otf_rowacc;
   d.R = (int)P->R;
   d.rnb_start = P->rnb_start;
   d.rnb_count = P->rnb_count;
@@ -197,7 +207,7 @@ void build_batch(wfp_batch* B) {
   std::vector<InstDesc> desc(n);
   // otf, loc4, loc8, g8, g4: (instance, blocks); g8 / g4: instances whose
   // lag blocks are short (the plan's lanes per lag), 4 rows per block
-  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf, g8, g4, rcv;
+  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf, otfr, g8, g4, rcv;
   for (int i = 0; i < n; ++i) {
     const wfp_plan* P = B->plans[i];
     desc[i] = describe(P);
@@ -207,7 +217,8 @@ void build_batch(wfp_batch* B) {
     if (P->otf) {
       if (P->p != 8) fail(WFP_EDOMAIN, "batched on-the-fly local sums take p = 8");
       otf.push_back(make_int2(i, (int)nblk(M, kOtfRows)));
-      B->lds_otf = std::max(B->lds_otf, (size_t)(P->NQ - 1) * kOtfChunk * sizeof(double));
+      for (int bb = 0; bb < (int)nblk(M, 256); ++bb) otfr.push_back(make_int2(i, bb));
+      B->lds_otf = std::max(B->lds_otf, (size_t)(P->NQ + kOtfRows) * kOtfChunk * sizeof(double));
     } else if (P->lgrp == 8) {
       g8.push_back(make_int2(i, (int)nblk(M, 4)));
     } else if (P->lgrp == 4) {
@@ -264,6 +275,7 @@ void build_batch(wfp_batch* B) {
   B->wl_til = upload_work(B, til, 1, B->n_til);
   B->wl_rows = upload_work(B, rows, 1, B->n_rows);
   B->wl_otf = upload_work(B, xcd_balanced(otf), 8, B->n_otf);
+  B->wl_otfr = upload_work(B, otfr, 1, B->n_otfr);
   B->wl_g8 = upload_work(B, xcd_balanced(g8), 8, B->n_g8);
   B->wl_g4 = upload_work(B, xcd_balanced(g4), 8, B->n_g4);
   B->wl_rcv = upload_work(B, rcv, 1, B->n_rcv);
@@ -323,6 +335,8 @@ void enqueue_level(wfp_batch* B) {
   if (B->n_otf) {
     bl.work = B->wl_otf;
     hipLaunchKernelGGL(kb_local_otf, dim3(B->n_otf), dim3(64 * kOtfRows), B->lds_otf, s, bl);
+    bl.work = B->wl_otfr;
+    hipLaunchKernelGGL(kb_local_otf_reduce, dim3(B->n_otfr), dim3(256), 0, s, bl);
   }
   HIPCHK(hipStreamWaitEvent(s, B->ev_join, 0));
   if (B->n_dir) {

@@ -146,6 +146,29 @@ void source_range(const std::vector<double>& xs, double x, double r, bool period
   count = (int)(hi - lo);
 }
 
+bool upper_ranges(const std::vector<int>& nbs, const std::vector<int>& nbc, int rows, std::vector<int>& up,
+                  std::vector<int>& blk_end, std::vector<int64_t>& part_off, int64_t& total) {
+  const int64_t M = (int64_t)nbs.size();
+  const int64_t nb = (M + rows - 1) / rows;
+  up.assign(M, 0);
+  blk_end.assign(nb, 0);
+  part_off.assign(nb, 0);
+  for (int64_t j = 0; j < M; ++j) {
+    const int64_t st = nbs[j] <= j ? nbs[j] : (int64_t)nbs[j] - M;
+    const int64_t e = st + nbc[j];
+    if (!(st <= j && j < e && e <= j + M)) return false;
+    up[j] = (int)e;
+    blk_end[j / rows] = std::max(blk_end[j / rows], (int)e);
+  }
+  total = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    if (b > 0 && blk_end[b] < blk_end[b - 1]) return false;
+    part_off[b] = total;
+    total += (int64_t)blk_end[b] - b * rows;
+  }
+  return true;
+}
+
 bool is_pow2_pow5(int64_t n) {
   if (n < 1) return false;
   while (n % 2 == 0) n /= 2;

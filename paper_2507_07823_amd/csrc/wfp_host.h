@@ -53,6 +53,18 @@ inline double pair_distance(double a, double c, bool periodic) {
 void source_range(const std::vector<double>& xs, double x, double r, bool periodic,
                   bool inclusive, int& start, int& count);
 
+// Upper source ranges of the local sum that takes each unordered pair once.
+// Row j (sorted order) has the neighbour range [nbs[j], nbs[j] + nbc[j])
+// (mod M), which contains j; its upper range is the unwrapped [j, up[j]): the
+// sources from j upward (past M - 1 the indices continue at 0).  Per block of
+// `rows` consecutive rows: blk_end[b] = the largest up[j] of its rows, and
+// part_off[b] = the offset of its column sums (one per source u in
+// [rows b, blk_end[b])); total = their sum.  Returns false when a range does
+// not contain its row or the block ends decrease (the sums over covering
+// blocks rely on non-decreasing ends).
+bool upper_ranges(const std::vector<int>& nbs, const std::vector<int>& nbc, int rows, std::vector<int>& up,
+                  std::vector<int>& blk_end, std::vector<int64_t>& part_off, int64_t& total);
+
 // 2^a 5^b test and the radix sequence (4s, at most one 2, then 5s) used by
 // the LDS FFT.
 bool is_pow2_pow5(int64_t n);

@@ -58,14 +58,6 @@ constexpr int kPhiPieces = 512, kPhiDeg = 5;
 constexpr int kOtfRows = 16, kOtfChunk = 256;
 constexpr int kMaxOtfLags = 48;      // lags 1 .. NQ - 1 of a row staged by the symmetric local sum
 template <int P>
-__global__ void k_local_otf(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start,
-                            const int* __restrict__ nb_count, const double* __restrict__ xs,
-                            const double* __restrict__ hist, const double* __restrict__ scale, int periodic,
-                            double dt, double delta, int W, int ngl, const double* __restrict__ zs,
-                            const double* __restrict__ ws, const double* __restrict__ phitab,
-                            double* __restrict__ out);
-
-template <int P>
 __global__ void k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end,
                                 const int* __restrict__ blk_end, const int64_t* __restrict__ part_off,
                                 int nblk_rows, const double* __restrict__ xs, const double* __restrict__ hist,
@@ -282,11 +274,16 @@ struct InstDesc {
   const int *g_ptr, *g_col;
   const double *g_val, *g_dinv;
   double *g_rhs, *g_xa, *g_xb;
-  // local weights on the fly (p = 8)
+  // local weights on the fly (p = 8), each unordered pair once
   int otf, ngl;
   double delta;
   const int* nb_count;
   const double *otf_z, *otf_w, *phitab, *half_beta;
+  const int *otf_up_end, *otf_blk_end;
+  const int64_t* otf_part_off;
+  int otf_nblk;
+  const double *otf_na, *otf_nw;
+  double *otf_part, *otf_rowacc;
   // receivers
   int R;
   const int *rnb_start, *rnb_count, *ri0s;
@@ -307,6 +304,7 @@ __global__ void kb_local(BatchLaunch b, int xcd);
 __global__ void kb_local_g8(BatchLaunch b);
 __global__ void kb_local_g4(BatchLaunch b);
 __global__ void kb_local_otf(BatchLaunch b);
+__global__ void kb_local_otf_reduce(BatchLaunch b);
 __global__ void kb_hist_a(BatchLaunch b);
 __global__ void kb_hist_b(BatchLaunch b);
 __global__ void kb_hist_c(BatchLaunch b);

@@ -765,212 +765,6 @@ k_local_deriv2(int M, int NQ, int NH, const int* __restrict__ nb_start, const in
   }
 }
 
-// Local sum of lags m >= 1 with the weights evaluated on the fly (when the
-// stored weights would not fit): for every source l within delta,
-//   sum_i om_i(d) p_i(s_i),   p_i = the degree-(P-1) interpolant of the
-// history sigma_l^{L-m} (m >= 1; the lag-0 value taken as 0, it belongs to the
-// implicit solve) on the P lags from m0_i = max(m_min, floor(s_i) - P/2 + 1),
-// which equals sum_{m>=1} Q_m(d) sigma_l^{L-m} of the stored path regrouped by
-// quadrature node (Section 4.1: node lag s_i = W - (W - d/dt)(1 + z_i)/2,
-// weight ((delta - d)/2) w_i (1 - phi(s_i dt))).  One wavefront per target
-// row, lanes over sources.  Nodes come in order of decreasing s_i, so the
-// stencil start never grows; each lane keeps the Newton divided differences
-// T_k = f[m0 .. m0 + k] of its current stencil in registers and, per step
-// down, updates them from one older level:
-//   T'_0 = f(m0 - 1),  T'_k = (T_{k-1} - T'_{k-1}) / k,
-// and evaluates p(s) = T_0 + T_1 u + T_2 u (u - 1) + ... with u = s - m0.
-// phi comes from a piecewise polynomial table (kPhiPieces pieces of degree
-// kPhiDeg over s in [0, W], staged in LDS).
-// State of one (target, source) pair while its nodes are walked.  `k` is the
-// source's column in the LDS stage of density levels.
-template <int P>
-struct OtfPair {
-  double Dm, span, pair;
-  double T[P];
-  int k, mmin, mc;
-};
-
-// Lags 1 .. kOtfLags of kOtfChunk sources are staged per step (lag 0 is 0).
-
-template <int P>
-__device__ __forceinline__ void otf_begin(OtfPair<P>& a, bool active, int k, double d, double dt, double delta,
-                                          double Wd) {
-  // an inactive pair walks the nodes with zero weight on valid data
-  a.pair = 0.0;
-  a.mc = 0x7fffffff;
-  a.k = active ? k : 0;
-  a.Dm = active ? d / dt - Wd : -0.5 * Wd;    // inactive: D = W/2, nodes inside (0, W)
-  a.mmin = (active && d < dt) ? 0 : 1;
-  a.span = active ? delta - d : 0.0;
-}
-
-template <int P>
-__device__ __forceinline__ void otf_node(OtfPair<P>& a, double na_q, double nw_q, const double* __restrict__ tab,
-                                         double Wd, double pw, const double* __restrict__ sg) {
-  const double s = fma(a.Dm, na_q, Wd);       // W - (W - D)(1 + z_q)/2
-  // 1 - phi(s dt) from the table: piece pc covers s in [pc, pc + 1) / pw
-  const double v = s * pw;
-  int pc = (int)v;
-  pc = pc < 0 ? 0 : (pc >= kPhiPieces ? kPhiPieces - 1 : pc);
-  const double t = 2.0 * (v - pc) - 1.0;
-  const double* c = tab + pc * (kPhiDeg + 1);
-  double ph = c[kPhiDeg];
-#pragma unroll
-  for (int k = kPhiDeg - 1; k >= 0; --k) ph = fma(ph, t, c[k]);
-  const double om = a.span * nw_q * (1.0 - ph);
-  int m0 = (int)floor(s) - P / 2 + 1;
-  if (m0 < a.mmin) m0 = a.mmin;
-  // s rounds to W only for d within an ulp of delta (zero weight): keep the
-  // stencil inside lags 0 .. W + P/2 - 1
-  const int mtop = (int)Wd - P / 2;
-  if (m0 > mtop) m0 = mtop;
-  // staged level of lag m >= 1 at sg[(m - 1) * kOtfChunk + k]
-  if (a.mc == 0x7fffffff) {
-    a.mc = m0;
-#pragma unroll
-    for (int r = 0; r < P; ++r) {
-      const int m = m0 + r;
-      a.T[r] = (m >= 1) ? sg[(m - 1) * kOtfChunk + a.k] : 0.0;
-    }
-#pragma unroll
-    for (int k = 1; k < P; ++k)
-#pragma unroll
-      for (int r = P - 1; r >= k; --r) a.T[r] = (a.T[r] - a.T[r - 1]) * (1.0 / k);
-  }
-  while (a.mc > m0) {   // one level older at the front of the stencil
-    --a.mc;
-    double prev = a.T[0];
-    a.T[0] = (a.mc >= 1) ? sg[(a.mc - 1) * kOtfChunk + a.k] : 0.0;
-#pragma unroll
-    for (int k = 1; k < P; ++k) {
-      const double old = a.T[k];
-      a.T[k] = (prev - a.T[k - 1]) * (1.0 / k);
-      prev = old;
-    }
-  }
-  const double u = s - a.mc;
-  double pv = a.T[P - 1];
-#pragma unroll
-  for (int k = P - 2; k >= 0; --k) pv = fma(pv, u - k, a.T[k]);
-  a.pair = fma(om, pv, a.pair);
-}
-
-// kOtfRows consecutive target rows per block (one wavefront each) share the
-// sources: the union of their neighbour ranges is walked in chunks of
-// kOtfChunk sources whose density levels (lags 1..NQ-1) are staged in LDS
-// once per block; each row takes the chunk's sources inside its own range,
-// two per lane walking their nodes together.
-template <int P>
-__device__ __forceinline__ void k_local_otf_body(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start,
-                                                 const int* __restrict__ nb_count, const double* __restrict__ xs,
-                                                 const double* __restrict__ hist, const double* __restrict__ scale,
-                                                 int periodic, double dt, double delta, int W, int ngl,
-                                                 const double* __restrict__ zs, const double* __restrict__ ws,
-                                                 const double* __restrict__ phitab, double* __restrict__ out,
-                                                 int lb) {
-  extern __shared__ double sg[];                              // [NQ - 1][kOtfChunk]
-  __shared__ double tab[kPhiPieces * (kPhiDeg + 1)];
-  __shared__ double na[64], nw[64];
-  __shared__ int rs[kOtfRows], rn[kOtfRows];
-  __shared__ long long ub[2];
-  for (int i = threadIdx.x; i < kPhiPieces * (kPhiDeg + 1); i += blockDim.x) tab[i] = phitab[i];
-  for (int i = threadIdx.x; i < ngl; i += blockDim.x) {
-    na[i] = 0.5 * (1.0 + zs[i]);
-    nw[i] = 0.5 * ws[i];
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int j0 = lb * kOtfRows;
-  const int j = j0 + wv;
-  const bool row = j < M;
-  if (lane == 0) {
-    rs[wv] = row ? nb_start[j] : 0;
-    rn[wv] = row ? nb_count[j] : 0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // union of the rows' ranges in unwrapped source index (periodic lists wrap)
-    const long long base = rs[0];
-    long long hi = base;
-    for (int w = 0; w < kOtfRows; ++w) {
-      if (!rn[w]) continue;
-      long long a = rs[w];
-      if (a < base) a += M;
-      hi = hi > a + rn[w] ? hi : a + rn[w];
-    }
-    ub[0] = base;
-    ub[1] = hi;
-  }
-  __syncthreads();
-  const long long ustart = ub[0], uend = ub[1];
-  long long my0 = rs[wv];
-  if (my0 < ustart) my0 += M;
-  const long long my1 = my0 + rn[wv];
-  const double xa = row ? xs[j] : 0.0;
-  const double Wd = (double)W;
-  const double pw = (double)kPhiPieces / Wd;   // pieces per unit lag
-  const int nl = NQ - 1;
-  double acc = 0.0;
-  for (long long cb = ustart; cb < uend; cb += kOtfChunk) {
-    __syncthreads();   // the previous chunk is no longer read
-    for (int e = threadIdx.x; e < nl * kOtfChunk; e += blockDim.x) {
-      const int m = e / kOtfChunk + 1, k = e - (m - 1) * kOtfChunk;
-      const long long u = cb + k;
-      double v = 0.0;
-      if (u < uend) {
-        const int l = (int)(u % M);
-        v = hist[(int64_t)mod_slot(L - m, NH) * M + l];
-      }
-      sg[e] = v;
-    }
-    __syncthreads();
-    const long long a0 = my0 > cb ? my0 : cb;
-    const long long a1 = my1 < cb + kOtfChunk ? my1 : cb + kOtfChunk;
-    for (long long ua = a0 + lane; ua < a1; ua += 128) {
-      const long long ub2 = ua + 64;
-      double da = fabs(xa - xs[(int)(ua % M)]);
-      if (periodic && da > kPi) da = kTwoPi - da;
-      double db = 0.0;
-      bool bon = ub2 < a1;
-      if (bon) {
-        db = fabs(xa - xs[(int)(ub2 % M)]);
-        if (periodic && db > kPi) db = kTwoPi - db;
-      }
-      OtfPair<P> pa, pb;
-      otf_begin(pa, da < delta, (int)(ua - cb), da, dt, delta, Wd);
-      otf_begin(pb, bon && db < delta, (int)(ub2 - cb), db, dt, delta, Wd);
-      for (int q = 0; q < ngl; ++q) {
-        const double naq = na[q], nwq = nw[q];
-        otf_node(pa, naq, nwq, tab, Wd, pw, sg);
-        otf_node(pb, naq, nwq, tab, Wd, pw, sg);
-      }
-      acc += pa.pair + pb.pair;
-    }
-  }
-  acc = wave_sum(acc);
-  if (row && lane == 0) out[j] = scale[j] * acc;
-}
-
-template <int P>
-__global__ void __launch_bounds__(1024)
-k_local_otf(int M, int NH, int NQ, int64_t L, const int* __restrict__ nb_start, const int* __restrict__ nb_count,
-            const double* __restrict__ xs, const double* __restrict__ hist, const double* __restrict__ scale,
-            int periodic, double dt, double delta, int W, int ngl, const double* __restrict__ zs,
-            const double* __restrict__ ws, const double* __restrict__ phitab, double* __restrict__ out) {
-  k_local_otf_body<P>(M, NH, NQ, L, nb_start, nb_count, xs, hist, scale, periodic, dt, delta, W, ngl, zs, ws, phitab,
-                      out, xcd_block(blockIdx.x, gridDim.x));
-}
-
-#define WFP_OTF_INST(PP)                                                                                        \
-  template __global__ void k_local_otf<PP>(int, int, int, int64_t, const int*, const int*, const double*,      \
-                                           const double*, const double*, int, double, double, int, int,        \
-                                           const double*, const double*, const double*, double*);
-WFP_OTF_INST(2)
-WFP_OTF_INST(4)
-WFP_OTF_INST(6)
-WFP_OTF_INST(8)
-WFP_OTF_INST(10)
-WFP_OTF_INST(12)
-#undef WFP_OTF_INST
 
 // Local sum of lags m >= 1 with the weights evaluated on the fly, each
 // unordered pair of springs once.  Q_m(d) depends on the distance alone
@@ -1066,18 +860,18 @@ __device__ __forceinline__ void sym_node(double Dm, double span, int mmin, doubl
 }
 
 template <int P>
-__global__ void __launch_bounds__(1024)
-k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end, const int* __restrict__ blk_end,
-                const int64_t* __restrict__ part_off, int nblk_rows, const double* __restrict__ xs,
-                const double* __restrict__ hist, int periodic, double dt, double delta, int W, int ngl,
-                const double* __restrict__ na, const double* __restrict__ nw, const double* __restrict__ phitab,
-                double* __restrict__ rowacc, double* __restrict__ part) {
+__device__ __forceinline__ void k_local_otf_sym_body(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end,
+                                                     const int* __restrict__ blk_end,
+                                                     const int64_t* __restrict__ part_off,
+                                                     const double* __restrict__ xs, const double* __restrict__ hist,
+                                                     int periodic, double dt, double delta, int W, int ngl,
+                                                     const double* __restrict__ na, const double* __restrict__ nw,
+                                                     const double* __restrict__ phitab, double* __restrict__ rowacc,
+                                                     double* __restrict__ part, int b) {
   extern __shared__ double sg[];                              // [NQ][kOtfChunk], then [kOtfRows][kOtfChunk]
   __shared__ double tab[kPhiPieces * (kPhiDeg + 1)];
   __shared__ double rh[kOtfRows][kMaxOtfLags + 1];
   __shared__ int64_t slot[kMaxOtfLags + 1];                   // row offset of lag m's density level
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  if (b >= nblk_rows) return;                                 // padding block: nothing to do
   double* colp = sg + (size_t)NQ * kOtfChunk;                 // per-wavefront column sums of a chunk
   for (int i = threadIdx.x; i < kPhiPieces * (kPhiDeg + 1); i += blockDim.x) tab[i] = phitab[i];
   for (int m = threadIdx.x; m < NQ; m += blockDim.x) slot[m] = (int64_t)mod_slot(L - m, NH) * M;
@@ -1141,15 +935,31 @@ k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end
   if (row && lane == 0) rowacc[j] = acc;
 }
 
+template <int P>
+__global__ void __launch_bounds__(1024)
+k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end, const int* __restrict__ blk_end,
+                const int64_t* __restrict__ part_off, int nblk_rows, const double* __restrict__ xs,
+                const double* __restrict__ hist, int periodic, double dt, double delta, int W, int ngl,
+                const double* __restrict__ na, const double* __restrict__ nw, const double* __restrict__ phitab,
+                double* __restrict__ rowacc, double* __restrict__ part) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= nblk_rows) return;                                 // padding block: nothing to do
+  k_local_otf_sym_body<P>(M, NH, NQ, L, up_end, blk_end, part_off, xs, hist, periodic, dt, delta, W, ngl, na, nw,
+                          phitab, rowacc, part, b);
+}
+
 // Row l's total of the symmetric local sum: its own upper-range sum plus the
 // column sums that the blocks covering l wrote for it (blocks at or below
 // l's own whose source range reaches l, and in the periodic box the blocks
 // whose range wraps past M - 1 to l + M), in a fixed order; scaled per row.
-__global__ void __launch_bounds__(256)
-k_local_otf_reduce(int M, int nblk_rows, int periodic, const int* __restrict__ blk_end,
-                   const int64_t* __restrict__ part_off, const double* __restrict__ rowacc,
-                   const double* __restrict__ part, const double* __restrict__ scale, double* __restrict__ out) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_local_otf_reduce_body(int M, int nblk_rows, int periodic,
+                                                        const int* __restrict__ blk_end,
+                                                        const int64_t* __restrict__ part_off,
+                                                        const double* __restrict__ rowacc,
+                                                        const double* __restrict__ part,
+                                                        const double* __restrict__ scale, double* __restrict__ out,
+                                                        int bid) {
+  const int l = bid * 256 + threadIdx.x;
   if (l >= M) return;
   double acc = rowacc[l];
   for (int b = l / kOtfRows; b >= 0 && blk_end[b] > l; --b) acc += part[part_off[b] + (l - b * kOtfRows)];
@@ -1158,6 +968,13 @@ k_local_otf_reduce(int M, int nblk_rows, int periodic, const int* __restrict__ b
     for (int b = nblk_rows - 1; b >= 0 && blk_end[b] > lw; --b) acc += part[part_off[b] + (lw - (long long)b * kOtfRows)];
   }
   out[l] = scale[l] * acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_local_otf_reduce(int M, int nblk_rows, int periodic, const int* __restrict__ blk_end,
+                   const int64_t* __restrict__ part_off, const double* __restrict__ rowacc,
+                   const double* __restrict__ part, const double* __restrict__ scale, double* __restrict__ out) {
+  k_local_otf_reduce_body(M, nblk_rows, periodic, blk_end, part_off, rowacc, part, scale, out, blockIdx.x);
 }
 
 #define WFP_OTFS_INST(PP)                                                                                      \
@@ -2047,13 +1864,25 @@ __global__ void __launch_bounds__(256) kb_local_g4(BatchLaunch b) {
                       d.loc, w.y);
 }
 
+// On-the-fly local sums (each unordered pair once, p = 8): the block pass over
+// (instance, row block) items, then the per-row totals over (instance, 256
+// rows) items.
 __global__ void __launch_bounds__(1024) kb_local_otf(BatchLaunch b) {
   const int2 w = b.work[xcd_block(blockIdx.x, gridDim.x)];
   if (w.x < 0) return;   // block-uniform
   const InstDesc& d = b.desc[w.x];
   if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
-  k_local_otf_body<8>(d.M, d.NH, d.NQ, *b.level, d.nb_start, d.nb_count, d.xs, d.hist, d.half_beta, 1, d.dt,
-                      d.delta, d.W, d.ngl, d.otf_z, d.otf_w, d.phitab, d.loc, w.y);
+  k_local_otf_sym_body<8>(d.M, d.NH, d.NQ, *b.level, d.otf_up_end, d.otf_blk_end, d.otf_part_off, d.xs, d.hist, 1,
+                          d.dt, d.delta, d.W, d.ngl, d.otf_na, d.otf_nw, d.phitab, d.otf_rowacc, d.otf_part, w.y);
+}
+
+__global__ void __launch_bounds__(256) kb_local_otf_reduce(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
+  k_local_otf_reduce_body(d.M, d.otf_nblk, 1, d.otf_blk_end, d.otf_part_off, d.otf_rowacc, d.otf_part, d.half_beta,
+                          d.loc, w.y);
 }
 
 __global__ void __launch_bounds__(256) kb_hist_a(BatchLaunch b) {

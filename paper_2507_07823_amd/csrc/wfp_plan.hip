@@ -643,22 +643,12 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     }
     // upper source ranges of the symmetric local sum (each unordered pair once)
     {
-      const int nb = (int)nblk(M, kOtfRows);
-      std::vector<int> up(M), be(nb, 0);
-      std::vector<int64_t> po(nb);
-      for (int64_t j = 0; j < M; ++j) {
-        const int64_t st = nbs[j] <= j ? nbs[j] : (int64_t)nbs[j] - M;
-        const int64_t e = st + nbc[j];
-        if (!(st <= j && j < e && e <= j + M)) fail(WFP_EINVAL, "neighbour range does not contain its row");
-        up[j] = (int)e;
-        be[j / kOtfRows] = std::max(be[j / kOtfRows], (int)e);
-      }
+      std::vector<int> up, be;
+      std::vector<int64_t> po;
       int64_t tot_part = 0;
-      for (int b = 0; b < nb; ++b) {
-        if (b > 0 && be[b] < be[b - 1]) fail(WFP_EINVAL, "upper source ranges not monotone");
-        po[b] = tot_part;
-        tot_part += (int64_t)be[b] - (int64_t)b * kOtfRows;
-      }
+      if (!upper_ranges(nbs, nbc, kOtfRows, up, be, po, tot_part))
+        fail(WFP_EINVAL, "upper source ranges of the on-the-fly local sum are inconsistent");
+      const int nb = (int)be.size();
       P->otf_nblk = nb;
       P->otf_up_end = P->alloc<int>(M);
       P->otf_blk_end = P->alloc<int>(nb);
@@ -1116,13 +1106,6 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   HIPCHK(hipFuncSetAttribute((const void*)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HIPCHK(hipFuncSetAttribute((const void*)k_hist_b, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   if (P->otf) {
-    const size_t need = (size_t)(P->NQ - 1) * kOtfChunk * sizeof(double) +
-                        (size_t)kPhiPieces * (kPhiDeg + 1) * sizeof(double) + 2048;
-    if (need > 160 * 1024) fail(WFP_EDOMAIN, "on-the-fly local sum: density stage too large for LDS");
-    const void* fns[6] = {(const void*)k_local_otf<2>, (const void*)k_local_otf<4>, (const void*)k_local_otf<6>,
-                          (const void*)k_local_otf<8>, (const void*)k_local_otf<10>, (const void*)k_local_otf<12>};
-    const int dyn = (int)((size_t)(P->NQ - 1) * kOtfChunk * sizeof(double));
-    for (const void* f : fns) HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
     const size_t sym_lds = (size_t)(P->NQ + kOtfRows) * kOtfChunk * sizeof(double) +
                            (size_t)kPhiPieces * (kPhiDeg + 1) * sizeof(double) +
                            (size_t)kOtfRows * (kMaxOtfLags + 1) * sizeof(double) + 128 * sizeof(double);
