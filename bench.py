@@ -351,6 +351,7 @@ def adjoint_leg(levels, every):
     ok = bool(torch.isfinite(gb).all() and torch.isfinite(gx).all())
     plan.close()
     return {"workload": "periodic adjoint", "M": M, "R": R, "levels": levels, "checkpoint_every": every,
+            "beta": [round(float(p["beta"].min()), 4), round(float(p["beta"].max()), 4)],
             "plan_setup_s": setup, "forward_s": t_fwd, "gradient_s": t_bwd,
             "plain_scatterer_steps_per_s": M * levels / t_fwd,
             "forward_plus_gradient_scatterer_steps_per_s": M * levels / (t_fwd + t_bwd),
@@ -359,8 +360,9 @@ def adjoint_leg(levels, every):
 
 def batch_leg(n_inst, levels, m_max, trial_levels=3, uneven=True):
     """The batched form on uneven periodic instances (M log-uniform in
-    [100, m_max], dt in {1e-3, 2e-3, 5e-3}, beta ~ U[1, 10], one random pulse
-    each), autotuned, against the same instances marched one plain plan at a
+    [100, m_max], dt in {1e-3, 2e-3, 5e-3}, beta ~ U[1, 10] scaled per
+    instance to keep the dense-medium number <= 0.1, one random pulse each),
+    autotuned, against the same instances marched one plain plan at a
     time.  With `uneven`, instance i marches its own level count
     levels - (i mod 4) levels / 8 (wfp_batch_set_levels), the plain plans the
     same counts; the rate counts each instance's own levels."""
@@ -657,7 +659,9 @@ def headline(steps, warmup, profile_levels):
     cfg = {"workload": "clumped free space (10 % of springs in 100 Gaussian clumps of width 1e-3)",
            "M": M, "dt": p["dt"], "K": info["K"], "W": info["W"], "p": info["p"], "n_fine": info["n_fine"],
            "pairs": info["n_pairs"], "local_mode": "on the fly", "solve_mode": info["solve_mode"],
-           "beta_uniform": [1.0, 10.0], "beta_clumped": list(workloads.CLUMP_BETA),
+           "beta_uniform": [round(float(p["beta"][:M - M // 10].min()), 4),
+                            round(float(p["beta"][:M - M // 10].max()), 4)],
+           "beta_clumped": list(workloads.CLUMP_BETA),
            "levels_timed": steps, "parallelism": "single GPU", "plan_setup_s": setup}
     return dict(value=M * steps / elapsed, elapsed=elapsed, config=cfg, parity=parity, roofline=roofline,
                 stages=stages)

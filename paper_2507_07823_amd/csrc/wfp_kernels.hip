@@ -787,22 +787,32 @@ k_local_deriv2(int M, int NQ, int NH, const int* __restrict__ nb_start, const in
 // block's wavefronts in LDS in a fixed order and written to
 // part[part_off[b] + (u - j0)] for the block's unwrapped source u;
 // k_local_otf_reduce adds them up per row.
-// Factors of the Lagrange weights at u: prefix (u - r)/(r + 1) = fma(u, ca, cb),
-// suffix (r + 1 - u)/(P - 1 - r) = fma(u, cc, cd), r = 0..P-2.  Held in
-// registers across the node loop (as operands they would take the scalar
-// constant bus twice per FMA and cost a register copy each).
+// Lagrange weights at u as prefix times suffix products:
+//   v_r = lambda_0 [(lambda_r / lambda_0) prod_{k<r} (u - k)] [prod_{k>r} (k - u)],
+//   lambda_r = 1 / (r! (P-1-r)!),
+// the ratio lambda_r / lambda_0 carried by the prefix (its factor for k = r is
+// rho_r (u - r) = fma(u, rho_r, -r rho_r), rho_r = (P-1-r)/(r+1)) and
+// lambda_0 = 1/(P-1)! by the pair's span, once per pair.  The suffix factors
+// (k - u) take one scalar constant each.  The P - 1 prefix factor pairs are
+// held in registers across the node loop (as operands an FMA would read two
+// scalar constants, one over the constant-bus limit, and cost a register
+// copy each).
 template <int P>
 struct LagFactors {
-  double ca[P - 1], cb[P - 1], cc[P - 1], cd[P - 1];
+  double ca[P - 1], cb[P - 1];
   __device__ __forceinline__ void init() {
 #pragma unroll
     for (int r = 0; r < P - 1; ++r) {
-      ca[r] = 1.0 / (r + 1);
-      cb[r] = -(double)r / (r + 1);
-      cc[r] = -1.0 / (P - 1 - r);
-      cd[r] = (double)(r + 1) / (P - 1 - r);
-      asm volatile("" : "+v"(ca[r]), "+v"(cb[r]), "+v"(cc[r]), "+v"(cd[r]));
+      const double rho = (double)(P - 1 - r) / (r + 1);
+      ca[r] = rho;
+      cb[r] = -r * rho;
+      asm volatile("" : "+v"(ca[r]), "+v"(cb[r]));
     }
+  }
+  static constexpr double lambda0() {
+    double l = 1.0;
+    for (int k = 2; k < P; ++k) l /= k;
+    return l;
   }
 };
 
@@ -843,7 +853,7 @@ __device__ __forceinline__ void sym_node(double Dm, double span, int mmin, doubl
   for (int r = 0; r < P - 1; ++r) A[r + 1] = A[r] * fma(u, lf.ca[r], lf.cb[r]);
   B[P - 1] = 1.0;
 #pragma unroll
-  for (int r = P - 2; r >= 0; --r) B[r] = B[r + 1] * fma(u, lf.cc[r], lf.cd[r]);
+  for (int r = P - 2; r >= 0; --r) B[r] = B[r + 1] * ((double)(r + 1) - u);
   double pa = 0.0, pcl = 0.0;
 #pragma unroll
   for (int r = 0; r < P; ++r) {
@@ -914,7 +924,7 @@ __device__ __forceinline__ void k_local_otf_sym_body(int M, int NH, int NQ, int6
       const int k = (int)(ua - cb);
       const double Dm = on ? d / dt - Wd : -0.5 * Wd;    // off: D = W/2, nodes inside (0, W), zero weight
       const int mmin = (on && d < dt) ? 0 : 1;
-      const double span = on ? delta - d : 0.0;
+      const double span = on ? (delta - d) * LagFactors<P>::lambda0() : 0.0;
       double pa = 0.0, pcol = 0.0;
       for (int q = 0; q < ngl; ++q) sym_node<P>(Dm, span, mmin, na[q], nw[q], tab, Wd, pw, sg + k, rh[wv], lf, pa, pcol);
       acc += pa;

@@ -27,6 +27,23 @@ def _rng(*seed):
     return np.random.default_rng(list(seed))
 
 
+# Largest dense-medium number theta = dt sqrt(rho mean(beta)) a workload is
+# drawn with (rho: springs per unit length).  Many springs per time step act on
+# a wave like a continuous elastic medium of stiffness density rho mean(beta);
+# for that medium the discrete march with p = 8 has a growing mode once theta
+# exceeds about 0.15-0.2 (at 0.29: +0.017 per level), whatever dt and rho are
+# separately.  0.1 leaves a margin.
+THETA_MAX = 0.1
+
+
+def stable_beta_scale(M, length, dt, beta_mean, theta_max=THETA_MAX):
+    """Factor s <= 1 for stiffnesses of mean beta_mean, so that M springs
+    spread uniformly over an interval of the given length keep
+    theta = dt sqrt(rho s beta_mean) <= theta_max (rho = M / length)."""
+    theta = dt * math.sqrt(M / length * beta_mean)
+    return min(1.0, (theta_max / theta) ** 2)
+
+
 def periodic_single_pulse(seed, M, dt, n_steps, beta_range=(1.0, 10.0),
                           x_range=(0.3, 2.0), width=0.3, centre=-2.0, n_recv=0,
                           name="periodic"):
@@ -74,7 +91,9 @@ def clumped_free_space(seed=3, M=1_000_000, dt=5e-4, n_steps=4000, n_clumps=100,
                        frac=0.1, clump_sigma=1e-3, margin=0.0528, clump_beta=CLUMP_BETA):
     """Free space, M springs uniform in Omega with a fraction in tight Gaussian
     clumps, Gaussian-modulated plane wave of angular frequency 1000 entering
-    from the left.  Uniform springs: beta ~ U[1, 10].  Clumped springs: beta ~
+    from the left.  Uniform springs: beta ~ U[1, 10] scaled by
+    stable_beta_scale (1 up to M ~ 4.5e4; 0.05 at M = 1e6, where the 9e5
+    uniform springs alone would make theta = 0.45).  Clumped springs: beta ~
     U[clump_beta]; at M = 1e6 a clump holds 1000 springs within ~1e-3 (total
     stiffness ~5500 with U[1, 10]), and the discrete march (p = 8, dt = 5e-4)
     of such a clump grows by ~x360 per 100 levels in any exact implementation
@@ -91,7 +110,8 @@ def clumped_free_space(seed=3, M=1_000_000, dt=5e-4, n_steps=4000, n_clumps=100,
     xc = np.concatenate([r.normal(c, clump_sigma, k) for c, k in zip(centres, per)])
     xc = np.clip(xc, lo, hi)
     x = np.concatenate([xu, xc])
-    beta = np.concatenate([r.uniform(1.0, 10.0, n_un), r.uniform(clump_beta[0], clump_beta[1], n_cl)])
+    s_un = stable_beta_scale(n_un, hi - lo, dt, 5.5)
+    beta = np.concatenate([s_un * r.uniform(1.0, 10.0, n_un), r.uniform(clump_beta[0], clump_beta[1], n_cl)])
     s0 = lo - 0.4
     packets = np.array([[1.0, s0, 0.05, 1000.0, 0.0]])
     return dict(x=x, beta=beta, packets=packets, boundary=1, dt=dt, n_steps=n_steps,
@@ -259,11 +279,12 @@ def disordered_long(M, seed=11, refine=1, n_recv=50):
 
 
 def adjoint_periodic(seed=5, M=100_000, dt=1e-3, n_steps=5000, R=64):
-    """Periodic, M springs with beta ~ U[1, 10], a single Gaussian pulse
+    """Periodic, M springs with beta ~ U[1, 10] scaled by stable_beta_scale
+    (0.092 at M = 1e5, dt = 1e-3: U[0.092, 0.92]), a single Gaussian pulse
     (width 0.05) and R receivers spread over the spring region."""
     r = _rng(seed)
     x = r.uniform(-PI + 1.2, PI, M)
-    beta = r.uniform(1.0, 10.0, M)
+    beta = stable_beta_scale(M, 2 * PI - 1.2, dt, 5.5) * r.uniform(1.0, 10.0, M)
     packets = np.array([[1.0, -PI + 0.6, 0.05, 0.0, 0.0]])
     xr = -PI + 1.2 + (np.arange(R) + 0.5) * (2 * PI - 1.2) / R
     return dict(x=x, beta=beta, packets=packets, boundary=0, dt=dt, n_steps=n_steps,
@@ -272,7 +293,9 @@ def adjoint_periodic(seed=5, M=100_000, dt=1e-3, n_steps=5000, R=64):
 
 def batch_instances(seed=4, n=512, n_steps=2000, m_range=(100, 100_000)):
     """n independent periodic problems with log-uniform M, dt in {1,2,5}e-3,
-    beta ~ U[1, 10] and one random Gaussian pulse each."""
+    beta ~ U[1, 10] scaled per instance by stable_beta_scale (the dense
+    instances at the larger time steps get weaker springs) and one random
+    Gaussian pulse each."""
     out = []
     for i in range(n):
         r = _rng(seed, i)
@@ -281,7 +304,7 @@ def batch_instances(seed=4, n=512, n_steps=2000, m_range=(100, 100_000)):
         w = r.uniform(0.03, 0.07)
         c = r.uniform(-PI + 0.55, -PI + 0.65)
         x = r.uniform(-PI + 1.2, PI, M)
-        beta = r.uniform(1.0, 10.0, M)
+        beta = stable_beta_scale(M, 2 * PI - 1.2, dt, 5.5) * r.uniform(1.0, 10.0, M)
         out.append(dict(x=x, beta=beta, packets=np.array([[1.0, c, w, 0.0, 0.0]]),
                         boundary=0, dt=dt, n_steps=n_steps, x_recv=np.zeros(0),
                         name=f"batch-{i}"))

@@ -357,12 +357,12 @@ def batch_paths_cases():
                      boundary=0, dt=1e-3, x_recv=np.zeros(0)), 260, 0))
     x = rng.uniform(-np.pi + 1.2, np.pi, 300)
     out.append((dict(x=x, beta=rng.uniform(1.0, 10.0, 300), packets=np.array([[1.0, -np.pi + 0.9, 0.05, 0.0, 0.0]]),
-                     boundary=0, dt=2e-3, x_recv=np.array([-1.5, 0.0, 1.5])), 220, 2))
+                     boundary=0, dt=2e-3, x_recv=np.array([-2.1, -1.9, -1.8])), 220, 2))
     p = workloads.small_periodic()
     out.append((dict(p, x_recv=np.linspace(0.3, 2.0, 5)), 300, 0))
     x = rng.uniform(-np.pi + 1.2, np.pi, 1500)
     out.append((dict(x=x, beta=rng.uniform(1.0, 10.0, 1500), packets=np.array([[1.0, -np.pi + 0.9, 0.06, 0.0, 0.0]]),
-                     boundary=0, dt=5e-3, x_recv=np.array([-1.0, 1.0])), 180, 0))
+                     boundary=0, dt=5e-3, x_recv=np.array([-1.9, -1.5])), 180, 0))
     return out
 
 

@@ -1,6 +1,12 @@
 """Stability of the discrete march for one spring (a property of the scheme of
 Sections 3-4 with p-point interpolation; Section 5 analyses p = 1, 2 only).
 
+Dense media: with many springs per time step the springs act on a wave like
+a continuous elastic medium, and growth is decided by the dense-medium number
+theta = dt sqrt(rho mean(beta)) (rho springs per unit length), not by dt, rho
+or beta separately: theta = 0.29 grows by ~2 % per level at dt = 0.01 and
+0.02 alike, theta = 0.1 does not grow.  The workloads keep theta <= 0.1.
+
 Zero driving, a random density history: with p = 8 and dt = 1e-3 the march
 decays for beta dt / 2 = 0.2 and grows for beta dt / 2 = 0.4, while p = 4 still
 decays at 0.4.  Clusters of nearby stiff springs act like one spring of summed
@@ -116,3 +122,58 @@ def test_p8_threshold_and_the_filter_setting():
     assert root_modulus(0.35, 8, 0.01) > 1.0
     assert 1.15 < root_modulus(0.5, 8, 0.01) < 1.25
     assert root_modulus(0.5, 6, 0.01) < 1.0 and root_modulus(0.5, 4, 0.01) < 1.0
+
+
+def dense_growth(M, dt, s, n, seed=7):
+    """Growth per level of the homogeneous periodic march (zero driving, a
+    seeded random density history) of M springs uniform on [-pi + 1.2, pi]
+    with beta ~ s U[1, 10]: the log-slope of max |sigma| over the last
+    quarter of n levels."""
+    r = np.random.default_rng(seed)
+    x = r.uniform(-math.pi + 1.2, math.pi, M)
+    beta = s * r.uniform(1.0, 10.0, M)
+    prm = Params(dt=dt)
+    o = Oracle(x, beta, prm, lambda t: np.zeros(M))
+    o.set_state(dict(L=100, hist=r.standard_normal((prm.m_max, M)),
+                     ring=np.zeros((prm.W, prm.K + 1), complex), alpha=np.zeros(prm.K + 1, complex),
+                     dalpha=np.zeros(prm.K + 1, complex)))
+    with np.errstate(all="ignore"):
+        v = [float(np.max(np.abs(o.step()[0]))) for _ in range(n)]
+    q = n // 4
+    return (math.log(v[-1]) - math.log(v[-q])) / q
+
+
+def theta_of(M, dt, s):
+    return dt * math.sqrt(M / (2 * math.pi - 1.2) * 5.5 * s)
+
+
+def test_dense_medium_growth_depends_on_theta():
+    """theta = 0.29 with the same springs per time step (rho dt = 1.57) at
+    dt = 0.01 and dt = 0.02: the same growth rate; theta = 0.1 at dt = 0.02:
+    no growth.  (Larger rho dt at the same theta: +0.018 and +0.017 per level
+    at rho dt = 3.1 and 6.2.)"""
+    assert abs(theta_of(800, 0.01, 1.0) - theta_of(400, 0.02, 0.5)) < 1e-12
+    r1 = dense_growth(800, 0.01, 1.0, 1500)
+    r2 = dense_growth(400, 0.02, 0.5, 1500)
+    assert r1 > 0.01 and r2 > 0.01, (r1, r2)
+    assert abs(r1 - r2) < 0.25 * r1, (r1, r2)
+    s = (0.1 / theta_of(400, 0.02, 1.0)) ** 2
+    assert dense_growth(400, 0.02, s, 1500) < 1e-3
+
+
+def test_workloads_keep_theta_small():
+    """Every randomly placed workload is drawn with theta <= 0.1 (the batched
+    recipe instance by instance; the uniform part of the clumped free-space
+    workload; the gradient workload)."""
+    from paper_2507_07823_amd import workloads as w
+    span = 2 * math.pi - 1.2
+    for p in w.batch_instances(n=64):
+        assert p["dt"] * math.sqrt(p["x"].size / span * p["beta"].mean()) < 0.1 * (1 + 0.05)
+    p = w.adjoint_periodic()
+    assert p["dt"] * math.sqrt(p["x"].size / span * p["beta"].mean()) < 0.105
+    p = w.multiband_periodic()
+    assert p["dt"] * math.sqrt(p["x"].size / span * p["beta"].mean()) < 0.1
+    p = w.clumped_free_space()
+    n_un = int(round(0.9 * p["x"].size))
+    lo, hi = p["x"][:n_un].min(), p["x"][:n_un].max()
+    assert p["dt"] * math.sqrt(n_un / (hi - lo) * p["beta"][:n_un].mean()) < 0.105
