@@ -137,6 +137,43 @@ def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, kernel="wfp:
     ])
 
 
+def counters_summary(dirs, kernel, avg_ms, pairs, nodes=35):
+    """Per-dispatch means of every counter of ``kernel`` in the given
+    rocprofv3 --pmc runs, and the derived VALU/LDS/FP64 figures of the
+    pair-once local sum (256 compute units in 8 XCDs, GRBM_GUI_ACTIVE summed
+    over the XCDs; one (unordered pair, node) step per lane)."""
+    vals, n = {}, 0
+    for d in dirs:
+        for fn in os.listdir(d):
+            if fn.endswith("counter_collection.csv"):
+                names = set()
+                with open(os.path.join(d, fn)) as f:
+                    for r in csv.DictReader(f):
+                        names.add(r["Counter_Name"])
+                for c in sorted(names):
+                    m, n = _counter_means(d, c)[kernel]
+                    vals[c] = m
+    steps = pairs / 2 * nodes / 64
+    busy = vals["SQ_ACTIVE_INST_VALU"] / 256 / (vals["GRBM_GUI_ACTIVE"] / 8)
+    flops = 64 * vals["SQ_INSTS_VALU_FLOPS_FP64"]
+    f64 = vals["SQ_INSTS_VALU_FMA_F64"] + vals["SQ_INSTS_VALU_ADD_F64"] + vals["SQ_INSTS_VALU_MUL_F64"]
+    lines = [f"kernel: {kernel}", f"kernel_source_sha256: {kernel_source_hash(kernel)}", f"dispatches: {n}", ""]
+    lines += [f"{c}: {v:.6g}" for c, v in sorted(vals.items())]
+    lines += [
+        f"VALU_busy: {busy:.3f}",
+        f"VALU_lanes_active: {vals['SQ_THREAD_CYCLES_VALU'] / (64 * vals['SQ_ACTIVE_INST_VALU']):.4f}",
+        f"LDS_active_fraction: {vals['SQ_ACTIVE_INST_LDS'] / 256 / (vals['GRBM_GUI_ACTIVE'] / 8):.3f}",
+        f"FP64_flops_executed: {flops:.4g}",
+        f"FP64_executed_TFLOPs_at_{avg_ms:g}ms: {flops / (avg_ms * 1e-3) / 1e12:.2f}",
+        f"FP64_executed_fraction_of_78.6_peak: {flops / (avg_ms * 1e-3) / 78.6e12:.3f}",
+        f"FP64_share_of_VALU_instructions: {f64 / vals['SQ_INSTS_VALU']:.3f}",
+        f"VALU_instructions_per_node_wavefront: {vals['SQ_INSTS_VALU'] / steps:.1f}",
+        f"LDS_instructions_per_node_wavefront: {vals['SQ_INSTS_LDS'] / steps:.2f}",
+        f"LDS_bank_conflicts_per_LDS_instruction: {vals['SQ_LDS_BANK_CONFLICT'] / vals['SQ_INSTS_LDS']:.2e}",
+    ]
+    return "\n".join(lines)
+
+
 def trace_tail_mean(d, kernel, n):
     """Mean duration (us) of the last n dispatches of `kernel` in a rocprofv3
     kernel trace (kernel_trace.csv), e.g. bench.py's timed-alone pass."""
@@ -765,6 +802,9 @@ def main():
                                                        "KERNEL"),
                     help="print the traffic summary of rocprofv3 --pmc runs and exit")
     ap.add_argument("--stats-summary", metavar="DIR", help="print a rocprofv3 --stats table and exit")
+    ap.add_argument("--counters-summary", nargs=5, metavar=("DIR1", "DIR2", "KERNEL", "AVG_MS", "PAIRS"),
+                    help="print the counters of KERNEL from two rocprofv3 --pmc runs, with the VALU/LDS/FP64 "
+                         "figures derived at a launch time of AVG_MS over PAIRS ordered neighbour pairs, and exit")
     ap.add_argument("--trace-tail", nargs=3, metavar=("DIR", "KERNEL", "N"),
                     help="print the mean duration of the last N dispatches of KERNEL in a kernel trace and exit")
     args = ap.parse_args()
@@ -773,6 +813,10 @@ def main():
         return
     if args.stats_summary:
         print(stats_summary(args.stats_summary))
+        return
+    if args.counters_summary:
+        d1, d2, k, ms, pairs = args.counters_summary
+        print(counters_summary([d1, d2], k, float(ms), float(pairs)))
         return
     if args.trace_tail:
         d, k, n = args.trace_tail

@@ -207,3 +207,101 @@ def test_batch_receivers_match_plain_plans(wfp):
         say(f"  instance {i}: R = {R}, max |u| = {np.max(np.abs(ref)):.2e}, max |batch - plan| = {err:.2e}")
     assert worst < 1e-12 and seen > 1e-3
     b.close()
+
+
+GOLDEN_DIR = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _load_golden_module():
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(GOLDEN_DIR, "make_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_batch_recipe_instances_against_oracle(wfp):
+    """The batched workload's instances with M <= 1e4 among its first 24,
+    marched together, each for its own level count N_i (1125..2000,
+    wfp_batch_set_levels): sampled springs at levels 499, 999, 1499 and every
+    spring at each instance's last level against the oracle's own marches
+    (tests/golden/batch_recipe.npz)."""
+    import os
+    import torch
+    g = np.load(os.path.join(GOLDEN_DIR, "batch_recipe.npz"))
+    cases = _load_golden_module().batch_recipe_cases()
+    assert [c[0] for c in cases] == list(g["index"])
+    insts = [c[1] for c in cases]
+    ends = [c[2] for c in cases]
+    say(f"batch recipe: {len(insts)} instances, M = {[p['x'].size for p in insts]}, levels {ends}")
+    b = wfp.Batch(insts, [p["dt"] for p in insts])
+    b.set_levels(ends)
+    worst = 0.0
+    for L1 in (500, 1000, 1500, 2000):
+        fin = [torch.full((p["x"].size,), float("nan"), dtype=torch.float64, device="cuda") for p in insts]
+        b.run(L1 - b.level, fin)
+        torch.cuda.synchronize()
+        for k, (i, p, n) in enumerate(cases):
+            got = fin[k].cpu().numpy()
+            smax = float(g["sigma_max"][k])
+            if L1 - 1 < n:                       # still marching: level L1 - 1
+                key = f"at{L1 - 1}_{i}"
+                if key in g:
+                    e = float(np.max(np.abs(got[g[f"sample_{i}"]] - g[key]))) / smax
+                    worst = max(worst, e)
+            elif L1 == 2000 or L1 - 500 < n:     # its last level
+                assert b.plan(k).level == n
+                e = float(np.max(np.abs(got - g[f"last_{i}"]))) / smax
+                worst = max(worst, e)
+    say(f"  worst rho over the compared levels: {worst:.2e}")
+    assert worst < 1e-10
+    assert b.level == 2000
+    b.close()
+
+
+def test_batch_paths_against_oracle(wfp):
+    """Five instances that between them take every batched kernel path (tiled
+    Jacobi solve, global sweeps with a wavefront per row, local weights on the
+    fly, receivers, direct small-run solve), each with its own level count:
+    their last levels and receivers at every level against the oracle
+    (tests/golden/batch_paths.npz); receiver rows at and beyond an instance's
+    end are left untouched."""
+    import os
+    import torch
+    g = np.load(os.path.join(GOLDEN_DIR, "batch_paths.npz"))
+    cases = _load_golden_module().batch_paths_cases()
+    insts = [c[0] for c in cases]
+    ends = [c[1] for c in cases]
+    modes = [c[2] for c in cases]
+    n = max(ends)
+    b = wfp.Batch(insts, [p["dt"] for p in insts], per_instance=[{"local_mode": m} for m in modes])
+    infos = [b.plan(i).info for i in range(b.n)]
+    say("batch paths: " + "; ".join(f"M={q['M']} solve_mode={q['solve_mode']} tiles={q['n_solve_tiles']} "
+                                    f"direct={q['n_direct_tiles']} wave={q['sweep_wave']} local_mode={q['local_mode']} "
+                                    f"R={q['R']}" for q in infos))
+    assert infos[0]["solve_mode"] == 0 and infos[0]["n_solve_tiles"] > 0
+    assert infos[1]["solve_mode"] == 1 and infos[1]["sweep_wave"] == 1
+    assert infos[2]["local_mode"] == 2 and infos[2]["R"] == 3
+    assert infos[4]["n_direct_tiles"] > 0
+    b.set_levels(ends)
+    fin = [torch.empty(p["x"].size, dtype=torch.float64, device="cuda") for p in insts]
+    rec = [torch.full((n, p["x_recv"].size), float("nan"), dtype=torch.float64, device="cuda")
+           if p["x_recv"].size else None for p in insts]
+    b.run(n, fin, rec)
+    torch.cuda.synchronize()
+    for i, p in enumerate(insts):
+        smax = float(g[f"smax_{i}"])
+        e = float(np.max(np.abs(fin[i].cpu().numpy() - g[f"last_{i}"]))) / smax
+        msg = f"  instance {i}: levels {ends[i]} rho(last sigma) = {e:.2e}"
+        assert b.plan(i).level == ends[i]
+        assert e < 1e-10
+        if rec[i] is not None:
+            u = rec[i].cpu().numpy()
+            ref = g[f"recv_{i}"]
+            eu = rho(u[:ends[i]], ref)
+            msg += f" rho(receivers) = {eu:.2e}"
+            assert eu < 1e-10 and np.max(np.abs(ref)) > 1e-3       # the scattered field reaches them
+            assert np.isnan(u[ends[i]:]).all()
+        say(msg)
+    b.close()
