@@ -191,11 +191,12 @@ std::vector<int> radix_sequence(int64_t n) {
 std::vector<double> window_pieces(const WindowSeries& ws, int pieces, int deg) {
   const int n = deg + 1;
   std::vector<double> out((size_t)pieces * n);
+  // Chebyshev points of the piece, in the local variable x in [0, 1]
   std::vector<long double> t(n);
-  for (int i = 0; i < n; ++i) t[i] = std::cos(3.14159265358979323846264338327950288L * (i + 0.5L) / n);
+  for (int i = 0; i < n; ++i) t[i] = 0.5L + 0.5L * std::cos(3.14159265358979323846264338327950288L * (i + 0.5L) / n);
   for (int k = 0; k < pieces; ++k) {
-    const long double half = 1.0L / pieces;
-    const long double centre = -1.0L + (2.0L * k + 1.0L) / pieces;
+    const long double width = 2.0L / pieces;
+    const long double left = -1.0L + 2.0L * k / pieces;
     // Vandermonde system V c = f, V_ij = t_i^j
     std::vector<long double> a((size_t)n * (n + 1));
     for (int i = 0; i < n; ++i) {
@@ -204,7 +205,7 @@ std::vector<double> window_pieces(const WindowSeries& ws, int pieces, int deg) {
         a[(size_t)i * (n + 1) + j] = p;
         p *= t[i];
       }
-      a[(size_t)i * (n + 1) + n] = cheb_eval(ws.phi.data(), ws.n, (double)(centre + half * t[i]));
+      a[(size_t)i * (n + 1) + n] = cheb_eval(ws.phi.data(), ws.n, (double)(left + width * t[i]));
     }
     for (int c = 0; c < n; ++c) {
       int piv = c;

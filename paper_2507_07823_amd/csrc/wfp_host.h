@@ -34,7 +34,7 @@ WindowSeries window_series(double b, int n);
 
 // The window phi(u) of a series on [-1, 1] as `pieces` polynomials of degree
 // `deg`: piece k covers u in [-1 + 2k/pieces, -1 + 2(k+1)/pieces] and holds
-// monomial coefficients c_0..c_deg in t = (u - centre) / half_width,
+// monomial coefficients c_0..c_deg in x = (u + 1) pieces / 2 - k in [0, 1],
 // interpolating phi at deg + 1 Chebyshev points (solved in long double).
 std::vector<double> window_pieces(const WindowSeries& ws, int pieces, int deg);
 double cheb_eval(const double* a, int n, double s);   // prime convention

@@ -821,23 +821,25 @@ __device__ __forceinline__ void sym_node(double Dm, double span, int mmin, doubl
                                          const double* __restrict__ tab, double Wd, double pw,
                                          const double* __restrict__ sgk, const double* __restrict__ rh,
                                          const LagFactors<P>& lf, double& acc_a, double& acc_c) {
-  const double s = fma(Dm, na_q, Wd);         // W - (W - D)(1 + z_q)/2
-  // window piece: pc covers s in [pc, pc + 1) / pw (its coefficients are
-  // loaded here and used last, so the loads overlap the interpolation)
+  const double s = fma(Dm, na_q, Wd);         // W - (W - D)(1 + z_q)/2, in [0, W]
+  // window piece: pc covers s in [pc, pc + 1) / pw, its polynomial in the
+  // local variable x = v - pc (coefficients loaded here and used last, so the
+  // loads overlap the interpolation).  v = pw W (s = W, only where the pair's
+  // span rounds to 0) takes the last piece at x = 0, a weight-zero node.
   const double v = s * pw;
   int pc = (int)v;
-  pc = pc < 0 ? 0 : (pc >= kPhiPieces ? kPhiPieces - 1 : pc);
+  pc = pc >= kPhiPieces ? kPhiPieces - 1 : pc;
   const double* c = tab + pc * (kPhiDeg + 1);
   double cf[kPhiDeg + 1];
 #pragma unroll
   for (int k = 0; k <= kPhiDeg; ++k) cf[k] = c[k];
-  const double t = 2.0 * (v - pc) - 1.0;
-  int m0 = (int)floor(s) - P / 2 + 1;
-  if (m0 < mmin) m0 = mmin;
-  // s rounds to W only for d within an ulp of delta (zero weight): keep the
-  // stencil inside lags 0 .. W + P/2 - 1
+  const double x = __builtin_amdgcn_fract(v);
+  // stencil start max(mmin, floor(s) - P/2 + 1) (s >= 0: truncation is the
+  // floor); s rounds to W only for d within an ulp of delta (zero weight):
+  // the upper clamp keeps the stencil inside lags 0 .. W + P/2 - 1
   const int mtop = (int)Wd - P / 2;
-  if (m0 > mtop) m0 = mtop;
+  int m0;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(m0) : "v"((int)s - P / 2 + 1), "v"(mmin), "s"(mtop));
   const double* sp = sgk + m0 * kOtfChunk;
   const double* rp = rh + m0;
   double fa[P], fc[P];
@@ -863,7 +865,7 @@ __device__ __forceinline__ void sym_node(double Dm, double span, int mmin, doubl
   }
   double ph = cf[kPhiDeg];
 #pragma unroll
-  for (int k = kPhiDeg - 1; k >= 0; --k) ph = fma(ph, t, cf[k]);
+  for (int k = kPhiDeg - 1; k >= 0; --k) ph = fma(ph, x, cf[k]);
   const double om = span * nw_q * (1.0 - ph);
   acc_a = fma(om, pa, acc_a);
   acc_c = fma(om, pcl, acc_c);

@@ -634,7 +634,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
         const double u = -1.0 + 2.0 * i / 20000.0;
         int pc = (int)((u + 1.0) * (0.5 * kPhiPieces));
         pc = pc < 0 ? 0 : (pc >= kPhiPieces ? kPhiPieces - 1 : pc);
-        const double tt = (u + 1.0) * kPhiPieces - (2 * pc + 1);
+        const double tt = (u + 1.0) * (0.5 * kPhiPieces) - pc;
         double v = tab[(size_t)pc * (kPhiDeg + 1) + kPhiDeg];
         for (int k = kPhiDeg - 1; k >= 0; --k) v = std::fma(v, tt, tab[(size_t)pc * (kPhiDeg + 1) + k]);
         worst = std::max(worst, std::fabs(v - cheb_eval(ws.phi.data(), ws.n, u)));

@@ -65,7 +65,7 @@ static void check_window() {
     const double u = -1.0 + 2.0 * i / 4000.0;
     int pc = (int)((u + 1.0) * (0.5 * pieces));
     pc = std::min(std::max(pc, 0), pieces - 1);
-    const double t = (u + 1.0) * pieces - (2 * pc + 1);
+    const double t = (u + 1.0) * (0.5 * pieces) - pc;
     double v = tab[(size_t)pc * (deg + 1) + deg];
     for (int k = deg - 1; k >= 0; --k) v = std::fma(v, t, tab[(size_t)pc * (deg + 1) + k]);
     worst = std::max(worst, std::fabs(v - cheb_eval(ws.phi.data(), ws.n, u)));
