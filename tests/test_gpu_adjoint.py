@@ -214,50 +214,84 @@ def test_gradient_dense_nearby_coupling(wfp):
     assert eu < TOL and eb < TOL and ex < TOL
 
 
-def test_gradient_full_size_position_directional(wfp):
+def _clear_of_breaks(x, xr, j, h, prm, z):
+    """True if moving spring j by up to +-2h moves no pair distance with its
+    neighbours or the receivers across a point where Q_m(d) is not smooth: the
+    class switch d = dt, the window's end d = delta, or a node's stencil shift
+    (floor of s_q = W - (W - D)(1 + z_q)/2 changing, Section 4.1)."""
+    pts = np.concatenate([np.delete(x, j), xr])
+    d = np.abs(np.mod(pts - x[j] + np.pi, 2 * np.pi) - np.pi)
+    d = d[d < prm.delta + 3 * h]
+    if np.any(np.abs(d - prm.dt) < 3 * h) or np.any(np.abs(d - prm.delta) < 3 * h):
+        return False
+    base = np.floor(prm.W - (prm.W - d[:, None] / prm.dt) * (1 + z[None, :]) / 2)
+    for sg in (-2.0, 2.0):
+        D = (d + sg * h) / prm.dt
+        if np.any(np.floor(prm.W - (prm.W - D[:, None]) * (1 + z[None, :]) / 2) != base):
+            return False
+    return True
+
+
+def test_gradient_full_size_position_single_coordinates(wfp):
     """At the adjoint workload's full size (M = 1e5, R = 64) the position
     gradient against central differences of the GPU's own loss (its forward
-    march is parity-tested) over 1000 levels with checkpoints every 250,
-    along a smooth displacement field d_j = sin(1.3 x_j + 0.4): neighbours
-    move nearly together, so pair distances change by at most ~h delta and
-    the step h can be large enough for the differences of J (~1e-3, rounding
-    noise ~1e-16 relative over the march) to resolve the derivative.  Pairs
-    crossing the nearby/intermediate switch d = dt change their weights only
-    at the level of the interpolation error there.  Differences at h and h/2
-    are extrapolated (Richardson)."""
+    march is parity-tested) over 1000 levels with checkpoints every 250, one
+    spring at a time.  The discrete loss is piecewise smooth in the positions:
+    Q_m(d) jumps at the class switch d = dt and has a kink wherever a
+    quadrature node's p-point stencil shifts (Section 4.1), about once per dt
+    of distance per node, so with ~1400 neighbours per spring a difference
+    along all coordinates at once crosses many of them (the oracle's own
+    differences along a smooth direction over a dense slab settle 7e-4 away
+    from its gradient, while single clear coordinates agree to 6e-8).  Here:
+    the three springs of largest |dJ/dx_j| whose pairs stay clear of every
+    such point within +-2h (h = 1e-7), checked on the host, among those with
+    |dJ/dx_j| >= 5 % of the largest (the pulse reaches the edge of the medium
+    only; at ~1400 neighbours per spring few springs are clear).  Bound:
+    1e-6 |dJ/dx_j| plus the rounding floor of the difference of two losses,
+    4 eps J / (2 h).  The gradient formula itself is pinned in the dense
+    regime on the oracle (tests/test_oracle_adjoint.py) and the GPU matches the
+    oracle's gradient with dense coupling to 1e-13."""
     import torch
+    from oracle.params import Params
     from paper_2507_07823_amd import workloads
     p = workloads.adjoint_periodic()
-    n, every, h = 1000, 250, 1e-4
+    n, every, h = 1000, 250, 1e-7
     x0, M, R = p["x"], p["x"].size, p["x_recv"].size
     dt = p["dt"]
-    d = np.sin(1.3 * x0 + 0.4)
-    say(f"adjoint full size (positions): M={M} R={R} levels={n}, smooth direction, h={h}")
+    prm = Params(dt=dt)
+    z, _ = np.polynomial.legendre.leggauss(prm.n_gl_local)
 
     def loss(x):
-        q = dict(p, x=np.mod(x + np.pi, 2 * np.pi) - np.pi)     # the box is periodic
-        plan = wfp.Plan(q, dt, checkpoint_every=every)
+        plan = wfp.Plan(dict(p, x=np.mod(x + np.pi, 2 * np.pi) - np.pi), dt, checkpoint_every=every)   # periodic box
         u = torch.empty((n, R), dtype=torch.float64, device="cuda")
         plan.run(n, None, 1, u)
         J = 0.5 * dt * float((u * u).sum())
         return plan, u, J
 
-    plan, u, _ = loss(x0)
+    plan, u, J0 = loss(x0)
     _, gx = plan.gradient(dt * u, positions=True)
     gx = gx.cpu().numpy()
     plan.close()
-
-    def central(hh):
-        pl, _, jp = loss(x0 + hh * d)
+    gmax = float(np.abs(gx).max())
+    chosen = []
+    for j in np.argsort(-np.abs(gx)):
+        if abs(gx[j]) < 0.05 * gmax or len(chosen) == 3:
+            break
+        if _clear_of_breaks(x0, p["x_recv"], int(j), h, prm, z):
+            chosen.append(int(j))
+    floor = 4 * np.finfo(float).eps * J0 / (2 * h)
+    say(f"adjoint full size (positions): M={M} R={R} levels={n} J={J0:.6e} max|dJ/dx|={gmax:.3e}, "
+        f"springs {chosen}, h={h}, rounding floor {floor:.2e}")
+    assert len(chosen) >= 2
+    for j in chosen:
+        xp, xm = x0.copy(), x0.copy()
+        xp[j] += h
+        xm[j] -= h
+        pl, _, jp = loss(xp)
         pl.close()
-        pl, _, jm = loss(x0 - hh * d)
+        pl, _, jm = loss(xm)
         pl.close()
-        return (jp - jm) / (2 * hh)
-
-    f1, f2 = central(h), central(h / 2)
-    fd = (4 * f2 - f1) / 3
-    an = float(gx @ d)
-    say(f"  directional derivative: gradient {an:.12e}  central differences {f1:.12e} {f2:.12e}"
-        f"  extrapolated {fd:.12e}  rel {abs(fd - an) / abs(an):.2e}")
-    assert abs(an) > 0
-    assert abs(fd - an) <= 1e-4 * abs(an)
+        fd = (jp - jm) / (2 * h)
+        rel = abs(fd - gx[j]) / abs(gx[j])
+        say(f"  spring {j}: gradient {gx[j]:.12e}  central difference {fd:.12e}  rel {rel:.2e}")
+        assert abs(fd - gx[j]) <= 1e-6 * abs(gx[j]) + floor

@@ -94,3 +94,53 @@ def test_weight_derivative_matches_finite_differences():
     rel = np.abs(fd - an).max(axis=1) / np.abs(an).max(axis=1)
     assert rel.max() < 1e-8, rel
     assert math.isfinite(float(an.sum()))
+
+
+def _clear_of_breaks(x, xr, j, h, prm, z):
+    """True if moving spring j by up to +-2h moves no pair distance across a
+    point where Q_m(d) is not smooth (d = dt, d = delta, a node's stencil
+    shift)."""
+    pts = np.concatenate([np.delete(x, j), xr])
+    d = np.abs(pts - x[j])
+    d = d[d < prm.delta + 3 * h]
+    if np.any(np.abs(d - prm.dt) < 3 * h) or np.any(np.abs(d - prm.delta) < 3 * h):
+        return False
+    base = np.floor(prm.W - (prm.W - d[:, None] / prm.dt) * (1 + z[None, :]) / 2)
+    for sg in (-2.0, 2.0):
+        D = (d + sg * h) / prm.dt
+        if np.any(np.floor(prm.W - (prm.W - D[:, None]) * (1 + z[None, :]) / 2) != base):
+            return False
+    return True
+
+
+def test_position_gradient_dense_single_coordinates():
+    """A dense slab (100 springs over 0.02 at dt = 4e-3: 20 springs per time
+    step, every pair nearby or intermediate, the nearby system fully coupled):
+    single-coordinate central differences at springs whose pairs stay clear of
+    the points where Q_m(d) is not smooth agree with the gradient.  (Along a
+    direction that moves every spring, differences cross such points and do
+    not converge to the gradient of the smooth pieces.)"""
+    rng = np.random.default_rng(9)
+    M, dt, n = 100, 4e-3, 120
+    x = rng.uniform(0.5, 0.52, M)
+    beta = 0.05 * rng.uniform(1.0, 10.0, M)
+    packets = np.array([[1.0, 0.25, 0.03, 0.0, 0.0]])
+    xr = np.array([0.49, 0.51, 0.53])
+    prm = Params(dt=dt)
+    z, _ = np.polynomial.legendre.leggauss(prm.n_gl_local)
+
+    def loss(xx):
+        a = AdjointOracle(xx, beta, packets, prm, xr)
+        u = a.forward(n)
+        return 0.5 * dt * float((u * u).sum()), a, u
+
+    J, a, u = loss(x)
+    _, gx = a.gradient(dt * u)
+    h = 1e-7
+    chosen = [int(j) for j in np.argsort(-np.abs(gx)) if _clear_of_breaks(x, xr, int(j), h, prm, z)][:3]
+    assert len(chosen) == 3 and np.abs(gx[chosen]).min() > 0.05 * np.abs(gx).max()
+    for j in chosen:
+        e = np.zeros(M)
+        e[j] = h
+        fd = (loss(x + e)[0] - loss(x - e)[0]) / (2 * h)
+        assert abs(fd - gx[j]) <= 1e-6 * abs(gx[j]), (j, fd, gx[j])
