@@ -773,10 +773,9 @@ k_local_deriv2(int M, int NQ, int NH, const int* __restrict__ nb_start, const in
 //   row j:  sum_i om_i(d) sum_r v_{i,r} sigma_l^{L-m0_i-r},
 //   row l:  sum_i om_i(d) sum_r v_{i,r} sigma_j^{L-m0_i-r},
 // with the P lags from m0_i = max(m_min, floor(s_i) - P/2 + 1) (lag 0 taken as
-// 0: it belongs to the implicit solve) and the Lagrange weights at u = s_i - m0_i
-//   v_r = [prod_{k<r} (u - k)/r!] [prod_{k>r} (k - u)/(P-1-r)!],
-// formed as products of a prefix and a suffix (the node weight om_i folded
-// into the suffix).  Sources are taken in sorted order: row j walks its upper
+// 0: it belongs to the implicit solve) and the Lagrange weights v_{i,r} of
+// those lags at u = s_i - m0_i (SymLagrange below).  Sources are taken in
+// sorted order: row j walks its upper
 // range, the springs from j (itself, once) up to the first one beyond delta
 // (unwrapped: periodic ranges continue past M - 1 at 0).  Every unordered pair
 // lies in exactly one upper range because delta < pi.
@@ -787,32 +786,53 @@ k_local_deriv2(int M, int NQ, int NH, const int* __restrict__ nb_start, const in
 // block's wavefronts in LDS in a fixed order and written to
 // part[part_off[b] + (u - j0)] for the block's unwrapped source u;
 // k_local_otf_reduce adds them up per row.
-// Lagrange weights at u as prefix times suffix products:
-//   v_r = lambda_0 [(lambda_r / lambda_0) prod_{k<r} (u - k)] [prod_{k>r} (k - u)],
-//   lambda_r = 1 / (r! (P-1-r)!),
-// the ratio lambda_r / lambda_0 carried by the prefix (its factor for k = r is
-// rho_r (u - r) = fma(u, rho_r, -r rho_r), rho_r = (P-1-r)/(r+1)) and
-// lambda_0 = 1/(P-1)! by the pair's span, once per pair.  The suffix factors
-// (k - u) take one scalar constant each.  The P - 1 prefix factor pairs are
-// held in registers across the node loop (as operands an FMA would read two
-// scalar constants, one over the constant-bus limit, and cost a register
-// copy each).
+// Lagrange weights of the P equispaced stencil lags in the centred variable
+// y = u - (P-1)/2, whose nodes pair up as -a_j, +a_j, a_j = j + 1/2
+// (j = 0..P/2-1; lag r < P/2 and lag P-1-r share j = P/2-1-r):
+//   v_r = lambda_r (y - a_j) Q_j,   v_{P-1-r} = -lambda_r (y + a_j) Q_j,
+//   Q_j = prod_{i != j} (y^2 - a_i^2),   lambda_r = (-1)^{P-1-r} / (r! (P-1-r)!),
+// Q_j as products of a prefix and a suffix over i.  Every constant is a
+// scalar operand of its instruction (one per instruction); the -a_j^2 are
+// held in scalar registers by the caller (as immediates the compiler would
+// rebuild them in vector registers at every node).
 template <int P>
-struct LagFactors {
-  double ca[P - 1], cb[P - 1];
-  __device__ __forceinline__ void init() {
+struct SymLagrange {
+  static constexpr int H = P / 2;
+  static constexpr double a(int j) { return j + 0.5; }
+  struct Squares {
+    double na2[H];
+    __device__ __forceinline__ void init() {
 #pragma unroll
-    for (int r = 0; r < P - 1; ++r) {
-      const double rho = (double)(P - 1 - r) / (r + 1);
-      ca[r] = rho;
-      cb[r] = -r * rho;
-      asm volatile("" : "+v"(ca[r]), "+v"(cb[r]));
+      for (int j = 0; j < H; ++j) {
+        na2[j] = -a(j) * a(j);
+        asm volatile("" : "+s"(na2[j]));
+      }
     }
+  };
+  static constexpr double lambda(int r) {
+    double f = 1.0;
+    for (int k = 2; k <= r; ++k) f *= k;
+    for (int k = 2; k <= P - 1 - r; ++k) f *= k;
+    return ((P - 1 - r) % 2 ? -1.0 : 1.0) / f;
   }
-  static constexpr double lambda0() {
-    double l = 1.0;
-    for (int k = 2; k < P; ++k) l /= k;
-    return l;
+  __device__ __forceinline__ static void weights(double y, const Squares& sq, double (&w)[P]) {
+    double e[H], pre[H], suf[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) e[j] = fma(y, y, sq.na2[j]);
+    pre[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j < H; ++j) pre[j] = pre[j - 1] * e[j - 1];
+    suf[H - 1] = 1.0;
+#pragma unroll
+    for (int j = H - 2; j >= 0; --j) suf[j] = suf[j + 1] * e[j + 1];
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      const int j = H - 1 - r;
+      const double t = lambda(r) * (pre[j] * suf[j]);
+      const double ta = t * a(j);
+      w[r] = fma(t, y, -ta);
+      w[P - 1 - r] = fma(-t, y, -ta);
+    }
   }
 };
 
@@ -820,15 +840,16 @@ template <int P>
 __device__ __forceinline__ void sym_node(double Dm, double span, int mmin, double na_q, double nw_q,
                                          const double* __restrict__ tab, double Wd, double pw,
                                          const double* __restrict__ sgk, const double* __restrict__ rh,
-                                         const LagFactors<P>& lf, double& acc_a, double& acc_c) {
+                                         const typename SymLagrange<P>::Squares& sq, double& acc_a,
+                                         double& acc_c) {
   const double s = fma(Dm, na_q, Wd);         // W - (W - D)(1 + z_q)/2, in [0, W]
   // window piece: pc covers s in [pc, pc + 1) / pw, its polynomial in the
   // local variable x = v - pc (coefficients loaded here and used last, so the
   // loads overlap the interpolation).  v = pw W (s = W, only where the pair's
   // span rounds to 0) takes the last piece at x = 0, a weight-zero node.
   const double v = s * pw;
-  int pc = (int)v;
-  pc = pc >= kPhiPieces ? kPhiPieces - 1 : pc;
+  unsigned pc = (unsigned)v;
+  pc = pc >= (unsigned)kPhiPieces ? kPhiPieces - 1 : pc;
   const double* c = tab + pc * (kPhiDeg + 1);
   double cf[kPhiDeg + 1];
 #pragma unroll
@@ -848,20 +869,13 @@ __device__ __forceinline__ void sym_node(double Dm, double span, int mmin, doubl
     fa[r] = sp[r * kOtfChunk];
     fc[r] = rp[r];
   }
-  const double u = s - m0;
-  double A[P], B[P];
-  A[0] = 1.0;
-#pragma unroll
-  for (int r = 0; r < P - 1; ++r) A[r + 1] = A[r] * fma(u, lf.ca[r], lf.cb[r]);
-  B[P - 1] = 1.0;
-#pragma unroll
-  for (int r = P - 2; r >= 0; --r) B[r] = B[r + 1] * ((double)(r + 1) - u);
+  double w[P];
+  SymLagrange<P>::weights(s - (m0 + 0.5 * (P - 1)), sq, w);
   double pa = 0.0, pcl = 0.0;
 #pragma unroll
   for (int r = 0; r < P; ++r) {
-    const double w = A[r] * B[r];
-    pa = fma(w, fa[r], pa);
-    pcl = fma(w, fc[r], pcl);
+    pa = fma(w[r], fa[r], pa);
+    pcl = fma(w[r], fc[r], pcl);
   }
   double ph = cf[kPhiDeg];
 #pragma unroll
@@ -903,8 +917,8 @@ __device__ __forceinline__ void k_local_otf_sym_body(int M, int NH, int NQ, int6
   const double Wd = (double)W;
   const double pw = (double)kPhiPieces / Wd;
   const int64_t pbase = part_off[b];
-  LagFactors<P> lf;
-  lf.init();
+  typename SymLagrange<P>::Squares sq;
+  sq.init();
   double acc = 0.0;
   for (long long cb = j0; cb < uend; cb += kOtfChunk) {
     __syncthreads();   // the previous chunk is no longer read
@@ -926,9 +940,9 @@ __device__ __forceinline__ void k_local_otf_sym_body(int M, int NH, int NQ, int6
       const int k = (int)(ua - cb);
       const double Dm = on ? d / dt - Wd : -0.5 * Wd;    // off: D = W/2, nodes inside (0, W), zero weight
       const int mmin = (on && d < dt) ? 0 : 1;
-      const double span = on ? (delta - d) * LagFactors<P>::lambda0() : 0.0;
+      const double span = on ? delta - d : 0.0;
       double pa = 0.0, pcol = 0.0;
-      for (int q = 0; q < ngl; ++q) sym_node<P>(Dm, span, mmin, na[q], nw[q], tab, Wd, pw, sg + k, rh[wv], lf, pa, pcol);
+      for (int q = 0; q < ngl; ++q) sym_node<P>(Dm, span, mmin, na[q], nw[q], tab, Wd, pw, sg + k, rh[wv], sq, pa, pcol);
       acc += pa;
       if (ua != (long long)j) colp[wv * kOtfChunk + k] = pcol;
     }
