@@ -123,7 +123,31 @@ def spring_array_transmission(w, xs, beta):
     return out
 
 
-def spring_array_field(xr, t, xs, beta, mu, t0, w_max=None, dw=None):
+def spring_chain_transmission(w, xs, beta):
+    """T(w) as spring_array_transmission, by transfer matrices instead of
+    the dense solve: in the frequency domain u'' + w^2 u = sum_j beta_j u(x_j)
+    delta(x - x_j) (the Green's function's jump -1 in u'), so crossing spring
+    j from right to left keeps u and lowers u' by beta_j u(x_j), and between
+    springs (u, u') propagates freely.  Starting from u = e^{iwx} right of the
+    last spring, the state left of the first one is a e^{iwx} + b e^{-iwx};
+    T = 1/a.  O(M) per frequency; xs need not be sorted."""
+    order = np.argsort(np.asarray(xs, dtype=np.float64))
+    xs = np.asarray(xs, dtype=np.float64)[order]
+    beta = np.asarray(beta, dtype=np.float64)[order]
+    w = np.asarray(w, dtype=np.float64)
+    u = np.exp(1j * w * xs[-1])
+    du = 1j * w * u
+    for j in range(xs.size - 1, -1, -1):
+        du = du - beta[j] * u                       # across spring j, right to left
+        if j > 0:
+            h = xs[j] - xs[j - 1]                   # back to spring j - 1
+            c, sn = np.cos(w * h), np.sin(w * h)
+            u, du = c * u - sn / w * du, w * sn * u + c * du
+    a = 0.5 * (u + du / (1j * w)) * np.exp(-1j * w * xs[0])
+    return 1.0 / a
+
+
+def spring_array_field(xr, t, xs, beta, mu, t0, w_max=None, dw=None, transmission=None):
     """Total field u_inc + u at a point xr to the right of every spring, for
     the free-space springs xs, beta and the incident wave f(x - t) with
     f(s) = exp(-mu (s - t0)^2), at times t: the inverse transform of
@@ -132,7 +156,8 @@ def spring_array_field(xr, t, xs, beta, mu, t0, w_max=None, dw=None):
     e^{-w^2/(4 mu)}, by the trapezoid rule on a midpoint grid of |w| <= w_max
     (the spectrum falls like e^{-w^2/(4 mu)}); it converges geometrically while
     dw is well below the width of the sharpest resonance (the resonances are
-    poles a distance ~ that width off the real axis)."""
+    poles a distance ~ that width off the real axis).  `transmission` is
+    spring_array_transmission (default) or spring_chain_transmission."""
     t = np.atleast_1d(np.asarray(t, dtype=np.float64))
     if w_max is None:
         w_max = math.sqrt(4.0 * mu * 40.0)              # e^{-40} of the peak
@@ -141,7 +166,7 @@ def spring_array_field(xr, t, xs, beta, mu, t0, w_max=None, dw=None):
     n = int(math.ceil(w_max / dw))
     w = (np.arange(n) + 0.5) * dw                       # w > 0; w < 0 by conjugate symmetry
     F = math.sqrt(math.pi / mu) * np.exp(-1j * w * t0 - w * w / (4.0 * mu))
-    U = spring_array_transmission(w, xs, beta) * F * np.exp(1j * w * xr)
+    U = (transmission or spring_array_transmission)(w, xs, beta) * F * np.exp(1j * w * xr)
     # u(t) = (1/2pi) int U e^{-iwt} dw = (1/pi) Re int_0^inf U e^{-iwt} dw
     out = np.empty(t.size)
     for i, tt in enumerate(t):

@@ -158,3 +158,22 @@ def test_frequency_domain_field_of_springs():
     tot = ur[lv, 0] + np.exp(-mu * (xr - tt - t0) ** 2)
     ex = spring_array_field(xr, tt, x, beta, mu, t0, dw=1e-3)
     assert np.max(np.abs(tot - ex)) < 1e-9 * np.max(np.abs(ex))
+
+
+def test_chain_transmission_matches_the_dense_solve():
+    """Transfer matrices (spring_chain_transmission) against the dense
+    frequency-domain solve (spring_array_transmission) for the ten-spring
+    array of stiffness 100 and unsorted random springs, and the one-spring
+    closed form T = 2iw / (2iw - beta)."""
+    from oracle.exact import spring_array_transmission, spring_chain_transmission
+    w = np.linspace(0.05, 25.0, 997)
+    T1 = spring_chain_transmission(w, [0.7], [3.0])
+    assert np.max(np.abs(T1 - 2j * w / (2j * w - 3.0))) < 1e-14
+    cases = [(np.linspace(-1.0, 1.0, 10), np.full(10, 100.0))]
+    rng = np.random.default_rng(3)
+    for M in (2, 7, 15):
+        cases.append((rng.uniform(-1.0, 1.0, M), rng.uniform(0.1, 20.0, M)))
+    for x, beta in cases:
+        Td = spring_array_transmission(w, x, beta)
+        Tc = spring_chain_transmission(w, x, beta)
+        assert np.max(np.abs(Tc - Td)) < 1e-11 * max(1.0, np.max(np.abs(Td))), x.size
