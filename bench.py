@@ -159,6 +159,9 @@ def counters_summary(dirs, kernel, avg_ms, pairs, nodes=35):
     f64 = vals["SQ_INSTS_VALU_FMA_F64"] + vals["SQ_INSTS_VALU_ADD_F64"] + vals["SQ_INSTS_VALU_MUL_F64"]
     lines = [f"kernel: {kernel}", f"kernel_source_sha256: {kernel_source_hash(kernel)}", f"dispatches: {n}", ""]
     lines += [f"{c}: {v:.6g}" for c, v in sorted(vals.items())]
+    if "SQ_LDS_IDX_ACTIVE" in vals:
+        lines.append(f"LDS_busy (SQ_LDS_IDX_ACTIVE per CU-cycle): "
+                     f"{vals['SQ_LDS_IDX_ACTIVE'] / 256 / (vals['GRBM_GUI_ACTIVE'] / 8):.3f}")
     lines += [
         f"VALU_busy: {busy:.3f}",
         f"VALU_lanes_active: {vals['SQ_THREAD_CYCLES_VALU'] / (64 * vals['SQ_ACTIVE_INST_VALU']):.4f}",
@@ -802,9 +805,10 @@ def main():
                                                        "KERNEL"),
                     help="print the traffic summary of rocprofv3 --pmc runs and exit")
     ap.add_argument("--stats-summary", metavar="DIR", help="print a rocprofv3 --stats table and exit")
-    ap.add_argument("--counters-summary", nargs=5, metavar=("DIR1", "DIR2", "KERNEL", "AVG_MS", "PAIRS"),
-                    help="print the counters of KERNEL from two rocprofv3 --pmc runs, with the VALU/LDS/FP64 "
-                         "figures derived at a launch time of AVG_MS over PAIRS ordered neighbour pairs, and exit")
+    ap.add_argument("--counters-summary", nargs="+", metavar="ARG",
+                    help="DIR [DIR ...] KERNEL AVG_MS PAIRS: print the counters of KERNEL from rocprofv3 --pmc "
+                         "runs, with the VALU/LDS/FP64 figures derived at a launch time of AVG_MS over PAIRS "
+                         "ordered neighbour pairs, and exit")
     ap.add_argument("--trace-tail", nargs=3, metavar=("DIR", "KERNEL", "N"),
                     help="print the mean duration of the last N dispatches of KERNEL in a kernel trace and exit")
     args = ap.parse_args()
@@ -815,8 +819,8 @@ def main():
         print(stats_summary(args.stats_summary))
         return
     if args.counters_summary:
-        d1, d2, k, ms, pairs = args.counters_summary
-        print(counters_summary([d1, d2], k, float(ms), float(pairs)))
+        *dirs, k, ms, pairs = args.counters_summary
+        print(counters_summary(dirs, k, float(ms), float(pairs)))
         return
     if args.trace_tail:
         d, k, n = args.trace_tail
