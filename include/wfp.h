@@ -101,8 +101,12 @@ typedef struct {
                               library's choice, which is one XCD's compute units when the local
                               sum reads at least 64 MB per level, else one stream   [0] */
   int32_t local_mode;      /* 1: local weights stored per pair (read every level); 2: evaluated on the
-                              fly every level (memory O(M), arithmetic O(pairs N_L p)); 0: stored when
-                              they fit in 60% of the free device memory, else on the fly   [0] */
+                              fly every level (memory O(M), arithmetic O(pairs N_L p)); 3: stored once
+                              per unordered pair (Q_m depends on the distance alone) and applied to
+                              both rows, about half the bytes of 1, no gradient pass (wfp_adjoint
+                              returns WFP_EDOMAIN) and not in batches; 0: stored (1) when they fit in
+                              60% of the free device memory, else 3 when half of that fits and
+                              checkpoint_every is 0, else on the fly   [0] */
   int32_t check_finite;    /* nonzero: every wfp_run ends by checking the newest density level and the
                               mode state alpha, alpha' for NaN or Inf (one small kernel), waits for the
                               plan's stream and returns WFP_ENONFINITE if any is found (the levels stay
@@ -121,7 +125,8 @@ typedef struct {
   int32_t solve_mode;          /* 0: dense inverses of small nearby-runs and LDS tiles,
                                   1: global Jacobi sweeps (dense nearby coupling) */
   int32_t overlap_cus;         /* compute units of the concurrent history chain, -1: one stream */
-  int32_t local_mode;          /* 1: stored local weights, 2: evaluated on the fly */
+  int32_t local_mode;          /* 1: stored local weights, 2: evaluated on the fly, 3: stored once per
+                                  unordered pair */
   int32_t reserved;
   int64_t n_weights_lag1;      /* nonzero stored local weights of lag 1 (part of n_weights_nonzero) */
   int32_t n_solve_tiles;       /* solve_mode 0: LDS tiles of the Jacobi solve (long nearby runs) */

@@ -497,6 +497,10 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
       g_last_error = "the batched form covers periodic problems";
       return WFP_EDOMAIN;
     }
+    if (pars[i].local_mode == 3) {
+      g_last_error = "the batched form takes local_mode 0, 1 or 2";
+      return WFP_EDOMAIN;
+    }
   }
   wfp_batch* B = new wfp_batch();
   wfp_status st = guard([&] {

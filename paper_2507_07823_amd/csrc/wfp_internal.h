@@ -181,6 +181,16 @@ struct wfp_plan {
   int solve_threads = 64;
   // local weights evaluated on the fly (when the stored ones would not fit)
   bool otf = false;
+  // local_mode 3: the on-the-fly layout (upper ranges, partials, lag-0
+  // nearby weights) with the local sum's weights stored once per unordered
+  // pair: per row and lag a run over the first sources of its upper range
+  bool sym_stored = false;
+  int64_t* sym_rb = nullptr;      // row j's first weight in sym_q
+  uint2* sym_acx = nullptr;       // (count, offset within the row) per (row, lag)
+  double* sym_q = nullptr;
+  int64_t* sym_upb = nullptr;     // row j's first pair in sym_colpart
+  double* sym_colpart = nullptr;  // per upper pair: the column term (row l's share)
+  int2* sym_cov = nullptr;        // per row: first covering row below it, first wrapped one
   double *otf_z = nullptr, *otf_w = nullptr, *phitab = nullptr, *half_beta = nullptr;
   double* halfs = nullptr;       // 1/2 per row (the local part without beta)
   // symmetric on-the-fly local sum: per row the unwrapped end of its upper

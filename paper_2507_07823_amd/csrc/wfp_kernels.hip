@@ -974,6 +974,93 @@ k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end
                           phitab, rowacc, part, b);
 }
 
+// Local sum of lags m >= 1 from stored weights, each unordered pair once.
+// One wavefront per row j walks its upper range [j, up_end[j]) (unwrapped:
+// periodic ranges continue past M - 1 at 0), lanes over the sources, lags in
+// groups of eight with every load of a group issued before its use.  Row j's
+// weights are one run per lag m over the first c_jm sources of the range
+// (those whose stencils reach lag m: a prefix, as the distance grows along the
+// range), at Qs[rb[j] + o_jm + i], sacx[j NQ + m] = (c_jm, o_jm), unscaled.
+// The row's own sum sum_m sum_i Q sigma_l goes to rowacc[j]; each pair's
+// column term sum_m Q sigma_j^{L-m} (row l's share) to colpart[upb[j] + i]
+// (0 for the row itself); k_local_sym_reduce adds them up per row.
+__global__ void __launch_bounds__(256)
+k_local_sym_rows(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end, const double* __restrict__ hist,
+                 const int64_t* __restrict__ rb, const uint2* __restrict__ sacx, const double* __restrict__ Qs,
+                 const int64_t* __restrict__ upb, double* __restrict__ rowacc, double* __restrict__ colpart) {
+  __shared__ double rv[4][kMaxOtfLags + 1];                   // each row's own history, lags 0 .. NQ - 1
+  __shared__ uint2 cw[4][kMaxOtfLags + 1];
+  __shared__ int64_t slot[kMaxOtfLags + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nb = gridDim.x;
+  const int j = xcd_block(blockIdx.x, nb) * 4 + wv;
+  for (int m = threadIdx.x; m < NQ; m += blockDim.x) slot[m] = (int64_t)mod_slot(L - m, NH) * M;
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4 * NQ; e += blockDim.x) {
+    const int w = e / NQ, m = e - w * NQ;
+    const int jr = xcd_block(blockIdx.x, nb) * 4 + w;
+    const bool ok = m >= 1 && jr < M;
+    rv[w][m] = ok ? hist[slot[m] + jr] : 0.0;
+    cw[w][m] = ok ? sacx[(int64_t)jr * NQ + m] : make_uint2(0u, 0u);
+  }
+  __syncthreads();
+  if (j >= M) return;                                         // no barrier below
+  const int n = up_end[j] - j;
+  const double* __restrict__ qrow = Qs + rb[j];
+  double* __restrict__ cp = colpart + upb[j];
+  double acc = 0.0;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    const bool in = i < n;
+    int l = j + i;
+    if (l >= M) l -= M;
+    double pc = 0.0;
+    for (int mb = 1; mb < NQ; mb += 8) {
+      double w[8], h[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int m = mb + r;
+        const uint2 c = m < NQ ? cw[wv][m] : make_uint2(0u, 0u);
+        const bool on = in && i < (int)c.x;
+        w[r] = on ? qrow[c.y + i] : 0.0;
+        h[r] = on ? hist[slot[m] + l] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int m = mb + r;
+        if (m < NQ) {
+          acc = fma(w[r], h[r], acc);
+          pc = fma(w[r], rv[wv][m], pc);
+        }
+      }
+    }
+    if (in) cp[i] = i == 0 ? 0.0 : pc;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) rowacc[j] = acc;
+}
+
+// Row l's total of the pair-once stored local sum: its own sum plus the column
+// terms of the rows whose upper range covers it: rows cov[l].x .. l - 1 (up_end
+// is non-decreasing, so they are consecutive) and, in the periodic box, rows
+// cov[l].y .. M - 1 whose range wraps to l + M.  One wavefront per row, lanes
+// over the covering rows, added in a fixed order (lane sums, then a fixed
+// tree); scaled per row.
+__global__ void __launch_bounds__(256)
+k_local_sym_reduce(int M, const int2* __restrict__ cov, const int64_t* __restrict__ upb,
+                   const double* __restrict__ rowacc, const double* __restrict__ colpart,
+                   const double* __restrict__ scale, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= M) return;
+  const int2 c = cov[l];
+  double acc = 0.0;
+  for (int jr = c.x + lane; jr < l; jr += 64) acc += colpart[upb[jr] + (l - jr)];
+  for (int jr = c.y + lane; jr < M; jr += 64) acc += colpart[upb[jr] + ((long long)l + M - jr)];
+  acc = wave_sum(acc);
+  if (lane == 0) out[l] = scale[l] * (rowacc[l] + acc);
+}
+
 // Row l's total of the symmetric local sum: its own upper-range sum plus the
 // column sums that the blocks covering l wrote for it (blocks at or below
 // l's own whose source range reaches l, and in the periodic box the blocks

@@ -91,7 +91,7 @@ void validate(const wfp_problem* prob, const wfp_params* par) {
   if (par->eps_window < 0 || !(par->eps_window < 1) || par->gamma < 0 || !(par->gamma < 1))
     fail(WFP_EINVAL, "eps_window and gamma must lie in [0, 1)");
   if (par->W < 0 || par->K < 0 || par->n_gl_local < 0 || par->n_gl_pq < 0 || par->rbc_period < 0 ||
-      par->solve_iters < 0 || par->checkpoint_every < 0 || par->local_mode < 0 || par->local_mode > 2)
+      par->solve_iters < 0 || par->checkpoint_every < 0 || par->local_mode < 0 || par->local_mode > 3)
     fail(WFP_EINVAL, "negative size parameter");
   const int p = par->p > 0 ? par->p : 8;
   if (par->p < 0 || p % 2 || p < 2 || p > kMaxP) fail(WFP_EINVAL, "p must be even, 2..12");
@@ -551,12 +551,18 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   {
     int mode = par->local_mode;
     if (mode == 0) {
+      // per ordered pair when the dense set-up array and the packed weights
+      // fit; else once per unordered pair (about half of both; no gradient
+      // pass, so only without checkpoints); else on the fly
       size_t fr = 0, to = 0;
       HIPCHK(hipMemGetInfo(&fr, &to));
-      const double need = 8.0 * (double)tot * 1.7;    // dense set-up array + packed weights
-      mode = need < 0.6 * (double)fr ? 1 : 2;
+      const double need = 8.0 * (double)tot * 1.7;
+      if (need < 0.6 * (double)fr) mode = 1;
+      else if (par->checkpoint_every == 0 && 0.5 * need < 0.6 * (double)fr) mode = 3;
+      else mode = 2;
     }
-    P->otf = mode == 2;
+    P->otf = mode == 2 || mode == 3;
+    P->sym_stored = mode == 3;
   }
   // on the fly: only the lag-0 weights of nearby pairs are stored (for the solve)
   std::vector<int64_t> qoN(M);
@@ -658,6 +664,88 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
       upload(P->otf_up_end, up, s);
       upload(P->otf_blk_end, be, s);
       upload(P->otf_part_off, po, s);
+      if (P->sym_stored) {
+        // weights of each unordered pair once: row j against its upper range
+        // [j, up[j]) (dense, lag-major, unscaled), then per lag the run of
+        // sources that carry it (from the row itself), packed
+        std::vector<int> ust(M), ucnt(M);
+        std::vector<int64_t> uoff(M), upb(M);
+        std::vector<double> ones(M, 1.0);
+        int64_t tot_up = 0, np_up = 0;
+        for (int64_t j = 0; j < M; ++j) {
+          ust[j] = (int)j;
+          ucnt[j] = up[j] - (int)j;
+          if (ucnt[j] >= 65536) fail(WFP_EDOMAIN, "more than 65535 upper neighbours of one scatterer");
+          uoff[j] = tot_up;
+          upb[j] = np_up;
+          tot_up += (int64_t)ucnt[j] * P->NQ;
+          np_up += ucnt[j];
+        }
+        int* ust_d = P->alloc<int>(M);
+        int* ucnt_d = P->alloc<int>(M);
+        int64_t* uoff_d = P->alloc<int64_t>(M);
+        int64_t* upb_d = P->alloc<int64_t>(M);
+        double* ones_d = P->alloc<double>(M);
+        signed char* umlo = P->alloc<signed char>(np_up);
+        double* dense = P->alloc<double>(tot_up);
+        unsigned* uac = P->alloc<unsigned>((size_t)M * P->NQ);
+        upload(ust_d, ust, s);
+        upload(ucnt_d, ucnt, s);
+        upload(uoff_d, uoff, s);
+        upload(upb_d, upb, s);
+        upload(ones_d, ones, s);
+        launch_local_weights(P, (int)M, P->xs, ust_d, ucnt_d, uoff_d, ones_d, 0, upb_d, umlo, dense);
+        hipLaunchKernelGGL(k_row_ranges, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ,
+                           ucnt_d, upb_d, umlo, uac);
+        HIPCHK(hipGetLastError());
+        std::vector<unsigned> ach((size_t)M * P->NQ);
+        HIPCHK(hipMemcpyAsync(ach.data(), uac, ach.size() * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<int64_t> rb(M);
+        std::vector<uint2> acxh((size_t)M * P->NQ);
+        int64_t packed = 0;
+        for (int64_t j = 0; j < M; ++j) {
+          rb[j] = packed;
+          unsigned within = 0;
+          for (int m = 0; m < P->NQ; ++m) {
+            const unsigned v = ach[(size_t)j * P->NQ + m];
+            const unsigned c = m >= 1 ? v >> 16 : 0u;
+            if (c > 0 && (v & 0xffffu) != 0)
+              fail(WFP_EINVAL, "stored pair-once weights: a lag's sources do not start at the row");
+            acxh[(size_t)j * P->NQ + m] = make_uint2(c, within);
+            within += c;
+          }
+          packed += within;
+        }
+        P->sym_rb = P->alloc<int64_t>(M);
+        P->sym_acx = P->alloc<uint2>(acxh.size());
+        P->sym_q = P->alloc<double>(packed + 2);
+        upload(P->sym_rb, rb, s);
+        upload(P->sym_acx, acxh, s);
+        hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ,
+                           1, ucnt_d, uoff_d, dense, uac, P->sym_rb, P->sym_q);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+        P->n_weights_stored = packed;
+        P->sym_upb = upb_d;
+        P->sym_colpart = P->alloc<double>(np_up);
+        // rows covering row l: j < l with up[j] > l, and j > l with up[j] > l + M
+        // (periodic); up is non-decreasing, so each is a run ending at l - 1 or M - 1
+        std::vector<int2> cov(M);
+        {
+          int64_t a = 0, b = 0;
+          for (int64_t l = 0; l < M; ++l) {
+            while (a < l && up[a] <= l) ++a;
+            while (b < M && (int64_t)up[b] <= l + M) ++b;
+            cov[l] = make_int2((int)a, periodic ? (int)std::max<int64_t>(b, l + 1) : (int)M);
+          }
+        }
+        P->sym_cov = P->alloc<int2>(M);
+        upload(P->sym_cov, cov, s);
+        for (void* q : {(void*)dense, (void*)uac, (void*)umlo, (void*)ust_d, (void*)ucnt_d, (void*)uoff_d,
+                        (void*)ones_d})
+          P->release(q);
+      }
     }
     P->otf_z = P->alloc<double>(P->ngl);
     P->otf_w = P->alloc<double>(P->ngl);
@@ -1155,6 +1243,14 @@ void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
                         (int)P->M, P->NH, P->NQ, L, P->otf_up_end, P->otf_blk_end, P->otf_part_off, P->otf_nblk,  \
                         P->xs, hist, periodic, P->dt, P->delta, P->W, P->ngl, P->otf_na, P->otf_nw, P->phitab,  \
                         P->otf_rowacc, P->otf_part)
+  if (P->sym_stored) {
+    hipExtLaunchKernelGGL(k_local_sym_rows, dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
+                          (int)P->M, P->NH, P->NQ, L, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
+                          P->sym_upb, P->otf_rowacc, P->sym_colpart);
+    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 4)), dim3(256), 0, s, nullptr, eb, 0, (int)P->M,
+                          P->sym_cov, P->sym_upb, P->otf_rowacc, P->sym_colpart, scale, out);
+    return;
+  }
   switch (P->p) {
     case 2: WFP_OTF(2); break;
     case 4: WFP_OTF(4); break;
@@ -1801,7 +1897,7 @@ wfp_status wfp_plan_info(const wfp_plan* P, wfp_info* info) {
   info->n_weights_stored = P->n_weights_stored;
   info->solve_mode = P->solve_global ? 1 : 0;
   info->overlap_cus = P->overlap_cus;
-  info->local_mode = P->otf ? 2 : 1;
+  info->local_mode = P->sym_stored ? 3 : (P->otf ? 2 : 1);
   info->n_weights_lag1 = P->n_weights_lag1;
   info->n_solve_tiles = P->solve_global ? 0 : P->ntile;
   info->n_direct_tiles = P->solve_global ? 0 : P->n_direct_tiles;
