@@ -974,6 +974,47 @@ k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end
                           phitab, rowacc, part, b);
 }
 
+// Row l's total of the symmetric local sum: its own upper-range sum plus the
+// column sums that the blocks covering l wrote for it (blocks at or below
+// l's own whose source range reaches l, and in the periodic box the blocks
+// whose range wraps past M - 1 to l + M), in a fixed order; scaled per row.
+__device__ __forceinline__ void k_local_otf_reduce_body(int M, int nblk_rows, int periodic,
+                                                        const int* __restrict__ blk_end,
+                                                        const int64_t* __restrict__ part_off,
+                                                        const double* __restrict__ rowacc,
+                                                        const double* __restrict__ part,
+                                                        const double* __restrict__ scale, double* __restrict__ out,
+                                                        int bid) {
+  const int l = bid * 256 + threadIdx.x;
+  if (l >= M) return;
+  double acc = rowacc[l];
+  for (int b = l / kOtfRows; b >= 0 && blk_end[b] > l; --b) acc += part[part_off[b] + (l - b * kOtfRows)];
+  if (periodic) {
+    const long long lw = (long long)l + M;
+    for (int b = nblk_rows - 1; b >= 0 && blk_end[b] > lw; --b) acc += part[part_off[b] + (lw - (long long)b * kOtfRows)];
+  }
+  out[l] = scale[l] * acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_local_otf_reduce(int M, int nblk_rows, int periodic, const int* __restrict__ blk_end,
+                   const int64_t* __restrict__ part_off, const double* __restrict__ rowacc,
+                   const double* __restrict__ part, const double* __restrict__ scale, double* __restrict__ out) {
+  k_local_otf_reduce_body(M, nblk_rows, periodic, blk_end, part_off, rowacc, part, scale, out, blockIdx.x);
+}
+
+#define WFP_OTFS_INST(PP)                                                                                      \
+  template __global__ void k_local_otf_sym<PP>(int, int, int, int64_t, const int*, const int*, const int64_t*, \
+                                               int, const double*, const double*, int, double, double, int, int, \
+                                               const double*, const double*, const double*, double*, double*);
+WFP_OTFS_INST(2)
+WFP_OTFS_INST(4)
+WFP_OTFS_INST(6)
+WFP_OTFS_INST(8)
+WFP_OTFS_INST(10)
+WFP_OTFS_INST(12)
+#undef WFP_OTFS_INST
+
 // Local sum of lags m >= 1 from stored weights, each unordered pair once.
 // One wavefront per row j walks its upper range [j, up_end[j]) (unwrapped:
 // periodic ranges continue past M - 1 at 0), lanes over the sources, lags in
@@ -1061,46 +1102,6 @@ k_local_sym_reduce(int M, const int2* __restrict__ cov, const int64_t* __restric
   if (lane == 0) out[l] = scale[l] * (rowacc[l] + acc);
 }
 
-// Row l's total of the symmetric local sum: its own upper-range sum plus the
-// column sums that the blocks covering l wrote for it (blocks at or below
-// l's own whose source range reaches l, and in the periodic box the blocks
-// whose range wraps past M - 1 to l + M), in a fixed order; scaled per row.
-__device__ __forceinline__ void k_local_otf_reduce_body(int M, int nblk_rows, int periodic,
-                                                        const int* __restrict__ blk_end,
-                                                        const int64_t* __restrict__ part_off,
-                                                        const double* __restrict__ rowacc,
-                                                        const double* __restrict__ part,
-                                                        const double* __restrict__ scale, double* __restrict__ out,
-                                                        int bid) {
-  const int l = bid * 256 + threadIdx.x;
-  if (l >= M) return;
-  double acc = rowacc[l];
-  for (int b = l / kOtfRows; b >= 0 && blk_end[b] > l; --b) acc += part[part_off[b] + (l - b * kOtfRows)];
-  if (periodic) {
-    const long long lw = (long long)l + M;
-    for (int b = nblk_rows - 1; b >= 0 && blk_end[b] > lw; --b) acc += part[part_off[b] + (lw - (long long)b * kOtfRows)];
-  }
-  out[l] = scale[l] * acc;
-}
-
-__global__ void __launch_bounds__(256)
-k_local_otf_reduce(int M, int nblk_rows, int periodic, const int* __restrict__ blk_end,
-                   const int64_t* __restrict__ part_off, const double* __restrict__ rowacc,
-                   const double* __restrict__ part, const double* __restrict__ scale, double* __restrict__ out) {
-  k_local_otf_reduce_body(M, nblk_rows, periodic, blk_end, part_off, rowacc, part, scale, out, blockIdx.x);
-}
-
-#define WFP_OTFS_INST(PP)                                                                                      \
-  template __global__ void k_local_otf_sym<PP>(int, int, int, int64_t, const int*, const int*, const int64_t*, \
-                                               int, const double*, const double*, int, double, double, int, int, \
-                                               const double*, const double*, const double*, double*, double*);
-WFP_OTFS_INST(2)
-WFP_OTFS_INST(4)
-WFP_OTFS_INST(6)
-WFP_OTFS_INST(8)
-WFP_OTFS_INST(10)
-WFP_OTFS_INST(12)
-#undef WFP_OTFS_INST
 
 // Driving data g_j(t) = beta_j f(x_j - t) (eq. (gj); f periodised in the
 // periodic box), stored negated: ginc_j = -g_j.  Thread (row, packet) sums the
