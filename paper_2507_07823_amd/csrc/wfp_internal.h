@@ -191,6 +191,7 @@ struct wfp_plan {
   int64_t* sym_upb = nullptr;     // row j's first pair in sym_colpart
   double* sym_colpart = nullptr;  // per upper pair: the column term (row l's share)
   int2* sym_cov = nullptr;        // per row: first covering row below it, first wrapped one
+  int sym_kmax = 0;               // longest lag-1 run of a row, less one
   double *otf_z = nullptr, *otf_w = nullptr, *phitab = nullptr, *half_beta = nullptr;
   double* halfs = nullptr;       // 1/2 per row (the local part without beta)
   // symmetric on-the-fly local sum: per row the unwrapped end of its upper

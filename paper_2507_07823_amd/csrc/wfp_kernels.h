@@ -65,7 +65,7 @@ __global__ void k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __r
                                 const double* __restrict__ na, const double* __restrict__ nw,
                                 const double* __restrict__ phitab, double* __restrict__ rowacc,
                                 double* __restrict__ part);
-__global__ void k_local_sym_rows(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end,
+__global__ void k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __restrict__ up_end,
                                  const double* __restrict__ hist, const int64_t* __restrict__ rb,
                                  const uint2* __restrict__ sacx, const double* __restrict__ Qs,
                                  const int64_t* __restrict__ upb, double* __restrict__ rowacc,
@@ -73,6 +73,11 @@ __global__ void k_local_sym_rows(int M, int NH, int NQ, int64_t L, const int* __
 __global__ void k_local_sym_reduce(int M, const int2* __restrict__ cov, const int64_t* __restrict__ upb,
                                    const double* __restrict__ rowacc, const double* __restrict__ colpart,
                                    const double* __restrict__ scale, double* __restrict__ out);
+__global__ void k_local_sym_lag1(int M, int NQ, int NH, int64_t L, int periodic, int kmax,
+                                 const int64_t* __restrict__ rb, const uint2* __restrict__ sacx,
+                                 const double* __restrict__ Qs, const double* __restrict__ hist,
+                                 const double* __restrict__ scale, const double* __restrict__ base,
+                                 double* __restrict__ out);
 __global__ void k_local_otf_reduce(int M, int nblk_rows, int periodic, const int* __restrict__ blk_end,
                                    const int64_t* __restrict__ part_off, const double* __restrict__ rowacc,
                                    const double* __restrict__ part, const double* __restrict__ scale,

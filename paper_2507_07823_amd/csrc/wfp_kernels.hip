@@ -1015,7 +1015,8 @@ WFP_OTFS_INST(10)
 WFP_OTFS_INST(12)
 #undef WFP_OTFS_INST
 
-// Local sum of lags m >= 1 from stored weights, each unordered pair once.
+// Local sum of lags m >= mfirst (1, or 2 with the lag-1 part added by
+// k_local_sym_lag1) from stored weights, each unordered pair once.
 // One wavefront per row j walks its upper range [j, up_end[j]) (unwrapped:
 // periodic ranges continue past M - 1 at 0), lanes over the sources, lags in
 // groups of eight with every load of a group issued before its use.  Row j's
@@ -1026,9 +1027,10 @@ WFP_OTFS_INST(12)
 // column term sum_m Q sigma_j^{L-m} (row l's share) to colpart[upb[j] + i]
 // (0 for the row itself); k_local_sym_reduce adds them up per row.
 __global__ void __launch_bounds__(256)
-k_local_sym_rows(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end, const double* __restrict__ hist,
-                 const int64_t* __restrict__ rb, const uint2* __restrict__ sacx, const double* __restrict__ Qs,
-                 const int64_t* __restrict__ upb, double* __restrict__ rowacc, double* __restrict__ colpart) {
+k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __restrict__ up_end,
+                 const double* __restrict__ hist, const int64_t* __restrict__ rb, const uint2* __restrict__ sacx,
+                 const double* __restrict__ Qs, const int64_t* __restrict__ upb, double* __restrict__ rowacc,
+                 double* __restrict__ colpart) {
   __shared__ double rv[4][kMaxOtfLags + 1];                   // each row's own history, lags 0 .. NQ - 1
   __shared__ uint2 cw[4][kMaxOtfLags + 1];
   __shared__ int64_t slot[kMaxOtfLags + 1];
@@ -1056,7 +1058,7 @@ k_local_sym_rows(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_en
     int l = j + i;
     if (l >= M) l -= M;
     double pc = 0.0;
-    for (int mb = 1; mb < NQ; mb += 8) {
+    for (int mb = mfirst; mb < NQ; mb += 8) {
       double w[8], h[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -1101,6 +1103,40 @@ k_local_sym_reduce(int M, const int2* __restrict__ cov, const int64_t* __restric
   acc = wave_sum(acc);
   if (lane == 0) out[l] = scale[l] * (rowacc[l] + acc);
 }
+
+// Lag 1 of the pair-once stored local sum, added to the lags >= 2 total
+// `base` (already scaled): row l's own lag-1 run Q_1(d) sigma^{L-1} over the
+// first c_l1 sources of its upper range, and the column terms of the rows
+// j = l - k (k = 1 .. kmax, modulo M in the periodic box) whose lag-1 run
+// reaches l (k < c_j1).  One thread per row, in a fixed order; the runs are
+// short (pairs closer than about p/2 dt).
+__global__ void __launch_bounds__(256)
+k_local_sym_lag1(int M, int NQ, int NH, int64_t L, int periodic, int kmax, const int64_t* __restrict__ rb,
+                 const uint2* __restrict__ sacx, const double* __restrict__ Qs, const double* __restrict__ hist,
+                 const double* __restrict__ scale, const double* __restrict__ base, double* __restrict__ out) {
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  if (l >= M) return;
+  const double* __restrict__ h = hist + (int64_t)mod_slot(L - 1, NH) * M;
+  const uint2 c = sacx[(int64_t)l * NQ + 1];
+  const double* __restrict__ q = Qs + rb[l] + c.y;
+  double a = 0.0;
+  for (int i = 0; i < (int)c.x; ++i) {
+    int ll = l + i;
+    if (ll >= M) ll -= M;
+    a = fma(q[i], h[ll], a);
+  }
+  for (int k = 1; k <= kmax; ++k) {
+    int j = l - k;
+    if (j < 0) {
+      if (!periodic) break;
+      j += M;
+    }
+    const uint2 cj = sacx[(int64_t)j * NQ + 1];
+    if (k < (int)cj.x) a = fma(Qs[rb[j] + cj.y + k], h[j], a);
+  }
+  out[l] = base[l] + scale[l] * a;
+}
+
 
 
 // Driving data g_j(t) = beta_j f(x_j - t) (eq. (gj); f periodised in the

@@ -742,6 +742,9 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
         }
         P->sym_cov = P->alloc<int2>(M);
         upload(P->sym_cov, cov, s);
+        for (int64_t j = 0; j < M; ++j)
+          P->sym_kmax = std::max(P->sym_kmax, (int)acxh[(size_t)j * P->NQ + 1].x - 1);
+        P->locb = P->alloc<double>(2 * (size_t)M);
         for (void* q : {(void*)dense, (void*)uac, (void*)umlo, (void*)ust_d, (void*)ucnt_d, (void*)uoff_d,
                         (void*)ones_d})
           P->release(q);
@@ -1233,6 +1236,11 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
 // Local sum of lags >= 1 with the weights evaluated on the fly, scaled per row:
 // each unordered pair once (k_local_otf_sym), then the per-row totals
 // (k_local_otf_reduce).  ea / eb bracket both launches.
+// The on-the-fly schedule (the whole local sum after the previous level's
+// solve); stored weights, per ordered pair or once per pair, take the
+// pipelined one (lags >= 2 ahead, lag 1 after the previous solve).
+bool otf_schedule(const wfp_plan* P) { return P->otf && !P->sym_stored; }
+
 void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, const double* scale, double* out,
                       hipEvent_t ea = nullptr, hipEvent_t eb = nullptr) {
   const int nblocks = 8 * (int)nblk(P->otf_nblk, 8);
@@ -1245,7 +1253,7 @@ void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
                         P->otf_rowacc, P->otf_part)
   if (P->sym_stored) {
     hipExtLaunchKernelGGL(k_local_sym_rows, dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
-                          (int)P->M, P->NH, P->NQ, L, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
+                          (int)P->M, P->NH, P->NQ, L, 1, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
                           P->sym_upb, P->otf_rowacc, P->sym_colpart);
     hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 4)), dim3(256), 0, s, nullptr, eb, 0, (int)P->M,
                           P->sym_cov, P->sym_upb, P->otf_rowacc, P->sym_colpart, scale, out);
@@ -1335,6 +1343,15 @@ double* locb_second(wfp_plan* P, int64_t L) {
 
 void launch_local_big(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, hipEvent_t ea = nullptr,
                       hipEvent_t eb = nullptr) {
+  if (P->sym_stored) {
+    hipExtLaunchKernelGGL(k_local_sym_rows, dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
+                          (int)P->M, P->NH, P->NQ, L, 2, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
+                          P->sym_upb, P->otf_rowacc, P->sym_colpart);
+    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 4)), dim3(256), 0, s, nullptr, eb, 0, (int)P->M,
+                          P->sym_cov, P->sym_upb, P->otf_rowacc, P->sym_colpart, P->half_beta,
+                          P->locb + (L & 1) * P->M);
+    return;
+  }
   launch_local_sum(P, s, hist, L, 2, P->locb + (L & 1) * P->M, ea, eb, locb_second(P, L));
 }
 
@@ -1365,6 +1382,12 @@ const double* driving_row(wfp_plan* P, hipStream_t s, int64_t L) {
 }
 
 void launch_local_lag1(wfp_plan* P, hipStream_t s, const double* hist, int64_t L) {
+  if (P->sym_stored) {
+    hipLaunchKernelGGL(k_local_sym_lag1, dim3(nblk(P->M, 256)), dim3(256), 0, s, (int)P->M, P->NQ, P->NH, L,
+                       P->boundary == WFP_PERIODIC ? 1 : 0, P->sym_kmax, P->sym_rb, P->sym_acx, P->sym_q, hist,
+                       P->half_beta, P->locb + (L & 1) * P->M, P->loc);
+    return;
+  }
   const int nb = 8 * (int)nblk(nblk(P->M, 16), 8);   // 16 rows per block of 256 threads
   hipLaunchKernelGGL(k_local_lag1, dim3(nb), dim3(kRowThreads), 0, s, (int)P->M, P->NQ, P->NH, L, P->nb_start,
                      P->rowbase, P->acx, P->Qc, hist, P->locb + (L & 1) * P->M, locb_second(P, L), P->lsplit - 1,
@@ -1398,13 +1421,13 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
       ea = take_event(P);
       eb = take_event(P);
     }
-    if (P->otf && overlap) {
+    if (otf_schedule(P) && overlap) {
       // on the local sum's compute units, joined before the solve
       HIPCHK(hipStreamWaitEvent(P->sd, P->ev_solved, 0));
       launch_local_otf(P, P->sd, S.hist, L, P->half_beta, P->loc);
       HIPCHK(hipEventRecord(P->ev_big[L & 1], P->sd));
       HIPCHK(hipStreamWaitEvent(s, P->ev_big[L & 1], 0));
-    } else if (P->otf) {
+    } else if (otf_schedule(P)) {
       launch_local_otf(P, s, S.hist, L, P->half_beta, P->loc, ea, eb);
     } else if (!ahead) {
       launch_local_big(P, s, S.hist, L, ea, eb);
@@ -1468,7 +1491,7 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
   {
     StageTimer st(P, WFP_STAGE_SOLVE, s);
     if (ahead) HIPCHK(hipStreamWaitEvent(s, P->ev_big[L & 1], 0));   // driving data and local sum of level L
-    else if (!P->otf) launch_local_lag1(P, s, S.hist, L);
+    else if (!otf_schedule(P)) launch_local_lag1(P, s, S.hist, L);
     if (P->n_direct_tiles > 0)
       hipLaunchKernelGGL(k_solve_direct, dim3(P->n_direct_tiles), dim3(256), 0, s, (int)P->M, P->dt_g0, P->dt_n,
                          P->dt_p0, P->pt_cs, P->pt_cn, P->pt_inv, P->inv, gin, P->loc, P->i0s, P->iw,
@@ -1549,7 +1572,7 @@ void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, d
   // level L's driving data and lag-1 part, then the lags >= 2 part of level
   // L + 1 (it needs sigma^{L-1} and older only), while sb runs level L's chain
   // and sa its solve
-  const bool ahead = ov && !P->otf;
+  const bool ahead = ov && !otf_schedule(P);
   // the queue that solves (and signals ev_solved)
   hipStream_t sm = ahead ? P->sb : P->sa;
   if (ov) {
