@@ -36,9 +36,9 @@ def wfp():
     return w
 
 
-def _march(w, p, n, **kw):
+def _march(w, prob, n, **kw):
     import torch
-    plan = w.Plan(p, p["dt"], **kw)
+    plan = w.Plan(prob, prob["dt"], **kw)
     sig, u = plan.march(n)
     torch.cuda.synchronize()
     out = sig.cpu().numpy(), (None if u is None else u.cpu().numpy()), plan.info
@@ -141,3 +141,25 @@ def test_pair_once_refused_by_gradient_and_batch(wfp):
     plan.close()
     with pytest.raises(RuntimeError, match="local_mode 0, 1 or 2"):
         wfp.Batch([p], [p["dt"]], per_instance=[{"local_mode": 3}])
+
+
+@pytest.mark.parametrize("p", [2, 4, 6, 10, 12])
+def test_every_interpolation_order_matches_stored(wfp, p):
+    """The on-the-fly kernel (local_mode 2, one template per p) and the
+    pair-once stored weights (local_mode 3) against the weights stored per
+    ordered pair (local_mode 1) at every even p other than 8: 120 random
+    springs in the periodic box, 250 levels."""
+    rng = np.random.default_rng(40 + p)
+    x = rng.uniform(-np.pi + 1.2, np.pi, 120)
+    beta = rng.uniform(1.0, 10.0, 120)
+    prob = dict(x=x, beta=beta, packets=np.array([[1.0, -np.pi + 0.6, 0.05, 0.0, 0.0]]), boundary=PERIODIC,
+                x_recv=np.zeros(0), dt=5e-3)
+    n = 250
+    s1, _, i1 = _march(wfp, prob, n, local_mode=1, p=p)
+    s2, _, i2 = _march(wfp, prob, n, local_mode=2, p=p)
+    s3, _, i3 = _march(wfp, prob, n, local_mode=3, p=p)
+    assert (i1["p"], i2["p"], i3["p"]) == (p, p, p)
+    e2, e3 = rho(s2, s1), rho(s3, s1)
+    say(f"p = {p}: on the fly {e2:.2e}, pair-once stored {e3:.2e} against per-pair stored (max |sigma| "
+        f"{np.max(np.abs(s1)):.2e})")
+    assert e2 < 1e-12 and e3 < 1e-12 and np.max(np.abs(s1)) > 1e-2
