@@ -360,22 +360,22 @@ def cpu_baseline(levels):
                       f"0..{levels - 1} of the CPU oracle, timed after its {pre:.0f} s set-up"}
 
 
-def adjoint_leg(levels, every):
-    """Forward + gradient pass on the adjoint workload (M = 1e5 springs, 64
-    receivers, dt = 1e-3) over `levels` levels with checkpoints every `every`
-    levels, against the plain forward march of the same plan.  A first
-    gradient call over one checkpoint segment (derivative-weight set-up) is
-    not timed."""
+def _adjoint_run(p, levels, every):
+    """Forward march then gradient pass over `levels` levels of the adjoint
+    workload on a plan with checkpoint_every = `every` (> 0: checkpoints, the
+    gradient pass replays each segment; < 0: every level recorded in blocks of
+    -every levels, no replay).  A first gradient call over one block or
+    segment (derivative-weight set-up) is not timed."""
     import torch
-    from paper_2507_07823_amd import wfp, workloads
-    p = workloads.adjoint_periodic()
+    from paper_2507_07823_amd import wfp
     M, R = p["x"].size, p["x_recv"].size
     t0 = time.perf_counter()
     plan = wfp.Plan(p, p["dt"], checkpoint_every=every)
     setup = time.perf_counter() - t0
     u = torch.empty((levels, R), dtype=torch.float64, device="cuda")
-    plan.run(every, None, 1, u[:every])
-    plan.gradient(p["dt"] * u[:every])               # warm-up and one-time set-up on one segment
+    first = min(levels, abs(every))
+    plan.run(first, None, 1, u[:first])
+    plan.gradient(p["dt"] * u[:first])               # warm-up and one-time set-up
     plan.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -389,13 +389,42 @@ def adjoint_leg(levels, every):
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
     ok = bool(torch.isfinite(gb).all() and torch.isfinite(gx).all())
+    dev_bytes = plan.query_info()["device_bytes"]
     plan.close()
-    return {"workload": "periodic adjoint", "M": M, "R": R, "levels": levels, "checkpoint_every": every,
-            "beta": [round(float(p["beta"].min()), 4), round(float(p["beta"].max()), 4)],
-            "plan_setup_s": setup, "forward_s": t_fwd, "gradient_s": t_bwd,
-            "plain_scatterer_steps_per_s": M * levels / t_fwd,
+    return {"levels": levels, "checkpoint_every": every, "plan_setup_s": setup, "forward_s": t_fwd,
+            "gradient_s": t_bwd, "forward_scatterer_steps_per_s": M * levels / t_fwd,
             "forward_plus_gradient_scatterer_steps_per_s": M * levels / (t_fwd + t_bwd),
-            "gradient_over_plain_time": t_bwd / t_fwd, "finite": ok}
+            "gradient_over_forward_time": t_bwd / t_fwd, "device_bytes": dev_bytes, "finite": ok}
+
+
+def adjoint_leg(levels, every):
+    """Forward + gradient pass on the adjoint workload (M = 1e5 springs, 64
+    receivers, dt = 1e-3): over `levels` levels with every level recorded
+    (blocks of `every`), and over at most 1000 levels with checkpoints every
+    `every` levels (the replayed form), against a plain forward march (no
+    checkpoints, no recording) of the same levels."""
+    import torch
+    from paper_2507_07823_amd import wfp, workloads
+    p = workloads.adjoint_periodic()
+    M, R = p["x"].size, p["x_recv"].size
+    plain = wfp.Plan(p, p["dt"])
+    u = torch.empty((levels, R), dtype=torch.float64, device="cuda")
+    plain.run(10, None, 1, u[:10])
+    plain.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain.run(levels, None, 1, u)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain.close()
+    del u
+    rec = _adjoint_run(p, levels, -every)
+    ck = _adjoint_run(p, min(levels, 1000), every)
+    return {"workload": "periodic adjoint", "M": M, "R": R, "levels": levels,
+            "beta": [round(float(p["beta"].min()), 4), round(float(p["beta"].max()), 4)],
+            "plain_forward_s": t_plain, "plain_scatterer_steps_per_s": M * levels / t_plain,
+            "recorded": rec, "checkpointed": ck,
+            "forward_plus_gradient_over_plain_time": (rec["forward_s"] + rec["gradient_s"]) / t_plain}
 
 
 def batch_leg(n_inst, levels, m_max, trial_levels=3, uneven=True):

@@ -59,7 +59,7 @@ typedef int32_t wfp_status;
 #define WFP_PERIODIC 0      /* periodic box [-pi, pi) (Section 2) */
 #define WFP_FREE_SPACE 1    /* free space via outgoing windowing (Section 4.4) */
 
-#define WFP_ABI_VERSION 6
+#define WFP_ABI_VERSION 7
 
 typedef struct wfp_plan wfp_plan;
 
@@ -92,7 +92,11 @@ typedef struct {
   int32_t nufft_width;     /* spreading-kernel width in fine-grid points     [16] */
   int32_t solve_iters;     /* Jacobi sweeps of the per-step solve            [from a contraction bound] */
   int32_t checkpoint_every;/* > 0: wfp_run stores the march state every this many levels (for
-                              wfp_adjoint); 0: no checkpoints                [0] */
+                              wfp_adjoint, which replays each segment from its checkpoint);
+                              -C < 0: wfp_run records every level's densities and forward
+                              derivative term (16 M bytes a level, in blocks of C levels, C
+                              <= 2^20; periodic plans with R >= 1 only) and wfp_adjoint needs
+                              no replay; 0: neither                           [0] */
   int32_t overlap_cus;     /* > 0: wfp_run puts the history chain (spread, FFTs, modes) and the
                               solve on a stream restricted to the first overlap_cus compute
                               units and the local sum on the others, the next level's local
@@ -170,8 +174,9 @@ wfp_status wfp_plan_info(const wfp_plan* plan, wfp_info* info);
  * Asynchronous on the plan's stream, unless the plan checks for non-finite
  * values (check_finite), which waits for the stream at the end.  The first
  * call allocates the plan's block of driving-data levels (device memory held
- * until wfp_plan_destroy), and checkpointing runs allocate their checkpoints;
- * later calls allocate nothing.
+ * until wfp_plan_destroy); checkpointing and recording runs allocate each
+ * checkpoint or recorded block the first time they reach it (held until
+ * wfp_plan_destroy, reused after wfp_reset); nothing else is allocated.
  * Errors: WFP_EINVAL, WFP_EHIP, WFP_ENONFINITE, WFP_ENOMEM. */
 wfp_status wfp_run(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t save_every,
                    double* u_recv_out);
@@ -183,7 +188,7 @@ wfp_status wfp_run(wfp_plan* plan, int64_t n_steps, double* sigma_out, int64_t s
  * static scratch array, 8 MiB per GPU, held by each GPU the library runs on
  * until the process ends.  Same arguments, outputs and stream ordering as
  * wfp_run.  Limits: M <= 1048544 springs (one level of driving data must fit);
- * plans with checkpoint_every > 0 (their checkpoints are allocated) and plans
+ * plans with checkpoint_every != 0 (their checkpoints or recorded levels are allocated) and plans
  * with stage timing on (it creates events) are refused with WFP_EINVAL.  The
  * scratch array is shared by every call on one GPU and keeps the last call's
  * contents; each call recomputes what it reads, but calls that overlap on one
@@ -217,7 +222,7 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
 
 /* Gradient of a receiver loss J(u) through the march (not in the paper: the
  * transpose of every step of Section 4.2, run backwards in time).
- * Requires a periodic plan with R >= 1 and checkpoint_every > 0 whose levels
+ * Requires a periodic plan with R >= 1 and checkpoint_every != 0 whose levels
  * 0 .. n_levels-1 were computed by wfp_run since plan creation or wfp_reset
  * (no wfp_set_state in between); the plan's own state is not changed.
  *   dJdu       device [n_levels][R]: dJ/du(x_r, t_L) for the levels 0..n_levels-1
@@ -226,9 +231,12 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
  *              differentiated in the distance; where a pair sits exactly at the
  *              nearby/intermediate switch d = dt the one-sided derivative of
  *              its class is used)
- * Device memory: the first call allocates a second and third march state, a
- * segment of checkpoint_every + m_max - 1 density levels and, with grad_x,
- * derivative weights as large as the local weights.  Asynchronous on the plan's stream.
+ * Device memory: the first call allocates an adjoint march state and, with
+ * checkpoints, a replay state, a segment of checkpoint_every + m_max - 1
+ * density levels and one of checkpoint_every derivative terms; with grad_x,
+ * derivative weights as large as the local weights.  With recorded levels
+ * (checkpoint_every < 0) the recorded blocks take the place of the replay.
+ * Asynchronous on the plan's stream.
  * Errors: WFP_EINVAL, WFP_EDOMAIN (free space), WFP_ESTATE, WFP_ENOMEM, WFP_EHIP. */
 wfp_status wfp_adjoint(wfp_plan* plan, int64_t n_levels, const double* dJdu, double* grad_beta,
                        double* grad_x);
@@ -282,8 +290,10 @@ wfp_status wfp_plan_autotune(wfp_plan* plan, int32_t trial_levels, int32_t* over
  *                     on the fly with p = 8 only; local_mode 0 here: stored for the
  *                     instances with the fewest neighbour pairs while their weights
  *                     fit in 45 % of the free device memory).  Synchronous.
- *                     Errors: WFP_EDOMAIN (free space, or an instance whose
- *                     stages exceed the LDS), as for plans.
+ *                     Errors: WFP_EDOMAIN (free space, local_mode 3, or an
+ *                     instance whose stages exceed the LDS), WFP_EINVAL
+ *                     (checkpoint_every != 0: no gradient pass in batches), as
+ *                     for plans.
  *   wfp_batch_run     march n_steps levels of every instance; sigma_final is a
  *                     HOST array of n DEVICE pointers (entries may be NULL, the
  *                     array may be NULL): instance i's densities of its last

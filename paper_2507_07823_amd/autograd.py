@@ -13,6 +13,9 @@ class WFPReceivers(torch.autograd.Function):
                 device, copied to the host for plan creation)
     problem     dict with packets, x_recv, boundary (periodic box only for the
                 backward pass)
+    checkpoint_every  > 0: march-state checkpoints every that many levels
+                (the backward pass replays each segment); -C < 0: every level
+                recorded in blocks of C (16 M bytes per level, no replay)
     returns     float64 CUDA tensor [n_steps][R]: u(x_r, t_L), L = 0..n_steps-1
     """
 

@@ -501,6 +501,12 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
       g_last_error = "the batched form takes local_mode 0, 1 or 2";
       return WFP_EDOMAIN;
     }
+    if (pars[i].checkpoint_every != 0) {
+      // its levels are marched by the batch's own launches, which neither
+      // store checkpoints nor record levels for a gradient pass
+      g_last_error = "the batched form takes checkpoint_every 0";
+      return WFP_EINVAL;
+    }
   }
   wfp_batch* B = new wfp_batch();
   wfp_status st = guard([&] {

@@ -246,11 +246,17 @@ struct wfp_plan {
   std::vector<int64_t> rqoff_h;
   int64_t dense_total = 0;
   double *glz_d = nullptr, *glw_d = nullptr, *lagw_d = nullptr;
-  // checkpoints of the current run (state at levels c * ckpt_every, c >= 1)
+  // checkpoints of the current run (state at levels c * ckpt_every, c >= 1);
+  // ckpt_every < 0 records every level instead, in blocks of -ckpt_every levels
   int ckpt_every = 0;
   bool ck_from0 = true;          // the levels run so far started from level 0
   std::vector<char*> ckpts;
   size_t ckpt_bytes = 0;
+  // recorded levels, block b = levels b C .. b C + C - 1 (C = -ckpt_every):
+  // rec_sig[b] rows NQ - 1 + i = sigma^{bC+i} after the NQ - 1 levels before
+  // the block (sorted order), rec_D[b] row i = the forward derivative term of
+  // level bC + i (f' + d/dx u_H at the springs)
+  std::vector<double*> rec_sig, rec_D;
   // gradient pass: replay and adjoint states, per-segment buffers
   bool grad_ready = false, gradx_ready = false;
   double *rhist = nullptr, *ahist = nullptr;

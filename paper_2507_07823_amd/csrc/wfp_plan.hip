@@ -91,8 +91,13 @@ void validate(const wfp_problem* prob, const wfp_params* par) {
   if (par->eps_window < 0 || !(par->eps_window < 1) || par->gamma < 0 || !(par->gamma < 1))
     fail(WFP_EINVAL, "eps_window and gamma must lie in [0, 1)");
   if (par->W < 0 || par->K < 0 || par->n_gl_local < 0 || par->n_gl_pq < 0 || par->rbc_period < 0 ||
-      par->solve_iters < 0 || par->checkpoint_every < 0 || par->local_mode < 0 || par->local_mode > 3)
+      par->solve_iters < 0 || par->local_mode < 0 || par->local_mode > 3)
     fail(WFP_EINVAL, "negative size parameter");
+  if (par->checkpoint_every < -(1 << 20)) fail(WFP_EINVAL, "recording blocks of at most 2^20 levels");
+  if (par->checkpoint_every < 0 && prob->boundary != WFP_PERIODIC)
+    fail(WFP_EDOMAIN, "recorded levels (checkpoint_every < 0) serve the gradient pass, periodic box only");
+  if (par->checkpoint_every < 0 && prob->R < 1)
+    fail(WFP_EINVAL, "recorded levels (checkpoint_every < 0) serve the gradient pass, which needs receivers");
   const int p = par->p > 0 ? par->p : 8;
   if (par->p < 0 || p % 2 || p < 2 || p > kMaxP) fail(WFP_EINVAL, "p must be even, 2..12");
   for (int64_t j = 0; j < prob->M; ++j) {
@@ -1562,9 +1567,17 @@ void zero_state_ref(wfp_plan* P, const StateRef& S) {
   HIPCHK(hipGetLastError());
 }
 
+void dterm_setup(wfp_plan* P);
+void fwd_dterm(wfp_plan* P, const StateRef& S, int64_t L, double* out);
+
 void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, double* u_recv_out) {
   const StateRef S = main_state(P);
   const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+  // recording: every level's densities and forward derivative term, for a
+  // gradient pass without the forward replay
+  const bool rec = P->ckpt_every < 0 && P->ck_from0;
+  const int64_t RC = -(int64_t)P->ckpt_every, hd = P->NQ - 1;
+  if (rec && n > 0) dterm_setup(P);
   // the concurrent chain is used when configured and no checkpoints are taken
   // (per-stage timing measures each stage alone: one stream while profiling)
   const bool ov = P->overlap_cus > 0 && P->ckpt_every == 0 && n > 0 && !P->profiling;
@@ -1600,8 +1613,26 @@ void run_levels(wfp_plan* P, int64_t n, double* sigma_out, int64_t save_every, d
       while (P->ckpts.size() <= c) P->ckpts.push_back(P->alloc<char>(state_bytes(P)));
       copy_state(P, S, P->ckpts[c], true);
     }
+    const size_t rb = rec ? (size_t)(L / RC) : 0;
+    if (rec && L % RC == 0) {
+      while (P->rec_D.size() <= rb) {
+        double* sig = P->alloc<double>((size_t)(RC + hd) * P->M);
+        double* dt = P->alloc<double>((size_t)RC * P->M);
+        P->rec_sig.push_back(sig);
+        P->rec_D.push_back(dt);
+      }
+      if (hd > 0)
+        hipLaunchKernelGGL(k_seg_head, dim3(nblk(hd * P->M, 256)), dim3(256), 0, P->stream, (int)P->M, P->NH, L,
+                           (int)hd, S.hist, P->rec_sig[rb]);
+    }
     double* save = (sigma_out && i % save_every == 0) ? sigma_out + (i / save_every) * P->M : nullptr;
     march_level(P, S, L, false, none, save, u_recv_out ? u_recv_out + i * P->R : nullptr, ov, ahead);
+    if (rec) {
+      const int64_t r = L - (int64_t)rb * RC;
+      HIPCHK(hipMemcpyAsync(P->rec_sig[rb] + (hd + r) * P->M, S.hist + (L % P->NH) * P->M, P->M * sizeof(double),
+                            hipMemcpyDeviceToDevice, P->stream));
+      fwd_dterm(P, S, L, P->rec_D[rb] + r * P->M);
+    }
   }
   if (ov) {
     // later work on the caller's stream waits for the whole run
@@ -1634,24 +1665,25 @@ void grad_setup(wfp_plan* P) {
   if (P->grad_ready) return;
   const int64_t M = P->M, R = P->R, C = P->ckpt_every;
   hipStream_t s = P->stream;
-  P->rhist = P->alloc<double>((size_t)P->NH * M);
+  if (C > 0) {
+    // the forward replay's state and the segment's densities after the
+    // NQ - 1 levels before it (row NQ - 1 + L - a); recorded levels need neither
+    P->rhist = P->alloc<double>((size_t)P->NH * M);
+    P->rring = P->alloc<double2>((size_t)P->W * P->npos);
+    P->ralpha = P->alloc<double2>(P->npos);
+    P->rdalpha = P->alloc<double2>(P->npos);
+    P->segsig = P->alloc<double>((size_t)(C + P->NQ - 1) * M);
+  }
   P->ahist = P->alloc<double>((size_t)P->NH * M);
-  P->rring = P->alloc<double2>((size_t)P->W * P->npos);
   P->aring = P->alloc<double2>((size_t)P->W * P->npos);
-  P->ralpha = P->alloc<double2>(P->npos);
-  P->rdalpha = P->alloc<double2>(P->npos);
   P->aalpha = P->alloc<double2>(P->npos);
   P->adalpha = P->alloc<double2>(P->npos);
-  // the segment's densities after the NQ - 1 levels before it (row NQ - 1 + L - a)
-  P->segsig = P->alloc<double>((size_t)(C + P->NQ - 1) * M);
   P->gb_acc = P->alloc<double>(M);
   P->gx_acc = P->alloc<double>(M);
   P->xloc = P->alloc<double>(M);
   P->xloc2 = P->alloc<double>(M);
   P->xw = P->alloc<double>(M);
-  P->fprime = P->alloc<double>(M);
-  P->gridd = P->alloc<double>(P->nf);
-  P->yd = P->alloc<double2>(P->K + 1);
+  dterm_setup(P);
   P->esort = P->alloc<double>(R);
   // receivers as spreading sources, in ascending x
   std::vector<int> ord(R);
@@ -1748,12 +1780,40 @@ void gradx_setup(wfp_plan* P) {
   for (int64_t r = 0; r < R; ++r) rt += (int64_t)P->rnbc_h[r] * P->NQ;
   P->dQr = P->alloc<double>(rt);
   launch_local_weights(P, (int)R, P->xr, P->rnb_start, P->rnb_count, P->rqoff, mh, 1, nullptr, nullptr, P->dQr);
-  P->segD = P->alloc<double>((size_t)P->ckpt_every * M);
+  if (P->ckpt_every > 0) P->segD = P->alloc<double>((size_t)P->ckpt_every * M);
   HIPCHK(hipStreamSynchronize(s));
   P->release(tmp);
   P->release(hs);
   P->release(mh);
   P->gradx_ready = true;
+}
+
+// Buffers of the forward derivative term: f' at the springs, d/dx u_H on the
+// fine grid and its modes.
+void dterm_setup(wfp_plan* P) {
+  if (P->fprime) return;
+  P->fprime = P->alloc<double>(P->M);
+  P->gridd = P->alloc<double>(P->nf);
+  P->yd = P->alloc<double2>(P->K + 1);
+}
+
+void deriv_field(wfp_plan* P, const StateRef& S);
+
+// The part of D_j^L that needs the forward state right after level L (held by
+// S): f'(x_j - t_L) + d/dx u_H at x_j.  The derivative local sum of the
+// forward densities is formed in the backward sweep, in the same pass over the
+// derivative weights as the adjoint one.
+void fwd_dterm(wfp_plan* P, const StateRef& S, int64_t L, double* out) {
+  hipStream_t s = P->stream;
+  const int M = (int)P->M;
+  const Packets pk{P->npk, 1, P->packets};
+  int pp = 1;
+  while (pp < P->npk) pp *= 2;
+  hipLaunchKernelGGL(k_incident, dim3(nblk(M, 256 / pp)), dim3(256), 0, s, M, (double)L * P->dt, P->xs, P->beta,
+                     pk, pp, 1, P->fprime);
+  deriv_field(P, S);
+  hipLaunchKernelGGL(k_fwd_dterm, dim3(nblk(M, 256)), dim3(256), 0, s, M, P->fprime, P->i0s, P->iw, P->gridd,
+                     P->nf, P->width, out);
 }
 
 // d/dx u_H at the scatterers' grid: modes -i k alpha_k through the type-2
@@ -1772,40 +1832,35 @@ void deriv_field(wfp_plan* P, const StateRef& S) {
 
 void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, double* grad_x) {
   hipStream_t s = P->stream;
-  const int64_t M = P->M, R = P->R, C = P->ckpt_every;
+  // recorded levels: the blocks written by the forward run; else each segment
+  // is replayed from the checkpoint that starts it
+  const bool recorded = P->ckpt_every < 0;
+  const int64_t M = P->M, R = P->R, C = recorded ? -(int64_t)P->ckpt_every : P->ckpt_every;
   const bool wx = grad_x != nullptr;
   grad_setup(P);
   if (wx) gradx_setup(P);
   const StateRef rep{P->rhist, P->rring, P->ralpha, P->rdalpha};
   const StateRef adj{P->ahist, P->aring, P->aalpha, P->adalpha};
   const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
-  const Packets pk{P->npk, 1, P->packets};
-  int pp = 1;
-  while (pp < P->npk) pp *= 2;
   zero_state_ref(P, adj);
   hipLaunchKernelGGL(k_fill, dim3(nblk(M, 256)), dim3(256), 0, s, P->gb_acc, M, 0.0);
   hipLaunchKernelGGL(k_fill, dim3(nblk(M, 256)), dim3(256), 0, s, P->gx_acc, M, 0.0);
   const int64_t nseg = (N + C - 1) / C;
+  const int hd = P->NQ - 1;   // levels kept before the segment
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {
     const int64_t a = sg * C, b = std::min(N, a + C);
-    if (sg == 0) zero_state_ref(P, rep);
-    else copy_state(P, rep, P->ckpts[(size_t)sg - 1], false);
-    const int hd = P->NQ - 1;   // levels kept before the segment
-    hipLaunchKernelGGL(k_seg_head, dim3(nblk((int64_t)hd * M, 256)), dim3(256), 0, s, (int)M, P->NH, a, hd,
-                       P->rhist, P->segsig);
-    for (int64_t L = a; L < b; ++L) {
-      march_level(P, rep, L, false, none, nullptr, nullptr);
-      HIPCHK(hipMemcpyAsync(P->segsig + (hd + L - a) * M, P->rhist + (L % P->NH) * M, M * sizeof(double),
-                            hipMemcpyDeviceToDevice, s));
-      if (wx) {
-        // f' and d/dx u_H need the forward state of level L; the forward
-        // derivative local sum is formed in the backward sweep below, in the
-        // same pass over the derivative weights as the adjoint one
-        hipLaunchKernelGGL(k_incident, dim3(nblk(M, 256 / pp)), dim3(256), 0, s, (int)M, (double)L * P->dt, P->xs,
-                           P->beta, pk, pp, 1, P->fprime);
-        deriv_field(P, rep);
-        hipLaunchKernelGGL(k_fwd_dterm, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->fprime, P->i0s, P->iw,
-                           P->gridd, P->nf, P->width, P->segD + (L - a) * M);
+    double* const segsig = recorded ? P->rec_sig[(size_t)sg] : P->segsig;
+    double* const segD = recorded ? P->rec_D[(size_t)sg] : P->segD;
+    if (!recorded) {
+      if (sg == 0) zero_state_ref(P, rep);
+      else copy_state(P, rep, P->ckpts[(size_t)sg - 1], false);
+      hipLaunchKernelGGL(k_seg_head, dim3(nblk((int64_t)hd * M, 256)), dim3(256), 0, s, (int)M, P->NH, a, hd,
+                         P->rhist, segsig);
+      for (int64_t L = a; L < b; ++L) {
+        march_level(P, rep, L, false, none, nullptr, nullptr);
+        HIPCHK(hipMemcpyAsync(segsig + (hd + L - a) * M, P->rhist + (L % P->NH) * M, M * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+        if (wx) fwd_dterm(P, rep, L, segD + (L - a) * M);
       }
     }
     for (int64_t L = b - 1; L >= a; --L) {
@@ -1824,11 +1879,11 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
         deriv_field(P, adj);
         const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
         hipLaunchKernelGGL(k_local_deriv2, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)M, P->NQ, P->NH,
-                           P->nb_start, P->drowbase, P->acxd, P->DQa, (const double*)P->segsig,
+                           P->nb_start, P->drowbase, P->acxd, P->DQa, (const double*)segsig,
                            (int64_t)(hd + L - a), (const double*)P->ahist, Rv, P->xloc2, P->xloc);
       }
       hipLaunchKernelGGL(k_adj_grad, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->ahist + (Rv % P->NH) * M,
-                         P->segsig + (hd + L - a) * M, P->beta, wx ? P->segD + (L - a) * M : nullptr, P->xloc2,
+                         segsig + (hd + L - a) * M, P->beta, wx ? segD + (L - a) * M : nullptr, P->xloc2,
                          P->xloc, P->xw, P->i0s, P->iw, P->gridd, P->nf, P->width, P->gb_acc,
                          wx ? P->gx_acc : nullptr);
     }
@@ -2008,7 +2063,8 @@ wfp_status wfp_run_noalloc(wfp_plan* P, int64_t n_steps, double* sigma_out, int6
   }
   return guard([&] {
     HIPCHK(hipSetDevice(P->device));
-    if (P->ckpt_every > 0) fail(WFP_EINVAL, "wfp_run_noalloc: plans that store checkpoints allocate them; use wfp_run");
+    if (P->ckpt_every != 0)
+      fail(WFP_EINVAL, "wfp_run_noalloc: plans that store checkpoints or record levels allocate them; use wfp_run");
     if (P->profiling) fail(WFP_EINVAL, "wfp_run_noalloc: stage timing creates events; use wfp_run");
     if ((size_t)P->M > kScratchDoubles - kScratchHead)
       fail(WFP_EINVAL, "wfp_run_noalloc: M above " + std::to_string(kScratchDoubles - kScratchHead) +
@@ -2105,8 +2161,8 @@ wfp_status wfp_adjoint(wfp_plan* P, int64_t n_levels, const double* dJdu, double
     g_last_error = "the gradient pass needs stored local weights (local_mode 1)";
     return WFP_EDOMAIN;
   }
-  if (P->ckpt_every < 1 || !P->ck_from0 || P->level < n_levels) {
-    g_last_error = "run the n_levels levels from level 0 with checkpoint_every > 0 first";
+  if (P->ckpt_every == 0 || !P->ck_from0 || P->level < n_levels) {
+    g_last_error = "run the n_levels levels from level 0 with checkpoint_every != 0 first";
     return WFP_ESTATE;
   }
   return guard([&] {

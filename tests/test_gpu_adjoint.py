@@ -96,6 +96,42 @@ def test_gradient_ragged_segments(wfp):
     # beta only
     _, gb3, gx3 = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False)
     assert gx3 is None and np.array_equal(gb, gb3)
+    # recorded levels (no replay), in blocks that split the run differently:
+    # the same kernels on the same states, so the same bits
+    for blk in (-50, -37, -1000):
+        u4, gb4, gx4 = _gpu_gradient(wfp, p, n, dJdu, blk)
+        assert np.array_equal(u4, u) and np.array_equal(gb4, gb) and np.array_equal(gx4, gx), blk
+    _, gb5, gx5 = _gpu_gradient(wfp, p, n, dJdu, -37, positions=False)
+    assert gx5 is None and np.array_equal(gb5, gb)
+
+
+def test_recorded_levels_across_calls_and_resets(wfp):
+    """A recording plan marched in several calls, differentiated over fewer
+    levels than it ran, then reset and marched again (its blocks reused):
+    every gradient equals that of a checkpointing plan with the same history,
+    bit for bit."""
+    import torch
+    p = _case(10, 40, 3, 0.01, (0.2, 1.8), [1.0, -1.5, 0.12, 10.0, 0.0])
+    R = p["x_recv"].size
+    say("adjoint recorded levels: M=40 R=3 dt=0.01, blocks of 32 against checkpoints every 25")
+    rec = wfp.Plan(p, p["dt"], checkpoint_every=-32)
+    ck = wfp.Plan(p, p["dt"], checkpoint_every=25)
+    rng = np.random.default_rng(3)
+    for calls, n_grad in (((100, 37, 64), 150), ((90,), 90)):
+        rec.reset()
+        ck.reset()
+        for c in calls:
+            rec.run(c)
+            ck.run(c)
+        e = torch.from_numpy(rng.standard_normal((n_grad, R))).cuda()
+        gb_r, gx_r = rec.gradient(e)
+        gb_c, gx_c = ck.gradient(e)
+        torch.cuda.synchronize()
+        say(f"  calls {calls}, gradient over {n_grad} levels")
+        assert torch.equal(gb_r, gb_c) and torch.equal(gx_r, gx_c)
+        assert float(gb_c.abs().max()) > 0 and float(gx_c.abs().max()) > 0
+    rec.close()
+    ck.close()
 
 
 def test_autograd_function_matches_plan_gradient(wfp):
@@ -136,6 +172,24 @@ def test_adjoint_state_errors(wfp):
         plan.gradient(e)
     assert ei.value.status == wfp.WFP_ESTATE
     plan.close()
+    # recorded levels: a state set from outside, or driving data supplied by
+    # the caller, leaves a history the recording does not describe
+    plan = wfp.Plan(p, p["dt"], checkpoint_every=-4)
+    plan.run(10)
+    st = plan.get_state()
+    plan.set_state(st["L"], st["hist"], st["ring"], st["alpha"], st["dalpha"])
+    with pytest.raises(wfp.WFPError) as ei:
+        plan.gradient(e)
+    assert ei.value.status == wfp.WFP_ESTATE
+    plan.reset()
+    plan.march_driven(torch.zeros((10, 5), dtype=torch.float64, device="cuda"))
+    with pytest.raises(wfp.WFPError) as ei:
+        plan.gradient(e)
+    assert ei.value.status == wfp.WFP_ESTATE
+    with pytest.raises(wfp.WFPError) as ei:
+        plan.run_noalloc(1)                           # recording allocates its blocks
+    assert ei.value.status == wfp.WFP_EINVAL
+    plan.close()
 
 
 def test_gradient_full_size_beta_directional(wfp):
@@ -166,6 +220,14 @@ def test_gradient_full_size_beta_directional(wfp):
     gb, _ = plan.gradient(p["dt"] * u, positions=False)
     gb = gb.cpu().numpy()
     plan.close()
+    # recorded levels (blocks of 128, no replay) give the same bits
+    rec = wfp.Plan(p, p["dt"], checkpoint_every=-128)
+    u2 = torch.empty((n, R), dtype=torch.float64, device="cuda")
+    rec.run(n, None, 1, u2)
+    gb2, _ = rec.gradient(p["dt"] * u2, positions=False)
+    torch.cuda.synchronize()
+    rec.close()
+    assert torch.equal(u2, u) and np.array_equal(gb2.cpu().numpy(), gb)
     d = np.random.default_rng(13).uniform(0.5, 1.5, M)
 
     def central(hh):
@@ -212,6 +274,14 @@ def test_gradient_dense_nearby_coupling(wfp):
     say(f"adjoint dense cluster: M={M} levels={n} solve_mode=1: rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  "
         f"rho(x) = {ex:.2e}")
     assert eu < TOL and eb < TOL and ex < TOL
+    # recorded levels instead of the replay: the same bits
+    rec = wfp.Plan(p, p["dt"], checkpoint_every=-64)
+    u2 = torch.empty_like(u)
+    rec.run(n, None, 1, u2)
+    gb2, gx2 = rec.gradient(torch.from_numpy(np.ascontiguousarray(g["dJdu"])).cuda())
+    torch.cuda.synchronize()
+    rec.close()
+    assert torch.equal(u2, u) and torch.equal(gb2, gb) and torch.equal(gx2, gx)
 
 
 def _clear_of_breaks(x, xr, j, h, prm, z):

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib, root):
 
 
 def test_abi_version_and_strings(lib):
-    assert lib.wfp_abi_version() == 6
+    assert lib.wfp_abi_version() == 7
     assert lib.wfp_status_string(wfp.WFP_EDOMAIN) == b"outside the supported domain"
     assert lib.wfp_status_string(wfp.WFP_ENONFINITE) == b"non-finite values in the march"
 
@@ -56,6 +56,12 @@ def _base():
     (lambda p: p.update(boundary=wfp.FREE_SPACE, x=np.array([0.1, 3.0])), 0.01, {}, wfp.WFP_EDOMAIN),
     (lambda p: p.update(packets=np.array([[1.0, -2.0, 0.0, 0.0, 0.0]])), 0.01, {}, wfp.WFP_EINVAL),
     (lambda p: p.update(x_recv=np.array([4.0])), 0.01, {}, wfp.WFP_EINVAL),
+    # recorded levels (checkpoint_every < 0) serve the gradient pass: the
+    # periodic box, with receivers, blocks of at most 2^20 levels
+    (lambda p: p.update(boundary=wfp.FREE_SPACE, x_recv=np.array([0.3])), 0.01, {"checkpoint_every": -8},
+     wfp.WFP_EDOMAIN),
+    (lambda p: None, 0.01, {"checkpoint_every": -8}, wfp.WFP_EINVAL),
+    (lambda p: p.update(x_recv=np.array([0.3])), 0.01, {"checkpoint_every": -(1 << 21)}, wfp.WFP_EINVAL),
 ])
 def test_invalid_problems_rejected_on_host(mutate, dt, kw, code):
     p = _base()
@@ -94,6 +100,12 @@ def test_batch_rejects_free_space_before_any_device_work(lib):
     assert lib.wfp_batch_create(1, probs, pars, None, ctypes.byref(h)) == w.WFP_EDOMAIN
     assert b"local_mode" in lib.wfp_last_error()
     assert h.value is None
+    # nor checkpoints or recorded levels (no gradient pass in batches)
+    for every in (10, -10):
+        pars[0] = w.make_params(0.01, checkpoint_every=every)
+        assert lib.wfp_batch_create(1, probs, pars, None, ctypes.byref(h)) == w.WFP_EINVAL
+        assert b"checkpoint_every" in lib.wfp_last_error()
+        assert h.value is None
 
 
 def test_null_plan_arguments_rejected(lib):
