@@ -466,7 +466,7 @@ def batch_leg(n_inst, levels, m_max, trial_levels=3, uneven=True):
     return {"workload": "batched periodic instances", "instances": n_inst, "M_range": [100, m_max],
             "total_M": total_m, "levels": levels, "level_counts": "own" if uneven else "equal",
             "scatterer_steps": work, "plan_setup_s": setup, "instances_on_the_fly": n_otf,
-            "autotuned": {"rows_per_block": shape[0], "xcd_remap": shape[1]},
+            "autotuned": {"rows_per_block": shape[0], "xcd_remap": shape[1], "spread_pass": shape[2]},
             "batched_scatterer_steps_per_s": work / t_batch,
             "plain_one_by_one_scatterer_steps_per_s": work / t_plain,
             "batched_over_plain": t_plain / t_batch}

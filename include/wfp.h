@@ -315,10 +315,19 @@ wfp_status wfp_plan_autotune(wfp_plan* plan, int32_t trial_levels, int32_t* over
  *                     at or beyond an instance's end are not written.  Waits
  *                     for the batch's earlier work.
  *   wfp_batch_reset   all instances back to level 0.
- *   wfp_batch_autotune  from level 0: times trial_levels levels for each launch
- *                     shape of the local sum (4 or 8 rows per block, with or
- *                     without the XCD-aware block order), keeps the fastest,
- *                     reports it and leaves the batch at level 0.
+ *   wfp_batch_autotune  from level 0: times trial_levels levels for each
+ *                     launch shape: the local sum's (4 or 8 rows per block,
+ *                     with or without the XCD-aware block order) times the
+ *                     spread tile (0: one fine-grid row per workgroup, the
+ *                     type-1 spread fused into the transform's row pass; 1: a
+ *                     separate pass over tiles of 256 consecutive cells, the
+ *                     row pass reading the spread grid; the sources are
+ *                     binned per fine-grid cell either way), keeps the
+ *                     fastest, reports it and leaves the batch at level 0.
+ *                     Every shape computes the same bits.
+ *   wfp_batch_set_shape  sets that launch shape directly (rows_per_block 4 or
+ *                     8, xcd_remap 0 or 1, spread_pass 0 or 1); waits for the
+ *                     batch's earlier work.  Errors: WFP_EINVAL.
  *   wfp_batch_size    number of instances and the current level.
  *   wfp_batch_plan    instance i's plan (owned by the batch: never destroy it;
  *                     wfp_get_state / wfp_plan_info on it are valid between runs).
@@ -331,7 +340,9 @@ wfp_status wfp_batch_run(wfp_batch* batch, int64_t n_steps, double* const* u_rec
 wfp_status wfp_batch_set_levels(wfp_batch* batch, const int64_t* n_levels);
 wfp_status wfp_batch_reset(wfp_batch* batch);
 wfp_status wfp_batch_autotune(wfp_batch* batch, int32_t trial_levels, int32_t* rows_per_block,
-                              int32_t* xcd_remap);
+                              int32_t* xcd_remap, int32_t* spread_pass);
+wfp_status wfp_batch_set_shape(wfp_batch* batch, int32_t rows_per_block, int32_t xcd_remap,
+                               int32_t spread_pass);
 wfp_status wfp_batch_size(const wfp_batch* batch, int32_t* n, int64_t* level);
 wfp_plan* wfp_batch_plan(wfp_batch* batch, int32_t i);
 void wfp_batch_destroy(wfp_batch* batch);

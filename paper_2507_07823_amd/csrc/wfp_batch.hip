@@ -21,8 +21,8 @@ struct wfp_batch {
   int2 *wl_inc = nullptr, *wl_loc4 = nullptr, *wl_loc8 = nullptr, *wl_a = nullptr, *wl_b = nullptr,
        *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr, *wl_otf = nullptr,
        *wl_swt = nullptr, *wl_sww = nullptr, *wl_g8 = nullptr, *wl_g4 = nullptr, *wl_rcv = nullptr,
-       *wl_otfr = nullptr;
-  int n_otfr = 0;
+       *wl_otfr = nullptr, *wl_sp = nullptr;
+  int n_otfr = 0, n_sp = 0;
   int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0, n_otf = 0,
       n_swt = 0, n_sww = 0, n_g8 = 0, n_g4 = 0, n_rcv = 0;
   // receiver outputs of the current run: per instance a device pointer (or
@@ -39,6 +39,10 @@ struct wfp_batch {
   std::vector<int> cnt_swt, cnt_sww;
   // launch shape of the local sum: rows per block (4 or 8) and the XCD remap
   int loc_rows = 4, loc_xcd = 1;
+  // spread tile: 0 = one fine-grid row per workgroup, spread inside the row
+  // pass of the transform (cells n1 apart); 1 = 256 consecutive cells per
+  // workgroup in a separate coalesced pass, the row pass reading the grid
+  int spread_pass = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<void*> owned;
@@ -106,6 +110,7 @@ InstDesc describe(const wfp_plan* P) {
   d.T1 = P->T1;
   d.V = P->V;
   d.grid2 = P->grid2;
+  d.gsp = P->gsp;
   d.dk1 = P->dk1;
   d.dk2 = P->dk2;
   d.pk = P->pk;
@@ -207,10 +212,13 @@ void build_batch(wfp_batch* B) {
   std::vector<InstDesc> desc(n);
   // otf, loc4, loc8, g8, g4: (instance, blocks); g8 / g4: instances whose
   // lag blocks are short (the plan's lanes per lag), 4 rows per block
-  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf, otfr, g8, g4, rcv;
+  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf, otfr, g8, g4, rcv, sp;
   for (int i = 0; i < n; ++i) {
+    // the spread grid of the separate spread pass
+    if (!B->plans[i]->gsp) B->plans[i]->gsp = B->plans[i]->alloc<double>(B->plans[i]->nf);
     const wfp_plan* P = B->plans[i];
     desc[i] = describe(P);
+    for (int b = 0; b < (int)nblk(P->nf, 256); ++b) sp.push_back(make_int2(i, b));
     const int M = (int)P->M;
     const int rpb = 256 / desc[i].pp;
     for (int b = 0; b < (int)nblk(M, rpb); ++b) inc.push_back(make_int2(i, b));
@@ -269,6 +277,7 @@ void build_batch(wfp_batch* B) {
   B->wl_loc4 = upload_work(B, xcd_balanced(loc4), 8, B->n_loc4);
   B->wl_loc8 = upload_work(B, xcd_balanced(loc8), 8, B->n_loc8);
   B->wl_a = upload_work(B, wa, 1, B->n_a);
+  B->wl_sp = upload_work(B, sp, 1, B->n_sp);
   B->wl_b = upload_work(B, wb, 1, B->n_b);
   B->wl_c = upload_work(B, wc, 1, B->n_c);
   B->wl_dir = upload_work(B, dir, 1, B->n_dir);
@@ -309,8 +318,12 @@ void enqueue_level(wfp_batch* B) {
   {
     hipStream_t c = B->bs2;
     BatchLaunch bc{B->desc_d, nullptr, B->level_d};
+    if (B->spread_pass) {
+      bc.work = B->wl_sp;
+      hipLaunchKernelGGL(kb_spread_grid, dim3(B->n_sp), dim3(256), 0, c, bc);
+    }
     bc.work = B->wl_a;
-    hipLaunchKernelGGL(kb_hist_a, dim3(B->n_a), dim3(256), B->lds_a, c, bc);
+    hipLaunchKernelGGL(kb_hist_a, dim3(B->n_a), dim3(256), B->lds_a, c, bc, B->spread_pass);
     bc.work = B->wl_b;
     hipLaunchKernelGGL(kb_hist_b, dim3(B->n_b), dim3(512), B->lds_b, c, bc);
     bc.work = B->wl_c;
@@ -606,7 +619,8 @@ wfp_status wfp_batch_reset(wfp_batch* B) {
   });
 }
 
-wfp_status wfp_batch_autotune(wfp_batch* B, int32_t trial_levels, int32_t* rows_per_block, int32_t* xcd_remap) {
+wfp_status wfp_batch_autotune(wfp_batch* B, int32_t trial_levels, int32_t* rows_per_block, int32_t* xcd_remap,
+                              int32_t* spread_pass) {
   if (!B || trial_levels < 1) {
     g_last_error = "autotune needs a batch and trial_levels >= 1";
     return WFP_EINVAL;
@@ -620,11 +634,14 @@ wfp_status wfp_batch_autotune(wfp_batch* B, int32_t trial_levels, int32_t* rows_
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&c));
     float best = 1e30f;
-    int br = 4, bx = 1;
-    const int cand[4][2] = {{4, 1}, {8, 1}, {4, 0}, {8, 0}};
+    int br = 4, bx = 1, bs = 0;
+    // (rows per block, XCD remap, spread tile)
+    const int cand[8][3] = {{4, 1, 0}, {8, 1, 0}, {4, 0, 0}, {8, 0, 0},
+                            {4, 1, 1}, {8, 1, 1}, {4, 0, 1}, {8, 0, 1}};
     for (const auto& cd : cand) {
       B->loc_rows = cd[0];
       B->loc_xcd = cd[1];
+      B->spread_pass = cd[2];
       drop_graph(B);
       capture(B);
       HIPCHK(hipGraphLaunch(B->exec, B->bs));       // warm-up level
@@ -638,6 +655,7 @@ wfp_status wfp_batch_autotune(wfp_batch* B, int32_t trial_levels, int32_t* rows_
         best = ms;
         br = cd[0];
         bx = cd[1];
+        bs = cd[2];
       }
       reset_batch(B);
     }
@@ -645,9 +663,28 @@ wfp_status wfp_batch_autotune(wfp_batch* B, int32_t trial_levels, int32_t* rows_
     HIPCHK(hipEventDestroy(c));
     B->loc_rows = br;
     B->loc_xcd = bx;
+    B->spread_pass = bs;
     drop_graph(B);
     if (rows_per_block) *rows_per_block = br;
     if (xcd_remap) *xcd_remap = bx;
+    if (spread_pass) *spread_pass = bs;
+  });
+}
+
+wfp_status wfp_batch_set_shape(wfp_batch* B, int32_t rows_per_block, int32_t xcd_remap, int32_t spread_pass) {
+  if (!B || (rows_per_block != 4 && rows_per_block != 8) || (xcd_remap != 0 && xcd_remap != 1) ||
+      (spread_pass != 0 && spread_pass != 1)) {
+    g_last_error = "set_shape takes a batch, rows_per_block 4 or 8, xcd_remap 0 or 1, spread_pass 0 or 1";
+    return WFP_EINVAL;
+  }
+  return guard([&] {
+    HIPCHK(hipSetDevice(B->device));
+    // the captured level is rebuilt at the next run, after the earlier levels
+    HIPCHK(hipStreamSynchronize(B->bs));
+    B->loc_rows = rows_per_block;
+    B->loc_xcd = xcd_remap;
+    B->spread_pass = spread_pass;
+    drop_graph(B);
   });
 }
 

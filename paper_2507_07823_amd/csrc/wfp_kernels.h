@@ -275,6 +275,7 @@ struct InstDesc {
   const double2* tw1;
   double2 *T1, *V;
   double* grid2;
+  double* gsp;                 // fine grid spread by a separate pass (batched spread_pass 1)
   const double *dk1, *dk2, *pk, *qk, *rot;
   double2 *ring, *alpha, *dalpha, *ybuf;
   const int *dt_g0, *dt_n, *dt_p0, *pt_cs, *pt_cn;
@@ -318,7 +319,8 @@ __global__ void kb_local_g8(BatchLaunch b);
 __global__ void kb_local_g4(BatchLaunch b);
 __global__ void kb_local_otf(BatchLaunch b);
 __global__ void kb_local_otf_reduce(BatchLaunch b);
-__global__ void kb_hist_a(BatchLaunch b);
+__global__ void kb_spread_grid(BatchLaunch b);
+__global__ void kb_hist_a(BatchLaunch b, int from_grid);
 __global__ void kb_hist_b(BatchLaunch b);
 __global__ void kb_hist_c(BatchLaunch b);
 __global__ void kb_solve_direct(BatchLaunch b);

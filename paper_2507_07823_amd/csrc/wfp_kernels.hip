@@ -2035,13 +2035,33 @@ __global__ void __launch_bounds__(256) kb_local_otf_reduce(BatchLaunch b) {
                           d.loc, w.y);
 }
 
-__global__ void __launch_bounds__(256) kb_hist_a(BatchLaunch b) {
+// Type-1 spreading as its own pass: a work item is 256 consecutive cells of
+// one instance's fine grid (one thread per cell, coalesced), written to the
+// instance's spread grid for kb_hist_a(from_grid = 1).
+__global__ void __launch_bounds__(256) kb_spread_grid(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;
+  const int cell = w.y * 256 + (int)threadIdx.x;
+  if (cell >= d.nf) return;
+  const double* sig = d.hist + (int64_t)mod_slot(*b.level - 1, d.NH) * d.M;
+  d.gsp[cell] = spread_cell(cell, sig, d.M, d.cstart, d.ccount, d.swoff, d.sw);
+}
+
+// Row pass of the fine-grid transform; from_grid = 0 spreads the row's cells
+// itself, 1 reads them from the spread grid.
+__global__ void __launch_bounds__(256) kb_hist_a(BatchLaunch b, int from_grid) {
   const int2 w = b.work[blockIdx.x];
   if (w.x < 0) return;
   const InstDesc& d = b.desc[w.x];
   if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
-  const double* sig = d.hist + (int64_t)mod_slot(*b.level - 1, d.NH) * d.M;
   const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+  if (from_grid) {
+    k_hist_a_body(d.f2, d.n1, nullptr, 0, nullptr, nullptr, nullptr, nullptr, d.tw, d.T1, none, w.y, d.gsp);
+    return;
+  }
+  const double* sig = d.hist + (int64_t)mod_slot(*b.level - 1, d.NH) * d.M;
   k_hist_a_body(d.f2, d.n1, sig, d.M, d.cstart, d.ccount, d.swoff, d.sw, d.tw, d.T1, none, w.y);
 }
 

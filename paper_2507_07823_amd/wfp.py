@@ -110,8 +110,10 @@ def load_library():
     lib.wfp_batch_reset.argtypes = [vp]
     lib.wfp_batch_reset.restype = ctypes.c_int32
     lib.wfp_batch_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                                       ctypes.POINTER(ctypes.c_int32)]
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.wfp_batch_autotune.restype = ctypes.c_int32
+    lib.wfp_batch_set_shape.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.wfp_batch_set_shape.restype = ctypes.c_int32
     lib.wfp_batch_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
     lib.wfp_batch_size.restype = ctypes.c_int32
     lib.wfp_batch_plan.argtypes = [vp, ctypes.c_int32]
@@ -435,10 +437,17 @@ class Batch:
         _check(self._lib.wfp_batch_reset(self._h))
 
     def autotune(self, trial_levels=5):
+        """Time every launch shape from level 0 and keep the fastest; returns
+        (rows_per_block, xcd_remap, spread_pass)."""
         r = ctypes.c_int32()
         x = ctypes.c_int32()
-        _check(self._lib.wfp_batch_autotune(self._h, int(trial_levels), ctypes.byref(r), ctypes.byref(x)))
-        return r.value, x.value
+        sp = ctypes.c_int32()
+        _check(self._lib.wfp_batch_autotune(self._h, int(trial_levels), ctypes.byref(r), ctypes.byref(x),
+                                            ctypes.byref(sp)))
+        return r.value, x.value, sp.value
+
+    def set_shape(self, rows_per_block, xcd_remap, spread_pass):
+        _check(self._lib.wfp_batch_set_shape(self._h, int(rows_per_block), int(xcd_remap), int(spread_pass)))
 
     def plan(self, i):
         """Instance i's plan (borrowed: valid while the batch lives)."""

@@ -126,12 +126,24 @@ def test_autotune_and_reset_keep_results(wfp):
     b.reset()
     assert b.level == 0
     shape = b.autotune(3)
-    say(f"autotuned local-sum shape: rows per block {shape[0]}, xcd remap {shape[1]}")
-    assert shape[0] in (4, 8) and shape[1] in (0, 1)
+    say(f"autotuned launch shape: rows per block {shape[0]}, xcd remap {shape[1]}, spread pass {shape[2]}")
+    assert shape[0] in (4, 8) and shape[1] in (0, 1) and shape[2] in (0, 1)
     assert b.level == 0
     again = _batch_run(b, insts, n)
     for a, c in zip(first, again):
         assert np.array_equal(a, c)
+    # every launch shape, the spread tile included, computes the same bits
+    for rows in (4, 8):
+        for xcd in (0, 1):
+            for sp in (0, 1):
+                b.reset()
+                b.set_shape(rows, xcd, sp)
+                out = _batch_run(b, insts, n)
+                say(f"  shape ({rows}, {xcd}, {sp})")
+                for a, c in zip(first, out):
+                    assert np.array_equal(a, c)
+    with pytest.raises(wfp.WFPError):
+        b.set_shape(6, 0, 0)
     b.close()
 
 

@@ -109,10 +109,14 @@ def test_batch_rejects_free_space_before_any_device_work(lib):
 
 
 def test_null_plan_arguments_rejected(lib):
-    """The driven march and the schedule autotune check their arguments
-    before any device call."""
+    """The driven march, the schedule autotunes and the batch's launch-shape
+    setter check their arguments before any device call."""
     NULL = ctypes.c_void_p(0)
     g = (ctypes.c_double * 4)()
     assert lib.wfp_run_driven(NULL, 1, ctypes.cast(g, ctypes.c_void_p), NULL, 1, NULL) == wfp.WFP_EINVAL
     assert lib.wfp_plan_autotune(NULL, 3, None) == wfp.WFP_EINVAL
     assert b"plan" in lib.wfp_last_error()
+    assert lib.wfp_batch_autotune(NULL, 3, None, None, None) == wfp.WFP_EINVAL
+    assert b"batch" in lib.wfp_last_error()
+    assert lib.wfp_batch_set_shape(NULL, 4, 1, 0) == wfp.WFP_EINVAL
+    assert b"batch" in lib.wfp_last_error()
