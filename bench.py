@@ -721,6 +721,11 @@ def headline(steps, warmup, profile_levels):
                     "traffic": read_traffic("wfp::k_local_otf_sym"), "avg_launch_ms": avg,
                     "flops_per_launch": flops, "flop_count": "ordered neighbour pairs x 1.6 kflop",
                     "timed_with": "HIP events on the plan's stream"}
+        # the operands each lane reads from LDS per (unordered pair, node): the
+        # source and row stencils (p values each) and the window piece
+        lds = info["n_pairs"] / 2 * info["n_gl_local"] * (2 * info["p"] + 6) * 8.0
+        roofline["lds_operand_bytes_per_launch"] = lds
+        roofline["lds_operand_GBps"] = lds / (avg * 1e-3) / 1e9
         log(f"stages: {json.dumps(stages)}")
     parity = clumped_parity(plan, p)
     log(f"parity vs oracle: {parity}")
