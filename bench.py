@@ -360,7 +360,7 @@ def cpu_baseline(levels):
                       f"0..{levels - 1} of the CPU oracle, timed after its {pre:.0f} s set-up"}
 
 
-def _adjoint_run(p, levels, every):
+def _adjoint_run(p, levels, every, positions=True, local_mode=0):
     """Forward march then gradient pass over `levels` levels of the adjoint
     workload on a plan with checkpoint_every = `every` (> 0: checkpoints, the
     gradient pass replays each segment; < 0: every level recorded in blocks of
@@ -370,39 +370,43 @@ def _adjoint_run(p, levels, every):
     from paper_2507_07823_amd import wfp
     M, R = p["x"].size, p["x_recv"].size
     t0 = time.perf_counter()
-    plan = wfp.Plan(p, p["dt"], checkpoint_every=every)
+    plan = wfp.Plan(p, p["dt"], checkpoint_every=every, local_mode=local_mode)
     setup = time.perf_counter() - t0
     u = torch.empty((levels, R), dtype=torch.float64, device="cuda")
     first = min(levels, abs(every))
     plan.run(first, None, 1, u[:first])
-    plan.gradient(p["dt"] * u[:first])               # warm-up and one-time set-up
+    plan.gradient(p["dt"] * u[:first], positions=positions)   # warm-up and one-time set-up
     plan.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.run(levels, None, 1, u)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    log(f"adjoint workload, checkpoint_every {every}, local_mode {local_mode}: forward {levels} levels {t_fwd:.2f} s")
     e = p["dt"] * u                                  # dJ/du of J = dt/2 sum u^2
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    gb, gx = plan.gradient(e)
+    gb, gx = plan.gradient(e, positions=positions)
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
-    ok = bool(torch.isfinite(gb).all() and torch.isfinite(gx).all())
-    dev_bytes = plan.query_info()["device_bytes"]
+    log(f"  gradient pass ({'beta, x' if positions else 'beta'}) {t_bwd:.2f} s")
+    ok = bool(torch.isfinite(gb).all() and (gx is None or torch.isfinite(gx).all()))
+    info = plan.query_info()
     plan.close()
-    return {"levels": levels, "checkpoint_every": every, "plan_setup_s": setup, "forward_s": t_fwd,
+    return {"levels": levels, "checkpoint_every": every, "local_mode": info["local_mode"],
+            "gradients": "beta, x" if positions else "beta", "plan_setup_s": setup, "forward_s": t_fwd,
             "gradient_s": t_bwd, "forward_scatterer_steps_per_s": M * levels / t_fwd,
             "forward_plus_gradient_scatterer_steps_per_s": M * levels / (t_fwd + t_bwd),
-            "gradient_over_forward_time": t_bwd / t_fwd, "device_bytes": dev_bytes, "finite": ok}
+            "gradient_over_forward_time": t_bwd / t_fwd, "device_bytes": info["device_bytes"], "finite": ok}
 
 
 def adjoint_leg(levels, every):
     """Forward + gradient pass on the adjoint workload (M = 1e5 springs, 64
     receivers, dt = 1e-3): over `levels` levels with every level recorded
     (blocks of `every`), and over at most 1000 levels with checkpoints every
-    `every` levels (the replayed form), against a plain forward march (no
-    checkpoints, no recording) of the same levels."""
+    `every` levels (the replayed form) and for dJ/dbeta alone with the weights
+    stored per ordered pair and once per pair (recorded), against a plain
+    forward march (no checkpoints, no recording) of the same levels."""
     import torch
     from paper_2507_07823_amd import wfp, workloads
     p = workloads.adjoint_periodic()
@@ -416,14 +420,18 @@ def adjoint_leg(levels, every):
     plain.run(levels, None, 1, u)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    log(f"adjoint workload: plain forward {levels} levels {t_plain:.2f} s")
     plain.close()
     del u
     rec = _adjoint_run(p, levels, -every)
     ck = _adjoint_run(p, min(levels, 1000), every)
+    # dJ/dbeta alone: weights stored per ordered pair against once per pair
+    b1 = _adjoint_run(p, min(levels, 1000), -every, positions=False, local_mode=1)
+    b3 = _adjoint_run(p, min(levels, 1000), -every, positions=False, local_mode=3)
     return {"workload": "periodic adjoint", "M": M, "R": R, "levels": levels,
             "beta": [round(float(p["beta"].min()), 4), round(float(p["beta"].max()), 4)],
             "plain_forward_s": t_plain, "plain_scatterer_steps_per_s": M * levels / t_plain,
-            "recorded": rec, "checkpointed": ck,
+            "recorded": rec, "checkpointed": ck, "beta_only_per_pair": b1, "beta_only_pair_once": b3,
             "forward_plus_gradient_over_plain_time": (rec["forward_s"] + rec["gradient_s"]) / t_plain}
 
 

@@ -2157,8 +2157,14 @@ wfp_status wfp_adjoint(wfp_plan* P, int64_t n_levels, const double* dJdu, double
     g_last_error = "the gradient pass needs receivers (R >= 1)";
     return WFP_EINVAL;
   }
-  if (P->otf) {
-    g_last_error = "the gradient pass needs stored local weights (local_mode 1)";
+  if (P->otf && !P->sym_stored) {
+    g_last_error = "the gradient pass needs stored local weights (local_mode 1, or 3 for dJ/dbeta alone)";
+    return WFP_EDOMAIN;
+  }
+  if (P->sym_stored && grad_x) {
+    // the position gradient's derivative weights are packed like the weights
+    // stored per ordered pair
+    g_last_error = "dJ/dx needs the weights stored per ordered pair (local_mode 1); local_mode 3 gives dJ/dbeta alone";
     return WFP_EDOMAIN;
   }
   if (P->ckpt_every == 0 || !P->ck_from0 || P->level < n_levels) {

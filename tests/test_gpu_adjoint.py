@@ -53,9 +53,9 @@ def _oracle_gradient(p, n, seed=50):
     return dJdu, gb, gx, u
 
 
-def _gpu_gradient(w, p, n, dJdu, every, positions=True):
+def _gpu_gradient(w, p, n, dJdu, every, positions=True, **kw):
     import torch
-    plan = w.Plan(p, p["dt"], checkpoint_every=every)
+    plan = w.Plan(p, p["dt"], checkpoint_every=every, **kw)
     u = torch.empty((n, p["x_recv"].size), dtype=torch.float64, device="cuda")
     plan.run(n, None, 1, u)
     e = torch.from_numpy(np.ascontiguousarray(dJdu)).cuda()
@@ -103,6 +103,30 @@ def test_gradient_ragged_segments(wfp):
         assert np.array_equal(u4, u) and np.array_equal(gb4, gb) and np.array_equal(gx4, gx), blk
     _, gb5, gx5 = _gpu_gradient(wfp, p, n, dJdu, -37, positions=False)
     assert gx5 is None and np.array_equal(gb5, gb)
+
+
+def test_pair_once_beta_gradient(wfp):
+    """dJ/dbeta with the weights stored once per unordered pair (local_mode 3;
+    the adjoint level applies the same symmetric local sum): the ragged case
+    against the oracle's reverse sweep, against local_mode 1 (the same sums in
+    another order), and with recorded levels against checkpoints (the same
+    bits).  dJ/dx is refused there."""
+    p = _case(8, 60, 4, 0.01, (0.0, 2.0), [1.0, -1.6, 0.1, 20.0, 0.3])
+    n = 237
+    say(f"adjoint pair-once: M=60 R=4 dt=0.01 levels={n} checkpoint_every=50, local_mode 3, dJ/dbeta")
+    dJdu, gb_o, _, u_o = _oracle_gradient(p, n, seed=51)
+    u3, gb3, gx3 = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=3)
+    assert gx3 is None
+    eu, eb = rho(u3, u_o), rho(gb3, gb_o)
+    _, gb1, _ = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=1)
+    e13 = rho(gb3, gb1)
+    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  against local_mode 1: {e13:.2e}")
+    assert eu < TOL and eb < TOL and e13 < 1e-12
+    u4, gb4, _ = _gpu_gradient(wfp, p, n, dJdu, -37, positions=False, local_mode=3)
+    assert np.array_equal(u4, u3) and np.array_equal(gb4, gb3)
+    with pytest.raises(wfp.WFPError) as ei:
+        _gpu_gradient(wfp, p, n, dJdu, 50, positions=True, local_mode=3)
+    assert ei.value.status == wfp.WFP_EDOMAIN
 
 
 def test_recorded_levels_across_calls_and_resets(wfp):
@@ -282,6 +306,17 @@ def test_gradient_dense_nearby_coupling(wfp):
     torch.cuda.synchronize()
     rec.close()
     assert torch.equal(u2, u) and torch.equal(gb2, gb) and torch.equal(gx2, gx)
+    # dJ/dbeta with the weights stored once per unordered pair
+    po = wfp.Plan(p, p["dt"], checkpoint_every=100, local_mode=3)
+    assert po.info["solve_mode"] == 1 and po.info["local_mode"] == 3
+    u3 = torch.empty_like(u)
+    po.run(n, None, 1, u3)
+    gb3, _ = po.gradient(torch.from_numpy(np.ascontiguousarray(g["dJdu"])).cuda(), positions=False)
+    torch.cuda.synchronize()
+    po.close()
+    e3u, e3b = rho(u3.cpu().numpy(), g["u"]), rho(gb3.cpu().numpy(), g["grad_beta"])
+    say(f"  local_mode 3: rho(u) = {e3u:.2e}  rho(beta) = {e3b:.2e}")
+    assert e3u < TOL and e3b < TOL
 
 
 def _clear_of_breaks(x, xr, j, h, prm, z):
