@@ -107,11 +107,10 @@ typedef struct {
   int32_t local_mode;      /* 1: local weights stored per pair (read every level); 2: evaluated on the
                               fly every level (memory O(M), arithmetic O(pairs N_L p)); 3: stored once
                               per unordered pair (Q_m depends on the distance alone) and applied to
-                              both rows, about half the bytes of 1, gradient pass for dJ/dbeta
-                              only (wfp_adjoint with grad_x returns WFP_EDOMAIN) and not in
-                              batches; 0: stored (1) when they fit in
-                              60% of the free device memory, else 3 when half of that fits and
-                              checkpoint_every is 0, else on the fly   [0] */
+                              both rows, about half the bytes of 1 (the gradient pass's
+                              derivative weights likewise), not in batches; 0: stored (1) when
+                              they fit in 60% of the free device memory, else 3 when half of
+                              that fits, else on the fly                     [0] */
   int32_t check_finite;    /* nonzero: every wfp_run ends by checking the newest density level and the
                               mode state alpha, alpha' for NaN or Inf (one small kernel), waits for the
                               plan's stream and returns WFP_ENONFINITE if any is found (the levels stay
@@ -223,12 +222,12 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
 
 /* Gradient of a receiver loss J(u) through the march (not in the paper: the
  * transpose of every step of Section 4.2, run backwards in time).
- * Requires a periodic plan with R >= 1, stored local weights (local_mode 1; or
- * 3, with grad_x NULL) and checkpoint_every != 0 whose levels 0 .. n_levels-1
- * were computed by wfp_run since plan creation or wfp_reset (no
- * wfp_set_state in between); the plan's own state is not changed.  The
- * adjoint level applies the same local sum as the forward one: Q_m depends
- * on the distance alone, so the sum over pairs is its own transpose.
+ * Requires a periodic plan with R >= 1, stored local weights (local_mode 1 or
+ * 3) and checkpoint_every != 0 whose levels 0 .. n_levels-1 were computed by
+ * wfp_run since plan creation or wfp_reset (no wfp_set_state in between); the
+ * plan's own state is not changed.  The adjoint level applies the same local
+ * sum as the forward one: Q_m depends on the distance alone, so the sum over
+ * pairs is its own transpose.
  *   dJdu       device [n_levels][R]: dJ/du(x_r, t_L) for the levels 0..n_levels-1
  *   grad_beta  device [M] (caller order): dJ/dbeta_j
  *   grad_x     device [M] (caller order) or NULL: dJ/dx_j (the local weights are
@@ -238,11 +237,12 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
  * Device memory: the first call allocates an adjoint march state and, with
  * checkpoints, a replay state, a segment of checkpoint_every + m_max - 1
  * density levels and one of checkpoint_every derivative terms; with grad_x,
- * derivative weights as large as the local weights.  With recorded levels
+ * derivative weights as large as the local weights (stored per ordered pair
+ * or once per pair, as the weights are).  With recorded levels
  * (checkpoint_every < 0) the recorded blocks take the place of the replay.
  * Asynchronous on the plan's stream.
- * Errors: WFP_EINVAL, WFP_EDOMAIN (free space, weights on the fly, grad_x with
- * local_mode 3), WFP_ESTATE, WFP_ENOMEM, WFP_EHIP. */
+ * Errors: WFP_EINVAL, WFP_EDOMAIN (free space, weights on the fly), WFP_ESTATE,
+ * WFP_ENOMEM, WFP_EHIP. */
 wfp_status wfp_adjoint(wfp_plan* plan, int64_t n_levels, const double* dJdu, double* grad_beta,
                        double* grad_x);
 

@@ -202,6 +202,13 @@ struct wfp_plan {
   int64_t* otf_part_off = nullptr;
   double* otf_part = nullptr;
   double* otf_rowacc = nullptr;
+  // gradient pass with weights stored once per pair: the signed derivative
+  // weights of each row's upper range (lags 0 .. NQ - 1, packed like sym_q),
+  // the two sums' row and column terms, and a row scale of ones
+  int64_t* symd_rb = nullptr;
+  uint2* symd_acx = nullptr;
+  double *symd_q = nullptr, *symd_row1 = nullptr, *symd_row2 = nullptr, *symd_col1 = nullptr,
+         *symd_col2 = nullptr, *symd_one = nullptr;
   double *otf_na = nullptr, *otf_nw = nullptr;
   int otf_nblk = 0;
   // stored weights: the lags >= 2 part of the local sum of level L, in

@@ -70,6 +70,12 @@ __global__ void k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, c
                                  const uint2* __restrict__ sacx, const double* __restrict__ Qs,
                                  const int64_t* __restrict__ upb, double* __restrict__ rowacc,
                                  double* __restrict__ colpart);
+__global__ void k_local_sym_deriv2(int M, int NQ, int NH, const int* __restrict__ up_end,
+                                   const double* __restrict__ h1, int64_t r1, const double* __restrict__ h2,
+                                   int64_t L2, const int64_t* __restrict__ rb, const uint2* __restrict__ sacx,
+                                   const double* __restrict__ Qs, const int64_t* __restrict__ upb,
+                                   double* __restrict__ row1, double* __restrict__ row2, double* __restrict__ col1,
+                                   double* __restrict__ col2);
 __global__ void k_local_sym_reduce(int M, const int2* __restrict__ cov, const int64_t* __restrict__ upb,
                                    const double* __restrict__ rowacc, const double* __restrict__ colpart,
                                    const double* __restrict__ scale, double* __restrict__ out);

@@ -1083,6 +1083,89 @@ k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __rest
   if (lane == 0) rowacc[j] = acc;
 }
 
+// The gradient pass's two signed derivative local sums (lags 0 .. NQ - 1)
+// from derivative weights stored once per unordered pair.  Row j's weight
+// for the source l of its upper range is w = (1/2) dQ_m/dd sign(x_j - x_l),
+// which changes sign with the pair's order, so row l's share is -w times row
+// j's values.  Values for the first sum from a linear buffer (row r1 - m for
+// lag m: the forward densities of the segment and the NQ - 1 levels before
+// it), for the second from a ring (slot L2 - m mod NH: the adjoint state).
+// One wavefront per row as in k_local_sym_rows; each pair's column terms,
+// negated, go to col1 / col2[upb[j] + i] (0 for the row itself), and
+// k_local_sym_reduce adds them up per row.
+__global__ void __launch_bounds__(256)
+k_local_sym_deriv2(int M, int NQ, int NH, const int* __restrict__ up_end, const double* __restrict__ h1, int64_t r1,
+                   const double* __restrict__ h2, int64_t L2, const int64_t* __restrict__ rb,
+                   const uint2* __restrict__ sacx, const double* __restrict__ Qs, const int64_t* __restrict__ upb,
+                   double* __restrict__ row1, double* __restrict__ row2, double* __restrict__ col1,
+                   double* __restrict__ col2) {
+  __shared__ double rv1[4][kMaxOtfLags + 1], rv2[4][kMaxOtfLags + 1];   // each row's own values, lags 0 .. NQ - 1
+  __shared__ uint2 cw[4][kMaxOtfLags + 1];
+  __shared__ int64_t s1[kMaxOtfLags + 1], s2[kMaxOtfLags + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nb = gridDim.x;
+  const int j = xcd_block(blockIdx.x, nb) * 4 + wv;
+  for (int m = threadIdx.x; m < NQ; m += blockDim.x) {
+    s1[m] = (r1 - m) * M;
+    s2[m] = (int64_t)mod_slot(L2 - m, NH) * M;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4 * NQ; e += blockDim.x) {
+    const int w = e / NQ, m = e - w * NQ;
+    const int jr = xcd_block(blockIdx.x, nb) * 4 + w;
+    const bool ok = jr < M;
+    rv1[w][m] = ok ? h1[s1[m] + jr] : 0.0;
+    rv2[w][m] = ok ? h2[s2[m] + jr] : 0.0;
+    cw[w][m] = ok ? sacx[(int64_t)jr * NQ + m] : make_uint2(0u, 0u);
+  }
+  __syncthreads();
+  if (j >= M) return;                                         // no barrier below
+  const int n = up_end[j] - j;
+  const double* __restrict__ qrow = Qs + rb[j];
+  double* __restrict__ cp1 = col1 + upb[j];
+  double* __restrict__ cp2 = col2 + upb[j];
+  double a1 = 0.0, a2 = 0.0;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    const bool in = i < n;
+    int l = j + i;
+    if (l >= M) l -= M;
+    double p1 = 0.0, p2 = 0.0;
+    for (int mb = 0; mb < NQ; mb += 8) {
+      double w[8], g1[8], g2[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int m = mb + r;
+        const uint2 c = m < NQ ? cw[wv][m] : make_uint2(0u, 0u);
+        const bool on = in && i < (int)c.x;
+        w[r] = on ? qrow[c.y + i] : 0.0;
+        g1[r] = on ? h1[s1[m] + l] : 0.0;
+        g2[r] = on ? h2[s2[m] + l] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int m = mb + r;
+        if (m < NQ) {
+          a1 = fma(w[r], g1[r], a1);
+          a2 = fma(w[r], g2[r], a2);
+          p1 = fma(w[r], rv1[wv][m], p1);
+          p2 = fma(w[r], rv2[wv][m], p2);
+        }
+      }
+    }
+    if (in) {
+      cp1[i] = i == 0 ? 0.0 : -p1;
+      cp2[i] = i == 0 ? 0.0 : -p2;
+    }
+  }
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    row1[j] = a1;
+    row2[j] = a2;
+  }
+}
+
 // Row l's total of the pair-once stored local sum: its own sum plus the column
 // terms of the rows whose upper range covers it: rows cov[l].x .. l - 1 (up_end
 // is non-decreasing, so they are consecutive) and, in the periodic box, rows

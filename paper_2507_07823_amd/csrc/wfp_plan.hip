@@ -557,13 +557,12 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     int mode = par->local_mode;
     if (mode == 0) {
       // per ordered pair when the dense set-up array and the packed weights
-      // fit; else once per unordered pair (about half of both; no gradient
-      // pass, so only without checkpoints); else on the fly
+      // fit; else once per unordered pair (about half of both); else on the fly
       size_t fr = 0, to = 0;
       HIPCHK(hipMemGetInfo(&fr, &to));
       const double need = 8.0 * (double)tot * 1.7;
       if (need < 0.6 * (double)fr) mode = 1;
-      else if (par->checkpoint_every == 0 && 0.5 * need < 0.6 * (double)fr) mode = 3;
+      else if (0.5 * need < 0.6 * (double)fr) mode = 3;
       else mode = 2;
     }
     P->otf = mode == 2 || mode == 3;
@@ -1737,18 +1736,13 @@ void grad_setup(wfp_plan* P) {
   P->grad_ready = true;
 }
 
-// Signed derivative weights for the position gradient: scatterer rows packed
-// with lags m >= 0 (same source ranges as the weights), receivers in the
-// layout of their weights with the sign of x_source - x_receiver.
-void gradx_setup(wfp_plan* P) {
-  if (P->gradx_ready) return;
-  const int64_t M = P->M, R = P->R;
+// Weights stored per ordered pair: the signed derivative weights in the
+// layout of the weights (same source ranges, lags 0 .. NQ - 1).
+void gradx_setup_per_pair(wfp_plan* P, const double* halfs) {
+  const int64_t M = P->M;
   hipStream_t s = P->stream;
   double* tmp = P->alloc<double>(P->dense_total);
-  double* hs = P->alloc<double>(std::max(M, R));
-  std::vector<double> halfs(std::max(M, R), 0.5);
-  upload(hs, halfs, s);
-  launch_local_weights(P, (int)M, P->xs, P->nb_start, P->nb_count, P->qoff, hs, 1, nullptr, nullptr, tmp);
+  launch_local_weights(P, (int)M, P->xs, P->nb_start, P->nb_count, P->qoff, halfs, 1, nullptr, nullptr, tmp);
   std::vector<unsigned> ach((size_t)M * P->NQ);
   HIPCHK(hipMemcpyAsync(ach.data(), P->ac, ach.size() * sizeof(unsigned), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1773,6 +1767,91 @@ void gradx_setup(wfp_plan* P) {
   hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, 0,
                      P->nb_count, P->qoff, tmp, P->ac, P->drowbase, P->DQa);
   HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(tmp);
+}
+
+// Weights stored once per unordered pair: each row's signed derivative
+// weights against its upper range, per lag the run of sources that carry it
+// (from the row itself), packed; the row and column buffers of the two sums.
+void gradx_setup_pair_once(wfp_plan* P, const double* halfs) {
+  const int64_t M = P->M;
+  hipStream_t s = P->stream;
+  std::vector<int> up(M), ust(M), ucnt(M);
+  HIPCHK(hipMemcpyAsync(up.data(), P->otf_up_end, M * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int64_t> uoff(M);
+  int64_t tot_up = 0, np_up = 0;
+  for (int64_t j = 0; j < M; ++j) {
+    ust[j] = (int)j;
+    ucnt[j] = up[j] - (int)j;
+    uoff[j] = tot_up;
+    tot_up += (int64_t)ucnt[j] * P->NQ;
+    np_up += ucnt[j];
+  }
+  int* ust_d = P->alloc<int>(M);
+  int* ucnt_d = P->alloc<int>(M);
+  int64_t* uoff_d = P->alloc<int64_t>(M);
+  signed char* umlo = P->alloc<signed char>(np_up);
+  double* dense = P->alloc<double>(tot_up);
+  unsigned* uac = P->alloc<unsigned>((size_t)M * P->NQ);
+  upload(ust_d, ust, s);
+  upload(ucnt_d, ucnt, s);
+  upload(uoff_d, uoff, s);
+  launch_local_weights(P, (int)M, P->xs, ust_d, ucnt_d, uoff_d, halfs, 1, P->sym_upb, umlo, dense);
+  hipLaunchKernelGGL(k_row_ranges, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, ucnt_d,
+                     P->sym_upb, umlo, uac);
+  HIPCHK(hipGetLastError());
+  std::vector<unsigned> ach((size_t)M * P->NQ);
+  HIPCHK(hipMemcpyAsync(ach.data(), uac, ach.size() * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int64_t> rb(M);
+  std::vector<uint2> acxh((size_t)M * P->NQ);
+  int64_t packed = 0;
+  for (int64_t j = 0; j < M; ++j) {
+    rb[j] = packed;
+    unsigned within = 0;
+    for (int m = 0; m < P->NQ; ++m) {
+      const unsigned v = ach[(size_t)j * P->NQ + m];
+      const unsigned c = v >> 16;
+      if (c > 0 && (v & 0xffffu) != 0)
+        fail(WFP_EINVAL, "pair-once derivative weights: a lag's sources do not start at the row");
+      acxh[(size_t)j * P->NQ + m] = make_uint2(c, within);
+      within += c;
+    }
+    packed += within;
+  }
+  P->symd_rb = P->alloc<int64_t>(M);
+  P->symd_acx = P->alloc<uint2>(acxh.size());
+  P->symd_q = P->alloc<double>(packed + 2);
+  upload(P->symd_rb, rb, s);
+  upload(P->symd_acx, acxh, s);
+  hipLaunchKernelGGL(k_pack_weights, dim3(nblk(M, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)M, P->NQ, 0,
+                     ucnt_d, uoff_d, dense, uac, P->symd_rb, P->symd_q);
+  HIPCHK(hipGetLastError());
+  P->symd_row1 = P->alloc<double>(M);
+  P->symd_row2 = P->alloc<double>(M);
+  P->symd_col1 = P->alloc<double>(np_up);
+  P->symd_col2 = P->alloc<double>(np_up);
+  P->symd_one = P->alloc<double>(M);
+  upload(P->symd_one, std::vector<double>(M, 1.0), s);
+  HIPCHK(hipStreamSynchronize(s));
+  for (void* q : {(void*)dense, (void*)uac, (void*)umlo, (void*)ust_d, (void*)ucnt_d, (void*)uoff_d}) P->release(q);
+}
+
+// Signed derivative weights for the position gradient, (1/2) dQ_m/dd times
+// the sign of x_target - x_source: scatterer rows with lags m >= 0 (per
+// ordered pair in the layout of the weights, or once per pair), receivers in
+// the layout of their weights with the sign of x_source - x_receiver.
+void gradx_setup(wfp_plan* P) {
+  if (P->gradx_ready) return;
+  const int64_t M = P->M, R = P->R;
+  hipStream_t s = P->stream;
+  double* hs = P->alloc<double>(std::max(M, R));
+  std::vector<double> halfs(std::max(M, R), 0.5);
+  upload(hs, halfs, s);
+  if (P->sym_stored) gradx_setup_pair_once(P, hs);
+  else gradx_setup_per_pair(P, hs);
   std::vector<double> mhalf(R, -0.5);
   double* mh = P->alloc<double>(R);
   upload(mh, mhalf, s);
@@ -1782,7 +1861,6 @@ void gradx_setup(wfp_plan* P) {
   launch_local_weights(P, (int)R, P->xr, P->rnb_start, P->rnb_count, P->rqoff, mh, 1, nullptr, nullptr, P->dQr);
   if (P->ckpt_every > 0) P->segD = P->alloc<double>((size_t)P->ckpt_every * M);
   HIPCHK(hipStreamSynchronize(s));
-  P->release(tmp);
   P->release(hs);
   P->release(mh);
   P->gradx_ready = true;
@@ -1877,10 +1955,21 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
       march_level(P, adj, Rv, true, ex, nullptr, nullptr);
       if (wx) {
         deriv_field(P, adj);
-        const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
-        hipLaunchKernelGGL(k_local_deriv2, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)M, P->NQ, P->NH,
-                           P->nb_start, P->drowbase, P->acxd, P->DQa, (const double*)segsig,
-                           (int64_t)(hd + L - a), (const double*)P->ahist, Rv, P->xloc2, P->xloc);
+        if (P->sym_stored) {
+          hipLaunchKernelGGL(k_local_sym_deriv2, dim3(8 * nblk(nblk(M, 4), 8)), dim3(256), 0, s, (int)M, P->NQ,
+                             P->NH, P->otf_up_end, (const double*)segsig, (int64_t)(hd + L - a),
+                             (const double*)P->ahist, Rv, P->symd_rb, P->symd_acx, P->symd_q, P->sym_upb,
+                             P->symd_row1, P->symd_row2, P->symd_col1, P->symd_col2);
+          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 4)), dim3(256), 0, s, (int)M, P->sym_cov, P->sym_upb,
+                             P->symd_row1, P->symd_col1, P->symd_one, P->xloc2);
+          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 4)), dim3(256), 0, s, (int)M, P->sym_cov, P->sym_upb,
+                             P->symd_row2, P->symd_col2, P->symd_one, P->xloc);
+        } else {
+          const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
+          hipLaunchKernelGGL(k_local_deriv2, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)M, P->NQ, P->NH,
+                             P->nb_start, P->drowbase, P->acxd, P->DQa, (const double*)segsig,
+                             (int64_t)(hd + L - a), (const double*)P->ahist, Rv, P->xloc2, P->xloc);
+        }
       }
       hipLaunchKernelGGL(k_adj_grad, dim3(nblk(M, 256)), dim3(256), 0, s, (int)M, P->ahist + (Rv % P->NH) * M,
                          segsig + (hd + L - a) * M, P->beta, wx ? segD + (L - a) * M : nullptr, P->xloc2,
@@ -2158,13 +2247,7 @@ wfp_status wfp_adjoint(wfp_plan* P, int64_t n_levels, const double* dJdu, double
     return WFP_EINVAL;
   }
   if (P->otf && !P->sym_stored) {
-    g_last_error = "the gradient pass needs stored local weights (local_mode 1, or 3 for dJ/dbeta alone)";
-    return WFP_EDOMAIN;
-  }
-  if (P->sym_stored && grad_x) {
-    // the position gradient's derivative weights are packed like the weights
-    // stored per ordered pair
-    g_last_error = "dJ/dx needs the weights stored per ordered pair (local_mode 1); local_mode 3 gives dJ/dbeta alone";
+    g_last_error = "the gradient pass needs stored local weights (local_mode 1 or 3)";
     return WFP_EDOMAIN;
   }
   if (P->ckpt_every == 0 || !P->ck_from0 || P->level < n_levels) {

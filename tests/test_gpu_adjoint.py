@@ -105,28 +105,69 @@ def test_gradient_ragged_segments(wfp):
     assert gx5 is None and np.array_equal(gb5, gb)
 
 
-def test_pair_once_beta_gradient(wfp):
-    """dJ/dbeta with the weights stored once per unordered pair (local_mode 3;
-    the adjoint level applies the same symmetric local sum): the ragged case
-    against the oracle's reverse sweep, against local_mode 1 (the same sums in
-    another order), and with recorded levels against checkpoints (the same
-    bits).  dJ/dx is refused there."""
+def test_pair_once_gradient(wfp):
+    """Both gradients with the weights stored once per unordered pair
+    (local_mode 3: the adjoint level applies the same symmetric local sum,
+    and the signed derivative weights, antisymmetric in the pair, are stored
+    once too): the ragged case against the oracle's reverse sweep, against
+    local_mode 1 (the same sums in another order), and with recorded levels
+    against checkpoints (the same bits)."""
     p = _case(8, 60, 4, 0.01, (0.0, 2.0), [1.0, -1.6, 0.1, 20.0, 0.3])
     n = 237
-    say(f"adjoint pair-once: M=60 R=4 dt=0.01 levels={n} checkpoint_every=50, local_mode 3, dJ/dbeta")
-    dJdu, gb_o, _, u_o = _oracle_gradient(p, n, seed=51)
-    u3, gb3, gx3 = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=3)
-    assert gx3 is None
-    eu, eb = rho(u3, u_o), rho(gb3, gb_o)
-    _, gb1, _ = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=1)
-    e13 = rho(gb3, gb1)
-    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  against local_mode 1: {e13:.2e}")
-    assert eu < TOL and eb < TOL and e13 < 1e-12
-    u4, gb4, _ = _gpu_gradient(wfp, p, n, dJdu, -37, positions=False, local_mode=3)
-    assert np.array_equal(u4, u3) and np.array_equal(gb4, gb3)
-    with pytest.raises(wfp.WFPError) as ei:
-        _gpu_gradient(wfp, p, n, dJdu, 50, positions=True, local_mode=3)
-    assert ei.value.status == wfp.WFP_EDOMAIN
+    say(f"adjoint pair-once: M=60 R=4 dt=0.01 levels={n} checkpoint_every=50, local_mode 3")
+    dJdu, gb_o, gx_o, u_o = _oracle_gradient(p, n, seed=51)
+    u3, gb3, gx3 = _gpu_gradient(wfp, p, n, dJdu, 50, local_mode=3)
+    eu, eb, ex = rho(u3, u_o), rho(gb3, gb_o), rho(gx3, gx_o)
+    _, gb1, gx1 = _gpu_gradient(wfp, p, n, dJdu, 50, local_mode=1)
+    e13b, e13x = rho(gb3, gb1), rho(gx3, gx1)
+    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}; against local_mode 1: "
+        f"{e13b:.2e} / {e13x:.2e}")
+    assert eu < TOL and eb < TOL and ex < TOL and e13b < 1e-12 and e13x < 1e-12
+    u4, gb4, gx4 = _gpu_gradient(wfp, p, n, dJdu, -37, local_mode=3)
+    assert np.array_equal(u4, u3) and np.array_equal(gb4, gb3) and np.array_equal(gx4, gx3)
+    _, gb5, gx5 = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=3)
+    assert gx5 is None and np.array_equal(gb5, gb3)
+
+
+def test_pair_once_gradient_across_the_seam(wfp):
+    """Both gradients with the weights stored once per pair for 40 springs
+    within 0.5 of the periodic seam at +-pi (upper ranges wrap past the last
+    spring to the first), against the oracle's reverse sweep."""
+    rng = np.random.default_rng(23)
+    x = np.mod(rng.uniform(-0.5, 0.5, 40) + 2 * np.pi, 2 * np.pi) - np.pi
+    p = dict(x=x, beta=rng.uniform(1.0, 10.0, 40), packets=np.array([[1.0, 2.2, 0.1, 0.0, 0.0]]), boundary=0,
+             x_recv=np.array([np.pi - 0.3, -np.pi + 0.05, -np.pi + 0.4]), dt=0.01)
+    n = 150
+    say(f"adjoint pair-once across the seam: M=40 R=3 dt=0.01 levels={n} checkpoint_every=40, local_mode 3")
+    dJdu, gb_o, gx_o, u_o = _oracle_gradient(p, n, seed=52)
+    u3, gb3, gx3 = _gpu_gradient(wfp, p, n, dJdu, 40, local_mode=3)
+    eu, eb, ex = rho(u3, u_o), rho(gb3, gb_o), rho(gx3, gx_o)
+    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}")
+    assert eu < TOL and eb < TOL and ex < TOL
+
+
+def test_pair_once_gradient_full_size_matches_per_pair(wfp):
+    """At the adjoint workload's full size (M = 1e5, R = 64, 300 levels,
+    levels recorded): both gradients with the weights stored once per pair
+    against those stored per ordered pair (the same sums over about 1400
+    neighbours per spring, added in another order)."""
+    import torch
+    from paper_2507_07823_amd import workloads
+    p = workloads.adjoint_periodic()
+    n, R = 300, p["x_recv"].size
+    say(f"adjoint full size, local_mode 3 against 1: M={p['x'].size} R={R} levels={n}")
+    out = {}
+    for mode in (1, 3):
+        plan = wfp.Plan(p, p["dt"], checkpoint_every=-100, local_mode=mode)
+        u = torch.empty((n, R), dtype=torch.float64, device="cuda")
+        plan.run(n, None, 1, u)
+        gb, gx = plan.gradient(p["dt"] * u)
+        torch.cuda.synchronize()
+        out[mode] = (u.cpu().numpy(), gb.cpu().numpy(), gx.cpu().numpy())
+        plan.close()
+    eu, eb, ex = (rho(out[3][k], out[1][k]) for k in range(3))
+    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}")
+    assert eu < 1e-12 and eb < 1e-12 and ex < 1e-12
 
 
 def test_recorded_levels_across_calls_and_resets(wfp):
@@ -306,17 +347,18 @@ def test_gradient_dense_nearby_coupling(wfp):
     torch.cuda.synchronize()
     rec.close()
     assert torch.equal(u2, u) and torch.equal(gb2, gb) and torch.equal(gx2, gx)
-    # dJ/dbeta with the weights stored once per unordered pair
+    # both gradients with the weights stored once per unordered pair
     po = wfp.Plan(p, p["dt"], checkpoint_every=100, local_mode=3)
     assert po.info["solve_mode"] == 1 and po.info["local_mode"] == 3
     u3 = torch.empty_like(u)
     po.run(n, None, 1, u3)
-    gb3, _ = po.gradient(torch.from_numpy(np.ascontiguousarray(g["dJdu"])).cuda(), positions=False)
+    gb3, gx3 = po.gradient(torch.from_numpy(np.ascontiguousarray(g["dJdu"])).cuda())
     torch.cuda.synchronize()
     po.close()
-    e3u, e3b = rho(u3.cpu().numpy(), g["u"]), rho(gb3.cpu().numpy(), g["grad_beta"])
-    say(f"  local_mode 3: rho(u) = {e3u:.2e}  rho(beta) = {e3b:.2e}")
-    assert e3u < TOL and e3b < TOL
+    e3u, e3b, e3x = rho(u3.cpu().numpy(), g["u"]), rho(gb3.cpu().numpy(), g["grad_beta"]), rho(gx3.cpu().numpy(),
+                                                                                               g["grad_x"])
+    say(f"  local_mode 3: rho(u) = {e3u:.2e}  rho(beta) = {e3b:.2e}  rho(x) = {e3x:.2e}")
+    assert e3u < TOL and e3b < TOL and e3x < TOL
 
 
 def _clear_of_breaks(x, xr, j, h, prm, z):

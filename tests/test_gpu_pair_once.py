@@ -129,21 +129,19 @@ def test_pair_once_dense_cluster_against_oracle(wfp):
     assert e < TOL
 
 
-def test_pair_once_gradient_beta_only_and_batch_refusal(wfp):
+def test_pair_once_gradient_and_batch_refusal(wfp):
     """With weights stored once per unordered pair the gradient pass gives
-    dJ/dbeta (checked against the oracle in tests/test_gpu_adjoint.py) and
-    refuses dJ/dx; the batched form refuses the mode."""
+    both gradients (checked against the oracle in tests/test_gpu_adjoint.py);
+    the batched form refuses the mode."""
     import torch
     p = workloads.small_periodic()
     p = dict(p, x_recv=np.array([0.5, 1.5]))
     plan = wfp.Plan(p, p["dt"], local_mode=3, checkpoint_every=20)
     u = torch.empty((40, 2), dtype=torch.float64, device="cuda")
     plan.run(40, None, 1, u)
-    with pytest.raises(RuntimeError, match="local_mode 1"):
-        plan.gradient(u)
-    gb, gx = plan.gradient(u, positions=False)
+    gb, gx = plan.gradient(u)
     torch.cuda.synchronize()
-    assert gx is None and bool(torch.isfinite(gb).all()) and float(gb.abs().max()) > 0
+    assert bool(torch.isfinite(gb).all() and torch.isfinite(gx).all()) and float(gb.abs().max()) > 0
     plan.close()
     with pytest.raises(RuntimeError, match="local_mode 0, 1 or 2"):
         wfp.Batch([p], [p["dt"]], per_instance=[{"local_mode": 3}])
