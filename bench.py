@@ -402,16 +402,18 @@ def _adjoint_run(p, levels, every, positions=True, local_mode=0):
 
 def adjoint_leg(levels, every):
     """Forward + gradient pass on the adjoint workload (M = 1e5 springs, 64
-    receivers, dt = 1e-3): over `levels` levels with every level recorded
-    (blocks of `every`), and over at most 1000 levels with checkpoints every
-    `every` levels (the replayed form), and over `levels` levels with every
-    level recorded and the weights stored once per unordered pair, against a
-    plain forward march (no checkpoints, no recording) of the same levels."""
+    receivers, dt = 1e-3): with the weights stored per ordered pair over
+    `levels` levels with every level recorded (blocks of `every`) and over at
+    most 1000 levels with checkpoints every `every` levels (the replayed
+    form), and over `levels` levels recorded with the weights stored once per
+    unordered pair (the library's choice for this workload), against a plain
+    forward march (weights per ordered pair, no checkpoints, no recording) of
+    the same levels."""
     import torch
     from paper_2507_07823_amd import wfp, workloads
     p = workloads.adjoint_periodic()
     M, R = p["x"].size, p["x_recv"].size
-    plain = wfp.Plan(p, p["dt"])
+    plain = wfp.Plan(p, p["dt"], local_mode=1)
     u = torch.empty((levels, R), dtype=torch.float64, device="cuda")
     plain.run(10, None, 1, u[:10])
     plain.reset()
@@ -423,8 +425,8 @@ def adjoint_leg(levels, every):
     log(f"adjoint workload: plain forward {levels} levels {t_plain:.2f} s")
     plain.close()
     del u
-    rec = _adjoint_run(p, levels, -every)
-    ck = _adjoint_run(p, min(levels, 1000), every)
+    rec = _adjoint_run(p, levels, -every, local_mode=1)
+    ck = _adjoint_run(p, min(levels, 1000), every, local_mode=1)
     # the weights (and derivative weights) stored once per unordered pair
     po = _adjoint_run(p, levels, -every, local_mode=3)
     return {"workload": "periodic adjoint", "M": M, "R": R, "levels": levels,

@@ -108,9 +108,11 @@ typedef struct {
                               fly every level (memory O(M), arithmetic O(pairs N_L p)); 3: stored once
                               per unordered pair (Q_m depends on the distance alone) and applied to
                               both rows, about half the bytes of 1 (the gradient pass's
-                              derivative weights likewise), not in batches; 0: stored (1) when
-                              they fit in 60% of the free device memory, else 3 when half of
-                              that fits, else on the fly                     [0] */
+                              derivative weights likewise), not in batches; 0: 3 when half of
+                              the per-pair set-up fits in 60% of the free device memory and
+                              either the springs have 256 or more neighbours on average or the
+                              per-pair weights would not fit, else 1 when they fit, else on
+                              the fly                                         [0] */
   int32_t check_finite;    /* nonzero: every wfp_run ends by checking the newest density level and the
                               mode state alpha, alpha' for NaN or Inf (one small kernel), waits for the
                               plan's stream and returns WFP_ENONFINITE if any is found (the levels stay

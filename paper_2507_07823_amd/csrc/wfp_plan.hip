@@ -62,6 +62,11 @@ namespace {
 // wavefronts per row of the stored-weight local sum (rows of 16 lanes per
 // lag); 2 measured fastest of 1 to 4 at M = 1e4, 1e5 and 1e6
 constexpr int kLocalSplit = 2;
+// mean neighbours per spring from which local_mode 0 stores the weights once
+// per unordered pair even where the per-pair weights fit (measured on one
+// MI355X: 9 % slower at 138 neighbours, 3 % faster at 207, 18 % at 412, 29 %
+// at 1373)
+constexpr double kPairOnceNeighbours = 256.0;
 
 void zero_state(wfp_plan* P) {
   auto fill = [&](double* ptr, int64_t n) {
@@ -556,13 +561,19 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
   {
     int mode = par->local_mode;
     if (mode == 0) {
-      // per ordered pair when the dense set-up array and the packed weights
-      // fit; else once per unordered pair (about half of both); else on the fly
+      // once per unordered pair (about half the set-up array and packed
+      // weights) when that fits and either the springs have many neighbours
+      // (there the halved stream outweighs the prefix runs' idle lanes: it
+      // measured faster from about 200 neighbours per spring on) or the
+      // per-pair weights would not fit; else per ordered pair when they fit;
+      // else on the fly
       size_t fr = 0, to = 0;
       HIPCHK(hipMemGetInfo(&fr, &to));
       const double need = 8.0 * (double)tot * 1.7;
-      if (need < 0.6 * (double)fr) mode = 1;
-      else if (0.5 * need < 0.6 * (double)fr) mode = 3;
+      const bool fits1 = need < 0.6 * (double)fr, fits3 = 0.5 * need < 0.6 * (double)fr;
+      const bool dense = (double)P->n_pairs >= kPairOnceNeighbours * (double)M;
+      if (fits3 && (dense || !fits1)) mode = 3;
+      else if (fits1) mode = 1;
       else mode = 2;
     }
     P->otf = mode == 2 || mode == 3;
