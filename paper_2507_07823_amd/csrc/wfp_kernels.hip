@@ -1015,6 +1015,21 @@ WFP_OTFS_INST(10)
 WFP_OTFS_INST(12)
 #undef WFP_OTFS_INST
 
+// First lag m in [m0, NQ) whose run of sources reaches index i0 of the upper
+// range (c_m > i0), NQ if none.  The runs are prefixes whose length does not
+// decrease with the lag (a source carries the lags from its stencil's lowest
+// one up, and that grows with the distance), so the lags below it contribute
+// only zeros for sources i0 and beyond.
+__device__ __forceinline__ int first_lag_reaching(const uint2* __restrict__ cw, int m0, int NQ, int i0) {
+  int lo = m0, hi = NQ;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((int)cw[mid].x > i0) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 // Local sum of lags m >= mfirst (1, or 2 with the lag-1 part added by
 // k_local_sym_lag1) from stored weights, each unordered pair once.
 // One wavefront per row j walks its upper range [j, up_end[j]) (unwrapped:
@@ -1058,7 +1073,7 @@ k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __rest
     int l = j + i;
     if (l >= M) l -= M;
     double pc = 0.0;
-    for (int mb = mfirst; mb < NQ; mb += 8) {
+    for (int mb = first_lag_reaching(cw[wv], mfirst, NQ, i0); mb < NQ; mb += 8) {
       double w[8], h[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -1131,7 +1146,7 @@ k_local_sym_deriv2(int M, int NQ, int NH, const int* __restrict__ up_end, const 
     int l = j + i;
     if (l >= M) l -= M;
     double p1 = 0.0, p2 = 0.0;
-    for (int mb = 0; mb < NQ; mb += 8) {
+    for (int mb = first_lag_reaching(cw[wv], 0, NQ, i0); mb < NQ; mb += 8) {
       double w[8], g1[8], g2[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
