@@ -832,6 +832,8 @@ def main():
                     help="levels timed at M = 1e4 in the disordered leg (negative skips the leg)")
     ap.add_argument("--balanced-levels", type=int, default=500,
                     help="levels per size of the free-space scaling-study leg (0 skips it)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the adjoint leg (--adjoint-levels levels) and print its result")
     ap.add_argument("--balanced-only", action="store_true",
                     help="only run the scaling-study leg (for counter runs of its kernels) and print its result")
     ap.add_argument("--balanced-sizes", type=str, default="1000,10000,100000,1000000",
@@ -879,7 +881,7 @@ def main():
     # the CPU oracle baseline runs in a child process beside the GPU legs
     child = None
     if not (args.no_cpu_baseline or args.headline_only or args.balanced_only or args.disordered_full
-            or args.copy_calibration):
+            or args.copy_calibration or args.adjoint_only):
         child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
                                   "--cpu-levels", str(args.cpu_levels)], stdout=subprocess.PIPE, text=True)
     try:
@@ -912,6 +914,9 @@ def run_gpu_legs(args):
     if args.disordered_full:
         print(json.dumps(disordered_full(refines=[int(v) for v in args.disordered_refines.split(",")])),
               flush=True)
+        return None
+    if args.adjoint_only:
+        print(json.dumps(adjoint_leg(args.adjoint_levels, 250)), flush=True)
         return None
     h = headline(args.steps, args.warmup, args.profile_levels)
     out = {

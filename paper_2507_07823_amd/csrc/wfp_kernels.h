@@ -171,11 +171,11 @@ __global__ void k_solve_direct(int M, const int* __restrict__ dt_g0, const int* 
                                const double* __restrict__ grid2, int nf, int width,
                                double* __restrict__ sig_out, double* __restrict__ save_row,
                                const int* __restrict__ perm);
-__global__ void k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
+__global__ void k_receivers(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
                             const int* __restrict__ nb_count, const int64_t* __restrict__ qoff,
-                            const double* __restrict__ Q, const double* __restrict__ hist,
-                            const int* __restrict__ i0s, const double* __restrict__ iw,
-                            const double* __restrict__ grid2, int nf, int width, double* __restrict__ out);
+                            const double* __restrict__ Q, const double* __restrict__ hist, const int* __restrict__ i0s,
+                            const double* __restrict__ iw, const double* __restrict__ grid2, int nf, int width,
+                            double* __restrict__ out);
 
 // ---- history part as three kernels (four-step transform, n = n1 n2) ----
 __global__ void k_hist_a(FftPlan f2, int n1, const double* __restrict__ sig, int M,

@@ -1509,12 +1509,51 @@ __device__ __forceinline__ void k_receivers_body(int R, int M, int NQ, int NH, i
   if (lane == 0) out[r] = acc + interp_pre(r, i0s, iw, grid2, nf, width);
 }
 
-__global__ void __launch_bounds__(256)
-k_receivers(int R, int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start,
-            const int* __restrict__ nb_count, const int64_t* __restrict__ qoff, const double* __restrict__ Q,
-            const double* __restrict__ hist, const int* __restrict__ i0s, const double* __restrict__ iw,
-            const double* __restrict__ grid2, int nf, int width, double* __restrict__ out) {
-  k_receivers_body(R, M, NQ, NH, L, nb_start, nb_count, qoff, Q, hist, i0s, iw, grid2, nf, width, out, blockIdx.x);
+// The same with a workgroup of 16 wavefronts per receiver (receivers are few
+// and may have thousands of neighbours, so one wavefront each leaves most of
+// the chip idle and waits on one load at a time): wavefront w takes the lags
+// m = w, w + 16, ..., its lanes the sources, four loads in flight per lane;
+// the wavefronts' sums are added in a fixed order.
+__global__ void __launch_bounds__(1024)
+k_receivers(int M, int NQ, int NH, int64_t L, const int* __restrict__ nb_start, const int* __restrict__ nb_count,
+            const int64_t* __restrict__ qoff, const double* __restrict__ Q, const double* __restrict__ hist,
+            const int* __restrict__ i0s, const double* __restrict__ iw, const double* __restrict__ grid2, int nf,
+            int width, double* __restrict__ out) {
+  __shared__ double part[16];
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = nb_count[r], st = nb_start[r];
+  const int64_t base = qoff[r];
+  double acc = 0.0;
+  for (int m = wv; m < NQ; m += 16) {
+    const double* __restrict__ sl = hist + (int64_t)mod_slot(L - m, NH) * M;
+    const double* __restrict__ qm = Q + base + (int64_t)m * n;
+    for (int i0 = 0; i0 < n; i0 += 256) {
+      double q[4], h[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + lane + 64 * u;
+        q[u] = 0.0;
+        h[u] = 0.0;
+        if (i < n) {
+          int l = st + i;
+          if (l >= M) l -= M;
+          q[u] = qm[i];
+          h[u] = sl[l];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = fma(q[u], h[u], acc);
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) part[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < 16; ++w) sum += part[w];
+    out[r] = sum + interp_pre(r, i0s, iw, grid2, nf, width);
+  }
 }
 
 // Element k of the packed input of the u (or v) grid transform from the modes

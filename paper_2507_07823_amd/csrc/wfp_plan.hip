@@ -1539,9 +1539,9 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
   }
   if (P->R > 0 && u_recv_row) {
     StageTimer st(P, WFP_STAGE_RECV, s);
-    hipLaunchKernelGGL(k_receivers, dim3(nblk(P->R, kRowThreads / 64)), dim3(kRowThreads), 0, s, (int)P->R,
-                       (int)P->M, P->NQ, P->NH, L, P->rnb_start, P->rnb_count, P->rqoff, P->Qr, S.hist,
-                       P->ri0s, P->riw, P->grid2, P->nf, P->width, u_recv_row);
+    hipLaunchKernelGGL(k_receivers, dim3(P->R), dim3(1024), 0, s, (int)P->M, P->NQ, P->NH, L, P->rnb_start,
+                       P->rnb_count, P->rqoff, P->Qr, S.hist, P->ri0s, P->riw, P->grid2, P->nf, P->width,
+                       u_recv_row);
   }
   // the next level's chain overwrites grid2, read by the solve and receivers above
   if (overlap) HIPCHK(hipEventRecord(P->ev_solved, s));
