@@ -1184,22 +1184,56 @@ k_local_sym_deriv2(int M, int NQ, int NH, const int* __restrict__ up_end, const 
 // Row l's total of the pair-once stored local sum: its own sum plus the column
 // terms of the rows whose upper range covers it: rows cov[l].x .. l - 1 (up_end
 // is non-decreasing, so they are consecutive) and, in the periodic box, rows
-// cov[l].y .. M - 1 whose range wraps to l + M.  One wavefront per row, lanes
-// over the covering rows, added in a fixed order (lane sums, then a fixed
-// tree); scaled per row.
-__global__ void __launch_bounds__(256)
+// cov[l].y .. M - 1 whose range wraps to l + M; scaled per row.  A workgroup
+// takes 64 consecutive rows, one per lane, so that a covering row's terms for
+// them are consecutive in its block of colpart (one coalesced load per
+// covering row).  The union of the 64 rows' covering rows is cut into 16
+// consecutive parts, one per wavefront, each adding its part in order; the
+// partial sums are then added in a fixed order.
+constexpr int kReduceWaves = 16;
+__global__ void __launch_bounds__(64 * kReduceWaves)
 k_local_sym_reduce(int M, const int2* __restrict__ cov, const int64_t* __restrict__ upb,
                    const double* __restrict__ rowacc, const double* __restrict__ colpart,
                    const double* __restrict__ scale, double* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (l >= M) return;
-  const int2 c = cov[l];
+  __shared__ double part[kReduceWaves][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l0 = blockIdx.x * 64;
+  const int l = l0 + lane;
+  const bool act = l < M;
+  const int2 c = act ? cov[l] : make_int2(M, M);
+  // cov[l].x and cov[l].y do not decrease with l: the block's covering rows
+  // below are cov[l0].x .. lend - 2, its wrapping rows cov[l0].y .. M - 1
+  const int lend = min(l0 + 64, M);
+  const int2 c0 = cov[l0];
+  const int a0 = c0.x, n1 = max(lend - 1 - a0, 0);
+  const int b0 = c0.y, n2 = max(M - b0, 0);
+  const int ntot = n1 + n2;
+  const int q0 = (int)((int64_t)wv * ntot / kReduceWaves), q1 = (int)((int64_t)(wv + 1) * ntot / kReduceWaves);
   double acc = 0.0;
-  for (int jr = c.x + lane; jr < l; jr += 64) acc += colpart[upb[jr] + (l - jr)];
-  for (int jr = c.y + lane; jr < M; jr += 64) acc += colpart[upb[jr] + ((long long)l + M - jr)];
-  acc = wave_sum(acc);
-  if (lane == 0) out[l] = scale[l] * (rowacc[l] + acc);
+  for (int q = q0; q < q1; q += 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = q + u;
+      v[u] = 0.0;
+      if (t < q1) {
+        const bool wrap = t >= n1;
+        const int jr = wrap ? b0 + (t - n1) : a0 + t;
+        const bool ok = act && (wrap ? jr >= c.y : (jr >= c.x && jr < l));
+        if (ok) v[u] = colpart[upb[jr] + (wrap ? (int64_t)l + M - jr : (int64_t)(l - jr))];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += v[u];
+  }
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0 && act) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kReduceWaves; ++w) t += part[w][lane];
+    out[l] = scale[l] * (rowacc[l] + t);
+  }
 }
 
 // Lag 1 of the pair-once stored local sum, added to the lags >= 2 total

@@ -1270,7 +1270,7 @@ void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
     hipExtLaunchKernelGGL(k_local_sym_rows, dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
                           (int)P->M, P->NH, P->NQ, L, 1, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
                           P->sym_upb, P->otf_rowacc, P->sym_colpart);
-    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 4)), dim3(256), 0, s, nullptr, eb, 0, (int)P->M,
+    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 64)), dim3(1024), 0, s, nullptr, eb, 0, (int)P->M,
                           P->sym_cov, P->sym_upb, P->otf_rowacc, P->sym_colpart, scale, out);
     return;
   }
@@ -1362,7 +1362,7 @@ void launch_local_big(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
     hipExtLaunchKernelGGL(k_local_sym_rows, dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
                           (int)P->M, P->NH, P->NQ, L, 2, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
                           P->sym_upb, P->otf_rowacc, P->sym_colpart);
-    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 4)), dim3(256), 0, s, nullptr, eb, 0, (int)P->M,
+    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 64)), dim3(1024), 0, s, nullptr, eb, 0, (int)P->M,
                           P->sym_cov, P->sym_upb, P->otf_rowacc, P->sym_colpart, P->half_beta,
                           P->locb + (L & 1) * P->M);
     return;
@@ -1971,9 +1971,9 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
                              P->NH, P->otf_up_end, (const double*)segsig, (int64_t)(hd + L - a),
                              (const double*)P->ahist, Rv, P->symd_rb, P->symd_acx, P->symd_q, P->sym_upb,
                              P->symd_row1, P->symd_row2, P->symd_col1, P->symd_col2);
-          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 4)), dim3(256), 0, s, (int)M, P->sym_cov, P->sym_upb,
+          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 64)), dim3(1024), 0, s, (int)M, P->sym_cov, P->sym_upb,
                              P->symd_row1, P->symd_col1, P->symd_one, P->xloc2);
-          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 4)), dim3(256), 0, s, (int)M, P->sym_cov, P->sym_upb,
+          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 64)), dim3(1024), 0, s, (int)M, P->sym_cov, P->sym_upb,
                              P->symd_row2, P->symd_col2, P->symd_one, P->xloc);
         } else {
           const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
