@@ -110,7 +110,7 @@ typedef struct {
                               both rows, about half the bytes of 1 (the gradient pass's
                               derivative weights likewise), not in batches; 0: 3 when half of
                               the per-pair set-up fits in 60% of the free device memory and
-                              either the springs have 256 or more neighbours on average or the
+                              either the springs have 96 or more neighbours on average or the
                               per-pair weights would not fit, else 1 when they fit, else on
                               the fly                                         [0] */
   int32_t check_finite;    /* nonzero: every wfp_run ends by checking the newest density level and the

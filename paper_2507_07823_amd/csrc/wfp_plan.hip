@@ -64,9 +64,9 @@ namespace {
 constexpr int kLocalSplit = 2;
 // mean neighbours per spring from which local_mode 0 stores the weights once
 // per unordered pair even where the per-pair weights fit (measured on one
-// MI355X: 9 % slower at 138 neighbours, 3 % faster at 207, 18 % at 412, 29 %
-// at 1373)
-constexpr double kPairOnceNeighbours = 256.0;
+// MI355X with the library's schedule: 22 % slower at 69 neighbours, 3-4 %
+// faster at 101, 17 % at 138, 18 % at 207, 35 % at 1373)
+constexpr double kPairOnceNeighbours = 96.0;
 
 void zero_state(wfp_plan* P) {
   auto fill = [&](double* ptr, int64_t n) {
@@ -562,9 +562,9 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
     int mode = par->local_mode;
     if (mode == 0) {
       // once per unordered pair (about half the set-up array and packed
-      // weights) when that fits and either the springs have many neighbours
+      // weights) when that fits and either the springs have enough neighbours
       // (there the halved stream outweighs the prefix runs' idle lanes: it
-      // measured faster from about 200 neighbours per spring on) or the
+      // measured faster from about 100 neighbours per spring on) or the
       // per-pair weights would not fit; else per ordered pair when they fit;
       // else on the fly
       size_t fr = 0, to = 0;
@@ -1398,7 +1398,7 @@ const double* driving_row(wfp_plan* P, hipStream_t s, int64_t L) {
 
 void launch_local_lag1(wfp_plan* P, hipStream_t s, const double* hist, int64_t L) {
   if (P->sym_stored) {
-    hipLaunchKernelGGL(k_local_sym_lag1, dim3(nblk(P->M, 256)), dim3(256), 0, s, (int)P->M, P->NQ, P->NH, L,
+    hipLaunchKernelGGL(k_local_sym_lag1, dim3(nblk(P->M, 16)), dim3(256), 0, s, (int)P->M, P->NQ, P->NH, L,
                        P->boundary == WFP_PERIODIC ? 1 : 0, P->sym_kmax, P->sym_rb, P->sym_acx, P->sym_q, hist,
                        P->half_beta, P->locb + (L & 1) * P->M, P->loc);
     return;
