@@ -205,6 +205,7 @@ struct wfp_plan {
   // gradient pass with weights stored once per pair: the signed derivative
   // weights of each row's upper range (lags 0 .. NQ - 1, packed like sym_q),
   // the two sums' row and column terms, and a row scale of ones
+  int sym_spl = 1;               // sources per lane of the pair-once kernels (1 or 2)
   int64_t* symd_rb = nullptr;
   uint2* symd_acx = nullptr;
   double *symd_q = nullptr, *symd_row1 = nullptr, *symd_row2 = nullptr, *symd_col1 = nullptr,

@@ -65,11 +65,13 @@ __global__ void k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __r
                                 const double* __restrict__ na, const double* __restrict__ nw,
                                 const double* __restrict__ phitab, double* __restrict__ rowacc,
                                 double* __restrict__ part);
+template <int SPL>
 __global__ void k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __restrict__ up_end,
                                  const double* __restrict__ hist, const int64_t* __restrict__ rb,
                                  const uint2* __restrict__ sacx, const double* __restrict__ Qs,
                                  const int64_t* __restrict__ upb, double* __restrict__ rowacc,
                                  double* __restrict__ colpart);
+template <int SPL>
 __global__ void k_local_sym_deriv2(int M, int NQ, int NH, const int* __restrict__ up_end,
                                    const double* __restrict__ h1, int64_t r1, const double* __restrict__ h2,
                                    int64_t L2, const int64_t* __restrict__ rb, const uint2* __restrict__ sacx,

@@ -1033,15 +1033,17 @@ __device__ __forceinline__ int first_lag_reaching(const uint2* __restrict__ cw, 
 // Local sum of lags m >= mfirst (1, or 2 with the lag-1 part added by
 // k_local_sym_lag1) from stored weights, each unordered pair once.
 // One wavefront per row j walks its upper range [j, up_end[j]) (unwrapped:
-// periodic ranges continue past M - 1 at 0), each lane over two consecutive
-// sources, lags in groups of four with every load of a group issued before
-// its use.  Row j's
+// periodic ranges continue past M - 1 at 0), each lane over SPL consecutive
+// sources (2: one 16-byte load of each pair's weights and densities, for long
+// ranges; 1: every lane busy on short ones), lags in groups of 8 / SPL with
+// every load of a group issued before its use.  Row j's
 // weights are one run per lag m over the first c_jm sources of the range
 // (those whose stencils reach lag m: a prefix, as the distance grows along the
 // range), at Qs[rb[j] + o_jm + i], sacx[j NQ + m] = (c_jm, o_jm), unscaled.
 // The row's own sum sum_m sum_i Q sigma_l goes to rowacc[j]; each pair's
 // column term sum_m Q sigma_j^{L-m} (row l's share) to colpart[upb[j] + i]
 // (0 for the row itself); k_local_sym_reduce adds them up per row.
+template <int SPL>
 __global__ void __launch_bounds__(256)
 k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __restrict__ up_end,
                  const double* __restrict__ hist, const int64_t* __restrict__ rb, const uint2* __restrict__ sacx,
@@ -1067,57 +1069,90 @@ k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __rest
   const int n = up_end[j] - j;
   const double* __restrict__ qrow = Qs + rb[j];
   double* __restrict__ cp = colpart + upb[j];
-  double acc0 = 0.0, acc1 = 0.0;
-  for (int i0 = 0; i0 < n; i0 += 128) {
-    // sources i and i + 1 of the range, one 16-byte load of each pair's
-    // weights and densities (a weight one past a run is read and dropped:
-    // the packed array carries two spare elements; a density pair that would
-    // run past source M - 1 continues at source 0)
-    const int i = i0 + 2 * lane;
-    const bool in0 = i < n, in1 = i + 1 < n;
-    int l = j + i;
-    if (l >= M) l -= M;
-    const bool adj = l + 1 < M;
-    double pc0 = 0.0, pc1 = 0.0;
-    for (int mb = first_lag_reaching(cw[wv], mfirst, NQ, i0); mb < NQ; mb += 4) {
-      d2u w[4], h[4];
+  if constexpr (SPL == 1) {
+    double acc = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 64) {
+      const int i = i0 + lane;
+      const bool in = i < n;
+      int l = j + i;
+      if (l >= M) l -= M;
+      double pc = 0.0;
+      for (int mb = first_lag_reaching(cw[wv], mfirst, NQ, i0); mb < NQ; mb += 8) {
+        double w[8], h[8];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = mb + r;
-        const uint2 c = m < NQ ? cw[wv][m] : make_uint2(0u, 0u);
-        w[r] = d2u{0.0, 0.0};
-        h[r] = d2u{0.0, 0.0};
-        if (in0 && i < (int)c.x) {
-          const double* __restrict__ hp = hist + slot[m];
-          w[r] = *(const d2u*)(qrow + c.y + i);
-          if (adj) {
-            h[r] = *(const d2u*)(hp + l);
-          } else {
-            h[r].x = hp[l];
-            h[r].y = hp[0];
-          }
-          if (!(in1 && i + 1 < (int)c.x)) {
-            w[r].y = 0.0;
-            h[r].y = 0.0;
+        for (int r = 0; r < 8; ++r) {
+          const int m = mb + r;
+          const uint2 c = m < NQ ? cw[wv][m] : make_uint2(0u, 0u);
+          const bool on = in && i < (int)c.x;
+          w[r] = on ? qrow[c.y + i] : 0.0;
+          h[r] = on ? hist[slot[m] + l] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int m = mb + r;
+          if (m < NQ) {
+            acc = fma(w[r], h[r], acc);
+            pc = fma(w[r], rv[wv][m], pc);
           }
         }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = mb + r;
-        if (m < NQ) {
-          acc0 = fma(w[r].x, h[r].x, acc0);
-          acc1 = fma(w[r].y, h[r].y, acc1);
-          pc0 = fma(w[r].x, rv[wv][m], pc0);
-          pc1 = fma(w[r].y, rv[wv][m], pc1);
-        }
-      }
+      if (in) cp[i] = i == 0 ? 0.0 : pc;
     }
-    if (in0) cp[i] = i == 0 ? 0.0 : pc0;
-    if (in1) cp[i + 1] = pc1;
+    acc = wave_sum(acc);
+    if (lane == 0) rowacc[j] = acc;
+  } else {
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 128) {
+      // sources i and i + 1 of the range, one 16-byte load of each pair's
+      // weights and densities (a weight one past a run is read and dropped:
+      // the packed array carries two spare elements; a density pair that would
+      // run past source M - 1 continues at source 0)
+      const int i = i0 + 2 * lane;
+      const bool in0 = i < n, in1 = i + 1 < n;
+      int l = j + i;
+      if (l >= M) l -= M;
+      const bool adj = l + 1 < M;
+      double pc0 = 0.0, pc1 = 0.0;
+      for (int mb = first_lag_reaching(cw[wv], mfirst, NQ, i0); mb < NQ; mb += 4) {
+        d2u w[4], h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = mb + r;
+          const uint2 c = m < NQ ? cw[wv][m] : make_uint2(0u, 0u);
+          w[r] = d2u{0.0, 0.0};
+          h[r] = d2u{0.0, 0.0};
+          if (in0 && i < (int)c.x) {
+            const double* __restrict__ hp = hist + slot[m];
+            w[r] = *(const d2u*)(qrow + c.y + i);
+            if (adj) {
+              h[r] = *(const d2u*)(hp + l);
+            } else {
+              h[r].x = hp[l];
+              h[r].y = hp[0];
+            }
+            if (!(in1 && i + 1 < (int)c.x)) {
+              w[r].y = 0.0;
+              h[r].y = 0.0;
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = mb + r;
+          if (m < NQ) {
+            acc0 = fma(w[r].x, h[r].x, acc0);
+            acc1 = fma(w[r].y, h[r].y, acc1);
+            pc0 = fma(w[r].x, rv[wv][m], pc0);
+            pc1 = fma(w[r].y, rv[wv][m], pc1);
+          }
+        }
+      }
+      if (in0) cp[i] = i == 0 ? 0.0 : pc0;
+      if (in1) cp[i + 1] = pc1;
+    }
+    const double acc = wave_sum(acc0 + acc1);
+    if (lane == 0) rowacc[j] = acc;
   }
-  const double acc = wave_sum(acc0 + acc1);
-  if (lane == 0) rowacc[j] = acc;
 }
 
 // The gradient pass's two signed derivative local sums (lags 0 .. NQ - 1)
@@ -1127,9 +1162,10 @@ k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __rest
 // j's values.  Values for the first sum from a linear buffer (row r1 - m for
 // lag m: the forward densities of the segment and the NQ - 1 levels before
 // it), for the second from a ring (slot L2 - m mod NH: the adjoint state).
-// One wavefront per row, two sources per lane, as in k_local_sym_rows; each
+// One wavefront per row, SPL sources per lane, as in k_local_sym_rows; each
 // pair's column terms, negated, go to col1 / col2[upb[j] + i] (0 for the row
 // itself), and k_local_sym_reduce adds them up per row.
+template <int SPL>
 __global__ void __launch_bounds__(256)
 k_local_sym_deriv2(int M, int NQ, int NH, const int* __restrict__ up_end, const double* __restrict__ h1, int64_t r1,
                    const double* __restrict__ h2, int64_t L2, const int64_t* __restrict__ rb,
@@ -1161,74 +1197,128 @@ k_local_sym_deriv2(int M, int NQ, int NH, const int* __restrict__ up_end, const 
   const double* __restrict__ qrow = Qs + rb[j];
   double* __restrict__ cp1 = col1 + upb[j];
   double* __restrict__ cp2 = col2 + upb[j];
-  double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
-  for (int i0 = 0; i0 < n; i0 += 128) {
-    // sources i and i + 1, 16-byte loads as in k_local_sym_rows
-    const int i = i0 + 2 * lane;
-    const bool in0 = i < n, in1 = i + 1 < n;
-    int l = j + i;
-    if (l >= M) l -= M;
-    const bool adj = l + 1 < M;
-    double p1 = 0.0, p2 = 0.0, q1 = 0.0, q2 = 0.0;
-    for (int mb = first_lag_reaching(cw[wv], 0, NQ, i0); mb < NQ; mb += 4) {
-      d2u w[4], g1[4], g2[4];
+  if constexpr (SPL == 1) {
+    double a1 = 0.0, a2 = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 64) {
+      const int i = i0 + lane;
+      const bool in = i < n;
+      int l = j + i;
+      if (l >= M) l -= M;
+      double p1 = 0.0, p2 = 0.0;
+      for (int mb = first_lag_reaching(cw[wv], 0, NQ, i0); mb < NQ; mb += 8) {
+        double w[8], g1[8], g2[8];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = mb + r;
-        const uint2 c = m < NQ ? cw[wv][m] : make_uint2(0u, 0u);
-        w[r] = d2u{0.0, 0.0};
-        g1[r] = d2u{0.0, 0.0};
-        g2[r] = d2u{0.0, 0.0};
-        if (in0 && i < (int)c.x) {
-          const double* __restrict__ hp1 = h1 + s1[m];
-          const double* __restrict__ hp2 = h2 + s2[m];
-          w[r] = *(const d2u*)(qrow + c.y + i);
-          if (adj) {
-            g1[r] = *(const d2u*)(hp1 + l);
-            g2[r] = *(const d2u*)(hp2 + l);
-          } else {
-            g1[r].x = hp1[l];
-            g1[r].y = hp1[0];
-            g2[r].x = hp2[l];
-            g2[r].y = hp2[0];
-          }
-          if (!(in1 && i + 1 < (int)c.x)) {
-            w[r].y = 0.0;
-            g1[r].y = 0.0;
-            g2[r].y = 0.0;
+        for (int r = 0; r < 8; ++r) {
+          const int m = mb + r;
+          const uint2 c = m < NQ ? cw[wv][m] : make_uint2(0u, 0u);
+          const bool on = in && i < (int)c.x;
+          w[r] = on ? qrow[c.y + i] : 0.0;
+          g1[r] = on ? h1[s1[m] + l] : 0.0;
+          g2[r] = on ? h2[s2[m] + l] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int m = mb + r;
+          if (m < NQ) {
+            a1 = fma(w[r], g1[r], a1);
+            a2 = fma(w[r], g2[r], a2);
+            p1 = fma(w[r], rv1[wv][m], p1);
+            p2 = fma(w[r], rv2[wv][m], p2);
           }
         }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = mb + r;
-        if (m < NQ) {
-          a1 = fma(w[r].x, g1[r].x, a1);
-          b1 = fma(w[r].y, g1[r].y, b1);
-          a2 = fma(w[r].x, g2[r].x, a2);
-          b2 = fma(w[r].y, g2[r].y, b2);
-          p1 = fma(w[r].x, rv1[wv][m], p1);
-          q1 = fma(w[r].y, rv1[wv][m], q1);
-          p2 = fma(w[r].x, rv2[wv][m], p2);
-          q2 = fma(w[r].y, rv2[wv][m], q2);
-        }
+      if (in) {
+        cp1[i] = i == 0 ? 0.0 : -p1;
+        cp2[i] = i == 0 ? 0.0 : -p2;
       }
     }
-    if (in0) {
-      cp1[i] = i == 0 ? 0.0 : -p1;
-      cp2[i] = i == 0 ? 0.0 : -p2;
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if (lane == 0) {
+      row1[j] = a1;
+      row2[j] = a2;
     }
-    if (in1) {
-      cp1[i + 1] = -q1;
-      cp2[i + 1] = -q2;
+  } else {
+    double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 128) {
+      // sources i and i + 1, 16-byte loads as in k_local_sym_rows
+      const int i = i0 + 2 * lane;
+      const bool in0 = i < n, in1 = i + 1 < n;
+      int l = j + i;
+      if (l >= M) l -= M;
+      const bool adj = l + 1 < M;
+      double p1 = 0.0, p2 = 0.0, q1 = 0.0, q2 = 0.0;
+      for (int mb = first_lag_reaching(cw[wv], 0, NQ, i0); mb < NQ; mb += 4) {
+        d2u w[4], g1[4], g2[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = mb + r;
+          const uint2 c = m < NQ ? cw[wv][m] : make_uint2(0u, 0u);
+          w[r] = d2u{0.0, 0.0};
+          g1[r] = d2u{0.0, 0.0};
+          g2[r] = d2u{0.0, 0.0};
+          if (in0 && i < (int)c.x) {
+            const double* __restrict__ hp1 = h1 + s1[m];
+            const double* __restrict__ hp2 = h2 + s2[m];
+            w[r] = *(const d2u*)(qrow + c.y + i);
+            if (adj) {
+              g1[r] = *(const d2u*)(hp1 + l);
+              g2[r] = *(const d2u*)(hp2 + l);
+            } else {
+              g1[r].x = hp1[l];
+              g1[r].y = hp1[0];
+              g2[r].x = hp2[l];
+              g2[r].y = hp2[0];
+            }
+            if (!(in1 && i + 1 < (int)c.x)) {
+              w[r].y = 0.0;
+              g1[r].y = 0.0;
+              g2[r].y = 0.0;
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = mb + r;
+          if (m < NQ) {
+            a1 = fma(w[r].x, g1[r].x, a1);
+            b1 = fma(w[r].y, g1[r].y, b1);
+            a2 = fma(w[r].x, g2[r].x, a2);
+            b2 = fma(w[r].y, g2[r].y, b2);
+            p1 = fma(w[r].x, rv1[wv][m], p1);
+            q1 = fma(w[r].y, rv1[wv][m], q1);
+            p2 = fma(w[r].x, rv2[wv][m], p2);
+            q2 = fma(w[r].y, rv2[wv][m], q2);
+          }
+        }
+      }
+      if (in0) {
+        cp1[i] = i == 0 ? 0.0 : -p1;
+        cp2[i] = i == 0 ? 0.0 : -p2;
+      }
+      if (in1) {
+        cp1[i + 1] = -q1;
+        cp2[i + 1] = -q2;
+      }
     }
-  }
-  const double s1sum = wave_sum(a1 + b1), s2sum = wave_sum(a2 + b2);
-  if (lane == 0) {
-    row1[j] = s1sum;
-    row2[j] = s2sum;
+    const double s1sum = wave_sum(a1 + b1), s2sum = wave_sum(a2 + b2);
+    if (lane == 0) {
+      row1[j] = s1sum;
+      row2[j] = s2sum;
+    }
   }
 }
+
+template __global__ void k_local_sym_rows<1>(int, int, int, int64_t, int, const int*, const double*, const int64_t*,
+                                             const uint2*, const double*, const int64_t*, double*, double*);
+template __global__ void k_local_sym_rows<2>(int, int, int, int64_t, int, const int*, const double*, const int64_t*,
+                                             const uint2*, const double*, const int64_t*, double*, double*);
+template __global__ void k_local_sym_deriv2<1>(int, int, int, const int*, const double*, int64_t, const double*,
+                                               int64_t, const int64_t*, const uint2*, const double*,
+                                               const int64_t*, double*, double*, double*, double*);
+template __global__ void k_local_sym_deriv2<2>(int, int, int, const int*, const double*, int64_t, const double*,
+                                               int64_t, const int64_t*, const uint2*, const double*,
+                                               const int64_t*, double*, double*, double*, double*);
 
 // Row l's total of the pair-once stored local sum: its own sum plus the column
 // terms of the rows whose upper range covers it: rows cov[l].x .. l - 1 (up_end

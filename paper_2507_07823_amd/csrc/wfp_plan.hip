@@ -67,6 +67,9 @@ constexpr int kLocalSplit = 2;
 // MI355X with the library's schedule: 22 % slower at 69 neighbours, 3-4 %
 // faster at 101, 17 % at 138, 18 % at 207, 35 % at 1373)
 constexpr double kPairOnceNeighbours = 96.0;
+// mean upper-range length (sources per row, each pair once) from which the
+// pair-once kernels take two consecutive sources per lane
+constexpr int kSymPairedRange = 96;
 
 void zero_state(wfp_plan* P) {
   auto fill = [&](double* ptr, int64_t n) {
@@ -744,6 +747,10 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
         P->n_weights_stored = packed;
         P->sym_upb = upb_d;
         P->sym_colpart = P->alloc<double>(np_up);
+        // two sources per lane when the upper ranges are long enough to keep
+        // the lanes busy (measured: faster at 206 sources per range, slower at
+        // 69, where half the lanes would idle)
+        P->sym_spl = np_up >= (int64_t)kSymPairedRange * M ? 2 : 1;
         // rows covering row l: j < l with up[j] > l, and j > l with up[j] > l + M
         // (periodic); up is non-decreasing, so each is a run ending at l - 1 or M - 1
         std::vector<int2> cov(M);
@@ -1267,7 +1274,8 @@ void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
                         P->xs, hist, periodic, P->dt, P->delta, P->W, P->ngl, P->otf_na, P->otf_nw, P->phitab,  \
                         P->otf_rowacc, P->otf_part)
   if (P->sym_stored) {
-    hipExtLaunchKernelGGL(k_local_sym_rows, dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
+    hipExtLaunchKernelGGL(P->sym_spl == 2 ? k_local_sym_rows<2> : k_local_sym_rows<1>,
+                          dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
                           (int)P->M, P->NH, P->NQ, L, 1, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
                           P->sym_upb, P->otf_rowacc, P->sym_colpart);
     hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 64)), dim3(1024), 0, s, nullptr, eb, 0, (int)P->M,
@@ -1359,7 +1367,8 @@ double* locb_second(wfp_plan* P, int64_t L) {
 void launch_local_big(wfp_plan* P, hipStream_t s, const double* hist, int64_t L, hipEvent_t ea = nullptr,
                       hipEvent_t eb = nullptr) {
   if (P->sym_stored) {
-    hipExtLaunchKernelGGL(k_local_sym_rows, dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
+    hipExtLaunchKernelGGL(P->sym_spl == 2 ? k_local_sym_rows<2> : k_local_sym_rows<1>,
+                          dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
                           (int)P->M, P->NH, P->NQ, L, 2, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
                           P->sym_upb, P->otf_rowacc, P->sym_colpart);
     hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 64)), dim3(1024), 0, s, nullptr, eb, 0, (int)P->M,
@@ -1967,7 +1976,8 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
       if (wx) {
         deriv_field(P, adj);
         if (P->sym_stored) {
-          hipLaunchKernelGGL(k_local_sym_deriv2, dim3(8 * nblk(nblk(M, 4), 8)), dim3(256), 0, s, (int)M, P->NQ,
+          hipLaunchKernelGGL(P->sym_spl == 2 ? k_local_sym_deriv2<2> : k_local_sym_deriv2<1>,
+                             dim3(8 * nblk(nblk(M, 4), 8)), dim3(256), 0, s, (int)M, P->NQ,
                              P->NH, P->otf_up_end, (const double*)segsig, (int64_t)(hd + L - a),
                              (const double*)P->ahist, Rv, P->symd_rb, P->symd_acx, P->symd_q, P->sym_upb,
                              P->symd_row1, P->symd_row2, P->symd_col1, P->symd_col2);

@@ -129,6 +129,29 @@ def test_pair_once_dense_cluster_against_oracle(wfp):
     assert e < TOL
 
 
+def test_pair_once_dense_cluster_across_the_seam_against_oracle(wfp):
+    """300 springs within 0.005 of the periodic seam at dt = 1e-3: upper
+    ranges of about 150 sources (two sources per lane in the pair-once
+    kernels), which run past the last sorted spring to the first, so density
+    pairs straddle source M - 1 and source 0."""
+    rng = np.random.default_rng(31)
+    x = np.mod(np.pi + rng.uniform(-0.005, 0.005, 300) + np.pi, 2 * np.pi) - np.pi
+    beta = rng.uniform(0.05, 0.5, 300)
+    p = dict(x=x, beta=beta, packets=np.array([[1.0, np.pi - 0.2, 0.03, 0.0, 0.0]]), boundary=PERIODIC,
+             x_recv=np.zeros(0), dt=1e-3)
+    xs = np.sort(x)
+    gap = np.diff(np.concatenate([xs, xs[:1] + 2 * np.pi]))
+    assert np.max(gap) > np.pi                      # one cluster across the seam
+    n = 350
+    sig, _, info = _march(wfp, p, n, local_mode=3)
+    assert info["local_mode"] == 3
+    assert info["n_pairs"] / 2 / x.size > 96         # long upper ranges: two sources per lane
+    ref, _ = _oracle(p, n)
+    e = rho(sig, ref)
+    say(f"pair-once dense cluster across the seam vs oracle: rho = {e:.2e} (max |sigma| {np.max(np.abs(ref)):.2e})")
+    assert e < TOL and np.max(np.abs(ref)) > 1e-2
+
+
 def test_pair_once_gradient_and_batch_refusal(wfp):
     """With weights stored once per unordered pair the gradient pass gives
     both gradients (checked against the oracle in tests/test_gpu_adjoint.py);
