@@ -224,8 +224,9 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
 
 /* Gradient of a receiver loss J(u) through the march (not in the paper: the
  * transpose of every step of Section 4.2, run backwards in time).
- * Requires a periodic plan with R >= 1, stored local weights (local_mode 1 or
- * 3) and checkpoint_every != 0 whose levels 0 .. n_levels-1 were computed by
+ * Requires a periodic plan with R >= 1 (stored local weights, local_mode 1 or
+ * 3, for grad_x; weights on the fly give grad_beta alone) and
+ * checkpoint_every != 0 whose levels 0 .. n_levels-1 were computed by
  * wfp_run since plan creation or wfp_reset (no wfp_set_state in between); the
  * plan's own state is not changed.  The adjoint level applies the same local
  * sum as the forward one: Q_m depends on the distance alone, so the sum over
@@ -243,8 +244,8 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
  * or once per pair, as the weights are).  With recorded levels
  * (checkpoint_every < 0) the recorded blocks take the place of the replay.
  * Asynchronous on the plan's stream.
- * Errors: WFP_EINVAL, WFP_EDOMAIN (free space, weights on the fly), WFP_ESTATE,
- * WFP_ENOMEM, WFP_EHIP. */
+ * Errors: WFP_EINVAL, WFP_EDOMAIN (free space, grad_x with weights on the
+ * fly), WFP_ESTATE, WFP_ENOMEM, WFP_EHIP. */
 wfp_status wfp_adjoint(wfp_plan* plan, int64_t n_levels, const double* dJdu, double* grad_beta,
                        double* grad_x);
 

@@ -2267,8 +2267,9 @@ wfp_status wfp_adjoint(wfp_plan* P, int64_t n_levels, const double* dJdu, double
     g_last_error = "the gradient pass needs receivers (R >= 1)";
     return WFP_EINVAL;
   }
-  if (P->otf && !P->sym_stored) {
-    g_last_error = "the gradient pass needs stored local weights (local_mode 1 or 3)";
+  if (P->otf && !P->sym_stored && grad_x) {
+    // dJ/dx needs the derivative weights dQ_m/dd, which are stored
+    g_last_error = "dJ/dx needs stored local weights (local_mode 1 or 3); on the fly the pass gives dJ/dbeta alone";
     return WFP_EDOMAIN;
   }
   if (P->ckpt_every == 0 || !P->ck_from0 || P->level < n_levels) {

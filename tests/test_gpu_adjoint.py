@@ -129,6 +129,29 @@ def test_pair_once_gradient(wfp):
     assert gx5 is None and np.array_equal(gb5, gb3)
 
 
+def test_on_the_fly_beta_gradient(wfp):
+    """dJ/dbeta with the local weights evaluated on the fly (local_mode 2: the
+    adjoint level runs the same symmetric on-the-fly local sum on the adjoint
+    state): the ragged case against the oracle's reverse sweep and against
+    local_mode 1; recorded levels give the checkpointed bits; dJ/dx, which
+    needs the stored derivative weights, is refused."""
+    p = _case(8, 60, 4, 0.01, (0.0, 2.0), [1.0, -1.6, 0.1, 20.0, 0.3])
+    n = 237
+    say(f"adjoint on the fly: M=60 R=4 dt=0.01 levels={n} checkpoint_every=50, local_mode 2, dJ/dbeta")
+    dJdu, gb_o, _, u_o = _oracle_gradient(p, n, seed=51)
+    u2, gb2, gx2 = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=2)
+    assert gx2 is None
+    _, gb1, _ = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=1)
+    eu, eb, e21 = rho(u2, u_o), rho(gb2, gb_o), rho(gb2, gb1)
+    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  against local_mode 1: {e21:.2e}")
+    assert eu < TOL and eb < TOL and e21 < 1e-12
+    _, gb4, _ = _gpu_gradient(wfp, p, n, dJdu, -37, positions=False, local_mode=2)
+    assert np.array_equal(gb4, gb2)
+    with pytest.raises(wfp.WFPError) as ei:
+        _gpu_gradient(wfp, p, n, dJdu, 50, positions=True, local_mode=2)
+    assert ei.value.status == wfp.WFP_EDOMAIN
+
+
 def test_pair_once_gradient_across_the_seam(wfp):
     """Both gradients with the weights stored once per pair for 40 springs
     within 0.5 of the periodic seam at +-pi (upper ranges wrap past the last
