@@ -108,7 +108,7 @@ typedef struct {
                               fly every level (memory O(M), arithmetic O(pairs N_L p)); 3: stored once
                               per unordered pair (Q_m depends on the distance alone) and applied to
                               both rows, about half the bytes of 1 (the gradient pass's
-                              derivative weights likewise), not in batches; 0: 3 when half of
+                              derivative weights likewise); 0: 3 when half of
                               the per-pair set-up fits in 60% of the free device memory and
                               either the springs have 96 or more neighbours on average or the
                               per-pair weights would not fit, else 1 when they fit, else on
@@ -294,14 +294,16 @@ wfp_status wfp_plan_autotune(wfp_plan* plan, int32_t trial_levels, int32_t* over
  * marched on its own adds the lag-1 part of its local sum separately).
  *   wfp_batch_create  host problem data as for wfp_plan_create (probs[n],
  *                     pars[n]); builds one plan per instance (one stream each;
- *                     local weights stored or on the fly per pars[i].local_mode,
- *                     on the fly with p = 8 only; local_mode 0 here: stored for the
- *                     instances with the fewest neighbour pairs while their weights
- *                     fit in 45 % of the free device memory).  Synchronous.
- *                     Errors: WFP_EDOMAIN (free space, local_mode 3, or an
- *                     instance whose stages exceed the LDS), WFP_EINVAL
- *                     (checkpoint_every != 0: no gradient pass in batches), as
- *                     for plans.
+ *                     local weights stored per pair, stored once per pair or on
+ *                     the fly per pars[i].local_mode, on the fly with p = 8 only;
+ *                     local_mode 0 here: stored for the instances with the fewest
+ *                     neighbour pairs while their weights fit in 45 % of the free
+ *                     device memory, once per pair where the springs have 96 or
+ *                     more neighbours or only half fits, else on the fly).
+ *                     Synchronous.
+ *                     Errors: WFP_EDOMAIN (free space, or an instance whose
+ *                     stages exceed the LDS), WFP_EINVAL (checkpoint_every != 0:
+ *                     no gradient pass in batches), as for plans.
  *   wfp_batch_run     march n_steps levels of every instance; sigma_final is a
  *                     HOST array of n DEVICE pointers (entries may be NULL, the
  *                     array may be NULL): instance i's densities of its last

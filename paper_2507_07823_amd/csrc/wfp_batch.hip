@@ -21,8 +21,8 @@ struct wfp_batch {
   int2 *wl_inc = nullptr, *wl_loc4 = nullptr, *wl_loc8 = nullptr, *wl_a = nullptr, *wl_b = nullptr,
        *wl_c = nullptr, *wl_dir = nullptr, *wl_til = nullptr, *wl_rows = nullptr, *wl_otf = nullptr,
        *wl_swt = nullptr, *wl_sww = nullptr, *wl_g8 = nullptr, *wl_g4 = nullptr, *wl_rcv = nullptr,
-       *wl_otfr = nullptr, *wl_sp = nullptr;
-  int n_otfr = 0, n_sp = 0;
+       *wl_otfr = nullptr, *wl_sp = nullptr, *wl_sym = nullptr, *wl_symr = nullptr;
+  int n_otfr = 0, n_sp = 0, n_sym = 0, n_symr = 0;
   int n_inc = 0, n_loc4 = 0, n_loc8 = 0, n_a = 0, n_b = 0, n_c = 0, n_dir = 0, n_til = 0, n_rows = 0, n_otf = 0,
       n_swt = 0, n_sww = 0, n_g8 = 0, n_g4 = 0, n_rcv = 0;
   // receiver outputs of the current run: per instance a device pointer (or
@@ -162,6 +162,14 @@ InstDesc describe(const wfp_plan* P) {
   d.otf_nw = P->otf_nw;
   d.otf_part = P->otf_part;
   d.otf_rowacc = P->otf_rowacc;
+  d.sym = P->sym_stored ? 1 : 0;
+  d.sym_spl = P->sym_spl;
+  d.sym_rb = P->sym_rb;
+  d.sym_acx = P->sym_acx;
+  d.sym_q = P->sym_q;
+  d.sym_upb = P->sym_upb;
+  d.sym_colpart = P->sym_colpart;
+  d.sym_cov = P->sym_cov;
   d.R = (int)P->R;
   d.rnb_start = P->rnb_start;
   d.rnb_count = P->rnb_count;
@@ -212,7 +220,7 @@ void build_batch(wfp_batch* B) {
   std::vector<InstDesc> desc(n);
   // otf, loc4, loc8, g8, g4: (instance, blocks); g8 / g4: instances whose
   // lag blocks are short (the plan's lanes per lag), 4 rows per block
-  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf, otfr, g8, g4, rcv, sp;
+  std::vector<int2> inc, loc4, loc8, wa, wb, wc, dir, til, rows, otf, otfr, g8, g4, rcv, sp, sym, symr;
   for (int i = 0; i < n; ++i) {
     // the spread grid of the separate spread pass
     if (!B->plans[i]->gsp) B->plans[i]->gsp = B->plans[i]->alloc<double>(B->plans[i]->nf);
@@ -222,7 +230,10 @@ void build_batch(wfp_batch* B) {
     const int M = (int)P->M;
     const int rpb = 256 / desc[i].pp;
     for (int b = 0; b < (int)nblk(M, rpb); ++b) inc.push_back(make_int2(i, b));
-    if (P->otf) {
+    if (P->sym_stored) {
+      sym.push_back(make_int2(i, (int)nblk(M, 4)));
+      for (int bb = 0; bb < (int)nblk(M, 64); ++bb) symr.push_back(make_int2(i, bb));
+    } else if (P->otf) {
       if (P->p != 8) fail(WFP_EDOMAIN, "batched on-the-fly local sums take p = 8");
       otf.push_back(make_int2(i, (int)nblk(M, kOtfRows)));
       for (int bb = 0; bb < (int)nblk(M, 256); ++bb) otfr.push_back(make_int2(i, bb));
@@ -285,6 +296,8 @@ void build_batch(wfp_batch* B) {
   B->wl_rows = upload_work(B, rows, 1, B->n_rows);
   B->wl_otf = upload_work(B, xcd_balanced(otf), 8, B->n_otf);
   B->wl_otfr = upload_work(B, otfr, 1, B->n_otfr);
+  B->wl_sym = upload_work(B, xcd_balanced(sym), 8, B->n_sym);
+  B->wl_symr = upload_work(B, symr, 1, B->n_symr);
   B->wl_g8 = upload_work(B, xcd_balanced(g8), 8, B->n_g8);
   B->wl_g4 = upload_work(B, xcd_balanced(g4), 8, B->n_g4);
   B->wl_rcv = upload_work(B, rcv, 1, B->n_rcv);
@@ -350,6 +363,12 @@ void enqueue_level(wfp_batch* B) {
     hipLaunchKernelGGL(kb_local_otf, dim3(B->n_otf), dim3(64 * kOtfRows), B->lds_otf, s, bl);
     bl.work = B->wl_otfr;
     hipLaunchKernelGGL(kb_local_otf_reduce, dim3(B->n_otfr), dim3(256), 0, s, bl);
+  }
+  if (B->n_sym) {
+    bl.work = B->wl_sym;
+    hipLaunchKernelGGL(kb_local_sym, dim3(B->n_sym), dim3(256), 0, s, bl);
+    bl.work = B->wl_symr;
+    hipLaunchKernelGGL(kb_local_sym_reduce, dim3(B->n_symr), dim3(64 * kReduceWaves), 0, s, bl);
   }
   HIPCHK(hipStreamWaitEvent(s, B->ev_join, 0));
   if (B->n_dir) {
@@ -468,6 +487,7 @@ std::vector<int> choose_local_modes(int n, const wfp_problem* probs, const wfp_p
   std::vector<int> mode(n);
   std::vector<std::pair<double, int>> cand;
   std::vector<double> packed(n), dense(n);
+  std::vector<char> many(n, 0);
   for (int i = 0; i < n; ++i) {
     mode[i] = pars[i].local_mode;
     if (mode[i] != 0) continue;
@@ -478,13 +498,21 @@ std::vector<int> choose_local_modes(int n, const wfp_problem* probs, const wfp_p
     const double pairs = (double)count_pairs(probs[i].x, probs[i].M, W * pars[i].dt);
     packed[i] = 8.0 * pairs * (W / 2 + p);        // nonzero lags per pair
     dense[i] = 8.0 * pairs * (W + p / 2);
+    many[i] = pairs >= kPairOnceNeighbours * (double)probs[i].M ? 1 : 0;
     cand.push_back({packed[i], i});
   }
   std::sort(cand.begin(), cand.end());
   double used = 0.0;
   for (auto& c : cand) {
     const int i = c.second;
-    if (used + packed[i] <= 0.45 * (double)fr && dense[i] <= 0.25 * (double)fr) {
+    // as for a plan: once per unordered pair (half the bytes) for springs
+    // with many neighbours or where per-pair weights would not fit
+    const bool fits1 = used + packed[i] <= 0.45 * (double)fr && dense[i] <= 0.25 * (double)fr;
+    const bool fits3 = used + 0.5 * packed[i] <= 0.45 * (double)fr && 0.5 * dense[i] <= 0.25 * (double)fr;
+    if (fits3 && (many[i] || !fits1)) {
+      mode[i] = 3;
+      used += 0.5 * packed[i];
+    } else if (fits1) {
       mode[i] = 1;
       used += packed[i];
     } else {
@@ -508,10 +536,6 @@ wfp_status wfp_batch_create(int32_t n, const wfp_problem* probs, const wfp_param
   for (int32_t i = 0; i < n; ++i) {
     if (probs[i].boundary != WFP_PERIODIC) {
       g_last_error = "the batched form covers periodic problems";
-      return WFP_EDOMAIN;
-    }
-    if (pars[i].local_mode == 3) {
-      g_last_error = "the batched form takes local_mode 0, 1 or 2";
       return WFP_EDOMAIN;
     }
     if (pars[i].checkpoint_every != 0) {

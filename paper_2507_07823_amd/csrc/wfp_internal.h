@@ -25,6 +25,13 @@ using namespace wfp;
 
 extern thread_local std::string g_last_error;
 
+// mean neighbours per spring from which local_mode 0 (plans and batch
+// instances) stores the weights once per unordered pair even where the
+// per-pair weights fit (measured on one MI355X with the library's schedule:
+// 22 % slower at 69 neighbours, 3-4 % faster at 101, 17 % at 138, 18 % at 207,
+// 35 % at 1373)
+constexpr double kPairOnceNeighbours = 96.0;
+
 struct Error {
   wfp_status code;
   std::string msg;

@@ -56,6 +56,8 @@ __global__ void k_local_weights(int nrows, const double* __restrict__ xt,
 
 constexpr int kPhiPieces = 512, kPhiDeg = 5;
 constexpr int kOtfRows = 16, kOtfChunk = 256;
+// wavefronts of a pair-once reduce workgroup (64 rows, one per lane)
+constexpr int kReduceWaves = 16;
 constexpr int kMaxOtfLags = 48;      // lags 1 .. NQ - 1 of a row staged by the symmetric local sum
 template <int P>
 __global__ void k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end,
@@ -306,6 +308,14 @@ struct InstDesc {
   int otf_nblk;
   const double *otf_na, *otf_nw;
   double *otf_part, *otf_rowacc;
+  // weights stored once per unordered pair (otf_up_end, otf_rowacc shared)
+  int sym, sym_spl;
+  const int64_t* sym_rb;
+  const uint2* sym_acx;
+  const double* sym_q;
+  const int64_t* sym_upb;
+  double* sym_colpart;
+  const int2* sym_cov;
   // receivers
   int R;
   const int *rnb_start, *rnb_count, *ri0s;
@@ -327,6 +337,8 @@ __global__ void kb_local_g8(BatchLaunch b);
 __global__ void kb_local_g4(BatchLaunch b);
 __global__ void kb_local_otf(BatchLaunch b);
 __global__ void kb_local_otf_reduce(BatchLaunch b);
+__global__ void kb_local_sym(BatchLaunch b);
+__global__ void kb_local_sym_reduce(BatchLaunch b);
 __global__ void kb_spread_grid(BatchLaunch b);
 __global__ void kb_hist_a(BatchLaunch b, int from_grid);
 __global__ void kb_hist_b(BatchLaunch b);

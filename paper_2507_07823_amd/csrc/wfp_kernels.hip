@@ -1044,22 +1044,22 @@ __device__ __forceinline__ int first_lag_reaching(const uint2* __restrict__ cw, 
 // column term sum_m Q sigma_j^{L-m} (row l's share) to colpart[upb[j] + i]
 // (0 for the row itself); k_local_sym_reduce adds them up per row.
 template <int SPL>
-__global__ void __launch_bounds__(256)
-k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __restrict__ up_end,
-                 const double* __restrict__ hist, const int64_t* __restrict__ rb, const uint2* __restrict__ sacx,
-                 const double* __restrict__ Qs, const int64_t* __restrict__ upb, double* __restrict__ rowacc,
-                 double* __restrict__ colpart) {
+__device__ __forceinline__ void k_local_sym_rows_body(int M, int NH, int NQ, int64_t L, int mfirst,
+                                                      const int* __restrict__ up_end, const double* __restrict__ hist,
+                                                      const int64_t* __restrict__ rb, const uint2* __restrict__ sacx,
+                                                      const double* __restrict__ Qs, const int64_t* __restrict__ upb,
+                                                      double* __restrict__ rowacc, double* __restrict__ colpart,
+                                                      int b) {
   __shared__ double rv[4][kMaxOtfLags + 1];                   // each row's own history, lags 0 .. NQ - 1
   __shared__ uint2 cw[4][kMaxOtfLags + 1];
   __shared__ int64_t slot[kMaxOtfLags + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nb = gridDim.x;
-  const int j = xcd_block(blockIdx.x, nb) * 4 + wv;
+  const int j = b * 4 + wv;
   for (int m = threadIdx.x; m < NQ; m += blockDim.x) slot[m] = (int64_t)mod_slot(L - m, NH) * M;
   __syncthreads();
   for (int e = threadIdx.x; e < 4 * NQ; e += blockDim.x) {
     const int w = e / NQ, m = e - w * NQ;
-    const int jr = xcd_block(blockIdx.x, nb) * 4 + w;
+    const int jr = b * 4 + w;
     const bool ok = m >= 1 && jr < M;
     rv[w][m] = ok ? hist[slot[m] + jr] : 0.0;
     cw[w][m] = ok ? sacx[(int64_t)jr * NQ + m] : make_uint2(0u, 0u);
@@ -1153,6 +1153,16 @@ k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __rest
     const double acc = wave_sum(acc0 + acc1);
     if (lane == 0) rowacc[j] = acc;
   }
+}
+
+template <int SPL>
+__global__ void __launch_bounds__(256)
+k_local_sym_rows(int M, int NH, int NQ, int64_t L, int mfirst, const int* __restrict__ up_end,
+                 const double* __restrict__ hist, const int64_t* __restrict__ rb, const uint2* __restrict__ sacx,
+                 const double* __restrict__ Qs, const int64_t* __restrict__ upb, double* __restrict__ rowacc,
+                 double* __restrict__ colpart) {
+  k_local_sym_rows_body<SPL>(M, NH, NQ, L, mfirst, up_end, hist, rb, sacx, Qs, upb, rowacc, colpart,
+                             xcd_block(blockIdx.x, gridDim.x));
 }
 
 // The gradient pass's two signed derivative local sums (lags 0 .. NQ - 1)
@@ -1329,14 +1339,15 @@ template __global__ void k_local_sym_deriv2<2>(int, int, int, const int*, const 
 // covering row).  The union of the 64 rows' covering rows is cut into 16
 // consecutive parts, one per wavefront, each adding its part in order; the
 // partial sums are then added in a fixed order.
-constexpr int kReduceWaves = 16;
-__global__ void __launch_bounds__(64 * kReduceWaves)
-k_local_sym_reduce(int M, const int2* __restrict__ cov, const int64_t* __restrict__ upb,
-                   const double* __restrict__ rowacc, const double* __restrict__ colpart,
-                   const double* __restrict__ scale, double* __restrict__ out) {
+__device__ __forceinline__ void k_local_sym_reduce_body(int M, const int2* __restrict__ cov,
+                                                        const int64_t* __restrict__ upb,
+                                                        const double* __restrict__ rowacc,
+                                                        const double* __restrict__ colpart,
+                                                        const double* __restrict__ scale, double* __restrict__ out,
+                                                        int bid) {
   __shared__ double part[kReduceWaves][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int l0 = blockIdx.x * 64;
+  const int l0 = bid * 64;
   const int l = l0 + lane;
   const bool act = l < M;
   const int2 c = act ? cov[l] : make_int2(M, M);
@@ -1373,6 +1384,13 @@ k_local_sym_reduce(int M, const int2* __restrict__ cov, const int64_t* __restric
     for (int w = 0; w < kReduceWaves; ++w) t += part[w][lane];
     out[l] = scale[l] * (rowacc[l] + t);
   }
+}
+
+__global__ void __launch_bounds__(64 * kReduceWaves)
+k_local_sym_reduce(int M, const int2* __restrict__ cov, const int64_t* __restrict__ upb,
+                   const double* __restrict__ rowacc, const double* __restrict__ colpart,
+                   const double* __restrict__ scale, double* __restrict__ out) {
+  k_local_sym_reduce_body(M, cov, upb, rowacc, colpart, scale, out, blockIdx.x);
 }
 
 // Lag 1 of the pair-once stored local sum, added to the lags >= 2 total
@@ -2350,6 +2368,31 @@ __global__ void __launch_bounds__(256) kb_local_otf_reduce(BatchLaunch b) {
   if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
   k_local_otf_reduce_body(d.M, d.otf_nblk, 1, d.otf_blk_end, d.otf_part_off, d.otf_rowacc, d.otf_part, d.half_beta,
                           d.loc, w.y);
+}
+
+// Weights stored once per unordered pair (lags >= 1 in one pass, as in a
+// plan's on-the-fly schedule): the rows over (instance, block of 4 rows)
+// items, then the per-row totals over (instance, 64 rows) items, scaled by
+// beta_j / 2 into the instance's local sum.
+__global__ void __launch_bounds__(256) kb_local_sym(BatchLaunch b) {
+  const int2 w = b.work[xcd_block(blockIdx.x, gridDim.x)];
+  if (w.x < 0) return;   // block-uniform
+  const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;   // the instance has marched its own levels (block-uniform)
+  if (d.sym_spl == 2)
+    k_local_sym_rows_body<2>(d.M, d.NH, d.NQ, *b.level, 1, d.otf_up_end, d.hist, d.sym_rb, d.sym_acx, d.sym_q,
+                             d.sym_upb, d.otf_rowacc, d.sym_colpart, w.y);
+  else
+    k_local_sym_rows_body<1>(d.M, d.NH, d.NQ, *b.level, 1, d.otf_up_end, d.hist, d.sym_rb, d.sym_acx, d.sym_q,
+                             d.sym_upb, d.otf_rowacc, d.sym_colpart, w.y);
+}
+
+__global__ void __launch_bounds__(64 * kReduceWaves) kb_local_sym_reduce(BatchLaunch b) {
+  const int2 w = b.work[blockIdx.x];
+  if (w.x < 0) return;
+  const InstDesc& d = b.desc[w.x];
+  if (*b.level >= d.end) return;
+  k_local_sym_reduce_body(d.M, d.sym_cov, d.sym_upb, d.otf_rowacc, d.sym_colpart, d.half_beta, d.loc, w.y);
 }
 
 // Type-1 spreading as its own pass: a work item is 256 consecutive cells of

@@ -62,11 +62,6 @@ namespace {
 // wavefronts per row of the stored-weight local sum (rows of 16 lanes per
 // lag); 2 measured fastest of 1 to 4 at M = 1e4, 1e5 and 1e6
 constexpr int kLocalSplit = 2;
-// mean neighbours per spring from which local_mode 0 stores the weights once
-// per unordered pair even where the per-pair weights fit (measured on one
-// MI355X with the library's schedule: 22 % slower at 69 neighbours, 3-4 %
-// faster at 101, 17 % at 138, 18 % at 207, 35 % at 1373)
-constexpr double kPairOnceNeighbours = 96.0;
 // mean upper-range length (sources per row, each pair once) from which the
 // pair-once kernels take two consecutive sources per lane
 constexpr int kSymPairedRange = 96;
@@ -1278,7 +1273,7 @@ void launch_local_otf(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
                           dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
                           (int)P->M, P->NH, P->NQ, L, 1, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
                           P->sym_upb, P->otf_rowacc, P->sym_colpart);
-    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 64)), dim3(1024), 0, s, nullptr, eb, 0, (int)P->M,
+    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 64)), dim3(64 * kReduceWaves), 0, s, nullptr, eb, 0, (int)P->M,
                           P->sym_cov, P->sym_upb, P->otf_rowacc, P->sym_colpart, scale, out);
     return;
   }
@@ -1371,7 +1366,7 @@ void launch_local_big(wfp_plan* P, hipStream_t s, const double* hist, int64_t L,
                           dim3(8 * nblk(nblk(P->M, 4), 8)), dim3(256), 0, s, ea, nullptr, 0,
                           (int)P->M, P->NH, P->NQ, L, 2, P->otf_up_end, hist, P->sym_rb, P->sym_acx, P->sym_q,
                           P->sym_upb, P->otf_rowacc, P->sym_colpart);
-    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 64)), dim3(1024), 0, s, nullptr, eb, 0, (int)P->M,
+    hipExtLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(P->M, 64)), dim3(64 * kReduceWaves), 0, s, nullptr, eb, 0, (int)P->M,
                           P->sym_cov, P->sym_upb, P->otf_rowacc, P->sym_colpart, P->half_beta,
                           P->locb + (L & 1) * P->M);
     return;
@@ -1981,9 +1976,9 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
                              P->NH, P->otf_up_end, (const double*)segsig, (int64_t)(hd + L - a),
                              (const double*)P->ahist, Rv, P->symd_rb, P->symd_acx, P->symd_q, P->sym_upb,
                              P->symd_row1, P->symd_row2, P->symd_col1, P->symd_col2);
-          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 64)), dim3(1024), 0, s, (int)M, P->sym_cov, P->sym_upb,
+          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 64)), dim3(64 * kReduceWaves), 0, s, (int)M, P->sym_cov, P->sym_upb,
                              P->symd_row1, P->symd_col1, P->symd_one, P->xloc2);
-          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 64)), dim3(1024), 0, s, (int)M, P->sym_cov, P->sym_upb,
+          hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 64)), dim3(64 * kReduceWaves), 0, s, (int)M, P->sym_cov, P->sym_upb,
                              P->symd_row2, P->symd_col2, P->symd_one, P->xloc);
         } else {
           const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);

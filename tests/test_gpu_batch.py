@@ -147,13 +147,14 @@ def test_autotune_and_reset_keep_results(wfp):
     b.close()
 
 
-def test_batch_with_on_the_fly_instances(wfp):
+@pytest.mark.parametrize("modes", [[2, 1, 2, 1, 2, 1], [3, 1, 3, 2, 3, 1]])
+def test_batch_with_mixed_local_modes(wfp, modes):
     """Instances whose local weights are evaluated on the fly (local_mode 2)
-    next to stored ones: each matches its own plan with the same mode."""
+    or stored once per unordered pair (local_mode 3) next to ones stored per
+    ordered pair: each matches its own plan with the same mode."""
     import torch
     insts = _instances()
     n = 90
-    modes = [2, 1, 2, 1, 2, 1]
     b = wfp.Batch(insts, [p["dt"] for p in insts], per_instance=[{"local_mode": m} for m in modes])
     fin = _batch_run(b, insts, n)
     worst = 0.0

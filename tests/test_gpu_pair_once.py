@@ -152,10 +152,9 @@ def test_pair_once_dense_cluster_across_the_seam_against_oracle(wfp):
     assert e < TOL and np.max(np.abs(ref)) > 1e-2
 
 
-def test_pair_once_gradient_and_batch_refusal(wfp):
+def test_pair_once_gradient(wfp):
     """With weights stored once per unordered pair the gradient pass gives
-    both gradients (checked against the oracle in tests/test_gpu_adjoint.py);
-    the batched form refuses the mode."""
+    both gradients (checked against the oracle in tests/test_gpu_adjoint.py)."""
     import torch
     p = workloads.small_periodic()
     p = dict(p, x_recv=np.array([0.5, 1.5]))
@@ -166,8 +165,6 @@ def test_pair_once_gradient_and_batch_refusal(wfp):
     torch.cuda.synchronize()
     assert bool(torch.isfinite(gb).all() and torch.isfinite(gx).all()) and float(gb.abs().max()) > 0
     plan.close()
-    with pytest.raises(RuntimeError, match="local_mode 0, 1 or 2"):
-        wfp.Batch([p], [p["dt"]], per_instance=[{"local_mode": 3}])
 
 
 @pytest.mark.parametrize("p", [2, 4, 6, 10, 12])

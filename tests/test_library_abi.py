@@ -93,14 +93,9 @@ def test_batch_rejects_free_space_before_any_device_work(lib):
     assert lib.wfp_batch_create(1, probs, pars, None, ctypes.byref(h)) == w.WFP_EDOMAIN
     assert lib.wfp_batch_create(0, probs, pars, None, ctypes.byref(h)) == w.WFP_EINVAL
     assert h.value is None
-    # stored weights once per unordered pair are not taken by the batched form
+    # checkpoints and recorded levels are refused (no gradient pass in batches)
     w._fill_problem(probs[0], dict(x=np.array([0.1]), beta=np.array([1.0]), packets=np.array([[1, 0, 0.1, 0, 0]]),
                                    boundary=w.PERIODIC), keep)
-    pars[0] = w.make_params(0.01, local_mode=3)
-    assert lib.wfp_batch_create(1, probs, pars, None, ctypes.byref(h)) == w.WFP_EDOMAIN
-    assert b"local_mode" in lib.wfp_last_error()
-    assert h.value is None
-    # nor checkpoints or recorded levels (no gradient pass in batches)
     for every in (10, -10):
         pars[0] = w.make_params(0.01, checkpoint_every=every)
         assert lib.wfp_batch_create(1, probs, pars, None, ctypes.byref(h)) == w.WFP_EINVAL
