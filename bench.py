@@ -694,6 +694,19 @@ def disordered_full(M=10_000, chunk=50_000, refines=(1, 2)):
     return out
 
 
+def lds_ceiling():
+    """LDS read bytes per second of this GPU from the committed probe program
+    (built beside the library), or None if it is missing or fails."""
+    probe = os.path.join(ROOT, "paper_2507_07823_amd", "lds_probe")
+    if not os.path.exists(probe):
+        return None
+    try:
+        r = subprocess.run([probe], capture_output=True, text=True, timeout=60)
+        return float(json.loads(r.stdout.strip().splitlines()[-1])["lds_read_bytes_per_s"])
+    except (subprocess.SubprocessError, ValueError, IndexError, KeyError, OSError):
+        return None
+
+
 def headline(steps, warmup, profile_levels):
     """The clumped free-space workload at full size (M = 1e6): set-up, `warmup`
     untimed levels, `steps` timed levels, then a profiled pass of
@@ -733,10 +746,15 @@ def headline(steps, warmup, profile_levels):
                     "flops_per_launch": flops, "flop_count": "ordered neighbour pairs x 1.6 kflop",
                     "timed_with": "HIP events on the plan's stream"}
         # the operands each lane reads from LDS per (unordered pair, node): the
-        # source and row stencils (p values each) and the window piece
+        # source and row stencils (p values each) and the window piece,
+        # against this GPU's LDS read throughput measured by the probe
         lds = info["n_pairs"] / 2 * info["n_gl_local"] * (2 * info["p"] + 6) * 8.0
         roofline["lds_operand_bytes_per_launch"] = lds
         roofline["lds_operand_GBps"] = lds / (avg * 1e-3) / 1e9
+        ceiling = lds_ceiling()
+        if ceiling:
+            roofline["lds_ceiling_GBps"] = ceiling / 1e9
+            roofline["lds_frac"] = roofline["lds_operand_GBps"] / roofline["lds_ceiling_GBps"]
         log(f"stages: {json.dumps(stages)}")
     parity = clumped_parity(plan, p)
     log(f"parity vs oracle: {parity}")

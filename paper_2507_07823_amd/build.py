@@ -20,13 +20,29 @@ FLAGS = [
 ]
 
 
+PROBE = os.path.join(HERE, "lds_probe")
+
+
 def build_library(verbose=True):
     cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose=True):
+    """The LDS read-throughput probe that bench.py runs beside the on-the-fly
+    local sum's roofline (a separate program: the library has no use for it)."""
+    flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    cmd = [HIPCC] + flags + [os.path.join(CSRC, "lds_probe.hip"), "-o", PROBE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(PROBE + ".tmp", PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":
