@@ -405,8 +405,9 @@ def adjoint_leg(levels, every):
     receivers, dt = 1e-3): with the weights stored per ordered pair over
     `levels` levels with every level recorded (blocks of `every`) and over at
     most 1000 levels with checkpoints every `every` levels (the replayed
-    form), and over `levels` levels recorded with the weights stored once per
-    unordered pair (the library's choice for this workload), against a plain
+    form), over `levels` levels recorded with the weights stored once per
+    unordered pair (the library's choice for this workload), and over at most
+    1000 levels recorded with the weights evaluated on the fly, against a plain
     forward march (weights per ordered pair, no checkpoints, no recording) of
     the same levels."""
     import torch
@@ -429,10 +430,12 @@ def adjoint_leg(levels, every):
     ck = _adjoint_run(p, min(levels, 1000), every, local_mode=1)
     # the weights (and derivative weights) stored once per unordered pair
     po = _adjoint_run(p, levels, -every, local_mode=3)
+    # nothing stored: weights and derivative weights evaluated on the fly
+    of = _adjoint_run(p, min(levels, 1000), -every, local_mode=2)
     return {"workload": "periodic adjoint", "M": M, "R": R, "levels": levels,
             "beta": [round(float(p["beta"].min()), 4), round(float(p["beta"].max()), 4)],
             "plain_forward_s": t_plain, "plain_scatterer_steps_per_s": M * levels / t_plain,
-            "recorded": rec, "checkpointed": ck, "pair_once_recorded": po,
+            "recorded": rec, "checkpointed": ck, "pair_once_recorded": po, "on_the_fly_recorded": of,
             "forward_plus_gradient_over_plain_time": (rec["forward_s"] + rec["gradient_s"]) / t_plain}
 
 

@@ -224,8 +224,7 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
 
 /* Gradient of a receiver loss J(u) through the march (not in the paper: the
  * transpose of every step of Section 4.2, run backwards in time).
- * Requires a periodic plan with R >= 1 (stored local weights, local_mode 1 or
- * 3, for grad_x; weights on the fly give grad_beta alone) and
+ * Requires a periodic plan with R >= 1 (any local_mode) and
  * checkpoint_every != 0 whose levels 0 .. n_levels-1 were computed by
  * wfp_run since plan creation or wfp_reset (no wfp_set_state in between); the
  * plan's own state is not changed.  The adjoint level applies the same local
@@ -241,11 +240,13 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
  * checkpoints, a replay state, a segment of checkpoint_every + m_max - 1
  * density levels and one of checkpoint_every derivative terms; with grad_x,
  * derivative weights as large as the local weights (stored per ordered pair
- * or once per pair, as the weights are).  With recorded levels
+ * or once per pair, as the weights are; with weights on the fly their
+ * derivatives are evaluated on the fly too, each pair once, and only two
+ * column buffers of the size of the forward ones are added).  With recorded levels
  * (checkpoint_every < 0) the recorded blocks take the place of the replay.
  * Asynchronous on the plan's stream.
- * Errors: WFP_EINVAL, WFP_EDOMAIN (free space, grad_x with weights on the
- * fly), WFP_ESTATE, WFP_ENOMEM, WFP_EHIP. */
+ * Errors: WFP_EINVAL, WFP_EDOMAIN (free space), WFP_ESTATE, WFP_ENOMEM,
+ * WFP_EHIP. */
 wfp_status wfp_adjoint(wfp_plan* plan, int64_t n_levels, const double* dJdu, double* grad_beta,
                        double* grad_x);
 

@@ -1330,6 +1330,214 @@ template __global__ void k_local_sym_deriv2<2>(int, int, int, const int*, const 
                                                int64_t, const int64_t*, const uint2*, const double*,
                                                const int64_t*, double*, double*, double*, double*);
 
+// The gradient pass's two signed derivative local sums (lags 0 .. NQ - 1)
+// with the weights evaluated on the fly, each unordered pair once.  For the
+// pair (j, l) at distance d (Section 4.1),
+//   Q_m(d) = sum_i om_i(d) v_{i,m}(s_i(d)),  om_i = (delta - d) (w_i/2) (1 - phi(s_i)),
+//   s_i = W - (W - d/dt)(1 + z_i)/2,  ds_i/dd = (1 + z_i)/(2 dt),
+// so dQ_m/dd = sum_i [ dom_i/dd v_{i,m} + om_i v'_{i,m} ds_i/dd ] with
+//   dom_i/dd = (w_i/2) ( -(1 - phi(s_i)) - (delta - d) phi'(s_i) ds_i/dd )
+// (phi' from the derivative of the window piece's polynomial, v' from the
+// centred Lagrange form below).  Row j's weight for source l is
+// (1/2) dQ_m/dd sign(x_j - x_l), which changes sign with the pair's order:
+// row j adds it times the source's values, row l minus it times row j's.
+// First sum from a linear buffer of levels (row r1 - m for lag m: the forward
+// densities), second from a ring (slot L2 - m mod NH: the adjoint state);
+// lag 0 holds the current level of each.  Blocks of kOtfRows rows walk the
+// union of their upper ranges in chunks of kOtfDerivChunk sources, staged in
+// LDS with both histories; the column terms are added over the block's
+// wavefronts in a fixed order into part1 / part2, and k_local_otf_reduce adds
+// them up per row.
+// c_r = a w_r(y) + b w_r'(y) for the centred Lagrange weights of the p-point
+// stencil (the weights' form in SymLagrange, differentiated through the
+// prefix and suffix products of the factors y^2 - a_k^2): one node's
+// derivative weights, with a = d(omega)/dd and b = omega ds/dd.
+template <int P>
+__device__ __forceinline__ void sym_lagrange_comb(double y, const typename SymLagrange<P>::Squares& sq, double a,
+                                                  double b, double (&c)[P]) {
+  constexpr int H = P / 2;
+  double e[H], pre[H], suf[H], dpre[H], dsuf[H];
+  const double y2 = 2.0 * y;
+#pragma unroll
+  for (int j = 0; j < H; ++j) e[j] = fma(y, y, sq.na2[j]);
+  pre[0] = 1.0;
+  dpre[0] = 0.0;
+#pragma unroll
+  for (int j = 1; j < H; ++j) {
+    pre[j] = pre[j - 1] * e[j - 1];
+    dpre[j] = fma(dpre[j - 1], e[j - 1], pre[j - 1] * y2);
+  }
+  suf[H - 1] = 1.0;
+  dsuf[H - 1] = 0.0;
+#pragma unroll
+  for (int j = H - 2; j >= 0; --j) {
+    suf[j] = suf[j + 1] * e[j + 1];
+    dsuf[j] = fma(dsuf[j + 1], e[j + 1], suf[j + 1] * y2);
+  }
+#pragma unroll
+  for (int r = 0; r < H; ++r) {
+    const int j = H - 1 - r;
+    const double lam = SymLagrange<P>::lambda(r), aj = SymLagrange<P>::a(j);
+    // w_r = t (y - a_j), w_{P-1-r} = -t (y + a_j); w' adds t' (y -+ a_j) +- t
+    const double t = lam * (pre[j] * suf[j]);
+    const double td = lam * fma(dpre[j], suf[j], pre[j] * dsuf[j]);
+    const double T = fma(a, t, b * td), bt = b * t;
+    c[r] = fma(T, y - aj, bt);
+    c[P - 1 - r] = -fma(T, y + aj, bt);
+  }
+}
+
+template <int P>
+__global__ void __launch_bounds__(64 * kOtfRows)
+k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict__ up_end, const int* __restrict__ blk_end,
+                   const int64_t* __restrict__ part_off, int nblk_rows, const double* __restrict__ xs,
+                   const double* __restrict__ h1, int64_t r1, const double* __restrict__ h2, int64_t L2,
+                   int periodic, double dt, double delta, int W, int ngl, const double* __restrict__ na,
+                   const double* __restrict__ nw, const double* __restrict__ phitab, double* __restrict__ row1,
+                   double* __restrict__ row2, double* __restrict__ part1, double* __restrict__ part2) {
+  constexpr int CH = kOtfDerivChunk;
+  // both histories side by side (one 16-byte read per stencil point):
+  // [NQ][CH] pairs of the sources', then [kOtfRows][CH] x 2 column sums
+  extern __shared__ double2 sd2[];
+  __shared__ double tab[kPhiPieces * (kPhiDeg + 1)];
+  __shared__ double2 rh[kOtfRows][kMaxOtfLags + 1];
+  __shared__ int64_t sl1[kMaxOtfLags + 1], sl2[kMaxOtfLags + 1];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= nblk_rows) return;   // padding block: nothing to do (block-uniform)
+  double2* sg = sd2;
+  double* cp1 = (double*)(sd2 + (size_t)NQ * CH);
+  double* cp2 = cp1 + (size_t)kOtfRows * CH;
+  for (int i = threadIdx.x; i < kPhiPieces * (kPhiDeg + 1); i += blockDim.x) tab[i] = phitab[i];
+  for (int m = threadIdx.x; m < NQ; m += blockDim.x) {
+    sl1[m] = (r1 - m) * M;
+    sl2[m] = (int64_t)mod_slot(L2 - m, NH) * M;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j0 = b * kOtfRows;
+  const int j = j0 + wv;
+  const bool row = j < M;
+  __syncthreads();
+  for (int e = threadIdx.x; e < kOtfRows * NQ; e += blockDim.x) {
+    const int w = e / NQ, m = e - w * NQ;
+    const bool ok = j0 + w < M;
+    rh[w][m] = ok ? make_double2(h1[sl1[m] + (j0 + w)], h2[sl2[m] + (j0 + w)]) : make_double2(0.0, 0.0);
+  }
+  const long long uend = blk_end[b];
+  const long long my1 = row ? up_end[j] : j;
+  const double xa = row ? xs[j] : 0.0;
+  const double Wd = (double)W;
+  const double pw = (double)kPhiPieces / Wd;
+  const int64_t pbase = part_off[b];
+  typename SymLagrange<P>::Squares sq;
+  sq.init();
+  double acc1 = 0.0, acc2 = 0.0;
+  for (long long cb = j0; cb < uend; cb += CH) {
+    __syncthreads();   // the previous chunk is no longer read
+    for (int e = threadIdx.x; e < NQ * CH; e += blockDim.x) {
+      const int m = e / CH, k = e - m * CH;
+      const long long u = cb + k;   // < 2M
+      double v1 = 0.0, v2 = 0.0;
+      if (u < uend) {
+        const int uu = (int)(u < M ? u : u - M);
+        v1 = h1[sl1[m] + uu];
+        v2 = h2[sl2[m] + uu];
+      }
+      sg[e] = make_double2(v1, v2);
+    }
+    for (int e = threadIdx.x; e < kOtfRows * CH; e += blockDim.x) {
+      cp1[e] = 0.0;
+      cp2[e] = 0.0;
+    }
+    __syncthreads();
+    const long long a0 = (long long)j > cb ? (long long)j : cb;
+    const long long a1 = my1 < cb + CH ? my1 : cb + CH;
+    for (long long ua = a0 + lane; ua < a1; ua += 64) {
+      const int l = ua < M ? (int)ua : (int)(ua - M);
+      double y = xa - xs[l];
+      if (periodic) y -= kTwoPi * rint(y * kInvTwoPi);
+      const double d = fabs(y);
+      const bool on = d < delta;
+      const double f = on ? 0.5 * ((y > 0.0) ? 1.0 : ((y < 0.0) ? -1.0 : 0.0)) : 0.0;
+      const int k = (int)(ua - cb);
+      const double Dm = on ? d / dt - Wd : -0.5 * Wd;
+      const int mmin = (on && d < dt) ? 0 : 1;
+      const double span = on ? delta - d : 0.0;
+      const int mtop = (int)Wd - P / 2;
+      double s1 = 0.0, s2 = 0.0, t1 = 0.0, t2 = 0.0;
+      for (int q = 0; q < ngl; ++q) {
+        const double naq = na[q], nwq = nw[q];
+        const double s = fma(Dm, naq, Wd);
+        const double ds_dd = naq / dt;
+        const double v = s * pw;
+        unsigned pc = (unsigned)v;
+        pc = pc >= (unsigned)kPhiPieces ? kPhiPieces - 1 : pc;
+        const double* c = tab + pc * (kPhiDeg + 1);
+        const double x = __builtin_amdgcn_fract(v);
+        double ph = c[kPhiDeg], dph = 0.0;
+#pragma unroll
+        for (int kk = kPhiDeg - 1; kk >= 0; --kk) {
+          dph = fma(dph, x, ph);
+          ph = fma(ph, x, c[kk]);
+        }
+        int m0 = (int)s - P / 2 + 1;
+        m0 = m0 < mmin ? mmin : (m0 > mtop ? mtop : m0);
+        // d/dd [omega v_r(s)] = (d omega/dd) v_r + omega v_r' ds/dd
+        const double om = span * nwq * (1.0 - ph);
+        const double dom = nwq * (-(1.0 - ph) - span * (dph * pw) * ds_dd);
+        double cw[P];
+        sym_lagrange_comb<P>(s - (m0 + 0.5 * (P - 1)), sq, dom, om * ds_dd, cw);
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          const double2 g = sg[(m0 + r) * CH + k], o = rh[wv][m0 + r];
+          s1 = fma(cw[r], g.x, s1);
+          s2 = fma(cw[r], g.y, s2);
+          t1 = fma(cw[r], o.x, t1);
+          t2 = fma(cw[r], o.y, t2);
+        }
+      }
+      acc1 = fma(f, s1, acc1);
+      acc2 = fma(f, s2, acc2);
+      if (ua != (long long)j) {
+        cp1[wv * CH + k] = -f * t1;
+        cp2[wv * CH + k] = -f * t2;
+      }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < CH; k += blockDim.x) {
+      const long long u = cb + k;
+      if (u < uend) {
+        double u1 = 0.0, u2 = 0.0;
+#pragma unroll
+        for (int w = 0; w < kOtfRows; ++w) {
+          u1 += cp1[w * CH + k];
+          u2 += cp2[w * CH + k];
+        }
+        part1[pbase + (u - j0)] = u1;
+        part2[pbase + (u - j0)] = u2;
+      }
+    }
+  }
+  acc1 = wave_sum(acc1);
+  acc2 = wave_sum(acc2);
+  if (row && lane == 0) {
+    row1[j] = acc1;
+    row2[j] = acc2;
+  }
+}
+
+#define WFP_OTFD_INST(PP)                                                                                       \
+  template __global__ void k_local_otf_deriv2<PP>(int, int, int, const int*, const int*, const int64_t*, int,     \
+                                                  const double*, const double*, int64_t, const double*, int64_t,  \
+                                                  int, double, double, int, int, const double*, const double*,    \
+                                                  const double*, double*, double*, double*, double*);
+WFP_OTFD_INST(2)
+WFP_OTFD_INST(4)
+WFP_OTFD_INST(6)
+WFP_OTFD_INST(8)
+WFP_OTFD_INST(10)
+WFP_OTFD_INST(12)
+#undef WFP_OTFD_INST
+
 // Row l's total of the pair-once stored local sum: its own sum plus the column
 // terms of the rows whose upper range covers it: rows cov[l].x .. l - 1 (up_end
 // is non-decreasing, so they are consecutive) and, in the periodic box, rows

@@ -673,6 +673,7 @@ void build(wfp_plan* P, const wfp_problem* prob, const wfp_params* par) {
       P->otf_blk_end = P->alloc<int>(nb);
       P->otf_part_off = P->alloc<int64_t>(nb);
       P->otf_part = P->alloc<double>(tot_part);
+      P->otf_tot_part = tot_part;
       P->otf_rowacc = P->alloc<double>(M);
       upload(P->otf_up_end, up, s);
       upload(P->otf_blk_end, be, s);
@@ -1854,6 +1855,18 @@ void gradx_setup_pair_once(wfp_plan* P, const double* halfs) {
   for (void* q : {(void*)dense, (void*)uac, (void*)umlo, (void*)ust_d, (void*)ucnt_d, (void*)uoff_d}) P->release(q);
 }
 
+// Dynamic LDS of the on-the-fly derivative sums: both histories of a chunk
+// and the two column sums of its rows.
+size_t otf_deriv_lds(const wfp_plan* P) {
+  return (size_t)(2 * P->NQ + 2 * kOtfRows) * kOtfDerivChunk * sizeof(double);
+}
+
+// Static LDS of the same kernel: the window table, both row histories side
+// by side and their slot tables, plus room for the arrays' alignment.
+constexpr size_t kOtfDerivStaticLds = (size_t)kPhiPieces * (kPhiDeg + 1) * sizeof(double) +
+                                      (size_t)kOtfRows * (kMaxOtfLags + 1) * sizeof(double2) +
+                                      2 * (size_t)(kMaxOtfLags + 1) * sizeof(int64_t) + 64;
+
 // Signed derivative weights for the position gradient, (1/2) dQ_m/dd times
 // the sign of x_target - x_source: scatterer rows with lags m >= 0 (per
 // ordered pair in the layout of the weights, or once per pair), receivers in
@@ -1865,8 +1878,26 @@ void gradx_setup(wfp_plan* P) {
   double* hs = P->alloc<double>(std::max(M, R));
   std::vector<double> halfs(std::max(M, R), 0.5);
   upload(hs, halfs, s);
-  if (P->sym_stored) gradx_setup_pair_once(P, hs);
-  else gradx_setup_per_pair(P, hs);
+  if (P->sym_stored) {
+    gradx_setup_pair_once(P, hs);
+  } else if (P->otf) {
+    // on the fly: only the row and column buffers of the two sums
+    const size_t lds = otf_deriv_lds(P);
+    if (lds + kOtfDerivStaticLds > 160 * 1024)
+      fail(WFP_EDOMAIN, "on-the-fly position gradient: too many lags for the LDS stage");
+    const void* fns[6] = {(const void*)k_local_otf_deriv2<2>, (const void*)k_local_otf_deriv2<4>,
+                          (const void*)k_local_otf_deriv2<6>, (const void*)k_local_otf_deriv2<8>,
+                          (const void*)k_local_otf_deriv2<10>, (const void*)k_local_otf_deriv2<12>};
+    for (const void* f : fns) HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    P->otfd_row1 = P->alloc<double>(M);
+    P->otfd_row2 = P->alloc<double>(M);
+    P->otfd_part1 = P->alloc<double>(std::max<int64_t>(P->otf_tot_part, 1));
+    P->otfd_part2 = P->alloc<double>(std::max<int64_t>(P->otf_tot_part, 1));
+    P->symd_one = P->alloc<double>(M);
+    upload(P->symd_one, std::vector<double>(M, 1.0), s);
+  } else {
+    gradx_setup_per_pair(P, hs);
+  }
   std::vector<double> mhalf(R, -0.5);
   double* mh = P->alloc<double>(R);
   upload(mh, mhalf, s);
@@ -1921,6 +1952,34 @@ void deriv_field(wfp_plan* P, const StateRef& S) {
                      P->npos, P->T1, P->tw, P->tw1, P->dk1, P->dk2, P->pk, P->qk, P->rot, S.ring, S.alpha,
                      S.dalpha, P->yd, P->V, P->fir_groups, P->hist_threads == 1024 ? 1 : 0);
   launch_hist_c(P, s, (double2*)P->gridd);
+}
+
+// Both derivative local sums of a gradient level with the weights on the fly:
+// forward densities from rows r1 - m of `fwd`, adjoint ones from the adjoint
+// ring at level L2 - m, into P->xloc2 and P->xloc.
+void launch_otf_deriv2(wfp_plan* P, hipStream_t s, const double* fwd, int64_t r1, int64_t L2) {
+  const int nblocks = 8 * (int)nblk(P->otf_nblk, 8);
+  const int periodic = P->boundary == WFP_PERIODIC ? 1 : 0;
+  const size_t lds = otf_deriv_lds(P);
+#define WFP_OTFD(PP)                                                                                           \
+  hipLaunchKernelGGL(k_local_otf_deriv2<PP>, dim3(nblocks), dim3(64 * kOtfRows), lds, s, (int)P->M, P->NH,      \
+                     P->NQ, P->otf_up_end, P->otf_blk_end, P->otf_part_off, P->otf_nblk, P->xs, fwd, r1,        \
+                     (const double*)P->ahist, L2, periodic, P->dt, P->delta, P->W, P->ngl, P->otf_na, P->otf_nw, \
+                     P->phitab, P->otfd_row1, P->otfd_row2, P->otfd_part1, P->otfd_part2)
+  switch (P->p) {
+    case 2: WFP_OTFD(2); break;
+    case 4: WFP_OTFD(4); break;
+    case 6: WFP_OTFD(6); break;
+    case 8: WFP_OTFD(8); break;
+    case 10: WFP_OTFD(10); break;
+    default: WFP_OTFD(12); break;
+  }
+#undef WFP_OTFD
+  hipLaunchKernelGGL(k_local_otf_reduce, dim3(nblk(P->M, 256)), dim3(256), 0, s, (int)P->M, P->otf_nblk, periodic,
+                     P->otf_blk_end, P->otf_part_off, P->otfd_row1, P->otfd_part1, P->symd_one, P->xloc2);
+  hipLaunchKernelGGL(k_local_otf_reduce, dim3(nblk(P->M, 256)), dim3(256), 0, s, (int)P->M, P->otf_nblk, periodic,
+                     P->otf_blk_end, P->otf_part_off, P->otfd_row2, P->otfd_part2, P->symd_one, P->xloc);
+  HIPCHK(hipGetLastError());
 }
 
 void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, double* grad_x) {
@@ -1980,6 +2039,8 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
                              P->symd_row1, P->symd_col1, P->symd_one, P->xloc2);
           hipLaunchKernelGGL(k_local_sym_reduce, dim3(nblk(M, 64)), dim3(64 * kReduceWaves), 0, s, (int)M, P->sym_cov, P->sym_upb,
                              P->symd_row2, P->symd_col2, P->symd_one, P->xloc);
+        } else if (P->otf) {
+          launch_otf_deriv2(P, s, segsig, (int64_t)(hd + L - a), Rv);
         } else {
           const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
           hipLaunchKernelGGL(k_local_deriv2, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)M, P->NQ, P->NH,
@@ -2261,11 +2322,6 @@ wfp_status wfp_adjoint(wfp_plan* P, int64_t n_levels, const double* dJdu, double
   if (P->R < 1) {
     g_last_error = "the gradient pass needs receivers (R >= 1)";
     return WFP_EINVAL;
-  }
-  if (P->otf && !P->sym_stored && grad_x) {
-    // dJ/dx needs the derivative weights dQ_m/dd, which are stored
-    g_last_error = "dJ/dx needs stored local weights (local_mode 1 or 3); on the fly the pass gives dJ/dbeta alone";
-    return WFP_EDOMAIN;
   }
   if (P->ckpt_every == 0 || !P->ck_from0 || P->level < n_levels) {
     g_last_error = "run the n_levels levels from level 0 with checkpoint_every != 0 first";

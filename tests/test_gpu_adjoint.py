@@ -129,33 +129,34 @@ def test_pair_once_gradient(wfp):
     assert gx5 is None and np.array_equal(gb5, gb3)
 
 
-def test_on_the_fly_beta_gradient(wfp):
-    """dJ/dbeta with the local weights evaluated on the fly (local_mode 2: the
-    adjoint level runs the same symmetric on-the-fly local sum on the adjoint
-    state): the ragged case against the oracle's reverse sweep and against
-    local_mode 1; recorded levels give the checkpointed bits; dJ/dx, which
-    needs the stored derivative weights, is refused."""
+def test_on_the_fly_gradient(wfp):
+    """Both gradients with the local weights evaluated on the fly (local_mode
+    2: the adjoint level runs the same symmetric on-the-fly local sum on the
+    adjoint state, and the derivative sums evaluate dQ_m/dd on the fly, each
+    pair once): the ragged case against the oracle's reverse sweep and against
+    local_mode 1; recorded levels give the checkpointed bits."""
     p = _case(8, 60, 4, 0.01, (0.0, 2.0), [1.0, -1.6, 0.1, 20.0, 0.3])
     n = 237
-    say(f"adjoint on the fly: M=60 R=4 dt=0.01 levels={n} checkpoint_every=50, local_mode 2, dJ/dbeta")
-    dJdu, gb_o, _, u_o = _oracle_gradient(p, n, seed=51)
-    u2, gb2, gx2 = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=2)
-    assert gx2 is None
-    _, gb1, _ = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=1)
-    eu, eb, e21 = rho(u2, u_o), rho(gb2, gb_o), rho(gb2, gb1)
-    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  against local_mode 1: {e21:.2e}")
-    assert eu < TOL and eb < TOL and e21 < 1e-12
-    _, gb4, _ = _gpu_gradient(wfp, p, n, dJdu, -37, positions=False, local_mode=2)
-    assert np.array_equal(gb4, gb2)
-    with pytest.raises(wfp.WFPError) as ei:
-        _gpu_gradient(wfp, p, n, dJdu, 50, positions=True, local_mode=2)
-    assert ei.value.status == wfp.WFP_EDOMAIN
+    say(f"adjoint on the fly: M=60 R=4 dt=0.01 levels={n} checkpoint_every=50, local_mode 2")
+    dJdu, gb_o, gx_o, u_o = _oracle_gradient(p, n, seed=51)
+    u2, gb2, gx2 = _gpu_gradient(wfp, p, n, dJdu, 50, local_mode=2)
+    _, gb1, gx1 = _gpu_gradient(wfp, p, n, dJdu, 50, local_mode=1)
+    eu, eb, ex = rho(u2, u_o), rho(gb2, gb_o), rho(gx2, gx_o)
+    e21b, e21x = rho(gb2, gb1), rho(gx2, gx1)
+    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}; against local_mode 1: "
+        f"{e21b:.2e} / {e21x:.2e}")
+    assert eu < TOL and eb < TOL and ex < TOL and e21b < 1e-12 and e21x < 1e-12
+    _, gb4, gx4 = _gpu_gradient(wfp, p, n, dJdu, -37, local_mode=2)
+    assert np.array_equal(gb4, gb2) and np.array_equal(gx4, gx2)
+    _, gb5, gx5 = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=2)
+    assert gx5 is None and np.array_equal(gb5, gb2)
 
 
 def test_pair_once_gradient_across_the_seam(wfp):
-    """Both gradients with the weights stored once per pair for 40 springs
-    within 0.5 of the periodic seam at +-pi (upper ranges wrap past the last
-    spring to the first), against the oracle's reverse sweep."""
+    """Both gradients with the weights stored once per pair and evaluated on
+    the fly (each pair once) for 40 springs within 0.5 of the periodic seam at
+    +-pi (upper ranges wrap past the last spring to the first), against the
+    oracle's reverse sweep."""
     rng = np.random.default_rng(23)
     x = np.mod(rng.uniform(-0.5, 0.5, 40) + 2 * np.pi, 2 * np.pi) - np.pi
     p = dict(x=x, beta=rng.uniform(1.0, 10.0, 40), packets=np.array([[1.0, 2.2, 0.1, 0.0, 0.0]]), boundary=0,
@@ -163,24 +164,27 @@ def test_pair_once_gradient_across_the_seam(wfp):
     n = 150
     say(f"adjoint pair-once across the seam: M=40 R=3 dt=0.01 levels={n} checkpoint_every=40, local_mode 3")
     dJdu, gb_o, gx_o, u_o = _oracle_gradient(p, n, seed=52)
-    u3, gb3, gx3 = _gpu_gradient(wfp, p, n, dJdu, 40, local_mode=3)
-    eu, eb, ex = rho(u3, u_o), rho(gb3, gb_o), rho(gx3, gx_o)
-    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}")
-    assert eu < TOL and eb < TOL and ex < TOL
+    for mode in (3, 2):
+        u3, gb3, gx3 = _gpu_gradient(wfp, p, n, dJdu, 40, local_mode=mode)
+        eu, eb, ex = rho(u3, u_o), rho(gb3, gb_o), rho(gx3, gx_o)
+        say(f"  local_mode {mode}: rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}")
+        assert eu < TOL and eb < TOL and ex < TOL
 
 
 def test_pair_once_gradient_full_size_matches_per_pair(wfp):
     """At the adjoint workload's full size (M = 1e5, R = 64, 300 levels,
     levels recorded): both gradients with the weights stored once per pair
     against those stored per ordered pair (the same sums over about 1400
-    neighbours per spring, added in another order)."""
+    neighbours per spring, added in another order), and with the weights
+    evaluated on the fly (the window from its piecewise polynomial instead of
+    the Chebyshev series, so agreement to the window's accuracy, 1e-10)."""
     import torch
     from paper_2507_07823_amd import workloads
     p = workloads.adjoint_periodic()
     n, R = 300, p["x_recv"].size
-    say(f"adjoint full size, local_mode 3 against 1: M={p['x'].size} R={R} levels={n}")
+    say(f"adjoint full size, local_mode 3 and 2 against 1: M={p['x'].size} R={R} levels={n}")
     out = {}
-    for mode in (1, 3):
+    for mode in (1, 3, 2):
         plan = wfp.Plan(p, p["dt"], checkpoint_every=-100, local_mode=mode)
         u = torch.empty((n, R), dtype=torch.float64, device="cuda")
         plan.run(n, None, 1, u)
@@ -189,8 +193,11 @@ def test_pair_once_gradient_full_size_matches_per_pair(wfp):
         out[mode] = (u.cpu().numpy(), gb.cpu().numpy(), gx.cpu().numpy())
         plan.close()
     eu, eb, ex = (rho(out[3][k], out[1][k]) for k in range(3))
-    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}")
+    say(f"  local_mode 3: rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}")
     assert eu < 1e-12 and eb < 1e-12 and ex < 1e-12
+    eu, eb, ex = (rho(out[2][k], out[1][k]) for k in range(3))
+    say(f"  local_mode 2: rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}")
+    assert eu < TOL and eb < TOL and ex < TOL
 
 
 def test_recorded_levels_across_calls_and_resets(wfp):
@@ -382,6 +389,18 @@ def test_gradient_dense_nearby_coupling(wfp):
                                                                                                g["grad_x"])
     say(f"  local_mode 3: rho(u) = {e3u:.2e}  rho(beta) = {e3b:.2e}  rho(x) = {e3x:.2e}")
     assert e3u < TOL and e3b < TOL and e3x < TOL
+    # and with the weights evaluated on the fly
+    po = wfp.Plan(p, p["dt"], checkpoint_every=-100, local_mode=2)
+    assert po.info["local_mode"] == 2
+    u2 = torch.empty_like(u)
+    po.run(n, None, 1, u2)
+    gb2, gx2 = po.gradient(torch.from_numpy(np.ascontiguousarray(g["dJdu"])).cuda())
+    torch.cuda.synchronize()
+    po.close()
+    e2u, e2b, e2x = rho(u2.cpu().numpy(), g["u"]), rho(gb2.cpu().numpy(), g["grad_beta"]), rho(gx2.cpu().numpy(),
+                                                                                               g["grad_x"])
+    say(f"  local_mode 2: rho(u) = {e2u:.2e}  rho(beta) = {e2b:.2e}  rho(x) = {e2x:.2e}")
+    assert e2u < TOL and e2b < TOL and e2x < TOL
 
 
 def _clear_of_breaks(x, xr, j, h, prm, z):
