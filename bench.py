@@ -698,14 +698,17 @@ def disordered_full(M=10_000, chunk=50_000, refines=(1, 2)):
 
 
 def lds_ceiling():
-    """LDS read bytes per second of this GPU from the committed probe program
-    (built beside the library), or None if it is missing or fails."""
+    """LDS read rates of this GPU from the committed probe program (built
+    beside the library): a dict with the ceiling (16-byte reads) and the rate
+    of the 8-byte pair reads the local sum issues, or None if it is missing or
+    fails."""
     probe = os.path.join(ROOT, "paper_2507_07823_amd", "lds_probe")
     if not os.path.exists(probe):
         return None
     try:
         r = subprocess.run([probe], capture_output=True, text=True, timeout=60)
-        return float(json.loads(r.stdout.strip().splitlines()[-1])["lds_read_bytes_per_s"])
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+        return {"ceiling": float(d["lds_read_bytes_per_s"]), "b64x2": float(d["ds_read2st64_b64_bytes_per_s"])}
     except (subprocess.SubprocessError, ValueError, IndexError, KeyError, OSError):
         return None
 
@@ -750,14 +753,17 @@ def headline(steps, warmup, profile_levels):
                     "timed_with": "HIP events on the plan's stream"}
         # the operands each lane reads from LDS per (unordered pair, node): the
         # source and row stencils (p values each) and the window piece,
-        # against this GPU's LDS read throughput measured by the probe
+        # against this GPU's LDS read throughput measured by the probe (its
+        # ceiling, 16-byte reads; and the rate of the 8-byte pair reads that
+        # carry the stencils)
         lds = info["n_pairs"] / 2 * info["n_gl_local"] * (2 * info["p"] + 6) * 8.0
         roofline["lds_operand_bytes_per_launch"] = lds
         roofline["lds_operand_GBps"] = lds / (avg * 1e-3) / 1e9
         ceiling = lds_ceiling()
         if ceiling:
-            roofline["lds_ceiling_GBps"] = ceiling / 1e9
+            roofline["lds_ceiling_GBps"] = ceiling["ceiling"] / 1e9
             roofline["lds_frac"] = roofline["lds_operand_GBps"] / roofline["lds_ceiling_GBps"]
+            roofline["lds_read2_b64_GBps"] = ceiling["b64x2"] / 1e9
         log(f"stages: {json.dumps(stages)}")
     parity = clumped_parity(plan, p)
     log(f"parity vs oracle: {parity}")
