@@ -41,8 +41,8 @@ def _case(seed, M, R, dt, x_range, pulse):
     return dict(x=x, beta=beta, packets=np.array([pulse]), boundary=0, x_recv=xr, dt=dt)
 
 
-def _oracle_gradient(p, n, seed=50):
-    prm = Params(dt=p["dt"])
+def _oracle_gradient(p, n, seed=50, order=8):
+    prm = Params(dt=p["dt"], p=order)
     rng = np.random.default_rng(seed)
     bstar = p["beta"] * (1 + 0.05 * rng.standard_normal(p["beta"].size))
     target = AdjointOracle(p["x"], bstar, p["packets"], prm, p["x_recv"]).forward(n)
@@ -53,10 +53,10 @@ def _oracle_gradient(p, n, seed=50):
     return dJdu, gb, gx, u
 
 
-def _gpu_gradient(w, p, n, dJdu, every, positions=True, **kw):
+def _gpu_gradient(w, prob, n, dJdu, every, positions=True, **kw):
     import torch
-    plan = w.Plan(p, p["dt"], checkpoint_every=every, **kw)
-    u = torch.empty((n, p["x_recv"].size), dtype=torch.float64, device="cuda")
+    plan = w.Plan(prob, prob["dt"], checkpoint_every=every, **kw)
+    u = torch.empty((n, prob["x_recv"].size), dtype=torch.float64, device="cuda")
     plan.run(n, None, 1, u)
     e = torch.from_numpy(np.ascontiguousarray(dJdu)).cuda()
     gb, gx = plan.gradient(e, positions=positions)
@@ -150,6 +150,25 @@ def test_on_the_fly_gradient(wfp):
     assert np.array_equal(gb4, gb2) and np.array_equal(gx4, gx2)
     _, gb5, gx5 = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=2)
     assert gx5 is None and np.array_equal(gb5, gb2)
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 10, 12])
+def test_on_the_fly_gradient_other_orders(wfp, order):
+    """Both gradients with the weights evaluated on the fly at the other
+    stencil orders p (each its own instance of the derivative kernel): the
+    ragged case over 150 levels against the oracle's reverse sweep at the same
+    p, and against the weights stored per ordered pair."""
+    p = _case(8, 60, 4, 0.01, (0.0, 2.0), [1.0, -1.6, 0.1, 20.0, 0.3])
+    n = 150
+    say(f"adjoint on the fly, p={order}: M=60 R=4 dt=0.01 levels={n} checkpoint_every=-40")
+    dJdu, gb_o, gx_o, u_o = _oracle_gradient(p, n, seed=53, order=order)
+    u2, gb2, gx2 = _gpu_gradient(wfp, p, n, dJdu, -40, local_mode=2, p=order)
+    _, gb1, gx1 = _gpu_gradient(wfp, p, n, dJdu, -40, local_mode=1, p=order)
+    eu, eb, ex = rho(u2, u_o), rho(gb2, gb_o), rho(gx2, gx_o)
+    e21b, e21x = rho(gb2, gb1), rho(gx2, gx1)
+    say(f"  rho(u) = {eu:.2e}  rho(beta) = {eb:.2e}  rho(x) = {ex:.2e}; against local_mode 1: "
+        f"{e21b:.2e} / {e21x:.2e}")
+    assert eu < TOL and eb < TOL and ex < TOL and e21b < 1e-12 and e21x < 1e-12
 
 
 def test_pair_once_gradient_across_the_seam(wfp):
