@@ -422,6 +422,58 @@ def test_gradient_dense_nearby_coupling(wfp):
     assert e2u < TOL and e2b < TOL and e2x < TOL
 
 
+def test_on_the_fly_gradient_at_M1e6(wfp):
+    """The gradient where no stored form fits: M = 1e6 periodic springs at
+    dt = 1e-4 (about 1400 neighbours each, as in the adjoint workload), whose
+    weights and derivative weights would take about 430 GB stored once per pair.
+    With the weights on the fly (local_mode 2, levels recorded) over 180
+    levels, a narrow pulse placed just outside the springs reaching them, the
+    beta gradient along a random positive direction against central
+    differences of the GPU's own loss (h = 1e-3, whose O(h^2) error is ~1e-6
+    at M = 1e5); the position gradient finite and not zero."""
+    import time
+    import torch
+    from paper_2507_07823_amd import workloads
+    p = workloads.adjoint_periodic(M=1_000_000, dt=1e-4)
+    # a pulse of width 0.0015 centred 0.015 before the first spring (its 1e-12
+    # support ends 0.004 before it) and receivers about the medium's edge
+    p["packets"] = np.array([[1.0, -np.pi + 1.2 - 0.015, 0.0015, 0.0, 0.0]])
+    p["x_recv"] = -np.pi + np.array([1.19, 1.195, 1.2, 1.205, 1.21, 1.22, 1.23, 1.25])
+    n, h = 180, 1e-3
+    M, R = p["x"].size, p["x_recv"].size
+    say(f"adjoint on the fly at M={M}: R={R} dt=1e-4 levels={n} checkpoint_every=-60")
+
+    def loss(beta, grad=False):
+        plan = wfp.Plan(dict(p, beta=beta), p["dt"], checkpoint_every=-60, local_mode=2)
+        u = torch.empty((n, R), dtype=torch.float64, device="cuda")
+        t0 = time.perf_counter()
+        plan.run(n, None, 1, u)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        J = 0.5 * p["dt"] * float((u * u).sum())
+        out = None
+        if grad:
+            t0 = time.perf_counter()
+            gb, gx = plan.gradient(p["dt"] * u)
+            torch.cuda.synchronize()
+            say(f"  forward {tf:.2f} s, gradient (beta, x) {time.perf_counter() - t0:.2f} s, "
+                f"{plan.query_info()['device_bytes'] / 1e9:.1f} GB on the device")
+            out = (gb.cpu().numpy(), gx.cpu().numpy())
+        plan.close()
+        return J, out
+
+    J0, (gb, gx) = loss(p["beta"], grad=True)
+    assert J0 > 0 and np.all(np.isfinite(gb)) and np.all(np.isfinite(gx)) and np.abs(gx).max() > 0
+    d = np.random.default_rng(14).uniform(0.5, 1.5, M)
+    jp, _ = loss(p["beta"] * (1 + h * d))
+    jm, _ = loss(p["beta"] * (1 - h * d))
+    fd = (jp - jm) / (2 * h)
+    an = float(gb @ (p["beta"] * d))
+    say(f"  J = {J0:.6e}; directional derivative: gradient {an:.12e}  central difference {fd:.12e}  "
+        f"rel {abs(an - fd) / abs(fd):.2e}")
+    assert abs(an) > 0 and abs(an - fd) <= 1e-4 * abs(fd)
+
+
 def _clear_of_breaks(x, xr, j, h, prm, z):
     """True if moving spring j by up to +-2h moves no pair distance with its
     neighbours or the receivers across a point where Q_m(d) is not smooth: the
