@@ -1873,6 +1873,10 @@ constexpr size_t kOtfDerivStaticLds = (size_t)kPhiPieces * (kPhiDeg + 1) * sizeo
 // the layout of their weights with the sign of x_source - x_receiver.
 void gradx_setup(wfp_plan* P) {
   if (P->gradx_ready) return;
+  // on the fly, the derivative sums stage m_max lags of two histories per
+  // chunk in LDS (refused before anything is allocated)
+  if (!P->sym_stored && P->otf && otf_deriv_lds(P) + kOtfDerivStaticLds > 160 * 1024)
+    fail(WFP_EDOMAIN, "on-the-fly position gradient: too many lags for the LDS stage (W + p/2 > 45)");
   const int64_t M = P->M, R = P->R;
   hipStream_t s = P->stream;
   double* hs = P->alloc<double>(std::max(M, R));
@@ -1883,8 +1887,6 @@ void gradx_setup(wfp_plan* P) {
   } else if (P->otf) {
     // on the fly: only the row and column buffers of the two sums
     const size_t lds = otf_deriv_lds(P);
-    if (lds + kOtfDerivStaticLds > 160 * 1024)
-      fail(WFP_EDOMAIN, "on-the-fly position gradient: too many lags for the LDS stage");
     const void* fns[6] = {(const void*)k_local_otf_deriv2<2>, (const void*)k_local_otf_deriv2<4>,
                           (const void*)k_local_otf_deriv2<6>, (const void*)k_local_otf_deriv2<8>,
                           (const void*)k_local_otf_deriv2<10>, (const void*)k_local_otf_deriv2<12>};

@@ -304,6 +304,20 @@ def test_adjoint_state_errors(wfp):
         plan.run_noalloc(1)                           # recording allocates its blocks
     assert ei.value.status == wfp.WFP_EINVAL
     plan.close()
+    # with the weights on the fly the derivative sums stage m_max = W + p/2
+    # lags of two histories in LDS: more than 45 are refused, before anything
+    # is allocated or launched; the beta gradient alone is not affected
+    plan = wfp.Plan(p, p["dt"], checkpoint_every=-4, local_mode=2, W=42)
+    assert plan.info["local_mode"] == 2 and plan.info["m_max"] == 46
+    plan.run(10)
+    for _ in range(2):
+        with pytest.raises(wfp.WFPError) as ei:
+            plan.gradient(e)
+        assert ei.value.status == wfp.WFP_EDOMAIN
+    gb, gx = plan.gradient(e, positions=False)
+    torch.cuda.synchronize()
+    assert gx is None and bool(torch.isfinite(gb).all())
+    plan.close()
 
 
 def test_gradient_full_size_beta_directional(wfp):
