@@ -246,7 +246,7 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
  * (checkpoint_every < 0) the recorded blocks take the place of the replay.
  * Asynchronous on the plan's stream.
  * Errors: WFP_EINVAL, WFP_EDOMAIN (free space; grad_x with the weights on
- * the fly and m_max = W + p/2 > 45, more lags than its LDS stage holds),
+ * the fly and m_max = W + p/2 > 46, more lags than its LDS stage holds),
  * WFP_ESTATE, WFP_ENOMEM, WFP_EHIP. */
 wfp_status wfp_adjoint(wfp_plan* plan, int64_t n_levels, const double* dJdu, double* grad_beta,
                        double* grad_x);

@@ -215,8 +215,10 @@ struct wfp_plan {
   int sym_spl = 1;               // sources per lane of the pair-once kernels (1 or 2)
   int64_t otf_tot_part = 0;      // length of otf_part
   // gradient pass with the weights on the fly: the two derivative sums' row
-  // and column terms (in the layout of otf_rowacc / otf_part)
+  // and column terms and those of the next adjoint level's local sum (in the
+  // layout of otf_rowacc / otf_part), and that sum per row
   double *otfd_row1 = nullptr, *otfd_row2 = nullptr, *otfd_part1 = nullptr, *otfd_part2 = nullptr;
+  double *otfd_row3 = nullptr, *otfd_part3 = nullptr, *otfd_next = nullptr;
   int64_t* symd_rb = nullptr;
   uint2* symd_acx = nullptr;
   double *symd_q = nullptr, *symd_row1 = nullptr, *symd_row2 = nullptr, *symd_col1 = nullptr,

@@ -59,7 +59,7 @@ constexpr int kOtfRows = 16, kOtfChunk = 256;
 // wavefronts of a pair-once reduce workgroup (64 rows, one per lane)
 constexpr int kReduceWaves = 16;
 // sources per LDS chunk of the on-the-fly derivative local sums
-constexpr int kOtfDerivChunk = 128;
+constexpr int kOtfDerivChunk = 112;
 constexpr int kMaxOtfLags = 48;      // lags 1 .. NQ - 1 of a row staged by the symmetric local sum
 template <int P>
 __global__ void k_local_otf_sym(int M, int NH, int NQ, int64_t L, const int* __restrict__ up_end,
@@ -82,8 +82,8 @@ __global__ void k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict_
                                    int64_t r1, const double* __restrict__ h2, int64_t L2, int periodic, double dt,
                                    double delta, int W, int ngl, const double* __restrict__ na,
                                    const double* __restrict__ nw, const double* __restrict__ phitab,
-                                   double* __restrict__ row1, double* __restrict__ row2, double* __restrict__ part1,
-                                   double* __restrict__ part2);
+                                   double* __restrict__ row1, double* __restrict__ row2, double* __restrict__ row3,
+                                   double* __restrict__ part1, double* __restrict__ part2, double* __restrict__ part3);
 template <int SPL>
 __global__ void k_local_sym_deriv2(int M, int NQ, int NH, const int* __restrict__ up_end,
                                    const double* __restrict__ h1, int64_t r1, const double* __restrict__ h2,

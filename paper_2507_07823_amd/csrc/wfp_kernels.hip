@@ -1347,14 +1347,19 @@ template __global__ void k_local_sym_deriv2<2>(int, int, int, const int*, const 
 // union of their upper ranges in chunks of kOtfDerivChunk sources, staged in
 // LDS with both histories; the column terms are added over the block's
 // wavefronts in a fixed order into part1 / part2, and k_local_otf_reduce adds
-// them up per row.
-// c_r = a w_r(y) + b w_r'(y) for the centred Lagrange weights of the p-point
-// stencil (the weights' form in SymLagrange, differentiated through the
-// prefix and suffix products of the factors y^2 - a_k^2): one node's
-// derivative weights, with a = d(omega)/dd and b = omega ds/dd.
+// them up per row.  The same pass forms the next adjoint level's explicit
+// local sum, sum_{m >= 1} (1/2) Q_m(d) of the second history at lag m - 1
+// (the adjoint state one level on), into row3 / part3: its weights om_i v_i
+// come with the derivative ones, its operands are the loaded ones shifted by
+// one lag plus lag m0 - 1 (zero below lag 0).
+// c_r = a w_r(y) + b w_r'(y) and v_r = g w_r(y) for the centred Lagrange
+// weights of the p-point stencil (the weights' form in SymLagrange,
+// differentiated through the prefix and suffix products of the factors
+// y^2 - a_k^2): one node's derivative weights, with a = d(omega)/dd and
+// b = omega ds/dd, and its weights, with g = omega.
 template <int P>
 __device__ __forceinline__ void sym_lagrange_comb(double y, const typename SymLagrange<P>::Squares& sq, double a,
-                                                  double b, double (&c)[P]) {
+                                                  double b, double g, double (&c)[P], double (&v)[P]) {
   constexpr int H = P / 2;
   double e[H], pre[H], suf[H], dpre[H], dsuf[H];
   const double y2 = 2.0 * y;
@@ -1381,9 +1386,11 @@ __device__ __forceinline__ void sym_lagrange_comb(double y, const typename SymLa
     // w_r = t (y - a_j), w_{P-1-r} = -t (y + a_j); w' adds t' (y -+ a_j) +- t
     const double t = lam * (pre[j] * suf[j]);
     const double td = lam * fma(dpre[j], suf[j], pre[j] * dsuf[j]);
-    const double T = fma(a, t, b * td), bt = b * t;
+    const double T = fma(a, t, b * td), bt = b * t, gt = g * t;
     c[r] = fma(T, y - aj, bt);
     c[P - 1 - r] = -fma(T, y + aj, bt);
+    v[r] = gt * (y - aj);
+    v[P - 1 - r] = -gt * (y + aj);
   }
 }
 
@@ -1394,10 +1401,11 @@ k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict__ up_end, const 
                    const double* __restrict__ h1, int64_t r1, const double* __restrict__ h2, int64_t L2,
                    int periodic, double dt, double delta, int W, int ngl, const double* __restrict__ na,
                    const double* __restrict__ nw, const double* __restrict__ phitab, double* __restrict__ row1,
-                   double* __restrict__ row2, double* __restrict__ part1, double* __restrict__ part2) {
+                   double* __restrict__ row2, double* __restrict__ row3, double* __restrict__ part1,
+                   double* __restrict__ part2, double* __restrict__ part3) {
   constexpr int CH = kOtfDerivChunk;
   // both histories side by side (one 16-byte read per stencil point):
-  // [NQ][CH] pairs of the sources', then [kOtfRows][CH] x 2 column sums
+  // [NQ][CH] pairs of the sources', then [kOtfRows][CH] x 3 column sums
   extern __shared__ double2 sd2[];
   __shared__ double tab[kPhiPieces * (kPhiDeg + 1)];
   __shared__ double2 rh[kOtfRows][kMaxOtfLags + 1];
@@ -1407,6 +1415,8 @@ k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict__ up_end, const 
   double2* sg = sd2;
   double* cp1 = (double*)(sd2 + (size_t)NQ * CH);
   double* cp2 = cp1 + (size_t)kOtfRows * CH;
+  double* cp3 = cp2 + (size_t)kOtfRows * CH;
+  const double* sgd = (const double*)sg;
   for (int i = threadIdx.x; i < kPhiPieces * (kPhiDeg + 1); i += blockDim.x) tab[i] = phitab[i];
   for (int m = threadIdx.x; m < NQ; m += blockDim.x) {
     sl1[m] = (r1 - m) * M;
@@ -1430,7 +1440,7 @@ k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict__ up_end, const 
   const int64_t pbase = part_off[b];
   typename SymLagrange<P>::Squares sq;
   sq.init();
-  double acc1 = 0.0, acc2 = 0.0;
+  double acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   for (long long cb = j0; cb < uend; cb += CH) {
     __syncthreads();   // the previous chunk is no longer read
     for (int e = threadIdx.x; e < NQ * CH; e += blockDim.x) {
@@ -1447,6 +1457,7 @@ k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict__ up_end, const 
     for (int e = threadIdx.x; e < kOtfRows * CH; e += blockDim.x) {
       cp1[e] = 0.0;
       cp2[e] = 0.0;
+      cp3[e] = 0.0;
     }
     __syncthreads();
     const long long a0 = (long long)j > cb ? (long long)j : cb;
@@ -1463,7 +1474,7 @@ k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict__ up_end, const 
       const int mmin = (on && d < dt) ? 0 : 1;
       const double span = on ? delta - d : 0.0;
       const int mtop = (int)Wd - P / 2;
-      double s1 = 0.0, s2 = 0.0, t1 = 0.0, t2 = 0.0;
+      double s1 = 0.0, s2 = 0.0, t1 = 0.0, t2 = 0.0, s3 = 0.0, t3 = 0.0;
       for (int q = 0; q < ngl; ++q) {
         const double naq = na[q], nwq = nw[q];
         const double s = fma(Dm, naq, Wd);
@@ -1484,8 +1495,14 @@ k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict__ up_end, const 
         // d/dd [omega v_r(s)] = (d omega/dd) v_r + omega v_r' ds/dd
         const double om = span * nwq * (1.0 - ph);
         const double dom = nwq * (-(1.0 - ph) - span * (dph * pw) * ds_dd);
-        double cw[P];
-        sym_lagrange_comb<P>(s - (m0 + 0.5 * (P - 1)), sq, dom, om * ds_dd, cw);
+        double cw[P], vw[P];
+        sym_lagrange_comb<P>(s - (m0 + 0.5 * (P - 1)), sq, dom, om * ds_dd, om, cw, vw);
+        // the second history one lag down for the next level's sum: lag m0 - 1
+        // (zero for m0 = 0, read at lag 0 to stay in bounds), then the loaded ones
+        const int mp = m0 > 0 ? m0 - 1 : 0;
+        double gp = sgd[2 * (mp * CH + k) + 1], op = rh[wv][mp].y;
+        gp = m0 > 0 ? gp : 0.0;
+        op = m0 > 0 ? op : 0.0;
 #pragma unroll
         for (int r = 0; r < P; ++r) {
           const double2 g = sg[(m0 + r) * CH + k], o = rh[wv][m0 + r];
@@ -1493,35 +1510,45 @@ k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict__ up_end, const 
           s2 = fma(cw[r], g.y, s2);
           t1 = fma(cw[r], o.x, t1);
           t2 = fma(cw[r], o.y, t2);
+          s3 = fma(vw[r], gp, s3);
+          t3 = fma(vw[r], op, t3);
+          gp = g.y;
+          op = o.y;
         }
       }
       acc1 = fma(f, s1, acc1);
       acc2 = fma(f, s2, acc2);
+      acc3 += s3;
       if (ua != (long long)j) {
         cp1[wv * CH + k] = -f * t1;
         cp2[wv * CH + k] = -f * t2;
+        cp3[wv * CH + k] = t3;
       }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < CH; k += blockDim.x) {
       const long long u = cb + k;
       if (u < uend) {
-        double u1 = 0.0, u2 = 0.0;
+        double u1 = 0.0, u2 = 0.0, u3 = 0.0;
 #pragma unroll
         for (int w = 0; w < kOtfRows; ++w) {
           u1 += cp1[w * CH + k];
           u2 += cp2[w * CH + k];
+          u3 += cp3[w * CH + k];
         }
         part1[pbase + (u - j0)] = u1;
         part2[pbase + (u - j0)] = u2;
+        part3[pbase + (u - j0)] = u3;
       }
     }
   }
   acc1 = wave_sum(acc1);
   acc2 = wave_sum(acc2);
+  acc3 = wave_sum(acc3);
   if (row && lane == 0) {
     row1[j] = acc1;
     row2[j] = acc2;
+    row3[j] = acc3;
   }
 }
 
@@ -1529,7 +1556,8 @@ k_local_otf_deriv2(int M, int NH, int NQ, const int* __restrict__ up_end, const 
   template __global__ void k_local_otf_deriv2<PP>(int, int, int, const int*, const int*, const int64_t*, int,     \
                                                   const double*, const double*, int64_t, const double*, int64_t,  \
                                                   int, double, double, int, int, const double*, const double*,    \
-                                                  const double*, double*, double*, double*, double*);
+                                                  const double*, double*, double*, double*, double*, double*,     \
+                                                  double*);
 WFP_OTFD_INST(2)
 WFP_OTFD_INST(4)
 WFP_OTFD_INST(6)

@@ -1421,11 +1421,13 @@ void launch_local_lag1(wfp_plan* P, hipStream_t s, const double* hist, int64_t L
 // data and the whole local sum of level L were launched on P->sd by the
 // caller, which signals ev_big[L & 1] after them.
 void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const ExtraSources& ex, double* save,
-                 double* u_recv_row, bool overlap = false, bool ahead = false) {
+                 double* u_recv_row, bool overlap = false, bool ahead = false, const double* local_ready = nullptr) {
   // overlap: the history chain on P->sb (its own compute units) after the
   // previous level's solve and receivers, everything else on P->sa; the solve
   // waits for both.  ahead: the solve and receivers follow the chain on P->sb
   // (no wait between queues on the chain -> solve -> chain path).
+  // local_ready: the level's explicit local sum, already formed (copied in
+  // place of the local-sum kernels).
   hipStream_t sc = overlap ? P->sb : P->stream;
   hipStream_t s = overlap ? (ahead ? P->sb : P->sa) : P->stream;
   if (overlap && sc != s) HIPCHK(hipStreamWaitEvent(sc, P->ev_solved, 0));
@@ -1437,11 +1439,14 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
   {
     // timed with events bound to the kernel's own dispatch (no marker gaps)
     hipEvent_t ea = nullptr, eb = nullptr;
-    if (P->profiling) {
+    const bool timed = P->profiling && !local_ready;
+    if (timed) {
       ea = take_event(P);
       eb = take_event(P);
     }
-    if (otf_schedule(P) && overlap) {
+    if (local_ready) {
+      HIPCHK(hipMemcpyAsync(P->loc, local_ready, P->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else if (otf_schedule(P) && overlap) {
       // on the local sum's compute units, joined before the solve
       HIPCHK(hipStreamWaitEvent(P->sd, P->ev_solved, 0));
       launch_local_otf(P, P->sd, S.hist, L, P->half_beta, P->loc);
@@ -1452,7 +1457,7 @@ void march_level(wfp_plan* P, const StateRef& S, int64_t L, bool driven, const E
     } else if (!ahead) {
       launch_local_big(P, s, S.hist, L, ea, eb);
     }
-    if (P->profiling) {
+    if (timed) {
       P->pending.push_back({WFP_STAGE_LOCAL, ea, eb});
       if (P->pending.size() >= 1024) flush_profile(P);
     }
@@ -1856,9 +1861,9 @@ void gradx_setup_pair_once(wfp_plan* P, const double* halfs) {
 }
 
 // Dynamic LDS of the on-the-fly derivative sums: both histories of a chunk
-// and the two column sums of its rows.
+// and the three column sums of its rows.
 size_t otf_deriv_lds(const wfp_plan* P) {
-  return (size_t)(2 * P->NQ + 2 * kOtfRows) * kOtfDerivChunk * sizeof(double);
+  return (size_t)(2 * P->NQ + 3 * kOtfRows) * kOtfDerivChunk * sizeof(double);
 }
 
 // Static LDS of the same kernel: the window table, both row histories side
@@ -1876,7 +1881,7 @@ void gradx_setup(wfp_plan* P) {
   // on the fly, the derivative sums stage m_max lags of two histories per
   // chunk in LDS (refused before anything is allocated)
   if (!P->sym_stored && P->otf && otf_deriv_lds(P) + kOtfDerivStaticLds > 160 * 1024)
-    fail(WFP_EDOMAIN, "on-the-fly position gradient: too many lags for the LDS stage (W + p/2 > 45)");
+    fail(WFP_EDOMAIN, "on-the-fly position gradient: too many lags for the LDS stage (W + p/2 > 46)");
   const int64_t M = P->M, R = P->R;
   hipStream_t s = P->stream;
   double* hs = P->alloc<double>(std::max(M, R));
@@ -1895,6 +1900,9 @@ void gradx_setup(wfp_plan* P) {
     P->otfd_row2 = P->alloc<double>(M);
     P->otfd_part1 = P->alloc<double>(std::max<int64_t>(P->otf_tot_part, 1));
     P->otfd_part2 = P->alloc<double>(std::max<int64_t>(P->otf_tot_part, 1));
+    P->otfd_row3 = P->alloc<double>(M);
+    P->otfd_part3 = P->alloc<double>(std::max<int64_t>(P->otf_tot_part, 1));
+    P->otfd_next = P->alloc<double>(M);
     P->symd_one = P->alloc<double>(M);
     upload(P->symd_one, std::vector<double>(M, 1.0), s);
   } else {
@@ -1958,7 +1966,9 @@ void deriv_field(wfp_plan* P, const StateRef& S) {
 
 // Both derivative local sums of a gradient level with the weights on the fly:
 // forward densities from rows r1 - m of `fwd`, adjoint ones from the adjoint
-// ring at level L2 - m, into P->xloc2 and P->xloc.
+// ring at level L2 - m, into P->xloc2 and P->xloc; and, in the same pass, the
+// explicit local sum of adjoint level L2 + 1 (scaled by beta/2 as the march's
+// own) into P->otfd_next.
 void launch_otf_deriv2(wfp_plan* P, hipStream_t s, const double* fwd, int64_t r1, int64_t L2) {
   const int nblocks = 8 * (int)nblk(P->otf_nblk, 8);
   const int periodic = P->boundary == WFP_PERIODIC ? 1 : 0;
@@ -1967,7 +1977,8 @@ void launch_otf_deriv2(wfp_plan* P, hipStream_t s, const double* fwd, int64_t r1
   hipLaunchKernelGGL(k_local_otf_deriv2<PP>, dim3(nblocks), dim3(64 * kOtfRows), lds, s, (int)P->M, P->NH,      \
                      P->NQ, P->otf_up_end, P->otf_blk_end, P->otf_part_off, P->otf_nblk, P->xs, fwd, r1,        \
                      (const double*)P->ahist, L2, periodic, P->dt, P->delta, P->W, P->ngl, P->otf_na, P->otf_nw, \
-                     P->phitab, P->otfd_row1, P->otfd_row2, P->otfd_part1, P->otfd_part2)
+                     P->phitab, P->otfd_row1, P->otfd_row2, P->otfd_row3, P->otfd_part1, P->otfd_part2,      \
+                     P->otfd_part3)
   switch (P->p) {
     case 2: WFP_OTFD(2); break;
     case 4: WFP_OTFD(4); break;
@@ -1981,6 +1992,8 @@ void launch_otf_deriv2(wfp_plan* P, hipStream_t s, const double* fwd, int64_t r1
                      P->otf_blk_end, P->otf_part_off, P->otfd_row1, P->otfd_part1, P->symd_one, P->xloc2);
   hipLaunchKernelGGL(k_local_otf_reduce, dim3(nblk(P->M, 256)), dim3(256), 0, s, (int)P->M, P->otf_nblk, periodic,
                      P->otf_blk_end, P->otf_part_off, P->otfd_row2, P->otfd_part2, P->symd_one, P->xloc);
+  hipLaunchKernelGGL(k_local_otf_reduce, dim3(nblk(P->M, 256)), dim3(256), 0, s, (int)P->M, P->otf_nblk, periodic,
+                     P->otf_blk_end, P->otf_part_off, P->otfd_row3, P->otfd_part3, P->half_beta, P->otfd_next);
   HIPCHK(hipGetLastError());
 }
 
@@ -1997,6 +2010,10 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
   const StateRef adj{P->ahist, P->aring, P->aalpha, P->adalpha};
   const ExtraSources none{nullptr, 0, nullptr, nullptr, nullptr, nullptr};
   zero_state_ref(P, adj);
+  // weights on the fly: each level's derivative pass also forms the next
+  // adjoint level's local sum (none before the first)
+  const bool fused = wx && P->otf && !P->sym_stored;
+  bool next_ready = false;
   hipLaunchKernelGGL(k_fill, dim3(nblk(M, 256)), dim3(256), 0, s, P->gb_acc, M, 0.0);
   hipLaunchKernelGGL(k_fill, dim3(nblk(M, 256)), dim3(256), 0, s, P->gx_acc, M, 0.0);
   const int64_t nseg = (N + C - 1) / C;
@@ -2028,7 +2045,7 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
                            P->esort);
         ex = ExtraSources{P->esort, (int)R, P->rcs, P->rcc, P->rwo, P->rsw};
       }
-      march_level(P, adj, Rv, true, ex, nullptr, nullptr);
+      march_level(P, adj, Rv, true, ex, nullptr, nullptr, false, false, next_ready ? P->otfd_next : nullptr);
       if (wx) {
         deriv_field(P, adj);
         if (P->sym_stored) {
@@ -2043,6 +2060,7 @@ void run_adjoint(wfp_plan* P, int64_t N, const double* e, double* grad_beta, dou
                              P->symd_row2, P->symd_col2, P->symd_one, P->xloc);
         } else if (P->otf) {
           launch_otf_deriv2(P, s, segsig, (int64_t)(hd + L - a), Rv);
+          next_ready = fused;
         } else {
           const int nlocblk = 8 * (int)nblk(nblk(M, kRowThreads / 64), 8);
           hipLaunchKernelGGL(k_local_deriv2, dim3(nlocblk), dim3(kRowThreads), 0, s, (int)M, P->NQ, P->NH,

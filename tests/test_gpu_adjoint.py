@@ -148,8 +148,10 @@ def test_on_the_fly_gradient(wfp):
     assert eu < TOL and eb < TOL and ex < TOL and e21b < 1e-12 and e21x < 1e-12
     _, gb4, gx4 = _gpu_gradient(wfp, p, n, dJdu, -37, local_mode=2)
     assert np.array_equal(gb4, gb2) and np.array_equal(gx4, gx2)
+    # dJ/dbeta alone: the adjoint levels form their own local sums (with dJ/dx
+    # the derivative pass forms them, the same terms added in another order)
     _, gb5, gx5 = _gpu_gradient(wfp, p, n, dJdu, 50, positions=False, local_mode=2)
-    assert gx5 is None and np.array_equal(gb5, gb2)
+    assert gx5 is None and rho(gb5, gb2) < 1e-13
 
 
 @pytest.mark.parametrize("order", [2, 4, 6, 10, 12])
@@ -305,10 +307,10 @@ def test_adjoint_state_errors(wfp):
     assert ei.value.status == wfp.WFP_EINVAL
     plan.close()
     # with the weights on the fly the derivative sums stage m_max = W + p/2
-    # lags of two histories in LDS: more than 45 are refused, before anything
+    # lags of two histories in LDS: more than 46 are refused, before anything
     # is allocated or launched; the beta gradient alone is not affected
-    plan = wfp.Plan(p, p["dt"], checkpoint_every=-4, local_mode=2, W=42)
-    assert plan.info["local_mode"] == 2 and plan.info["m_max"] == 46
+    plan = wfp.Plan(p, p["dt"], checkpoint_every=-4, local_mode=2, W=43)
+    assert plan.info["local_mode"] == 2 and plan.info["m_max"] == 47
     plan.run(10)
     for _ in range(2):
         with pytest.raises(wfp.WFPError) as ei:
