@@ -131,10 +131,12 @@ def test_pair_once_gradient(wfp):
 
 def test_on_the_fly_gradient(wfp):
     """Both gradients with the local weights evaluated on the fly (local_mode
-    2: the adjoint level runs the same symmetric on-the-fly local sum on the
-    adjoint state, and the derivative sums evaluate dQ_m/dd on the fly, each
-    pair once): the ragged case against the oracle's reverse sweep and against
-    local_mode 1; recorded levels give the checkpointed bits."""
+    2: the derivative sums evaluate dQ_m/dd on the fly, each pair once, and
+    form the next adjoint level's local sum in the same pass; the first
+    adjoint level, and every level of a dJ/dbeta-only pass, runs the
+    on-the-fly local sum on the adjoint state): the ragged case against the
+    oracle's reverse sweep and against local_mode 1; recorded levels give the
+    checkpointed bits."""
     p = _case(8, 60, 4, 0.01, (0.0, 2.0), [1.0, -1.6, 0.1, 20.0, 0.3])
     n = 237
     say(f"adjoint on the fly: M=60 R=4 dt=0.01 levels={n} checkpoint_every=50, local_mode 2")
