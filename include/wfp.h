@@ -241,8 +241,9 @@ wfp_status wfp_local_part(wfp_plan* plan, double* out);
  * density levels and one of checkpoint_every derivative terms; with grad_x,
  * derivative weights as large as the local weights (stored per ordered pair
  * or once per pair, as the weights are; with weights on the fly their
- * derivatives are evaluated on the fly too, each pair once, and only two
- * column buffers of the size of the forward ones are added).  With recorded levels
+ * derivatives are evaluated on the fly too, each pair once, in the pass
+ * that also forms the next adjoint level's local sum, and only three column
+ * buffers of the size of the forward one are added).  With recorded levels
  * (checkpoint_every < 0) the recorded blocks take the place of the replay.
  * Asynchronous on the plan's stream.
  * Errors: WFP_EINVAL, WFP_EDOMAIN (free space; grad_x with the weights on
